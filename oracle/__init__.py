@@ -1,0 +1,32 @@
+"""Plain FP64 CPU oracle for the LRDM density-response hot path.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product package imports, links or
+runs this code; only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may use it.  It shares no code with the
+HIP path: it is written directly from the paper (Das & Gavini, "Accelerating
+SCF iterations in Kohn-Sham DFT using a low rank approximation of the
+dielectric matrix"), in NumPy, double precision, with no blocking or fusion.
+
+Every function is pinned by a ``-m "not gpu"`` test in ``tests/test_oracle_*.py``
+against something other than itself (closed forms, dense diagonalisation,
+finite differences, 50-digit decimal arithmetic, invariants).
+"""
+from .lrdm_oracle import (  # noqa: F401
+    Grid,
+    hamiltonian_apply,
+    chebyshev_filter,
+    rayleigh_ritz,
+    fermi_dirac,
+    fermi_level,
+    divided_differences,
+    projected_perturbation,
+    fermi_shift,
+    response_density_matrix,
+    density_from_matrix,
+    density,
+    density_response,
+    hartree_kernel,
+    residual_derivative,
+    spin_factor,
+    recursive_fermi_response,
+)

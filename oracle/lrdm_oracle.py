@@ -1,0 +1,312 @@
+"""FP64 oracle of the LRDM hot path (test infrastructure only; see package doc).
+
+Notation follows the paper, carried to a periodic finite-difference grid (the
+paper states the method carries over to finite differences, end of Sec. II D):
+
+* grid of n = (nx, ny, nz) points, spacings h_d = L_d / n_d, cell volume
+  element dv = hx*hy*hz, arrays laid out [..., nz, ny, nx];
+* a block of N vectors is stored state-major, Psi[i] is state i;
+* vectors are l2-orthonormal (sum_p Psi_ip Psi_jp = delta_ij), so real-space
+  orbitals are Psi / sqrt(dv) and the FE overlap matrix of Eq. (16) becomes
+  dv * I, with n^e(x) the point value;
+* s = 2 (spin restricted, Eq. (1)) or s = 1 per channel (spin polarised,
+  Sec. II D, which drops the factor 2).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass(frozen=True)
+class Grid:
+    n: tuple      # (nx, ny, nz)
+    L: tuple      # (Lx, Ly, Lz)
+
+    @property
+    def M(self):
+        return int(self.n[0] * self.n[1] * self.n[2])
+
+    @property
+    def h(self):
+        return tuple(self.L[d] / self.n[d] for d in range(3))
+
+    @property
+    def dv(self):
+        hx, hy, hz = self.h
+        return hx * hy * hz
+
+    @property
+    def shape(self):
+        return (self.n[2], self.n[1], self.n[0])
+
+
+def spin_factor(nspin: int) -> float:
+    """Occupation per spatial state: 2 for spin-restricted (Eq. (1)), 1 per channel
+    when spin polarised (Sec. II D, response per channel without the factor 2)."""
+    return 2.0 if nspin == 1 else 1.0
+
+
+# ---------------------------------------------------------------------------
+# Hamiltonian and Chebyshev-filtered subspace iteration (Sec. II C)
+# ---------------------------------------------------------------------------
+def hamiltonian_apply(Y: np.ndarray, V: np.ndarray, grid: Grid) -> np.ndarray:
+    """H Y with H = -1/2 Laplacian + V (Eq. (1)); the Laplacian is the 7-point
+    periodic second difference.  Y: [..., nz, ny, nx]."""
+    hx, hy, hz = grid.h
+    lap = np.zeros_like(Y)
+    for axis, hd in ((-1, hx), (-2, hy), (-3, hz)):
+        lap += (np.roll(Y, 1, axis=axis) + np.roll(Y, -1, axis=axis) - 2.0 * Y) / (hd * hd)
+    return -0.5 * lap + V * Y
+
+
+def chebyshev_filter(X: np.ndarray, V: np.ndarray, grid: Grid, degree: int,
+                     a: float, b: float, a0: float) -> np.ndarray:
+    """Scaled Chebyshev filter T_c(Hbar) X / T_c(ybar0) of degree c (Sec. II C).
+
+    Hbar = (H - c0)/e maps the unwanted interval [a, b] to [-1, 1] and the wanted
+    spectrum below a to (-inf, -1); e = (b - a)/2, c0 = (b + a)/2, and a0 (a lower
+    bound of the spectrum) fixes the scaling ybar0 = (a0 - c0)/e.  This is the
+    three-term recurrence of Zhou, Saad, Tiago and Chelikowsky (J. Comput. Phys.
+    219, 2006), written out below:
+        sigma_1 = e / (a0 - c0),   Y_1 = (sigma_1 / e)(H - c0) X,
+        sigma_k = 1 / (2/sigma_1 - sigma_{k-1}),
+        Y_k = (2 sigma_k / e)(H - c0) Y_{k-1} - sigma_{k-1} sigma_k Y_{k-2},   Y_0 = X.
+    """
+    e = (b - a) / 2.0
+    c0 = (b + a) / 2.0
+    sigma1 = e / (a0 - c0)
+    y_prev = X.astype(np.float64, copy=True)
+    y = (sigma1 / e) * (hamiltonian_apply(y_prev, V, grid) - c0 * y_prev)
+    sigma = sigma1
+    for _ in range(2, degree + 1):
+        sigma_new = 1.0 / (2.0 / sigma1 - sigma)
+        y_new = (2.0 * sigma_new / e) * (hamiltonian_apply(y, V, grid) - c0 * y) \
+            - (sigma * sigma_new) * y_prev
+        y_prev, y = y, y_new
+        sigma = sigma_new
+    return y
+
+
+def rayleigh_ritz(Y: np.ndarray, V: np.ndarray, grid: Grid):
+    """Orthonormalise the filtered block and solve the projected problem (Sec. II C,
+    Eq. (15)): Psi_o = orth(Y), Hhat = Psi_o^T H Psi_o, Hhat Q = Q D,
+    Psi_R = Psi_o Q.  Returns (eps ascending [N], Psi_R [N][nz][ny][nx])."""
+    N = Y.shape[0]
+    Ycols = Y.reshape(N, -1).T                       # M x N, the paper's orientation
+    Psi_o, _ = np.linalg.qr(Ycols)                   # Householder QR
+    HPsi = hamiltonian_apply(Psi_o.T.reshape(Y.shape), V, grid).reshape(N, -1).T
+    Hhat = Psi_o.T @ HPsi
+    Hhat = 0.5 * (Hhat + Hhat.T)
+    eps, Q = np.linalg.eigh(Hhat)
+    Psi_R = Psi_o @ Q
+    return eps, Psi_R.T.reshape(Y.shape).copy()
+
+
+# ---------------------------------------------------------------------------
+# Occupations and Fermi level (Eq. (1))
+# ---------------------------------------------------------------------------
+def _logistic(y: np.ndarray) -> np.ndarray:
+    """1 / (1 + exp(y)) without overflow."""
+    y = np.asarray(y, dtype=np.float64)
+    out = np.empty_like(y)
+    pos = y >= 0
+    ey = np.exp(-y[pos])
+    out[pos] = ey / (1.0 + ey)
+    out[~pos] = 1.0 / (1.0 + np.exp(y[~pos]))
+    return out
+
+
+def fermi_dirac(eps: np.ndarray, mu: float, kT: float):
+    """f = 1/(1 + exp((eps - mu)/kT)) (Eq. (1)), 1 - f computed as f of the
+    negated argument (no subtraction), and f' = df/deps = -f (1 - f) / kT."""
+    y = (np.asarray(eps, dtype=np.float64) - mu) / kT
+    f = _logistic(y)
+    omf = _logistic(-y)
+    fp = -f * omf / kT
+    return f, omf, fp
+
+
+def fermi_level(eps: np.ndarray, n_electrons: float, kT: float, nspin: int = 1,
+                max_iter: int = 200):
+    """mu solving s * sum_{sigma,i} f(eps_sigma,i, mu) = N_e (Eq. (1)) by bisection on
+    [min eps - 50 kT, max eps + 50 kT]; stops when the bracket is within 2 ulp of
+    its midpoint or after max_iter halvings.  Returns (mu, converged)."""
+    eps = np.asarray(eps, dtype=np.float64).reshape(nspin, -1)
+    s = spin_factor(nspin)
+    lo = float(eps.min()) - 50.0 * kT
+    hi = float(eps.max()) + 50.0 * kT
+    converged = False
+    for _ in range(max_iter):
+        mid = 0.5 * (lo + hi)
+        if hi - lo <= 2.0 * np.spacing(abs(mid)):
+            converged = True
+            break
+        count = s * float(np.sum(fermi_dirac(eps, mid, kT)[0]))
+        if count > n_electrons:
+            hi = mid
+        else:
+            lo = mid
+    return 0.5 * (lo + hi), converged
+
+
+def divided_differences(eps: np.ndarray, mu: float, kT: float) -> np.ndarray:
+    """F_ij = (f_i - f_j)/(eps_i - eps_j), F_ii = f'_i: the Hadamard multiplier that
+    gives the derivative of f(D + lam H', mu) at lam = 0 for diagonal D (Eqs. (21)-(22);
+    Daleckii-Krein).  For eps_lo <= eps_hi and z = (eps_lo - eps_hi)/kT <= 0 the exact
+    identity f_lo - f_hi = -f_lo (1 - f_hi) expm1(z) gives
+        F = -(1/kT) f_lo (1 - f_hi) expm1(z)/z,
+    which neither overflows nor cancels near degeneracy (expm1(z)/z -> 1)."""
+    eps = np.asarray(eps, dtype=np.float64)
+    e_lo = np.minimum(eps[:, None], eps[None, :])
+    e_hi = np.maximum(eps[:, None], eps[None, :])
+    f_lo, _, _ = fermi_dirac(e_lo, mu, kT)
+    _, omf_hi, _ = fermi_dirac(e_hi, mu, kT)
+    z = (e_lo - e_hi) / kT
+    phi = np.ones_like(z)
+    nz = z != 0.0
+    phi[nz] = np.expm1(z[nz]) / z[nz]
+    return -(f_lo * omf_hi * phi) / kT
+
+
+# ---------------------------------------------------------------------------
+# Subspace density response (Sec. II C, Eqs. (19)-(22) and the traceless condition)
+# ---------------------------------------------------------------------------
+def projected_perturbation(Psi: np.ndarray, dV: np.ndarray) -> np.ndarray:
+    """Hbreve' = Psi_R^T H' Psi_R with H' = diag(dV) (Eq. (21)); Psi: [N][...]."""
+    N = Psi.shape[0]
+    P = Psi.reshape(N, -1).T                         # M x N
+    return P.T @ (dV.reshape(-1)[:, None] * P)
+
+
+def fermi_shift(Hp: list, fprime: list) -> float:
+    """mu' from Tr Gamma^(1) = 0 summed over channels (text after Eq. (24)):
+    mu' = sum f'_i H'_ii / sum f'_i; zero when sum f' underflows (mu in a gap)."""
+    num = 0.0
+    den = 0.0
+    for H, fp in zip(Hp, fprime):
+        num += float(np.sum(fp * np.diag(H)))
+        den += float(np.sum(fp))
+    if abs(den) < 1e-300:
+        return 0.0
+    return num / den
+
+
+def response_density_matrix(F: np.ndarray, Hp: np.ndarray, dmu: float,
+                            fprime: np.ndarray) -> np.ndarray:
+    """Gammabreve^(1) = d/dlam f(D + lam H', mu + lam mu') = F o H' - mu' diag(f')
+    (Eq. (22) with the exact Fermi-Dirac divided differences)."""
+    return F * Hp - dmu * np.diag(fprime)
+
+
+def density_from_matrix(Psi: np.ndarray, Gamma: np.ndarray, dv: float, s: float) -> np.ndarray:
+    """(s/dv) diag(Psi_R Gamma Psi_R^T) at every grid point (Eqs. (16), (20) with
+    M = dv I and point-value n^e)."""
+    N = Psi.shape[0]
+    P = Psi.reshape(N, -1).T                         # M x N
+    Z = P @ Gamma
+    return ((s / dv) * np.sum(P * Z, axis=1)).reshape(Psi.shape[1:])
+
+
+def density(Psi: np.ndarray, eps: np.ndarray, grid: Grid, n_electrons: float, kT: float,
+            nspin: int = 1):
+    """Output density rho = (s/dv) sum_i f_i |Psi_i|^2 per channel (Eq. (16))."""
+    Psi = Psi.reshape((nspin,) + Psi.shape[-4:])
+    eps = np.asarray(eps).reshape(nspin, -1)
+    mu, _ = fermi_level(eps, n_electrons, kT, nspin)
+    s = spin_factor(nspin)
+    rho = np.empty((nspin,) + grid.shape)
+    for c in range(nspin):
+        f, _, _ = fermi_dirac(eps[c], mu, kT)
+        rho[c] = density_from_matrix(Psi[c], np.diag(f), grid.dv, s)
+    return rho, mu
+
+
+def density_response(Psi: np.ndarray, eps: np.ndarray, grid: Grid, n_electrons: float,
+                     kT: float, dV: np.ndarray, nspin: int = 1):
+    """delta rho_k for each perturbation dV_k in the Ritz subspace (Eqs. (20)-(22),
+    Sec. II D for two channels with a common mu and mu').
+
+    Psi [nspin][N][nz][ny][nx], eps [nspin][N], dV [r][nspin][nz][ny][nx].
+    Returns (drho [r][nspin][nz][ny][nx], mu, dmu [r])."""
+    Psi = Psi.reshape((nspin,) + Psi.shape[-4:])
+    eps = np.asarray(eps, dtype=np.float64).reshape(nspin, -1)
+    dV = dV.reshape((-1, nspin) + grid.shape)
+    r = dV.shape[0]
+    s = spin_factor(nspin)
+    mu, _ = fermi_level(eps, n_electrons, kT, nspin)
+    occ = [fermi_dirac(eps[c], mu, kT) for c in range(nspin)]
+    Fm = [divided_differences(eps[c], mu, kT) for c in range(nspin)]
+    drho = np.empty_like(dV)
+    dmu = np.empty(r)
+    for k in range(r):
+        Hp = [projected_perturbation(Psi[c], dV[k, c]) for c in range(nspin)]
+        dmu[k] = fermi_shift(Hp, [occ[c][2] for c in range(nspin)])
+        for c in range(nspin):
+            G = response_density_matrix(Fm[c], Hp[c], dmu[k], occ[c][2])
+            drho[k, c] = density_from_matrix(Psi[c], G, grid.dv, s)
+    return drho, mu, dmu
+
+
+# ---------------------------------------------------------------------------
+# Residual derivative t = chi0 K u - u (Eqs. (3), (7))
+# ---------------------------------------------------------------------------
+def hartree_kernel(u: np.ndarray, grid: Grid) -> np.ndarray:
+    """K_c u: the Hartree potential of density u, -Lap_h dV = 4 pi u (Eq. (3)),
+    with the same 7-point Laplacian as H; the q = 0 component is set to zero."""
+    nx, ny, nz = grid.n
+    hx, hy, hz = grid.h
+    kx = 2 * np.pi * np.arange(nx) / nx
+    ky = 2 * np.pi * np.arange(ny) / ny
+    kz = 2 * np.pi * np.arange(nz) / nz
+    lam = ((2 - 2 * np.cos(kz))[:, None, None] / hz ** 2
+           + (2 - 2 * np.cos(ky))[None, :, None] / hy ** 2
+           + (2 - 2 * np.cos(kx))[None, None, :] / hx ** 2)
+    mult = np.zeros_like(lam)
+    mult[lam > 0] = 4 * np.pi / lam[lam > 0]
+    mult[0, 0, 0] = 0.0
+    uh = np.fft.fftn(u, axes=(-3, -2, -1))
+    return np.real(np.fft.ifftn(uh * mult, axes=(-3, -2, -1)))
+
+
+def residual_derivative(Psi: np.ndarray, eps: np.ndarray, grid: Grid, n_electrons: float,
+                        kT: float, u: np.ndarray, nspin: int = 1):
+    """t_k = d/dlam R[rho + lam u_k] = chi0 K u_k - u_k (Eqs. (3), (7)) with K = K_c:
+    the Hartree potential couples to the total density, so every channel sees
+    dV = K_c (sum_sigma u_sigma).  u, t: [r][nspin][nz][ny][nx]."""
+    u = u.reshape((-1, nspin) + grid.shape)
+    dV = np.empty_like(u)
+    for k in range(u.shape[0]):
+        vh = hartree_kernel(u[k].sum(axis=0), grid)
+        for c in range(nspin):
+            dV[k, c] = vh
+    drho, mu, dmu = density_response(Psi, eps, grid, n_electrons, kT, dV, nspin)
+    return drho - u, mu, dmu
+
+
+# ---------------------------------------------------------------------------
+# The paper's recursive Fermi-operator expansion (Eqs. (23)-(24))
+# ---------------------------------------------------------------------------
+def recursive_fermi_response(eps: np.ndarray, mu: float, kT: float, Hp: np.ndarray,
+                             depth: int):
+    """Response of the recursive expansion X_0 = 1/2 - 2^{-(T+2)} (D - mu)/kT,
+    X_n = X_{n-1}^2 / (X_{n-1}^2 + (1 - X_{n-1})^2) along D + lam H' at fixed mu
+    (Eqs. (23)-(24)), carried by first-order perturbation of each step:
+        X_n + lam X_n' = (X^2 + lam (X X' + X' X)) (Y + lam Y')^{-1},
+        Y = X^2 + (1 - X)^2,  Y' = 2 (X X' + X' X) - 2 X'  ... (first order).
+    X stays diagonal, so the inverse of Y is a diagonal inversion.
+    Returns (occupations diag(X_T), response matrix X_T')."""
+    x = 0.5 - (2.0 ** (-(depth + 2))) * (np.asarray(eps) - mu) / kT
+    xp = -(2.0 ** (-(depth + 2))) * Hp / kT
+    for _ in range(depth):
+        x2 = x * x
+        y = x2 + (1.0 - x) ** 2
+        # first-order pieces of X^2 and of Y = 2X^2 - 2X + 1 for diagonal X
+        x2p = x[:, None] * xp + xp * x[None, :]
+        yp = 2.0 * x2p - 2.0 * xp
+        yinv = 1.0 / y
+        # (A + lam A')(Y + lam Y')^{-1} = A Y^{-1} + lam (A' Y^{-1} - A Y^{-1} Y' Y^{-1})
+        xp = x2p * yinv[None, :] - (x2 * yinv)[:, None] * yp * yinv[None, :]
+        x = x2 * yinv
+    return x, xp

@@ -1,0 +1,422 @@
+"""Pins of the oracle: each function returns an error measure that is small for a
+correct oracle.  ``test_oracle_*.py`` asserts they are small; the mutation tests
+plant mistakes in the oracle and assert that at least one pin notices.
+
+Each pin compares the oracle with something other than itself: a closed form,
+a dense diagonalisation, a finite difference, 50-digit decimal arithmetic or an
+invariant of the mathematics.
+"""
+from __future__ import annotations
+
+import decimal
+
+import numpy as np
+from numpy.polynomial import chebyshev as npcheb
+
+import oracle as O
+from tests import bruteforce as bf
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def small_wells(n, L, seed, nwells=3, depth=(1.0, 2.0)):
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(0, 1, (nwells, 3)) * np.asarray(L)
+    d = rng.uniform(*depth, nwells)
+    w = rng.uniform(0.6, 1.0, nwells)
+    from inputs import gaussian_wells
+    return gaussian_wells(n, L, d, w, pos)
+
+
+# ------------------------------------------------------------------ stencil
+def pin_plane_wave():
+    """cos(k.x) is an eigenvector of -1/2 Lap_h + V0 with eigenvalue
+    sum_d (1 - cos(2 pi k_d / n_d)) / h_d^2 + V0."""
+    n, L = (6, 5, 7), (3.0, 2.5, 3.3)
+    g = O.Grid(n, L)
+    V0 = 0.37
+    z, y, x = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    err = 0.0
+    for k in [(1, 0, 0), (2, 1, 3), (0, 2, 1), (3, 2, 0)]:
+        th = [2 * np.pi * k[d] / n[d] for d in range(3)]
+        Y = np.cos(th[0] * x + th[1] * y + th[2] * z)[None]
+        lam = sum((1 - np.cos(th[d])) / g.h[d] ** 2 for d in range(3)) + V0
+        HY = O.hamiltonian_apply(Y, np.full(g.shape, V0), g)
+        err = max(err, _rel(HY, lam * Y))
+    return err
+
+
+def pin_dense_stencil():
+    n, L = (4, 3, 5), (2.0, 1.7, 2.6)
+    g = O.Grid(n, L)
+    rng = np.random.default_rng(1)
+    V = rng.standard_normal(g.shape)
+    Y = rng.standard_normal((3,) + g.shape)
+    H = bf.dense_hamiltonian(V, n, L)
+    ref = (H @ Y.reshape(3, -1).T).T.reshape(Y.shape)
+    return _rel(O.hamiltonian_apply(Y, V, g), ref)
+
+
+# ------------------------------------------------------------------ filter
+def pin_filter_polynomial(degree=9):
+    """T_c(Hbar) X / T_c(ybar0) from the dense eigendecomposition, with T_c evaluated
+    by numpy's Chebyshev series routine."""
+    n, L = (4, 4, 4), (3.0, 3.0, 3.0)
+    g = O.Grid(n, L)
+    V = small_wells(n, L, 2)
+    H = bf.dense_hamiltonian(V, n, L)
+    lam, Q = np.linalg.eigh(H)
+    a0, a, b = lam[0] - 0.05, lam[10], lam[-1] + 0.02
+    e, c0 = (b - a) / 2, (b + a) / 2
+    coef = np.zeros(degree + 1)
+    coef[-1] = 1.0
+    scale = npcheb.chebval((lam - c0) / e, coef) / npcheb.chebval((a0 - c0) / e, coef)
+    X = np.random.default_rng(3).standard_normal((5,) + g.shape)
+    Xc = X.reshape(5, -1).T
+    ref = (Q @ (scale[:, None] * (Q.T @ Xc))).T.reshape(X.shape)
+    return _rel(O.chebyshev_filter(X, V, g, degree, a, b, a0), ref)
+
+
+def pin_filter_scalar_identity(degree=7):
+    """On a plane wave with eigenvalue lam inside [a, b], the filter multiplies by
+    cos(c arccos(lbar)) / ((-1)^c cosh(c arccosh(-ybar0))), closed form."""
+    n, L = (5, 6, 4), (2.0, 2.4, 1.6)
+    g = O.Grid(n, L)
+    z, y, x = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    k = (2, 1, 1)
+    th = [2 * np.pi * k[d] / n[d] for d in range(3)]
+    Y = np.cos(th[0] * x + th[1] * y + th[2] * z)[None]
+    lam = sum((1 - np.cos(th[d])) / g.h[d] ** 2 for d in range(3))
+    b = sum(2.0 / hd ** 2 for hd in g.h)            # top of the spectrum of -1/2 Lap_h
+    a, a0 = lam - 0.7, -0.4
+    e, c0 = (b - a) / 2, (b + a) / 2
+    lbar, ybar0 = (lam - c0) / e, (a0 - c0) / e
+    factor = np.cos(degree * np.arccos(lbar)) / ((-1) ** degree * np.cosh(degree * np.arccosh(-ybar0)))
+    out = O.chebyshev_filter(Y, np.zeros(g.shape), g, degree, a, b, a0)
+    return _rel(out, factor * Y)
+
+
+def chfsi_passes(V, g, N, passes, degree, seed=4):
+    X = np.random.default_rng(seed).standard_normal((N,) + g.shape)
+    b = sum(2.0 / hd ** 2 for hd in g.h) + float(V.max())
+    a0 = float(V.min())
+    a = a0 + 0.3 * (b - a0)
+    eps = None
+    for _ in range(passes):
+        Y = O.chebyshev_filter(X, V, g, degree, a, b, a0)
+        eps, X = O.rayleigh_ritz(Y, V, g)
+        a = float(eps[-1])
+        a0 = float(eps[0]) - 0.5
+    return eps, X
+
+
+def pin_chfsi_exact_subspace():
+    """Repeated filter + Rayleigh-Ritz converges to the exact lowest eigenpairs
+    (dense diagonalisation): returns (max Ritz error, sin of the largest principal
+    angle) over the lowest N - 4 states."""
+    n, L = (6, 6, 6), (4.0, 4.0, 4.0)
+    g = O.Grid(n, L)
+    V = small_wells(n, L, 5, nwells=4)
+    lam, Q = np.linalg.eigh(bf.dense_hamiltonian(V, n, L))
+    N, keep = 14, 10
+    eps, Psi = chfsi_passes(V, g, N, passes=12, degree=12)
+    ritz_err = float(np.max(np.abs(eps[:keep] - lam[:keep])))
+    P = Psi[:keep].reshape(keep, -1).T
+    s = np.linalg.svd(Q[:, :keep].T @ P, compute_uv=False)
+    sin_max = float(np.sqrt(max(0.0, 1 - s.min() ** 2)))
+    return ritz_err, sin_max
+
+
+# ------------------------------------------------------------------ Rayleigh-Ritz
+def pin_rr_exact_eigenvectors():
+    n, L = (4, 4, 3), (3.0, 3.0, 2.4)
+    g = O.Grid(n, L)
+    V = small_wells(n, L, 6)
+    lam, Q = np.linalg.eigh(bf.dense_hamiltonian(V, n, L))
+    idx = [0, 1, 2, 5, 7, 11]
+    rng = np.random.default_rng(7)
+    mix = np.linalg.qr(rng.standard_normal((len(idx), len(idx))))[0]
+    Y = (Q[:, idx] @ mix * rng.uniform(0.5, 3, len(idx))[None, :]).T.reshape((len(idx),) + g.shape)
+    eps, _ = O.rayleigh_ritz(Y, V, g)
+    return float(np.max(np.abs(eps - lam[idx])))
+
+
+def pin_rr_generalized():
+    """Ritz values of span(Y) equal the generalized eigenvalues of (Y^T H Y, Y^T Y)
+    (scipy), the Ritz vectors are orthonormal and diagonalise H."""
+    from scipy.linalg import eigh as geigh
+    n, L = (5, 4, 4), (3.0, 2.4, 2.4)
+    g = O.Grid(n, L)
+    V = small_wells(n, L, 8)
+    H = bf.dense_hamiltonian(V, n, L)
+    Y = np.random.default_rng(9).standard_normal((9,) + g.shape)
+    Yc = Y.reshape(9, -1).T
+    ref = geigh(Yc.T @ H @ Yc, Yc.T @ Yc, eigvals_only=True)
+    eps, Psi = O.rayleigh_ritz(Y, V, g)
+    P = Psi.reshape(9, -1).T
+    e1 = float(np.max(np.abs(eps - ref)))
+    e2 = float(np.max(np.abs(P.T @ P - np.eye(9))))
+    e3 = float(np.max(np.abs(P.T @ H @ P - np.diag(eps))))
+    return max(e1, e2, e3)
+
+
+# ------------------------------------------------------------------ occupations
+def pin_fermi_level():
+    rng = np.random.default_rng(10)
+    errs = []
+    for nspin, kT in ((1, 0.01), (2, 0.005), (1, 0.1)):
+        eps = np.sort(rng.uniform(-2, 1, (nspin, 40)), axis=1)
+        s = O.spin_factor(nspin)
+        ne = 0.39 * s * 40 * nspin
+        mu, conv = O.fermi_level(eps, ne, kT, nspin)
+        count = s * np.sum(bf.occupations(eps, mu, kT))
+        errs.append(abs(count - ne) / ne)
+        errs.append(abs(mu - bf.fermi_level(eps, ne, kT, s)))
+        if not conv:
+            errs.append(1.0)
+    return max(errs)
+
+
+def pin_fermi_gap():
+    """With a gap of 1 Ha between the 4th and 5th levels, 8 electrons and a small kT,
+    mu sits inside the gap."""
+    eps = np.array([-3.0, -2.5, -2.2, -2.0, -1.0, -0.7, -0.2, 0.3])
+    mu, _ = O.fermi_level(eps, 8.0, 0.005, 1)
+    return 0.0 if (-2.0 < mu < -1.0) else 1.0
+
+
+def _dec_fermi(e, mu, kT):
+    return decimal.Decimal(1) / (decimal.Decimal(1) + ((decimal.Decimal(e) - decimal.Decimal(mu)) / decimal.Decimal(kT)).exp())
+
+
+def pin_divided_differences_decimal():
+    """F against 50-digit decimal arithmetic of (f_i - f_j)/(e_i - e_j) and of
+    -f(1-f)/kT on the diagonal, including near-degenerate pairs."""
+    decimal.getcontext().prec = 50
+    rng = np.random.default_rng(11)
+    mu, kT = 0.13, 0.01
+    base = rng.uniform(-0.1, 0.35, 12)
+    eps = np.concatenate([base, base[:4] + np.array([1e-11, 3e-9, 2e-7, 5e-5]), [mu, mu + 1e-12]])
+    F = O.divided_differences(eps, mu, kT)
+    err = 0.0
+    for i in range(len(eps)):
+        for j in range(len(eps)):
+            if eps[i] == eps[j]:
+                fi = _dec_fermi(eps[i], mu, kT)
+                ref = -fi * (1 - fi) / decimal.Decimal(kT)
+            else:
+                ref = (_dec_fermi(eps[i], mu, kT) - _dec_fermi(eps[j], mu, kT)) / \
+                      (decimal.Decimal(eps[i]) - decimal.Decimal(eps[j]))
+            ref = float(ref)
+            scale = max(abs(ref), 1e-300)
+            if abs(ref) > 1e-250:
+                err = max(err, abs(F[i, j] - ref) / scale)
+    return err
+
+
+def pin_divided_differences_naive():
+    rng = np.random.default_rng(12)
+    eps = np.sort(rng.uniform(-1, 1, 30))
+    mu, kT = 0.05, 0.02
+    F = O.divided_differences(eps, mu, kT)
+    scale = float(np.abs(F).max())
+    err = 0.0
+    for i in range(30):
+        for j in range(30):
+            # the plain quotient cancels when both occupations are near 1, so the
+            # comparison is in units of the largest entry
+            ref = bf.fd_scalar(eps[i], eps[j], mu, kT)
+            err = max(err, abs(F[i, j] - ref) / scale)
+    sym = float(np.max(np.abs(F - F.T)))
+    nonpos = float(max(F.max(), 0.0))
+    return max(err, sym, nonpos)
+
+
+# ------------------------------------------------------------------ response
+def _rr_system(n, L, N, seed, passes=4, degree=10):
+    g = O.Grid(n, L)
+    V = small_wells(n, L, seed, nwells=4)
+    eps, Psi = chfsi_passes(V, g, N, passes=passes, degree=degree, seed=seed)
+    return g, V, eps, Psi
+
+
+def pin_response_subspace_fd(nspin=1):
+    """delta rho from the oracle against a Richardson central difference in lam of the
+    subspace density (s/dv) diag(Psi f(eigh(D + lam H'), mu(lam)) Psi^T)."""
+    n, L = (5, 5, 4), (3.2, 3.2, 2.6)
+    N = 16
+    g, V, eps, Psi = _rr_system(n, L, N, seed=13)
+    rng = np.random.default_rng(14)
+    kT = 0.03
+    s = O.spin_factor(nspin)
+    ne = 0.7 * N * (2.0 if nspin == 1 else 2.0)
+    if nspin == 2:
+        eps2 = np.stack([eps, eps + rng.uniform(-0.02, 0.02, N)])
+        Psi2 = np.stack([Psi, Psi])
+    else:
+        eps2, Psi2 = eps[None], Psi[None]
+    dV = rng.standard_normal((1, nspin) + g.shape)
+    drho, mu, dmu = O.density_response(Psi2, eps2, g, ne, kT, dV, nspin)
+
+    P = [Psi2[c].reshape(N, -1) for c in range(nspin)]
+    Hp = [bf.projected(P[c], dV[0, c]) for c in range(nspin)]
+
+    def rho_all(lam):
+        # common mu(lam) across channels: diagonalise each channel, solve one count
+        ws, Ws = [], []
+        for c in range(nspin):
+            w, W = np.linalg.eigh(np.diag(eps2[c]) + lam * Hp[c])
+            ws.append(w)
+            Ws.append(W)
+        mu_l = bf.fermi_level(np.concatenate(ws), ne, kT, s)
+        out = []
+        for c in range(nspin):
+            f = bf.occupations(ws[c], mu_l, kT)
+            B = P[c].T @ Ws[c]
+            out.append((s / g.dv) * np.sum(B * B * f[None, :], axis=1))
+        return np.concatenate(out)
+
+    ref = bf.richardson_derivative(rho_all, 2e-4)
+    return _rel(drho[0].reshape(-1), ref)
+
+
+def pin_response_full_space():
+    """With N = M (all states) the subspace response is the exact full response:
+    Richardson central difference of the dense-diagonalisation density rho(V + lam dV)."""
+    n, L = (4, 4, 3), (3.0, 3.0, 2.2)
+    g = O.Grid(n, L)
+    V = small_wells(n, L, 15)
+    kT, ne, s = 0.05, 10.0, 2.0
+    lam_all, Q = np.linalg.eigh(bf.dense_hamiltonian(V, n, L))
+    Psi = Q.T.reshape((g.M,) + g.shape)
+    dV = np.random.default_rng(16).standard_normal(g.shape)
+    drho, _, _ = O.density_response(Psi[None], lam_all[None], g, ne, kT, dV[None, None], 1)
+    ref = bf.richardson_derivative(lambda t: bf.full_space_density(V + t * dV, n, L, ne, kT, s), 1e-3)
+    return _rel(drho.reshape(-1), ref)
+
+
+def invariants():
+    """Returns a dict of invariant violations: integral of delta rho, symmetry and
+    sign of chi0, constant perturbation, linearity, degenerate-rotation invariance."""
+    n, L = (5, 4, 4), (3.2, 2.6, 2.6)
+    N = 14
+    g, V, eps, Psi = _rr_system(n, L, N, seed=17)
+    kT, ne = 0.02, 14.0
+    rng = np.random.default_rng(18)
+    dV = rng.standard_normal((3, 1) + g.shape)
+    drho, mu, dmu = O.density_response(Psi[None], eps[None], g, ne, kT, dV, 1)
+    out = {}
+    norm = np.abs(drho).max()
+    out["integral"] = float(np.max(np.abs(g.dv * drho.reshape(3, -1).sum(axis=1)))) / (g.dv * norm * g.M)
+    ip = lambda a, b: g.dv * float(np.sum(a * b))  # noqa: E731
+    c01, c10 = ip(dV[0], drho[1]), ip(dV[1], drho[0])
+    out["symmetry"] = abs(c01 - c10) / max(abs(c01), 1e-300)
+    quad = [ip(dV[k], drho[k]) for k in range(3)]
+    out["nsd"] = max(0.0, max(quad))
+    const = np.full((1, 1) + g.shape, 0.7)
+    dc, _, _ = O.density_response(Psi[None], eps[None], g, ne, kT, const, 1)
+    out["constant"] = float(np.abs(dc).max()) / norm
+    comb = (2.0 * dV[0] - 0.5 * dV[2])[None]
+    dl, _, _ = O.density_response(Psi[None], eps[None], g, ne, kT, comb, 1)
+    out["linearity"] = _rel(dl[0], 2.0 * drho[0] - 0.5 * drho[2])
+    # rotation inside an exactly degenerate pair leaves delta rho unchanged
+    eps_d = eps.copy()
+    eps_d[6] = eps_d[5]
+    d1, _, _ = O.density_response(Psi[None], eps_d[None], g, ne, kT, dV[:1], 1)
+    Pr = Psi.copy()
+    c, s_ = np.cos(0.7), np.sin(0.7)
+    Pr[5], Pr[6] = c * Psi[5] + s_ * Psi[6], -s_ * Psi[5] + c * Psi[6]
+    d2, _, _ = O.density_response(Pr[None], eps_d[None], g, ne, kT, dV[:1], 1)
+    out["degenerate_rotation"] = _rel(d2, d1)
+    return out
+
+
+def pin_lindhard():
+    """V = 0 with all M states: dV = cos(q.x) gives delta rho = chi0(q) cos(q.x) with the
+    discrete Lindhard sum chi0(q) = (s/Omega) sum_k F(e_k, e_{k+q}) over grid
+    wavevectors, e_k = sum_d (1 - cos(2 pi k_d/n_d))/h_d^2 in closed form."""
+    n, L = (4, 4, 4), (2.8, 2.8, 2.8)
+    g = O.Grid(n, L)
+    kT, ne, s = 0.15, 12.0, 2.0
+    lam, Q = np.linalg.eigh(bf.dense_hamiltonian(np.zeros(g.shape), n, L))
+    Psi = Q.T.reshape((g.M,) + g.shape)
+    ks = [(kx, ky, kz) for kz in range(n[2]) for ky in range(n[1]) for kx in range(n[0])]
+    ek = {k: sum((1 - np.cos(2 * np.pi * k[d] / n[d])) / g.h[d] ** 2 for d in range(3)) for k in ks}
+    mu = bf.fermi_level(np.array(list(ek.values())), ne, kT, s)
+    z, y, x = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    err = 0.0
+    for q in [(1, 0, 0), (1, 1, 0), (2, 1, 3), (2, 2, 2)]:
+        dV = np.cos(2 * np.pi * (q[0] * x / n[0] + q[1] * y / n[1] + q[2] * z / n[2]))
+        drho, mu_o, _ = O.density_response(Psi[None], lam[None], g, ne, kT, dV[None, None], 1)
+        chi = 0.0
+        for k in ks:
+            kq = tuple((k[d] + q[d]) % n[d] for d in range(3))
+            chi += bf.fd_scalar(ek[k], ek[kq], mu, kT)
+        chi *= s / (g.M * g.dv)
+        err = max(err, _rel(drho[0, 0], chi * dV), abs(mu_o - mu))
+    return err
+
+
+# ------------------------------------------------------------------ Hartree kernel
+def pin_hartree_plane_wave():
+    n, L = (6, 5, 8), (3.0, 2.5, 4.1)
+    g = O.Grid(n, L)
+    z, y, x = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    err = 0.0
+    for q in [(1, 0, 0), (1, 2, 3), (3, 1, 4), (0, 0, 1)]:
+        th = [2 * np.pi * q[d] / n[d] for d in range(3)]
+        u = np.cos(th[0] * x + th[1] * y + th[2] * z + 0.3)
+        lam = sum((2 - 2 * np.cos(th[d])) / g.h[d] ** 2 for d in range(3))
+        err = max(err, _rel(O.hartree_kernel(u, g), (4 * np.pi / lam) * u))
+    return err
+
+
+def pin_hartree_poisson():
+    """-Lap_h (K u) = 4 pi (u - mean u), with the Laplacian taken from the stencil
+    (H with V = 0 is -1/2 Lap_h) rather than the Fourier symbol."""
+    n, L = (6, 7, 5), (3.0, 3.5, 2.5)
+    g = O.Grid(n, L)
+    u = np.random.default_rng(19).standard_normal(g.shape)
+    vh = O.hartree_kernel(u, g)
+    lap = -2.0 * O.hamiltonian_apply(vh[None], np.zeros(g.shape), g)[0]
+    return _rel(-lap, 4 * np.pi * (u - u.mean()))
+
+
+def pin_residual_derivative_spin():
+    """Spin pairs: every channel sees the Hartree potential of u_up + u_down, and
+    t = delta rho - u."""
+    n, L = (4, 4, 4), (3.0, 3.0, 3.0)
+    N = 10
+    g, V, eps, Psi = _rr_system(n, L, N, seed=20, passes=3, degree=8)
+    rng = np.random.default_rng(21)
+    u = rng.standard_normal((2, 2) + g.shape)
+    eps2 = np.stack([eps, eps + 0.01])
+    Psi2 = np.stack([Psi, Psi])
+    t, mu, dmu = O.residual_derivative(Psi2, eps2, g, 9.0, 0.02, u, 2)
+    dV = np.empty_like(u)
+    for k in range(2):
+        vh = O.hartree_kernel(u[k, 0] + u[k, 1], g)
+        dV[k, 0] = vh
+        dV[k, 1] = vh
+    drho, _, _ = O.density_response(Psi2, eps2, g, 9.0, 0.02, dV, 2)
+    return _rel(t, drho - u)
+
+
+# ------------------------------------------------------------------ recursion (Eqs. (23)-(24))
+def recursion_errors(depths=(4, 6, 8, 10, 12)):
+    """Error of the recursive Fermi-operator response against the exact divided
+    differences, for growing recursion depth T (fixed mu)."""
+    rng = np.random.default_rng(22)
+    N = 24
+    eps = np.sort(rng.uniform(-0.3, 0.3, N))
+    A = rng.standard_normal((N, N))
+    Hp = 0.5 * (A + A.T)
+    mu, kT = 0.01, 0.02
+    exact = O.divided_differences(eps, mu, kT) * Hp
+    errs = []
+    for T in depths:
+        _, xp = O.recursive_fermi_response(eps, mu, kT, Hp, T)
+        errs.append(_rel(xp, exact))
+    return errs

@@ -1,0 +1,142 @@
+"""Plant plausible mistakes in the oracle (on the CPU) and check that the pins
+notice each one: the pins have teeth."""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.lrdm_oracle as L
+from tests import pins as P
+
+
+def _patch(monkeypatch, name, fn):
+    monkeypatch.setattr(L, name, fn)
+    monkeypatch.setattr(oracle, name, fn)
+
+
+def _fails(check):
+    try:
+        return not check()
+    except Exception:
+        return True
+
+
+ORIG = {k: getattr(L, k) for k in dir(L) if not k.startswith("__")}
+
+
+def m_drop_dmu(mp):
+    _patch(mp, "fermi_shift", lambda Hp, fp: 0.0)
+    return lambda: P.invariants()["integral"] < 1e-13 and P.pin_response_subspace_fd() < 1e-8
+
+
+def m_flip_F(mp):
+    _patch(mp, "divided_differences", lambda e, mu, kT: -ORIG["divided_differences"](e, mu, kT))
+    return lambda: P.invariants()["nsd"] == 0.0
+
+
+def m_shift_F_index(mp):
+    _patch(mp, "divided_differences", lambda e, mu, kT: ORIG["divided_differences"](np.roll(e, 1), mu, kT))
+    return lambda: P.pin_response_subspace_fd() < 1e-8
+
+
+def m_spin_factor(mp):
+    _patch(mp, "spin_factor", lambda nspin: 1.0)
+    return lambda: P.pin_response_full_space() < 1e-8
+
+
+def m_laplacian_half(mp):
+    def bad(Y, V, grid):
+        return ORIG["hamiltonian_apply"](Y, V, grid) * 1.0 + 0.5 * (ORIG["hamiltonian_apply"](Y, 0 * V, grid))
+    _patch(mp, "hamiltonian_apply", bad)
+    return lambda: P.pin_plane_wave() < 1e-13
+
+
+def m_cheb_sigma_sign(mp):
+    def bad(X, V, grid, degree, a, b, a0):
+        e, c0 = (b - a) / 2, (b + a) / 2
+        s1 = e / (a0 - c0)
+        yp = X.copy()
+        y = (s1 / e) * (L.hamiltonian_apply(yp, V, grid) - c0 * yp)
+        s = s1
+        for _ in range(2, degree + 1):
+            sn = 1.0 / (2.0 / s1 + s)
+            yn = (2 * sn / e) * (L.hamiltonian_apply(y, V, grid) - c0 * y) - s * sn * yp
+            yp, y, s = y, yn, sn
+        return y
+    _patch(mp, "chebyshev_filter", bad)
+    return lambda: P.pin_filter_polynomial() < 1e-11
+
+
+def m_hartree_no_4pi(mp):
+    _patch(mp, "hartree_kernel", lambda u, g: ORIG["hartree_kernel"](u, g) / (4 * np.pi))
+    return lambda: P.pin_hartree_plane_wave() < 1e-12
+
+
+def m_projection_layout(mp):
+    def bad(Psi, dV):
+        N = Psi.shape[0]
+        Pm = Psi.reshape(-1, N)                      # wrong layout: M x N read from N x M data
+        return Pm.T @ (dV.reshape(-1)[:, None] * Pm)
+    _patch(mp, "projected_perturbation", bad)
+    return lambda: P.pin_response_subspace_fd() < 1e-8
+
+
+def m_density_no_dv(mp):
+    _patch(mp, "density_from_matrix", lambda Psi, G, dv, s: ORIG["density_from_matrix"](Psi, G, 1.0, s))
+    return lambda: P.pin_response_full_space() < 1e-8
+
+
+def m_rr_no_rotation(mp):
+    def bad(Y, V, grid):
+        N = Y.shape[0]
+        Q, _ = np.linalg.qr(Y.reshape(N, -1).T)
+        HQ = L.hamiltonian_apply(Q.T.reshape(Y.shape), V, grid).reshape(N, -1).T
+        eps = np.linalg.eigvalsh(Q.T @ HQ)
+        return eps, Q.T.reshape(Y.shape)
+    _patch(mp, "rayleigh_ritz", bad)
+    return lambda: P.pin_rr_generalized() < 1e-11
+
+
+def m_bisection_direction(mp):
+    def bad(eps, ne, kT, nspin=1, max_iter=200):
+        eps = np.asarray(eps).reshape(nspin, -1)
+        s = L.spin_factor(nspin)
+        lo, hi = eps.min() - 50 * kT, eps.max() + 50 * kT
+        for _ in range(max_iter):
+            mid = 0.5 * (lo + hi)
+            if s * np.sum(L.fermi_dirac(eps, mid, kT)[0]) > ne:
+                lo = mid
+            else:
+                hi = mid
+        return 0.5 * (lo + hi), True
+    _patch(mp, "fermi_level", bad)
+    return lambda: P.pin_fermi_level() < 1e-12
+
+
+def m_spin_channel_potential(mp):
+    def bad(Psi, eps, grid, ne, kT, u, nspin=1):
+        u = u.reshape((-1, nspin) + grid.shape)
+        dV = np.stack([[L.hartree_kernel(u[k, c], grid) for c in range(nspin)] for k in range(u.shape[0])])
+        drho, mu, dmu = L.density_response(Psi, eps, grid, ne, kT, dV, nspin)
+        return drho - u, mu, dmu
+    _patch(mp, "residual_derivative", bad)
+    return lambda: P.pin_residual_derivative_spin() < 1e-14
+
+
+def m_fermi_omf_subtraction_sign(mp):
+    def bad(eps, mu, kT):
+        f, omf, fp = ORIG["fermi_dirac"](eps, mu, kT)
+        return f, omf, f * omf / kT                  # wrong sign of f'
+    _patch(mp, "fermi_dirac", bad)
+    return lambda: P.pin_divided_differences_decimal() < 1e-13 and P.pin_response_subspace_fd() < 1e-8
+
+
+MUTANTS = [m_drop_dmu, m_flip_F, m_shift_F_index, m_spin_factor, m_laplacian_half,
+           m_cheb_sigma_sign, m_hartree_no_4pi, m_projection_layout, m_density_no_dv,
+           m_rr_no_rotation, m_bisection_direction, m_spin_channel_potential,
+           m_fermi_omf_subtraction_sign]
+
+
+@pytest.mark.parametrize("mutant", MUTANTS, ids=[m.__name__ for m in MUTANTS])
+def test_planted_mistake_is_caught(mutant, monkeypatch):
+    check = mutant(monkeypatch)
+    assert _fails(check), f"pins did not notice {mutant.__name__}"
