@@ -1,0 +1,192 @@
+/*
+ * lrdm.h -- C ABI of the LRDM density-response hot path on MI355X (gfx950).
+ *
+ * The method is the low-rank dielectric-matrix (LRDM) preconditioner of
+ * Das & Gavini, "Accelerating SCF iterations in Kohn-Sham DFT using a low rank
+ * approximation of the dielectric matrix".  Each rank-1 term needs the Gateaux
+ * derivative t_i of the SCF residual along a direction function u_i
+ * (Sec. II B, Eq. (7)), which the paper evaluates in the Chebyshev-filtered
+ * subspace (Sec. II C).  This library computes that path on one GPU:
+ *
+ *   chfsi_filter            Y = T_c(Hbar) X / T_c(ybar0)        (Sec. II C)
+ *   subspace_rayleigh_ritz  Psi_R, eps from the filtered block   (Sec. II C, Eq. (15))
+ *   density_response        delta rho[dV] in span(Psi_R)         (Eqs. (19)-(22))
+ *   lrdm_residual_derivative t = chi0 K_c u - u                  (Eqs. (3), (7))
+ *
+ * plus the single steps they are made of (stencil Hamiltonian, occupations and
+ * divided differences, projected perturbation, Hartree kernel).
+ *
+ * Discretisation (the paper's finite-element objects carried to a periodic
+ * finite-difference grid, as allowed at the end of Sec. II D):
+ *   grid n = (nx, ny, nz) points, spacing h_d = L_d / n_d, dv = hx*hy*hz,
+ *   M = nx*ny*nz; H = -1/2 Lap_h + diag(V) with the 7-point periodic stencil;
+ *   a block of N vectors is state-major: element (i, z, y, x) lives at
+ *   i*M + (z*ny + y)*nx + x ("x fastest"); Ritz vectors are l2-orthonormal,
+ *   so rho(x_p) = (s/dv) sum_i f_i Psi_ip^2 with s = 2 (spin restricted) or
+ *   s = 1 per channel (spin polarised, Sec. II D).
+ *
+ * Conventions for every entry point:
+ *   - Every array argument is a caller-owned DEVICE pointer on the context's
+ *     device, contiguous, in the layout stated.  The library never frees or
+ *     keeps a caller pointer after the call returns.
+ *   - Calls are asynchronous on the context's HIP stream (see
+ *     lrdm_set_checks for the synchronous checking mode).  One context per
+ *     stream; a context is not thread-safe.
+ *   - The context owns a device workspace, grown on demand up to the
+ *     workspace_limit given at creation; a call that would need more returns
+ *     LRDM_ENOMEM before launching anything.
+ *   - Arguments are validated on the host before any launch: positive sizes,
+ *     N <= M, 0 < N_e < s*N*nspin (N > N_e/2 for one channel, Eq. (14)),
+ *     kT > 0, degree >= 1, a0 < a < b, finite scalars, non-NULL pointers.
+ *     Failures return LRDM_EINVAL and leave a message for lrdm_last_error.
+ *     Validation runs before the context is used, so it also works with a
+ *     NULL context (which is itself reported as LRDM_EINVAL afterwards).
+ *   - HIP failures return LRDM_EDEVICE with the HIP message.
+ *   - Precision forms (lrdm_prec): LRDM_FP64 keeps blocks in double;
+ *     LRDM_FP32 keeps blocks in float and runs the long contractions on
+ *     FP32 matrix cores with FP64 partial sums; LRDM_BF16X3 keeps blocks in
+ *     float and runs the projection / back-projection contractions on BF16
+ *     matrix cores with each operand split as hi + lo (hi*hi + hi*lo + lo*hi,
+ *     FP32 accumulation inside a K tile, FP64 across tiles).  Potentials,
+ *     eigenvalues, occupations, densities, mu and mu' are always double, and
+ *     the subspace eigensolver, the Fermi-level bisection and the divided
+ *     differences always run in FP64 on the GPU.
+ */
+#ifndef LRDM_H
+#define LRDM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LRDM_OK = 0,
+  LRDM_EINVAL = -1,       /* invalid argument (see lrdm_last_error) */
+  LRDM_ENOMEM = -2,       /* workspace would exceed the context's limit, or allocation failed */
+  LRDM_EDEVICE = -3,      /* a HIP call failed */
+  LRDM_ENOTCONV = -4,     /* bisection or eigensolver did not converge (checking mode only) */
+  LRDM_ENONFINITE = -5,   /* NaN/Inf found in an output (checking mode only) */
+  LRDM_EUNSUPPORTED = -6  /* valid request this build does not implement */
+} lrdm_status;
+
+typedef enum { LRDM_FP64 = 0, LRDM_FP32 = 1, LRDM_BF16X3 = 2 } lrdm_prec;
+
+/* Periodic orthorhombic cell: n[d] points and length L[d] (bohr) along x, y, z. */
+typedef struct { int32_t n[3]; double L[3]; } lrdm_grid;
+
+/* Occupation model of Eq. (1): Fermi-Dirac with temperature kT (Ha) and
+ * n_electrons in total (over both channels when nspin = 2). */
+typedef struct { int32_t nspin; double kT; double n_electrons; } lrdm_occ;
+
+typedef struct lrdm_ctx lrdm_ctx;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context bound to HIP device `device` and stream `hip_stream`
+ * (a hipStream_t; NULL means the default stream).  workspace_limit is the
+ * largest device workspace, in bytes, the context may allocate (0 = no limit).
+ * Selects `device` as current for the calling thread. */
+lrdm_status lrdm_create(lrdm_ctx** ctx, int device, void* hip_stream, size_t workspace_limit);
+
+/* Release the context and its workspace (synchronises its stream first). */
+lrdm_status lrdm_destroy(lrdm_ctx* ctx);
+
+/* Switch the stream later calls are enqueued on. */
+lrdm_status lrdm_set_stream(lrdm_ctx* ctx, void* hip_stream);
+
+/* level 0 (default): calls only enqueue work.  level 1: every call also
+ * synchronises its stream and returns LRDM_ENOTCONV / LRDM_ENONFINITE when a
+ * device-side check failed (bisection bracket, eigensolver sweeps, NaN/Inf). */
+lrdm_status lrdm_set_checks(lrdm_ctx* ctx, int level);
+
+/* Bytes of device workspace the context currently holds. */
+size_t lrdm_workspace_bytes(const lrdm_ctx* ctx);
+
+/* Message of the last failure on this context; with ctx == NULL, the last
+ * failure of a call made on this thread without a usable context.  The string
+ * stays valid until the next call on the same context / thread. */
+const char* lrdm_last_error(const lrdm_ctx* ctx);
+
+/* ---------------------------------------------------------------- single steps */
+
+/* Y = H X with H = -1/2 Lap_h + diag(V) (Eq. (1), 7-point periodic stencil).
+ * V [nz][ny][nx] double; X, Y [N][nz][ny][nx], double (FP64) or float
+ * (FP32, BF16X3).  X and Y must not overlap. */
+lrdm_status lrdm_hamiltonian_apply(lrdm_ctx* ctx, const lrdm_grid* grid, const double* V,
+                                   const void* X, void* Y, int32_t N, lrdm_prec prec);
+
+/* Fermi level and occupations of Eq. (1), and the divided-difference matrix
+ * that turns H' into the subspace density-matrix response (Eq. (22)):
+ *   mu: s sum f(eps) = N_e by FP64 bisection on [min eps - 50 kT, max eps + 50 kT]
+ *       until the bracket is within 2 ulp (at most 200 halvings);
+ *   f_i = 1/(1 + exp((eps_i - mu)/kT)), fprime_i = -f_i (1 - f_i)/kT;
+ *   F_ij = (f_i - f_j)/(eps_i - eps_j), F_ii = fprime_i, evaluated as
+ *       -(1/kT) f_lo (1 - f_hi) expm1(z)/z, z = (eps_lo - eps_hi)/kT <= 0.
+ * eps [nspin][N] double.  Outputs (device, double): mu [1], f [nspin][N],
+ * fprime [nspin][N], F [nspin][N][N]; any output may be NULL. */
+lrdm_status lrdm_fermi_occupations(lrdm_ctx* ctx, const double* eps, int32_t N, const lrdm_occ* occ,
+                                   double* mu, double* f, double* fprime, double* F);
+
+/* Projected perturbation Hbreve'_k = Psi_R^T diag(dV_k) Psi_R (Eq. (21)) for
+ * k < r and each channel.  Psi [nspin][N][M] (double for FP64, float
+ * otherwise); dV [r][nspin][M] double; Hp [r][nspin][N][N] double (full,
+ * symmetric). */
+lrdm_status lrdm_projected_perturbation(lrdm_ctx* ctx, const lrdm_grid* grid, const void* Psi,
+                                        int32_t N, int32_t nspin, const double* dV, int32_t r,
+                                        lrdm_prec prec, double* Hp);
+
+/* Hartree kernel of Eq. (3): dV_k = 4 pi (-Lap_h)^{-1} u_k with the same
+ * 7-point Laplacian as H and the q = 0 component removed.  u, dV [r][M]
+ * double; may alias. */
+lrdm_status lrdm_hartree_kernel(lrdm_ctx* ctx, const lrdm_grid* grid, const double* u,
+                                double* dV, int32_t r);
+
+/* ---------------------------------------------------------------- hot path */
+
+/* ChFSI Chebyshev filter of degree `degree` (Sec. II C): with e = (b - a)/2,
+ * c0 = (b + a)/2, Hbar = (H - c0)/e maps the unwanted interval [a, b] to
+ * [-1, 1]; the output is Y = T_c(Hbar) X / T_c((a0 - c0)/e), computed by the
+ * scaled three-term recurrence of Zhou, Saad, Tiago & Chelikowsky (2006).
+ * a0 < a < b: a0 a lower bound of the spectrum, a the top of the wanted
+ * part, b an upper bound of the spectrum.  X, Y [N][nz][ny][nx] (double for
+ * FP64, float otherwise), must not overlap; X is not modified. */
+lrdm_status chfsi_filter(lrdm_ctx* ctx, const lrdm_grid* grid, const double* V,
+                         const void* X, void* Y, int32_t N, lrdm_prec prec,
+                         int32_t degree, double a, double b, double a0);
+
+/* Rayleigh-Ritz step of ChFSI (Sec. II C, Eq. (15)): orthonormalise the
+ * filtered block, project H, diagonalise the N x N projection in FP64 on the
+ * GPU and rotate.  Psi [N][nz][ny][nx]: in = filtered block, out = Ritz
+ * vectors (l2-orthonormal); eps [N] double, ascending.  Each channel of a
+ * spin-polarised system is a separate call with its own V. */
+lrdm_status subspace_rayleigh_ritz(lrdm_ctx* ctx, const lrdm_grid* grid, const double* V,
+                                   void* Psi, int32_t N, lrdm_prec prec, double* eps);
+
+/* Subspace density response (Eqs. (19)-(22), traceless condition after
+ * Eq. (24); per channel without the factor 2 in Sec. II D):
+ *   Hp_k = Psi^T diag(dV_k) Psi,  mu'_k = sum f'_i Hp_k,ii / sum f'_i (over
+ *   both channels), Gamma_k = F o Hp_k - mu'_k diag(f'),
+ *   drho_k(x_p) = (s/dv) sum_ij Psi_ip Gamma_k,ij Psi_jp.
+ * Psi [nspin][N][M]; eps [nspin][N]; dV, drho [r][nspin][M] double.
+ * mu [1] and dmu [r] (device, double) receive mu and mu'_k; either may be NULL. */
+lrdm_status density_response(lrdm_ctx* ctx, const lrdm_grid* grid, const void* Psi,
+                             const double* eps, int32_t N, const lrdm_occ* occ,
+                             const double* dV, int32_t r, lrdm_prec prec,
+                             double* drho, double* mu, double* dmu);
+
+/* Gateaux derivative of the SCF residual along u_k (Eq. (7)) with
+ * J = chi0 K - I (Eq. (3)) and K = K_c: every channel sees
+ * dV_k = K_c (sum_sigma u_k,sigma); t_k = drho[dV_k] - u_k.
+ * u, t [r][nspin][M] double; may not alias. */
+lrdm_status lrdm_residual_derivative(lrdm_ctx* ctx, const lrdm_grid* grid, const void* Psi,
+                                     const double* eps, int32_t N, const lrdm_occ* occ,
+                                     const double* u, int32_t r, lrdm_prec prec, double* t);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LRDM_H */

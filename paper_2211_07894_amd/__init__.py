@@ -1,0 +1,22 @@
+"""MI355X-native hot path of the LRDM preconditioner (Das & Gavini): ChFSI
+filter, Rayleigh-Ritz, subspace density response and residual derivative as
+hand-written HIP kernels behind the C ABI of include/lrdm.h.
+
+The Python layer only marshals torch device tensors into that ABI; see
+``paper_2211_07894_amd.lrdm``.
+"""
+from .lrdm import (  # noqa: F401
+    Grid,
+    Occupation,
+    LrdmError,
+    library,
+    context,
+    hamiltonian_apply,
+    fermi_occupations,
+    projected_perturbation,
+    hartree_kernel,
+    chfsi_filter,
+    subspace_rayleigh_ritz,
+    density_response,
+    residual_derivative,
+)

@@ -1,0 +1,460 @@
+// extern "C" entry points of liblrdm (declared in include/lrdm.h): argument
+// validation, workspace sizing and the sequence of kernel launches of each call.
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <stdexcept>
+#include <string>
+
+#include "lrdm_internal.h"
+
+namespace {
+
+thread_local std::string t_err;
+
+lrdm_status fail(lrdm_ctx* ctx, lrdm_status st, const std::string& msg) {
+  t_err = msg;
+  if (ctx) ctx->err = msg;
+  return st;
+}
+
+lrdm_status fail_hip(lrdm_ctx* ctx, const char* where, hipError_t e) {
+  return fail(ctx, LRDM_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+struct WsOverflow : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+
+#define LRDM_CHECK(ctx, expr)                                  \
+  do {                                                         \
+    const char* m_ = (expr);                                   \
+    if (m_) return fail((ctx), LRDM_EINVAL, m_);               \
+  } while (0)
+
+#define LRDM_NONNULL(ctx, p, name)                                              \
+  do {                                                                          \
+    if (!(p)) return fail((ctx), LRDM_EINVAL, std::string(name) + " is NULL");  \
+  } while (0)
+
+// Common prologue once arguments are valid: the context must exist, its device
+// becomes current and the workspace holds `bytes`.
+lrdm_status begin(lrdm_ctx* ctx, size_t bytes) {
+  if (!ctx) return fail(nullptr, LRDM_EINVAL, "ctx is NULL");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return fail_hip(ctx, "hipSetDevice", e);
+  ctx->ws_top = 0;
+  return lrdm::ws_reserve(ctx, bytes + (1u << 20));
+}
+
+// Epilogue: in checking mode wait for the stream and turn device status words
+// into status codes.
+lrdm_status finish(lrdm_ctx* ctx, lrdm_status st) {
+  if (st != LRDM_OK || !ctx->checks) return st;
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return fail_hip(ctx, "hipStreamSynchronize", e);
+  int h[LRDM_DS_COUNT] = {0, 0, 0, 0};
+  e = hipMemcpy(h, ctx->dstatus, sizeof(h), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail_hip(ctx, "status read", e);
+  e = hipMemset(ctx->dstatus, 0, sizeof(h));
+  if (e != hipSuccess) return fail_hip(ctx, "status reset", e);
+  if (h[LRDM_DS_BISECT]) return fail(ctx, LRDM_ENOTCONV, "Fermi-level bisection did not converge");
+  if (h[LRDM_DS_EIGH]) return fail(ctx, LRDM_ENOTCONV, "subspace eigensolver did not converge");
+  if (h[LRDM_DS_NONFINITE]) return fail(ctx, LRDM_ENONFINITE, "non-finite value in an output");
+  return LRDM_OK;
+}
+
+template <typename F>
+lrdm_status guarded(lrdm_ctx* ctx, F&& body) {
+  try {
+    return finish(ctx, body());
+  } catch (const WsOverflow& ex) {
+    return fail(ctx, LRDM_ENOMEM, ex.what());
+  } catch (const std::bad_alloc&) {
+    return fail(ctx, LRDM_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(ctx, LRDM_EDEVICE, "unexpected internal error");
+  }
+}
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const char* pa = static_cast<const char*>(a);
+  const char* pb = static_cast<const char*>(b);
+  return pa < pb + nb && pb < pa + na;
+}
+
+}  // namespace
+
+namespace lrdm {
+
+Grid3 make_grid3(const lrdm_grid* g) {
+  Grid3 r;
+  r.nx = g->n[0];
+  r.ny = g->n[1];
+  r.nz = g->n[2];
+  r.hx = g->L[0] / g->n[0];
+  r.hy = g->L[1] / g->n[1];
+  r.hz = g->L[2] / g->n[2];
+  r.M = (int64_t)r.nx * r.ny * r.nz;
+  r.dv = r.hx * r.hy * r.hz;
+  return r;
+}
+
+lrdm_status ws_reserve(lrdm_ctx* ctx, size_t bytes) {
+  if (bytes <= ctx->ws_cap) return LRDM_OK;
+  if (ctx->limit && bytes > ctx->limit) {
+    char msg[160];
+    std::snprintf(msg, sizeof msg, "workspace of %zu bytes exceeds the context limit of %zu", bytes,
+                  ctx->limit);
+    return fail(ctx, LRDM_ENOMEM, msg);
+  }
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return fail_hip(ctx, "hipStreamSynchronize", e);
+  if (ctx->ws) {
+    e = hipFree(ctx->ws);
+    ctx->ws = nullptr;
+    ctx->ws_cap = 0;
+    if (e != hipSuccess) return fail_hip(ctx, "hipFree", e);
+  }
+  e = hipMalloc(&ctx->ws, bytes);
+  if (e != hipSuccess) {
+    ctx->ws = nullptr;
+    return fail(ctx, LRDM_ENOMEM, std::string("hipMalloc of workspace: ") + hipGetErrorString(e));
+  }
+  ctx->ws_cap = bytes;
+  return LRDM_OK;
+}
+
+void* ws_take(lrdm_ctx* ctx, size_t bytes) {
+  const size_t b = ws_align(bytes);
+  if (ctx->ws_top + b > ctx->ws_cap) throw WsOverflow("internal workspace sizing error");
+  void* p = static_cast<char*>(ctx->ws) + ctx->ws_top;
+  ctx->ws_top += b;
+  return p;
+}
+
+size_t tn_bytes(int N, int64_t M, int batch, lrdm_prec prec) {
+  return tn_workspace_bytes(N, M, batch, prec);
+}
+
+}  // namespace lrdm
+
+using namespace lrdm;
+
+// ===================================================================== context
+
+extern "C" lrdm_status lrdm_create(lrdm_ctx** ctx, int device, void* hip_stream,
+                                   size_t workspace_limit) {
+  if (!ctx) return fail(nullptr, LRDM_EINVAL, "ctx output pointer is NULL");
+  *ctx = nullptr;
+  if (device < 0) return fail(nullptr, LRDM_EINVAL, "device must be >= 0");
+  hipError_t e = hipSetDevice(device);
+  if (e != hipSuccess) return fail_hip(nullptr, "hipSetDevice", e);
+  lrdm_ctx* c = new (std::nothrow) lrdm_ctx();
+  if (!c) return fail(nullptr, LRDM_ENOMEM, "host allocation failed");
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->limit = workspace_limit;
+  e = hipMalloc(&c->dstatus, 16 * sizeof(int));
+  if (e != hipSuccess) {
+    delete c;
+    return fail_hip(nullptr, "hipMalloc status", e);
+  }
+  e = hipMemset(c->dstatus, 0, 16 * sizeof(int));
+  if (e != hipSuccess) {
+    (void)hipFree(c->dstatus);
+    delete c;
+    return fail_hip(nullptr, "hipMemset status", e);
+  }
+  *ctx = c;
+  return LRDM_OK;
+}
+
+extern "C" lrdm_status lrdm_destroy(lrdm_ctx* ctx) {
+  if (!ctx) return fail(nullptr, LRDM_EINVAL, "ctx is NULL");
+  (void)hipSetDevice(ctx->device);
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->dstatus) (void)hipFree(ctx->dstatus);
+  delete ctx;
+  if (e != hipSuccess) return fail_hip(nullptr, "hipStreamSynchronize", e);
+  return LRDM_OK;
+}
+
+extern "C" lrdm_status lrdm_set_stream(lrdm_ctx* ctx, void* hip_stream) {
+  if (!ctx) return fail(nullptr, LRDM_EINVAL, "ctx is NULL");
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  return LRDM_OK;
+}
+
+extern "C" lrdm_status lrdm_set_checks(lrdm_ctx* ctx, int level) {
+  if (!ctx) return fail(nullptr, LRDM_EINVAL, "ctx is NULL");
+  if (level < 0 || level > 1) return fail(ctx, LRDM_EINVAL, "checks level must be 0 or 1");
+  ctx->checks = level;
+  return LRDM_OK;
+}
+
+extern "C" size_t lrdm_workspace_bytes(const lrdm_ctx* ctx) { return ctx ? ctx->ws_cap : 0; }
+
+extern "C" const char* lrdm_last_error(const lrdm_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : t_err.c_str();
+}
+
+// ===================================================================== single steps
+
+extern "C" lrdm_status lrdm_hamiltonian_apply(lrdm_ctx* ctx, const lrdm_grid* grid,
+                                              const double* V, const void* X, void* Y, int32_t N,
+                                              lrdm_prec prec) {
+  LRDM_CHECK(ctx, check_grid(grid));
+  LRDM_CHECK(ctx, check_block(grid, N));
+  LRDM_CHECK(ctx, check_prec(prec));
+  LRDM_NONNULL(ctx, V, "V");
+  LRDM_NONNULL(ctx, X, "X");
+  LRDM_NONNULL(ctx, Y, "Y");
+  const Grid3 g = make_grid3(grid);
+  const size_t blk = (size_t)g.M * N * prec_bytes(prec);
+  if (overlaps(X, blk, Y, blk)) return fail(ctx, LRDM_EINVAL, "X and Y must not overlap");
+  lrdm_status st = begin(ctx, 0);
+  if (st != LRDM_OK) return st;
+  return guarded(ctx, [&]() -> lrdm_status {
+    hipError_t e = (prec == LRDM_FP64)
+        ? launch_cheb_step<double>(ctx, g, V, static_cast<const double*>(X), nullptr,
+                                   static_cast<double*>(Y), N, 1.0, 0.0, 0.0)
+        : launch_cheb_step<float>(ctx, g, V, static_cast<const float*>(X), nullptr,
+                                  static_cast<float*>(Y), N, 1.0, 0.0, 0.0);
+    return e == hipSuccess ? LRDM_OK : fail_hip(ctx, "hamiltonian_apply", e);
+  });
+}
+
+extern "C" lrdm_status lrdm_fermi_occupations(lrdm_ctx* ctx, const double* eps, int32_t N,
+                                              const lrdm_occ* occ, double* mu, double* f,
+                                              double* fprime, double* F) {
+  if (N < 1 || N > 8192) return fail(ctx, LRDM_EINVAL, "N must be in [1, 8192]");
+  LRDM_CHECK(ctx, check_occ(occ, N));
+  LRDM_NONNULL(ctx, eps, "eps");
+  const int ns = occ->nspin;
+  const size_t vec = (size_t)ns * N * sizeof(double);
+  lrdm_status st = begin(ctx, 4 * ws_align(vec) + ws_align(8));
+  if (st != LRDM_OK) return st;
+  return guarded(ctx, [&]() -> lrdm_status {
+    double* mu_d = mu ? mu : static_cast<double*>(ws_take(ctx, 8));
+    double* f_d = f ? f : static_cast<double*>(ws_take(ctx, vec));
+    double* o_d = static_cast<double*>(ws_take(ctx, vec));
+    double* fp_d = fprime ? fprime : static_cast<double*>(ws_take(ctx, vec));
+    hipError_t e = launch_fermi(ctx, eps, N, ns, occ->kT, occ->n_electrons, mu_d, f_d, o_d, fp_d, F);
+    return e == hipSuccess ? LRDM_OK : fail_hip(ctx, "fermi_occupations", e);
+  });
+}
+
+extern "C" lrdm_status lrdm_projected_perturbation(lrdm_ctx* ctx, const lrdm_grid* grid,
+                                                   const void* Psi, int32_t N, int32_t nspin,
+                                                   const double* dV, int32_t r, lrdm_prec prec,
+                                                   double* Hp) {
+  LRDM_CHECK(ctx, check_grid(grid));
+  LRDM_CHECK(ctx, check_block(grid, N));
+  LRDM_CHECK(ctx, check_rank(r));
+  LRDM_CHECK(ctx, check_prec(prec));
+  if (prec != LRDM_FP64) return fail(ctx, LRDM_EUNSUPPORTED, "only LRDM_FP64 is available for this call");
+  if (nspin != 1 && nspin != 2) return fail(ctx, LRDM_EINVAL, "nspin must be 1 or 2");
+  LRDM_NONNULL(ctx, Psi, "Psi");
+  LRDM_NONNULL(ctx, dV, "dV");
+  LRDM_NONNULL(ctx, Hp, "Hp");
+  const Grid3 g = make_grid3(grid);
+  lrdm_status st = begin(ctx, tn_bytes(N, g.M, r * nspin, prec));
+  if (st != LRDM_OK) return st;
+  return guarded(ctx, [&]() -> lrdm_status {
+    hipError_t e;
+    if (prec == LRDM_FP64)
+      e = launch_tn_sym<double>(ctx, static_cast<const double*>(Psi), nullptr, dV, g.M, N, g.M,
+                                nspin, r * nspin, prec, Hp);
+    else
+      e = launch_tn_sym<float>(ctx, static_cast<const float*>(Psi), nullptr, dV, g.M, N, g.M,
+                               nspin, r * nspin, prec, Hp);
+    return e == hipSuccess ? LRDM_OK : fail_hip(ctx, "projected_perturbation", e);
+  });
+}
+
+extern "C" lrdm_status lrdm_hartree_kernel(lrdm_ctx* ctx, const lrdm_grid* grid, const double* u,
+                                           double* dV, int32_t r) {
+  LRDM_CHECK(ctx, check_grid(grid));
+  LRDM_CHECK(ctx, check_rank(r));
+  LRDM_NONNULL(ctx, u, "u");
+  LRDM_NONNULL(ctx, dV, "dV");
+  const Grid3 g = make_grid3(grid);
+  const size_t scratch = 2 * (size_t)r * g.M * sizeof(double);
+  lrdm_status st = begin(ctx, ws_align(scratch) + hartree_workspace_bytes(g));
+  if (st != LRDM_OK) return st;
+  return guarded(ctx, [&]() -> lrdm_status {
+    double* s = static_cast<double*>(ws_take(ctx, scratch));
+    hipError_t e = launch_hartree(ctx, g, u, 1, dV, 1, r, s);
+    return e == hipSuccess ? LRDM_OK : fail_hip(ctx, "hartree_kernel", e);
+  });
+}
+
+// ===================================================================== hot path
+
+namespace {
+
+template <typename T>
+hipError_t run_filter(lrdm_ctx* ctx, const Grid3& g, const double* V, const T* X, T* Y, int N,
+                      int degree, double a, double b, double a0) {
+  T* W = static_cast<T*>(ws_take(ctx, (size_t)g.M * N * sizeof(T)));
+  const double e = (b - a) / 2.0, c0 = (b + a) / 2.0;
+  const double sigma1 = e / (a0 - c0);
+  // Y_k lands in bufA for odd k and bufB for even k; choose so that Y_c is in Y.
+  T* bufA = (degree % 2 == 1) ? Y : W;
+  T* bufB = (degree % 2 == 1) ? W : Y;
+  LRDM_HIP(launch_cheb_step<T>(ctx, g, V, X, nullptr, bufA, N, sigma1 / e, c0, 0.0));
+  double sigma = sigma1;
+  for (int k = 2; k <= degree; ++k) {
+    const double sigma_new = 1.0 / (2.0 / sigma1 - sigma);
+    const T* ykm1 = (k % 2 == 0) ? bufA : bufB;   // Y_{k-1}
+    const T* ykm2 = (k == 2) ? X : ((k % 2 == 0) ? bufB : bufA);  // Y_{k-2}
+    T* out = (k % 2 == 1) ? bufA : bufB;          // overwrites Y_{k-2} (k > 2)
+    LRDM_HIP(launch_cheb_step<T>(ctx, g, V, ykm1, ykm2, out, N, 2.0 * sigma_new / e, c0,
+                                 -sigma * sigma_new));
+    sigma = sigma_new;
+  }
+  return hipSuccess;
+}
+
+// Shared body of density_response and lrdm_residual_derivative.
+template <typename T>
+hipError_t run_response(lrdm_ctx* ctx, const Grid3& g, const T* Psi, const double* eps, int N,
+                        const lrdm_occ* occ, const double* dV, int r, lrdm_prec prec,
+                        const double* sub, double* out, double* mu, double* dmu) {
+  const int ns = occ->nspin;
+  const int batch = r * ns;
+  const size_t vec = (size_t)ns * N * sizeof(double);
+  double* mu_d = mu ? mu : static_cast<double*>(ws_take(ctx, 8));
+  double* dmu_d = dmu ? dmu : static_cast<double*>(ws_take(ctx, (size_t)r * 8));
+  double* f = static_cast<double*>(ws_take(ctx, vec));
+  double* omf = static_cast<double*>(ws_take(ctx, vec));
+  double* fp = static_cast<double*>(ws_take(ctx, vec));
+  double* F = static_cast<double*>(ws_take(ctx, (size_t)ns * N * N * sizeof(double)));
+  double* Hp = static_cast<double*>(ws_take(ctx, (size_t)batch * N * N * sizeof(double)));
+  LRDM_HIP(launch_fermi(ctx, eps, N, ns, occ->kT, occ->n_electrons, mu_d, f, omf, fp, F));
+  LRDM_HIP(launch_tn_sym<T>(ctx, Psi, nullptr, dV, g.M, N, g.M, ns, batch, prec, Hp));
+  LRDM_HIP(launch_gamma(ctx, Hp, F, fp, N, ns, r, dmu_d));
+  const double s = (ns == 1) ? 2.0 : 1.0;
+  LRDM_HIP(launch_backproj<T>(ctx, Psi, Hp, N, g.M, ns, batch, prec, s / g.dv, sub, out));
+  if (ctx->checks) LRDM_HIP(launch_check_finite(ctx, out, (int64_t)batch * g.M));
+  return hipSuccess;
+}
+
+size_t response_bytes(int N, int64_t M, int r, int ns, lrdm_prec prec) {
+  const int batch = r * ns;
+  return ws_align(8) + ws_align((size_t)r * 8) + 3 * ws_align((size_t)ns * N * 8) +
+         ws_align((size_t)ns * N * N * 8) + ws_align((size_t)batch * N * N * 8) +
+         ws_align(tn_bytes(N, M, batch, prec));
+}
+
+}  // namespace
+
+extern "C" lrdm_status chfsi_filter(lrdm_ctx* ctx, const lrdm_grid* grid, const double* V,
+                                    const void* X, void* Y, int32_t N, lrdm_prec prec,
+                                    int32_t degree, double a, double b, double a0) {
+  LRDM_CHECK(ctx, check_grid(grid));
+  LRDM_CHECK(ctx, check_block(grid, N));
+  LRDM_CHECK(ctx, check_prec(prec));
+  LRDM_CHECK(ctx, check_filter(degree, a, b, a0));
+  LRDM_NONNULL(ctx, V, "V");
+  LRDM_NONNULL(ctx, X, "X");
+  LRDM_NONNULL(ctx, Y, "Y");
+  const Grid3 g = make_grid3(grid);
+  const size_t blk = (size_t)g.M * N * prec_bytes(prec);
+  if (overlaps(X, blk, Y, blk)) return fail(ctx, LRDM_EINVAL, "X and Y must not overlap");
+  lrdm_status st = begin(ctx, ws_align(blk));
+  if (st != LRDM_OK) return st;
+  return guarded(ctx, [&]() -> lrdm_status {
+    hipError_t e = (prec == LRDM_FP64)
+        ? run_filter<double>(ctx, g, V, static_cast<const double*>(X), static_cast<double*>(Y), N,
+                             degree, a, b, a0)
+        : run_filter<float>(ctx, g, V, static_cast<const float*>(X), static_cast<float*>(Y), N,
+                            degree, a, b, a0);
+    return e == hipSuccess ? LRDM_OK : fail_hip(ctx, "chfsi_filter", e);
+  });
+}
+
+extern "C" lrdm_status subspace_rayleigh_ritz(lrdm_ctx* ctx, const lrdm_grid* grid,
+                                              const double* V, void* Psi, int32_t N,
+                                              lrdm_prec prec, double* eps) {
+  LRDM_CHECK(ctx, check_grid(grid));
+  LRDM_CHECK(ctx, check_block(grid, N));
+  LRDM_CHECK(ctx, check_prec(prec));
+  if (prec != LRDM_FP64) return fail(ctx, LRDM_EUNSUPPORTED, "only LRDM_FP64 is available for this call");
+  LRDM_NONNULL(ctx, V, "V");
+  LRDM_NONNULL(ctx, Psi, "Psi");
+  LRDM_NONNULL(ctx, eps, "eps");
+  const Grid3 g = make_grid3(grid);
+  lrdm_status st = begin(ctx, rr_workspace_bytes(N, g.M, prec));
+  if (st != LRDM_OK) return st;
+  return guarded(ctx, [&]() -> lrdm_status {
+    if (prec == LRDM_FP64)
+      return rayleigh_ritz<double>(ctx, g, V, static_cast<double*>(Psi), N, prec, eps);
+    return rayleigh_ritz<float>(ctx, g, V, static_cast<float*>(Psi), N, prec, eps);
+  });
+}
+
+extern "C" lrdm_status density_response(lrdm_ctx* ctx, const lrdm_grid* grid, const void* Psi,
+                                        const double* eps, int32_t N, const lrdm_occ* occ,
+                                        const double* dV, int32_t r, lrdm_prec prec, double* drho,
+                                        double* mu, double* dmu) {
+  LRDM_CHECK(ctx, check_grid(grid));
+  LRDM_CHECK(ctx, check_block(grid, N));
+  LRDM_CHECK(ctx, check_occ(occ, N));
+  LRDM_CHECK(ctx, check_rank(r));
+  LRDM_CHECK(ctx, check_prec(prec));
+  if (prec != LRDM_FP64) return fail(ctx, LRDM_EUNSUPPORTED, "only LRDM_FP64 is available for this call");
+  LRDM_NONNULL(ctx, Psi, "Psi");
+  LRDM_NONNULL(ctx, eps, "eps");
+  LRDM_NONNULL(ctx, dV, "dV");
+  LRDM_NONNULL(ctx, drho, "drho");
+  const Grid3 g = make_grid3(grid);
+  lrdm_status st = begin(ctx, response_bytes(N, g.M, r, occ->nspin, prec));
+  if (st != LRDM_OK) return st;
+  return guarded(ctx, [&]() -> lrdm_status {
+    hipError_t e = (prec == LRDM_FP64)
+        ? run_response<double>(ctx, g, static_cast<const double*>(Psi), eps, N, occ, dV, r, prec,
+                               nullptr, drho, mu, dmu)
+        : run_response<float>(ctx, g, static_cast<const float*>(Psi), eps, N, occ, dV, r, prec,
+                              nullptr, drho, mu, dmu);
+    return e == hipSuccess ? LRDM_OK : fail_hip(ctx, "density_response", e);
+  });
+}
+
+extern "C" lrdm_status lrdm_residual_derivative(lrdm_ctx* ctx, const lrdm_grid* grid,
+                                                const void* Psi, const double* eps, int32_t N,
+                                                const lrdm_occ* occ, const double* u, int32_t r,
+                                                lrdm_prec prec, double* t) {
+  LRDM_CHECK(ctx, check_grid(grid));
+  LRDM_CHECK(ctx, check_block(grid, N));
+  LRDM_CHECK(ctx, check_occ(occ, N));
+  LRDM_CHECK(ctx, check_rank(r));
+  LRDM_CHECK(ctx, check_prec(prec));
+  if (prec != LRDM_FP64) return fail(ctx, LRDM_EUNSUPPORTED, "only LRDM_FP64 is available for this call");
+  LRDM_NONNULL(ctx, Psi, "Psi");
+  LRDM_NONNULL(ctx, eps, "eps");
+  LRDM_NONNULL(ctx, u, "u");
+  LRDM_NONNULL(ctx, t, "t");
+  const Grid3 g = make_grid3(grid);
+  const int ns = occ->nspin;
+  const size_t ubytes = (size_t)r * ns * g.M * sizeof(double);
+  if (overlaps(u, ubytes, t, ubytes)) return fail(ctx, LRDM_EINVAL, "u and t must not overlap");
+  const size_t scratch = 2 * (size_t)r * g.M * sizeof(double);
+  lrdm_status st = begin(ctx, ws_align(ubytes) + ws_align(scratch) + hartree_workspace_bytes(g) +
+                                  response_bytes(N, g.M, r, ns, prec));
+  if (st != LRDM_OK) return st;
+  return guarded(ctx, [&]() -> lrdm_status {
+    double* dV = static_cast<double*>(ws_take(ctx, ubytes));
+    double* s = static_cast<double*>(ws_take(ctx, scratch));
+    hipError_t e = launch_hartree(ctx, g, u, ns, dV, ns, r, s);
+    if (e != hipSuccess) return fail_hip(ctx, "hartree", e);
+    e = (prec == LRDM_FP64)
+        ? run_response<double>(ctx, g, static_cast<const double*>(Psi), eps, N, occ, dV, r, prec,
+                               u, t, nullptr, nullptr)
+        : run_response<float>(ctx, g, static_cast<const float*>(Psi), eps, N, occ, dV, r, prec, u,
+                              t, nullptr, nullptr);
+    return e == hipSuccess ? LRDM_OK : fail_hip(ctx, "residual_derivative", e);
+  });
+}

@@ -1,0 +1,118 @@
+// Internal declarations of liblrdm: the context, the workspace arena and the
+// kernel launchers.  Nothing here is part of the public C ABI (include/lrdm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "lrdm.h"
+
+struct lrdm_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  size_t limit = 0;          // 0 = unlimited
+  void* ws = nullptr;        // device workspace
+  size_t ws_cap = 0;
+  size_t ws_top = 0;         // bump pointer inside one call
+  int checks = 0;
+  int* dstatus = nullptr;    // device status words (see lrdm_dev_status)
+  std::string err;
+};
+
+// Device status word indices (checking mode).
+enum { LRDM_DS_BISECT = 0, LRDM_DS_EIGH = 1, LRDM_DS_NONFINITE = 2, LRDM_DS_COUNT = 4 };
+
+namespace lrdm {
+
+// Host-side argument checks (validate.cpp, no HIP).  Each returns nullptr when
+// the argument is acceptable, else a message.
+const char* check_grid(const lrdm_grid* g);
+const char* check_block(const lrdm_grid* g, int32_t N);
+const char* check_occ(const lrdm_occ* occ, int32_t N);
+const char* check_prec(int prec);
+const char* check_rank(int32_t r);
+const char* check_filter(int32_t degree, double a, double b, double a0);
+const char* check_ptr(const void* p, const char* name);
+
+inline int64_t grid_points(const lrdm_grid* g) {
+  return (int64_t)g->n[0] * g->n[1] * g->n[2];
+}
+inline size_t prec_bytes(lrdm_prec p) { return p == LRDM_FP64 ? 8 : 4; }
+
+// Workspace arena: reserve() guarantees `bytes` of capacity (growing the
+// allocation if needed, within the context limit); take() hands out aligned
+// slices of it for the duration of one ABI call.
+lrdm_status ws_reserve(lrdm_ctx* ctx, size_t bytes);
+inline size_t ws_align(size_t b) { return (b + 255) & ~size_t(255); }
+void* ws_take(lrdm_ctx* ctx, size_t bytes);
+
+struct Grid3 {
+  int nx, ny, nz;
+  double hx, hy, hz;
+  int64_t M;
+  double dv;
+};
+Grid3 make_grid3(const lrdm_grid* g);
+
+// ------------------------------------------------------------------ launchers
+// All launchers enqueue on ctx->stream and return the first HIP error.
+
+// Yout = alpha (H - c0) Yin + beta Yold  (Yold unused when beta == 0).
+template <typename T>
+hipError_t launch_cheb_step(lrdm_ctx* ctx, const Grid3& g, const double* V, const T* Yin,
+                            const T* Yold, T* Yout, int N, double alpha, double c0, double beta);
+
+// mu by bisection, occupations, f' and (optionally) F for nspin channels.
+hipError_t launch_fermi(lrdm_ctx* ctx, const double* eps, int N, int nspin, double kT,
+                        double n_electrons, double* mu, double* f, double* omf, double* fprime,
+                        double* F);
+
+// H[b] = A_c diag(w_b) B_c^T for b < batch, c = b % nspin, over the grid index;
+// only the upper triangle is formed and mirrored (the callers' products are
+// symmetric).  B == nullptr means B = A; w == nullptr means w = 1.
+// A, B: nspin blocks of [N][M].
+size_t tn_workspace_bytes(int N, int64_t M, int batch, lrdm_prec prec);
+template <typename T>
+hipError_t launch_tn_sym(lrdm_ctx* ctx, const T* A, const T* B, const double* w,
+                         int64_t w_stride, int N, int64_t M, int nspin, int batch, lrdm_prec prec,
+                         double* H);
+
+// dmu[k] and Gamma[k][c] = F[c] o Hp[k][c] - dmu[k] diag(fprime[c]), in place over Hp.
+hipError_t launch_gamma(lrdm_ctx* ctx, double* Hp, const double* F, const double* fprime, int N,
+                        int nspin, int r, double* dmu);
+
+// out[b][p] = scale * sum_ij A_c[i][p] G[b][i][j] A_c[j][p] (- sub[b][p] when sub != nullptr),
+// c = b % nspin, G symmetric.
+template <typename T>
+hipError_t launch_backproj(lrdm_ctx* ctx, const T* A, const double* G, int N, int64_t M, int nspin,
+                           int batch, lrdm_prec prec, double scale, const double* sub,
+                           double* out);
+
+// Out[i][p] = sum_j Wt[j][i] B[j][p]  (Out = Wt^T B), Wt double N x N.
+template <typename T>
+hipError_t launch_nn(lrdm_ctx* ctx, const double* Wt, const T* B, T* Out, int N, int64_t M);
+
+// Rayleigh-Ritz pieces (rr.hip).
+template <typename T>
+lrdm_status rayleigh_ritz(lrdm_ctx* ctx, const Grid3& g, const double* V, T* Psi, int N,
+                          lrdm_prec prec, double* eps);
+size_t rr_workspace_bytes(int N, int64_t M, lrdm_prec prec);
+
+// Hartree kernel (poisson.hip): dV[k] = 4 pi (-Lap_h)^{-1} (sum_c u[k][c]) for k < r,
+// written to every channel slot of dV when nspin_out > 1.
+hipError_t launch_hartree(lrdm_ctx* ctx, const Grid3& g, const double* u, int u_nspin,
+                          double* dV, int dv_nspin, int r, double* scratch);
+size_t hartree_workspace_bytes(const Grid3& g);
+
+hipError_t launch_check_finite(lrdm_ctx* ctx, const double* x, int64_t n);
+
+}  // namespace lrdm
+
+#define LRDM_HIP(call)                         \
+  do {                                         \
+    hipError_t e_ = (call);                    \
+    if (e_ != hipSuccess) return e_;           \
+  } while (0)

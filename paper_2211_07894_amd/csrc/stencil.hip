@@ -1,0 +1,132 @@
+// Stencil Hamiltonian applied to a block of vectors, fused with one step of the
+// Chebyshev three-term recurrence (Sec. II C):
+//     Yout = alpha (H - c0) Yin + beta Yold,   H = -1/2 Lap_h + diag(V)
+// with the 7-point periodic Laplacian.  alpha = 1, c0 = 0, beta = 0 gives H Y.
+//
+// Layout: vectors are [N][nz][ny][nx], x fastest.  A block owns one vector and a
+// run of z planes; it marches in z keeping the planes z-1, z, z+1 of its points
+// in registers and the whole current plane in LDS (double-buffered) for the x
+// and y neighbours.  Every element of Yin is read from HBM about once (plus two
+// halo planes per z run), Yold once, Yout written once: 3 M N s bytes per step,
+// the bound of this HBM-limited kernel.
+#include "lrdm_internal.h"
+
+namespace lrdm {
+namespace {
+
+template <typename T, int PPT>
+__global__ __launch_bounds__(1024) void cheb_plane_kernel(
+    const T* __restrict__ Yin, const T* Yold, T* Yout,
+    const double* __restrict__ V, int nx, int ny, int nz, int zrun, T wx, T wy, T wz, T dshift,
+    T alpha, T beta) {
+  extern __shared__ unsigned char smem_raw[];
+  T* plane = reinterpret_cast<T*>(smem_raw);
+  const int P = nx * ny;
+  const int64_t M = (int64_t)P * nz;
+  const int vec = blockIdx.x;
+  const int z0 = blockIdx.y * zrun;
+  const int z1 = min(nz, z0 + zrun);
+  const T* yin = Yin + (int64_t)vec * M;
+  const T* yold = Yold ? Yold + (int64_t)vec * M : nullptr;
+  T* yout = Yout + (int64_t)vec * M;
+
+  int xy[PPT];   // (y << 16) | x of each point owned by this thread, -1 if none
+  T prev[PPT], cur[PPT], next[PPT];
+  {
+    const int zm = (z0 == 0) ? nz - 1 : z0 - 1;
+    const int zp = (z0 + 1 == nz) ? 0 : z0 + 1;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const int qq = threadIdx.x + j * blockDim.x;
+      if (qq < P) {
+        const int y = qq / nx, x = qq - y * nx;
+        xy[j] = (y << 16) | x;
+        prev[j] = yin[(int64_t)zm * P + qq];
+        cur[j] = yin[(int64_t)z0 * P + qq];
+        next[j] = yin[(int64_t)zp * P + qq];
+      } else {
+        xy[j] = -1;
+        prev[j] = cur[j] = next[j] = T(0);
+      }
+    }
+  }
+  int buf = 0;
+  for (int z = z0; z < z1; ++z) {
+    T* pl = plane + buf * P;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j)
+      if (xy[j] >= 0) pl[threadIdx.x + j * blockDim.x] = cur[j];
+    __syncthreads();
+    const int zn = (z + 2 >= nz) ? z + 2 - nz : z + 2;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      if (xy[j] < 0) continue;
+      const int x = xy[j] & 0xffff, y = xy[j] >> 16;
+      const int q = y * nx + x;
+      const int xm = (x == 0) ? q + nx - 1 : q - 1;
+      const int xp = (x == nx - 1) ? q - nx + 1 : q + 1;
+      const int ym = (y == 0) ? q + P - nx : q - nx;
+      const int yp = (y == ny - 1) ? q - P + nx : q + nx;
+      const int64_t off = (int64_t)z * P + q;
+      const T c = cur[j];
+      const T hy = wx * (pl[xm] + pl[xp]) + wy * (pl[ym] + pl[yp]) +
+                   wz * (prev[j] + next[j]) + ((T)V[off] + dshift) * c;
+      T out = alpha * hy;
+      if (yold) out += beta * yold[off];
+      yout[off] = out;
+    }
+    // rotate the z window; the load of plane z + 2 overlaps the next plane's work
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      prev[j] = cur[j];
+      cur[j] = next[j];
+      if (xy[j] >= 0 && z + 1 < z1) next[j] = yin[(int64_t)zn * P + threadIdx.x + j * blockDim.x];
+    }
+    buf ^= 1;
+  }
+}
+
+template <typename T, int PPT>
+hipError_t launch_plane(lrdm_ctx* ctx, const Grid3& g, const double* V, const T* Yin,
+                        const T* Yold, T* Yout, int N, int threads, int zrun, double alpha,
+                        double c0, double beta) {
+  const int P = g.nx * g.ny;
+  const size_t smem = 2 * (size_t)P * sizeof(T);
+  const T wx = T(-0.5 / (g.hx * g.hx)), wy = T(-0.5 / (g.hy * g.hy)), wz = T(-0.5 / (g.hz * g.hz));
+  const T dshift = T(1.0 / (g.hx * g.hx) + 1.0 / (g.hy * g.hy) + 1.0 / (g.hz * g.hz) - c0);
+  dim3 grd(N, (g.nz + zrun - 1) / zrun);
+  if (smem > 65536)
+    LRDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&cheb_plane_kernel<T, PPT>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+  cheb_plane_kernel<T, PPT><<<grd, threads, smem, ctx->stream>>>(
+      Yin, beta != 0.0 ? Yold : nullptr, Yout, V, g.nx, g.ny, g.nz, zrun, wx, wy, wz, dshift,
+      T(alpha), T(beta));
+  return hipGetLastError();
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_cheb_step(lrdm_ctx* ctx, const Grid3& g, const double* V, const T* Yin,
+                            const T* Yold, T* Yout, int N, double alpha, double c0, double beta) {
+  const int P = g.nx * g.ny;
+  // whole plane per block: up to 1024 threads, PPT points per thread
+  int threads = P <= 1024 ? ((P + 63) / 64) * 64 : 1024;
+  const int ppt = (P + threads - 1) / threads;
+  // z runs: enough blocks for the chip (N * runs >= ~2048) but runs of >= 8 planes
+  int runs = 1;
+  while ((int64_t)N * runs < 2048 && g.nz / (runs * 2) >= 8) runs *= 2;
+  const int zrun = (g.nz + runs - 1) / runs;
+  if (ppt <= 1) return launch_plane<T, 1>(ctx, g, V, Yin, Yold, Yout, N, threads, zrun, alpha, c0, beta);
+  if (ppt <= 2) return launch_plane<T, 2>(ctx, g, V, Yin, Yold, Yout, N, threads, zrun, alpha, c0, beta);
+  if (ppt <= 4) return launch_plane<T, 4>(ctx, g, V, Yin, Yold, Yout, N, threads, zrun, alpha, c0, beta);
+  if (ppt <= 8) return launch_plane<T, 8>(ctx, g, V, Yin, Yold, Yout, N, threads, zrun, alpha, c0, beta);
+  return hipErrorInvalidValue;  // planes above 8192 points are rejected by validation
+}
+
+template hipError_t launch_cheb_step<double>(lrdm_ctx*, const Grid3&, const double*, const double*,
+                                             const double*, double*, int, double, double, double);
+template hipError_t launch_cheb_step<float>(lrdm_ctx*, const Grid3&, const double*, const float*,
+                                            const float*, float*, int, double, double, double);
+
+}  // namespace lrdm

@@ -1,0 +1,321 @@
+"""ctypes binding of liblrdm (include/lrdm.h): argument marshalling only.
+
+Every function takes torch tensors that already live on a ROCm device, checks
+dtype / shape / contiguity, and passes raw device pointers and the current HIP
+stream to the C ABI.  All arithmetic happens in the library's HIP kernels; if
+the library is missing or no GPU is present the calls raise, there is no
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblrdm.so")
+
+LRDM_OK = 0
+STATUS_NAMES = {0: "LRDM_OK", -1: "LRDM_EINVAL", -2: "LRDM_ENOMEM", -3: "LRDM_EDEVICE",
+                -4: "LRDM_ENOTCONV", -5: "LRDM_ENONFINITE", -6: "LRDM_EUNSUPPORTED"}
+PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+
+EXPORTED = [
+    "lrdm_create", "lrdm_destroy", "lrdm_set_stream", "lrdm_set_checks", "lrdm_workspace_bytes",
+    "lrdm_last_error", "lrdm_hamiltonian_apply", "lrdm_fermi_occupations",
+    "lrdm_projected_perturbation", "lrdm_hartree_kernel", "chfsi_filter",
+    "subspace_rayleigh_ritz", "density_response", "lrdm_residual_derivative",
+]
+
+
+class LrdmError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class c_grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("L", ctypes.c_double * 3)]
+
+
+class c_occ(ctypes.Structure):
+    _fields_ = [("nspin", ctypes.c_int32), ("kT", ctypes.c_double), ("n_electrons", ctypes.c_double)]
+
+
+@dataclass(frozen=True)
+class Grid:
+    n: tuple    # (nx, ny, nz)
+    L: tuple    # (Lx, Ly, Lz)
+
+    @property
+    def M(self) -> int:
+        return int(self.n[0] * self.n[1] * self.n[2])
+
+    @property
+    def shape(self) -> tuple:
+        return (self.n[2], self.n[1], self.n[0])
+
+    def c(self) -> c_grid:
+        g = c_grid()
+        for d in range(3):
+            g.n[d] = int(self.n[d])
+            g.L[d] = float(self.L[d])
+        return g
+
+
+@dataclass(frozen=True)
+class Occupation:
+    nspin: int
+    kT: float
+    n_electrons: float
+
+    def c(self) -> c_occ:
+        return c_occ(int(self.nspin), float(self.kT), float(self.n_electrons))
+
+
+_lib = None
+_lib_lock = threading.Lock()
+
+
+def library() -> ctypes.CDLL:
+    """Load liblrdm.so (built in-tree by paper_2211_07894_amd.build)."""
+    global _lib
+    with _lib_lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                                   "`python -m paper_2211_07894_amd.build` (no CPU fallback exists)")
+            lib = ctypes.CDLL(LIB_PATH)
+            vp, i32, f64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
+            G, O = ctypes.POINTER(c_grid), ctypes.POINTER(c_occ)
+            sig = {
+                "lrdm_create": [ctypes.POINTER(vp), ctypes.c_int, vp, sz],
+                "lrdm_destroy": [vp],
+                "lrdm_set_stream": [vp, vp],
+                "lrdm_set_checks": [vp, ctypes.c_int],
+                "lrdm_workspace_bytes": [vp],
+                "lrdm_last_error": [vp],
+                "lrdm_hamiltonian_apply": [vp, G, vp, vp, vp, i32, ctypes.c_int],
+                "lrdm_fermi_occupations": [vp, vp, i32, O, vp, vp, vp, vp],
+                "lrdm_projected_perturbation": [vp, G, vp, i32, i32, vp, i32, ctypes.c_int, vp],
+                "lrdm_hartree_kernel": [vp, G, vp, vp, i32],
+                "chfsi_filter": [vp, G, vp, vp, vp, i32, ctypes.c_int, i32, f64, f64, f64],
+                "subspace_rayleigh_ritz": [vp, G, vp, vp, i32, ctypes.c_int, vp],
+                "density_response": [vp, G, vp, vp, i32, O, vp, i32, ctypes.c_int, vp, vp, vp],
+                "lrdm_residual_derivative": [vp, G, vp, vp, i32, O, vp, i32, ctypes.c_int, vp],
+            }
+            for name, args in sig.items():
+                fn = getattr(lib, name)
+                fn.argtypes = args
+                fn.restype = ctypes.c_int
+            lib.lrdm_workspace_bytes.restype = sz
+            lib.lrdm_last_error.restype = ctypes.c_char_p
+            _lib = lib
+        return _lib
+
+
+class Context:
+    """One liblrdm context per (device, HIP stream)."""
+
+    def __init__(self, device: int, stream: int, workspace_limit: int = 0):
+        self.lib = library()
+        self.ptr = ctypes.c_void_p()
+        st = self.lib.lrdm_create(ctypes.byref(self.ptr), int(device), ctypes.c_void_p(stream),
+                                  int(workspace_limit))
+        if st != LRDM_OK:
+            raise LrdmError(st, self.lib.lrdm_last_error(None).decode())
+        self.device = device
+        self.stream = stream
+
+    def check(self, st: int):
+        if st != LRDM_OK:
+            raise LrdmError(st, self.lib.lrdm_last_error(self.ptr).decode())
+
+    def set_checks(self, level: int):
+        self.check(self.lib.lrdm_set_checks(self.ptr, int(level)))
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(self.lib.lrdm_workspace_bytes(self.ptr))
+
+    def close(self):
+        if self.ptr:
+            self.lib.lrdm_destroy(self.ptr)
+            self.ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_contexts: dict = {}
+
+
+def context(device=None) -> Context:
+    """Context bound to the current device and its current torch stream."""
+    if not torch.cuda.is_available():
+        raise RuntimeError("liblrdm needs a ROCm GPU; torch.cuda.is_available() is False")
+    dev = torch.cuda.current_device() if device is None else int(device)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    key = (dev, stream)
+    ctx = _contexts.get(key)
+    if ctx is None:
+        ctx = Context(dev, stream)
+        _contexts[key] = ctx
+    return ctx
+
+
+def release_contexts():
+    for c in list(_contexts.values()):
+        c.close()
+    _contexts.clear()
+
+
+# ------------------------------------------------------------------ marshalling helpers
+def _block_dtype(prec: str):
+    return torch.float64 if prec == "fp64" else torch.float32
+
+
+def _ptr(t: torch.Tensor, name: str, dtype=None, numel=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must hold {numel} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _prec(prec: str) -> int:
+    if prec not in PREC:
+        raise ValueError(f"prec must be one of {sorted(PREC)}")
+    return PREC[prec]
+
+
+# ------------------------------------------------------------------ single steps
+def hamiltonian_apply(grid: Grid, V, X, prec="fp64", out=None):
+    """Y = H X, H = -1/2 Lap_h + diag(V) (7-point periodic)."""
+    N = X.shape[0]
+    dt = _block_dtype(prec)
+    Y = torch.empty_like(X) if out is None else out
+    ctx = context(X.device.index)
+    g = grid.c()
+    ctx.check(ctx.lib.lrdm_hamiltonian_apply(ctx.ptr, ctypes.byref(g), _ptr(V, "V", torch.float64, grid.M),
+                                             _ptr(X, "X", dt, N * grid.M), _ptr(Y, "Y", dt, N * grid.M),
+                                             N, _prec(prec)))
+    return Y
+
+
+def fermi_occupations(eps, occ: Occupation, want_F=True):
+    """mu, f, f', F for eps [nspin][N] (FP64 on the GPU)."""
+    eps = eps.reshape(occ.nspin, -1)
+    N = eps.shape[1]
+    dev = eps.device
+    mu = torch.empty(1, dtype=torch.float64, device=dev)
+    f = torch.empty_like(eps)
+    fp = torch.empty_like(eps)
+    F = torch.empty((occ.nspin, N, N), dtype=torch.float64, device=dev) if want_F else None
+    ctx = context(dev.index)
+    o = occ.c()
+    ctx.check(ctx.lib.lrdm_fermi_occupations(ctx.ptr, _ptr(eps, "eps", torch.float64), N, ctypes.byref(o),
+                                             _ptr(mu, "mu"), _ptr(f, "f"), _ptr(fp, "fprime"),
+                                             _ptr(F, "F") if F is not None else None))
+    return mu, f, fp, F
+
+
+def projected_perturbation(grid: Grid, Psi, dV, nspin=1, prec="fp64"):
+    """Hp [r][nspin][N][N] = Psi^T diag(dV) Psi per direction and channel."""
+    N = Psi.shape[-4] if Psi.dim() >= 4 else Psi.shape[-2]
+    r = dV.numel() // (nspin * grid.M)
+    Hp = torch.empty((r, nspin, N, N), dtype=torch.float64, device=Psi.device)
+    ctx = context(Psi.device.index)
+    g = grid.c()
+    ctx.check(ctx.lib.lrdm_projected_perturbation(
+        ctx.ptr, ctypes.byref(g), _ptr(Psi, "Psi", _block_dtype(prec), nspin * N * grid.M), N, nspin,
+        _ptr(dV, "dV", torch.float64, r * nspin * grid.M), r, _prec(prec), _ptr(Hp, "Hp")))
+    return Hp
+
+
+def hartree_kernel(grid: Grid, u, out=None):
+    """dV = 4 pi (-Lap_h)^{-1} u per direction (q = 0 removed); u [r][nz][ny][nx]."""
+    r = u.numel() // grid.M
+    dV = torch.empty_like(u) if out is None else out
+    ctx = context(u.device.index)
+    g = grid.c()
+    ctx.check(ctx.lib.lrdm_hartree_kernel(ctx.ptr, ctypes.byref(g), _ptr(u, "u", torch.float64, r * grid.M),
+                                          _ptr(dV, "dV", torch.float64, r * grid.M), r))
+    return dV
+
+
+# ------------------------------------------------------------------ hot path
+def chfsi_filter(grid: Grid, V, X, degree: int, a: float, b: float, a0: float, prec="fp64", out=None):
+    """Y = T_c(Hbar) X / T_c(ybar0) (scaled Chebyshev filter of degree c)."""
+    N = X.shape[0]
+    dt = _block_dtype(prec)
+    Y = torch.empty_like(X) if out is None else out
+    ctx = context(X.device.index)
+    g = grid.c()
+    ctx.check(ctx.lib.chfsi_filter(ctx.ptr, ctypes.byref(g), _ptr(V, "V", torch.float64, grid.M),
+                                   _ptr(X, "X", dt, N * grid.M), _ptr(Y, "Y", dt, N * grid.M), N,
+                                   _prec(prec), int(degree), float(a), float(b), float(a0)))
+    return Y
+
+
+def subspace_rayleigh_ritz(grid: Grid, V, Psi, prec="fp64", eps=None):
+    """In place: filtered block -> Ritz vectors; returns eps (ascending, FP64)."""
+    N = Psi.shape[0]
+    e = torch.empty(N, dtype=torch.float64, device=Psi.device) if eps is None else eps
+    ctx = context(Psi.device.index)
+    g = grid.c()
+    ctx.check(ctx.lib.subspace_rayleigh_ritz(ctx.ptr, ctypes.byref(g), _ptr(V, "V", torch.float64, grid.M),
+                                             _ptr(Psi, "Psi", _block_dtype(prec), N * grid.M), N,
+                                             _prec(prec), _ptr(e, "eps", torch.float64, N)))
+    return e
+
+
+def density_response(grid: Grid, Psi, eps, occ: Occupation, dV, prec="fp64", out=None,
+                     mu=None, dmu=None):
+    """drho [r][nspin][M] for dV [r][nspin][M]; returns (drho, mu [1], dmu [r])."""
+    ns = occ.nspin
+    N = eps.numel() // ns
+    r = dV.numel() // (ns * grid.M)
+    dev = Psi.device
+    drho = torch.empty((r, ns) + grid.shape, dtype=torch.float64, device=dev) if out is None else out
+    mu = torch.empty(1, dtype=torch.float64, device=dev) if mu is None else mu
+    dmu = torch.empty(r, dtype=torch.float64, device=dev) if dmu is None else dmu
+    ctx = context(dev.index)
+    g = grid.c()
+    o = occ.c()
+    ctx.check(ctx.lib.density_response(
+        ctx.ptr, ctypes.byref(g), _ptr(Psi, "Psi", _block_dtype(prec), ns * N * grid.M),
+        _ptr(eps, "eps", torch.float64, ns * N), N, ctypes.byref(o),
+        _ptr(dV, "dV", torch.float64, r * ns * grid.M), r, _prec(prec),
+        _ptr(drho, "drho", torch.float64, r * ns * grid.M), _ptr(mu, "mu", torch.float64, 1),
+        _ptr(dmu, "dmu", torch.float64, r)))
+    return drho, mu, dmu
+
+
+def residual_derivative(grid: Grid, Psi, eps, occ: Occupation, u, prec="fp64", out=None):
+    """t_k = drho[K_c sum_sigma u_k,sigma] - u_k; u, t [r][nspin][M]."""
+    ns = occ.nspin
+    N = eps.numel() // ns
+    r = u.numel() // (ns * grid.M)
+    t = torch.empty_like(u) if out is None else out
+    ctx = context(Psi.device.index)
+    g = grid.c()
+    o = occ.c()
+    ctx.check(ctx.lib.lrdm_residual_derivative(
+        ctx.ptr, ctypes.byref(g), _ptr(Psi, "Psi", _block_dtype(prec), ns * N * grid.M),
+        _ptr(eps, "eps", torch.float64, ns * N), N, ctypes.byref(o),
+        _ptr(u, "u", torch.float64, r * ns * grid.M), r, _prec(prec),
+        _ptr(t, "t", torch.float64, r * ns * grid.M)))
+    return t

@@ -1,0 +1,99 @@
+"""The C ABI on a host without a GPU: the library loads, exports every symbol
+include/lrdm.h declares, and its host-side validation rejects bad arguments
+(before any device call) with the documented codes and messages."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2211_07894_amd import lrdm as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lrdm.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(?:lrdm_status|size_t|const char\*)\s+(\w+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB_PATH):
+        pytest.skip("liblrdm.so not built")
+    return B.library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(B.EXPORTED)
+
+
+def _grid(n=(8, 8, 8), L=(4.0, 4.0, 4.0)):
+    g = B.c_grid()
+    for d in range(3):
+        g.n[d] = n[d]
+        g.L[d] = L[d]
+    return g
+
+
+def _err(lib):
+    return lib.lrdm_last_error(None).decode()
+
+
+P = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
+
+
+@pytest.mark.parametrize("args,msg", [
+    (dict(n=(2, 8, 8)), "n[d] must be >= 3"),
+    (dict(L=(4.0, -1.0, 4.0)), "L[d] must be finite"),
+    (dict(N=0), "N must be >= 1"),
+    (dict(N=10 ** 6), "N must not exceed"),
+    (dict(prec=7), "prec must be"),
+    (dict(degree=0), "degree must be >= 1"),
+    (dict(a=2.0), "a0 < a < b"),
+    (dict(V=None), "V is NULL"),
+])
+def test_filter_validation(lib, args, msg):
+    a = dict(n=(8, 8, 8), L=(4.0, 4.0, 4.0), N=4, prec=0, degree=3, a=0.5, b=1.0, a0=-1.0, V=P)
+    a.update(args)
+    st = lib.chfsi_filter(None, ctypes.byref(_grid(a["n"], a["L"])), a["V"], P, ctypes.c_void_p(0x9000000),
+                          a["N"], a["prec"], a["degree"], a["a"], a["b"], a["a0"])
+    assert st == -1
+    assert msg in _err(lib)
+
+
+@pytest.mark.parametrize("occ,msg", [
+    ((3, 0.01, 10.0), "nspin must be 1 or 2"),
+    ((1, 0.0, 10.0), "kT must be finite and > 0"),
+    ((1, 0.01, 64.0), "below 2 N"),
+    ((2, 0.01, -1.0), "n_electrons must be finite and > 0"),
+])
+def test_response_occupation_validation(lib, occ, msg):
+    o = B.c_occ(*occ)
+    st = lib.density_response(None, ctypes.byref(_grid()), P, P, 32, ctypes.byref(o), P, 2, 0, P, None, None)
+    assert st == -1
+    assert msg in _err(lib)
+
+
+def test_null_context_reported_after_valid_arguments(lib):
+    o = B.c_occ(1, 0.01, 20.0)
+    st = lib.density_response(None, ctypes.byref(_grid()), P, P, 32, ctypes.byref(o), P, 2, 0, P, None, None)
+    assert st == -1 and "ctx is NULL" in _err(lib)
+
+
+def test_overlap_rejected(lib):
+    st = lib.lrdm_hamiltonian_apply(None, ctypes.byref(_grid()), P, P, ctypes.c_void_p(0x1000 + 8), 2, 0)
+    assert st == -1 and "must not overlap" in _err(lib)
+
+
+def test_rank_and_plane_limits(lib):
+    st = lib.lrdm_hartree_kernel(None, ctypes.byref(_grid()), P, P, 0)
+    assert st == -1 and "r (number of directions)" in _err(lib)
+    st = lib.lrdm_hartree_kernel(None, ctypes.byref(_grid((100, 100, 8), (4.0, 4.0, 4.0))), P, P, 1)
+    assert st == -1 and "8192 points" in _err(lib)

@@ -1,0 +1,195 @@
+"""HIP path against the FP64 oracle, element by element, on seeded inputs that
+span several 128-wide tiles and ragged tails.  FP64 tolerances follow the
+target of <= 1e-10 relative for the response; single steps are held tighter."""
+import numpy as np
+import pytest
+
+import oracle as O
+from inputs import grf_directions, random_block
+from tests.gpu_common import filter_bounds, oracle_subspace, rel, to_dev, to_host
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU hosts
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2211_07894_amd as L  # noqa: E402
+
+
+def _grid(g: O.Grid):
+    return L.Grid(tuple(g.n), tuple(g.L))
+
+
+@pytest.fixture(scope="module")
+def c24():
+    return oracle_subspace("c24_n32", passes=2)
+
+
+# ------------------------------------------------------------------ a1 stencil
+@pytest.mark.parametrize("n,box,N", [((24, 24, 24), (10.0, 10.0, 10.0), 5),
+                                     ((20, 18, 13), (7.0, 6.1, 5.2), 3),
+                                     ((64, 64, 64), (28.0, 28.0, 28.0), 2),
+                                     ((80, 80, 5), (34.0, 34.0, 2.1), 2)])
+def test_hamiltonian_apply_fp64(n, box, N):
+    g = O.Grid(n, box)
+    rng = np.random.default_rng(1)
+    V = rng.standard_normal(g.shape)
+    X = rng.standard_normal((N,) + g.shape)
+    Y = L.hamiltonian_apply(_grid(g), to_dev(V), to_dev(X))
+    ref = O.hamiltonian_apply(X, V, g)
+    assert rel(to_host(Y), ref) < 1e-14
+
+
+# ------------------------------------------------------------------ a2 filter
+@pytest.mark.parametrize("degree", [1, 2, 7, 20])
+def test_chfsi_filter_fp64(c24, degree):
+    wl, g, V, eps, Psi = c24
+    a, b, a0 = filter_bounds(V, g, eps)
+    X = random_block(wl.system_id, 6, wl.n)
+    Y = L.chfsi_filter(_grid(g), to_dev(V), to_dev(X), degree, a, b, a0)
+    ref = O.chebyshev_filter(X, V, g, degree, a, b, a0)
+    assert rel(to_host(Y), ref) < 1e-12
+
+
+# ------------------------------------------------------------------ a4 / a5 occupations
+@pytest.mark.parametrize("nspin,N", [(1, 32), (1, 300), (2, 77)])
+def test_fermi_occupations(nspin, N):
+    rng = np.random.default_rng(2)
+    eps = np.sort(rng.uniform(-1.5, 0.8, (nspin, N)), axis=1)
+    eps[0, 5] = eps[0, 4]                      # an exact degeneracy
+    eps[0, 9] = eps[0, 8] + 1e-13              # and a near one
+    kT, ne = 0.01, 0.39 * 2 * N * (1 if nspin == 1 else 1)
+    occ = L.Occupation(nspin, kT, ne)
+    mu, f, fp, F = L.fermi_occupations(to_dev(eps), occ)
+    mu_o, _ = O.fermi_level(eps, ne, kT, nspin)
+    assert abs(float(mu.item()) - mu_o) < 1e-13
+    for c in range(nspin):
+        fo, _, fpo = O.fermi_dirac(eps[c], mu_o, kT)
+        assert rel(to_host(f)[c], fo) < 1e-13
+        assert rel(to_host(fp)[c], fpo) < 1e-12
+        Fo = O.divided_differences(eps[c], mu_o, kT)
+        assert np.max(np.abs(to_host(F)[c] - Fo)) < 1e-11 * np.max(np.abs(Fo))
+
+
+# ------------------------------------------------------------------ a6 projection
+@pytest.mark.parametrize("n,N,nspin,r", [((24, 24, 24), 32, 1, 2), ((20, 18, 13), 150, 1, 3),
+                                         ((16, 16, 16), 257, 2, 2)])
+def test_projected_perturbation_fp64(n, N, nspin, r):
+    g = O.Grid(n, tuple(0.42 * x for x in n))
+    rng = np.random.default_rng(3)
+    Psi = rng.standard_normal((nspin, N) + g.shape)
+    dV = rng.standard_normal((r, nspin) + g.shape)
+    Hp = to_host(L.projected_perturbation(_grid(g), to_dev(Psi), to_dev(dV), nspin=nspin))
+    for k in range(r):
+        for c in range(nspin):
+            ref = O.projected_perturbation(Psi[c], dV[k, c])
+            assert np.max(np.abs(Hp[k, c] - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+# ------------------------------------------------------------------ a9 Hartree kernel
+@pytest.mark.parametrize("n", [(24, 24, 24), (20, 18, 13), (9, 16, 7)])
+def test_hartree_kernel(n):
+    g = O.Grid(n, tuple(0.45 * x for x in n))
+    u = np.random.default_rng(4).standard_normal((3,) + g.shape)
+    dV = to_host(L.hartree_kernel(_grid(g), to_dev(u)))
+    for k in range(3):
+        assert rel(dV[k], O.hartree_kernel(u[k], g)) < 1e-12
+
+
+# ------------------------------------------------------------------ a4-a8 density response
+def test_density_response_c24(c24):
+    wl, g, V, eps, Psi = c24
+    U = grf_directions(wl.system_id, wl.n, wl.L, wl.rank)
+    dV = np.stack([O.hartree_kernel(U[k, 0], g)[None] for k in range(wl.rank)])
+    drho, mu, dmu = L.density_response(_grid(g), to_dev(Psi[None]), to_dev(eps[None]),
+                                       L.Occupation(1, wl.kT, wl.n_electrons), to_dev(dV))
+    ref, mu_o, dmu_o = O.density_response(Psi[None], eps[None], g, wl.n_electrons, wl.kT, dV, 1)
+    for k in range(wl.rank):
+        assert rel(to_host(drho)[k], ref[k]) < 1e-10
+    assert abs(float(mu.item()) - mu_o) < 1e-12
+    assert np.max(np.abs(to_host(dmu) - dmu_o)) < 1e-10 * max(1.0, np.max(np.abs(dmu_o)))
+
+
+@pytest.mark.parametrize("nspin", [1, 2])
+def test_density_response_ragged_multitile(nspin):
+    """N = 150 (two 128-row tiles, ragged) on a ragged grid, random orthonormal
+    subspace and sorted energies spanning mu."""
+    g = O.Grid((20, 18, 13), (8.0, 7.2, 5.2))
+    N = 150
+    rng = np.random.default_rng(5)
+    Psi = np.stack([np.linalg.qr(rng.standard_normal((g.M, N)))[0].T.reshape((N,) + g.shape)
+                    for _ in range(nspin)])
+    eps = np.sort(rng.uniform(-1.0, 0.5, (nspin, N)), axis=1)
+    ne = 0.8 * N
+    dV = rng.standard_normal((3, nspin) + g.shape)
+    drho, mu, dmu = L.density_response(_grid(g), to_dev(Psi), to_dev(eps),
+                                       L.Occupation(nspin, 0.02, ne), to_dev(dV))
+    ref, mu_o, dmu_o = O.density_response(Psi, eps, g, ne, 0.02, dV, nspin)
+    for k in range(3):
+        assert rel(to_host(drho)[k], ref[k]) < 1e-10
+    assert np.max(np.abs(to_host(dmu) - dmu_o)) < 1e-10 * max(1.0, np.max(np.abs(dmu_o)))
+
+
+@pytest.mark.parametrize("nspin", [1, 2])
+def test_residual_derivative(c24, nspin):
+    wl, g, V, eps, Psi = c24
+    U = grf_directions(wl.system_id, wl.n, wl.L, 3, nspin=nspin)
+    Psi2 = np.stack([Psi] * nspin)
+    eps2 = np.stack([eps + 0.003 * c for c in range(nspin)])
+    ne = wl.n_electrons
+    t = L.residual_derivative(_grid(g), to_dev(Psi2), to_dev(eps2), L.Occupation(nspin, wl.kT, ne),
+                              to_dev(U))
+    ref, _, _ = O.residual_derivative(Psi2, eps2, g, ne, wl.kT, U, nspin)
+    for k in range(3):
+        assert rel(to_host(t)[k], ref[k]) < 1e-10
+
+
+# ------------------------------------------------------------------ a3 Rayleigh-Ritz
+def test_rayleigh_ritz_fp64(c24):
+    """Warm-started filtered block: Ritz values match the oracle's, the GPU Ritz
+    vectors are orthonormal, and the basis-invariant density response built on
+    them matches the oracle's."""
+    wl, g, V, eps, Psi = c24
+    a, b, a0 = filter_bounds(V, g, eps)
+    Y = O.chebyshev_filter(Psi, V, g, wl.degree, a, b, a0)
+    eps_o, Psi_o = O.rayleigh_ritz(Y, V, g)
+    Yd = to_dev(Y)
+    e = L.subspace_rayleigh_ritz(_grid(g), to_dev(V), Yd)
+    assert np.max(np.abs(to_host(e) - eps_o)) < 1e-10 * np.max(np.abs(eps_o))
+    P = to_host(Yd).reshape(wl.N, -1)
+    assert np.max(np.abs(P @ P.T - np.eye(wl.N))) < 1e-12
+    HP = O.hamiltonian_apply(P.reshape((wl.N,) + g.shape), V, g).reshape(wl.N, -1)
+    assert np.max(np.abs(P @ HP.T - np.diag(eps_o))) < 1e-10
+    U = grf_directions(wl.system_id, wl.n, wl.L, 2)
+    dV = U  # any perturbation; the response is invariant under rotations of the basis
+    d_gpu, _, _ = O.density_response(P.reshape((1, wl.N) + g.shape), to_host(e)[None], g,
+                                     wl.n_electrons, wl.kT, dV, 1)
+    d_ref, _, _ = O.density_response(Psi_o[None], eps_o[None], g, wl.n_electrons, wl.kT, dV, 1)
+    assert rel(d_gpu, d_ref) < 1e-9
+
+
+def test_rayleigh_ritz_multitile():
+    """N = 150 on a ragged grid: block-Jacobi with 3 blocks pairs and padding."""
+    g = O.Grid((20, 18, 13), (8.0, 7.2, 5.2))
+    rng = np.random.default_rng(6)
+    V = rng.uniform(-1, 0, g.shape)
+    N = 150
+    Y = rng.standard_normal((N,) + g.shape)
+    eps_o, _ = O.rayleigh_ritz(Y, V, g)
+    Yd = to_dev(Y)
+    e = to_host(L.subspace_rayleigh_ritz(_grid(g), to_dev(V), Yd))
+    assert np.max(np.abs(e - eps_o)) < 1e-10 * np.max(np.abs(eps_o))
+    P = to_host(Yd).reshape(N, -1)
+    assert np.max(np.abs(P @ P.T - np.eye(N))) < 1e-11
+
+
+# ------------------------------------------------------------------ validation on the device side
+def test_unsupported_and_invalid_are_errors():
+    g = L.Grid((8, 8, 8), (4.0, 4.0, 4.0))
+    X = torch.zeros((2, 8, 8, 8), dtype=torch.float64, device="cuda")
+    V = torch.zeros((8, 8, 8), dtype=torch.float64, device="cuda")
+    with pytest.raises(L.LrdmError):
+        L.chfsi_filter(g, V, X, 3, 1.0, 0.5, -1.0)      # a > b
+    with pytest.raises(L.LrdmError):
+        L.chfsi_filter(g, V, X, 3, 1.0, 2.0, -1.0, out=X)  # X aliases Y
