@@ -1,0 +1,276 @@
+"""Throughput of the LRDM density-response hot path on one MI355X.
+
+One step = one pass of the whole path over the synthetic 64^3 / 1024-state
+workload: chfsi_filter (degree 40) -> subspace_rayleigh_ritz ->
+lrdm_residual_derivative for all 16 direction functions (Hartree kernel,
+Fermi level, divided differences, projection, Fermi shift, back-projection,
+t = drho - u).  The metric is directions per second, r / T_step.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms fp64,...]
+
+Prints ONE JSON line.  Inputs are resident in HBM before timing starts.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "density-response directions/sec @64³ grid,1024 states vs FP64 path; rel err"
+WORKLOAD = "c64_n1024_slab"
+PEAK = {"hbm_GBs": 8000.0, "fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}   # TFLOP/s for contractions
+FORM_DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--forms", default="fp64")
+    ap.add_argument("--workload", default=WORKLOAD)
+    ap.add_argument("--warm-passes", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def kernel_source_hash(name: str) -> str:
+    p = os.path.join(ROOT, "paper_2211_07894_amd", "csrc", name)
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def traffic_record(kernel: str, workload: str, form: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken from the current kernel source; otherwise None."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        recs = json.load(open(p))
+    except Exception:
+        return None
+    for r in recs:
+        if r.get("kernel") == kernel and r.get("workload") == workload and r.get("form") == form:
+            if r.get("source_sha") == kernel_source_hash(r.get("source", "")):
+                return r.get("bytes_per_launch")
+    return None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: every box here has one MI355X and the path is "
+              "not sharded across GPUs (see DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2211_07894_amd as L
+    from inputs import make_workload
+
+    forms = [f.strip() for f in args.forms.split(",") if f.strip()]
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    wl = make_workload(args.workload)
+    grid = L.Grid(tuple(wl.n), tuple(wl.L))
+    occ = L.Occupation(1, wl.kT, wl.n_electrons)
+    M, N, r, c = wl.M, wl.N, wl.rank, wl.degree
+    hx, hy, hz = wl.h
+    V = torch.from_numpy(wl.V[0]).to(dev)
+    b_up = 2.0 / hx ** 2 + 2.0 / hy ** 2 + 2.0 / hz ** 2 + float(wl.V[0].max())
+    log(f"workload {wl.name}: M={M} N={N} r={r} degree={c}")
+    t0 = time.time()
+    X = torch.empty((N,) + grid.shape, dtype=torch.float64, device=dev)
+    chunk = 64
+    for s in range(0, N, chunk):
+        X[s:s + chunk] = torch.from_numpy(wl.block(states=range(s, min(N, s + chunk)))).to(dev)
+    U = torch.from_numpy(wl.directions()).to(dev)          # [r][1][nz][ny][nx]
+    log(f"inputs generated in {time.time() - t0:.1f}s")
+
+    # ---- warm start: ChFSI passes (FP64 form) until the Ritz pair nearest mu has
+    # a residual below 2e-3 or the pass budget is spent (untimed set-up)
+    t0 = time.time()
+    a0 = float(wl.V[0].min()) - 0.1
+    a = a0 + 0.25 * (b_up - a0)
+    Y = torch.empty_like(X)
+    eps = None
+    resid = float("nan")
+    for p in range(args.warm_passes):
+        deg = 10 if p == 0 else c
+        L.chfsi_filter(grid, V, X, deg, a, b_up, a0, out=Y)
+        eps = L.subspace_rayleigh_ritz(grid, V, Y)
+        X, Y = Y, X
+        a = float(eps[-1].item())
+        a0 = float(eps[0].item()) - 0.2
+        mu, _, _, _ = L.fermi_occupations(eps, occ, want_F=False)
+        i = int(torch.argmin(torch.abs(eps - mu)).item())
+        hpsi = L.hamiltonian_apply(grid, V, X[i:i + 1].contiguous())
+        resid = float(torch.linalg.vector_norm(hpsi[0] - eps[i] * X[i]).item())
+        log(f"warm pass {p}: degree {deg} residual(nearest mu) {resid:.2e} [{time.time() - t0:.1f}s]")
+        if p > 0 and resid < 2e-3:
+            break
+    torch.cuda.synchronize()
+    filt = (a, b_up, a0)
+
+    results = {}
+    ref_t = None
+    for form in forms:
+        dt = torch.float64 if form == "fp64" else torch.float32
+        Xf = X.to(dt).contiguous()
+        Yf = torch.empty_like(Xf)
+        t_out = torch.empty((r, 1) + grid.shape, dtype=torch.float64, device=dev)
+        ctx = L.context()
+
+        def step():
+            L.chfsi_filter(grid, V, Xf, c, *filt, prec=form, out=Yf)
+            e = L.subspace_rayleigh_ritz(grid, V, Yf, prec=form)
+            L.residual_derivative(grid, Yf[None], e[None], occ, U, prec=form, out=t_out)
+            return e
+
+        try:
+            for _ in range(args.warmup):
+                step()
+            torch.cuda.synchronize()
+        except L.LrdmError as ex:
+            log(f"form {form} unavailable: {ex}")
+            continue
+        ctx.profile(True)
+        for k in ["cheb_step", "hpsi", "proj", "gram", "backproj", "nn", "eigh", "hartree"]:
+            ctx.profile_read(k)
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        ctx.profile(False)
+        kern = {k: ctx.profile_read(k) for k in
+                ["cheb_step", "hpsi", "proj", "gram", "backproj", "nn", "eigh", "hartree"]}
+        ms_step = 1e3 * elapsed / args.steps
+        rel = None
+        if form == "fp64":
+            ref_t = t_out.clone()
+            rel = 0.0
+        elif ref_t is not None:
+            rel = float((torch.linalg.vector_norm(t_out - ref_t) / torch.linalg.vector_norm(ref_t)).item())
+        results[form] = dict(ms_per_step=ms_step, value=r * args.steps / elapsed, kernels=kern,
+                             rel_err_vs_fp64=rel)
+        log(f"form {form}: {ms_step:.1f} ms/step, {r * args.steps / elapsed:.2f} directions/s; "
+            + ", ".join(f"{k} {v[0] / max(v[1], 1):.3f}ms x{v[1]}" for k, v in kern.items() if v[1]))
+        del Xf, Yf
+
+    if not results:
+        log("no precision form ran")
+        sys.exit(1)
+    head = next(f for f in ("bf16x3", "fp32", "fp64") if f in results)
+    hr = results[head]
+
+    # ---- roofline of the dominant kernel (largest total time in the timed steps)
+    s_bytes = 8 if head == "fp64" else 4
+    per_launch = {
+        # algorithmic work per launch: back-projection 2 M N^2 + 2 M N per direction,
+        # projection 2 M N^2 per direction (full N x N), filter step 3 M N s bytes
+        "backproj": ("mfma", r * (2.0 * M * N * N + 2.0 * M * N)),
+        "proj": ("mfma", r * 2.0 * M * N * N),
+        "cheb_step": ("hbm", 3.0 * M * N * s_bytes + 8.0 * M),
+    }
+    dom = max(per_launch, key=lambda k: hr["kernels"][k][0])
+    ms_tot, launches = hr["kernels"][dom]
+    bound, work = per_launch[dom]
+    avg_s = ms_tot / 1e3 / max(launches, 1)
+    if bound == "hbm":
+        achieved, peak, unit = work / avg_s / 1e9, PEAK["hbm_GBs"], "GB/s"
+    else:
+        peak = PEAK["fp64"] if head == "fp64" else (PEAK["fp32"] if head == "fp32" else PEAK["bf16"])
+        achieved, unit = work / avg_s / 1e12, "TFLOP/s"
+    src = "gemm.hip" if dom in ("backproj", "proj") else "stencil.hip"
+    roofline = dict(kernel=dom, bound=bound, achieved=round(achieved, 3), peak=peak, unit=unit,
+                    frac=round(achieved / peak, 4),
+                    traffic=traffic_record(dom, WORKLOAD, head),
+                    avg_launch_ms=round(1e3 * avg_s, 4), launches=launches,
+                    work_per_launch=work, source=src)
+
+    # ---- CPU baseline: the oracle on a bounded sample of the same workload
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(wl, filt)
+
+    line = {
+        "metric": METRIC,
+        "value": round(hr["value"], 4),
+        "unit": "directions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(hr["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": FORM_DTYPE[head],
+        "data": "synthetic",
+        "config": {"workload": f"{wl.name}: periodic 64^3 grid, 28 bohr cell, 256 Gaussian wells "
+                               f"+ 20% slab at +0.5 Ha; 1024 states, 800 electrons, kT 0.005 Ha, "
+                               f"Chebyshev degree 40, 16 GRF directions",
+                   "form": head, "warm_start_residual": resid},
+        "rel_err_vs_fp64": hr["rel_err_vs_fp64"],
+        "forms": {f: {"value": round(v["value"], 4), "ms_per_step": round(v["ms_per_step"], 3),
+                      "rel_err_vs_fp64": v["rel_err_vs_fp64"],
+                      "kernel_ms": {k: round(x[0] / max(x[1], 1), 4) for k, x in v["kernels"].items() if x[1]}}
+                  for f, v in results.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(wl, filt):
+    """The FP64 oracle timed on the host on a bounded sample: the filter on 4 states
+    (scaled by N/4), Rayleigh-Ritz on 128 states of the same grid (scaled by
+    (N/128)^2, its leading M N^2 terms), and one full-size direction of the residual
+    derivative (scaled by r)."""
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    g = O.Grid(wl.n, wl.L)
+    V = wl.V[0]
+    N, r = wl.N, wl.rank
+    t0 = time.perf_counter()
+    Xs = wl.block(states=range(4))
+    O.chebyshev_filter(Xs, V, g, wl.degree, *filt)
+    t_filter = (time.perf_counter() - t0) * N / 4
+    Ys = wl.block(states=range(128))
+    t0 = time.perf_counter()
+    O.rayleigh_ritz(Ys, V, g)
+    t_rr = (time.perf_counter() - t0) * (N / 128) ** 2
+    del Ys
+    Psi = wl.block()
+    Psi /= np.sqrt(g.M)
+    eps = np.sort(np.random.default_rng(0).uniform(-2.0, 1.0, N))
+    u = wl.directions(rank=1)
+    t0 = time.perf_counter()
+    O.residual_derivative(Psi[None], eps[None], g, wl.n_electrons, wl.kT, u, 1)
+    t_dir = time.perf_counter() - t0
+    del Psi
+    t_step = t_filter + t_rr + r * t_dir
+    log(f"cpu oracle: filter {t_filter:.1f}s (scaled), RR {t_rr:.1f}s (scaled), direction {t_dir:.2f}s")
+    return {"value": round(r / t_step, 5), "unit": "directions/s", "cores": cores, "kind": "oracle",
+            "sample": "FP64 NumPy oracle: filter on 4 of 1024 states (x256), Rayleigh-Ritz on 128 "
+                      "states (x64), one full-size residual-derivative direction (x16); "
+                      f"estimated step {t_step:.1f}s"}
+
+
+if __name__ == "__main__":
+    main()

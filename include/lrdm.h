@@ -105,6 +105,17 @@ lrdm_status lrdm_set_checks(lrdm_ctx* ctx, int level);
 /* Bytes of device workspace the context currently holds. */
 size_t lrdm_workspace_bytes(const lrdm_ctx* ctx);
 
+/* Per-kernel timing for measurement: with enable = 1 the context records a
+ * hipEvent pair on its stream around each launch of its main kernels
+ * ("cheb_step": filter steps with a three-term update, "hpsi": plain H X or
+ * the first filter step, "proj": projected perturbation, "gram": Gram and
+ * projected-Hamiltonian products, "backproj", "nn", "eigh", "hartree").
+ * lrdm_profile_read synchronises the stream and returns, for one kernel name,
+ * the summed milliseconds and the number of launches recorded since the last
+ * read of that name, then forgets them. */
+lrdm_status lrdm_profile(lrdm_ctx* ctx, int enable);
+lrdm_status lrdm_profile_read(lrdm_ctx* ctx, const char* kernel, double* ms, int64_t* launches);
+
 /* Message of the last failure on this context; with ctx == NULL, the last
  * failure of a call made on this thread without a usable context.  The string
  * stays valid until the next call on the same context / thread. */

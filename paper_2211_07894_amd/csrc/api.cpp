@@ -133,6 +133,37 @@ void* ws_take(lrdm_ctx* ctx, size_t bytes) {
   return p;
 }
 
+static hipEvent_t pool_event(lrdm_ctx* ctx) {
+  if (!ctx->event_pool.empty()) {
+    hipEvent_t e = ctx->event_pool.back();
+    ctx->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+ProfScope::ProfScope(lrdm_ctx* ctx, const char* name) : ctx_(ctx), name_(name) {
+  if (!ctx_->profiling) return;
+  start_ = pool_event(ctx_);
+  if (start_ && hipEventRecord(start_, ctx_->stream) != hipSuccess) {
+    ctx_->event_pool.push_back(start_);
+    start_ = nullptr;
+  }
+}
+
+ProfScope::~ProfScope() {
+  if (!start_) return;
+  hipEvent_t stop = pool_event(ctx_);
+  if (!stop || hipEventRecord(stop, ctx_->stream) != hipSuccess) {
+    ctx_->event_pool.push_back(start_);
+    if (stop) ctx_->event_pool.push_back(stop);
+    return;
+  }
+  ctx_->prof.push_back({name_, start_, stop});
+}
+
 size_t tn_bytes(int N, int64_t M, int batch, lrdm_prec prec) {
   return tn_workspace_bytes(N, M, batch, prec);
 }
@@ -176,6 +207,11 @@ extern "C" lrdm_status lrdm_destroy(lrdm_ctx* ctx) {
   hipError_t e = hipStreamSynchronize(ctx->stream);
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->dstatus) (void)hipFree(ctx->dstatus);
+  for (const lrdm_prof_rec& r : ctx->prof) {
+    (void)hipEventDestroy(r.start);
+    (void)hipEventDestroy(r.stop);
+  }
+  for (hipEvent_t ev : ctx->event_pool) (void)hipEventDestroy(ev);
   delete ctx;
   if (e != hipSuccess) return fail_hip(nullptr, "hipStreamSynchronize", e);
   return LRDM_OK;
@@ -195,6 +231,40 @@ extern "C" lrdm_status lrdm_set_checks(lrdm_ctx* ctx, int level) {
 }
 
 extern "C" size_t lrdm_workspace_bytes(const lrdm_ctx* ctx) { return ctx ? ctx->ws_cap : 0; }
+
+extern "C" lrdm_status lrdm_profile(lrdm_ctx* ctx, int enable) {
+  if (!ctx) return fail(nullptr, LRDM_EINVAL, "ctx is NULL");
+  ctx->profiling = enable != 0;
+  return LRDM_OK;
+}
+
+extern "C" lrdm_status lrdm_profile_read(lrdm_ctx* ctx, const char* kernel, double* ms,
+                                         int64_t* launches) {
+  if (!ctx) return fail(nullptr, LRDM_EINVAL, "ctx is NULL");
+  if (!kernel || !ms || !launches) return fail(ctx, LRDM_EINVAL, "kernel, ms and launches must be non-NULL");
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return fail_hip(ctx, "hipStreamSynchronize", e);
+  double total = 0.0;
+  int64_t count = 0;
+  std::vector<lrdm_prof_rec> keep;
+  for (const lrdm_prof_rec& r : ctx->prof) {
+    if (std::strcmp(r.name, kernel) != 0) {
+      keep.push_back(r);
+      continue;
+    }
+    float t = 0.f;
+    e = hipEventElapsedTime(&t, r.start, r.stop);
+    if (e != hipSuccess) return fail_hip(ctx, "hipEventElapsedTime", e);
+    total += t;
+    ++count;
+    ctx->event_pool.push_back(r.start);
+    ctx->event_pool.push_back(r.stop);
+  }
+  ctx->prof.swap(keep);
+  *ms = total;
+  *launches = count;
+  return LRDM_OK;
+}
 
 extern "C" const char* lrdm_last_error(const lrdm_ctx* ctx) {
   return ctx ? ctx->err.c_str() : t_err.c_str();

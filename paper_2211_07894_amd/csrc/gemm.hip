@@ -390,6 +390,7 @@ hipError_t launch_tn_sym<double>(lrdm_ctx* ctx, const double* A, const double* B
   kchunk = (kchunk + KT - 1) / KT * KT;
   double* part = static_cast<double*>(ws_take(ctx, tn_workspace_bytes(N, M, batch, prec)));
   dim3 grd(ntiles, ns, batch);
+  ProfScope prof(ctx, w ? "proj" : "gram");
   tn_sym_f64_kernel<<<grd, 256, 0, ctx->stream>>>(A, B ? B : A, w, w_stride, N, M, nspin, ntb,
                                                    kchunk, part);
   LRDM_HIP(hipGetLastError());
@@ -404,6 +405,7 @@ hipError_t launch_backproj<double>(lrdm_ctx* ctx, const double* A, const double*
                                    int64_t M, int nspin, int batch, lrdm_prec, double scale,
                                    const double* sub, double* out) {
   dim3 grd((unsigned)((M + BT - 1) / BT), batch);
+  ProfScope prof(ctx, "backproj");
   backproj_f64_kernel<<<grd, 256, 0, ctx->stream>>>(A, G, N, M, nspin, scale, sub, out);
   return hipGetLastError();
 }
@@ -412,6 +414,7 @@ template <>
 hipError_t launch_nn<double>(lrdm_ctx* ctx, const double* Wt, const double* B, double* Out, int N,
                              int64_t M) {
   dim3 grd((unsigned)((M + BT - 1) / BT), (N + BT - 1) / BT);
+  ProfScope prof(ctx, "nn");
   nn_f64_kernel<double><<<grd, 256, 0, ctx->stream>>>(Wt, B, Out, N, M);
   return hipGetLastError();
 }

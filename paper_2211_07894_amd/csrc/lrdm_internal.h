@@ -7,8 +7,14 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "lrdm.h"
+
+struct lrdm_prof_rec {
+  const char* name;
+  hipEvent_t start, stop;
+};
 
 struct lrdm_ctx {
   int device = 0;
@@ -18,8 +24,11 @@ struct lrdm_ctx {
   size_t ws_cap = 0;
   size_t ws_top = 0;         // bump pointer inside one call
   int checks = 0;
-  int* dstatus = nullptr;    // device status words (see lrdm_dev_status)
+  int* dstatus = nullptr;    // device status words (LRDM_DS_*)
   std::string err;
+  bool profiling = false;    // record hipEvents around the main kernels
+  std::vector<lrdm_prof_rec> prof;
+  std::vector<hipEvent_t> event_pool;
 };
 
 // Device status word indices (checking mode).
@@ -108,6 +117,18 @@ hipError_t launch_hartree(lrdm_ctx* ctx, const Grid3& g, const double* u, int u_
 size_t hartree_workspace_bytes(const Grid3& g);
 
 hipError_t launch_check_finite(lrdm_ctx* ctx, const double* x, int64_t n);
+
+// Records a start/stop hipEvent pair on ctx->stream around its scope when the
+// context is profiling (see lrdm_profile).
+class ProfScope {
+ public:
+  ProfScope(lrdm_ctx* ctx, const char* name);
+  ~ProfScope();
+ private:
+  lrdm_ctx* ctx_;
+  const char* name_;
+  hipEvent_t start_ = nullptr;
+};
 
 }  // namespace lrdm
 

@@ -115,6 +115,7 @@ size_t hartree_workspace_bytes(const Grid3& g) {
 // scratch: 2 * r * M doubles
 hipError_t launch_hartree(lrdm_ctx* ctx, const Grid3& g, const double* u, int u_nspin, double* dV,
                           int dv_nspin, int r, double* scratch) {
+  ProfScope prof(ctx, "hartree");
   double* tabs = static_cast<double*>(ws_take(ctx, hartree_workspace_bytes(g)));
   double* Ux = tabs;
   double* Uy = Ux + (int64_t)g.nx * g.nx;

@@ -371,6 +371,7 @@ __global__ void canon_kernel(const double* __restrict__ lam, const double* __res
 // given, scales S symmetrically first.
 lrdm_status sym_eigh(lrdm_ctx* ctx, const double* S, int lda, int N, const double* dinv,
                      double* evals, double* evecs) {
+  ProfScope prof(ctx, "eigh");
   const int Np = ((N + JS - 1) / JS) * JS;
   const int nb = Np / JB;
   double* A = static_cast<double*>(ws_take(ctx, (size_t)Np * Np * sizeof(double)));

@@ -98,6 +98,7 @@ hipError_t launch_plane(lrdm_ctx* ctx, const Grid3& g, const double* V, const T*
   if (smem > 65536)
     LRDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&cheb_plane_kernel<T, PPT>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+  ProfScope prof(ctx, beta != 0.0 ? "cheb_step" : "hpsi");
   cheb_plane_kernel<T, PPT><<<grd, threads, smem, ctx->stream>>>(
       Yin, beta != 0.0 ? Yold : nullptr, Yout, V, g.nx, g.ny, g.nz, zrun, wx, wy, wz, dshift,
       T(alpha), T(beta));

@@ -25,6 +25,7 @@ PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 
 EXPORTED = [
     "lrdm_create", "lrdm_destroy", "lrdm_set_stream", "lrdm_set_checks", "lrdm_workspace_bytes",
+    "lrdm_profile", "lrdm_profile_read",
     "lrdm_last_error", "lrdm_hamiltonian_apply", "lrdm_fermi_occupations",
     "lrdm_projected_perturbation", "lrdm_hartree_kernel", "chfsi_filter",
     "subspace_rayleigh_ritz", "density_response", "lrdm_residual_derivative",
@@ -97,6 +98,8 @@ def library() -> ctypes.CDLL:
                 "lrdm_set_stream": [vp, vp],
                 "lrdm_set_checks": [vp, ctypes.c_int],
                 "lrdm_workspace_bytes": [vp],
+                "lrdm_profile": [vp, ctypes.c_int],
+                "lrdm_profile_read": [vp, ctypes.c_char_p, ctypes.POINTER(f64), ctypes.POINTER(ctypes.c_int64)],
                 "lrdm_last_error": [vp],
                 "lrdm_hamiltonian_apply": [vp, G, vp, vp, vp, i32, ctypes.c_int],
                 "lrdm_fermi_occupations": [vp, vp, i32, O, vp, vp, vp, vp],
@@ -136,6 +139,16 @@ class Context:
 
     def set_checks(self, level: int):
         self.check(self.lib.lrdm_set_checks(self.ptr, int(level)))
+
+    def profile(self, enable: bool):
+        self.check(self.lib.lrdm_profile(self.ptr, 1 if enable else 0))
+
+    def profile_read(self, kernel: str):
+        """(total milliseconds, launches) recorded for `kernel` since its last read."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self.check(self.lib.lrdm_profile_read(self.ptr, kernel.encode(), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
 
     @property
     def workspace_bytes(self) -> int:
