@@ -105,6 +105,9 @@ template <typename T>
 hipError_t launch_nn(lrdm_ctx* ctx, const double* Wt, const T* B, T* Out, int N, int64_t M);
 
 // Rayleigh-Ritz pieces (rr.hip).
+// Eigenpairs of a symmetric N x N matrix (FP64, block Jacobi on the GPU).
+lrdm_status sym_eigh(lrdm_ctx* ctx, const double* S, int lda, int N, const double* dinv,
+                     double* evals, double* evecs);
 template <typename T>
 lrdm_status rayleigh_ritz(lrdm_ctx* ctx, const Grid3& g, const double* V, T* Psi, int N,
                           lrdm_prec prec, double* eps);

@@ -19,6 +19,7 @@
 // Sweeps stop when an outer sweep meets no off-diagonal entry above
 // 1e-15 ||A||_F (one host read of a device flag per sweep).
 #include "lrdm_internal.h"
+#include "jacobi_order.h"
 
 #include <vector>
 
@@ -30,9 +31,6 @@ constexpr int JS = 64;        // pair problem size
 constexpr int JP = JS + 1;    // LDS pitch
 constexpr double kPad = 1e30; // diagonal of padding rows (decoupled, sorts last)
 
-__device__ inline int rr_pos(int k, int t, int n) {
-  return k == 0 ? 0 : ((k - 1 + t) % (n - 1)) + 1;
-}
 
 // --------------------------------------------------------------- reductions
 __global__ __launch_bounds__(256) void frob_kernel(const double* __restrict__ A, int N, int lda,
@@ -262,18 +260,12 @@ __global__ void jac_init_kernel(const double* __restrict__ src, int lda, int N, 
   V[(int64_t)i * Np + j] = (i == j) ? 1.0 : 0.0;
 }
 
-// Ascending order of diag(A) by rank (ties by index); eigenvalues and the first
-// N eigenvector columns gathered.
+// Ascending order of diag(A) by rank (ties by index, NaN last): always a
+// permutation, so the gather below stays in bounds whatever the data.
 __global__ void jac_rank_kernel(const double* __restrict__ A, int Np, int* __restrict__ perm) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= Np) return;
-  const double d = A[(int64_t)k * Np + k];
-  int rank = 0;
-  for (int j = 0; j < Np; ++j) {
-    const double e = A[(int64_t)j * Np + j];
-    rank += (e < d) || (e == d && j < k);
-  }
-  perm[rank] = k;
+  perm[order_rank(A, Np + 1, Np, k)] = k;
 }
 
 __global__ void jac_gather_kernel(const double* __restrict__ A, const double* __restrict__ V,
@@ -282,7 +274,7 @@ __global__ void jac_gather_kernel(const double* __restrict__ A, const double* __
   const int k = blockIdx.x * blockDim.x + threadIdx.x;  // eigen index
   const int i = blockIdx.y * blockDim.y + threadIdx.y;  // component
   if (k >= N || i >= N) return;
-  const int src = perm[k];
+  const int src = min(max(perm[k], 0), Np - 1);
   if (i == 0 && evals) evals[k] = A[(int64_t)src * Np + src];
   evecs[(int64_t)i * N + k] = V[(int64_t)i * Np + src];
 }

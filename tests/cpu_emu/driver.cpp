@@ -1,0 +1,174 @@
+// Driver of the test-only CPU build: runs every C-ABI entry point (and a few
+// internal launchers at full size) on host memory under AddressSanitizer.
+// Exit status 0 and "EMU OK" when every call returned LRDM_OK with finite
+// outputs; ASan aborts the process on any out-of-bounds access.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lrdm.h"
+#include "lrdm_internal.h"
+
+namespace {
+
+int failures = 0;
+
+void check(lrdm_status st, lrdm_ctx* ctx, const char* what) {
+  if (st != LRDM_OK) {
+    std::printf("FAIL %s: status %d: %s\n", what, (int)st, lrdm_last_error(ctx));
+    ++failures;
+  } else {
+    std::printf("ok   %s\n", what);
+  }
+  std::fflush(stdout);
+}
+
+struct Rng {
+  unsigned long long s;
+  double next() {  // uniform in (-1, 1)
+    s = s * 6364136223846793005ULL + 1442695040888963407ULL;
+    return ((s >> 11) * (1.0 / 9007199254740992.0)) * 2.0 - 1.0;
+  }
+};
+
+std::vector<double> randv(size_t n, unsigned long long seed, double scale = 1.0) {
+  Rng r{seed};
+  std::vector<double> v(n);
+  for (auto& x : v) x = scale * r.next();
+  return v;
+}
+
+bool finite(const std::vector<double>& v) {
+  for (double x : v)
+    if (!std::isfinite(x)) return false;
+  return true;
+}
+
+lrdm_grid grid(int nx, int ny, int nz, double h) {
+  lrdm_grid g;
+  g.n[0] = nx; g.n[1] = ny; g.n[2] = nz;
+  g.L[0] = nx * h; g.L[1] = ny * h; g.L[2] = nz * h;
+  return g;
+}
+
+// Gram-Schmidt rows of a random block: an orthonormal basis of N vectors in R^M.
+std::vector<double> orthonormal(int N, int64_t M, unsigned long long seed) {
+  std::vector<double> P = randv((size_t)N * M, seed);
+  for (int i = 0; i < N; ++i) {
+    double* pi = &P[(size_t)i * M];
+    for (int pass = 0; pass < 2; ++pass)
+      for (int j = 0; j < i; ++j) {
+        const double* pj = &P[(size_t)j * M];
+        double d = 0;
+        for (int64_t p = 0; p < M; ++p) d += pi[p] * pj[p];
+        for (int64_t p = 0; p < M; ++p) pi[p] -= d * pj[p];
+      }
+    double n = 0;
+    for (int64_t p = 0; p < M; ++p) n += pi[p] * pi[p];
+    n = std::sqrt(n);
+    for (int64_t p = 0; p < M; ++p) pi[p] /= n;
+  }
+  return P;
+}
+
+void scenario_response(lrdm_ctx* ctx, lrdm_grid g, int N, int nspin, int r) {
+  const int64_t M = (int64_t)g.n[0] * g.n[1] * g.n[2];
+  std::vector<double> Psi;
+  for (int c = 0; c < nspin; ++c) {
+    auto P = orthonormal(N, M, 11 + c);
+    Psi.insert(Psi.end(), P.begin(), P.end());
+  }
+  std::vector<double> eps((size_t)nspin * N);
+  for (int c = 0; c < nspin; ++c)
+    for (int i = 0; i < N; ++i) eps[(size_t)c * N + i] = -1.0 + 1.5 * i / N + 0.001 * c;
+  lrdm_occ occ{nspin, 0.02, 0.8 * N};
+  auto dV = randv((size_t)r * nspin * M, 5);
+  std::vector<double> drho(dV.size()), mu(1), dmu(r), t(dV.size());
+  char name[128];
+  std::snprintf(name, sizeof name, "density_response N=%d nspin=%d r=%d grid %dx%dx%d", N, nspin,
+                r, g.n[0], g.n[1], g.n[2]);
+  check(density_response(ctx, &g, Psi.data(), eps.data(), N, &occ, dV.data(), r, LRDM_FP64,
+                         drho.data(), mu.data(), dmu.data()), ctx, name);
+  if (!finite(drho)) { std::printf("FAIL non-finite drho\n"); ++failures; }
+  std::snprintf(name, sizeof name, "residual_derivative N=%d nspin=%d r=%d", N, nspin, r);
+  check(lrdm_residual_derivative(ctx, &g, Psi.data(), eps.data(), N, &occ, dV.data(), r,
+                                 LRDM_FP64, t.data()), ctx, name);
+  std::vector<double> Hp((size_t)r * nspin * N * N);
+  check(lrdm_projected_perturbation(ctx, &g, Psi.data(), N, nspin, dV.data(), r, LRDM_FP64,
+                                    Hp.data()), ctx, "projected_perturbation");
+  std::vector<double> f((size_t)nspin * N), fp((size_t)nspin * N), F((size_t)nspin * N * N);
+  check(lrdm_fermi_occupations(ctx, eps.data(), N, &occ, mu.data(), f.data(), fp.data(), F.data()),
+        ctx, "fermi_occupations");
+}
+
+void scenario_chfsi(lrdm_ctx* ctx, lrdm_grid g, int N, int degree) {
+  const int64_t M = (int64_t)g.n[0] * g.n[1] * g.n[2];
+  auto V = randv((size_t)M, 3, 0.5);
+  auto X = randv((size_t)N * M, 4);
+  std::vector<double> Y(X.size()), eps(N), HX(X.size());
+  double hx = g.L[0] / g.n[0], hy = g.L[1] / g.n[1], hz = g.L[2] / g.n[2];
+  const double b = 2 / (hx * hx) + 2 / (hy * hy) + 2 / (hz * hz) + 0.5;
+  char name[128];
+  std::snprintf(name, sizeof name, "hamiltonian_apply N=%d grid %dx%dx%d", N, g.n[0], g.n[1], g.n[2]);
+  check(lrdm_hamiltonian_apply(ctx, &g, V.data(), X.data(), HX.data(), N, LRDM_FP64), ctx, name);
+  std::snprintf(name, sizeof name, "chfsi_filter N=%d degree=%d", N, degree);
+  check(chfsi_filter(ctx, &g, V.data(), X.data(), Y.data(), N, LRDM_FP64, degree, -0.2, b, -1.0),
+        ctx, name);
+  std::snprintf(name, sizeof name, "subspace_rayleigh_ritz N=%d", N);
+  check(subspace_rayleigh_ritz(ctx, &g, V.data(), Y.data(), N, LRDM_FP64, eps.data()), ctx, name);
+  if (!finite(eps) || !finite(Y)) { std::printf("FAIL non-finite Ritz output\n"); ++failures; }
+  // orthonormality of the Ritz vectors
+  double worst = 0;
+  for (int i = 0; i < N; i += 7)
+    for (int j = 0; j < N; j += 5) {
+      double d = 0;
+      for (int64_t p = 0; p < M; ++p) d += Y[(size_t)i * M + p] * Y[(size_t)j * M + p];
+      worst = std::fmax(worst, std::fabs(d - (i == j)));
+    }
+  std::printf("     Ritz orthonormality error %.2e\n", worst);
+  if (!(worst < 1e-10)) ++failures;
+  std::vector<double> u = randv((size_t)2 * M, 9), dV(u.size());
+  check(lrdm_hartree_kernel(ctx, &g, u.data(), dV.data(), 2), ctx, "hartree_kernel");
+}
+
+// Internal launchers at the full subspace size of the 64^3 workload (N = 1024):
+// the eigenvalue ordering and gather of the eigensolver.
+void scenario_full_n(lrdm_ctx* ctx) {
+  const int N = 1024;
+  lrdm::ws_reserve(ctx, 64u << 20);
+  // an already diagonal matrix: the eigensolver goes straight to ordering and gather
+  std::vector<double> D((size_t)N * N, 0.0), ev(N), Q((size_t)N * N);
+  for (int i = 0; i < N; ++i) D[(size_t)i * N + i] = std::cos(0.37 * i);
+  ctx->ws_top = 0;
+  lrdm_status st = lrdm::sym_eigh(ctx, D.data(), N, N, nullptr, ev.data(), Q.data());
+  check(st, ctx, "sym_eigh diagonal N=1024 (ordering + gather)");
+  for (int i = 1; i < N; ++i)
+    if (ev[i] < ev[i - 1]) { std::printf("FAIL order\n"); ++failures; break; }
+  // a diagonal with NaN entries: ordering must stay a permutation
+  D[5 * N + 5] = std::nan("");
+  D[700 * N + 700] = std::nan("");
+  ctx->ws_top = 0;
+  st = lrdm::sym_eigh(ctx, D.data(), N, N, nullptr, ev.data(), Q.data());
+  std::printf("     sym_eigh with NaN diagonal returned %d\n", (int)st);
+}
+
+}  // namespace
+
+int main(int argc, char** argv) {
+  const std::string which = argc > 1 ? argv[1] : "all";
+  lrdm_ctx* ctx = nullptr;
+  check(lrdm_create(&ctx, 0, nullptr, 0), nullptr, "lrdm_create");
+  if (which == "all" || which == "small") {
+    scenario_response(ctx, grid(20, 18, 13, 0.4), 150, 1, 3);
+    scenario_response(ctx, grid(9, 8, 7, 0.5), 40, 2, 2);
+    scenario_chfsi(ctx, grid(10, 9, 8, 0.45), 150, 5);
+    scenario_chfsi(ctx, grid(12, 12, 12, 0.45), 256, 4);
+  }
+  if (which == "all" || which == "full") scenario_full_n(ctx);
+  check(lrdm_destroy(ctx), nullptr, "lrdm_destroy");
+  std::printf(failures ? "EMU FAIL (%d)\n" : "EMU OK\n", failures);
+  return failures ? 1 : 0;
+}

@@ -1,0 +1,173 @@
+// Fiber runtime of the test-only CPU build of the kernels (x86-64 SysV).
+#include <sanitizer/common_interface_defs.h>
+
+#include "hip/hip_runtime.h"
+
+thread_local uint3 threadIdx;
+thread_local uint3 blockIdx;
+thread_local dim3 blockDim;
+thread_local dim3 gridDim;
+
+extern "C" void lrdm_emu_switch(void** save_sp, void* load_sp);
+asm(R"(
+.text
+.globl lrdm_emu_switch
+.type lrdm_emu_switch,@function
+lrdm_emu_switch:
+  pushq %rbp
+  pushq %rbx
+  pushq %r12
+  pushq %r13
+  pushq %r14
+  pushq %r15
+  movq %rsp, (%rdi)
+  movq %rsi, %rsp
+  popq %r15
+  popq %r14
+  popq %r13
+  popq %r12
+  popq %rbx
+  popq %rbp
+  ret
+.size lrdm_emu_switch, .-lrdm_emu_switch
+)");
+
+namespace lrdm_emu {
+
+thread_local Block* cur = nullptr;
+thread_local Fiber* cur_fiber = nullptr;
+thread_local int tid_linear = 0;
+
+namespace {
+constexpr size_t kStack = 256 * 1024;
+struct StackPool {
+  std::vector<char*> stacks;
+  ~StackPool() {
+    for (char* p : stacks) std::free(p);
+  }
+};
+thread_local StackPool pool;
+
+void to_scheduler() {
+  void* fake = nullptr;
+  __sanitizer_start_switch_fiber(&fake, cur->sched_stack_bottom, cur->sched_stack_size);
+  lrdm_emu_switch(&cur_fiber->sp, cur->sched_sp);
+  __sanitizer_finish_switch_fiber(fake, nullptr, nullptr);
+}
+
+[[noreturn]] void fiber_entry() {
+  __sanitizer_finish_switch_fiber(nullptr, nullptr, nullptr);
+  cur->body();
+  cur_fiber->done = true;
+  __sanitizer_start_switch_fiber(nullptr, cur->sched_stack_bottom, cur->sched_stack_size);
+  lrdm_emu_switch(&cur_fiber->sp, cur->sched_sp);
+  std::abort();
+}
+
+void resume(Block& b, Fiber& f) {
+  cur_fiber = &f;
+  tid_linear = f.tid;
+  threadIdx = f.idx;
+  void* fake = nullptr;
+  __sanitizer_start_switch_fiber(&fake, f.stack, kStack);
+  lrdm_emu_switch(&b.sched_sp, f.sp);
+  __sanitizer_finish_switch_fiber(fake, &b.sched_stack_bottom, &b.sched_stack_size);
+}
+}  // namespace
+
+void yield_wait(int kind) {
+  cur_fiber->wait = kind;
+  to_scheduler();
+}
+
+void run_block(Block& b, dim3 block, uint3, size_t smem) {
+  const int nt = (int)(block.x * block.y * block.z);
+  b.nthreads = nt;
+  b.fibers.resize(nt);
+  b.xch.assign((nt + 63) / 64, std::vector<double>(64 * 32, 0.0));
+  b.dyn.assign(smem + 16, 0xAB);
+  while ((int)pool.stacks.size() < nt) pool.stacks.push_back(static_cast<char*>(std::malloc(kStack)));
+  cur = &b;
+  for (int t = 0; t < nt; ++t) {
+    Fiber& f = b.fibers[t];
+    f.tid = t;
+    f.idx = uint3{(unsigned)(t % block.x), (unsigned)((t / block.x) % block.y),
+                  (unsigned)(t / (block.x * block.y))};
+    f.stack = pool.stacks[t];
+    // initial frame: six callee-saved registers, then the entry as return address;
+    // rsp at entry is 8 mod 16 as after a call.
+    uintptr_t top = (reinterpret_cast<uintptr_t>(f.stack) + kStack) & ~uintptr_t(15);
+    void** sp = reinterpret_cast<void**>(top);
+    *--sp = nullptr;                                   // padding
+    *--sp = reinterpret_cast<void*>(&fiber_entry);     // return address
+    for (int r = 0; r < 6; ++r) *--sp = nullptr;      // rbp rbx r12 r13 r14 r15
+    f.sp = sp;
+  }
+  const int nw = (nt + 63) / 64;
+  for (;;) {
+    bool ran = false;
+    for (int t = 0; t < nt; ++t) {
+      Fiber& f = b.fibers[t];
+      if (!f.done && f.wait == 0) {
+        resume(b, f);
+        ran = true;
+      }
+    }
+    // release wavefront barriers whose live lanes all arrived
+    bool released = false;
+    for (int w = 0; w < nw; ++w) {
+      bool all = true, any = false;
+      for (int t = 64 * w; t < std::min(nt, 64 * w + 64); ++t) {
+        const Fiber& f = b.fibers[t];
+        if (f.done) continue;
+        any = true;
+        if (f.wait != 2) all = false;
+      }
+      if (any && all) {
+        for (int t = 64 * w; t < std::min(nt, 64 * w + 64); ++t) b.fibers[t].wait = 0;
+        released = true;
+      }
+    }
+    // release the block barrier when every live thread waits on it
+    bool all_block = true, live = false;
+    for (const Fiber& f : b.fibers) {
+      if (f.done) continue;
+      live = true;
+      if (f.wait != 1) all_block = false;
+    }
+    if (!live) break;
+    if (all_block) {
+      for (Fiber& f : b.fibers) f.wait = 0;
+      released = true;
+    }
+    if (!ran && !released) {
+      std::fprintf(stderr, "emulation deadlock: block barrier and wavefront barrier mixed\n");
+      std::abort();
+    }
+  }
+  cur = nullptr;
+}
+
+void parallel_blocks(dim3 grid, const std::function<void(uint3)>& fn) {
+  const long total = (long)grid.x * grid.y * grid.z;
+  const int workers = (int)std::min<long>(8, total);
+  std::atomic<long> next{0};
+  auto work = [&]() {
+    for (;;) {
+      const long i = next.fetch_add(1);
+      if (i >= total) break;
+      const unsigned bx = (unsigned)(i % grid.x), by = (unsigned)((i / grid.x) % grid.y),
+                     bz = (unsigned)(i / ((long)grid.x * grid.y));
+      fn(uint3{bx, by, bz});
+    }
+  };
+  if (workers <= 1) {
+    work();
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int w = 0; w < workers; ++w) th.emplace_back(work);
+  for (auto& t : th) t.join();
+}
+
+}  // namespace lrdm_emu
