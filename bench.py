@@ -145,7 +145,7 @@ def main():
             log(f"form {form} unavailable: {ex}")
             continue
         ctx.profile(True)
-        for k in ["cheb_step", "hpsi", "proj", "gram", "backproj", "nn", "gemm_nn", "eigh", "hartree"]:
+        for k in ["cheb_step", "hpsi", "proj", "gram", "backproj", "nn", "eigh", "jac_sweep", "jac_solve", "jac_update", "hartree"]:
             ctx.profile_read(k)
         torch.cuda.synchronize()
         t_start = time.perf_counter()
@@ -155,7 +155,7 @@ def main():
         elapsed = time.perf_counter() - t_start
         ctx.profile(False)
         kern = {k: ctx.profile_read(k) for k in
-                ["cheb_step", "hpsi", "proj", "gram", "backproj", "nn", "gemm_nn", "eigh", "hartree"]}
+                ["cheb_step", "hpsi", "proj", "gram", "backproj", "nn", "eigh", "jac_sweep", "jac_solve", "jac_update", "hartree"]}
         ms_step = 1e3 * elapsed / args.steps
         rel = None
         if form == "fp64":

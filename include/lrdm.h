@@ -109,7 +109,9 @@ size_t lrdm_workspace_bytes(const lrdm_ctx* ctx);
  * hipEvent pair on its stream around each launch of its main kernels
  * ("cheb_step": filter steps with a three-term update, "hpsi": plain H X or
  * the first filter step, "proj": projected perturbation, "gram": Gram and
- * projected-Hamiltonian products, "backproj", "nn", "eigh", "hartree").
+ * projected-Hamiltonian products, "backproj", "nn", "eigh" (one launch per
+ * eigensolve), "jac_sweep" (one per outer sweep), "jac_solve", "jac_update",
+ * "hartree").
  * lrdm_profile_read synchronises the stream and returns, for one kernel name,
  * the summed milliseconds and the number of launches recorded since the last
  * read of that name, then forgets them. */

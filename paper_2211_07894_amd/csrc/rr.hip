@@ -2,9 +2,9 @@
 // eigensolver it needs, both on the GPU.
 //
 // Orthonormalisation: with the filtered block Y (rows = vectors) and
-// G = Y Y^T = D Gs D (D = diag of column norms), the canonical orthogonalisation
-// T = Lambda^{-1/2} U^T D^{-1} (Gs = U Lambda U^T) gives orthonormal rows
-// Psi_o = T Y.  The projected Hamiltonian is Hhat = T (Y (H Y)^T) T^T, its
+// G = Y Y^T = D^{-1} Gs D^{-1} (D^{-1} = diag of row norms), the symmetric
+// (Loewdin) factor T = Gs^{-1/2} D, from a coupled Newton-Schulz iteration,
+// gives orthonormal rows Psi_o = T Y.  The projected Hamiltonian is Hhat = T (Y (H Y)^T) T^T, its
 // eigenpairs Hhat = Q E Q^T give eps = E and Psi_R = Q^T T Y: one pass over the
 // grid for Gram, one stencil pass, one pass for Y (HY)^T and one rotation pass.
 // Column scaling makes a warm-started block (Y ~ eigenvectors times filter
@@ -13,14 +13,18 @@
 // Eigensolver: two-sided block Jacobi.  The matrix (padded to a multiple of 64
 // with decoupled diagonal entries 1e30) is cut into 32-wide blocks; each outer
 // round pairs blocks by a round-robin tournament and a workgroup diagonalises
-// each 64 x 64 pair problem in LDS with cyclic Jacobi (rotations
+// each 64 x 64 pair problem in LDS with one or two sweeps of cyclic Jacobi
+// (1024 threads, one 2 x 2 block of the pair rotation per thread; rotations
 // t = sign(z)/(|z| + sqrt(1 + z^2)), z = (a_qq - a_pp)/(2 a_pq)); a second kernel
 // applies the pair rotations to A and to the eigenvector matrix as 64 x 64 GEMMs.
-// Sweeps stop when an outer sweep meets no off-diagonal entry above
-// 1e-15 ||A||_F (one host read of a device flag per sweep).
+// Rotations are applied above 1e-16 ||A||_F; sweeps stop when an outer sweep
+// meets no off-diagonal entry above 1e-13 ||A||_F (one host read of a device
+// flag per sweep), about ten times the rounding left by the 64-wide rotation
+// updates, so the stop is reachable.
 #include "lrdm_internal.h"
 #include "jacobi_order.h"
 
+#include <utility>
 #include <vector>
 
 namespace lrdm {
@@ -30,6 +34,7 @@ constexpr int JB = 32;        // block width
 constexpr int JS = 64;        // pair problem size
 constexpr int JP = JS + 1;    // LDS pitch
 constexpr double kPad = 1e30; // diagonal of padding rows (decoupled, sorts last)
+constexpr int kNewtonSchulz = 28;  // fixed Newton-Schulz steps of the orthonormalisation
 
 
 // --------------------------------------------------------------- reductions
@@ -49,7 +54,7 @@ __global__ __launch_bounds__(256) void frob_kernel(const double* __restrict__ A,
 }
 
 // --------------------------------------------------------------- block Jacobi
-__global__ __launch_bounds__(256) void jac_solve_kernel(const double* __restrict__ A, int Np,
+__global__ __launch_bounds__(1024) void jac_solve_kernel(const double* __restrict__ A, int Np,
                                                         int nb, int t,
                                                         const double* __restrict__ normF_ptr,
                                                         double* __restrict__ Ublk,
@@ -69,7 +74,7 @@ __global__ __launch_bounds__(256) void jac_solve_kernel(const double* __restrict
     U[a * JP + c] = (a == c) ? 1.0 : 0.0;
   }
   const double normF = *normF_ptr;
-  const double thr_apply = 1e-16 * normF, thr_flag = 1e-15 * normF;
+  const double thr_apply = 1e-16 * normF, thr_flag = 1e-13 * normF;
   int first_rot = 0;
   __syncthreads();
   for (int sw = 0; sw < max_inner; ++sw) {
@@ -347,13 +352,41 @@ __global__ void diag_rsqrt_kernel(const double* __restrict__ G, int N, double* _
   if (i < N) dinv[i] = 1.0 / sqrt(G[(int64_t)i * N + i]);
 }
 
-// T[k][j] = lambda_k^{-1/2} U[j][k] dinv_j
-__global__ void canon_kernel(const double* __restrict__ lam, const double* __restrict__ U,
-                             const double* __restrict__ dinv, int N, double* __restrict__ T) {
+
+// Gs = D G D (symmetrised), D = diag(dinv): the column-scaled Gram matrix.
+__global__ void gram_scale_kernel(const double* __restrict__ G, const double* __restrict__ dinv,
+                                  int N, double* __restrict__ Gs) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int k = blockIdx.y * blockDim.y + threadIdx.y;
-  if (j >= N || k >= N) return;
-  T[(int64_t)k * N + j] = U[(int64_t)j * N + k] * dinv[j] / sqrt(lam[k]);
+  const int i = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= N || j >= N) return;
+  Gs[(int64_t)i * N + j] = 0.5 * (G[(int64_t)i * N + j] + G[(int64_t)j * N + i]) * dinv[i] * dinv[j];
+}
+
+// Y0 = Gs / ||Gs||_F (spectrum in (0, 1]), Z0 = I.
+__global__ void ns_start_kernel(const double* __restrict__ Gs, const double* __restrict__ fro,
+                                int N, double* __restrict__ Y, double* __restrict__ Z) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= N || j >= N) return;
+  Y[(int64_t)i * N + j] = Gs[(int64_t)i * N + j] / *fro;
+  Z[(int64_t)i * N + j] = (i == j) ? 1.0 : 0.0;
+}
+
+// T = (3 I - W) / 2
+__global__ void ns_step_kernel(const double* __restrict__ W, int N, double* __restrict__ T) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= N || j >= N) return;
+  T[(int64_t)i * N + j] = (i == j ? 1.5 : 0.0) - 0.5 * W[(int64_t)i * N + j];
+}
+
+// Tm[i][j] = Z[i][j] dinv[j] / sqrt(||Gs||_F): Gs^{-1/2} D, orthonormal rows Tm Y.
+__global__ void ns_finish_kernel(const double* __restrict__ Z, const double* __restrict__ dinv,
+                                 const double* __restrict__ fro, int N, double* __restrict__ T) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= N || j >= N) return;
+  T[(int64_t)i * N + j] = Z[(int64_t)i * N + j] * dinv[j] / sqrt(*fro);
 }
 
 }  // namespace
@@ -387,12 +420,20 @@ lrdm_status sym_eigh(lrdm_ctx* ctx, const double* S, int lda, int N, const doubl
   const int max_sweeps = 40;
   int sweep = 0;
   for (; sweep < max_sweeps; ++sweep) {
+    ProfScope prof_sweep(ctx, "jac_sweep");
     if ((e = hipMemsetAsync(flag, 0, sizeof(int), ctx->stream)) != hipSuccess) return fail(e);
     for (int t = 0; t < nb - 1; ++t) {
-      jac_solve_kernel<<<nb / 2, 256, 0, ctx->stream>>>(A, Np, nb, t, normF, Ublk, flag, 12);
+      {
+        ProfScope prof_solve(ctx, "jac_solve");
+        jac_solve_kernel<<<nb / 2, 1024, 0, ctx->stream>>>(A, Np, nb, t, normF, Ublk, flag,
+                                                            sweep == 0 ? 2 : 1);
+      }
       if ((e = hipGetLastError()) != hipSuccess) return fail(e);
       const int np = nb / 2;
-      jac_update_kernel<<<np * np + (Np / JS) * np, 256, 0, ctx->stream>>>(A, V, Np, nb, t, Ublk);
+      {
+        ProfScope prof_update(ctx, "jac_update");
+        jac_update_kernel<<<np * np + (Np / JS) * np, 256, 0, ctx->stream>>>(A, V, Np, nb, t, Ublk);
+      }
       if ((e = hipGetLastError()) != hipSuccess) return fail(e);
     }
     int host_flag = 0;
@@ -458,13 +499,36 @@ lrdm_status rayleigh_ritz(lrdm_ctx* ctx, const Grid3& g, const double* V, T* Psi
   ctx->ws_top = mark;
   diag_rsqrt_kernel<<<(N + 255) / 256, 256, 0, ctx->stream>>>(G, N, dinv);
   if ((e = hipGetLastError()) != hipSuccess) return fail("scale", e);
-  lrdm_status st = sym_eigh(ctx, G, N, N, dinv, lam, Ug);
-  if (st != LRDM_OK) return st;
-  ctx->ws_top = mark;
+  // Loewdin factor Gs^{-1/2} by the coupled Newton-Schulz iteration
+  //   W = Z Y, T = (3I - W)/2, Y <- Y T, Z <- T Z   (Y -> Gs'^{1/2}, Z -> Gs'^{-1/2})
+  // on Gs' = Gs / ||Gs||_F, whose spectrum lies in (0, 1].  A fixed count of
+  // kNewtonSchulz steps: a warm-started block needs about 10, a cold one with
+  // cond(Gs) up to ~1e6 about 24; steps past convergence leave the fixed point.
+  double* Ya = X;
+  double* Za = C;
+  double* Yb = Hy;
+  double* Zb = Wt;
+  double* W = G;
+  double* Tn = Ug;
+  double* fro = lam;
   {
     dim3 blk(32, 8), grd((N + 31) / 32, (N + 7) / 8);
-    canon_kernel<<<grd, blk, 0, ctx->stream>>>(lam, Ug, dinv, N, Tm);
-    if ((e = hipGetLastError()) != hipSuccess) return fail("canonical", e);
+    gram_scale_kernel<<<grd, blk, 0, ctx->stream>>>(G, dinv, N, Tm);
+    frob_kernel<<<1, 256, 0, ctx->stream>>>(Tm, N, N, fro);
+    ns_start_kernel<<<grd, blk, 0, ctx->stream>>>(Tm, fro, N, Ya, Za);
+    if ((e = hipGetLastError()) != hipSuccess) return fail("scale", e);
+    for (int it = 0; it < kNewtonSchulz; ++it) {
+      if ((e = small_gemm(ctx, false, false, N, N, N, 1.0, Za, N, Ya, N, 0.0, W, N)) != hipSuccess)
+        return fail("newton-schulz", e);
+      ns_step_kernel<<<grd, blk, 0, ctx->stream>>>(W, N, Tn);
+      if ((e = small_gemm(ctx, false, false, N, N, N, 1.0, Ya, N, Tn, N, 0.0, Yb, N)) != hipSuccess ||
+          (e = small_gemm(ctx, false, false, N, N, N, 1.0, Tn, N, Za, N, 0.0, Zb, N)) != hipSuccess)
+        return fail("newton-schulz", e);
+      std::swap(Ya, Yb);
+      std::swap(Za, Zb);
+    }
+    ns_finish_kernel<<<grd, blk, 0, ctx->stream>>>(Za, dinv, fro, N, Tm);
+    if ((e = hipGetLastError()) != hipSuccess) return fail("scale", e);
   }
   // H Y and Y (H Y)^T
   if ((e = launch_cheb_step<T>(ctx, g, V, Psi, nullptr, HY, N, 1.0, 0.0, 0.0)) != hipSuccess)
@@ -477,7 +541,7 @@ lrdm_status rayleigh_ritz(lrdm_ctx* ctx, const Grid3& g, const double* V, T* Psi
     return fail("gemm", e);
   if ((e = small_gemm(ctx, false, true, N, N, N, 1.0, X, N, Tm, N, 0.0, C, N)) != hipSuccess)
     return fail("gemm", e);
-  st = sym_eigh(ctx, C, N, N, nullptr, eps, Ug);
+  lrdm_status st = sym_eigh(ctx, C, N, N, nullptr, eps, Ug);
   if (st != LRDM_OK) return st;
   ctx->ws_top = mark;
   // Psi_R = Q^T T Y: the rotation kernel computes Wt^T Y with Wt = T^T Q

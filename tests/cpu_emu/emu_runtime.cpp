@@ -75,6 +75,11 @@ void resume(Block& b, Fiber& f) {
 }
 }  // namespace
 
+Block& worker_block() {
+  static thread_local Block b;
+  return b;
+}
+
 void yield_wait(int kind) {
   cur_fiber->wait = kind;
   to_scheduler();
@@ -83,9 +88,10 @@ void yield_wait(int kind) {
 void run_block(Block& b, dim3 block, uint3, size_t smem) {
   const int nt = (int)(block.x * block.y * block.z);
   b.nthreads = nt;
-  b.fibers.resize(nt);
-  b.xch.assign((nt + 63) / 64, std::vector<double>(64 * 32, 0.0));
-  b.dyn.assign(smem + 16, 0xAB);
+  b.fibers.assign(nt, Fiber{});
+  if ((int)b.xch.size() < (nt + 63) / 64) b.xch.resize((nt + 63) / 64, std::vector<double>(64 * 32, 0.0));
+  if (b.dyn.size() < smem + 16) b.dyn.resize(smem + 16);
+  std::fill(b.dyn.begin(), b.dyn.end(), (unsigned char)0xAB);
   while ((int)pool.stacks.size() < nt) pool.stacks.push_back(static_cast<char*>(std::malloc(kStack)));
   cur = &b;
   for (int t = 0; t < nt; ++t) {
@@ -148,26 +154,69 @@ void run_block(Block& b, dim3 block, uint3, size_t smem) {
   cur = nullptr;
 }
 
-void parallel_blocks(dim3 grid, const std::function<void(uint3)>& fn) {
-  const long total = (long)grid.x * grid.y * grid.z;
-  const int workers = (int)std::min<long>(8, total);
+// Persistent pool of host threads that run the blocks of each launch; each
+// keeps its fiber stacks between launches.
+namespace {
+struct Pool {
+  std::mutex m;
+  std::condition_variable cv_job, cv_done;
+  const std::function<void(uint3)>* fn = nullptr;
+  dim3 grid;
+  long total = 0;
   std::atomic<long> next{0};
-  auto work = [&]() {
-    for (;;) {
-      const long i = next.fetch_add(1);
-      if (i >= total) break;
-      const unsigned bx = (unsigned)(i % grid.x), by = (unsigned)((i / grid.x) % grid.y),
-                     bz = (unsigned)(i / ((long)grid.x * grid.y));
-      fn(uint3{bx, by, bz});
-    }
-  };
-  if (workers <= 1) {
-    work();
-    return;
+  int active = 0;
+  long generation = 0;
+  bool stop = false;
+  std::vector<std::thread> workers;
+
+  explicit Pool(int n) {
+    for (int w = 0; w < n; ++w) workers.emplace_back([this] { loop(); });
   }
-  std::vector<std::thread> th;
-  for (int w = 0; w < workers; ++w) th.emplace_back(work);
-  for (auto& t : th) t.join();
+  ~Pool() {
+    {
+      std::lock_guard<std::mutex> lk(m);
+      stop = true;
+    }
+    cv_job.notify_all();
+    for (auto& t : workers) t.join();
+  }
+  void loop() {
+    long seen = 0;
+    for (;;) {
+      {
+        std::unique_lock<std::mutex> lk(m);
+        cv_job.wait(lk, [&] { return stop || generation != seen; });
+        if (stop) return;
+        seen = generation;
+      }
+      for (;;) {
+        const long i = next.fetch_add(1);
+        if (i >= total) break;
+        const unsigned bx = (unsigned)(i % grid.x), by = (unsigned)((i / grid.x) % grid.y),
+                       bz = (unsigned)(i / ((long)grid.x * grid.y));
+        (*fn)(uint3{bx, by, bz});
+      }
+      std::lock_guard<std::mutex> lk(m);
+      if (--active == 0) cv_done.notify_all();
+    }
+  }
+  void run(dim3 g, const std::function<void(uint3)>& f) {
+    std::unique_lock<std::mutex> lk(m);
+    fn = &f;
+    grid = g;
+    total = (long)g.x * g.y * g.z;
+    next = 0;
+    active = (int)workers.size();
+    ++generation;
+    cv_job.notify_all();
+    cv_done.wait(lk, [&] { return active == 0; });
+  }
+};
+}  // namespace
+
+void parallel_blocks(dim3 grid, const std::function<void(uint3)>& fn) {
+  static Pool pool(8);
+  pool.run(grid, fn);
 }
 
 }  // namespace lrdm_emu

@@ -103,11 +103,12 @@ inline double* wave_buf() { return cur->xch[wave()].data(); }
 inline unsigned char* dyn_smem() { return cur->dyn.data(); }
 
 void parallel_blocks(dim3 grid, const std::function<void(uint3)>& fn);
+Block& worker_block();
 
 template <typename K, typename... Args>
 void launch(K kernel, dim3 grid, dim3 block, size_t smem, hipStream_t, Args... args) {
   parallel_blocks(grid, [&](uint3 bidx) {
-    Block b;
+    Block& b = worker_block();
     b.body = [&]() { kernel(args...); };
     blockDim = block;
     gridDim = grid;
