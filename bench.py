@@ -39,10 +39,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--forms", default="fp64")
+    ap.add_argument("--forms", default="fp64,fp32,bf16x3")
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--warm-passes", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run three 1 GiB device copies first: a kernel of known traffic for "
+                         "scaling hardware byte counters")
     return ap.parse_args()
 
 
@@ -89,6 +92,14 @@ def main():
     V = torch.from_numpy(wl.V[0]).to(dev)
     b_up = 2.0 / hx ** 2 + 2.0 / hy ** 2 + 2.0 / hz ** 2 + float(wl.V[0].max())
     log(f"workload {wl.name}: M={M} N={N} r={r} degree={c}")
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)     # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)        # an elementwise kernel: 1 GiB in, 1 GiB out
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy calibration: 3 copies of 1 GiB")
     t0 = time.time()
     X = torch.empty((N,) + grid.shape, dtype=torch.float64, device=dev)
     chunk = 64
@@ -123,7 +134,7 @@ def main():
     filt = (a, b_up, a0)
 
     results = {}
-    ref_t = None
+    ref = None      # FP64 form's Ritz pairs and t on them: the per-stage reference
     for form in forms:
         dt = torch.float64 if form == "fp64" else torch.float32
         Xf = X.to(dt).contiguous()
@@ -157,14 +168,23 @@ def main():
         kern = {k: ctx.profile_read(k) for k in
                 ["cheb_step", "hpsi", "proj", "gram", "backproj", "nn", "eigh", "jac_sweep", "jac_solve", "jac_update", "hartree"]}
         ms_step = 1e3 * elapsed / args.steps
-        rel = None
+        # errors in delta rho = t + u relative to the FP64 form: per stage (this
+        # form's residual derivative on the FP64 Ritz pairs cast to its storage)
+        # and end to end (its own filter and Rayleigh-Ritz)
+        rel = rel_e2e = None
         if form == "fp64":
-            ref_t = t_out.clone()
-            rel = 0.0
-        elif ref_t is not None:
-            rel = float((torch.linalg.vector_norm(t_out - ref_t) / torch.linalg.vector_norm(ref_t)).item())
+            e_last = step()
+            torch.cuda.synchronize()
+            ref = dict(Psi=Yf.clone(), eps=e_last.clone(), t=t_out.clone())
+            rel = rel_e2e = 0.0
+        elif ref is not None:
+            drho_norm = torch.linalg.vector_norm(ref["t"] + U)
+            t_stage = L.residual_derivative(grid, ref["Psi"].to(dt)[None], ref["eps"][None], occ, U,
+                                            prec=form)
+            rel = float((torch.linalg.vector_norm(t_stage - ref["t"]) / drho_norm).item())
+            rel_e2e = float((torch.linalg.vector_norm(t_out - ref["t"]) / drho_norm).item())
         results[form] = dict(ms_per_step=ms_step, value=r * args.steps / elapsed, kernels=kern,
-                             rel_err_vs_fp64=rel)
+                             rel_err_vs_fp64=rel, rel_err_end_to_end=rel_e2e)
         log(f"form {form}: {ms_step:.1f} ms/step, {r * args.steps / elapsed:.2f} directions/s; "
             + ", ".join(f"{k} {v[0] / max(v[1], 1):.3f}ms x{v[1]}" for k, v in kern.items() if v[1]))
         del Xf, Yf
@@ -193,11 +213,15 @@ def main():
     else:
         peak = PEAK["fp64"] if head == "fp64" else (PEAK["fp32"] if head == "fp32" else PEAK["bf16"])
         achieved, unit = work / avg_s / 1e12, "TFLOP/s"
-    src = "gemm.hip" if dom in ("backproj", "proj") else "stencil.hip"
-    # executed work: the contractions skip the lower block triangle (128-wide tiles)
+    src = ("gemm.hip" if head == "fp64" else "gemm_lp.hip") if dom in ("backproj", "proj") \
+        else "stencil.hip"
+    # executed work: the contractions skip the lower block triangle (128-wide
+    # tiles); the BF16X3 form issues six BF16 products per FP32 product
     nt = (N + 127) // 128
-    executed = {"backproj": r * (2.0 * M * 128 * sum(N - 128 * i for i in range(nt)) + 2.0 * M * N),
-                "proj": r * 2.0 * M * 128 * 128 * nt * (nt + 1) / 2,
+    products = 6.0 if head == "bf16x3" else 1.0
+    executed = {"backproj": products * r * (2.0 * M * 128 * sum(N - 128 * i for i in range(nt))
+                                            + 2.0 * M * N),
+                "proj": products * r * 2.0 * M * 128 * 128 * nt * (nt + 1) / 2,
                 "cheb_step": work}[dom]
     ex_rate = executed / avg_s / (1e9 if bound == "hbm" else 1e12)
     roofline = dict(kernel=dom, bound=bound, achieved=round(achieved, 3), peak=peak, unit=unit,
@@ -230,8 +254,10 @@ def main():
                                f"Chebyshev degree 40, 16 GRF directions",
                    "form": head, "warm_start_residual": resid},
         "rel_err_vs_fp64": hr["rel_err_vs_fp64"],
+        "rel_err_end_to_end": hr["rel_err_end_to_end"],
         "forms": {f: {"value": round(v["value"], 4), "ms_per_step": round(v["ms_per_step"], 3),
                       "rel_err_vs_fp64": v["rel_err_vs_fp64"],
+                      "rel_err_end_to_end": v["rel_err_end_to_end"],
                       "kernel_ms": {k: round(x[0] / max(x[1], 1), 4) for k, x in v["kernels"].items() if x[1]}}
                   for f, v in results.items()},
         "roofline": roofline,

@@ -186,17 +186,18 @@ extern "C" lrdm_status lrdm_create(lrdm_ctx** ctx, int device, void* hip_stream,
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->limit = workspace_limit;
-  e = hipMalloc(&c->dstatus, 16 * sizeof(int));
+  e = hipMalloc(&c->dstatus, 64 * sizeof(int));
   if (e != hipSuccess) {
     delete c;
     return fail_hip(nullptr, "hipMalloc status", e);
   }
-  e = hipMemset(c->dstatus, 0, 16 * sizeof(int));
+  e = hipMemset(c->dstatus, 0, 64 * sizeof(int));
   if (e != hipSuccess) {
     (void)hipFree(c->dstatus);
     delete c;
     return fail_hip(nullptr, "hipMemset status", e);
   }
+  c->zeros = reinterpret_cast<const float*>(c->dstatus + 32);
   *ctx = c;
   return LRDM_OK;
 }
@@ -324,7 +325,6 @@ extern "C" lrdm_status lrdm_projected_perturbation(lrdm_ctx* ctx, const lrdm_gri
   LRDM_CHECK(ctx, check_block(grid, N));
   LRDM_CHECK(ctx, check_rank(r));
   LRDM_CHECK(ctx, check_prec(prec));
-  if (prec != LRDM_FP64) return fail(ctx, LRDM_EUNSUPPORTED, "only LRDM_FP64 is available for this call");
   if (nspin != 1 && nspin != 2) return fail(ctx, LRDM_EINVAL, "nspin must be 1 or 2");
   LRDM_NONNULL(ctx, Psi, "Psi");
   LRDM_NONNULL(ctx, dV, "dV");
@@ -416,7 +416,7 @@ size_t response_bytes(int N, int64_t M, int r, int ns, lrdm_prec prec) {
   const int batch = r * ns;
   return ws_align(8) + ws_align((size_t)r * 8) + 3 * ws_align((size_t)ns * N * 8) +
          ws_align((size_t)ns * N * N * 8) + ws_align((size_t)batch * N * N * 8) +
-         ws_align(tn_bytes(N, M, batch, prec));
+         ws_align(tn_bytes(N, M, batch, prec)) + backproj_workspace_bytes(N, M, ns, batch, prec);
 }
 
 }  // namespace
@@ -452,7 +452,6 @@ extern "C" lrdm_status subspace_rayleigh_ritz(lrdm_ctx* ctx, const lrdm_grid* gr
   LRDM_CHECK(ctx, check_grid(grid));
   LRDM_CHECK(ctx, check_block(grid, N));
   LRDM_CHECK(ctx, check_prec(prec));
-  if (prec != LRDM_FP64) return fail(ctx, LRDM_EUNSUPPORTED, "only LRDM_FP64 is available for this call");
   LRDM_NONNULL(ctx, V, "V");
   LRDM_NONNULL(ctx, Psi, "Psi");
   LRDM_NONNULL(ctx, eps, "eps");
@@ -475,7 +474,6 @@ extern "C" lrdm_status density_response(lrdm_ctx* ctx, const lrdm_grid* grid, co
   LRDM_CHECK(ctx, check_occ(occ, N));
   LRDM_CHECK(ctx, check_rank(r));
   LRDM_CHECK(ctx, check_prec(prec));
-  if (prec != LRDM_FP64) return fail(ctx, LRDM_EUNSUPPORTED, "only LRDM_FP64 is available for this call");
   LRDM_NONNULL(ctx, Psi, "Psi");
   LRDM_NONNULL(ctx, eps, "eps");
   LRDM_NONNULL(ctx, dV, "dV");
@@ -502,7 +500,6 @@ extern "C" lrdm_status lrdm_residual_derivative(lrdm_ctx* ctx, const lrdm_grid* 
   LRDM_CHECK(ctx, check_occ(occ, N));
   LRDM_CHECK(ctx, check_rank(r));
   LRDM_CHECK(ctx, check_prec(prec));
-  if (prec != LRDM_FP64) return fail(ctx, LRDM_EUNSUPPORTED, "only LRDM_FP64 is available for this call");
   LRDM_NONNULL(ctx, Psi, "Psi");
   LRDM_NONNULL(ctx, eps, "eps");
   LRDM_NONNULL(ctx, u, "u");

@@ -16,6 +16,7 @@
 //   B operand: lane l supplies B[l/16][l%16]   (k, col)
 //   D: lane l, register v holds D[4v + l/16][l%16].
 #include "lrdm_internal.h"
+#include "xcd.h"
 
 namespace lrdm {
 namespace {
@@ -30,75 +31,84 @@ __device__ inline d4 mfma64(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// Stage rows [r0, r0+BT) x cols [k0, k0+KT) of a row-major [nrows][ld] array into
-// S[k][row] (transposed), optionally scaling column k by w[k].  Each thread
-// loads 16 consecutive k of one row.  Out-of-range elements are zero.
+// 16 consecutive elements of storage type S from a 16-byte aligned address.
+__device__ inline void load16(const double* src, double (&v)[16]) {
+  const double2* s2 = reinterpret_cast<const double2*>(src);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const double2 x = s2[q];
+    v[2 * q] = x.x;
+    v[2 * q + 1] = x.y;
+  }
+}
+__device__ inline void load16(const float* src, float (&v)[16]) {
+  const float4* s4 = reinterpret_cast<const float4*>(src);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float4 x = s4[q];
+    v[4 * q] = x.x;
+    v[4 * q + 1] = x.y;
+    v[4 * q + 2] = x.z;
+    v[4 * q + 3] = x.w;
+  }
+}
+
+// Stage rows [r0, r0+BT) x cols [k0, k0+KT) of a row-major [nrows][ld] array of
+// storage type S (double or float; the arithmetic is FP64 either way) into
+// S[k][row] (transposed).  Each thread loads 16 consecutive k of one row.
+// Out-of-range elements are zero.  load() only issues the reads, so they stay in
+// flight during the current K-tile's matrix-core work.
+template <typename S>
 struct TileLoad {
-  double v[16];
-  __device__ inline void load(const double* __restrict__ X, int64_t ld, int nrows, int r0,
-                              int64_t k0, int64_t kend, const double* __restrict__ w) {
+  S v[16];
+  __device__ inline void load(const S* __restrict__ X, int64_t ld, int nrows, int r0,
+                              int64_t k0, int64_t kend) {
     const int t = threadIdx.x;
     const int row = t >> 1;
     const int64_t kb = k0 + (t & 1) * 16;
     const int gr = r0 + row;
-    const bool aligned = ((reinterpret_cast<uintptr_t>(X + (int64_t)gr * ld + kb) |
-                           reinterpret_cast<uintptr_t>(w ? w + kb : nullptr)) & 15) == 0;
+    const bool aligned = (reinterpret_cast<uintptr_t>(X + (int64_t)gr * ld + kb) & 15) == 0;
     if (gr < nrows && kb + 16 <= kend && aligned) {
-      const double2* src = reinterpret_cast<const double2*>(X + (int64_t)gr * ld + kb);
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        double2 x = src[q];
-        v[2 * q] = x.x;
-        v[2 * q + 1] = x.y;
-      }
-      if (w) {
-        const double2* ws = reinterpret_cast<const double2*>(w + kb);
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          double2 x = ws[q];
-          v[2 * q] *= x.x;
-          v[2 * q + 1] *= x.y;
-        }
-      }
+      load16(X + (int64_t)gr * ld + kb, v);
     } else {
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int64_t k = kb + q;
-        double x = 0.0;
-        if (gr < nrows && k < kend) {
-          x = X[(int64_t)gr * ld + k];
-          if (w) x *= w[k];
-        }
-        v[q] = x;
+        v[q] = (gr < nrows && k < kend) ? X[(int64_t)gr * ld + k] : (S)0;
       }
     }
   }
-  __device__ inline void store(double* S) const {
+  __device__ inline void store(double* Sm) const {
     const int t = threadIdx.x;
     const int row = t >> 1;
     const int kb = (t & 1) * 16;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) S[(kb + q) * LDP + row] = v[q];
+    for (int q = 0; q < 16; ++q) Sm[(kb + q) * LDP + row] = (double)v[q];
   }
 };
 
 // ------------------------------------------------------------------ tn_sym
-// grid: x = upper tile index, y = split, z = batch.  part layout:
+// 1-D grid over (split, batch) groups of upper tiles (xcd_map).  part layout:
 // [batch][split][tile][BT][BT].
+template <typename SA, typename SB>
 __global__ __launch_bounds__(256, 2) void tn_sym_f64_kernel(
-    const double* __restrict__ A, const double* __restrict__ B, const double* __restrict__ w,
-    int64_t w_stride, int N, int64_t M, int nspin, int ntb, int64_t kchunk,
+    const SA* __restrict__ A, const SB* __restrict__ B, const double* __restrict__ w,
+    int64_t w_stride, int N, int64_t M, int nspin, int ntb, int64_t kchunk, int nsplit, int batch,
     double* __restrict__ part) {
   __shared__ double As[KT * LDP];
   __shared__ double Bs[KT * LDP];
-  const int tile = blockIdx.x, split = blockIdx.y, b = blockIdx.z;
+  __shared__ double Ws[KT];   // w over the current K-tile (1 when w is absent)
+  const int ntiles = ntb * (ntb + 1) / 2;
+  int group, tile;
+  xcd_map(blockIdx.x, nsplit * batch, ntiles, group, tile);
+  const int split = group % nsplit, b = group / nsplit;
   // upper-triangle tile index -> (ti, tj), ti <= tj
   int ti = 0, rem = tile;
   while (rem >= ntb - ti) { rem -= ntb - ti; ++ti; }
   const int tj = ti + rem;
   const int c = b % nspin;
-  const double* Ac = A + (int64_t)c * N * M;
-  const double* Bc = B + (int64_t)c * N * M;
+  const SA* Ac = A + (int64_t)c * N * M;
+  const SB* Bc = B + (int64_t)c * N * M;
   const double* wb = w ? w + (int64_t)b * w_stride : nullptr;
   const int64_t kbeg = (int64_t)split * kchunk;
   const int64_t kend = min(M, kbeg + kchunk);
@@ -111,36 +121,47 @@ __global__ __launch_bounds__(256, 2) void tn_sym_f64_kernel(
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
-  TileLoad la, lb;
+  // the weight of B's column k is applied as B is read from LDS (the FP64 product
+  // w[k] * B[j][k], as if B had been scaled in memory)
+  auto wload = [&](int64_t k0) {
+    const int64_t k = k0 + threadIdx.x;
+    return (threadIdx.x < KT && k < kend) ? (wb ? wb[k] : 1.0) : 0.0;
+  };
+  TileLoad<SA> la;
+  TileLoad<SB> lb;
+  double wn = 0.0;
   if (kbeg < kend) {
-    la.load(Ac, M, N, ti * BT, kbeg, kend, nullptr);
-    lb.load(Bc, M, N, tj * BT, kbeg, kend, wb);
+    la.load(Ac, M, N, ti * BT, kbeg, kend);
+    lb.load(Bc, M, N, tj * BT, kbeg, kend);
+    wn = wload(kbeg);
   }
   for (int64_t k0 = kbeg; k0 < kend; k0 += KT) {
     __syncthreads();
     la.store(As);
     lb.store(Bs);
+    if (threadIdx.x < KT) Ws[threadIdx.x] = wn;
     __syncthreads();
     if (k0 + KT < kend) {
-      la.load(Ac, M, N, ti * BT, k0 + KT, kend, nullptr);
-      lb.load(Bc, M, N, tj * BT, k0 + KT, kend, wb);
+      la.load(Ac, M, N, ti * BT, k0 + KT, kend);
+      lb.load(Bc, M, N, tj * BT, k0 + KT, kend);
+      wn = wload(k0 + KT);
     }
 #pragma unroll
     for (int kk = 0; kk < KT; kk += 4) {
       const int kr = (kk + (lane >> 4)) * LDP;
+      const double wk = Ws[kk + (lane >> 4)];
       double a[4], bb[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) a[i] = As[kr + wr * 64 + i * 16 + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bb[j] = Bs[kr + wc * 64 + j * 16 + (lane & 15)];
+      for (int j = 0; j < 4; ++j) bb[j] = Bs[kr + wc * 64 + j * 16 + (lane & 15)] * wk;
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = mfma64(a[i], bb[j], acc[i][j]);
     }
   }
-  const int ntiles = ntb * (ntb + 1) / 2;
-  double* out = part + (((int64_t)b * gridDim.y + split) * ntiles + tile) * (BT * BT);
+  double* out = part + (((int64_t)b * nsplit + split) * ntiles + tile) * (BT * BT);
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -176,53 +197,54 @@ __global__ void tn_reduce_kernel(const double* __restrict__ part, int N, int ntb
 // ------------------------------------------------------------------ backproj
 // Stage G rows [j0, j0+KT) x cols [i0, i0+BT) (G symmetric: G[j][i] = G[i][j]) or
 // A rows [j0, j0+KT) x cols [p0, p0+BT) straight (no transpose) into S[k][col].
+template <typename S>
 struct RowLoad {
-  double v[16];
+  S v[16];
+  double fac;
   // thread t: row (t >> 3) of KT, 16 consecutive columns starting (t & 7) * 16
-  __device__ inline void load(const double* __restrict__ X, int64_t ld, int nrows, int64_t ncols,
+  __device__ inline void load(const S* __restrict__ X, int64_t ld, int nrows, int64_t ncols,
                               int j0, int64_t c0, double factor) {
     const int t = threadIdx.x;
     const int row = t >> 3;
     const int64_t cb = c0 + (t & 7) * 16;
     const int gr = j0 + row;
     const bool aligned = (reinterpret_cast<uintptr_t>(X + (int64_t)gr * ld + cb) & 15) == 0;
+    fac = factor;
     if (gr < nrows && cb + 16 <= ncols && aligned) {
-      const double2* src = reinterpret_cast<const double2*>(X + (int64_t)gr * ld + cb);
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        double2 x = src[q];
-        v[2 * q] = x.x * factor;
-        v[2 * q + 1] = x.y * factor;
-      }
+      load16(X + (int64_t)gr * ld + cb, v);
     } else {
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int64_t cc = cb + q;
-        v[q] = (gr < nrows && cc < ncols) ? X[(int64_t)gr * ld + cc] * factor : 0.0;
+        v[q] = (gr < nrows && cc < ncols) ? X[(int64_t)gr * ld + cc] : (S)0;
       }
     }
   }
-  __device__ inline void store(double* S) const {
+  // the factor is applied here, after the current K-tile's work, so that the
+  // reads issued by load() stay in flight meanwhile
+  __device__ inline void store(double* Sm) const {
     const int t = threadIdx.x;
     const int row = t >> 3;
     const int cb = (t & 7) * 16;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) S[row * LDP + cb + q] = v[q];
+    for (int q = 0; q < 16; ++q) Sm[row * LDP + cb + q] = (double)v[q] * fac;
   }
 };
 
-// grid: x = point block (BT points), y = batch b (direction * nspin + channel).
+// 1-D grid over (point block of BT points, batch b = direction * nspin + channel);
+// the directions of one point block run together on one XCD (xcd_map).
 __global__ __launch_bounds__(256, 2) void backproj_f64_kernel(
     const double* __restrict__ A, const double* __restrict__ G, int N, int64_t M, int nspin,
-    double scale, const double* __restrict__ sub, double* __restrict__ out) {
+    int batch, double scale, const double* __restrict__ sub, double* __restrict__ out) {
   __shared__ double Gs[KT * LDP];
   __shared__ double Ps[KT * LDP];
   __shared__ double red[4][64];
-  const int b = blockIdx.y;
+  int pblk, b;
+  xcd_map(blockIdx.x, (int)((M + BT - 1) / BT), batch, pblk, b);
   const int c = b % nspin;
   const double* Ac = A + (int64_t)c * N * M;
   const double* Gb = G + (int64_t)b * N * N;
-  const int64_t p0 = (int64_t)blockIdx.x * BT;
+  const int64_t p0 = (int64_t)pblk * BT;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int wr = wid >> 1, wc = wid & 1;
   double dsum[4] = {0.0, 0.0, 0.0, 0.0};   // per lane: columns wc*64 + j*16 + lane%16
@@ -234,7 +256,7 @@ __global__ __launch_bounds__(256, 2) void backproj_f64_kernel(
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-    RowLoad lg, lp;
+    RowLoad<double> lg, lp;
     // K runs over j in [i0, N): the diagonal block once, blocks right of it twice
     // (G symmetric), so only the upper block triangle is touched.
     lg.load(Gb, N, N, N, i0, i0, 1.0);
@@ -322,7 +344,8 @@ __global__ __launch_bounds__(256, 2) void nn_f64_kernel(const double* __restrict
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-  RowLoad lw, lb;
+  RowLoad<double> lw;
+  RowLoad<T> lb;
   lw.load(Wt, N, N, N, 0, i0, 1.0);
   lb.load(B, M, N, M, 0, p0, 1.0);
   for (int j0 = 0; j0 < N; j0 += KT) {
@@ -362,61 +385,78 @@ __global__ __launch_bounds__(256, 2) void nn_f64_kernel(const double* __restrict
     }
 }
 
-int pick_splits(int tiles_x_batch, int64_t M) {
-  // enough blocks to fill 256 CUs at two blocks per CU several times over,
-  // with each split at least 4096 grid points long
-  int s = 1;
-  while (tiles_x_batch * s < 2048 && M / (2 * s) >= 4096) s *= 2;
-  return s;
-}
-
 }  // namespace
 
 size_t tn_workspace_bytes(int N, int64_t M, int batch, lrdm_prec) {
   const int ntb = (N + BT - 1) / BT;
   const int ntiles = ntb * (ntb + 1) / 2;
-  const int ns = pick_splits(ntiles * batch, M);
+  const int ns = tn_splits(ntiles * batch, M);
   return (size_t)batch * ns * ntiles * BT * BT * sizeof(double);
 }
 
-template <>
-hipError_t launch_tn_sym<double>(lrdm_ctx* ctx, const double* A, const double* B,
-                                 const double* w, int64_t w_stride, int N, int64_t M, int nspin,
-                                 int batch, lrdm_prec prec, double* H) {
+template <typename SA, typename SB>
+hipError_t launch_tn_sym_f64(lrdm_ctx* ctx, const SA* A, const SB* B, const double* w,
+                             int64_t w_stride, int N, int64_t M, int nspin, int batch,
+                             double* H) {
   const int ntb = (N + BT - 1) / BT;
   const int ntiles = ntb * (ntb + 1) / 2;
-  const int ns = pick_splits(ntiles * batch, M);
+  const int ns = tn_splits(ntiles * batch, M);
   int64_t kchunk = (M + ns - 1) / ns;
   kchunk = (kchunk + KT - 1) / KT * KT;
-  double* part = static_cast<double*>(ws_take(ctx, tn_workspace_bytes(N, M, batch, prec)));
-  dim3 grd(ntiles, ns, batch);
-  ProfScope prof(ctx, w ? "proj" : "gram");
-  tn_sym_f64_kernel<<<grd, 256, 0, ctx->stream>>>(A, B ? B : A, w, w_stride, N, M, nspin, ntb,
-                                                   kchunk, part);
-  LRDM_HIP(hipGetLastError());
+  double* part = static_cast<double*>(ws_take(ctx, tn_workspace_bytes(N, M, batch, LRDM_FP64)));
+  const unsigned grd = (unsigned)(ntiles * ns * batch);
+  {
+    ProfScope prof(ctx, w ? "proj" : "gram");
+    if (B)
+      tn_sym_f64_kernel<SA, SB><<<grd, 256, 0, ctx->stream>>>(A, B, w, w_stride, N, M, nspin, ntb,
+                                                               kchunk, ns, batch, part);
+    else
+      tn_sym_f64_kernel<SA, SA><<<grd, 256, 0, ctx->stream>>>(A, A, w, w_stride, N, M, nspin, ntb,
+                                                               kchunk, ns, batch, part);
+    LRDM_HIP(hipGetLastError());
+  }
   dim3 blk(32, 8);
   dim3 grd2((N + 31) / 32, (N + 7) / 8, batch);
   tn_reduce_kernel<<<grd2, blk, 0, ctx->stream>>>(part, N, ntb, ns, H);
   return hipGetLastError();
+}
+template hipError_t launch_tn_sym_f64<double, double>(lrdm_ctx*, const double*, const double*,
+                                                      const double*, int64_t, int, int64_t, int,
+                                                      int, double*);
+template hipError_t launch_tn_sym_f64<float, float>(lrdm_ctx*, const float*, const float*,
+                                                    const double*, int64_t, int, int64_t, int, int,
+                                                    double*);
+template hipError_t launch_tn_sym_f64<float, double>(lrdm_ctx*, const float*, const double*,
+                                                     const double*, int64_t, int, int64_t, int,
+                                                     int, double*);
+
+template <>
+hipError_t launch_tn_sym<double>(lrdm_ctx* ctx, const double* A, const double* B,
+                                 const double* w, int64_t w_stride, int N, int64_t M, int nspin,
+                                 int batch, lrdm_prec, double* H) {
+  return launch_tn_sym_f64<double, double>(ctx, A, B, w, w_stride, N, M, nspin, batch, H);
 }
 
 template <>
 hipError_t launch_backproj<double>(lrdm_ctx* ctx, const double* A, const double* G, int N,
                                    int64_t M, int nspin, int batch, lrdm_prec, double scale,
                                    const double* sub, double* out) {
-  dim3 grd((unsigned)((M + BT - 1) / BT), batch);
+  const unsigned grd = (unsigned)((M + BT - 1) / BT * batch);
   ProfScope prof(ctx, "backproj");
-  backproj_f64_kernel<<<grd, 256, 0, ctx->stream>>>(A, G, N, M, nspin, scale, sub, out);
+  backproj_f64_kernel<<<grd, 256, 0, ctx->stream>>>(A, G, N, M, nspin, batch, scale, sub, out);
   return hipGetLastError();
 }
 
-template <>
-hipError_t launch_nn<double>(lrdm_ctx* ctx, const double* Wt, const double* B, double* Out, int N,
-                             int64_t M) {
+template <typename S>
+hipError_t launch_nn_f64(lrdm_ctx* ctx, const double* Wt, const S* B, S* Out, int N, int64_t M) {
   dim3 grd((unsigned)((M + BT - 1) / BT), (N + BT - 1) / BT);
   ProfScope prof(ctx, "nn");
-  nn_f64_kernel<double><<<grd, 256, 0, ctx->stream>>>(Wt, B, Out, N, M);
+  nn_f64_kernel<S><<<grd, 256, 0, ctx->stream>>>(Wt, B, Out, N, M);
   return hipGetLastError();
 }
+template hipError_t launch_nn_f64<double>(lrdm_ctx*, const double*, const double*, double*, int,
+                                          int64_t);
+template hipError_t launch_nn_f64<float>(lrdm_ctx*, const double*, const float*, float*, int,
+                                         int64_t);
 
 }  // namespace lrdm

@@ -1,33 +1,760 @@
-// Single-precision storage forms (FP32, BF16X3) of the contractions.  The
-// matrix-core kernels for these forms are not part of this build yet: the
-// entry points reject them with LRDM_EUNSUPPORTED before any launch, and these
-// definitions only complete the template set.
+// Matrix-core contractions for the single-precision storage forms (Psi, X, Y held
+// as FP32; eps, V, dV, drho and every N x N matrix stay FP64).
+//
+//  LRDM_FP32    FP32 operands on v_mfma_f32_16x16x4f32.
+//  LRDM_BF16X3  FP32 operands split exactly into three BF16 pieces,
+//               x = hi + mid + lo (8 + 8 + 8 significant bits), on
+//               v_mfma_f32_16x16x32_bf16, keeping the six products of order <= 2
+//               (hi*hi; hi*mid + mid*hi; hi*lo + mid*mid + lo*hi), so each product
+//               carries an error of about 2^-24, as in FP32.  The density is too
+//               sensitive for a two-piece split (hi*hi + hi*lo + lo*hi, error
+//               about 2^-16 per product): that leaves relative errors of a few
+//               1e-6 in the response density.
+//
+// The two response contractions (tn_sym, backproj; same meaning as the FP64
+// forms) share one 128 x 128 tile core computing C = A B^T over a K range.  A and B
+// tiles are staged in LDS as FP32 in [row][k] layout (k contiguous), so a lane
+// fetches 8 consecutive k of one row with two 16-byte LDS reads.  For the FP32
+// instruction the lanes of group g = lane/16 take k = 8g + s at step s (any
+// permutation of k is allowed as long as A and B use the same one); for the BF16
+// instruction those 8 values are exactly the operand of one lane.  Partial sums
+// live in FP32 for one K-tile (KT = 32 values of k) and are then added into FP64
+// registers, so FP32 rounding never accumulates over more than 32 terms.
+//
+// Lane layouts (measured on gfx950):
+//   v_mfma_f32_16x16x4f32:      A lane l -> A[l%16][l/16], B lane l -> B[l/16][l%16]
+//   v_mfma_f32_16x16x32_bf16:   A lane l -> A[l%16][8(l/16)+e], B -> B[8(l/16)+e][l%16]
+//   both:                       D lane l, register v -> D[4(l/16) + v][l%16]
 #include "lrdm_internal.h"
+#include "xcd.h"
 
 namespace lrdm {
+namespace {
 
-template <>
-hipError_t launch_tn_sym<float>(lrdm_ctx*, const float*, const float*, const double*, int64_t, int,
-                                int64_t, int, int, lrdm_prec, double*) {
-  return hipErrorNotSupported;
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+constexpr int BT = 128;      // output tile edge
+constexpr int KT = 32;       // k extent staged per step
+constexpr int KP = KT + 4;   // LDS row pitch in floats (16-byte aligned rows)
+
+enum class Core { F32, BF2, BF3 };  // BF2: two-piece split, order <= 1 (kept for measurement)
+
+__device__ inline f4 mfma_f32(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ inline f4 mfma_bf16(bf8 a, bf8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Exact split of 8 FP32 values into BF16 pieces (round to nearest even at each
+// stage; every remainder is exact in FP32).
+template <int NP>
+__device__ inline void split(const float (&x)[8], bf8 (&p)[NP]) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    float r = x[e];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      const __bf16 h = (__bf16)r;
+      p[q][e] = h;
+      r -= (float)h;
+    }
+  }
+}
+
+// Lane-local fragment of rows (base + 16i + lane%16), k = 8(lane/16) .. +7.
+__device__ inline void frag(const float* S, int base, int lane, float (&v)[4][8]) {
+  const int r = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const f4* p = reinterpret_cast<const f4*>(S + (base + i * 16 + r) * KP + 8 * g);
+    const f4 x = p[0], y = p[1];
+    v[i][0] = x[0]; v[i][1] = x[1]; v[i][2] = x[2]; v[i][3] = x[3];
+    v[i][4] = y[0]; v[i][5] = y[1]; v[i][6] = y[2]; v[i][7] = y[3];
+  }
+}
+
+// One K-tile of the wave's 64 x 64 sub-tile: acc += A_rows B_rows^T over KT.
+template <Core C>
+__device__ inline void kt_step(const float* As, const float* Bs, int wr, int wc, int lane,
+                               double (&acc)[4][4][4]) {
+  float a[4][8], b[4][8];
+  frag(As, wr * 64, lane, a);
+  frag(Bs, wc * 64, lane, b);
+  f4 c[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) c[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  if constexpr (C == Core::F32) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) c[i][j] = mfma_f32(a[i][s], b[j][s], c[i][j]);
+  } else {
+    constexpr int NP = (C == Core::BF3) ? 3 : 2;
+    bf8 pa[4][NP];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) split<NP>(a[i], pa[i]);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      bf8 pb[NP];
+      split<NP>(b[j], pb);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        // smallest terms first
+        if constexpr (C == Core::BF3) {
+          c[i][j] = mfma_bf16(pa[i][0], pb[2], c[i][j]);
+          c[i][j] = mfma_bf16(pa[i][1], pb[1], c[i][j]);
+          c[i][j] = mfma_bf16(pa[i][2], pb[0], c[i][j]);
+        }
+        c[i][j] = mfma_bf16(pa[i][0], pb[1], c[i][j]);
+        c[i][j] = mfma_bf16(pa[i][1], pb[0], c[i][j]);
+        c[i][j] = mfma_bf16(pa[i][0], pb[0], c[i][j]);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[i][j][v] += (double)c[i][j][v];
+}
+
+__device__ inline void zero(double (&acc)[4][4][4]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[i][j][v] = 0.0;
+}
+
+template <typename S>
+__device__ inline bool aligned16(const S* p) {
+  return (reinterpret_cast<uintptr_t>(p) & 15) == 0;
+}
+
+// Rows [r0, r0+BT) x k in [k0, k0+KT) of a row-major FP32 [nrows][ld] array (k
+// contiguous), times w[k] (the FP64 product rounded once) and a factor; zero
+// outside [0, nrows) x [., kend).  Thread t: row t/2, k = 16 (t%2) .. +15.  load()
+// only issues the global reads; the products are formed in store(), after the
+// current K-tile's matrix-core work, so the reads stay in flight meanwhile.
+struct StageDirect {
+  float v[16];
+  double wv[16];
+  float fac;
+  bool has_w;
+  __device__ inline void load(const float* __restrict__ X, int64_t ld, int nrows, int r0,
+                              int64_t k0, int64_t kend, const double* __restrict__ w,
+                              float factor) {
+    const int t = threadIdx.x;
+    const int gr = r0 + (t >> 1);
+    const int64_t kb = k0 + (t & 1) * 16;
+    const float* src = X + (int64_t)gr * ld + kb;
+    fac = factor;
+    has_w = (w != nullptr);
+    if (gr < nrows && kb + 16 <= kend && aligned16(src) && (!w || aligned16(w + kb))) {
+      const f4* s4 = reinterpret_cast<const f4*>(src);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const f4 x = s4[q];
+        v[4 * q] = x[0]; v[4 * q + 1] = x[1]; v[4 * q + 2] = x[2]; v[4 * q + 3] = x[3];
+      }
+      if (w) {
+        const double2* w2 = reinterpret_cast<const double2*>(w + kb);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const double2 y = w2[q];
+          wv[2 * q] = y.x;
+          wv[2 * q + 1] = y.y;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int64_t k = kb + q;
+        const bool in = gr < nrows && k < kend;
+        v[q] = in ? X[(int64_t)gr * ld + k] : 0.f;
+        wv[q] = (in && w) ? w[k] : 1.0;
+      }
+    }
+  }
+  __device__ inline void store(float* Sm) {
+    const int t = threadIdx.x;
+    if (has_w) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) v[q] = (float)((double)v[q] * wv[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] *= fac;
+    f4* dst = reinterpret_cast<f4*>(Sm + (t >> 1) * KP + (t & 1) * 16);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dst[q] = f4{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
+  }
+};
+
+// Columns [c0, c0+BT) x k in [k0, k0+KT) of a row-major FP32 [nk][ld] array whose
+// rows are indexed by k (columns contiguous), stored transposed as [column][k];
+// zero outside [0, nk) x [0, ncols).  Thread t: k = t%32, columns 16 (t/32) .. +15,
+// so that the transposed LDS writes of a wave fall on consecutive banks.
+struct StageTrans {
+  float v[16];
+  __device__ inline void load(const float* __restrict__ X, int64_t ld, int64_t nk, int64_t ncols,
+                              int64_t k0, int64_t c0) {
+    const int t = threadIdx.x;
+    const int64_t gk = k0 + (t & 31);
+    const int64_t cb = c0 + (t >> 5) * 16;
+    const float* src = X + gk * ld + cb;
+    if (gk < nk && cb + 16 <= ncols && aligned16(src)) {
+      const f4* s4 = reinterpret_cast<const f4*>(src);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const f4 x = s4[q];
+        v[4 * q] = x[0]; v[4 * q + 1] = x[1]; v[4 * q + 2] = x[2]; v[4 * q + 3] = x[3];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int64_t cc = cb + q;
+        v[q] = (gk < nk && cc < ncols) ? X[gk * ld + cc] : 0.f;
+      }
+    }
+  }
+  __device__ inline void store(float* Sm) const {
+    const int t = threadIdx.x;
+    const int kr = t & 31, cb = (t >> 5) * 16;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) Sm[(cb + q) * KP + kr] = v[q];
+  }
+};
+
+// ------------------------------------------------------------------ tn_sym
+// 1-D grid over (split, batch) groups of upper tiles (xcd_map); part
+// [batch][split][tile][BT][BT].
+template <Core C>
+__global__ __launch_bounds__(256, 1) void tn_sym_lp_kernel(
+    const float* __restrict__ A, const float* __restrict__ B, const double* __restrict__ w,
+    int64_t w_stride, int N, int64_t M, int nspin, int ntb, int64_t kchunk, int nsplit, int batch,
+    double* __restrict__ part) {
+  __shared__ __attribute__((aligned(16))) float As[BT * KP];
+  __shared__ __attribute__((aligned(16))) float Bs[BT * KP];
+  const int ntiles = ntb * (ntb + 1) / 2;
+  int group, tile;
+  xcd_map(blockIdx.x, nsplit * batch, ntiles, group, tile);
+  const int sp = group % nsplit, b = group / nsplit;
+  int ti = 0, rem = tile;
+  while (rem >= ntb - ti) { rem -= ntb - ti; ++ti; }
+  const int tj = ti + rem;
+  const int c = b % nspin;
+  const float* Ac = A + (int64_t)c * N * M;
+  const float* Bc = B + (int64_t)c * N * M;
+  const double* wb = w ? w + (int64_t)b * w_stride : nullptr;
+  const int64_t kbeg = (int64_t)sp * kchunk;
+  const int64_t kend = min(M, kbeg + kchunk);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  double acc[4][4][4];
+  zero(acc);
+  StageDirect la, lb;
+  if (kbeg < kend) {
+    la.load(Ac, M, N, ti * BT, kbeg, kend, nullptr, 1.f);
+    lb.load(Bc, M, N, tj * BT, kbeg, kend, wb, 1.f);
+  }
+  for (int64_t k0 = kbeg; k0 < kend; k0 += KT) {
+    __syncthreads();
+    la.store(As);
+    lb.store(Bs);
+    __syncthreads();
+    if (k0 + KT < kend) {
+      la.load(Ac, M, N, ti * BT, k0 + KT, kend, nullptr, 1.f);
+      lb.load(Bc, M, N, tj * BT, k0 + KT, kend, wb, 1.f);
+    }
+    kt_step<C>(As, Bs, wr, wc, lane, acc);
+  }
+  double* out = part + (((int64_t)b * nsplit + sp) * ntiles + tile) * (BT * BT);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = wr * 64 + i * 16 + 4 * (lane >> 4) + v;
+        const int col = wc * 64 + j * 16 + (lane & 15);
+        out[row * BT + col] = acc[i][j][v];
+      }
+}
+
+// Same fixed-order split sum as the FP64 form.
+__global__ void tn_reduce_lp_kernel(const double* __restrict__ part, int N, int ntb, int nsplit,
+                                    double* __restrict__ H) {
+  const int b = blockIdx.z;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= N || j >= N) return;
+  const int ii = min(i, j), jj = max(i, j);
+  const int ti = ii / BT, tj = jj / BT;
+  const int tile = ti * ntb - ti * (ti - 1) / 2 + (tj - ti);
+  const int ntiles = ntb * (ntb + 1) / 2;
+  const int r = ii - ti * BT, cc = jj - tj * BT;
+  double s = 0.0;
+  for (int q = 0; q < nsplit; ++q)
+    s += part[(((int64_t)b * nsplit + q) * ntiles + tile) * (BT * BT) + r * BT + cc];
+  H[((int64_t)b * N + i) * N + j] = s;
+}
+
+__global__ void to_f32_kernel(const double* __restrict__ x, float* __restrict__ y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (float)x[i];
+}
+
+// ================================================================== pipelined forms
+// Eight waves per block (two per SIMD), each owning a 32 x 64 part of the 128 x
+// 128 tile.  Operand tiles go from global memory straight into LDS
+// (global_load_lds_dwordx4: lane l of a wave writes 16 bytes at base + 16 l) in a
+// ring of NST stages, so NST - 1 K-tiles are in flight while one is multiplied.
+// A tile row (32 FP32 = eight 16-byte chunks) keeps logical chunk q in slot
+// q ^ (row & 7), which spreads a wave's fragment reads over the LDS banks.
+// Chunks outside the operands are fetched from a page of zeros.
+constexpr int PW = 8;                     // waves per block
+constexpr int PT = PW * 64;               // threads per block
+constexpr int NST = 3;                    // ring stages
+constexpr int TB = BT * KT * 4;           // bytes of one operand tile (16 KB)
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Wait until at most VM of this wave's global->LDS copies are outstanding, then
+// barrier: the "memory" clobber keeps the compiler from moving LDS accesses across.
+template <int VM>
+__device__ inline void wait_stage() {
+  asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(VM) : "memory");
+}
+
+__device__ inline void dma16(const void* src, unsigned char* lds) {
+  __builtin_amdgcn_global_load_lds(src, (lds_void*)lds, 16, 0, 0);
+}
+
+// This wave's share (2 of 16 copy instructions) of one operand tile: rows
+// [r0, r0+BT) x k in [k0, k0+KT) of the row-major FP32 [nrows][ld] array X.
+// Chunks with a row >= nrows or k >= kend (kend a multiple of 4) read zeros.
+__device__ inline void dma_tile(const float* __restrict__ X, int64_t ld, int nrows, int64_t r0,
+                                int64_t k0, int64_t kend, const float* zeros, unsigned char* tile,
+                                int wid, int lane) {
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int ins = wid * 2 + u;                      // 64 chunks = 8 rows each
+    const int r = ins * 8 + (lane >> 3);
+    const int q = (lane & 7) ^ ((lane >> 3) & 7);     // logical chunk of slot lane & 7
+    const int64_t k = k0 + 4 * q;
+    const int64_t gr = r0 + r;
+    const float* src = (gr < nrows && k < kend) ? X + gr * ld + k : zeros;
+    dma16(src, tile + ins * 1024);
+  }
+}
+
+// The weights w[k0 .. k0+KT) of one K-tile (16 chunks of two doubles; lanes
+// 16..63 repeat them), zeros at k >= kend (a multiple of 4).  Issued by wave 0.
+__device__ inline void dma_weights(const double* __restrict__ w, int64_t k0, int64_t kend,
+                                   const float* zeros, unsigned char* wtile, int lane) {
+  const int64_t k = k0 + 2 * (lane & 15);
+  const void* src = (k < kend) ? (const void*)(w + k) : (const void*)zeros;
+  dma16(src, wtile);
+}
+
+// Lane fragment of rows base + 16 i + lane%16, k = 8(lane/16) .. +7 of a swizzled tile.
+template <int NI>
+__device__ inline void frag_sw(const unsigned char* tile, int base, int lane, float (&v)[NI][8]) {
+  const int r16 = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    const int R = base + 16 * i + r16;
+    const f4 x = *reinterpret_cast<const f4*>(tile + (R * 8 + ((2 * g) ^ (R & 7))) * 16);
+    const f4 y = *reinterpret_cast<const f4*>(tile + (R * 8 + ((2 * g + 1) ^ (R & 7))) * 16);
+    v[i][0] = x[0]; v[i][1] = x[1]; v[i][2] = x[2]; v[i][3] = x[3];
+    v[i][4] = y[0]; v[i][5] = y[1]; v[i][6] = y[2]; v[i][7] = y[3];
+  }
+}
+
+// The wave's operands of one K-tile (rows of its 32 x 64 part), read from LDS
+// before the next copies are issued: an LDS read after a global->LDS copy would
+// make the compiler wait for every copy in flight.  weight() scales B's column k
+// by w[k] (FP32 product of the rounded weight).
+struct PipeFrag {
+  float a[2][8], b[4][8];
+  __device__ inline void load(const unsigned char* At, const unsigned char* Bt, int wr, int wc,
+                              int lane) {
+    frag_sw<2>(At, wr * 32, lane, a);
+    frag_sw<4>(Bt, wc * 64, lane, b);
+  }
+  // wt: the weights of the K-tile in LDS
+  __device__ inline void weight(const unsigned char* wt, int lane) {
+    const int g = lane >> 4;
+    float wf[8];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      // read as FP32 lanes like the tiles (the compiler then leaves the wait for
+      // the copies to wait_stage), then reinterpret the 16 bytes as two doubles
+      const f4 x = *reinterpret_cast<const f4*>(wt + (4 * g + h) * 16);
+      const d2v y = __builtin_bit_cast(d2v, x);
+      wf[2 * h] = (float)y[0];
+      wf[2 * h + 1] = (float)y[1];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) b[j][e] *= wf[e];
+  }
+};
+
+// acc += scale * A B^T over one K-tile of the wave's 32 x 64 part (registers only).
+template <Core C>
+__device__ inline void kt_step_pipe(PipeFrag& f, double scale, double (&acc)[2][4][4]) {
+  f4 c[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) c[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  if constexpr (C == Core::F32) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) c[i][j] = mfma_f32(f.a[i][s], f.b[j][s], c[i][j]);
+  } else {
+    constexpr int NP = (C == Core::BF3) ? 3 : 2;
+    bf8 pa[2][NP];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) split<NP>(f.a[i], pa[i]);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      bf8 pb[NP];
+      split<NP>(f.b[j], pb);
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        if constexpr (C == Core::BF3) {
+          c[i][j] = mfma_bf16(pa[i][0], pb[2], c[i][j]);
+          c[i][j] = mfma_bf16(pa[i][1], pb[1], c[i][j]);
+          c[i][j] = mfma_bf16(pa[i][2], pb[0], c[i][j]);
+        }
+        c[i][j] = mfma_bf16(pa[i][0], pb[1], c[i][j]);
+        c[i][j] = mfma_bf16(pa[i][1], pb[0], c[i][j]);
+        c[i][j] = mfma_bf16(pa[i][0], pb[0], c[i][j]);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[i][j][v] += scale * (double)c[i][j][v];
+}
+
+// Keeps the compiler from moving memory accesses across this point.
+__device__ inline void compiler_fence() { asm volatile("" ::: "memory"); }
+
+__device__ inline void zero_pipe(double (&acc)[2][4][4]) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[i][j][v] = 0.0;
+}
+
+// tn_sym, pipelined: same grid and partial layout as tn_sym_lp_kernel.  Requires M
+// a multiple of 4 and 16-byte aligned A, B and weight rows.  W: B weighted by w.
+template <Core C, bool W>
+__global__ __launch_bounds__(PT, 1) void tn_sym_pipe_kernel(
+    const float* __restrict__ A, const float* __restrict__ B, const double* __restrict__ w,
+    int64_t w_stride, int N, int64_t M, int nspin, int ntb, int64_t kchunk, int nsplit, int batch,
+    const float* __restrict__ zeros, double* __restrict__ part) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_pipe[];
+  constexpr int SB = 2 * TB + (W ? 1024 : 0);   // bytes of one stage
+  const int ntiles = ntb * (ntb + 1) / 2;
+  int group, tile;
+  xcd_map(blockIdx.x, nsplit * batch, ntiles, group, tile);
+  const int sp = group % nsplit, b = group / nsplit;
+  int ti = 0, rem = tile;
+  while (rem >= ntb - ti) { rem -= ntb - ti; ++ti; }
+  const int tj = ti + rem;
+  const int c = b % nspin;
+  const float* Ac = A + (int64_t)c * N * M;
+  const float* Bc = B + (int64_t)c * N * M;
+  const double* wb = W ? w + (int64_t)b * w_stride : nullptr;
+  const int64_t kbeg = (int64_t)sp * kchunk;
+  const int64_t kend = min(M, kbeg + kchunk);
+  const int nk = kbeg < kend ? (int)((kend - kbeg + KT - 1) / KT) : 0;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  // Every stage issues the same copies (zeros past the end), so the count of
+  // copies in flight per wave is the same at every wait: 4 per stage, plus the
+  // weights in wave 0.
+  auto issue = [&](int t) {
+    unsigned char* st = smem_pipe + (t % NST) * SB;
+    const int64_t k0 = kbeg + (int64_t)t * KT;
+    const int64_t ke = t < nk ? kend : k0;
+    dma_tile(Ac, M, N, (int64_t)ti * BT, k0, ke, zeros, st, wid, lane);
+    dma_tile(Bc, M, N, (int64_t)tj * BT, k0, ke, zeros, st + TB, wid, lane);
+    if (W && wid == 0) dma_weights(wb, k0, ke, zeros, st + 2 * TB, lane);
+  };
+  double acc[2][4][4];
+  zero_pipe(acc);
+  issue(0);
+  issue(1);
+  for (int t = 0; t < nk; ++t) {
+    if (W && wid == 0) wait_stage<5>(); else wait_stage<4>();
+    const unsigned char* st = smem_pipe + (t % NST) * SB;
+    PipeFrag f;
+    f.load(st, st + TB, wr, wc, lane);
+    if (W) f.weight(st + 2 * TB, lane);
+    compiler_fence();
+    issue(t + 2);
+    kt_step_pipe<C>(f, 1.0, acc);
+  }
+  wait_stage<0>();
+  double* out = part + (((int64_t)b * nsplit + sp) * ntiles + tile) * (BT * BT);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = wr * 32 + i * 16 + 4 * (lane >> 4) + v;
+        const int col = wc * 64 + j * 16 + (lane & 15);
+        out[row * BT + col] = acc[i][j][v];
+      }
+}
+
+// backproj, pipelined.  Gf: FP32 copies of the symmetric matrices [batch][N][ldk];
+// PT_: FP32 transposes of the blocks, [nspin][M][ldk] (A^T, points as rows); ldk a
+// multiple of KT with zeros in the columns >= N.  A ([nspin][N][M]) feeds the row-dot.
+template <Core C>
+__global__ __launch_bounds__(PT, 1) void backproj_pipe_kernel(
+    const float* __restrict__ A, const float* __restrict__ AT, const float* __restrict__ Gf,
+    int N, int64_t M, int ldk, int nspin, int batch, double scale, const double* __restrict__ sub,
+    const float* __restrict__ zeros, double* __restrict__ out) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_pipe[];
+  constexpr int SB = 2 * TB;
+  double* red = reinterpret_cast<double*>(smem_pipe + NST * SB);   // [PW][64]
+  // 1-D grid: the directions of one block of points run together on one XCD
+  int pblk, b;
+  xcd_map(blockIdx.x, (int)((M + BT - 1) / BT), batch, pblk, b);
+  const int c = b % nspin;
+  const float* Ac = A + (int64_t)c * N * M;
+  const float* ATc = AT + (int64_t)c * M * ldk;
+  const float* Gb = Gf + (int64_t)b * N * ldk;
+  const int64_t p0 = (int64_t)pblk * BT;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  double dsum[4] = {0.0, 0.0, 0.0, 0.0};
+  const int nib = (N + BT - 1) / BT;
+  for (int ib = 0; ib < nib; ++ib) {
+    const int i0 = ib * BT;
+    // j runs over [i0, N): the diagonal block once, blocks right of it twice
+    const int nk = (N - i0 + KT - 1) / KT;
+    auto issue = [&](int t) {
+      unsigned char* st = smem_pipe + (t % NST) * SB;
+      const int64_t j0 = i0 + (int64_t)t * KT;
+      const int64_t je = t < nk ? ldk : j0;
+      dma_tile(Gb, ldk, N, i0, j0, je, zeros, st, wid, lane);
+      dma_tile(ATc, ldk, (int)M, p0, j0, je, zeros, st + TB, wid, lane);
+    };
+    double acc[2][4][4];
+    zero_pipe(acc);
+    issue(0);
+    issue(1);
+    for (int t = 0; t < nk; ++t) {
+      wait_stage<4>();
+      const unsigned char* st = smem_pipe + (t % NST) * SB;
+      PipeFrag f;
+      f.load(st, st + TB, wr, wc, lane);
+      compiler_fence();
+      issue(t + 2);
+      kt_step_pipe<C>(f, (t * KT >= BT) ? 2.0 : 1.0, acc);
+    }
+    wait_stage<0>();   // the copies past the end land before the ring is reused
+    // row-dot with A[i][p]: all 32 reads issued first (indices clamped into
+    // range, out-of-range terms dropped afterwards)
+    float av[2][4][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gi = min(i0 + wr * 32 + i * 16 + 4 * (lane >> 4) + v, N - 1);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int64_t p = min(p0 + wc * 64 + j * 16 + (lane & 15), M - 1);
+          av[i][v][j] = Ac[(int64_t)gi * M + p];
+        }
+      }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gi = i0 + wr * 32 + i * 16 + 4 * (lane >> 4) + v;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int64_t p = p0 + wc * 64 + j * 16 + (lane & 15);
+          if (gi < N && p < M) dsum[j] += acc[i][j][v] * (double)av[i][v][j];
+        }
+      }
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    double v = dsum[j];
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    dsum[j] = v;
+  }
+  if (lane < 16) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) red[wid * 64 + j * 16 + lane] = dsum[j];
+  }
+  __syncthreads();
+  if (threadIdx.x < BT) {
+    const int col = threadIdx.x;
+    const int wcc = col >> 6, cl = col & 63;
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v += red[(2 * q + wcc) * 64 + cl];
+    const int64_t p = p0 + col;
+    if (p < M) {
+      double r = scale * v;
+      if (sub) r -= sub[(int64_t)b * M + p];
+      out[(int64_t)b * M + p] = r;
+    }
+  }
+}
+
+// Gf[b][i][j] = G[b][i][j] for j < N, 0 for N <= j < ldk.
+__global__ void gamma_pad_kernel(const double* __restrict__ G, float* __restrict__ Gf, int N,
+                                 int ldk, int batch) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)batch * N * ldk;
+  if (idx >= total) return;
+  const int j = (int)(idx % ldk);
+  const int64_t bi = idx / ldk;
+  Gf[idx] = j < N ? (float)G[bi * N + j] : 0.f;
+}
+
+// AT[c][p][j] = A[c][j][p] for j < N, 0 for N <= j < ldk: 64 x 64 tiles through LDS.
+__global__ __launch_bounds__(256) void transpose_pad_kernel(const float* __restrict__ A,
+                                                            float* __restrict__ AT, int N,
+                                                            int64_t M, int ldk) {
+  __shared__ float T[64][65];
+  const int c = blockIdx.z;
+  const float* Ac = A + (int64_t)c * N * M;
+  float* ATc = AT + (int64_t)c * M * ldk;
+  const int64_t p0 = (int64_t)blockIdx.x * 64;
+  const int j0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int r = ty; r < 64; r += 4) {
+    const int j = j0 + r;
+    const int64_t p = p0 + tx;
+    T[r][tx] = (j < N && p < M) ? Ac[(int64_t)j * M + p] : 0.f;
+  }
+  __syncthreads();
+  for (int r = ty; r < 64; r += 4) {
+    const int64_t p = p0 + r;
+    const int j = j0 + tx;
+    if (p < M && j < ldk) ATc[p * ldk + j] = T[tx][r];
+  }
+}
+
+}  // namespace
+
+static int pad_k(int N) { return (N + KT - 1) / KT * KT; }
+
+size_t backproj_workspace_bytes(int N, int64_t M, int nspin, int batch, lrdm_prec prec) {
+  if (prec == LRDM_FP64) return 0;
+  const size_t ldk = pad_k(N);
+  return ws_align((size_t)batch * N * ldk * sizeof(float)) +
+         ws_align((size_t)nspin * M * ldk * sizeof(float));
 }
 
 template <>
-hipError_t launch_backproj<float>(lrdm_ctx*, const float*, const double*, int, int64_t, int, int,
-                                  lrdm_prec, double, const double*, double*) {
-  return hipErrorNotSupported;
+hipError_t launch_tn_sym<float>(lrdm_ctx* ctx, const float* A, const float* B, const double* w,
+                                int64_t w_stride, int N, int64_t M, int nspin, int batch,
+                                lrdm_prec prec, double* H) {
+  if (prec == LRDM_FP64)
+    return launch_tn_sym_f64<float, float>(ctx, A, B, w, w_stride, N, M, nspin, batch, H);
+  const int ntb = (N + BT - 1) / BT;
+  const int ntiles = ntb * (ntb + 1) / 2;
+  const int ns = tn_splits(ntiles * batch, M);
+  int64_t kchunk = (M + ns - 1) / ns;
+  kchunk = (kchunk + KT - 1) / KT * KT;
+  double* part = static_cast<double*>(ws_take(ctx, tn_workspace_bytes(N, M, batch, prec)));
+  if (!B) B = A;
+  auto a16 = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  // the pipelined kernel copies 16-byte chunks of rows: rows must start aligned
+  const bool pipe = (M % 4 == 0) && a16(A) && a16(B) && (!w || (a16(w) && w_stride % 2 == 0));
+  const unsigned grd = (unsigned)(ntiles * ns * batch);
+  const int smem = NST * (2 * TB + (w ? 1024 : 0));
+  auto run_pipe = [&](auto kernel) -> hipError_t {
+    LRDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, smem));
+    kernel<<<grd, PT, smem, ctx->stream>>>(A, B, w, w_stride, N, M, nspin, ntb, kchunk, ns, batch,
+                                           ctx->zeros, part);
+    return hipGetLastError();
+  };
+  auto run_staged = [&](auto kernel) -> hipError_t {
+    kernel<<<grd, 256, 0, ctx->stream>>>(A, B, w, w_stride, N, M, nspin, ntb, kchunk, ns, batch,
+                                         part);
+    return hipGetLastError();
+  };
+  {
+    ProfScope prof(ctx, w ? "proj" : "gram");
+    const bool bf = (prec == LRDM_BF16X3);
+    if (pipe && w)
+      LRDM_HIP(bf ? run_pipe(tn_sym_pipe_kernel<Core::BF3, true>)
+                  : run_pipe(tn_sym_pipe_kernel<Core::F32, true>));
+    else if (pipe)
+      LRDM_HIP(bf ? run_pipe(tn_sym_pipe_kernel<Core::BF3, false>)
+                  : run_pipe(tn_sym_pipe_kernel<Core::F32, false>));
+    else
+      LRDM_HIP(bf ? run_staged(tn_sym_lp_kernel<Core::BF3>) : run_staged(tn_sym_lp_kernel<Core::F32>));
+  }
+  dim3 blk(32, 8);
+  dim3 grd2((N + 31) / 32, (N + 7) / 8, batch);
+  tn_reduce_lp_kernel<<<grd2, blk, 0, ctx->stream>>>(part, N, ntb, ns, H);
+  return hipGetLastError();
 }
 
 template <>
-hipError_t launch_nn<float>(lrdm_ctx*, const double*, const float*, float*, int, int64_t) {
-  return hipErrorNotSupported;
-}
-
-template <>
-lrdm_status rayleigh_ritz<float>(lrdm_ctx* ctx, const Grid3&, const double*, float*, int, lrdm_prec,
-                                 double*) {
-  ctx->err = "single-precision Rayleigh-Ritz is not available in this build";
-  return LRDM_EUNSUPPORTED;
+hipError_t launch_backproj<float>(lrdm_ctx* ctx, const float* A, const double* G, int N,
+                                  int64_t M, int nspin, int batch, lrdm_prec prec, double scale,
+                                  const double* sub, double* out) {
+  const int ldk = pad_k(N);
+  float* Gf = static_cast<float*>(ws_take(ctx, (size_t)batch * N * ldk * sizeof(float)));
+  float* AT = static_cast<float*>(ws_take(ctx, (size_t)nspin * M * ldk * sizeof(float)));
+  const int64_t nG = (int64_t)batch * N * ldk;
+  gamma_pad_kernel<<<(unsigned)((nG + 255) / 256), 256, 0, ctx->stream>>>(G, Gf, N, ldk, batch);
+  LRDM_HIP(hipGetLastError());
+  dim3 gt((unsigned)((M + 63) / 64), (unsigned)(ldk / 64 + (ldk % 64 ? 1 : 0)), nspin);
+  transpose_pad_kernel<<<gt, 256, 0, ctx->stream>>>(A, AT, N, M, ldk);
+  LRDM_HIP(hipGetLastError());
+  const unsigned grd = (unsigned)((M + BT - 1) / BT * batch);
+  const int smem = NST * 2 * TB + PW * 64 * (int)sizeof(double);
+  ProfScope prof(ctx, "backproj");
+  if (prec == LRDM_BF16X3) {
+    LRDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&backproj_pipe_kernel<Core::BF3>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, smem));
+    backproj_pipe_kernel<Core::BF3><<<grd, PT, smem, ctx->stream>>>(
+        A, AT, Gf, N, M, ldk, nspin, batch, scale, sub, ctx->zeros, out);
+  } else {
+    LRDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&backproj_pipe_kernel<Core::F32>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, smem));
+    backproj_pipe_kernel<Core::F32><<<grd, PT, smem, ctx->stream>>>(
+        A, AT, Gf, N, M, ldk, nspin, batch, scale, sub, ctx->zeros, out);
+  }
+  return hipGetLastError();
 }
 
 }  // namespace lrdm

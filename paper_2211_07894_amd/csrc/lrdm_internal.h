@@ -24,7 +24,8 @@ struct lrdm_ctx {
   size_t ws_cap = 0;
   size_t ws_top = 0;         // bump pointer inside one call
   int checks = 0;
-  int* dstatus = nullptr;    // device status words (LRDM_DS_*)
+  int* dstatus = nullptr;    // device status words (LRDM_DS_*), then the zero page
+  const float* zeros = nullptr;  // 128 bytes of device zeros (source of padding loads)
   std::string err;
   bool profiling = false;    // record hipEvents around the main kernels
   std::vector<lrdm_prof_rec> prof;
@@ -74,6 +75,11 @@ template <typename T>
 hipError_t launch_cheb_step(lrdm_ctx* ctx, const Grid3& g, const double* V, const T* Yin,
                             const T* Yold, T* Yout, int N, double alpha, double c0, double beta);
 
+// HY = H Y in FP64 arithmetic and storage for either storage type of Y.
+template <typename T>
+hipError_t launch_hpsi_f64(lrdm_ctx* ctx, const Grid3& g, const double* V, const T* Y, double* HY,
+                           int N);
+
 // mu by bisection, occupations, f' and (optionally) F for nspin channels.
 hipError_t launch_fermi(lrdm_ctx* ctx, const double* eps, int N, int nspin, double kT,
                         double n_electrons, double* mu, double* f, double* omf, double* fprime,
@@ -84,10 +90,22 @@ hipError_t launch_fermi(lrdm_ctx* ctx, const double* eps, int N, int nspin, doub
 // symmetric).  B == nullptr means B = A; w == nullptr means w = 1.
 // A, B: nspin blocks of [N][M].
 size_t tn_workspace_bytes(int N, int64_t M, int batch, lrdm_prec prec);
+// Split count of the K = M contraction: enough blocks to fill 256 CUs several
+// times over, with each split at least 4096 grid points long.
+inline int tn_splits(int tiles_x_batch, int64_t M) {
+  int s = 1;
+  while (tiles_x_batch * s < 2048 && M / (2 * s) >= 4096) s *= 2;
+  return s;
+}
+// T is the storage type of A and B; prec selects the arithmetic (LRDM_FP64: FP64
+// matrix cores on either storage type; LRDM_FP32 / LRDM_BF16X3: FP32 storage only).
 template <typename T>
 hipError_t launch_tn_sym(lrdm_ctx* ctx, const T* A, const T* B, const double* w,
                          int64_t w_stride, int N, int64_t M, int nspin, int batch, lrdm_prec prec,
                          double* H);
+template <typename SA, typename SB>
+hipError_t launch_tn_sym_f64(lrdm_ctx* ctx, const SA* A, const SB* B, const double* w,
+                             int64_t w_stride, int N, int64_t M, int nspin, int batch, double* H);
 
 // dmu[k] and Gamma[k][c] = F[c] o Hp[k][c] - dmu[k] diag(fprime[c]), in place over Hp.
 hipError_t launch_gamma(lrdm_ctx* ctx, double* Hp, const double* F, const double* fprime, int N,
@@ -95,14 +113,16 @@ hipError_t launch_gamma(lrdm_ctx* ctx, double* Hp, const double* F, const double
 
 // out[b][p] = scale * sum_ij A_c[i][p] G[b][i][j] A_c[j][p] (- sub[b][p] when sub != nullptr),
 // c = b % nspin, G symmetric.
+size_t backproj_workspace_bytes(int N, int64_t M, int nspin, int batch, lrdm_prec prec);
 template <typename T>
 hipError_t launch_backproj(lrdm_ctx* ctx, const T* A, const double* G, int N, int64_t M, int nspin,
                            int batch, lrdm_prec prec, double scale, const double* sub,
                            double* out);
 
-// Out[i][p] = sum_j Wt[j][i] B[j][p]  (Out = Wt^T B), Wt double N x N.
-template <typename T>
-hipError_t launch_nn(lrdm_ctx* ctx, const double* Wt, const T* B, T* Out, int N, int64_t M);
+// Out[i][p] = sum_j Wt[j][i] B[j][p]  (Out = Wt^T B), Wt double N x N, FP64
+// arithmetic for either storage type of B and Out.
+template <typename S>
+hipError_t launch_nn_f64(lrdm_ctx* ctx, const double* Wt, const S* B, S* Out, int N, int64_t M);
 
 // Rayleigh-Ritz pieces (rr.hip).
 // Eigenpairs of a symmetric N x N matrix (FP64, block Jacobi on the GPU).

@@ -461,7 +461,7 @@ size_t rr_workspace_bytes(int N, int64_t M, lrdm_prec prec) {
   const int Np = ((N + JS - 1) / JS) * JS;
   const int nb = Np / JB;
   size_t b = 0;
-  b += ws_align((size_t)M * N * prec_bytes(prec));          // H Y, later Psi_R
+  b += ws_align((size_t)M * N * sizeof(double));            // H Y, later Psi_R
   b += 6 * ws_align((size_t)N * N * sizeof(double));         // G, Hy, T, C, X, Wt
   b += 2 * ws_align((size_t)N * sizeof(double));             // dinv, lam
   // eigensolver
@@ -477,7 +477,8 @@ lrdm_status rayleigh_ritz(lrdm_ctx* ctx, const Grid3& g, const double* V, T* Psi
                           lrdm_prec prec, double* eps) {
   const int64_t M = g.M;
   const size_t nn = (size_t)N * N * sizeof(double);
-  T* HY = static_cast<T*>(ws_take(ctx, (size_t)M * N * sizeof(T)));
+  // H Y in FP64 whatever the storage type (later reused for Psi_R in type T)
+  double* HY = static_cast<double*>(ws_take(ctx, (size_t)M * N * sizeof(double)));
   double* G = static_cast<double*>(ws_take(ctx, nn));
   double* Hy = static_cast<double*>(ws_take(ctx, nn));
   double* Tm = static_cast<double*>(ws_take(ctx, nn));
@@ -493,8 +494,14 @@ lrdm_status rayleigh_ritz(lrdm_ctx* ctx, const Grid3& g, const double* V, T* Psi
     return LRDM_EDEVICE;
   };
   const size_t mark = ctx->ws_top;
+  // Every contraction here runs in FP64 arithmetic, and H Y is formed and kept
+  // in FP64, whatever the storage type of the block: a filtered block's columns
+  // span many orders of magnitude (1e-11 .. 1 at the 64^3 / 1024-state
+  // workload), so the scaled Gram matrix is far too ill-conditioned for FP32
+  // products, and the Loewdin coefficients (up to the inverse column norms)
+  // magnify any FP32 rounding of H Y or of the rotation.
   // G = Y Y^T
-  if ((e = launch_tn_sym<T>(ctx, Psi, nullptr, nullptr, 0, N, M, 1, 1, prec, G)) != hipSuccess)
+  if ((e = launch_tn_sym_f64<T, T>(ctx, Psi, nullptr, nullptr, 0, N, M, 1, 1, G)) != hipSuccess)
     return fail("gram", e);
   ctx->ws_top = mark;
   diag_rsqrt_kernel<<<(N + 255) / 256, 256, 0, ctx->stream>>>(G, N, dinv);
@@ -531,9 +538,8 @@ lrdm_status rayleigh_ritz(lrdm_ctx* ctx, const Grid3& g, const double* V, T* Psi
     if ((e = hipGetLastError()) != hipSuccess) return fail("scale", e);
   }
   // H Y and Y (H Y)^T
-  if ((e = launch_cheb_step<T>(ctx, g, V, Psi, nullptr, HY, N, 1.0, 0.0, 0.0)) != hipSuccess)
-    return fail("stencil", e);
-  if ((e = launch_tn_sym<T>(ctx, Psi, HY, nullptr, 0, N, M, 1, 1, prec, Hy)) != hipSuccess)
+  if ((e = launch_hpsi_f64<T>(ctx, g, V, Psi, HY, N)) != hipSuccess) return fail("stencil", e);
+  if ((e = launch_tn_sym_f64<T, double>(ctx, Psi, HY, nullptr, 0, N, M, 1, 1, Hy)) != hipSuccess)
     return fail("projection", e);
   ctx->ws_top = mark;
   // C = T Hy T^T
@@ -547,8 +553,9 @@ lrdm_status rayleigh_ritz(lrdm_ctx* ctx, const Grid3& g, const double* V, T* Psi
   // Psi_R = Q^T T Y: the rotation kernel computes Wt^T Y with Wt = T^T Q
   if ((e = small_gemm(ctx, true, false, N, N, N, 1.0, Tm, N, Ug, N, 0.0, Wt, N)) != hipSuccess)
     return fail("gemm", e);
-  if ((e = launch_nn<T>(ctx, Wt, Psi, HY, N, M)) != hipSuccess) return fail("rotation", e);
-  if ((e = hipMemcpyAsync(Psi, HY, (size_t)M * N * sizeof(T), hipMemcpyDeviceToDevice,
+  T* PR = reinterpret_cast<T*>(HY);
+  if ((e = launch_nn_f64<T>(ctx, Wt, Psi, PR, N, M)) != hipSuccess) return fail("rotation", e);
+  if ((e = hipMemcpyAsync(Psi, PR, (size_t)M * N * sizeof(T), hipMemcpyDeviceToDevice,
                           ctx->stream)) != hipSuccess)
     return fail("copy", e);
   return LRDM_OK;
@@ -556,5 +563,7 @@ lrdm_status rayleigh_ritz(lrdm_ctx* ctx, const Grid3& g, const double* V, T* Psi
 
 template lrdm_status rayleigh_ritz<double>(lrdm_ctx*, const Grid3&, const double*, double*, int,
                                            lrdm_prec, double*);
+template lrdm_status rayleigh_ritz<float>(lrdm_ctx*, const Grid3&, const double*, float*, int,
+                                          lrdm_prec, double*);
 
 }  // namespace lrdm

@@ -2,6 +2,8 @@
 // Chebyshev three-term recurrence (Sec. II C):
 //     Yout = alpha (H - c0) Yin + beta Yold,   H = -1/2 Lap_h + diag(V)
 // with the 7-point periodic Laplacian.  alpha = 1, c0 = 0, beta = 0 gives H Y.
+// Yin and Yold have storage type TI, Yout type TO; the arithmetic is done in TO
+// (H Y of an FP32 block can be formed and kept in FP64).
 //
 // Layout: vectors are [N][nz][ny][nx], x fastest.  A block owns one vector and a
 // run of z planes; it marches in z keeping the planes z-1, z, z+1 of its points
@@ -14,9 +16,9 @@
 namespace lrdm {
 namespace {
 
-template <typename T, int PPT>
+template <typename TI, typename T, int PPT>
 __global__ __launch_bounds__(1024) void cheb_plane_kernel(
-    const T* __restrict__ Yin, const T* Yold, T* Yout,
+    const TI* __restrict__ Yin, const TI* Yold, T* Yout,
     const double* __restrict__ V, int nx, int ny, int nz, int zrun, T wx, T wy, T wz, T dshift,
     T alpha, T beta) {
   extern __shared__ unsigned char smem_raw[];
@@ -26,8 +28,8 @@ __global__ __launch_bounds__(1024) void cheb_plane_kernel(
   const int vec = blockIdx.x;
   const int z0 = blockIdx.y * zrun;
   const int z1 = min(nz, z0 + zrun);
-  const T* yin = Yin + (int64_t)vec * M;
-  const T* yold = Yold ? Yold + (int64_t)vec * M : nullptr;
+  const TI* yin = Yin + (int64_t)vec * M;
+  const TI* yold = Yold ? Yold + (int64_t)vec * M : nullptr;
   T* yout = Yout + (int64_t)vec * M;
 
   int xy[PPT];   // (y << 16) | x of each point owned by this thread, -1 if none
@@ -41,9 +43,9 @@ __global__ __launch_bounds__(1024) void cheb_plane_kernel(
       if (qq < P) {
         const int y = qq / nx, x = qq - y * nx;
         xy[j] = (y << 16) | x;
-        prev[j] = yin[(int64_t)zm * P + qq];
-        cur[j] = yin[(int64_t)z0 * P + qq];
-        next[j] = yin[(int64_t)zp * P + qq];
+        prev[j] = (T)yin[(int64_t)zm * P + qq];
+        cur[j] = (T)yin[(int64_t)z0 * P + qq];
+        next[j] = (T)yin[(int64_t)zp * P + qq];
       } else {
         xy[j] = -1;
         prev[j] = cur[j] = next[j] = T(0);
@@ -72,7 +74,7 @@ __global__ __launch_bounds__(1024) void cheb_plane_kernel(
       const T hy = wx * (pl[xm] + pl[xp]) + wy * (pl[ym] + pl[yp]) +
                    wz * (prev[j] + next[j]) + ((T)V[off] + dshift) * c;
       T out = alpha * hy;
-      if (yold) out += beta * yold[off];
+      if (yold) out += beta * (T)yold[off];
       yout[off] = out;
     }
     // rotate the z window; the load of plane z + 2 overlaps the next plane's work
@@ -80,15 +82,15 @@ __global__ __launch_bounds__(1024) void cheb_plane_kernel(
     for (int j = 0; j < PPT; ++j) {
       prev[j] = cur[j];
       cur[j] = next[j];
-      if (xy[j] >= 0 && z + 1 < z1) next[j] = yin[(int64_t)zn * P + threadIdx.x + j * blockDim.x];
+      if (xy[j] >= 0 && z + 1 < z1) next[j] = (T)yin[(int64_t)zn * P + threadIdx.x + j * blockDim.x];
     }
     buf ^= 1;
   }
 }
 
-template <typename T, int PPT>
-hipError_t launch_plane(lrdm_ctx* ctx, const Grid3& g, const double* V, const T* Yin,
-                        const T* Yold, T* Yout, int N, int threads, int zrun, double alpha,
+template <typename TI, typename T, int PPT>
+hipError_t launch_plane(lrdm_ctx* ctx, const Grid3& g, const double* V, const TI* Yin,
+                        const TI* Yold, T* Yout, int N, int threads, int zrun, double alpha,
                         double c0, double beta) {
   const int P = g.nx * g.ny;
   const size_t smem = 2 * (size_t)P * sizeof(T);
@@ -96,20 +98,18 @@ hipError_t launch_plane(lrdm_ctx* ctx, const Grid3& g, const double* V, const T*
   const T dshift = T(1.0 / (g.hx * g.hx) + 1.0 / (g.hy * g.hy) + 1.0 / (g.hz * g.hz) - c0);
   dim3 grd(N, (g.nz + zrun - 1) / zrun);
   if (smem > 65536)
-    LRDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&cheb_plane_kernel<T, PPT>),
+    LRDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&cheb_plane_kernel<TI, T, PPT>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
   ProfScope prof(ctx, beta != 0.0 ? "cheb_step" : "hpsi");
-  cheb_plane_kernel<T, PPT><<<grd, threads, smem, ctx->stream>>>(
+  cheb_plane_kernel<TI, T, PPT><<<grd, threads, smem, ctx->stream>>>(
       Yin, beta != 0.0 ? Yold : nullptr, Yout, V, g.nx, g.ny, g.nz, zrun, wx, wy, wz, dshift,
       T(alpha), T(beta));
   return hipGetLastError();
 }
 
-}  // namespace
-
-template <typename T>
-hipError_t launch_cheb_step(lrdm_ctx* ctx, const Grid3& g, const double* V, const T* Yin,
-                            const T* Yold, T* Yout, int N, double alpha, double c0, double beta) {
+template <typename TI, typename T>
+hipError_t launch_stencil(lrdm_ctx* ctx, const Grid3& g, const double* V, const TI* Yin,
+                          const TI* Yold, T* Yout, int N, double alpha, double c0, double beta) {
   const int P = g.nx * g.ny;
   // whole plane per block: up to 1024 threads, PPT points per thread
   int threads = P <= 1024 ? ((P + 63) / 64) * 64 : 1024;
@@ -118,16 +118,38 @@ hipError_t launch_cheb_step(lrdm_ctx* ctx, const Grid3& g, const double* V, cons
   int runs = 1;
   while ((int64_t)N * runs < 2048 && g.nz / (runs * 2) >= 8) runs *= 2;
   const int zrun = (g.nz + runs - 1) / runs;
-  if (ppt <= 1) return launch_plane<T, 1>(ctx, g, V, Yin, Yold, Yout, N, threads, zrun, alpha, c0, beta);
-  if (ppt <= 2) return launch_plane<T, 2>(ctx, g, V, Yin, Yold, Yout, N, threads, zrun, alpha, c0, beta);
-  if (ppt <= 4) return launch_plane<T, 4>(ctx, g, V, Yin, Yold, Yout, N, threads, zrun, alpha, c0, beta);
-  if (ppt <= 8) return launch_plane<T, 8>(ctx, g, V, Yin, Yold, Yout, N, threads, zrun, alpha, c0, beta);
+  if (ppt <= 1)
+    return launch_plane<TI, T, 1>(ctx, g, V, Yin, Yold, Yout, N, threads, zrun, alpha, c0, beta);
+  if (ppt <= 2)
+    return launch_plane<TI, T, 2>(ctx, g, V, Yin, Yold, Yout, N, threads, zrun, alpha, c0, beta);
+  if (ppt <= 4)
+    return launch_plane<TI, T, 4>(ctx, g, V, Yin, Yold, Yout, N, threads, zrun, alpha, c0, beta);
+  if (ppt <= 8)
+    return launch_plane<TI, T, 8>(ctx, g, V, Yin, Yold, Yout, N, threads, zrun, alpha, c0, beta);
   return hipErrorInvalidValue;  // planes above 8192 points are rejected by validation
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_cheb_step(lrdm_ctx* ctx, const Grid3& g, const double* V, const T* Yin,
+                            const T* Yold, T* Yout, int N, double alpha, double c0, double beta) {
+  return launch_stencil<T, T>(ctx, g, V, Yin, Yold, Yout, N, alpha, c0, beta);
+}
+
+template <typename T>
+hipError_t launch_hpsi_f64(lrdm_ctx* ctx, const Grid3& g, const double* V, const T* Y, double* HY,
+                           int N) {
+  return launch_stencil<T, double>(ctx, g, V, Y, nullptr, HY, N, 1.0, 0.0, 0.0);
 }
 
 template hipError_t launch_cheb_step<double>(lrdm_ctx*, const Grid3&, const double*, const double*,
                                              const double*, double*, int, double, double, double);
 template hipError_t launch_cheb_step<float>(lrdm_ctx*, const Grid3&, const double*, const float*,
                                             const float*, float*, int, double, double, double);
+template hipError_t launch_hpsi_f64<double>(lrdm_ctx*, const Grid3&, const double*, const double*,
+                                            double*, int);
+template hipError_t launch_hpsi_f64<float>(lrdm_ctx*, const Grid3&, const double*, const float*,
+                                           double*, int);
 
 }  // namespace lrdm

@@ -1,25 +1,56 @@
-"""Turn a rocprofv3 database (rocpd SQLite, ROCm 7) into a short Markdown
-kernel summary.
+"""Short summaries of rocprofv3 output.
 
-    python -m paper_2211_07894_amd.profile_summary RESULTS.db "COMMAND" [--top 15]
+    python -m paper_2211_07894_amd.profile_summary trace RESULTS.db "COMMAND" [--top 15]
+        Markdown table of kernels by total GPU time from a --kernel-trace run
+        (rocpd SQLite, ROCm 7): calls, total and average duration, share.
 
-Prints a table of kernels by total GPU time: calls, total and average
-duration, share of the total.
+    python -m paper_2211_07894_amd.profile_summary traffic --fetch F.csv --write W.csv \
+        --form bf16x3 --workload c64_n1024_slab --out profiles/traffic.json --command "..."
+        HBM bytes per dispatch of the hot-path kernels from two --pmc runs
+        (FETCH_SIZE, then WRITE_SIZE, both in KiB per dispatch), each scaled by
+        what the same counter reads for the calibration copy (bench.py
+        --copy-calibration: three elementwise passes reading and writing 1 GiB).
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import hashlib
+import json
+import os
 import re
 import sqlite3
+import statistics
 import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+
+# profiling-scope name -> (kernel-name pattern, source file) for each storage form
+KERNELS = {
+    "fp64": {"proj": (r"tn_sym_f64_kernel<double, double>", "gemm.hip"),
+             "backproj": (r"backproj_f64_kernel", "gemm.hip"),
+             "cheb_step": (r"cheb_plane_kernel<double, double", "stencil.hip")},
+    "lp": {"proj": (r"tn_sym_pipe_kernel<.*true>", "gemm_lp.hip"),
+           "backproj": (r"backproj_pipe_kernel", "gemm_lp.hip"),
+           "cheb_step": (r"cheb_plane_kernel<float, float", "stencil.hip")},
+}
+CALIBRATION_BYTES = 1 << 30
 
 
 def short(name: str) -> str:
-    name = name.replace("lrdm::(anonymous namespace)::", "").replace("void ", "")
-    return re.sub(r"\(.*", "", name)
+    """Kernel name without namespace noise and without its argument list (the
+    last balanced parenthesised group; template arguments may hold parentheses)."""
+    name = name.replace("lrdm::(anonymous namespace)::", "").replace("void ", "").strip()
+    if name.endswith(")"):
+        depth = 0
+        for i in range(len(name) - 1, -1, -1):
+            depth += {")": 1, "(": -1}.get(name[i], 0)
+            if depth == 0:
+                return name[:i]
+    return name
 
 
-def summary(db_path: str, command: str, top: int = 15) -> str:
+def trace_summary(db_path: str, command: str, top: int = 15) -> str:
     db = sqlite3.connect(db_path)
     rows = list(db.execute(
         "select name, total_calls, total_duration, average, percentage from top_kernels"))
@@ -32,13 +63,97 @@ def summary(db_path: str, command: str, top: int = 15) -> str:
     return "\n".join(out) + "\n"
 
 
+def _col(header, *keys):
+    for k in keys:
+        for i, h in enumerate(header):
+            if h.strip().lower() == k.lower():
+                return i
+    raise KeyError(f"none of {keys} in {header}")
+
+
+def read_counter(path: str, counter: str):
+    """{dispatch id: (kernel name, value summed over the rows of that dispatch)}."""
+    with open(path, newline="") as f:
+        rd = csv.reader(f)
+        header = next(rd)
+        i_d = _col(header, "Dispatch_Id", "Dispatch_ID")
+        i_k = _col(header, "Kernel_Name")
+        i_c = _col(header, "Counter_Name")
+        i_v = _col(header, "Counter_Value")
+        out = {}
+        for row in rd:
+            if row[i_c] != counter:
+                continue
+            d = int(row[i_d])
+            name, v = out.get(d, (row[i_k], 0.0))
+            out[d] = (name, v + float(row[i_v]))
+    return out
+
+
+def _source_sha(name: str) -> str:
+    p = os.path.join(PKG, "csrc", name)
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def traffic(fetch_csv, write_csv, form, workload, command):
+    recs = []
+    data = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        disp = read_counter(path, counter)
+        cal = sorted((v for n, v in disp.values() if "elementwise" in n), reverse=True)[:3]
+        if not cal:
+            raise SystemExit(f"no calibration copy dispatches in {path}")
+        kib = statistics.median(cal)
+        factor = CALIBRATION_BYTES / (kib * 1024.0)   # true bytes per counted byte
+        data[counter] = (disp, factor, kib)
+    table = KERNELS["fp64" if form == "fp64" else "lp"]
+    for scope, (pat, src) in table.items():
+        per = {}
+        for counter, (disp, factor, _) in data.items():
+            vals = [v for n, v in disp.values() if re.search(pat, short(n))]
+            if vals:
+                per[counter] = statistics.median(vals) * 1024.0 * factor
+        if len(per) == 2:
+            recs.append({
+                "kernel": scope, "workload": workload, "form": form, "source": src,
+                "source_sha": _source_sha(src),
+                "fetch_bytes_per_launch": round(per["FETCH_SIZE"]),
+                "write_bytes_per_launch": round(per["WRITE_SIZE"]),
+                "bytes_per_launch": round(per["FETCH_SIZE"] + per["WRITE_SIZE"]),
+                "calibration": {c: {"copy_kib_counted": round(data[c][2]),
+                                    "factor": round(data[c][1], 4)} for c in data},
+                "command": command,
+            })
+    return recs
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("db")
-    ap.add_argument("command")
-    ap.add_argument("--top", type=int, default=15)
+    sub = ap.add_subparsers(dest="mode", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("db")
+    t.add_argument("command")
+    t.add_argument("--top", type=int, default=15)
+    q = sub.add_parser("traffic")
+    q.add_argument("--fetch", required=True)
+    q.add_argument("--write", required=True)
+    q.add_argument("--form", required=True)
+    q.add_argument("--workload", required=True)
+    q.add_argument("--out", required=True)
+    q.add_argument("--command", required=True)
     a = ap.parse_args(argv)
-    sys.stdout.write(summary(a.db, a.command, a.top))
+    if a.mode == "trace":
+        sys.stdout.write(trace_summary(a.db, a.command, a.top))
+        return 0
+    recs = traffic(a.fetch, a.write, a.form, a.workload, a.command)
+    old = []
+    if os.path.exists(a.out):
+        old = [r for r in json.load(open(a.out))
+               if not (r.get("form") == a.form and r.get("workload") == a.workload)]
+    json.dump(old + recs, open(a.out, "w"), indent=1)
+    for r in recs:
+        print(f"{r['kernel']}: fetch {r['fetch_bytes_per_launch'] / 1e9:.3f} GB, "
+              f"write {r['write_bytes_per_launch'] / 1e9:.3f} GB per launch")
     return 0
 
 

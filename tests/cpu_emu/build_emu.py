@@ -24,10 +24,16 @@ FLAGS = ["-std=c++20", "-O1", "-g", "-fsanitize=address", "-fno-omit-frame-point
 LAUNCH = re.compile(r"(\b[\w:]+(?:<[^;{}()]*?>)?)\s*<<<\s*(.*?)\s*>>>\s*\(", re.S)
 
 
+DYN_SMEM = re.compile(r"extern __shared__ (?:__attribute__\(\(aligned\(\d+\)\)\) )?unsigned char (\w+)\[\];")
+WAIT_BARRIER = re.compile(r'asm volatile\("s_waitcnt[^"]*s_barrier"[^;]*;')
+
+
 def translate(src: str) -> str:
     src = LAUNCH.sub(lambda m: f"lrdm_emu::launch({m.group(1)}, {m.group(2)}, ", src)
-    src = src.replace("extern __shared__ unsigned char smem_raw[];",
-                      "unsigned char* smem_raw = lrdm_emu::dyn_smem();")
+    src = DYN_SMEM.sub(lambda m: f"unsigned char* {m.group(1)} = lrdm_emu::dyn_smem();", src)
+    # a wait for this wave's global->LDS copies plus a block barrier: the stand-in
+    # performs those copies at once, so a barrier remains
+    src = WAIT_BARRIER.sub("__syncthreads();", src)
     return src
 
 

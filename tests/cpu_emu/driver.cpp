@@ -74,13 +74,34 @@ std::vector<double> orthonormal(int N, int64_t M, unsigned long long seed) {
   return P;
 }
 
-void scenario_response(lrdm_ctx* ctx, lrdm_grid g, int N, int nspin, int r) {
+const char* prec_name(lrdm_prec p) {
+  return p == LRDM_FP64 ? "fp64" : (p == LRDM_FP32 ? "fp32" : "bf16x3");
+}
+
+// Storage of a block in the form's element type.
+struct Block {
+  std::vector<double> d;
+  std::vector<float> f;
+  lrdm_prec prec;
+  Block(const std::vector<double>& x, lrdm_prec p) : prec(p) {
+    if (p == LRDM_FP64) d = x;
+    else f.assign(x.begin(), x.end());
+  }
+  void* data() { return prec == LRDM_FP64 ? (void*)d.data() : (void*)f.data(); }
+  std::vector<double> values() const {
+    return prec == LRDM_FP64 ? d : std::vector<double>(f.begin(), f.end());
+  }
+};
+
+void scenario_response(lrdm_ctx* ctx, lrdm_grid g, int N, int nspin, int r,
+                       lrdm_prec prec = LRDM_FP64) {
   const int64_t M = (int64_t)g.n[0] * g.n[1] * g.n[2];
-  std::vector<double> Psi;
+  std::vector<double> Psi0;
   for (int c = 0; c < nspin; ++c) {
     auto P = orthonormal(N, M, 11 + c);
-    Psi.insert(Psi.end(), P.begin(), P.end());
+    Psi0.insert(Psi0.end(), P.begin(), P.end());
   }
+  Block Psi(Psi0, prec);
   std::vector<double> eps((size_t)nspin * N);
   for (int c = 0; c < nspin; ++c)
     for (int i = 0; i < N; ++i) eps[(size_t)c * N + i] = -1.0 + 1.5 * i / N + 0.001 * c;
@@ -88,48 +109,68 @@ void scenario_response(lrdm_ctx* ctx, lrdm_grid g, int N, int nspin, int r) {
   auto dV = randv((size_t)r * nspin * M, 5);
   std::vector<double> drho(dV.size()), mu(1), dmu(r), t(dV.size());
   char name[128];
-  std::snprintf(name, sizeof name, "density_response N=%d nspin=%d r=%d grid %dx%dx%d", N, nspin,
-                r, g.n[0], g.n[1], g.n[2]);
-  check(density_response(ctx, &g, Psi.data(), eps.data(), N, &occ, dV.data(), r, LRDM_FP64,
+  std::snprintf(name, sizeof name, "density_response %s N=%d nspin=%d r=%d grid %dx%dx%d",
+                prec_name(prec), N, nspin, r, g.n[0], g.n[1], g.n[2]);
+  check(density_response(ctx, &g, Psi.data(), eps.data(), N, &occ, dV.data(), r, prec,
                          drho.data(), mu.data(), dmu.data()), ctx, name);
   if (!finite(drho)) { std::printf("FAIL non-finite drho\n"); ++failures; }
   std::snprintf(name, sizeof name, "residual_derivative N=%d nspin=%d r=%d", N, nspin, r);
   check(lrdm_residual_derivative(ctx, &g, Psi.data(), eps.data(), N, &occ, dV.data(), r,
-                                 LRDM_FP64, t.data()), ctx, name);
+                                 prec, t.data()), ctx, name);
   std::vector<double> Hp((size_t)r * nspin * N * N);
-  check(lrdm_projected_perturbation(ctx, &g, Psi.data(), N, nspin, dV.data(), r, LRDM_FP64,
+  check(lrdm_projected_perturbation(ctx, &g, Psi.data(), N, nspin, dV.data(), r, prec,
                                     Hp.data()), ctx, "projected_perturbation");
+  if (prec != LRDM_FP64) {
+    // the single-precision forms against the FP64 form on the same (rounded) block
+    Block P64(Psi.values(), LRDM_FP64);
+    std::vector<double> ref(dV.size());
+    check(density_response(ctx, &g, P64.data(), eps.data(), N, &occ, dV.data(), r, LRDM_FP64,
+                           ref.data(), mu.data(), dmu.data()), ctx, "density_response fp64 reference");
+    double num = 0, den = 0;
+    for (size_t i = 0; i < ref.size(); ++i) {
+      num += (drho[i] - ref[i]) * (drho[i] - ref[i]);
+      den += ref[i] * ref[i];
+    }
+    const double err = std::sqrt(num / den);
+    const double tol = prec == LRDM_FP32 ? 1e-5 : 1e-6;
+    std::printf("     %s drho rel err vs fp64 %.2e (bound %.0e)\n", prec_name(prec), err, tol);
+    if (!(err < tol)) ++failures;
+  }
   std::vector<double> f((size_t)nspin * N), fp((size_t)nspin * N), F((size_t)nspin * N * N);
   check(lrdm_fermi_occupations(ctx, eps.data(), N, &occ, mu.data(), f.data(), fp.data(), F.data()),
         ctx, "fermi_occupations");
 }
 
-void scenario_chfsi(lrdm_ctx* ctx, lrdm_grid g, int N, int degree) {
+void scenario_chfsi(lrdm_ctx* ctx, lrdm_grid g, int N, int degree, lrdm_prec prec = LRDM_FP64) {
   const int64_t M = (int64_t)g.n[0] * g.n[1] * g.n[2];
   auto V = randv((size_t)M, 3, 0.5);
-  auto X = randv((size_t)N * M, 4);
-  std::vector<double> Y(X.size()), eps(N), HX(X.size());
+  Block X(randv((size_t)N * M, 4), prec);
+  Block Y(std::vector<double>((size_t)N * M), prec), HX(std::vector<double>((size_t)N * M), prec);
+  std::vector<double> eps(N);
   double hx = g.L[0] / g.n[0], hy = g.L[1] / g.n[1], hz = g.L[2] / g.n[2];
   const double b = 2 / (hx * hx) + 2 / (hy * hy) + 2 / (hz * hz) + 0.5;
   char name[128];
-  std::snprintf(name, sizeof name, "hamiltonian_apply N=%d grid %dx%dx%d", N, g.n[0], g.n[1], g.n[2]);
-  check(lrdm_hamiltonian_apply(ctx, &g, V.data(), X.data(), HX.data(), N, LRDM_FP64), ctx, name);
-  std::snprintf(name, sizeof name, "chfsi_filter N=%d degree=%d", N, degree);
-  check(chfsi_filter(ctx, &g, V.data(), X.data(), Y.data(), N, LRDM_FP64, degree, -0.2, b, -1.0),
+  std::snprintf(name, sizeof name, "hamiltonian_apply %s N=%d grid %dx%dx%d", prec_name(prec), N,
+                g.n[0], g.n[1], g.n[2]);
+  check(lrdm_hamiltonian_apply(ctx, &g, V.data(), X.data(), HX.data(), N, prec), ctx, name);
+  std::snprintf(name, sizeof name, "chfsi_filter %s N=%d degree=%d", prec_name(prec), N, degree);
+  check(chfsi_filter(ctx, &g, V.data(), X.data(), Y.data(), N, prec, degree, -0.2, b, -1.0),
         ctx, name);
-  std::snprintf(name, sizeof name, "subspace_rayleigh_ritz N=%d", N);
-  check(subspace_rayleigh_ritz(ctx, &g, V.data(), Y.data(), N, LRDM_FP64, eps.data()), ctx, name);
-  if (!finite(eps) || !finite(Y)) { std::printf("FAIL non-finite Ritz output\n"); ++failures; }
+  std::snprintf(name, sizeof name, "subspace_rayleigh_ritz %s N=%d", prec_name(prec), N);
+  check(subspace_rayleigh_ritz(ctx, &g, V.data(), Y.data(), N, prec, eps.data()), ctx, name);
+  const std::vector<double> Yv = Y.values();
+  if (!finite(eps) || !finite(Yv)) { std::printf("FAIL non-finite Ritz output\n"); ++failures; }
   // orthonormality of the Ritz vectors
   double worst = 0;
   for (int i = 0; i < N; i += 7)
     for (int j = 0; j < N; j += 5) {
       double d = 0;
-      for (int64_t p = 0; p < M; ++p) d += Y[(size_t)i * M + p] * Y[(size_t)j * M + p];
+      for (int64_t p = 0; p < M; ++p) d += Yv[(size_t)i * M + p] * Yv[(size_t)j * M + p];
       worst = std::fmax(worst, std::fabs(d - (i == j)));
     }
-  std::printf("     Ritz orthonormality error %.2e\n", worst);
-  if (!(worst < 1e-10)) ++failures;
+  const double bound = prec == LRDM_FP64 ? 1e-10 : 1e-5;
+  std::printf("     Ritz orthonormality error %.2e (bound %.0e)\n", worst, bound);
+  if (!(worst < bound)) ++failures;
   std::vector<double> u = randv((size_t)2 * M, 9), dV(u.size());
   check(lrdm_hartree_kernel(ctx, &g, u.data(), dV.data(), 2), ctx, "hartree_kernel");
 }
@@ -155,6 +196,29 @@ void scenario_full_n(lrdm_ctx* ctx) {
   std::printf("     sym_eigh with NaN diagonal returned %d\n", (int)st);
 }
 
+// Projected perturbation of one form against FP64 on the same rounded block.
+void scenario_projection(lrdm_ctx* ctx, lrdm_grid g, int N, int r, lrdm_prec prec) {
+  const int64_t M = (int64_t)g.n[0] * g.n[1] * g.n[2];
+  Block Psi(orthonormal(N, M, 21), prec);
+  Block P64(Psi.values(), LRDM_FP64);
+  auto dV = randv((size_t)r * M, 7);
+  std::vector<double> H((size_t)r * N * N), R(H.size());
+  check(lrdm_projected_perturbation(ctx, &g, Psi.data(), N, 1, dV.data(), r, prec, H.data()), ctx,
+        "projected_perturbation (form)");
+  check(lrdm_projected_perturbation(ctx, &g, P64.data(), N, 1, dV.data(), r, LRDM_FP64, R.data()),
+        ctx, "projected_perturbation fp64");
+  double worst = 0, scale = 0;
+  size_t bad = 0;
+  for (size_t i = 0; i < H.size(); ++i) {
+    scale = std::fmax(scale, std::fabs(R[i]));
+    if (!std::isfinite(H[i])) { if (bad++ < 5) std::printf("     non-finite at %zu\n", i); continue; }
+    worst = std::fmax(worst, std::fabs(H[i] - R[i]));
+  }
+  std::printf("     %s projection: max err %.2e of max %.2e, non-finite %zu; H[0..3] %g %g %g vs %g %g %g\n",
+              prec_name(prec), worst, scale, bad, H[0], H[1], H[N + 1], R[0], R[1], R[N + 1]);
+  if (bad || !(worst < 1e-5 * scale)) ++failures;
+}
+
 }  // namespace
 
 int main(int argc, char** argv) {
@@ -166,6 +230,24 @@ int main(int argc, char** argv) {
     scenario_response(ctx, grid(9, 8, 7, 0.5), 40, 2, 2);
     scenario_chfsi(ctx, grid(10, 9, 8, 0.45), 150, 5);
     scenario_chfsi(ctx, grid(12, 12, 12, 0.45), 256, 4);
+  }
+  if (which == "all" || which == "lp") {
+    scenario_response(ctx, grid(20, 18, 13, 0.4), 150, 1, 3, LRDM_FP32);
+    scenario_response(ctx, grid(20, 18, 13, 0.4), 150, 1, 3, LRDM_BF16X3);
+    scenario_response(ctx, grid(9, 8, 7, 0.5), 40, 2, 2, LRDM_BF16X3);
+    // M = 693, not a multiple of 4: the projection takes the register-staged kernel
+    scenario_response(ctx, grid(7, 9, 11, 0.5), 70, 1, 2, LRDM_BF16X3);
+    scenario_response(ctx, grid(7, 9, 11, 0.5), 70, 2, 1, LRDM_FP32);
+    scenario_chfsi(ctx, grid(10, 9, 8, 0.45), 150, 5, LRDM_FP32);
+    scenario_chfsi(ctx, grid(12, 12, 12, 0.45), 130, 4, LRDM_BF16X3);
+  }
+  if (which == "pp") {
+    scenario_projection(ctx, grid(8, 8, 8, 0.5), 40, 1, LRDM_FP32);
+    scenario_projection(ctx, grid(8, 8, 8, 0.5), 40, 1, LRDM_BF16X3);
+  }
+  if (which == "lprr") {
+    scenario_chfsi(ctx, grid(10, 9, 8, 0.45), 150, 5, LRDM_FP32);
+    scenario_chfsi(ctx, grid(12, 12, 12, 0.45), 130, 4, LRDM_BF16X3);
   }
   if (which == "all" || which == "full") scenario_full_n(ctx);
   check(lrdm_destroy(ctx), nullptr, "lrdm_destroy");

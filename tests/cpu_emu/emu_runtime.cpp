@@ -90,8 +90,9 @@ void run_block(Block& b, dim3 block, uint3, size_t smem) {
   b.nthreads = nt;
   b.fibers.assign(nt, Fiber{});
   if ((int)b.xch.size() < (nt + 63) / 64) b.xch.resize((nt + 63) / 64, std::vector<double>(64 * 32, 0.0));
-  if (b.dyn.size() < smem + 16) b.dyn.resize(smem + 16);
-  std::fill(b.dyn.begin(), b.dyn.end(), (unsigned char)0xAB);
+  // exactly the requested dynamic LDS, so that AddressSanitizer sees any access
+  // past its end
+  b.dyn = std::vector<unsigned char>(smem ? smem : 1, (unsigned char)0xAB);
   while ((int)pool.stacks.size() < nt) pool.stacks.push_back(static_cast<char*>(std::malloc(kStack)));
   cur = &b;
   for (int t = 0; t < nt; ++t) {

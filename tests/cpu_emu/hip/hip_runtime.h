@@ -195,8 +195,16 @@ inline f4 mfma_f32_16x16x32_bf16(bf8 a, bf8 b, f4 c, int, int, int) {
   return out;
 }
 
+// global_load_lds_dwordx4: lane l copies `size` bytes from its own address to
+// base + size * l (base is the same for the whole wavefront).
+inline void global_load_lds(const void* src, void* base, unsigned size) {
+  std::memcpy(static_cast<unsigned char*>(base) + (size_t)size * lane(), src, size);
+}
+
 }  // namespace lrdm_emu
 
+#define __builtin_amdgcn_global_load_lds(src, dst, size, off, aux) \
+  lrdm_emu::global_load_lds((const void*)(src), (void*)(dst), (size))
 #define __builtin_amdgcn_mfma_f64_16x16x4f64 lrdm_emu::mfma_f64_16x16x4
 #define __builtin_amdgcn_mfma_f32_16x16x4f32 lrdm_emu::mfma_f32_16x16x4
 #define __builtin_amdgcn_mfma_f32_16x16x32_bf16 lrdm_emu::mfma_f32_16x16x32_bf16

@@ -19,3 +19,33 @@ def test_jacobi_index_logic(tmp_path):
     r = subprocess.run([str(exe)], capture_output=True, text=True)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "OK" in r.stdout
+
+
+def test_traffic_summary_scales_by_calibration_copy(tmp_path):
+    """HBM bytes per dispatch = counted KiB x 1024 x (1 GiB / counted bytes of the
+    calibration copy); median over the dispatches of each kernel."""
+    from paper_2211_07894_amd import profile_summary as ps
+
+    def write(path, counter, rows):
+        with open(path, "w") as f:
+            f.write("Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value\n")
+            for d, name, v in rows:
+                f.write(f'{d},"{name}",{counter},{v}\n')
+
+    gib_kib = (1 << 30) / 1024
+    copy = "void at::native::vectorized_elementwise_kernel<4, MulFunctor>(int)"
+    proj = "void lrdm::(anonymous namespace)::tn_sym_pipe_kernel<(lrdm::(anonymous namespace)::Core)2, true>(float const*)"
+    back = "void lrdm::(anonymous namespace)::backproj_pipe_kernel<(lrdm::(anonymous namespace)::Core)2>(float const*)"
+    write(tmp_path / "f.csv", "FETCH_SIZE",
+          [(1, copy, 1.25 * gib_kib), (2, copy, 1.25 * gib_kib), (3, copy, 1.25 * gib_kib),
+           (4, proj, 1000.0), (5, proj, 1000.0), (6, proj, 4000.0), (7, back, 500.0)])
+    write(tmp_path / "w.csv", "WRITE_SIZE",
+          [(1, copy, gib_kib), (2, copy, gib_kib), (3, copy, gib_kib),
+           (4, proj, 10.0), (5, proj, 10.0), (6, proj, 10.0), (7, back, 20.0)])
+    recs = {r["kernel"]: r for r in ps.traffic(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"),
+                                               "bf16x3", "wl", "cmd")}
+    assert set(recs) == {"proj", "backproj"}
+    assert recs["proj"]["fetch_bytes_per_launch"] == round(1000.0 * 1024 / 1.25)
+    assert recs["proj"]["write_bytes_per_launch"] == round(10.0 * 1024)
+    assert recs["backproj"]["bytes_per_launch"] == round(500.0 * 1024 / 1.25) + round(20.0 * 1024)
+    assert recs["proj"]["source"] == "gemm_lp.hip" and len(recs["proj"]["source_sha"]) == 16
