@@ -38,19 +38,42 @@ constexpr int kNewtonSchulz = 28;  // fixed Newton-Schulz steps of the orthonorm
 
 
 // --------------------------------------------------------------- reductions
-__global__ __launch_bounds__(256) void frob_kernel(const double* __restrict__ A, int N, int lda,
-                                                   double* __restrict__ out) {
+// Frobenius norm of the N x N matrix A (leading dimension lda): kFrobBlocks blocks
+// write partial sums of squares (grid-stride over rows), then one block adds
+// them in a fixed order.
+constexpr int kFrobBlocks = 256;
+
+__global__ __launch_bounds__(256) void frob_partial_kernel(const double* __restrict__ A, int N,
+                                                           int lda, double* __restrict__ part) {
   __shared__ double red[4];
   double s = 0.0;
-  for (int64_t e = threadIdx.x; e < (int64_t)N * N; e += blockDim.x) {
-    const int i = (int)(e / N), j = (int)(e - (int64_t)i * N);
-    const double v = A[(int64_t)i * lda + j];
-    s += v * v;
-  }
+  for (int i = blockIdx.x; i < N; i += gridDim.x)
+    for (int j = threadIdx.x; j < N; j += blockDim.x) {
+      const double v = A[(int64_t)i * lda + j];
+      s += v * v;
+    }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ __launch_bounds__(256) void frob_final_kernel(const double* __restrict__ part, int n,
+                                                         double* __restrict__ out) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += part[i];
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) *out = sqrt(red[0] + red[1] + red[2] + red[3]);
+}
+
+// out = ||A||_F, with `part` kFrobBlocks doubles of scratch.
+hipError_t frob(lrdm_ctx* ctx, const double* A, int N, int lda, double* part, double* out) {
+  frob_partial_kernel<<<kFrobBlocks, 256, 0, ctx->stream>>>(A, N, lda, part);
+  frob_final_kernel<<<1, 256, 0, ctx->stream>>>(part, kFrobBlocks, out);
+  return hipGetLastError();
 }
 
 // --------------------------------------------------------------- block Jacobi
@@ -403,6 +426,7 @@ lrdm_status sym_eigh(lrdm_ctx* ctx, const double* S, int lda, int N, const doubl
   double* V = static_cast<double*>(ws_take(ctx, (size_t)Np * Np * sizeof(double)));
   double* Ublk = static_cast<double*>(ws_take(ctx, (size_t)(nb / 2) * JS * JS * sizeof(double)));
   double* normF = static_cast<double*>(ws_take(ctx, 256));
+  double* fpart = static_cast<double*>(ws_take(ctx, kFrobBlocks * sizeof(double)));
   int* perm = static_cast<int*>(ws_take(ctx, (size_t)Np * sizeof(int)));
   int* flag = ctx->dstatus + LRDM_DS_COUNT;  // scratch word next to the status words
   auto fail = [&](hipError_t e) {
@@ -415,7 +439,7 @@ lrdm_status sym_eigh(lrdm_ctx* ctx, const double* S, int lda, int N, const doubl
     jac_init_kernel<<<grd, blk, 0, ctx->stream>>>(S, lda, N, Np, dinv, A, V);
     if ((e = hipGetLastError()) != hipSuccess) return fail(e);
   }
-  frob_kernel<<<1, 256, 0, ctx->stream>>>(A, N, Np, normF);
+  if ((e = frob(ctx, A, N, Np, fpart, normF)) != hipSuccess) return fail(e);
   if ((e = hipGetLastError()) != hipSuccess) return fail(e);
   const int max_sweeps = 40;
   int sweep = 0;
@@ -464,9 +488,10 @@ size_t rr_workspace_bytes(int N, int64_t M, lrdm_prec prec) {
   b += ws_align((size_t)M * N * sizeof(double));            // H Y, later Psi_R
   b += 6 * ws_align((size_t)N * N * sizeof(double));         // G, Hy, T, C, X, Wt
   b += 2 * ws_align((size_t)N * sizeof(double));             // dinv, lam
+  b += ws_align(kFrobBlocks * sizeof(double));               // norm partial sums
   // eigensolver
   b += 2 * ws_align((size_t)Np * Np * sizeof(double)) + ws_align((size_t)(nb / 2) * JS * JS * 8) +
-       ws_align(256) + ws_align((size_t)Np * 4);
+       ws_align(256) + ws_align((size_t)Np * 4) + ws_align(kFrobBlocks * sizeof(double));
   b += ws_align(tn_workspace_bytes(N, M, 1, prec));
   b += ws_align((size_t)N * N * sizeof(double));             // U of G
   return b;
@@ -488,6 +513,7 @@ lrdm_status rayleigh_ritz(lrdm_ctx* ctx, const Grid3& g, const double* V, T* Psi
   double* Ug = static_cast<double*>(ws_take(ctx, nn));
   double* dinv = static_cast<double*>(ws_take(ctx, (size_t)N * sizeof(double)));
   double* lam = static_cast<double*>(ws_take(ctx, (size_t)N * sizeof(double)));
+  double* fpart = static_cast<double*>(ws_take(ctx, kFrobBlocks * sizeof(double)));
   hipError_t e;
   auto fail = [&](const char* what, hipError_t err) {
     ctx->err = std::string("rayleigh_ritz: ") + what + ": " + hipGetErrorString(err);
@@ -521,7 +547,7 @@ lrdm_status rayleigh_ritz(lrdm_ctx* ctx, const Grid3& g, const double* V, T* Psi
   {
     dim3 blk(32, 8), grd((N + 31) / 32, (N + 7) / 8);
     gram_scale_kernel<<<grd, blk, 0, ctx->stream>>>(G, dinv, N, Tm);
-    frob_kernel<<<1, 256, 0, ctx->stream>>>(Tm, N, N, fro);
+    if ((e = frob(ctx, Tm, N, N, fpart, fro)) != hipSuccess) return fail("scale", e);
     ns_start_kernel<<<grd, blk, 0, ctx->stream>>>(Tm, fro, N, Ya, Za);
     if ((e = hipGetLastError()) != hipSuccess) return fail("scale", e);
     for (int it = 0; it < kNewtonSchulz; ++it) {

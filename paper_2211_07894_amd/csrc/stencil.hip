@@ -34,6 +34,7 @@ __global__ __launch_bounds__(1024) void cheb_plane_kernel(
 
   int xy[PPT];   // (y << 16) | x of each point owned by this thread, -1 if none
   T prev[PPT], cur[PPT], next[PPT];
+  T vcur[PPT], ocur[PPT];   // V and Yold at the current plane, loaded one plane ahead
   {
     const int zm = (z0 == 0) ? nz - 1 : z0 - 1;
     const int zp = (z0 + 1 == nz) ? 0 : z0 + 1;
@@ -46,9 +47,11 @@ __global__ __launch_bounds__(1024) void cheb_plane_kernel(
         prev[j] = (T)yin[(int64_t)zm * P + qq];
         cur[j] = (T)yin[(int64_t)z0 * P + qq];
         next[j] = (T)yin[(int64_t)zp * P + qq];
+        vcur[j] = (T)V[(int64_t)z0 * P + qq];
+        ocur[j] = yold ? (T)yold[(int64_t)z0 * P + qq] : T(0);
       } else {
         xy[j] = -1;
-        prev[j] = cur[j] = next[j] = T(0);
+        prev[j] = cur[j] = next[j] = vcur[j] = ocur[j] = T(0);
       }
     }
   }
@@ -59,7 +62,20 @@ __global__ __launch_bounds__(1024) void cheb_plane_kernel(
     for (int j = 0; j < PPT; ++j)
       if (xy[j] >= 0) pl[threadIdx.x + j * blockDim.x] = cur[j];
     __syncthreads();
+    // loads for the next planes, issued before this plane's arithmetic
+    const bool more = z + 1 < z1;
     const int zn = (z + 2 >= nz) ? z + 2 - nz : z + 2;
+    T nn[PPT], vn[PPT], on[PPT];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const int qq = threadIdx.x + j * blockDim.x;
+      nn[j] = vn[j] = on[j] = T(0);
+      if (xy[j] >= 0 && more) {
+        nn[j] = (T)yin[(int64_t)zn * P + qq];
+        vn[j] = (T)V[(int64_t)(z + 1) * P + qq];
+        if (yold) on[j] = (T)yold[(int64_t)(z + 1) * P + qq];
+      }
+    }
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
       if (xy[j] < 0) continue;
@@ -72,17 +88,18 @@ __global__ __launch_bounds__(1024) void cheb_plane_kernel(
       const int64_t off = (int64_t)z * P + q;
       const T c = cur[j];
       const T hy = wx * (pl[xm] + pl[xp]) + wy * (pl[ym] + pl[yp]) +
-                   wz * (prev[j] + next[j]) + ((T)V[off] + dshift) * c;
+                   wz * (prev[j] + next[j]) + (vcur[j] + dshift) * c;
       T out = alpha * hy;
-      if (yold) out += beta * (T)yold[off];
+      if (yold) out += beta * ocur[j];
       yout[off] = out;
     }
-    // rotate the z window; the load of plane z + 2 overlaps the next plane's work
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
       prev[j] = cur[j];
       cur[j] = next[j];
-      if (xy[j] >= 0 && z + 1 < z1) next[j] = (T)yin[(int64_t)zn * P + threadIdx.x + j * blockDim.x];
+      next[j] = nn[j];
+      vcur[j] = vn[j];
+      ocur[j] = on[j];
     }
     buf ^= 1;
   }
