@@ -310,3 +310,97 @@ def recursive_fermi_response(eps: np.ndarray, mu: float, kT: float, Hp: np.ndarr
         xp = x2p * yinv[None, :] - (x2 * yinv)[:, None] * yp * yinv[None, :]
         x = x2 * yinv
     return x, xp
+
+
+# ---------------------------------------------------------------------------
+# Adjoint of the subspace density response (vector-Jacobian product)
+# ---------------------------------------------------------------------------
+# The response delta rho = (s/dv) diag(Psi^T Gamma Psi), Gamma = F o H' - mu' diag(f')
+# (Eq. (22)), H' = Psi diag(dV) Psi^T (Eq. (21)), mu' fixed by Tr Gamma = 0 and mu
+# by the electron count (Eq. (1)), is differentiated here by hand.  With
+# g = dL/d(delta rho):
+#   A    = dL/dGamma = (s/dv) Psi diag(g) Psi^T
+#   dH'  = dL/dH'    = F o A - nu diag(f'),  nu = sum f'_i A_ii / sum f'_i
+#          (the same map as H' -> Gamma: the response is self-adjoint)
+#   dL/ddV_p  = sum_ij Psi_ip dH'_ij Psi_jp
+#   dL/dPsi   = 2 (s/dv) (Gamma Psi) o g + 2 (dH' Psi) o dV   (columns scaled)
+#   dL/deps   through F (second divided differences), f' (f''), and mu(eps)
+#             (dmu/deps_i = f'_i / sum f').
+def fermi_derivatives(eps: np.ndarray, mu: float, kT: float):
+    """d^k f / d eps^k for k = 1..4 at each eps, with a = f (1 - f):
+    f' = -a/kT, f'' = a (1 - 2f)/kT^2, f''' = -a (1 - 6a)/kT^3,
+    f'''' = a (1 - 2f)(1 - 12a)/kT^4 (a' = -(1 - 2f) a / kT)."""
+    f, omf, _ = fermi_dirac(eps, mu, kT)
+    a = f * omf
+    d = omf - f                    # 1 - 2f without cancellation of f near 1/2
+    return (-a / kT, a * d / kT ** 2, -a * (1.0 - 6.0 * a) / kT ** 3,
+            a * d * (1.0 - 12.0 * a) / kT ** 4)
+
+
+def second_divided_differences(eps: np.ndarray, mu: float, kT: float) -> np.ndarray:
+    """D_ij = f[eps_i, eps_i, eps_j] = (F_ij - f'_i)/(eps_j - eps_i), with the limit
+    f''_i / 2 at coincidence.  For |eps_j - eps_i| < 1e-3 kT the difference quotient
+    would cancel; there the Taylor series about eps_i,
+        f''/2 + f''' h/6 + f'''' h^2/24,   h = eps_j - eps_i,
+    is used (next term ~ (h/kT)^3 relative)."""
+    eps = np.asarray(eps, dtype=np.float64)
+    F = divided_differences(eps, mu, kT)
+    f1, f2, f3, f4 = fermi_derivatives(eps, mu, kT)
+    h = eps[None, :] - eps[:, None]
+    near = np.abs(h) < 1e-3 * kT
+    D = np.empty_like(F)
+    hs = np.where(near, 1.0, h)
+    D[~near] = ((F - f1[:, None]) / hs)[~near]
+    taylor = f2[:, None] / 2 + f3[:, None] * h / 6 + f4[:, None] * h * h / 24
+    D[near] = taylor[near]
+    return D
+
+
+def density_response_vjp(Psi: np.ndarray, eps: np.ndarray, grid: Grid, n_electrons: float,
+                         kT: float, dV: np.ndarray, g: np.ndarray, nspin: int = 1):
+    """dL/ddV, dL/dPsi and dL/deps for L with dL/d(delta rho) = g, where delta rho =
+    density_response(Psi, eps, grid, n_electrons, kT, dV, nspin).
+
+    Psi [nspin][N][nz][ny][nx], eps [nspin][N], dV and g [r][nspin][nz][ny][nx].
+    Returns (g_dV like dV, g_Psi like Psi, g_eps [nspin][N])."""
+    Psi = Psi.reshape((nspin,) + Psi.shape[-4:])
+    N = Psi.shape[1]
+    eps = np.asarray(eps, dtype=np.float64).reshape(nspin, -1)
+    dV = dV.reshape((-1, nspin) + grid.shape)
+    g = g.reshape(dV.shape)
+    r = dV.shape[0]
+    s = spin_factor(nspin)
+    c = s / grid.dv
+    mu, _ = fermi_level(eps, n_electrons, kT, nspin)
+    F = [divided_differences(eps[ch], mu, kT) for ch in range(nspin)]
+    D = [second_divided_differences(eps[ch], mu, kT) for ch in range(nspin)]
+    fd = [fermi_derivatives(eps[ch], mu, kT) for ch in range(nspin)]
+    fp = [fd[ch][0] for ch in range(nspin)]
+    S = float(sum(np.sum(x) for x in fp))
+    P = [Psi[ch].reshape(N, -1) for ch in range(nspin)]          # N x M
+    g_dV = np.zeros_like(dV)
+    g_Psi = np.zeros((nspin, N, grid.M))
+    Pm = [np.zeros((N, N)) for _ in range(nspin)]                # dL/dF
+    q = [np.zeros(N) for _ in range(nspin)]                      # dL/df'
+    for k in range(r):
+        Hp = [projected_perturbation(Psi[ch], dV[k, ch]) for ch in range(nspin)]
+        A = [c * projected_perturbation(Psi[ch], g[k, ch]) for ch in range(nspin)]
+        dmu = fermi_shift(Hp, fp)
+        nu = fermi_shift(A, fp)
+        for ch in range(nspin):
+            Gam = response_density_matrix(F[ch], Hp[ch], dmu, fp[ch])
+            dH = response_density_matrix(F[ch], A[ch], nu, fp[ch])
+            wv = dV[k, ch].reshape(-1)
+            gv = g[k, ch].reshape(-1)
+            g_dV[k, ch] = np.sum(P[ch] * (dH @ P[ch]), axis=0).reshape(grid.shape)
+            g_Psi[ch] += 2.0 * c * (Gam @ P[ch]) * gv[None, :] + 2.0 * (dH @ P[ch]) * wv[None, :]
+            Pm[ch] += A[ch] * Hp[ch]
+            # dL/df'_i: the -mu' diag(f') term and mu' = sum f' H'_ii / sum f'
+            q[ch] += -dmu * np.diag(A[ch]) - nu * (np.diag(Hp[ch]) - dmu)
+    # eps with mu held fixed, then the chain through mu(eps)
+    ge = np.stack([2.0 * np.sum(Pm[ch] * D[ch], axis=1) + q[ch] * fd[ch][1]
+                   for ch in range(nspin)])
+    dL_dmu = -float(np.sum(ge))
+    if abs(S) >= 1e-300:
+        ge = ge + np.stack(fp) / S * dL_dmu
+    return g_dV, g_Psi.reshape(Psi.shape), ge

@@ -420,3 +420,91 @@ def recursion_errors(depths=(4, 6, 8, 10, 12)):
         _, xp = O.recursive_fermi_response(eps, mu, kT, Hp, T)
         errs.append(_rel(xp, exact))
     return errs
+
+
+# ------------------------------------------------------------------ adjoint of the response
+def _dec_fermi_derivs(e, mu, kT):
+    """f, f' and f'' of the Fermi function in 50-digit decimal."""
+    f = _dec_fermi(e, mu, kT)
+    a = f * (1 - f)
+    k = decimal.Decimal(kT)
+    return f, -a / k, a * (1 - 2 * f) / (k * k)
+
+
+def pin_second_divided_differences_decimal():
+    """D_ij = f[e_i, e_i, e_j] against 50-digit decimal (f[e_i,e_j] - f'(e_i))/(e_j - e_i)
+    and f''(e_i)/2 at coincidence, for separations from 0 to 5 kT on both sides of
+    the Taylor threshold; error in units of f(1-f)/kT^2 at e_i."""
+    decimal.getcontext().prec = 50
+    mu, kT = 0.13, 0.01
+    rng = np.random.default_rng(21)
+    base = rng.uniform(mu - 0.06, mu + 0.06, 6)
+    offs = np.array([0.0, 1e-9, 1e-6, 1e-4, 9.9e-4, 1.01e-3, 1e-2, 0.1, 1.0, 5.0]) * kT
+    eps = np.concatenate([base, base[0] + offs[1:], base[3] - offs[1:]])
+    D = O.second_divided_differences(eps, mu, kT)
+    err = 0.0
+    for i in range(len(eps)):
+        fi, f1i, f2i = _dec_fermi_derivs(eps[i], mu, kT)
+        scale = float(fi * (1 - fi)) / kT ** 2
+        for j in range(len(eps)):
+            if eps[i] == eps[j]:
+                ref = f2i / 2
+            else:
+                fj = _dec_fermi(eps[j], mu, kT)
+                dij = (fi - fj) / (decimal.Decimal(eps[i]) - decimal.Decimal(eps[j]))
+                ref = (dij - f1i) / (decimal.Decimal(eps[j]) - decimal.Decimal(eps[i]))
+            err = max(err, abs(D[i, j] - float(ref)) / scale)
+    return err
+
+
+def _vjp_case(nspin, seed=0):
+    rng = np.random.default_rng(seed)
+    g = O.Grid((5, 4, 3), (2.5, 2.0, 1.5))
+    N = 9
+    Psi = np.stack([np.linalg.qr(rng.standard_normal((g.M, N)))[0].T.reshape((N,) + g.shape)
+                    for _ in range(nspin)])
+    eps = np.sort(rng.uniform(-1.0, 0.5, (nspin, N)), axis=1)
+    eps[0, 3] = eps[0, 2] + 1e-6           # a near-degenerate pair
+    ne = 0.6 * N
+    kT = 0.05
+    dV = rng.standard_normal((2, nspin) + g.shape)
+    G = rng.standard_normal((2, nspin) + g.shape)
+    return rng, g, Psi, eps, ne, kT, dV, G
+
+
+def pin_vjp_fd():
+    """<dL/dx, u> against Richardson-extrapolated central differences of
+    L = <G, delta rho> along random u, for x = dV, Psi, eps and both spin cases
+    (uses only the forward oracle).  Returns the largest relative error."""
+    worst = 0.0
+    for nspin in (1, 2):
+        rng, g, Psi, eps, ne, kT, dV, G = _vjp_case(nspin)
+        gdV, gP, ge = O.density_response_vjp(Psi, eps, g, ne, kT, dV, G, nspin)
+        base = {"dV": dV, "Psi": Psi, "eps": eps}
+        for name, gx in (("dV", gdV), ("Psi", gP), ("eps", ge)):
+            u = rng.standard_normal(base[name].shape)
+
+            def L(t):
+                a = dict(base)
+                a[name] = base[name] + t * u
+                d = O.density_response(a["Psi"], a["eps"], g, ne, kT, a["dV"], nspin)[0]
+                return float(np.sum(G * d))
+            h = 2e-4
+            c1 = (L(h) - L(-h)) / (2 * h)
+            c2 = (L(h / 2) - L(-h / 2)) / h
+            fd = (4 * c2 - c1) / 3
+            an = float(np.sum(gx * u))
+            worst = max(worst, abs(fd - an) / max(abs(an), 1e-300))
+    return worst
+
+
+def pin_vjp_self_adjoint():
+    """The response is a symmetric linear map of dV, so dL/ddV for L = <G, delta rho>
+    is the response to G itself."""
+    worst = 0.0
+    for nspin in (1, 2):
+        _, g, Psi, eps, ne, kT, dV, G = _vjp_case(nspin, seed=3)
+        gdV, _, _ = O.density_response_vjp(Psi, eps, g, ne, kT, dV, G, nspin)
+        ref = O.density_response(Psi, eps, g, ne, kT, G, nspin)[0]
+        worst = max(worst, float(np.linalg.norm(gdV - ref) / np.linalg.norm(ref)))
+    return worst
