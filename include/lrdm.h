@@ -11,6 +11,7 @@
  *   chfsi_filter            Y = T_c(Hbar) X / T_c(ybar0)        (Sec. II C)
  *   subspace_rayleigh_ritz  Psi_R, eps from the filtered block   (Sec. II C, Eq. (15))
  *   density_response        delta rho[dV] in span(Psi_R)         (Eqs. (19)-(22))
+ *   density_response_backward  its vector-Jacobian product (adjoint)
  *   lrdm_residual_derivative t = chi0 K_c u - u                  (Eqs. (3), (7))
  *
  * plus the single steps they are made of (stencil Hamiltonian, occupations and
@@ -197,6 +198,27 @@ lrdm_status density_response(lrdm_ctx* ctx, const lrdm_grid* grid, const void* P
 lrdm_status lrdm_residual_derivative(lrdm_ctx* ctx, const lrdm_grid* grid, const void* Psi,
                                      const double* eps, int32_t N, const lrdm_occ* occ,
                                      const double* u, int32_t r, lrdm_prec prec, double* t);
+
+/* Adjoint (vector-Jacobian product) of density_response: for a loss L with
+ * g_drho = dL/d(delta rho) [r][nspin][M], returns
+ *   g_dV  [r][nspin][M] double          dL/ddV  (the response to g_drho itself:
+ *                                       the map dV -> delta rho is symmetric)
+ *   g_Psi [nspin][N][M] (Psi's type)    dL/dPsi = 2 (s/dv) (Gamma Psi) o g
+ *                                                 + 2 (dH' Psi) o dV, summed over k
+ *   g_eps [nspin][N] double             dL/deps through the divided differences
+ *                                       (second divided differences of f, Eq. (22)),
+ *                                       f', mu' and mu(eps) (Eq. (1))
+ * with dH' = F o A - nu diag(f'), A = (s/dv) Psi diag(g) Psi^T, nu the Fermi
+ * shift of A (text after Eq. (24)).  Inputs as for density_response; Gamma and
+ * H' are recomputed, nothing of the forward call is kept.  Any of the three
+ * outputs may be NULL (not computed); g_Psi may not alias Psi.  FP64 outputs
+ * are written whatever prec is; prec selects the arithmetic of the two
+ * projections and the back-projection, the rotation for g_Psi is FP64. */
+lrdm_status density_response_backward(lrdm_ctx* ctx, const lrdm_grid* grid, const void* Psi,
+                                      const double* eps, int32_t N, const lrdm_occ* occ,
+                                      const double* dV, int32_t r, lrdm_prec prec,
+                                      const double* g_drho, double* g_dV, void* g_Psi,
+                                      double* g_eps);
 
 #ifdef __cplusplus
 }

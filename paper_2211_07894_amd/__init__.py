@@ -19,4 +19,6 @@ from .lrdm import (  # noqa: F401
     subspace_rayleigh_ritz,
     density_response,
     residual_derivative,
+    density_response_backward,
+    DensityResponse,
 )

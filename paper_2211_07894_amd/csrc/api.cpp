@@ -1,5 +1,6 @@
 // extern "C" entry points of liblrdm (declared in include/lrdm.h): argument
 // validation, workspace sizing and the sequence of kernel launches of each call.
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -412,6 +413,66 @@ hipError_t run_response(lrdm_ctx* ctx, const Grid3& g, const T* Psi, const doubl
   return hipSuccess;
 }
 
+// Adjoint of run_response (see density_response_backward in lrdm.h).
+template <typename T>
+hipError_t run_backward(lrdm_ctx* ctx, const Grid3& g, const T* Psi, const double* eps, int N,
+                        const lrdm_occ* occ, const double* dV, int r, lrdm_prec prec,
+                        const double* gd, double* g_dV, T* g_Psi, double* g_eps) {
+  const int ns = occ->nspin;
+  const int batch = r * ns;
+  const size_t vec = (size_t)ns * N * sizeof(double);
+  const size_t mat = (size_t)batch * N * N * sizeof(double);
+  double* mu = static_cast<double*>(ws_take(ctx, 8));
+  double* dmu = static_cast<double*>(ws_take(ctx, (size_t)r * 8));
+  double* nu = static_cast<double*>(ws_take(ctx, (size_t)r * 8));
+  double* f = static_cast<double*>(ws_take(ctx, vec));
+  double* omf = static_cast<double*>(ws_take(ctx, vec));
+  double* fp = static_cast<double*>(ws_take(ctx, vec));
+  double* part = static_cast<double*>(ws_take(ctx, vec));
+  double* F = static_cast<double*>(ws_take(ctx, (size_t)ns * N * N * sizeof(double)));
+  double* Hp = static_cast<double*>(ws_take(ctx, mat));
+  double* A = static_cast<double*>(ws_take(ctx, mat));
+  double* Gm = static_cast<double*>(ws_take(ctx, mat));
+  double* dH = static_cast<double*>(ws_take(ctx, mat));
+  double* gs = static_cast<double*>(ws_take(ctx, (size_t)batch * g.M * sizeof(double)));
+  const double c = ((ns == 1) ? 2.0 : 1.0) / g.dv;
+  LRDM_HIP(launch_fermi(ctx, eps, N, ns, occ->kT, occ->n_electrons, mu, f, omf, fp, F));
+  const size_t mark = ctx->ws_top;
+  // H' and A = (s/dv) Psi diag(g) Psi^T (recomputed; nothing of the forward call is kept)
+  LRDM_HIP(launch_tn_sym<T>(ctx, Psi, nullptr, dV, g.M, N, g.M, ns, batch, prec, Hp));
+  ctx->ws_top = mark;
+  LRDM_HIP(launch_scale(ctx, gd, c, (int64_t)batch * g.M, gs));
+  LRDM_HIP(launch_tn_sym<T>(ctx, Psi, nullptr, gs, g.M, N, g.M, ns, batch, prec, A));
+  ctx->ws_top = mark;
+  // Gamma and dH' = F o A - nu diag(f'): the same map applied to copies
+  LRDM_HIP(hipMemcpyAsync(Gm, Hp, mat, hipMemcpyDeviceToDevice, ctx->stream));
+  LRDM_HIP(launch_gamma(ctx, Gm, F, fp, N, ns, r, dmu));
+  LRDM_HIP(hipMemcpyAsync(dH, A, mat, hipMemcpyDeviceToDevice, ctx->stream));
+  LRDM_HIP(launch_gamma(ctx, dH, F, fp, N, ns, r, nu));
+  if (g_dV) {
+    LRDM_HIP(launch_backproj<T>(ctx, Psi, dH, N, g.M, ns, batch, prec, 1.0, nullptr, g_dV));
+    ctx->ws_top = mark;
+  }
+  if (g_Psi) LRDM_HIP(launch_adj_psi<T>(ctx, Gm, gs, dH, dV, r, Psi, N, g.M, ns, 2.0, g_Psi));
+  if (g_eps)
+    LRDM_HIP(launch_adj_eps(ctx, A, Hp, eps, F, f, omf, fp, dmu, nu, N, ns, r, occ->kT, part,
+                            g_eps));
+  if (ctx->checks) {
+    if (g_dV) LRDM_HIP(launch_check_finite(ctx, g_dV, (int64_t)batch * g.M));
+    if (g_eps) LRDM_HIP(launch_check_finite(ctx, g_eps, (int64_t)ns * N));
+  }
+  return hipSuccess;
+}
+
+size_t backward_bytes(int N, int64_t M, int r, int ns, lrdm_prec prec) {
+  const int batch = r * ns;
+  const size_t scratch = std::max(tn_bytes(N, M, batch, prec),
+                                  backproj_workspace_bytes(N, M, ns, batch, prec));
+  return ws_align(8) + 2 * ws_align((size_t)r * 8) + 4 * ws_align((size_t)ns * N * 8) +
+         ws_align((size_t)ns * N * N * 8) + 4 * ws_align((size_t)batch * N * N * 8) +
+         ws_align((size_t)batch * M * 8) + ws_align(scratch) + 4096;
+}
+
 size_t response_bytes(int N, int64_t M, int r, int ns, lrdm_prec prec) {
   const int batch = r * ns;
   return ws_align(8) + ws_align((size_t)r * 8) + 3 * ws_align((size_t)ns * N * 8) +
@@ -523,5 +584,36 @@ extern "C" lrdm_status lrdm_residual_derivative(lrdm_ctx* ctx, const lrdm_grid* 
         : run_response<float>(ctx, g, static_cast<const float*>(Psi), eps, N, occ, dV, r, prec, u,
                               t, nullptr, nullptr);
     return e == hipSuccess ? LRDM_OK : fail_hip(ctx, "residual_derivative", e);
+  });
+}
+
+extern "C" lrdm_status density_response_backward(lrdm_ctx* ctx, const lrdm_grid* grid,
+                                                 const void* Psi, const double* eps, int32_t N,
+                                                 const lrdm_occ* occ, const double* dV, int32_t r,
+                                                 lrdm_prec prec, const double* g_drho,
+                                                 double* g_dV, void* g_Psi, double* g_eps) {
+  LRDM_CHECK(ctx, check_grid(grid));
+  LRDM_CHECK(ctx, check_block(grid, N));
+  LRDM_CHECK(ctx, check_occ(occ, N));
+  LRDM_CHECK(ctx, check_rank(r));
+  LRDM_CHECK(ctx, check_prec(prec));
+  LRDM_NONNULL(ctx, Psi, "Psi");
+  LRDM_NONNULL(ctx, eps, "eps");
+  LRDM_NONNULL(ctx, dV, "dV");
+  LRDM_NONNULL(ctx, g_drho, "g_drho");
+  const Grid3 g = make_grid3(grid);
+  const int ns = occ->nspin;
+  const size_t blk = (size_t)ns * N * g.M * prec_bytes(prec);
+  if (g_Psi && overlaps(Psi, blk, g_Psi, blk))
+    return fail(ctx, LRDM_EINVAL, "g_Psi must not overlap Psi");
+  lrdm_status st = begin(ctx, backward_bytes(N, g.M, r, ns, prec));
+  if (st != LRDM_OK) return st;
+  return guarded(ctx, [&]() -> lrdm_status {
+    hipError_t e = (prec == LRDM_FP64)
+        ? run_backward<double>(ctx, g, static_cast<const double*>(Psi), eps, N, occ, dV, r, prec,
+                               g_drho, g_dV, static_cast<double*>(g_Psi), g_eps)
+        : run_backward<float>(ctx, g, static_cast<const float*>(Psi), eps, N, occ, dV, r, prec,
+                              g_drho, g_dV, static_cast<float*>(g_Psi), g_eps);
+    return e == hipSuccess ? LRDM_OK : fail_hip(ctx, "density_response_backward", e);
   });
 }

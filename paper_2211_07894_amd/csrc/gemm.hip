@@ -385,6 +385,88 @@ __global__ __launch_bounds__(256, 2) void nn_f64_kernel(const double* __restrict
     }
 }
 
+// ------------------------------------------------------------------ adjoint rotation
+// Out_c[i][p] = scale * sum_m w_m[p] sum_j X_m[i][j] Psi_c[j][p] over the nmat
+// symmetric matrices X_m of channel c (m = 0 .. nmat-1 at X + ((m * nspin) + c) N^2,
+// weights at w + ((m * nspin) + c) M; two lists, the second starting at m = nx).
+// FP64 arithmetic for either storage type.  grid x = point block, y = row block,
+// z = channel.  The column weights travel with each staged K-tile.
+template <typename T>
+__global__ __launch_bounds__(256, 2) void adj_psi_f64_kernel(
+    const double* __restrict__ X1, const double* __restrict__ w1, const double* __restrict__ X2,
+    const double* __restrict__ w2, int nx, const T* __restrict__ Psi, int N, int64_t M, int nspin,
+    double scale, T* __restrict__ Out) {
+  __shared__ double Xs[KT * LDP];
+  __shared__ double Bs[KT * LDP];
+  __shared__ double Wc[BT];
+  const int64_t p0 = (int64_t)blockIdx.x * BT;
+  const int i0 = blockIdx.y * BT;
+  const int c = blockIdx.z;
+  const T* Pc = Psi + (int64_t)c * N * M;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  const int nkt = (N + KT - 1) / KT;
+  const int nstep = 2 * nx * nkt;              // (matrix, K-tile) steps
+  d4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  RowLoad<double> lx;
+  RowLoad<T> lb;
+  double wn = 0.0;
+  auto load = [&](int step) {
+    const int m = step / nkt, j0 = (step % nkt) * KT;
+    const int64_t b = (int64_t)(m % nx) * nspin + c;
+    const double* X = (m < nx ? X1 : X2) + b * N * N;
+    const double* w = (m < nx ? w1 : w2) + b * M;
+    lx.load(X, N, N, N, j0, i0, 1.0);
+    lb.load(Pc, M, N, M, j0, p0, 1.0);
+    if (threadIdx.x < BT) {
+      const int64_t p = p0 + threadIdx.x;
+      wn = p < M ? w[p] : 0.0;
+    }
+  };
+  if (nstep > 0) load(0);
+  for (int step = 0; step < nstep; ++step) {
+    __syncthreads();
+    lx.store(Xs);
+    lb.store(Bs);
+    if (threadIdx.x < BT) Wc[threadIdx.x] = wn;
+    __syncthreads();
+    if (step + 1 < nstep) load(step + 1);
+    double wcol[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) wcol[j] = Wc[wc * 64 + j * 16 + (lane & 15)];
+#pragma unroll
+    for (int kk = 0; kk < KT; kk += 4) {
+      const int kr = (kk + (lane >> 4)) * LDP;
+      double a[4], bb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = Xs[kr + wr * 64 + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bb[j] = Bs[kr + wc * 64 + j * 16 + (lane & 15)] * wcol[j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = mfma64(a[i], bb[j], acc[i][j]);
+    }
+  }
+  T* Oc = Out + (int64_t)c * N * M;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int gi = i0 + wr * 64 + i * 16 + 4 * v + (lane >> 4);
+      if (gi >= N) continue;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t p = p0 + wc * 64 + j * 16 + (lane & 15);
+        if (p < M) Oc[(int64_t)gi * M + p] = (T)(scale * acc[i][j][v]);
+      }
+    }
+}
+
 }  // namespace
 
 size_t tn_workspace_bytes(int N, int64_t M, int batch, lrdm_prec) {
@@ -458,5 +540,22 @@ template hipError_t launch_nn_f64<double>(lrdm_ctx*, const double*, const double
                                           int64_t);
 template hipError_t launch_nn_f64<float>(lrdm_ctx*, const double*, const float*, float*, int,
                                          int64_t);
+
+template <typename T>
+hipError_t launch_adj_psi(lrdm_ctx* ctx, const double* X1, const double* w1, const double* X2,
+                          const double* w2, int nx, const T* Psi, int N, int64_t M, int nspin,
+                          double scale, T* Out) {
+  dim3 grd((unsigned)((M + BT - 1) / BT), (N + BT - 1) / BT, nspin);
+  ProfScope prof(ctx, "adj_psi");
+  adj_psi_f64_kernel<T><<<grd, 256, 0, ctx->stream>>>(X1, w1, X2, w2, nx, Psi, N, M, nspin, scale,
+                                                      Out);
+  return hipGetLastError();
+}
+template hipError_t launch_adj_psi<double>(lrdm_ctx*, const double*, const double*, const double*,
+                                           const double*, int, const double*, int, int64_t, int,
+                                           double, double*);
+template hipError_t launch_adj_psi<float>(lrdm_ctx*, const double*, const double*, const double*,
+                                          const double*, int, const float*, int, int64_t, int,
+                                          double, float*);
 
 }  // namespace lrdm

@@ -124,6 +124,25 @@ hipError_t launch_backproj(lrdm_ctx* ctx, const T* A, const double* G, int N, in
 template <typename S>
 hipError_t launch_nn_f64(lrdm_ctx* ctx, const double* Wt, const S* B, S* Out, int N, int64_t M);
 
+// Adjoint rotation (gemm.hip): Out_c = scale * sum_m (X_m Psi_c) o w_m over two lists
+// of nx symmetric matrices [nx][nspin][N][N] with weights [nx][nspin][M], FP64
+// arithmetic; Out has Psi's storage type and layout.
+template <typename T>
+hipError_t launch_adj_psi(lrdm_ctx* ctx, const double* X1, const double* w1, const double* X2,
+                          const double* w2, int nx, const T* Psi, int N, int64_t M, int nspin,
+                          double scale, T* Out);
+
+// Adjoint pieces (adjoint.hip).
+// y[i] = a * x[i] for i < n.
+hipError_t launch_scale(lrdm_ctx* ctx, const double* x, double a, int64_t n, double* y);
+// dL/deps for each channel from A = dL/dGamma and H' ([r][nspin][N][N] each), the
+// Fermi quantities of launch_fermi, mu' and nu ([r]), including the chain through mu;
+// part: nspin N doubles of scratch.
+hipError_t launch_adj_eps(lrdm_ctx* ctx, const double* A, const double* Hp, const double* eps,
+                          const double* F, const double* f, const double* omf, const double* fp,
+                          const double* dmu, const double* nu, int N, int nspin, int r, double kT,
+                          double* part, double* g_eps);
+
 // Rayleigh-Ritz pieces (rr.hip).
 // Eigenpairs of a symmetric N x N matrix (FP64, block Jacobi on the GPU).
 lrdm_status sym_eigh(lrdm_ctx* ctx, const double* S, int lda, int N, const double* dinv,

@@ -29,6 +29,7 @@ EXPORTED = [
     "lrdm_last_error", "lrdm_hamiltonian_apply", "lrdm_fermi_occupations",
     "lrdm_projected_perturbation", "lrdm_hartree_kernel", "chfsi_filter",
     "subspace_rayleigh_ritz", "density_response", "lrdm_residual_derivative",
+    "density_response_backward",
 ]
 
 
@@ -109,6 +110,8 @@ def library() -> ctypes.CDLL:
                 "subspace_rayleigh_ritz": [vp, G, vp, vp, i32, ctypes.c_int, vp],
                 "density_response": [vp, G, vp, vp, i32, O, vp, i32, ctypes.c_int, vp, vp, vp],
                 "lrdm_residual_derivative": [vp, G, vp, vp, i32, O, vp, i32, ctypes.c_int, vp],
+                "density_response_backward": [vp, G, vp, vp, i32, O, vp, i32, ctypes.c_int, vp,
+                                              vp, vp, vp],
             }
             for name, args in sig.items():
                 fn = getattr(lib, name)
@@ -332,3 +335,63 @@ def residual_derivative(grid: Grid, Psi, eps, occ: Occupation, u, prec="fp64", o
         _ptr(u, "u", torch.float64, r * ns * grid.M), r, _prec(prec),
         _ptr(t, "t", torch.float64, r * ns * grid.M)))
     return t
+
+
+def _opt_ptr(t, name, dtype, numel):
+    return None if t is None else _ptr(t, name, dtype, numel)
+
+
+def density_response_backward(grid: Grid, Psi, eps, occ: Occupation, dV, g_drho, prec="fp64",
+                              want=("dV", "Psi", "eps")):
+    """Vector-Jacobian product of density_response for dL/d(delta rho) = g_drho
+    [r][nspin][M]: returns (g_dV [r][nspin][M], g_Psi like Psi, g_eps [nspin][N]);
+    entries not named in `want` are None and are not computed."""
+    ns = occ.nspin
+    N = eps.numel() // ns
+    r = dV.numel() // (ns * grid.M)
+    dev = Psi.device
+    g_dV = torch.empty((r, ns) + grid.shape, dtype=torch.float64, device=dev) if "dV" in want else None
+    g_Psi = torch.empty_like(Psi) if "Psi" in want else None
+    g_eps = torch.empty((ns, N), dtype=torch.float64, device=dev) if "eps" in want else None
+    ctx = context(dev.index)
+    g = grid.c()
+    o = occ.c()
+    ctx.check(ctx.lib.density_response_backward(
+        ctx.ptr, ctypes.byref(g), _ptr(Psi, "Psi", _block_dtype(prec), ns * N * grid.M),
+        _ptr(eps, "eps", torch.float64, ns * N), N, ctypes.byref(o),
+        _ptr(dV, "dV", torch.float64, r * ns * grid.M), r, _prec(prec),
+        _ptr(g_drho, "g_drho", torch.float64, r * ns * grid.M),
+        _opt_ptr(g_dV, "g_dV", torch.float64, r * ns * grid.M),
+        _opt_ptr(g_Psi, "g_Psi", _block_dtype(prec), ns * N * grid.M),
+        _opt_ptr(g_eps, "g_eps", torch.float64, ns * N)))
+    return g_dV, g_Psi, g_eps
+
+
+class DensityResponse(torch.autograd.Function):
+    """delta rho = density_response(Psi, eps, dV) with the library's adjoint as
+    backward.  Only the inputs are kept for backward (Psi, eps and dV by
+    reference); H' and Gamma are recomputed there.
+
+        drho = DensityResponse.apply(Psi, eps, dV, grid, occ, prec)
+    """
+
+    @staticmethod
+    def forward(ctx, Psi, eps, dV, grid, occ, prec="fp64"):
+        drho, _, _ = density_response(grid, Psi.detach(), eps.detach(), occ, dV.detach(), prec=prec)
+        ctx.save_for_backward(Psi, eps, dV)
+        ctx.grid, ctx.occ, ctx.prec = grid, occ, prec
+        return drho
+
+    @staticmethod
+    def backward(ctx, g):
+        Psi, eps, dV = ctx.saved_tensors
+        want = tuple(n for n, need in zip(("Psi", "eps", "dV"), ctx.needs_input_grad[:3]) if need)
+        g_dV, g_Psi, g_eps = density_response_backward(
+            ctx.grid, Psi.detach(), eps.detach(), ctx.occ, dV.detach(),
+            g.detach().to(torch.float64).contiguous(), prec=ctx.prec, want=want)
+        if g_eps is not None:
+            g_eps = g_eps.reshape(eps.shape)
+        if g_dV is not None:
+            g_dV = g_dV.reshape(dV.shape)
+        return g_Psi, g_eps, g_dV, None, None, None
+

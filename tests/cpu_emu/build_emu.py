@@ -37,35 +37,49 @@ def translate(src: str) -> str:
     return src
 
 
-def build(driver: str) -> str:
-    os.makedirs(os.path.join(OUT, "src"), exist_ok=True)
+def build(driver: str, shared: bool = False) -> str:
+    """The ASan driver executable, or (shared=True) an optimised shared library
+    exporting the C ABI on host memory, without a sanitizer, for numerical checks
+    of the kernels against the oracle on the CPU."""
+    out = os.path.join(OUT, "shared") if shared else OUT
+    flags = ([f for f in FLAGS if f not in ("-fsanitize=address", "-O1")] + ["-O2", "-fPIC"]
+             if shared else FLAGS)
+    os.makedirs(os.path.join(out, "src"), exist_ok=True)
     units = []
     for f in sorted(os.listdir(CSRC)):
         if not f.endswith((".hip", ".cpp")):
             continue
         text = open(os.path.join(CSRC, f)).read()
-        dst = os.path.join(OUT, "src", f.rsplit(".", 1)[0] + ".cpp")
+        dst = os.path.join(out, "src", f.rsplit(".", 1)[0] + ".cpp")
         open(dst, "w").write(translate(text) if f.endswith(".hip") else text)
         units.append(dst)
     units.append(os.path.join(HERE, "emu_runtime.cpp"))
-    units.append(driver)
+    if not shared:
+        units.append(driver)
 
     def comp(u):
-        obj = os.path.join(OUT, os.path.basename(u) + ".o")
-        r = subprocess.run([CLANG, *FLAGS, "-c", u, "-o", obj], capture_output=True, text=True)
+        obj = os.path.join(out, os.path.basename(u) + ".o")
+        r = subprocess.run([CLANG, *flags, "-c", u, "-o", obj], capture_output=True, text=True)
         if r.returncode:
             raise RuntimeError(f"{u}:\n{r.stderr}")
         return obj
 
     with ThreadPoolExecutor(8) as ex:
         objs = list(ex.map(comp, units))
-    exe = os.path.join(OUT, "lrdm_emu_driver")
-    r = subprocess.run([CLANG, "-fsanitize=address", *objs, "-o", exe, "-lpthread"],
-                       capture_output=True, text=True)
+    if shared:
+        exe = os.path.join(out, "liblrdm_emu.so")
+        cmd = [CLANG, "-shared", *objs, "-o", exe, "-lpthread"]
+    else:
+        exe = os.path.join(out, "lrdm_emu_driver")
+        cmd = [CLANG, "-fsanitize=address", *objs, "-o", exe, "-lpthread"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode:
         raise RuntimeError(r.stderr)
     return exe
 
 
 if __name__ == "__main__":
-    print(build(sys.argv[1] if len(sys.argv) > 1 else os.path.join(HERE, "driver.cpp")))
+    if len(sys.argv) > 1 and sys.argv[1] == "--shared":
+        print(build("", shared=True))
+    else:
+        print(build(sys.argv[1] if len(sys.argv) > 1 else os.path.join(HERE, "driver.cpp")))

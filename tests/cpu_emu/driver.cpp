@@ -219,6 +219,44 @@ void scenario_projection(lrdm_ctx* ctx, lrdm_grid g, int N, int r, lrdm_prec pre
   if (bad || !(worst < 1e-5 * scale)) ++failures;
 }
 
+// Adjoint of the response: all outputs, finite, and dL/ddV equal to the response
+// to g itself (the map is symmetric).
+void scenario_backward(lrdm_ctx* ctx, lrdm_grid g, int N, int nspin, int r, lrdm_prec prec) {
+  const int64_t M = (int64_t)g.n[0] * g.n[1] * g.n[2];
+  std::vector<double> P0;
+  for (int c = 0; c < nspin; ++c) {
+    auto P = orthonormal(N, M, 31 + c);
+    P0.insert(P0.end(), P.begin(), P.end());
+  }
+  Block Psi(P0, prec), gPsi(std::vector<double>(P0.size()), prec);
+  std::vector<double> eps((size_t)nspin * N);
+  for (int c = 0; c < nspin; ++c)
+    for (int i = 0; i < N; ++i) eps[(size_t)c * N + i] = -1.0 + 1.5 * i / N + 0.001 * c;
+  lrdm_occ occ{nspin, 0.03, 0.7 * N};
+  auto dV = randv((size_t)r * nspin * M, 41);
+  auto G = randv((size_t)r * nspin * M, 43);
+  std::vector<double> gdV(dV.size()), geps((size_t)nspin * N), ref(dV.size()), mu(1), dmu(r);
+  char name[128];
+  std::snprintf(name, sizeof name, "density_response_backward %s N=%d nspin=%d r=%d grid %dx%dx%d",
+                prec_name(prec), N, nspin, r, g.n[0], g.n[1], g.n[2]);
+  check(density_response_backward(ctx, &g, Psi.data(), eps.data(), N, &occ, dV.data(), r, prec,
+                                  G.data(), gdV.data(), gPsi.data(), geps.data()), ctx, name);
+  if (!finite(gdV) || !finite(geps) || !finite(gPsi.values())) {
+    std::printf("FAIL non-finite gradient\n");
+    ++failures;
+  }
+  check(density_response(ctx, &g, Psi.data(), eps.data(), N, &occ, G.data(), r, prec, ref.data(),
+                         mu.data(), dmu.data()), ctx, "density_response of g");
+  double num = 0, den = 0;
+  for (size_t i = 0; i < ref.size(); ++i) {
+    num += (gdV[i] - ref[i]) * (gdV[i] - ref[i]);
+    den += ref[i] * ref[i];
+  }
+  const double err = std::sqrt(num / den);
+  std::printf("     self-adjointness %.2e\n", err);
+  if (!(err < (prec == LRDM_FP64 ? 1e-12 : 1e-5))) ++failures;
+}
+
 }  // namespace
 
 int main(int argc, char** argv) {
@@ -240,6 +278,12 @@ int main(int argc, char** argv) {
     scenario_response(ctx, grid(7, 9, 11, 0.5), 70, 2, 1, LRDM_FP32);
     scenario_chfsi(ctx, grid(10, 9, 8, 0.45), 150, 5, LRDM_FP32);
     scenario_chfsi(ctx, grid(12, 12, 12, 0.45), 130, 4, LRDM_BF16X3);
+  }
+  if (which == "all" || which == "adj") {
+    scenario_backward(ctx, grid(20, 18, 13, 0.4), 150, 1, 2, LRDM_FP64);
+    scenario_backward(ctx, grid(9, 8, 7, 0.5), 40, 2, 2, LRDM_FP64);
+    scenario_backward(ctx, grid(20, 18, 13, 0.4), 150, 1, 2, LRDM_BF16X3);
+    scenario_backward(ctx, grid(7, 9, 11, 0.5), 70, 2, 1, LRDM_FP32);
   }
   if (which == "pp") {
     scenario_projection(ctx, grid(8, 8, 8, 0.5), 40, 1, LRDM_FP32);

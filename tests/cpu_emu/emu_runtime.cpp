@@ -1,6 +1,17 @@
 // Fiber runtime of the test-only CPU build of the kernels (x86-64 SysV).
 #include <sanitizer/common_interface_defs.h>
 
+// Fiber annotations for AddressSanitizer; weak, so that the build without the
+// sanitizer (a shared library for numerical checks) links and skips them.
+extern "C" {
+__attribute__((weak)) void __sanitizer_start_switch_fiber(void**, const void*, size_t);
+__attribute__((weak)) void __sanitizer_finish_switch_fiber(void*, const void**, size_t*);
+}
+#define ASAN_START(a, b, c) \
+  do { if (&__sanitizer_start_switch_fiber) __sanitizer_start_switch_fiber(a, b, c); } while (0)
+#define ASAN_FINISH(a, b, c) \
+  do { if (&__sanitizer_finish_switch_fiber) __sanitizer_finish_switch_fiber(a, b, c); } while (0)
+
 #include "hip/hip_runtime.h"
 
 thread_local uint3 threadIdx;
@@ -50,16 +61,16 @@ thread_local StackPool pool;
 
 void to_scheduler() {
   void* fake = nullptr;
-  __sanitizer_start_switch_fiber(&fake, cur->sched_stack_bottom, cur->sched_stack_size);
+  ASAN_START(&fake, cur->sched_stack_bottom, cur->sched_stack_size);
   lrdm_emu_switch(&cur_fiber->sp, cur->sched_sp);
-  __sanitizer_finish_switch_fiber(fake, nullptr, nullptr);
+  ASAN_FINISH(fake, nullptr, nullptr);
 }
 
 [[noreturn]] void fiber_entry() {
-  __sanitizer_finish_switch_fiber(nullptr, nullptr, nullptr);
+  ASAN_FINISH(nullptr, nullptr, nullptr);
   cur->body();
   cur_fiber->done = true;
-  __sanitizer_start_switch_fiber(nullptr, cur->sched_stack_bottom, cur->sched_stack_size);
+  ASAN_START(nullptr, cur->sched_stack_bottom, cur->sched_stack_size);
   lrdm_emu_switch(&cur_fiber->sp, cur->sched_sp);
   std::abort();
 }
@@ -69,9 +80,9 @@ void resume(Block& b, Fiber& f) {
   tid_linear = f.tid;
   threadIdx = f.idx;
   void* fake = nullptr;
-  __sanitizer_start_switch_fiber(&fake, f.stack, kStack);
+  ASAN_START(&fake, f.stack, kStack);
   lrdm_emu_switch(&b.sched_sp, f.sp);
-  __sanitizer_finish_switch_fiber(fake, &b.sched_stack_bottom, &b.sched_stack_size);
+  ASAN_FINISH(fake, &b.sched_stack_bottom, &b.sched_stack_size);
 }
 }  // namespace
 
