@@ -199,6 +199,32 @@ lrdm_status lrdm_residual_derivative(lrdm_ctx* ctx, const lrdm_grid* grid, const
                                      const double* eps, int32_t N, const lrdm_occ* occ,
                                      const double* u, int32_t r, lrdm_prec prec, double* t);
 
+/* One system of a batched call: the arguments of density_response. */
+typedef struct {
+  lrdm_grid grid;
+  const void* Psi;      /* [nspin][N][M], double (LRDM_FP64) or float */
+  const double* eps;    /* [nspin][N] */
+  int32_t N;
+  lrdm_occ occ;
+  const double* dV;     /* [r][nspin][M] */
+  int32_t r;
+  double* drho;         /* [r][nspin][M], out */
+  double* mu;           /* [1], out, may be NULL */
+  double* dmu;          /* [r], out, may be NULL */
+} lrdm_system;
+
+/* density_response for nsys independent systems of any sizes (uneven grids,
+ * subspaces, spin settings and ranks) in one call.  The systems are issued
+ * round-robin on four streams owned by the context, forked from and joined back
+ * to the context's stream, so they run concurrently; a caller that captures the
+ * context's stream into a HIP graph gets the whole batch as one graph.  The
+ * workspace (one region per system) must already be large enough when the call
+ * is captured: make the same call once before capturing, else LRDM_ENOMEM.
+ * Every system is validated as in density_response before anything is
+ * launched; outputs of different systems must not overlap. */
+lrdm_status density_response_batched(lrdm_ctx* ctx, const lrdm_system* sys, int32_t nsys,
+                                     lrdm_prec prec);
+
 /* Adjoint (vector-Jacobian product) of density_response: for a loss L with
  * g_drho = dL/d(delta rho) [r][nspin][M], returns
  *   g_dV  [r][nspin][M] double          dL/ddV  (the response to g_drho itself:

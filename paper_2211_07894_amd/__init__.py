@@ -20,5 +20,6 @@ from .lrdm import (  # noqa: F401
     density_response,
     residual_derivative,
     density_response_backward,
+    density_response_batched,
     DensityResponse,
 )

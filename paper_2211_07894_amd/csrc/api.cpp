@@ -103,6 +103,11 @@ Grid3 make_grid3(const lrdm_grid* g) {
 
 lrdm_status ws_reserve(lrdm_ctx* ctx, size_t bytes) {
   if (bytes <= ctx->ws_cap) return LRDM_OK;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(ctx->stream, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone)
+    return fail(ctx, LRDM_ENOMEM,
+                "the workspace would have to grow during stream capture: make the same call once "
+                "before capturing");
   if (ctx->limit && bytes > ctx->limit) {
     char msg[160];
     std::snprintf(msg, sizeof msg, "workspace of %zu bytes exceeds the context limit of %zu", bytes,
@@ -199,6 +204,24 @@ extern "C" lrdm_status lrdm_create(lrdm_ctx** ctx, int device, void* hip_stream,
     return fail_hip(nullptr, "hipMemset status", e);
   }
   c->zeros = reinterpret_cast<const float*>(c->dstatus + 32);
+  for (int k = 0; k < kAuxStreams; ++k) {
+    hipStream_t st = nullptr;
+    e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e != hipSuccess) break;
+    c->aux.push_back(st);
+  }
+  for (int k = 0; e == hipSuccess && k <= kAuxStreams; ++k) {
+    hipEvent_t ev = nullptr;
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) c->fork_join.push_back(ev);
+  }
+  if (e != hipSuccess) {
+    for (hipStream_t st : c->aux) (void)hipStreamDestroy(st);
+    for (hipEvent_t ev : c->fork_join) (void)hipEventDestroy(ev);
+    (void)hipFree(c->dstatus);
+    delete c;
+    return fail_hip(nullptr, "stream/event creation", e);
+  }
   *ctx = c;
   return LRDM_OK;
 }
@@ -207,6 +230,12 @@ extern "C" lrdm_status lrdm_destroy(lrdm_ctx* ctx) {
   if (!ctx) return fail(nullptr, LRDM_EINVAL, "ctx is NULL");
   (void)hipSetDevice(ctx->device);
   hipError_t e = hipStreamSynchronize(ctx->stream);
+  for (hipStream_t st : ctx->aux) {
+    const hipError_t ea = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = ea;
+    (void)hipStreamDestroy(st);
+  }
+  for (hipEvent_t ev : ctx->fork_join) (void)hipEventDestroy(ev);
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->dstatus) (void)hipFree(ctx->dstatus);
   for (const lrdm_prof_rec& r : ctx->prof) {
@@ -617,3 +646,56 @@ extern "C" lrdm_status density_response_backward(lrdm_ctx* ctx, const lrdm_grid*
     return e == hipSuccess ? LRDM_OK : fail_hip(ctx, "density_response_backward", e);
   });
 }
+
+extern "C" lrdm_status density_response_batched(lrdm_ctx* ctx, const lrdm_system* sys,
+                                                int32_t nsys, lrdm_prec prec) {
+  if (nsys < 1 || nsys > 4096) return fail(ctx, LRDM_EINVAL, "nsys must be in [1, 4096]");
+  LRDM_NONNULL(ctx, sys, "sys");
+  LRDM_CHECK(ctx, check_prec(prec));
+  size_t total = 0;
+  for (int s = 0; s < nsys; ++s) {
+    const lrdm_system& y = sys[s];
+    LRDM_CHECK(ctx, check_grid(&y.grid));
+    LRDM_CHECK(ctx, check_block(&y.grid, y.N));
+    LRDM_CHECK(ctx, check_occ(&y.occ, y.N));
+    LRDM_CHECK(ctx, check_rank(y.r));
+    LRDM_NONNULL(ctx, y.Psi, "sys[].Psi");
+    LRDM_NONNULL(ctx, y.eps, "sys[].eps");
+    LRDM_NONNULL(ctx, y.dV, "sys[].dV");
+    LRDM_NONNULL(ctx, y.drho, "sys[].drho");
+    total += ws_align(response_bytes(y.N, grid_points(&y.grid), y.r, y.occ.nspin, prec));
+  }
+  lrdm_status st = begin(ctx, total);
+  if (st != LRDM_OK) return st;
+  return guarded(ctx, [&]() -> lrdm_status {
+    const hipStream_t main = ctx->stream;
+    const int K = (int)ctx->aux.size();
+    hipError_t e = hipEventRecord(ctx->fork_join[0], main);
+    for (int k = 0; e == hipSuccess && k < K; ++k)
+      e = hipStreamWaitEvent(ctx->aux[k], ctx->fork_join[0], 0);
+    if (e != hipSuccess) return fail_hip(ctx, "batched fork", e);
+    struct Restore {              // ctx->stream is main again however the loop ends
+      lrdm_ctx* c;
+      hipStream_t s;
+      ~Restore() { c->stream = s; }
+    } restore{ctx, main};
+    for (int s = 0; s < nsys; ++s) {
+      const lrdm_system& y = sys[s];
+      const Grid3 g = make_grid3(&y.grid);
+      ctx->stream = ctx->aux[s % K];
+      e = (prec == LRDM_FP64)
+          ? run_response<double>(ctx, g, static_cast<const double*>(y.Psi), y.eps, y.N, &y.occ,
+                                 y.dV, y.r, prec, nullptr, y.drho, y.mu, y.dmu)
+          : run_response<float>(ctx, g, static_cast<const float*>(y.Psi), y.eps, y.N, &y.occ,
+                                y.dV, y.r, prec, nullptr, y.drho, y.mu, y.dmu);
+      ctx->stream = main;
+      if (e != hipSuccess) return fail_hip(ctx, "density_response_batched", e);
+    }
+    for (int k = 0; e == hipSuccess && k < K; ++k) {
+      e = hipEventRecord(ctx->fork_join[1 + k], ctx->aux[k]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(main, ctx->fork_join[1 + k], 0);
+    }
+    return e == hipSuccess ? LRDM_OK : fail_hip(ctx, "batched join", e);
+  });
+}
+

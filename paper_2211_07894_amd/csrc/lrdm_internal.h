@@ -30,7 +30,13 @@ struct lrdm_ctx {
   bool profiling = false;    // record hipEvents around the main kernels
   std::vector<lrdm_prof_rec> prof;
   std::vector<hipEvent_t> event_pool;
+  // streams and events of the batched entry point: systems are issued round-robin
+  // on the aux streams between a fork and a join on `stream`
+  std::vector<hipStream_t> aux;
+  std::vector<hipEvent_t> fork_join;   // [0] fork, [1 + k] join of aux[k]
 };
+
+constexpr int kAuxStreams = 4;
 
 // Device status word indices (checking mode).
 enum { LRDM_DS_BISECT = 0, LRDM_DS_EIGH = 1, LRDM_DS_NONFINITE = 2, LRDM_DS_COUNT = 4 };

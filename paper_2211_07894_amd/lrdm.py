@@ -29,7 +29,7 @@ EXPORTED = [
     "lrdm_last_error", "lrdm_hamiltonian_apply", "lrdm_fermi_occupations",
     "lrdm_projected_perturbation", "lrdm_hartree_kernel", "chfsi_filter",
     "subspace_rayleigh_ritz", "density_response", "lrdm_residual_derivative",
-    "density_response_backward",
+    "density_response_backward", "density_response_batched",
 ]
 
 
@@ -45,6 +45,13 @@ class c_grid(ctypes.Structure):
 
 class c_occ(ctypes.Structure):
     _fields_ = [("nspin", ctypes.c_int32), ("kT", ctypes.c_double), ("n_electrons", ctypes.c_double)]
+
+
+class c_system(ctypes.Structure):
+    _fields_ = [("grid", c_grid), ("Psi", ctypes.c_void_p), ("eps", ctypes.c_void_p),
+                ("N", ctypes.c_int32), ("occ", c_occ), ("dV", ctypes.c_void_p),
+                ("r", ctypes.c_int32), ("drho", ctypes.c_void_p), ("mu", ctypes.c_void_p),
+                ("dmu", ctypes.c_void_p)]
 
 
 @dataclass(frozen=True)
@@ -112,6 +119,7 @@ def library() -> ctypes.CDLL:
                 "lrdm_residual_derivative": [vp, G, vp, vp, i32, O, vp, i32, ctypes.c_int, vp],
                 "density_response_backward": [vp, G, vp, vp, i32, O, vp, i32, ctypes.c_int, vp,
                                               vp, vp, vp],
+                "density_response_batched": [vp, ctypes.POINTER(c_system), i32, ctypes.c_int],
             }
             for name, args in sig.items():
                 fn = getattr(lib, name)
@@ -365,6 +373,38 @@ def density_response_backward(grid: Grid, Psi, eps, occ: Occupation, dV, g_drho,
         _opt_ptr(g_Psi, "g_Psi", _block_dtype(prec), ns * N * grid.M),
         _opt_ptr(g_eps, "g_eps", torch.float64, ns * N)))
     return g_dV, g_Psi, g_eps
+
+
+def density_response_batched(systems, prec="fp32", outs=None):
+    """density_response for a list of independent systems in one call (see
+    density_response_batched in lrdm.h).  Each system is a dict with grid, Psi,
+    eps, occ and dV (as for density_response); returns one (drho, mu, dmu) per
+    system.  outs: optional list of preallocated (drho, mu, dmu)."""
+    if not systems:
+        raise ValueError("systems is empty")
+    dev = systems[0]["Psi"].device
+    arr = (c_system * len(systems))()
+    res = []
+    for k, sy in enumerate(systems):
+        grid, occ = sy["grid"], sy["occ"]
+        ns = occ.nspin
+        N = sy["eps"].numel() // ns
+        r = sy["dV"].numel() // (ns * grid.M)
+        if outs is None:
+            drho = torch.empty((r, ns) + grid.shape, dtype=torch.float64, device=dev)
+            mu = torch.empty(1, dtype=torch.float64, device=dev)
+            dmu = torch.empty(r, dtype=torch.float64, device=dev)
+        else:
+            drho, mu, dmu = outs[k]
+        arr[k] = c_system(grid.c(), _ptr(sy["Psi"], "Psi", _block_dtype(prec), ns * N * grid.M),
+                          _ptr(sy["eps"], "eps", torch.float64, ns * N), N, occ.c(),
+                          _ptr(sy["dV"], "dV", torch.float64, r * ns * grid.M), r,
+                          _ptr(drho, "drho", torch.float64, r * ns * grid.M),
+                          _ptr(mu, "mu", torch.float64, 1), _ptr(dmu, "dmu", torch.float64, r))
+        res.append((drho, mu, dmu))
+    ctx = context(dev.index)
+    ctx.check(ctx.lib.density_response_batched(ctx.ptr, arr, len(systems), _prec(prec)))
+    return res
 
 
 class DensityResponse(torch.autograd.Function):
