@@ -469,11 +469,15 @@ __global__ __launch_bounds__(256, 2) void adj_psi_f64_kernel(
 
 }  // namespace
 
-size_t tn_workspace_bytes(int N, int64_t M, int batch, lrdm_prec) {
+size_t tn_part_bytes(int N, int64_t M, int batch) {
   const int ntb = (N + BT - 1) / BT;
   const int ntiles = ntb * (ntb + 1) / 2;
   const int ns = tn_splits(ntiles * batch, M);
   return (size_t)batch * ns * ntiles * BT * BT * sizeof(double);
+}
+
+size_t tn_workspace_bytes(int N, int64_t M, int batch, lrdm_prec prec) {
+  return ws_align(tn_part_bytes(N, M, batch)) + tn_split_bytes(N, M, prec);
 }
 
 template <typename SA, typename SB>
@@ -485,7 +489,7 @@ hipError_t launch_tn_sym_f64(lrdm_ctx* ctx, const SA* A, const SB* B, const doub
   const int ns = tn_splits(ntiles * batch, M);
   int64_t kchunk = (M + ns - 1) / ns;
   kchunk = (kchunk + KT - 1) / KT * KT;
-  double* part = static_cast<double*>(ws_take(ctx, tn_workspace_bytes(N, M, batch, LRDM_FP64)));
+  double* part = static_cast<double*>(ws_take(ctx, tn_part_bytes(N, M, batch)));
   const unsigned grd = (unsigned)(ntiles * ns * batch);
   {
     ProfScope prof(ctx, w ? "proj" : "gram");

@@ -668,6 +668,339 @@ __global__ __launch_bounds__(256) void transpose_pad_kernel(const float* __restr
   }
 }
 
+// ================================================================== pre-split BF16X3
+// The exact three-piece split costs about as much VALU work as the six products,
+// and inside the kernels every wave repeats it for the fragments it shares with
+// other waves.  So the operands that carry no weight are split once per call
+// into three BF16 planes (x = hi + mid + lo), and the kernels read the pieces:
+// the back-projection reads pieces of both Gamma and Psi^T and splits nothing;
+// the projection carries the weight on its A side (H'_ij = sum_p (w_p Psi_ip)
+// Psi_jp), splits only that, and reads the pieces of Psi for B.
+//
+// A piece tile is 128 rows x 32 k of BF16 (64 bytes per row, four 16-byte
+// chunks); chunk q of row r sits in slot q ^ ((r >> 2) & 3), so the 16 rows that
+// one fragment read touches fall on distinct bank groups.
+constexpr int PB = BT * KT * 2;           // bytes of one piece tile (8 KB)
+
+// x -> three BF16 planes, rows of length ld: P[q][row][k] for q = hi, mid, lo.
+__global__ void split3_kernel(const float* __restrict__ X, int64_t n, __bf16* __restrict__ P) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float r = X[i];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const __bf16 h = (__bf16)r;
+    P[q * n + i] = h;
+    r -= (float)h;
+  }
+}
+
+// PT[c][q][p][j] = piece q of A[c][j][p] for j < N, 0 for N <= j < ldk.
+__global__ __launch_bounds__(256) void transpose_split3_kernel(const float* __restrict__ A,
+                                                              __bf16* __restrict__ PT, int N,
+                                                              int64_t M, int ldk) {
+  __shared__ float T[64][65];
+  const int c = blockIdx.z;
+  const float* Ac = A + (int64_t)c * N * M;
+  const int64_t plane = M * ldk;
+  __bf16* PTc = PT + (int64_t)c * 3 * plane;
+  const int64_t p0 = (int64_t)blockIdx.x * 64;
+  const int j0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int r = ty; r < 64; r += 4) {
+    const int j = j0 + r;
+    const int64_t p = p0 + tx;
+    T[r][tx] = (j < N && p < M) ? Ac[(int64_t)j * M + p] : 0.f;
+  }
+  __syncthreads();
+  for (int r = ty; r < 64; r += 4) {
+    const int64_t p = p0 + r;
+    const int j = j0 + tx;
+    if (p < M && j < ldk) {
+      float x = T[tx][r];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const __bf16 h = (__bf16)x;
+        PTc[q * plane + p * ldk + j] = h;
+        x -= (float)h;
+      }
+    }
+  }
+}
+
+// G3[b][q][i][j] = piece q of (float)G[b][i][j] for j < N, 0 for N <= j < ldk.
+__global__ void gamma_split3_kernel(const double* __restrict__ G, __bf16* __restrict__ G3, int N,
+                                    int ldk, int batch) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per = (int64_t)N * ldk;
+  if (idx >= (int64_t)batch * per) return;
+  const int64_t b = idx / per, rem = idx - b * per;
+  const int j = (int)(rem % ldk);
+  const int64_t i = rem / ldk;
+  float x = j < N ? (float)G[(b * N + i) * N + j] : 0.f;
+  __bf16* out = G3 + b * 3 * per + rem;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const __bf16 h = (__bf16)x;
+    out[q * per] = h;
+    x -= (float)h;
+  }
+}
+
+// This wave's share (one of eight copy instructions, 16 rows each) of a piece
+// tile: rows [r0, r0+BT) x k in [k0, k0+KT) of the row-major BF16 plane X
+// (row length ld); chunks with row >= nrows or k >= kend (a multiple of 8) read
+// zeros.
+__device__ inline void dma_piece(const __bf16* __restrict__ X, int64_t ld, int64_t nrows,
+                                 int64_t r0, int64_t k0, int64_t kend, const float* zeros,
+                                 unsigned char* tile, int wid, int lane) {
+  const int r = wid * 16 + (lane >> 2);
+  const int q = (lane & 3) ^ ((r >> 2) & 3);
+  const int64_t k = k0 + 8 * q;
+  const int64_t gr = r0 + r;
+  const void* src = (gr < nrows && k < kend) ? (const void*)(X + gr * ld + k) : (const void*)zeros;
+  dma16(src, tile + wid * 1024);
+}
+
+// Lane fragment of rows base + 16 i + lane%16, k = 8(lane/16) .. +7 of a piece tile.
+template <int NI>
+__device__ inline void frag_piece(const unsigned char* tile, int base, int lane, bf8 (&v)[NI]) {
+  const int r16 = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    const int R = base + 16 * i + r16;
+    v[i] = *reinterpret_cast<const bf8*>(tile + R * 64 + ((g ^ ((R >> 2) & 3)) * 16));
+  }
+}
+
+// The six products of order <= 2, smallest first.
+__device__ inline f4 mfma6(const bf8 (&a)[3], const bf8 (&b)[3], f4 c) {
+  c = mfma_bf16(a[0], b[2], c);
+  c = mfma_bf16(a[1], b[1], c);
+  c = mfma_bf16(a[2], b[0], c);
+  c = mfma_bf16(a[0], b[1], c);
+  c = mfma_bf16(a[1], b[0], c);
+  return mfma_bf16(a[0], b[0], c);
+}
+
+// Projection, BF16X3, pre-split B: H[b] = (w o A_c) B_c^T with A = B = Psi; A
+// FP32 tiles weighted and split in the kernel, B from the pieces P3
+// [nspin][3][N][M].  Same grid and partial layout as tn_sym_pipe_kernel; M a
+// multiple of 8, aligned rows.
+__global__ __launch_bounds__(PT, 1) void tn_sym_p3_kernel(
+    const float* __restrict__ A, const __bf16* __restrict__ P3, const double* __restrict__ w,
+    int64_t w_stride, int N, int64_t M, int nspin, int ntb, int64_t kchunk, int nsplit, int batch,
+    const float* __restrict__ zeros, double* __restrict__ part) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_pipe[];
+  constexpr int SB = TB + 3 * PB + 1024;   // A (FP32), B pieces, weights
+  const int ntiles = ntb * (ntb + 1) / 2;
+  int group, tile;
+  xcd_map(blockIdx.x, nsplit * batch, ntiles, group, tile);
+  const int sp = group % nsplit, b = group / nsplit;
+  int ti = 0, rem = tile;
+  while (rem >= ntb - ti) { rem -= ntb - ti; ++ti; }
+  const int tj = ti + rem;
+  const int c = b % nspin;
+  const float* Ac = A + (int64_t)c * N * M;
+  const __bf16* Pc = P3 + (int64_t)c * 3 * N * M;
+  const double* wb = w + (int64_t)b * w_stride;
+  const int64_t kbeg = (int64_t)sp * kchunk;
+  const int64_t kend = min(M, kbeg + kchunk);
+  const int nk = kbeg < kend ? (int)((kend - kbeg + KT - 1) / KT) : 0;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  // copies per stage and wave: 2 (A) + 3 (pieces of B), plus the weights in wave 0
+  auto issue = [&](int t) {
+    unsigned char* st = smem_pipe + (t % NST) * SB;
+    const int64_t k0 = kbeg + (int64_t)t * KT;
+    const int64_t ke = t < nk ? kend : k0;
+    dma_tile(Ac, M, N, (int64_t)ti * BT, k0, ke, zeros, st, wid, lane);
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      dma_piece(Pc + (int64_t)q * N * M, M, N, (int64_t)tj * BT, k0, ke, zeros,
+                st + TB + q * PB, wid, lane);
+    if (wid == 0) dma_weights(wb, k0, ke, zeros, st + TB + 3 * PB, lane);
+  };
+  double acc[2][4][4];
+  zero_pipe(acc);
+  issue(0);
+  issue(1);
+  for (int t = 0; t < nk; ++t) {
+    if (wid == 0) wait_stage<6>(); else wait_stage<5>();
+    const unsigned char* st = smem_pipe + (t % NST) * SB;
+    float a[2][8];
+    frag_sw<2>(st, wr * 32, lane, a);
+    bf8 pb[4][3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      bf8 v[4];
+      frag_piece<4>(st + TB + q * PB, wc * 64, lane, v);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) pb[j][q] = v[j];
+    }
+    float wf[8];
+    {
+      const int g = lane >> 4;
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const f4 x = *reinterpret_cast<const f4*>(st + TB + 3 * PB + (4 * g + h) * 16);
+        const d2v y = __builtin_bit_cast(d2v, x);
+        wf[2 * h] = (float)y[0];
+        wf[2 * h + 1] = (float)y[1];
+      }
+    }
+    compiler_fence();
+    issue(t + 2);
+    bf8 pa[2][3];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) a[i][e] *= wf[e];
+      split<3>(a[i], pa[i]);
+    }
+    f4 cc[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) cc[i][j] = mfma6(pa[i], pb[j], f4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[i][j][v] += (double)cc[i][j][v];
+  }
+  wait_stage<0>();
+  double* out = part + (((int64_t)b * nsplit + sp) * ntiles + tile) * (BT * BT);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = wr * 32 + i * 16 + 4 * (lane >> 4) + v;
+        const int col = wc * 64 + j * 16 + (lane & 15);
+        out[row * BT + col] = acc[i][j][v];
+      }
+}
+
+// Back-projection, BF16X3, both operands pre-split: G3 [batch][3][N][ldk] (FP32
+// rounding of Gamma, split), PT3 [nspin][3][M][ldk] (Psi^T split).  Otherwise as
+// backproj_pipe_kernel.
+__global__ __launch_bounds__(PT, 1) void backproj_p3_kernel(
+    const float* __restrict__ A, const __bf16* __restrict__ PT3, const __bf16* __restrict__ G3,
+    int N, int64_t M, int ldk, int nspin, int batch, double scale, const double* __restrict__ sub,
+    const float* __restrict__ zeros, double* __restrict__ out) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_pipe[];
+  constexpr int SB = 6 * PB;
+  double* red = reinterpret_cast<double*>(smem_pipe + NST * SB);   // [PW][64]
+  int pblk, b;
+  xcd_map(blockIdx.x, (int)((M + BT - 1) / BT), batch, pblk, b);
+  const int c = b % nspin;
+  const float* Ac = A + (int64_t)c * N * M;
+  const int64_t gplane = (int64_t)N * ldk, pplane = M * ldk;
+  const __bf16* Gb = G3 + (int64_t)b * 3 * gplane;
+  const __bf16* Pb = PT3 + (int64_t)c * 3 * pplane;
+  const int64_t p0 = (int64_t)pblk * BT;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  double dsum[4] = {0.0, 0.0, 0.0, 0.0};
+  const int nib = (N + BT - 1) / BT;
+  for (int ib = 0; ib < nib; ++ib) {
+    const int i0 = ib * BT;
+    const int nk = (N - i0 + KT - 1) / KT;
+    auto issue = [&](int t) {
+      unsigned char* st = smem_pipe + (t % NST) * SB;
+      const int64_t j0 = i0 + (int64_t)t * KT;
+      const int64_t je = t < nk ? ldk : j0;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        dma_piece(Gb + q * gplane, ldk, N, i0, j0, je, zeros, st + q * PB, wid, lane);
+        dma_piece(Pb + q * pplane, ldk, M, p0, j0, je, zeros, st + (3 + q) * PB, wid, lane);
+      }
+    };
+    double acc[2][4][4];
+    zero_pipe(acc);
+    issue(0);
+    issue(1);
+    for (int t = 0; t < nk; ++t) {
+      wait_stage<6>();
+      const unsigned char* st = smem_pipe + (t % NST) * SB;
+      bf8 pa[2][3], pb[4][3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        bf8 va[2], vb[4];
+        frag_piece<2>(st + q * PB, wr * 32, lane, va);
+        frag_piece<4>(st + (3 + q) * PB, wc * 64, lane, vb);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) pa[i][q] = va[i];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) pb[j][q] = vb[j];
+      }
+      compiler_fence();
+      issue(t + 2);
+      const double f = (t * KT >= BT) ? 2.0 : 1.0;
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const f4 cc = mfma6(pa[i], pb[j], f4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[i][j][v] += f * (double)cc[v];
+        }
+    }
+    wait_stage<0>();
+    float av[2][4][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gi = min(i0 + wr * 32 + i * 16 + 4 * (lane >> 4) + v, N - 1);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int64_t p = min(p0 + wc * 64 + j * 16 + (lane & 15), M - 1);
+          av[i][v][j] = Ac[(int64_t)gi * M + p];
+        }
+      }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gi = i0 + wr * 32 + i * 16 + 4 * (lane >> 4) + v;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int64_t p = p0 + wc * 64 + j * 16 + (lane & 15);
+          if (gi < N && p < M) dsum[j] += acc[i][j][v] * (double)av[i][v][j];
+        }
+      }
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    double v = dsum[j];
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    dsum[j] = v;
+  }
+  if (lane < 16) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) red[wid * 64 + j * 16 + lane] = dsum[j];
+  }
+  __syncthreads();
+  if (threadIdx.x < BT) {
+    const int col = threadIdx.x;
+    const int wcc = col >> 6, cl = col & 63;
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v += red[(2 * q + wcc) * 64 + cl];
+    const int64_t p = p0 + col;
+    if (p < M) {
+      double r = scale * v;
+      if (sub) r -= sub[(int64_t)b * M + p];
+      out[(int64_t)b * M + p] = r;
+    }
+  }
+}
+
 }  // namespace
 
 static int pad_k(int N) { return (N + KT - 1) / KT * KT; }
@@ -675,8 +1008,13 @@ static int pad_k(int N) { return (N + KT - 1) / KT * KT; }
 size_t backproj_workspace_bytes(int N, int64_t M, int nspin, int batch, lrdm_prec prec) {
   if (prec == LRDM_FP64) return 0;
   const size_t ldk = pad_k(N);
-  return ws_align((size_t)batch * N * ldk * sizeof(float)) +
-         ws_align((size_t)nspin * M * ldk * sizeof(float));
+  const size_t el = (prec == LRDM_BF16X3) ? 3 * sizeof(__bf16) : sizeof(float);
+  return ws_align((size_t)batch * N * ldk * el) + ws_align((size_t)nspin * M * ldk * el);
+}
+
+// Pieces of Psi for the pre-split projection (nspin <= 2).
+size_t tn_split_bytes(int N, int64_t M, lrdm_prec prec) {
+  return prec == LRDM_BF16X3 ? ws_align((size_t)2 * 3 * N * M * sizeof(__bf16)) : 0;
 }
 
 template <>
@@ -690,12 +1028,35 @@ hipError_t launch_tn_sym<float>(lrdm_ctx* ctx, const float* A, const float* B, c
   const int ns = tn_splits(ntiles * batch, M);
   int64_t kchunk = (M + ns - 1) / ns;
   kchunk = (kchunk + KT - 1) / KT * KT;
-  double* part = static_cast<double*>(ws_take(ctx, tn_workspace_bytes(N, M, batch, prec)));
+  double* part = static_cast<double*>(ws_take(ctx, tn_part_bytes(N, M, batch)));
   if (!B) B = A;
   auto a16 = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
   // the pipelined kernel copies 16-byte chunks of rows: rows must start aligned
   const bool pipe = (M % 4 == 0) && a16(A) && a16(B) && (!w || (a16(w) && w_stride % 2 == 0));
   const unsigned grd = (unsigned)(ntiles * ns * batch);
+  if (pipe && w && B == A && prec == LRDM_BF16X3 && M % 8 == 0 && nspin <= 2) {
+    // pieces of Psi once per call, then the weighted A side split in the kernel
+    __bf16* P3 = static_cast<__bf16*>(ws_take(ctx, tn_split_bytes(N, M, prec)));
+    const int64_t n = (int64_t)N * M;
+    for (int c = 0; c < nspin; ++c) {
+      split3_kernel<<<(unsigned)((n + 255) / 256), 256, 0, ctx->stream>>>(A + c * n, n,
+                                                                          P3 + c * 3 * n);
+      LRDM_HIP(hipGetLastError());
+    }
+    const int smem = NST * (TB + 3 * PB + 1024);
+    LRDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&tn_sym_p3_kernel),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, smem));
+    {
+      ProfScope prof(ctx, "proj");
+      tn_sym_p3_kernel<<<grd, PT, smem, ctx->stream>>>(A, P3, w, w_stride, N, M, nspin, ntb,
+                                                       kchunk, ns, batch, ctx->zeros, part);
+      LRDM_HIP(hipGetLastError());
+    }
+    dim3 blk(32, 8);
+    dim3 grd2((N + 31) / 32, (N + 7) / 8, batch);
+    tn_reduce_lp_kernel<<<grd2, blk, 0, ctx->stream>>>(part, N, ntb, ns, H);
+    return hipGetLastError();
+  }
   const int smem = NST * (2 * TB + (w ? 1024 : 0));
   auto run_pipe = [&](auto kernel) -> hipError_t {
     LRDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
@@ -732,28 +1093,38 @@ hipError_t launch_backproj<float>(lrdm_ctx* ctx, const float* A, const double* G
                                   int64_t M, int nspin, int batch, lrdm_prec prec, double scale,
                                   const double* sub, double* out) {
   const int ldk = pad_k(N);
+  const unsigned grd = (unsigned)((M + BT - 1) / BT * batch);
+  dim3 gt((unsigned)((M + 63) / 64), (unsigned)(ldk / 64 + (ldk % 64 ? 1 : 0)), nspin);
+  if (prec == LRDM_BF16X3) {
+    const int64_t nG = (int64_t)batch * N * ldk;
+    __bf16* G3 = static_cast<__bf16*>(ws_take(ctx, (size_t)nG * 3 * sizeof(__bf16)));
+    __bf16* PT3 = static_cast<__bf16*>(ws_take(ctx, (size_t)nspin * M * ldk * 3 * sizeof(__bf16)));
+    gamma_split3_kernel<<<(unsigned)((nG + 255) / 256), 256, 0, ctx->stream>>>(G, G3, N, ldk,
+                                                                              batch);
+    LRDM_HIP(hipGetLastError());
+    transpose_split3_kernel<<<gt, 256, 0, ctx->stream>>>(A, PT3, N, M, ldk);
+    LRDM_HIP(hipGetLastError());
+    const int smem = NST * 6 * PB + PW * 64 * (int)sizeof(double);
+    LRDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&backproj_p3_kernel),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, smem));
+    ProfScope prof(ctx, "backproj");
+    backproj_p3_kernel<<<grd, PT, smem, ctx->stream>>>(A, PT3, G3, N, M, ldk, nspin, batch, scale,
+                                                       sub, ctx->zeros, out);
+    return hipGetLastError();
+  }
   float* Gf = static_cast<float*>(ws_take(ctx, (size_t)batch * N * ldk * sizeof(float)));
   float* AT = static_cast<float*>(ws_take(ctx, (size_t)nspin * M * ldk * sizeof(float)));
   const int64_t nG = (int64_t)batch * N * ldk;
   gamma_pad_kernel<<<(unsigned)((nG + 255) / 256), 256, 0, ctx->stream>>>(G, Gf, N, ldk, batch);
   LRDM_HIP(hipGetLastError());
-  dim3 gt((unsigned)((M + 63) / 64), (unsigned)(ldk / 64 + (ldk % 64 ? 1 : 0)), nspin);
   transpose_pad_kernel<<<gt, 256, 0, ctx->stream>>>(A, AT, N, M, ldk);
   LRDM_HIP(hipGetLastError());
-  const unsigned grd = (unsigned)((M + BT - 1) / BT * batch);
   const int smem = NST * 2 * TB + PW * 64 * (int)sizeof(double);
+  LRDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&backproj_pipe_kernel<Core::F32>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, smem));
   ProfScope prof(ctx, "backproj");
-  if (prec == LRDM_BF16X3) {
-    LRDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&backproj_pipe_kernel<Core::BF3>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, smem));
-    backproj_pipe_kernel<Core::BF3><<<grd, PT, smem, ctx->stream>>>(
-        A, AT, Gf, N, M, ldk, nspin, batch, scale, sub, ctx->zeros, out);
-  } else {
-    LRDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&backproj_pipe_kernel<Core::F32>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, smem));
-    backproj_pipe_kernel<Core::F32><<<grd, PT, smem, ctx->stream>>>(
-        A, AT, Gf, N, M, ldk, nspin, batch, scale, sub, ctx->zeros, out);
-  }
+  backproj_pipe_kernel<Core::F32><<<grd, PT, smem, ctx->stream>>>(
+      A, AT, Gf, N, M, ldk, nspin, batch, scale, sub, ctx->zeros, out);
   return hipGetLastError();
 }
 

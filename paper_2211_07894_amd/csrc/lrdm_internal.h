@@ -96,6 +96,8 @@ hipError_t launch_fermi(lrdm_ctx* ctx, const double* eps, int N, int nspin, doub
 // symmetric).  B == nullptr means B = A; w == nullptr means w = 1.
 // A, B: nspin blocks of [N][M].
 size_t tn_workspace_bytes(int N, int64_t M, int batch, lrdm_prec prec);
+size_t tn_split_bytes(int N, int64_t M, lrdm_prec prec);
+size_t tn_part_bytes(int N, int64_t M, int batch);
 // Split count of the K = M contraction: enough blocks to fill 256 CUs several
 // times over, with each split at least 4096 grid points long.
 inline int tn_splits(int tiles_x_batch, int64_t M) {

@@ -30,9 +30,12 @@ KERNELS = {
     "fp64": {"proj": (r"tn_sym_f64_kernel<double, double>", "gemm.hip"),
              "backproj": (r"backproj_f64_kernel", "gemm.hip"),
              "cheb_step": (r"cheb_plane_kernel<double, double", "stencil.hip")},
-    "lp": {"proj": (r"tn_sym_pipe_kernel<.*true>", "gemm_lp.hip"),
-           "backproj": (r"backproj_pipe_kernel", "gemm_lp.hip"),
-           "cheb_step": (r"cheb_plane_kernel<float, float", "stencil.hip")},
+    "fp32": {"proj": (r"tn_sym_pipe_kernel<.*true>", "gemm_lp.hip"),
+             "backproj": (r"backproj_pipe_kernel", "gemm_lp.hip"),
+             "cheb_step": (r"cheb_plane_kernel<float, float", "stencil.hip")},
+    "bf16x3": {"proj": (r"tn_sym_p3_kernel|tn_sym_pipe_kernel<.*true>", "gemm_lp.hip"),
+               "backproj": (r"backproj_p3_kernel|backproj_pipe_kernel", "gemm_lp.hip"),
+               "cheb_step": (r"cheb_plane_kernel<float, float", "stencil.hip")},
 }
 CALIBRATION_BYTES = 1 << 30
 
@@ -106,7 +109,7 @@ def traffic(fetch_csv, write_csv, form, workload, command):
         kib = statistics.median(cal)
         factor = CALIBRATION_BYTES / (kib * 1024.0)   # true bytes per counted byte
         data[counter] = (disp, factor, kib)
-    table = KERNELS["fp64" if form == "fp64" else "lp"]
+    table = KERNELS[form]
     for scope, (pat, src) in table.items():
         per = {}
         for counter, (disp, factor, _) in data.items():
