@@ -34,7 +34,8 @@ constexpr int JB = 32;        // block width
 constexpr int JS = 64;        // pair problem size
 constexpr int JP = JS + 1;    // LDS pitch
 constexpr double kPad = 1e30; // diagonal of padding rows (decoupled, sorts last)
-constexpr int kNewtonSchulz = 28;  // fixed Newton-Schulz steps of the orthonormalisation
+constexpr int kNewtonSchulz = 28;  // at most this many Newton-Schulz steps
+constexpr double kNewtonSchulzTol = 1e-10;  // stop one step after ||W - I||_F < tol
 
 
 // --------------------------------------------------------------- reductions
@@ -310,15 +311,29 @@ __global__ void jac_gather_kernel(const double* __restrict__ A, const double* __
 // --------------------------------------------------------------- small FP64 GEMM
 // C[m x n] = alpha op(A) op(B) + beta C, op = transpose when the flag is set.
 // 64 x 64 tiles, 256 threads, 4 x 4 per thread, K steps of 16.
+// When *skip is set (skip may be null) the block does no product: it copies its
+// tile of copy_src (leading dimension ldc) into C, or leaves C alone when
+// copy_src is null.
 __global__ __launch_bounds__(256) void small_gemm_kernel(int ta, int tb, int m, int n, int k,
                                                          double alpha, const double* __restrict__ A,
                                                          int lda, const double* __restrict__ B,
                                                          int ldb, double beta,
-                                                         double* __restrict__ C, int ldc) {
+                                                         double* __restrict__ C, int ldc,
+                                                         const int* __restrict__ skip,
+                                                         const double* __restrict__ copy_src) {
   __shared__ double As[16][65];
   __shared__ double Bs[16][65];
   const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
   const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  if (skip && *skip) {
+    if (copy_src) {
+      for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int gi = i0 + (e >> 6), gj = j0 + (e & 63);
+        if (gi < m && gj < n) C[(int64_t)gi * ldc + gj] = copy_src[(int64_t)gi * ldc + gj];
+      }
+    }
+    return;
+  }
   double acc[4][4] = {};
   for (int k0 = 0; k0 < k; k0 += 16) {
     for (int e = threadIdx.x; e < 16 * 64; e += 256) {
@@ -362,10 +377,10 @@ __global__ __launch_bounds__(256) void small_gemm_kernel(int ta, int tb, int m, 
 
 hipError_t small_gemm(lrdm_ctx* ctx, bool ta, bool tb, int m, int n, int k, double alpha,
                       const double* A, int lda, const double* B, int ldb, double beta, double* C,
-                      int ldc) {
+                      int ldc, const int* skip = nullptr, const double* copy_src = nullptr) {
   dim3 grd((n + 63) / 64, (m + 63) / 64);
   small_gemm_kernel<<<grd, 256, 0, ctx->stream>>>(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta,
-                                                  C, ldc);
+                                                  C, ldc, skip, copy_src);
   return hipGetLastError();
 }
 
@@ -396,11 +411,54 @@ __global__ void ns_start_kernel(const double* __restrict__ Gs, const double* __r
 }
 
 // T = (3 I - W) / 2
-__global__ void ns_step_kernel(const double* __restrict__ W, int N, double* __restrict__ T) {
+// T = (3I - W)/2 and, per block, the partial sum of (W - I)^2 (blockDim 32 x 8);
+// nothing once the iteration has stopped.
+__global__ __launch_bounds__(256) void ns_step_kernel(const double* __restrict__ W, int N,
+                                                      double* __restrict__ T,
+                                                      const int* __restrict__ stop,
+                                                      double* __restrict__ part) {
+  __shared__ double red[4];
+  if (*stop) return;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y * blockDim.y + threadIdx.y;
-  if (i >= N || j >= N) return;
-  T[(int64_t)i * N + j] = (i == j ? 1.5 : 0.0) - 0.5 * W[(int64_t)i * N + j];
+  double d2 = 0.0;
+  if (i < N && j < N) {
+    const double w = W[(int64_t)i * N + j];
+    const double d = w - (i == j ? 1.0 : 0.0);
+    d2 = d * d;
+    T[(int64_t)i * N + j] = (i == j ? 1.5 : 0.0) - 0.5 * w;
+  }
+  const int t = threadIdx.y * blockDim.x + threadIdx.x;
+  for (int off = 32; off > 0; off >>= 1) d2 += __shfl_down(d2, off, 64);
+  if ((t & 63) == 0) red[t >> 6] = d2;
+  __syncthreads();
+  if (t == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// pending = 1 once ||W - I||_F < tol (fixed-order sum of the partials); the step
+// that detected it still updates Y and Z, and the following ones copy.
+__global__ __launch_bounds__(256) void ns_check_kernel(const double* __restrict__ part, int n,
+                                                       double tol, const int* __restrict__ stop,
+                                                       int* __restrict__ pending) {
+  __shared__ double red[4];
+  if (*stop) return;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += part[i];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0 && red[0] + red[1] + red[2] + red[3] < tol * tol) *pending = 1;
+}
+
+__global__ void ns_flags_kernel(int* __restrict__ stop, int* __restrict__ pending, int reset) {
+  if (threadIdx.x == 0) {
+    if (reset) {
+      *stop = 0;
+      *pending = 0;
+    } else if (*pending) {
+      *stop = 1;
+    }
+  }
 }
 
 // Tm[i][j] = Z[i][j] dinv[j] / sqrt(||Gs||_F): Gs^{-1/2} D, orthonormal rows Tm Y.
@@ -481,6 +539,10 @@ lrdm_status sym_eigh(lrdm_ctx* ctx, const double* S, int lda, int N, const doubl
   return LRDM_OK;
 }
 
+size_t ns_part_bytes(int N) {
+  return (size_t)((N + 31) / 32) * ((N + 7) / 8) * sizeof(double);
+}
+
 size_t rr_workspace_bytes(int N, int64_t M, lrdm_prec prec) {
   const int Np = ((N + JS - 1) / JS) * JS;
   const int nb = Np / JB;
@@ -489,6 +551,7 @@ size_t rr_workspace_bytes(int N, int64_t M, lrdm_prec prec) {
   b += 6 * ws_align((size_t)N * N * sizeof(double));         // G, Hy, T, C, X, Wt
   b += 2 * ws_align((size_t)N * sizeof(double));             // dinv, lam
   b += ws_align(kFrobBlocks * sizeof(double));               // norm partial sums
+  b += ws_align(ns_part_bytes(N));                           // Newton-Schulz residuals
   // eigensolver
   b += 2 * ws_align((size_t)Np * Np * sizeof(double)) + ws_align((size_t)(nb / 2) * JS * JS * 8) +
        ws_align(256) + ws_align((size_t)Np * 4) + ws_align(kFrobBlocks * sizeof(double));
@@ -514,6 +577,9 @@ lrdm_status rayleigh_ritz(lrdm_ctx* ctx, const Grid3& g, const double* V, T* Psi
   double* dinv = static_cast<double*>(ws_take(ctx, (size_t)N * sizeof(double)));
   double* lam = static_cast<double*>(ws_take(ctx, (size_t)N * sizeof(double)));
   double* fpart = static_cast<double*>(ws_take(ctx, kFrobBlocks * sizeof(double)));
+  double* ns_part = static_cast<double*>(ws_take(ctx, ns_part_bytes(N)));
+  int* ns_stop = ctx->dstatus + LRDM_DS_COUNT + 1;     // scratch words after the status
+  int* ns_pending = ctx->dstatus + LRDM_DS_COUNT + 2;  // words (the zero page starts at 32)
   hipError_t e;
   auto fail = [&](const char* what, hipError_t err) {
     ctx->err = std::string("rayleigh_ritz: ") + what + ": " + hipGetErrorString(err);
@@ -534,9 +600,10 @@ lrdm_status rayleigh_ritz(lrdm_ctx* ctx, const Grid3& g, const double* V, T* Psi
   if ((e = hipGetLastError()) != hipSuccess) return fail("scale", e);
   // Loewdin factor Gs^{-1/2} by the coupled Newton-Schulz iteration
   //   W = Z Y, T = (3I - W)/2, Y <- Y T, Z <- T Z   (Y -> Gs'^{1/2}, Z -> Gs'^{-1/2})
-  // on Gs' = Gs / ||Gs||_F, whose spectrum lies in (0, 1].  A fixed count of
-  // kNewtonSchulz steps: a warm-started block needs about 10, a cold one with
-  // cond(Gs) up to ~1e6 about 24; steps past convergence leave the fixed point.
+  // on Gs' = Gs / ||Gs||_F, whose spectrum lies in (0, 1].  At most
+  // kNewtonSchulz steps (a cold block with cond(Gs) up to ~1e6 needs about 24); the
+  // device stops the iteration one step after ||W - I||_F < kNewtonSchulzTol, and
+  // the remaining launches only copy Y and Z, with no host read-back.
   double* Ya = X;
   double* Za = C;
   double* Yb = Hy;
@@ -549,14 +616,22 @@ lrdm_status rayleigh_ritz(lrdm_ctx* ctx, const Grid3& g, const double* V, T* Psi
     gram_scale_kernel<<<grd, blk, 0, ctx->stream>>>(G, dinv, N, Tm);
     if ((e = frob(ctx, Tm, N, N, fpart, fro)) != hipSuccess) return fail("scale", e);
     ns_start_kernel<<<grd, blk, 0, ctx->stream>>>(Tm, fro, N, Ya, Za);
+    ns_flags_kernel<<<1, 64, 0, ctx->stream>>>(ns_stop, ns_pending, 1);
     if ((e = hipGetLastError()) != hipSuccess) return fail("scale", e);
+    const int nparts = (int)(grd.x * grd.y);
     for (int it = 0; it < kNewtonSchulz; ++it) {
-      if ((e = small_gemm(ctx, false, false, N, N, N, 1.0, Za, N, Ya, N, 0.0, W, N)) != hipSuccess)
+      if ((e = small_gemm(ctx, false, false, N, N, N, 1.0, Za, N, Ya, N, 0.0, W, N, ns_stop)) !=
+          hipSuccess)
         return fail("newton-schulz", e);
-      ns_step_kernel<<<grd, blk, 0, ctx->stream>>>(W, N, Tn);
-      if ((e = small_gemm(ctx, false, false, N, N, N, 1.0, Ya, N, Tn, N, 0.0, Yb, N)) != hipSuccess ||
-          (e = small_gemm(ctx, false, false, N, N, N, 1.0, Tn, N, Za, N, 0.0, Zb, N)) != hipSuccess)
+      ns_step_kernel<<<grd, blk, 0, ctx->stream>>>(W, N, Tn, ns_stop, ns_part);
+      ns_check_kernel<<<1, 256, 0, ctx->stream>>>(ns_part, nparts, kNewtonSchulzTol, ns_stop,
+                                                  ns_pending);
+      if ((e = small_gemm(ctx, false, false, N, N, N, 1.0, Ya, N, Tn, N, 0.0, Yb, N, ns_stop,
+                          Ya)) != hipSuccess ||
+          (e = small_gemm(ctx, false, false, N, N, N, 1.0, Tn, N, Za, N, 0.0, Zb, N, ns_stop,
+                          Za)) != hipSuccess)
         return fail("newton-schulz", e);
+      ns_flags_kernel<<<1, 64, 0, ctx->stream>>>(ns_stop, ns_pending, 0);
       std::swap(Ya, Yb);
       std::swap(Za, Zb);
     }
