@@ -151,6 +151,19 @@ hipError_t launch_adj_eps(lrdm_ctx* ctx, const double* A, const double* Hp, cons
                           const double* dmu, const double* nu, int N, int nspin, int r, double kT,
                           double* part, double* g_eps);
 
+// Orthonormalising factor of a Gram matrix G = Y Y^T (chol.hip): T (N x N) with the
+// first `live` rows of T Y orthonormal and the others the explicit residuals of the
+// dependent rows of Y (Schur-complement pivot below tau after unit-diagonal
+// scaling) against the independent ones before them; cond estimates the condition
+// number of the scaled Gram matrix.
+struct CholInfo {
+  int live;
+  double cond;
+};
+lrdm_status chol_orth(lrdm_ctx* ctx, const double* G, int N, double tau, double* T,
+                      CholInfo* info);
+size_t chol_orth_bytes(int N);
+
 // Rayleigh-Ritz pieces (rr.hip).
 // Eigenpairs of a symmetric N x N matrix (FP64, block Jacobi on the GPU).
 lrdm_status sym_eigh(lrdm_ctx* ctx, const double* S, int lda, int N, const double* dinv,

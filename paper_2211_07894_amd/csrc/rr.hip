@@ -1,14 +1,14 @@
 // Rayleigh-Ritz step of ChFSI (Sec. II C, Eq. (15)) and the FP64 symmetric
 // eigensolver it needs, both on the GPU.
 //
-// Orthonormalisation: with the filtered block Y (rows = vectors) and
-// G = Y Y^T = D^{-1} Gs D^{-1} (D^{-1} = diag of row norms), the symmetric
-// (Loewdin) factor T = Gs^{-1/2} D, from a coupled Newton-Schulz iteration,
-// gives orthonormal rows Psi_o = T Y.  The projected Hamiltonian is Hhat = T (Y (H Y)^T) T^T, its
-// eigenpairs Hhat = Q E Q^T give eps = E and Psi_R = Q^T T Y: one pass over the
-// grid for Gram, one stencil pass, one pass for Y (HY)^T and one rotation pass.
-// Column scaling makes a warm-started block (Y ~ eigenvectors times filter
-// gains) well conditioned, which is the regime of ChFSI inside an SCF loop.
+// Orthonormalisation: column-scaled Cholesky QR of the filtered block Y (rows =
+// vectors), with rank detection (chol.hip).  After a high-degree filter the rows'
+// norms span many orders of magnitude and the top states of a cold block can be
+// swamped by the lower ones; such rows are numerically dependent on the rest and
+// are replaced by fixed pseudo-random rows, which a second Cholesky pass makes
+// orthonormal to the others.  A warm-started block is well conditioned after the
+// column scaling and takes one pass: one grid pass for the Gram matrix, one stencil
+// pass, one pass for Y (HY)^T and one rotation pass.
 //
 // Eigensolver: two-sided block Jacobi.  The matrix (padded to a multiple of 64
 // with decoupled diagonal entries 1e30) is cut into 32-wide blocks; each outer
@@ -18,12 +18,13 @@
 // t = sign(z)/(|z| + sqrt(1 + z^2)), z = (a_qq - a_pp)/(2 a_pq)); a second kernel
 // applies the pair rotations to A and to the eigenvector matrix as 64 x 64 GEMMs.
 // Rotations are applied above 1e-16 ||A||_F; sweeps stop when an outer sweep
-// meets no off-diagonal entry above 1e-13 ||A||_F (one host read of a device
-// flag per sweep), about ten times the rounding left by the 64-wide rotation
-// updates, so the stop is reachable.
+// leaves no off-diagonal entry above 1e-13 ||A||_F (a reduction after the sweep
+// and one host read of its flag), about ten times the rounding left by the
+// 64-wide rotation updates, so the stop is reachable.
 #include "lrdm_internal.h"
 #include "jacobi_order.h"
 
+#include <algorithm>
 #include <utility>
 #include <vector>
 
@@ -34,8 +35,9 @@ constexpr int JB = 32;        // block width
 constexpr int JS = 64;        // pair problem size
 constexpr int JP = JS + 1;    // LDS pitch
 constexpr double kPad = 1e30; // diagonal of padding rows (decoupled, sorts last)
-constexpr int kNewtonSchulz = 28;  // at most this many Newton-Schulz steps
-constexpr double kNewtonSchulzTol = 1e-10;  // stop one step after ||W - I||_F < tol
+constexpr double kDependentTol = 1e-10;  // Schur pivot (unit diagonal) of a dependent row
+constexpr double kOnePassCond = 1e3;     // one Cholesky pass when cond(Gs) is below this
+constexpr int kMaxOrthPasses = 5;        // Cholesky passes before giving up
 
 
 // --------------------------------------------------------------- reductions
@@ -81,8 +83,7 @@ hipError_t frob(lrdm_ctx* ctx, const double* A, int N, int lda, double* part, do
 __global__ __launch_bounds__(1024) void jac_solve_kernel(const double* __restrict__ A, int Np,
                                                         int nb, int t,
                                                         const double* __restrict__ normF_ptr,
-                                                        double* __restrict__ Ublk,
-                                                        int* __restrict__ flag, int max_inner) {
+                                                        double* __restrict__ Ublk, int max_inner) {
   __shared__ double S[JS * JP];
   __shared__ double U[JS * JP];
   __shared__ double rc[JB], rs[JB], rt[JB];
@@ -99,7 +100,6 @@ __global__ __launch_bounds__(1024) void jac_solve_kernel(const double* __restric
   }
   const double normF = *normF_ptr;
   const double thr_apply = 1e-16 * normF, thr_flag = 1e-13 * normF;
-  int first_rot = 0;
   __syncthreads();
   for (int sw = 0; sw < max_inner; ++sw) {
     if (threadIdx.x == 0) any_rot = 0;
@@ -163,7 +163,6 @@ __global__ __launch_bounds__(1024) void jac_solve_kernel(const double* __restric
       __syncthreads();
     }
     const int rot = any_rot;
-    if (sw == 0) first_rot = rot;
     __syncthreads();
     if (!rot) break;
   }
@@ -172,7 +171,19 @@ __global__ __launch_bounds__(1024) void jac_solve_kernel(const double* __restric
     const int a = e / JS, c = e - a * JS;
     Ub[e] = U[a * JP + c];
   }
-  if (threadIdx.x == 0 && first_rot) atomicOr(flag, 1);
+}
+
+// *flag = 1 when an off-diagonal entry of the leading N x N block exceeds
+// 1e-13 ||A||_F (blocks stride over rows; any thread that sees one stores 1).
+__global__ __launch_bounds__(256) void jac_offmax_kernel(const double* __restrict__ A, int Np,
+                                                         int N, const double* __restrict__ normF,
+                                                         int* __restrict__ flag) {
+  const double thr = 1e-13 * *normF;
+  bool big = false;
+  for (int i = blockIdx.x; i < N; i += gridDim.x)
+    for (int j = threadIdx.x; j < N; j += blockDim.x)
+      big |= (j != i) && fabs(A[(int64_t)i * Np + j]) > thr;
+  if (big) *flag = 1;
 }
 
 // 64x64x64 product C = op(X) Y with X, Y, C in LDS (pitch JP); thread (tr, tc)
@@ -385,89 +396,32 @@ hipError_t small_gemm(lrdm_ctx* ctx, bool ta, bool tb, int m, int n, int k, doub
 }
 
 // --------------------------------------------------------------- RR helpers
-__global__ void diag_rsqrt_kernel(const double* __restrict__ G, int N, double* __restrict__ dinv) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < N) dinv[i] = 1.0 / sqrt(G[(int64_t)i * N + i]);
-}
-
-
-// Gs = D G D (symmetrised), D = diag(dinv): the column-scaled Gram matrix.
-__global__ void gram_scale_kernel(const double* __restrict__ G, const double* __restrict__ dinv,
-                                  int N, double* __restrict__ Gs) {
+// Wt = T^T (N x N).
+__global__ void transpose_kernel(const double* __restrict__ T, int N, double* __restrict__ Wt) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y * blockDim.y + threadIdx.y;
-  if (i >= N || j >= N) return;
-  Gs[(int64_t)i * N + j] = 0.5 * (G[(int64_t)i * N + j] + G[(int64_t)j * N + i]) * dinv[i] * dinv[j];
+  if (i < N && j < N) Wt[(int64_t)j * N + i] = T[(int64_t)i * N + j];
 }
 
-// Y0 = Gs / ||Gs||_F (spectrum in (0, 1]), Z0 = I.
-__global__ void ns_start_kernel(const double* __restrict__ Gs, const double* __restrict__ fro,
-                                int N, double* __restrict__ Y, double* __restrict__ Z) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = blockIdx.y * blockDim.y + threadIdx.y;
-  if (i >= N || j >= N) return;
-  Y[(int64_t)i * N + j] = Gs[(int64_t)i * N + j] / *fro;
-  Z[(int64_t)i * N + j] = (i == j) ? 1.0 : 0.0;
+// splitmix64 output function (Steele, Lea and Flood, OOPSLA 2014) of a 64-bit counter.
+__device__ inline uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
 }
 
-// T = (3 I - W) / 2
-// T = (3I - W)/2 and, per block, the partial sum of (W - I)^2 (blockDim 32 x 8);
-// nothing once the iteration has stopped.
-__global__ __launch_bounds__(256) void ns_step_kernel(const double* __restrict__ W, int N,
-                                                      double* __restrict__ T,
-                                                      const int* __restrict__ stop,
-                                                      double* __restrict__ part) {
-  __shared__ double red[4];
-  if (*stop) return;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = blockIdx.y * blockDim.y + threadIdx.y;
-  double d2 = 0.0;
-  if (i < N && j < N) {
-    const double w = W[(int64_t)i * N + j];
-    const double d = w - (i == j ? 1.0 : 0.0);
-    d2 = d * d;
-    T[(int64_t)i * N + j] = (i == j ? 1.5 : 0.0) - 0.5 * w;
-  }
-  const int t = threadIdx.y * blockDim.x + threadIdx.x;
-  for (int off = 32; off > 0; off >>= 1) d2 += __shfl_down(d2, off, 64);
-  if ((t & 63) == 0) red[t >> 6] = d2;
-  __syncthreads();
-  if (t == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
-}
-
-// pending = 1 once ||W - I||_F < tol (fixed-order sum of the partials); the step
-// that detected it still updates Y and Z, and the following ones copy.
-__global__ __launch_bounds__(256) void ns_check_kernel(const double* __restrict__ part, int n,
-                                                       double tol, const int* __restrict__ stop,
-                                                       int* __restrict__ pending) {
-  __shared__ double red[4];
-  if (*stop) return;
-  double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) s += part[i];
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-  __syncthreads();
-  if (threadIdx.x == 0 && red[0] + red[1] + red[2] + red[3] < tol * tol) *pending = 1;
-}
-
-__global__ void ns_flags_kernel(int* __restrict__ stop, int* __restrict__ pending, int reset) {
-  if (threadIdx.x == 0) {
-    if (reset) {
-      *stop = 0;
-      *pending = 0;
-    } else if (*pending) {
-      *stop = 1;
-    }
-  }
-}
-
-// Tm[i][j] = Z[i][j] dinv[j] / sqrt(||Gs||_F): Gs^{-1/2} D, orthonormal rows Tm Y.
-__global__ void ns_finish_kernel(const double* __restrict__ Z, const double* __restrict__ dinv,
-                                 const double* __restrict__ fro, int N, double* __restrict__ T) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = blockIdx.y * blockDim.y + threadIdx.y;
-  if (i >= N || j >= N) return;
-  T[(int64_t)i * N + j] = Z[(int64_t)i * N + j] * dinv[j] / sqrt(*fro);
+// Rows r in [k, N) of Z (row length M): uniform values on [-sqrt(3/M), sqrt(3/M))
+// keyed by (r, p), so that each row has unit expected norm; a fixed function of
+// the indices, hence the same on every call.
+template <typename T>
+__global__ void fill_rows_kernel(T* __restrict__ Z, int N, int64_t M, int k) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = k + blockIdx.y;
+  if (p >= M || r >= N) return;
+  const uint64_t z = splitmix64((uint64_t)r * (uint64_t)M + (uint64_t)p);
+  const double u = (double)(z >> 11) * 0x1.0p-53;  // [0, 1)
+  Z[(int64_t)r * M + p] = (T)((2.0 * u - 1.0) * sqrt(3.0 / (double)M));
 }
 
 }  // namespace
@@ -507,7 +461,7 @@ lrdm_status sym_eigh(lrdm_ctx* ctx, const double* S, int lda, int N, const doubl
     for (int t = 0; t < nb - 1; ++t) {
       {
         ProfScope prof_solve(ctx, "jac_solve");
-        jac_solve_kernel<<<nb / 2, 1024, 0, ctx->stream>>>(A, Np, nb, t, normF, Ublk, flag,
+        jac_solve_kernel<<<nb / 2, 1024, 0, ctx->stream>>>(A, Np, nb, t, normF, Ublk,
                                                             sweep == 0 ? 2 : 1);
       }
       if ((e = hipGetLastError()) != hipSuccess) return fail(e);
@@ -518,6 +472,8 @@ lrdm_status sym_eigh(lrdm_ctx* ctx, const double* S, int lda, int N, const doubl
       }
       if ((e = hipGetLastError()) != hipSuccess) return fail(e);
     }
+    jac_offmax_kernel<<<kFrobBlocks, 256, 0, ctx->stream>>>(A, Np, N, normF, flag);
+    if ((e = hipGetLastError()) != hipSuccess) return fail(e);
     int host_flag = 0;
     if ((e = hipMemcpyAsync(&host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream)) !=
         hipSuccess)
@@ -539,34 +495,40 @@ lrdm_status sym_eigh(lrdm_ctx* ctx, const double* S, int lda, int N, const doubl
   return LRDM_OK;
 }
 
-size_t ns_part_bytes(int N) {
-  return (size_t)((N + 31) / 32) * ((N + 7) / 8) * sizeof(double);
-}
-
 size_t rr_workspace_bytes(int N, int64_t M, lrdm_prec prec) {
   const int Np = ((N + JS - 1) / JS) * JS;
   const int nb = Np / JB;
+  const size_t s = prec == LRDM_FP64 ? sizeof(double) : sizeof(float);
   size_t b = 0;
-  b += ws_align((size_t)M * N * sizeof(double));            // H Y, later Psi_R
+  b += ws_align((size_t)M * N * sizeof(double));            // H B, later Psi_R
+  b += ws_align((size_t)M * N * s);                         // completed basis Z
   b += 6 * ws_align((size_t)N * N * sizeof(double));         // G, Hy, T, C, X, Wt
-  b += 2 * ws_align((size_t)N * sizeof(double));             // dinv, lam
-  b += ws_align(kFrobBlocks * sizeof(double));               // norm partial sums
-  b += ws_align(ns_part_bytes(N));                           // Newton-Schulz residuals
+  b += ws_align((size_t)N * N * sizeof(double));             // eigenvectors
+  size_t inner = chol_orth_bytes(N);
   // eigensolver
-  b += 2 * ws_align((size_t)Np * Np * sizeof(double)) + ws_align((size_t)(nb / 2) * JS * JS * 8) +
-       ws_align(256) + ws_align((size_t)Np * 4) + ws_align(kFrobBlocks * sizeof(double));
-  b += ws_align(tn_workspace_bytes(N, M, 1, prec));
-  b += ws_align((size_t)N * N * sizeof(double));             // U of G
-  return b;
+  inner = std::max(inner, 2 * ws_align((size_t)Np * Np * sizeof(double)) +
+                              ws_align((size_t)(nb / 2) * JS * JS * 8) + ws_align(256) +
+                              ws_align((size_t)Np * 4) + ws_align(kFrobBlocks * sizeof(double)));
+  inner = std::max(inner, ws_align(tn_workspace_bytes(N, M, 1, prec)));
+  return b + inner;
 }
 
+// Psi (N rows of M points, filtered block Y on entry) -> Ritz vectors, eps ascending.
+// Orthonormal basis: B = Y and T = factor of B B^T; while T leaves dependent rows or
+// cond(Gs) >= kOnePassCond, the next pass takes B <- T B (independent rows first,
+// then the explicit residuals of the dependent ones; from the second pass on, rows
+// still dependent are replaced by fixed pseudo-random rows) and refactors.  A
+// warm-started block takes one pass, an ill-conditioned one two (Cholesky QR
+// twice), a numerically rank-deficient one three.  Then
+//   Hhat = T (B (H B)^T) T^T = Q E Q^T, eps = E, Psi_R = Q^T T B.
 template <typename T>
 lrdm_status rayleigh_ritz(lrdm_ctx* ctx, const Grid3& g, const double* V, T* Psi, int N,
                           lrdm_prec prec, double* eps) {
   const int64_t M = g.M;
   const size_t nn = (size_t)N * N * sizeof(double);
-  // H Y in FP64 whatever the storage type (later reused for Psi_R in type T)
+  // H B in FP64 whatever the storage type (later reused for Psi_R in type T)
   double* HY = static_cast<double*>(ws_take(ctx, (size_t)M * N * sizeof(double)));
+  T* Z = static_cast<T*>(ws_take(ctx, (size_t)M * N * sizeof(T)));
   double* G = static_cast<double*>(ws_take(ctx, nn));
   double* Hy = static_cast<double*>(ws_take(ctx, nn));
   double* Tm = static_cast<double*>(ws_take(ctx, nn));
@@ -574,73 +536,46 @@ lrdm_status rayleigh_ritz(lrdm_ctx* ctx, const Grid3& g, const double* V, T* Psi
   double* X = static_cast<double*>(ws_take(ctx, nn));
   double* Wt = static_cast<double*>(ws_take(ctx, nn));
   double* Ug = static_cast<double*>(ws_take(ctx, nn));
-  double* dinv = static_cast<double*>(ws_take(ctx, (size_t)N * sizeof(double)));
-  double* lam = static_cast<double*>(ws_take(ctx, (size_t)N * sizeof(double)));
-  double* fpart = static_cast<double*>(ws_take(ctx, kFrobBlocks * sizeof(double)));
-  double* ns_part = static_cast<double*>(ws_take(ctx, ns_part_bytes(N)));
-  int* ns_stop = ctx->dstatus + LRDM_DS_COUNT + 1;     // scratch words after the status
-  int* ns_pending = ctx->dstatus + LRDM_DS_COUNT + 2;  // words (the zero page starts at 32)
   hipError_t e;
   auto fail = [&](const char* what, hipError_t err) {
     ctx->err = std::string("rayleigh_ritz: ") + what + ": " + hipGetErrorString(err);
     return LRDM_EDEVICE;
   };
   const size_t mark = ctx->ws_top;
-  // Every contraction here runs in FP64 arithmetic, and H Y is formed and kept
-  // in FP64, whatever the storage type of the block: a filtered block's columns
-  // span many orders of magnitude (1e-11 .. 1 at the 64^3 / 1024-state
-  // workload), so the scaled Gram matrix is far too ill-conditioned for FP32
-  // products, and the Loewdin coefficients (up to the inverse column norms)
-  // magnify any FP32 rounding of H Y or of the rotation.
-  // G = Y Y^T
-  if ((e = launch_tn_sym_f64<T, T>(ctx, Psi, nullptr, nullptr, 0, N, M, 1, 1, G)) != hipSuccess)
-    return fail("gram", e);
-  ctx->ws_top = mark;
-  diag_rsqrt_kernel<<<(N + 255) / 256, 256, 0, ctx->stream>>>(G, N, dinv);
-  if ((e = hipGetLastError()) != hipSuccess) return fail("scale", e);
-  // Loewdin factor Gs^{-1/2} by the coupled Newton-Schulz iteration
-  //   W = Z Y, T = (3I - W)/2, Y <- Y T, Z <- T Z   (Y -> Gs'^{1/2}, Z -> Gs'^{-1/2})
-  // on Gs' = Gs / ||Gs||_F, whose spectrum lies in (0, 1].  At most
-  // kNewtonSchulz steps (a cold block with cond(Gs) up to ~1e6 needs about 24); the
-  // device stops the iteration one step after ||W - I||_F < kNewtonSchulzTol, and
-  // the remaining launches only copy Y and Z, with no host read-back.
-  double* Ya = X;
-  double* Za = C;
-  double* Yb = Hy;
-  double* Zb = Wt;
-  double* W = G;
-  double* Tn = Ug;
-  double* fro = lam;
-  {
-    dim3 blk(32, 8), grd((N + 31) / 32, (N + 7) / 8);
-    gram_scale_kernel<<<grd, blk, 0, ctx->stream>>>(G, dinv, N, Tm);
-    if ((e = frob(ctx, Tm, N, N, fpart, fro)) != hipSuccess) return fail("scale", e);
-    ns_start_kernel<<<grd, blk, 0, ctx->stream>>>(Tm, fro, N, Ya, Za);
-    ns_flags_kernel<<<1, 64, 0, ctx->stream>>>(ns_stop, ns_pending, 1);
-    if ((e = hipGetLastError()) != hipSuccess) return fail("scale", e);
-    const int nparts = (int)(grd.x * grd.y);
-    for (int it = 0; it < kNewtonSchulz; ++it) {
-      if ((e = small_gemm(ctx, false, false, N, N, N, 1.0, Za, N, Ya, N, 0.0, W, N, ns_stop)) !=
-          hipSuccess)
-        return fail("newton-schulz", e);
-      ns_step_kernel<<<grd, blk, 0, ctx->stream>>>(W, N, Tn, ns_stop, ns_part);
-      ns_check_kernel<<<1, 256, 0, ctx->stream>>>(ns_part, nparts, kNewtonSchulzTol, ns_stop,
-                                                  ns_pending);
-      if ((e = small_gemm(ctx, false, false, N, N, N, 1.0, Ya, N, Tn, N, 0.0, Yb, N, ns_stop,
-                          Ya)) != hipSuccess ||
-          (e = small_gemm(ctx, false, false, N, N, N, 1.0, Tn, N, Za, N, 0.0, Zb, N, ns_stop,
-                          Za)) != hipSuccess)
-        return fail("newton-schulz", e);
-      ns_flags_kernel<<<1, 64, 0, ctx->stream>>>(ns_stop, ns_pending, 0);
-      std::swap(Ya, Yb);
-      std::swap(Za, Zb);
+  const dim3 blk(32, 8), grd((N + 31) / 32, (N + 7) / 8);
+  // Every contraction here runs in FP64 arithmetic, and H B is formed and kept in
+  // FP64, whatever the storage type of the block: a filtered block's rows span many
+  // orders of magnitude (1e-11 .. 1 at the 64^3 / 1024-state workload), so its
+  // Gram matrix and the orthonormalising coefficients need FP64 products.
+  T* B = Psi;
+  T* spare = Z;
+  CholInfo ci;
+  for (int pass = 0;; ++pass) {
+    if (pass > 0) {
+      if (pass == kMaxOrthPasses) {
+        ctx->err = "rayleigh_ritz: the block could not be orthonormalised";
+        return LRDM_ENOTCONV;
+      }
+      transpose_kernel<<<grd, blk, 0, ctx->stream>>>(Tm, N, Wt);
+      if ((e = launch_nn_f64<T>(ctx, Wt, B, spare, N, M)) != hipSuccess)
+        return fail("rotation", e);
+      if (pass > 1 && ci.live < N) {
+        fill_rows_kernel<T><<<dim3((unsigned)((M + 255) / 256), N - ci.live), 256, 0,
+                              ctx->stream>>>(spare, N, M, ci.live);
+        if ((e = hipGetLastError()) != hipSuccess) return fail("fill", e);
+      }
+      std::swap(B, spare);
     }
-    ns_finish_kernel<<<grd, blk, 0, ctx->stream>>>(Za, dinv, fro, N, Tm);
-    if ((e = hipGetLastError()) != hipSuccess) return fail("scale", e);
+    if ((e = launch_tn_sym_f64<T, T>(ctx, B, nullptr, nullptr, 0, N, M, 1, 1, G)) != hipSuccess)
+      return fail("gram", e);
+    ctx->ws_top = mark;
+    lrdm_status st = chol_orth(ctx, G, N, kDependentTol, Tm, &ci);
+    if (st != LRDM_OK) return st;
+    if (ci.live == N && ci.cond < kOnePassCond) break;
   }
-  // H Y and Y (H Y)^T
-  if ((e = launch_hpsi_f64<T>(ctx, g, V, Psi, HY, N)) != hipSuccess) return fail("stencil", e);
-  if ((e = launch_tn_sym_f64<T, double>(ctx, Psi, HY, nullptr, 0, N, M, 1, 1, Hy)) != hipSuccess)
+  // H B and B (H B)^T
+  if ((e = launch_hpsi_f64<T>(ctx, g, V, B, HY, N)) != hipSuccess) return fail("stencil", e);
+  if ((e = launch_tn_sym_f64<T, double>(ctx, B, HY, nullptr, 0, N, M, 1, 1, Hy)) != hipSuccess)
     return fail("projection", e);
   ctx->ws_top = mark;
   // C = T Hy T^T
@@ -651,9 +586,13 @@ lrdm_status rayleigh_ritz(lrdm_ctx* ctx, const Grid3& g, const double* V, T* Psi
   lrdm_status st = sym_eigh(ctx, C, N, N, nullptr, eps, Ug);
   if (st != LRDM_OK) return st;
   ctx->ws_top = mark;
-  // Psi_R = Q^T T Y: the rotation kernel computes Wt^T Y with Wt = T^T Q
+  // Psi_R = Q^T T B: the rotation kernel computes Wt^T B with Wt = T^T Q
   if ((e = small_gemm(ctx, true, false, N, N, N, 1.0, Tm, N, Ug, N, 0.0, Wt, N)) != hipSuccess)
     return fail("gemm", e);
+  if (B != Psi) {
+    if ((e = launch_nn_f64<T>(ctx, Wt, B, Psi, N, M)) != hipSuccess) return fail("rotation", e);
+    return LRDM_OK;
+  }
   T* PR = reinterpret_cast<T*>(HY);
   if ((e = launch_nn_f64<T>(ctx, Wt, Psi, PR, N, M)) != hipSuccess) return fail("rotation", e);
   if ((e = hipMemcpyAsync(Psi, PR, (size_t)M * N * sizeof(T), hipMemcpyDeviceToDevice,

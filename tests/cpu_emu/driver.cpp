@@ -175,6 +175,37 @@ void scenario_chfsi(lrdm_ctx* ctx, lrdm_grid g, int N, int degree, lrdm_prec pre
   check(lrdm_hartree_kernel(ctx, &g, u.data(), dV.data(), 2), ctx, "hartree_kernel");
 }
 
+// Rayleigh-Ritz of a block with exactly and nearly dependent rows (exact copies, a
+// combination, a zero row): the orthonormalisation takes its multi-pass route,
+// residual rows and pseudo-random completion included; the Ritz vectors must still
+// be orthonormal.
+void scenario_rr_dependent(lrdm_ctx* ctx, lrdm_grid g, int N, lrdm_prec prec) {
+  const int64_t M = (int64_t)g.n[0] * g.n[1] * g.n[2];
+  auto V = randv((size_t)M, 3, 0.5);
+  std::vector<double> y = randv((size_t)N * M, 12);
+  auto row = [&](int i) { return y.begin() + (size_t)i * M; };
+  std::copy(row(3), row(4), row(N / 3));                              // exact copy
+  for (int64_t p = 0; p < M; ++p) y[(size_t)(N / 2) * M + p] = 2 * row(10)[p] - row(11)[p];
+  for (int64_t p = 0; p < M; ++p) y[(size_t)(N - 2) * M + p] = row(0)[p] * (1 + 1e-13);
+  std::fill(row(N - 1), row(N), 0.0);                                 // zero row
+  Block Y(y, prec);
+  std::vector<double> eps(N);
+  char name[128];
+  std::snprintf(name, sizeof name, "subspace_rayleigh_ritz dependent rows %s N=%d", prec_name(prec), N);
+  check(subspace_rayleigh_ritz(ctx, &g, V.data(), Y.data(), N, prec, eps.data()), ctx, name);
+  const std::vector<double> Yv = Y.values();
+  double worst = 0;
+  for (int i = 0; i < N; i += 3)
+    for (int j = 0; j < N; j += 2) {
+      double d = 0;
+      for (int64_t p = 0; p < M; ++p) d += Yv[(size_t)i * M + p] * Yv[(size_t)j * M + p];
+      worst = std::fmax(worst, std::fabs(d - (i == j)));
+    }
+  const double bound = prec == LRDM_FP64 ? 1e-10 : 1e-5;
+  std::printf("     Ritz orthonormality error %.2e (bound %.0e)\n", worst, bound);
+  if (!(worst < bound) || !finite(eps)) ++failures;
+}
+
 // Internal launchers at the full subspace size of the 64^3 workload (N = 1024):
 // the eigenvalue ordering and gather of the eigensolver.
 void scenario_full_n(lrdm_ctx* ctx) {
@@ -268,6 +299,7 @@ int main(int argc, char** argv) {
     scenario_response(ctx, grid(9, 8, 7, 0.5), 40, 2, 2);
     scenario_chfsi(ctx, grid(10, 9, 8, 0.45), 150, 5);
     scenario_chfsi(ctx, grid(12, 12, 12, 0.45), 256, 4);
+    scenario_rr_dependent(ctx, grid(10, 9, 8, 0.45), 150, LRDM_FP64);
   }
   if (which == "all" || which == "lp") {
     scenario_response(ctx, grid(20, 18, 13, 0.4), 150, 1, 3, LRDM_FP32);
@@ -288,6 +320,10 @@ int main(int argc, char** argv) {
   if (which == "pp") {
     scenario_projection(ctx, grid(8, 8, 8, 0.5), 40, 1, LRDM_FP32);
     scenario_projection(ctx, grid(8, 8, 8, 0.5), 40, 1, LRDM_BF16X3);
+  }
+  if (which == "all" || which == "rank") {
+    scenario_rr_dependent(ctx, grid(10, 9, 8, 0.45), 150, LRDM_FP64);
+    scenario_rr_dependent(ctx, grid(7, 9, 11, 0.5), 70, LRDM_FP32);
   }
   if (which == "lprr") {
     scenario_chfsi(ctx, grid(10, 9, 8, 0.45), 150, 5, LRDM_FP32);

@@ -184,6 +184,106 @@ def test_rayleigh_ritz_multitile():
     assert np.max(np.abs(P @ P.T - np.eye(N))) < 1e-11
 
 
+def _ritz_checks(Yd, e, V, g, N, tol_orth=1e-12):
+    """Orthonormal Ritz vectors that diagonalise H in their span: returns the
+    vectors (host) after asserting both properties."""
+    P = to_host(Yd).reshape(N, -1)
+    assert np.max(np.abs(P @ P.T - np.eye(N))) < tol_orth
+    HP = O.hamiltonian_apply(P.reshape((N,) + g.shape), V, g).reshape(N, -1)
+    assert np.max(np.abs(P @ HP.T - np.diag(e))) < 1e-10 * np.max(np.abs(e))
+    return P
+
+
+@pytest.mark.parametrize("degree", [40, 90])
+def test_rayleigh_ritz_ill_conditioned_block(degree):
+    """A cold block filtered with a high degree: the column-scaled Gram matrix has
+    condition ~6e8 at degree 40 (two Cholesky passes) and is numerically singular at
+    degree 90 (dependent rows resolved through their explicit residuals).  Ritz
+    values match the oracle's Householder-QR Rayleigh-Ritz on the same block."""
+    g = O.Grid((16, 16, 16), (7.0, 7.0, 7.0))
+    rng = np.random.default_rng(6)
+    V = rng.uniform(-1, 0, g.shape)
+    N = 200
+    Y0 = rng.standard_normal((N,) + g.shape)
+    b = sum(2.0 / h ** 2 for h in g.h) + V.max()
+    e0, X = O.rayleigh_ritz(Y0, V, g)
+    Y = O.chebyshev_filter(X, V, g, degree, e0[-1], b, e0[0] - 0.2)
+    eps_o, _ = O.rayleigh_ritz(Y, V, g)
+    Yd = to_dev(Y)
+    e = to_host(L.subspace_rayleigh_ritz(_grid(g), to_dev(V), Yd))
+    scale = np.max(np.abs(eps_o))
+    if degree == 40:
+        assert np.max(np.abs(e - eps_o)) < 1e-10 * scale
+    else:   # the top of a rank-deficient block is resolved only to the residuals' level
+        assert np.max(np.abs(e[:N // 2] - eps_o[:N // 2])) < 1e-10 * scale
+        assert np.max(np.abs(e - eps_o)) < 1e-7 * scale
+    _ritz_checks(Yd, e, V, g, N)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_rayleigh_ritz_dependent_rows(prec):
+    """Exact copies, an exact combination, a near copy (1e-13) and a zero row: the
+    Ritz vectors are still orthonormal (dependent directions completed by fixed
+    pseudo-random rows), the independent rows lie in their span, and they
+    diagonalise H there.  (Where rows are dependent the completion is not unique,
+    so the top Ritz pairs are checked by these properties, not against the oracle.)"""
+    g = O.Grid((10, 9, 8), (4.5, 4.05, 3.6))
+    rng = np.random.default_rng(12)
+    V = rng.uniform(-1, 0, g.shape)
+    N = 150
+    Y = rng.standard_normal((N,) + g.shape)
+    Y[50] = Y[3]
+    Y[75] = 2.0 * Y[10] - Y[11]
+    Y[148] = Y[0] * (1 + 1e-13)
+    Y[149] = 0.0
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    Yd = to_dev(Y, dt)
+    e = to_host(L.subspace_rayleigh_ritz(_grid(g), to_dev(V), Yd, prec=prec))
+    P = to_host(Yd).reshape(N, -1)
+    bound = 1e-12 if prec == "fp64" else 1e-5
+    assert np.all(np.isfinite(e))
+    assert np.max(np.abs(P @ P.T - np.eye(N))) < bound
+    keep = [i for i in range(N) if i not in (50, 75, 148, 149)]
+    Yk = to_host(to_dev(Y, dt)).reshape(N, -1)[keep]
+    assert np.linalg.norm(Yk - (Yk @ P.T) @ P) / np.linalg.norm(Yk) < (1e-12 if prec == "fp64" else 1e-5)
+    HP = O.hamiltonian_apply(P.reshape((N,) + g.shape), V, g).reshape(N, -1)
+    assert np.max(np.abs(P @ HP.T - np.diag(e))) < (1e-10 if prec == "fp64" else 1e-4) * np.max(np.abs(e))
+
+
+def test_rayleigh_ritz_full_size_cold_start():
+    """The 64^3 / 1024-state workload from its seeded cold block: a degree-10 pass,
+    then degree-40 passes, as at the start of ChFSI.  After the degree-40 filter the
+    top states are far below the bottom ones (gain ratio ~1e13) and the scaled Gram
+    matrix is numerically singular; every pass must still return orthonormal Ritz
+    vectors that diagonalise H in their span (checked with FP64 products on the
+    device: ||Psi Psi^T - I||_max and ||Psi H Psi^T - diag(eps)||_max)."""
+    from inputs import make_workload
+    wl = make_workload("c64_n1024_slab")
+    grid = L.Grid(tuple(wl.n), tuple(wl.L))
+    N = wl.N
+    V = torch.from_numpy(wl.V[0]).to("cuda")
+    X = torch.empty((N,) + grid.shape, dtype=torch.float64, device="cuda")
+    for s0 in range(0, N, 64):
+        X[s0:s0 + 64] = torch.from_numpy(wl.block(states=range(s0, min(N, s0 + 64)))).to("cuda")
+    b = sum(2.0 / h ** 2 for h in wl.h) + float(wl.V[0].max())
+    a0 = float(wl.V[0].min()) - 0.1
+    a = a0 + 0.25 * (b - a0)
+    eye = torch.eye(N, dtype=torch.float64, device="cuda")
+    for p, deg in enumerate((10, 40, 40)):
+        Y = L.chfsi_filter(grid, V, X, deg, a, b, a0)
+        e = L.subspace_rayleigh_ritz(grid, V, Y)
+        P = Y.reshape(N, -1)
+        orth = float((P @ P.T - eye).abs().max())
+        HP = L.hamiltonian_apply(grid, V, Y).reshape(N, -1)
+        ritz = float((P @ HP.T - torch.diag(e)).abs().max())
+        print(f"pass {p} (degree {deg}): orth {orth:.2e} ritz {ritz:.2e} eps [{float(e[0]):.6f}, {float(e[-1]):.6f}]")
+        assert orth < 1e-11
+        assert ritz < 1e-10 * float(e.abs().max())
+        X = Y
+        a, a0 = float(e[-1]), float(e[0]) - 0.2
+        del HP
+
+
 # ------------------------------------------------------------------ validation on the device side
 def test_unsupported_and_invalid_are_errors():
     g = L.Grid((8, 8, 8), (4.0, 4.0, 4.0))
