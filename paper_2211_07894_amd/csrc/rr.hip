@@ -36,7 +36,11 @@ constexpr int JS = 64;        // pair problem size
 constexpr int JP = JS + 1;    // LDS pitch
 constexpr double kPad = 1e30; // diagonal of padding rows (decoupled, sorts last)
 constexpr double kDependentTol = 1e-10;  // Schur pivot (unit diagonal) of a dependent row
-constexpr double kOnePassCond = 1e3;     // one Cholesky pass when cond(Gs) is below this
+// One Cholesky pass when cond(Gs) is below this: the basis T Y is then orthonormal
+// to about u cond(Gs), 1e-13 for FP64 storage and 1e-9 (below the FP32 rounding
+// of the stored Ritz vectors) for FP32 storage.
+constexpr double kOnePassCond64 = 1e3;
+constexpr double kOnePassCond32 = 1e7;
 constexpr int kMaxOrthPasses = 5;        // Cholesky passes before giving up
 
 
@@ -515,7 +519,7 @@ size_t rr_workspace_bytes(int N, int64_t M, lrdm_prec prec) {
 
 // Psi (N rows of M points, filtered block Y on entry) -> Ritz vectors, eps ascending.
 // Orthonormal basis: B = Y and T = factor of B B^T; while T leaves dependent rows or
-// cond(Gs) >= kOnePassCond, the next pass takes B <- T B (independent rows first,
+// cond(Gs) is too large for one pass, the next pass takes B <- T B (independent rows first,
 // then the explicit residuals of the dependent ones; from the second pass on, rows
 // still dependent are replaced by fixed pseudo-random rows) and refactors.  A
 // warm-started block takes one pass, an ill-conditioned one two (Cholesky QR
@@ -571,7 +575,8 @@ lrdm_status rayleigh_ritz(lrdm_ctx* ctx, const Grid3& g, const double* V, T* Psi
     ctx->ws_top = mark;
     lrdm_status st = chol_orth(ctx, G, N, kDependentTol, Tm, &ci);
     if (st != LRDM_OK) return st;
-    if (ci.live == N && ci.cond < kOnePassCond) break;
+    if (ci.live == N && ci.cond < (sizeof(T) == sizeof(double) ? kOnePassCond64 : kOnePassCond32))
+      break;
   }
   // H B and B (H B)^T
   if ((e = launch_hpsi_f64<T>(ctx, g, V, B, HY, N)) != hipSuccess) return fail("stencil", e);
