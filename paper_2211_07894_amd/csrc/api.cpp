@@ -401,18 +401,34 @@ hipError_t run_filter(lrdm_ctx* ctx, const Grid3& g, const double* V, const T* X
   T* W = static_cast<T*>(ws_take(ctx, (size_t)g.M * N * sizeof(T)));
   const double e = (b - a) / 2.0, c0 = (b + a) / 2.0;
   const double sigma1 = e / (a0 - c0);
+  // the vectorised step reads V in the storage type
+  auto aligned = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  const bool vec = cheb_vec_ok<T>(g) && aligned(X) && aligned(Y) && aligned(W);
+  const T* Vt = nullptr;
+  if (vec) {
+    if constexpr (sizeof(T) == sizeof(double)) {
+      Vt = V;
+    } else {
+      float* Vf = static_cast<float*>(ws_take(ctx, (size_t)g.M * sizeof(float)));
+      LRDM_HIP(launch_to_float(ctx, V, g.M, Vf));
+      Vt = Vf;
+    }
+  }
+  auto step = [&](const T* yin, const T* yold, T* yout, double alpha, double beta) {
+    return vec ? launch_cheb_step_vec<T>(ctx, g, Vt, yin, yold, yout, N, alpha, c0, beta)
+               : launch_cheb_step<T>(ctx, g, V, yin, yold, yout, N, alpha, c0, beta);
+  };
   // Y_k lands in bufA for odd k and bufB for even k; choose so that Y_c is in Y.
   T* bufA = (degree % 2 == 1) ? Y : W;
   T* bufB = (degree % 2 == 1) ? W : Y;
-  LRDM_HIP(launch_cheb_step<T>(ctx, g, V, X, nullptr, bufA, N, sigma1 / e, c0, 0.0));
+  LRDM_HIP(step(X, nullptr, bufA, sigma1 / e, 0.0));
   double sigma = sigma1;
   for (int k = 2; k <= degree; ++k) {
     const double sigma_new = 1.0 / (2.0 / sigma1 - sigma);
     const T* ykm1 = (k % 2 == 0) ? bufA : bufB;   // Y_{k-1}
     const T* ykm2 = (k == 2) ? X : ((k % 2 == 0) ? bufB : bufA);  // Y_{k-2}
     T* out = (k % 2 == 1) ? bufA : bufB;          // overwrites Y_{k-2} (k > 2)
-    LRDM_HIP(launch_cheb_step<T>(ctx, g, V, ykm1, ykm2, out, N, 2.0 * sigma_new / e, c0,
-                                 -sigma * sigma_new));
+    LRDM_HIP(step(ykm1, ykm2, out, 2.0 * sigma_new / e, -sigma * sigma_new));
     sigma = sigma_new;
   }
   return hipSuccess;
@@ -524,7 +540,7 @@ extern "C" lrdm_status chfsi_filter(lrdm_ctx* ctx, const lrdm_grid* grid, const 
   const Grid3 g = make_grid3(grid);
   const size_t blk = (size_t)g.M * N * prec_bytes(prec);
   if (overlaps(X, blk, Y, blk)) return fail(ctx, LRDM_EINVAL, "X and Y must not overlap");
-  lrdm_status st = begin(ctx, ws_align(blk));
+  lrdm_status st = begin(ctx, ws_align(blk) + ws_align((size_t)g.M * sizeof(float)));
   if (st != LRDM_OK) return st;
   return guarded(ctx, [&]() -> lrdm_status {
     hipError_t e = (prec == LRDM_FP64)

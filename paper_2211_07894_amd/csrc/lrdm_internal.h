@@ -81,6 +81,18 @@ template <typename T>
 hipError_t launch_cheb_step(lrdm_ctx* ctx, const Grid3& g, const double* V, const T* Yin,
                             const T* Yold, T* Yout, int N, double alpha, double c0, double beta);
 
+// The same step in its vectorised form, with V given in the storage type (Vt);
+// usable when cheb_vec_ok(g): nx a multiple of the 16-byte group and at most 2048
+// groups per plane.  Yout may equal Yold.
+template <typename T>
+bool cheb_vec_ok(const Grid3& g);
+template <typename T>
+hipError_t launch_cheb_step_vec(lrdm_ctx* ctx, const Grid3& g, const T* Vt, const T* Yin,
+                                const T* Yold, T* Yout, int N, double alpha, double c0,
+                                double beta);
+// b[i] = (float)a[i], i < n.
+hipError_t launch_to_float(lrdm_ctx* ctx, const double* a, int64_t n, float* b);
+
 // HY = H Y in FP64 arithmetic and storage for either storage type of Y.
 template <typename T>
 hipError_t launch_hpsi_f64(lrdm_ctx* ctx, const Grid3& g, const double* V, const T* Y, double* HY,
