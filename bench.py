@@ -156,7 +156,7 @@ def main():
             log(f"form {form} unavailable: {ex}")
             continue
         ctx.profile(True)
-        for k in ["cheb_step", "hpsi", "proj", "gram", "backproj", "nn", "eigh", "jac_sweep", "jac_solve", "jac_update", "hartree"]:
+        for k in ["cheb_step", "hpsi", "proj", "gram", "backproj", "nn", "eigh", "chol", "jac_sweep", "jac_solve", "jac_update", "hartree"]:
             ctx.profile_read(k)
         torch.cuda.synchronize()
         t_start = time.perf_counter()
@@ -166,7 +166,7 @@ def main():
         elapsed = time.perf_counter() - t_start
         ctx.profile(False)
         kern = {k: ctx.profile_read(k) for k in
-                ["cheb_step", "hpsi", "proj", "gram", "backproj", "nn", "eigh", "jac_sweep", "jac_solve", "jac_update", "hartree"]}
+                ["cheb_step", "hpsi", "proj", "gram", "backproj", "nn", "eigh", "chol", "jac_sweep", "jac_solve", "jac_update", "hartree"]}
         ms_step = 1e3 * elapsed / args.steps
         # errors in delta rho = t + u relative to the FP64 form: per stage (this
         # form's residual derivative on the FP64 Ritz pairs cast to its storage)

@@ -372,6 +372,7 @@ size_t chol_orth_bytes(int N) {
 
 lrdm_status chol_orth(lrdm_ctx* ctx, const double* G, int N, double tau, double* T,
                       CholInfo* info) {
+  ProfScope prof(ctx, "chol");
   const int Np = ((N + CB - 1) / CB) * CB;
   const int nb = Np / CB;
   const size_t mark = ctx->ws_top;
