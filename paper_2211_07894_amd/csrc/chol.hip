@@ -79,61 +79,101 @@ __global__ void chol_init_kernel(const double* __restrict__ G, const double* __r
   A[(int64_t)i * Np + j] = v;
 }
 
-// Factor the diagonal block kb in LDS (dependent rows: zero column, unit diagonal)
-// and write L_kk to A and its inverse to Linv[kb].
+// Factor the diagonal block kb (dependent rows: zero column, unit diagonal) and
+// write L_kk to A and its inverse to Linv[kb].  256 threads; thread t keeps the
+// lower-triangle entries e = t + 256 s (row-major order of the triangle) in
+// registers.  Column j: its entries, as updated so far, go to an LDS column buffer
+// (two alternating buffers), and after one barrier every thread applies
+// S_il -= S_ij S_lj / S_jj to the entries it owns with l > j (nothing for a
+// dependent column).  The inverse is built row by row: X[i][c] =
+// (delta_ic - sum_{l<i} L_il X_lc) / L_ii, the sum split over four threads per c
+// (X[l][c] = 0 for l < c, so the terms below the column start vanish).
+constexpr int kTri = CB * (CB + 1) / 2;          // 2080 lower-triangle entries
+constexpr int kOwn = (kTri + 255) / 256;         // 9 per thread
+
 __global__ __launch_bounds__(256) void chol_diag_kernel(double* __restrict__ A, int Np, int kb,
                                                         double tau, int* __restrict__ dead,
                                                         double* __restrict__ Linv) {
-  __shared__ double S[CB * CP];
+  __shared__ double col[2][CB];
+  __shared__ double piv[CB];
+  __shared__ double red[4][CB];
+  __shared__ double L[CB * CP];
   __shared__ double X[CB * CP];
-  __shared__ int dd[CB];
   const int t = threadIdx.x;
   const int64_t o = (int64_t)kb * CB;
-  for (int e = t; e < CB * CB; e += blockDim.x) {
-    const int i = e / CB, j = e % CB;
-    S[i * CP + j] = (j <= i) ? A[(o + i) * Np + o + j] : 0.0;
+  int ri[kOwn], ci[kOwn];
+  double v[kOwn];
+#pragma unroll
+  for (int s = 0; s < kOwn; ++s) {
+    const int e = t + 256 * s;
+    int i = -1, l = -1;
+    if (e < kTri) {
+      i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+      while ((i + 1) * (i + 2) / 2 <= e) ++i;
+      while (i * (i + 1) / 2 > e) --i;
+      l = e - i * (i + 1) / 2;
+    }
+    ri[s] = i;
+    ci[s] = l;
+    v[s] = (i >= 0) ? A[(o + i) * Np + o + l] : 0.0;
+    if (l == 0) col[0][i] = v[s];
   }
   __syncthreads();
   for (int j = 0; j < CB; ++j) {
-    const double d = S[j * CP + j];
+    const double* cj = col[j & 1];
+    double* cn = col[(j + 1) & 1];
+    const double d = cj[j];
     const bool live = d > tau;  // NaN is dependent
-    const double r = live ? sqrt(d) : 1.0;
-    __syncthreads();
-    if (t > j && t < CB) S[t * CP + j] = live ? S[t * CP + j] / r : 0.0;
-    if (t == 0) {
-      S[j * CP + j] = r;
-      dd[j] = live ? 0 : 1;
+    const double inv = live ? 1.0 / d : 0.0;
+#pragma unroll
+    for (int s = 0; s < kOwn; ++s) {
+      if (ci[s] > j) v[s] -= cj[ri[s]] * cj[ci[s]] * inv;
+      if (ci[s] == j + 1) cn[ri[s]] = v[s];
     }
-    __syncthreads();
-    // trailing update of the block: S[i][l] -= S[i][j] S[l][j], j < l <= i
-    const int m = CB - 1 - j;
-    for (int e = t; e < m * m; e += blockDim.x) {
-      const int i = j + 1 + e / m, l = j + 1 + e % m;
-      if (i >= l) S[i * CP + l] -= S[i * CP + j] * S[l * CP + j];
-    }
+    if (t == 0) piv[j] = d;
     __syncthreads();
   }
-  // X = S^{-1}: thread c solves column c by forward substitution
-  if (t < CB) {
-    const int c = t;
-    for (int i = 0; i < CB; ++i) {
-      if (i < c) {
-        X[i * CP + c] = 0.0;
-        continue;
-      }
-      double s = (i == c) ? 1.0 : 0.0;
-      for (int l = c; l < i; ++l) s -= S[i * CP + l] * X[l * CP + c];
-      X[i * CP + c] = s / S[i * CP + i];
-    }
+  // L from the entries as they stood when their column was eliminated
+#pragma unroll
+  for (int s = 0; s < kOwn; ++s) {
+    if (ri[s] < 0) continue;
+    const int i = ri[s], l = ci[s];
+    const double d = piv[l];
+    const bool live = d > tau;
+    double x;
+    if (i == l)
+      x = live ? sqrt(d) : 1.0;
+    else
+      x = live ? v[s] / sqrt(d) : 0.0;
+    L[i * CP + l] = x;
+  }
+  for (int e = t; e < CB * CB; e += 256) {
+    const int i = e / CB, c = e % CB;
+    if (c > i) L[i * CP + c] = 0.0;
+    X[i * CP + c] = 0.0;
   }
   __syncthreads();
+  // X = L^{-1}, row by row; thread (c, part) with c = t % 64, part = t / 64
+  {
+    const int c = t & 63, part = t >> 6;
+    for (int i = 0; i < CB; ++i) {
+      double sum = 0.0;
+      for (int l = c + part; l < i; l += 4) sum += L[i * CP + l] * X[l * CP + c];
+      red[part][c] = sum;
+      __syncthreads();
+      if (part == 0 && c <= i)
+        X[i * CP + c] = ((i == c ? 1.0 : 0.0) - (red[0][c] + red[1][c] + red[2][c] + red[3][c])) /
+                        L[i * CP + i];
+      __syncthreads();
+    }
+  }
   double* Li = Linv + (int64_t)kb * CB * CB;
-  for (int e = t; e < CB * CB; e += blockDim.x) {
+  for (int e = t; e < CB * CB; e += 256) {
     const int i = e / CB, j = e % CB;
-    A[(o + i) * Np + o + j] = (j <= i) ? S[i * CP + j] : 0.0;
+    A[(o + i) * Np + o + j] = L[i * CP + j];
     Li[e] = X[i * CP + j];
   }
-  if (t < CB) dead[o + t] = dd[t];
+  if (t < CB) dead[o + t] = piv[t] > tau ? 0 : 1;
 }
 
 // Panel below the diagonal block: L_ib,kb = A_ib,kb Linv_kk^T, dependent columns zero.
@@ -279,30 +319,40 @@ __global__ void chol_rows_kernel(const double* __restrict__ X, int Np, int N,
   T[(int64_t)r * N + j] = X[(int64_t)perm[r] * Np + j];
 }
 
-// ||A||_inf of the N x N matrix (max absolute row sum) -> *out; one block.
-__global__ __launch_bounds__(256) void chol_infnorm_kernel(const double* __restrict__ A, int N,
-                                                           int lda, double* __restrict__ out) {
+// rowsum[i] = sum_j |A[i][j]| (one block per row) ...
+__global__ __launch_bounds__(256) void chol_rowsum_kernel(const double* __restrict__ A, int N,
+                                                          int lda, double* __restrict__ rowsum) {
+  __shared__ double red[4];
+  const int i = blockIdx.x;
+  double s = 0.0;
+  for (int j = threadIdx.x; j < N; j += blockDim.x) s += fabs(A[(int64_t)i * lda + j]);
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) rowsum[i] = red[0] + red[1] + red[2] + red[3];
+}
+
+// ... and *out = max_i rowsum[i] = ||A||_inf (NaN propagates); one block.
+__global__ __launch_bounds__(256) void chol_max_kernel(const double* __restrict__ x, int N,
+                                                       double* __restrict__ out) {
   __shared__ double red[4];
   double mx = 0.0;
-  for (int i = threadIdx.x; i < N; i += blockDim.x) {
-    double s = 0.0;
-    for (int j = 0; j < N; ++j) s += fabs(A[(int64_t)i * lda + j]);
-    mx = nan_max(mx, s);
-  }
+  for (int i = threadIdx.x; i < N; i += blockDim.x) mx = nan_max(mx, x[i]);
   for (int off = 32; off > 0; off >>= 1) mx = nan_max(mx, __shfl_down(mx, off, 64));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
   __syncthreads();
   if (threadIdx.x == 0) *out = nan_max(nan_max(red[0], red[1]), nan_max(red[2], red[3]));
 }
 
-// y = T_k v (one block per row; rows from k = sc[2] on give 0) ...
+// y = T v over the rows i < kmax (one block per row; rows from kmax on give 0;
+// kmax = sc[2] when sc is given, else N) ...
 __global__ __launch_bounds__(256) void chol_mv_kernel(const double* __restrict__ T, int N,
                                                       const double* __restrict__ v,
                                                       const double* __restrict__ sc,
                                                       double* __restrict__ y) {
   __shared__ double red[4];
   const int i = blockIdx.x;
-  const int k = (int)sc[2];
+  const int k = sc ? (int)sc[2] : N;
   double s = 0.0;
   if (i < k)
     for (int j = threadIdx.x; j < N; j += blockDim.x) s += T[(int64_t)i * N + j] * v[j];
@@ -310,17 +360,6 @@ __global__ __launch_bounds__(256) void chol_mv_kernel(const double* __restrict__
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) y[i] = red[0] + red[1] + red[2] + red[3];
-}
-
-// ... w = T^T y (thread per column, rows in order) ...
-__global__ __launch_bounds__(256) void chol_mtv_kernel(const double* __restrict__ T, int N,
-                                                       const double* __restrict__ y,
-                                                       double* __restrict__ w) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= N) return;
-  double s = 0.0;
-  for (int i = 0; i < N; ++i) s += T[(int64_t)i * N + j] * y[i];
-  w[j] = s;
 }
 
 // ... and v = w / ||w||, sc[1] = ||w|| (the Rayleigh estimate of ||T^T T||_2 for a
@@ -344,6 +383,13 @@ __global__ void chol_fill_kernel(double* __restrict__ v, int N) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   // a fixed start vector with no special structure: 1 + j/N, normalised later
   if (j < N) v[j] = (1.0 + (double)j / N) / sqrt((double)N);
+}
+
+// Tt = T^T (N x N).
+__global__ void chol_transpose_kernel(const double* __restrict__ T, int N, double* __restrict__ Tt) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i < N && j < N) Tt[(int64_t)j * N + i] = T[(int64_t)i * N + j];
 }
 
 // T[r][j] *= dinv[j]
@@ -395,7 +441,8 @@ lrdm_status chol_orth(lrdm_ctx* ctx, const double* G, int N, double tau, double*
   const dim3 blk(32, 8);
   chol_dinv_kernel<<<(N + 255) / 256, 256, 0, ctx->stream>>>(G, N, dinv);
   chol_init_kernel<<<dim3((Np + 31) / 32, (Np + 7) / 8), blk, 0, ctx->stream>>>(G, dinv, N, Np, A);
-  chol_infnorm_kernel<<<1, 256, 0, ctx->stream>>>(A, N, Np, sc);
+  chol_rowsum_kernel<<<N, 256, 0, ctx->stream>>>(A, N, Np, pw);
+  chol_max_kernel<<<1, 256, 0, ctx->stream>>>(pw, N, sc);
   if ((e = hipGetLastError()) != hipSuccess) return fail(e);
   for (int kb = 0; kb < nb; ++kb) {
     chol_diag_kernel<<<1, 256, 0, ctx->stream>>>(A, Np, kb, tau, dead, Linv);
@@ -434,10 +481,11 @@ lrdm_status chol_orth(lrdm_ctx* ctx, const double* G, int N, double tau, double*
   chol_rows_kernel<<<dim3((N + 31) / 32, (N + 7) / 8), blk, 0, ctx->stream>>>(X, Np, N, perm, sc,
                                                                               T);
   // ||Gs^{-1}||_2 on the independent rows = ||T_k^T T_k||_2 (unscaled T): power iteration
+  chol_transpose_kernel<<<dim3((N + 31) / 32, (N + 7) / 8), blk, 0, ctx->stream>>>(T, N, tmp);
   chol_fill_kernel<<<(N + 255) / 256, 256, 0, ctx->stream>>>(pv, N);
   for (int it = 0; it < kPowerSteps; ++it) {
-    chol_mv_kernel<<<N, 256, 0, ctx->stream>>>(T, N, pv, sc, pw);
-    chol_mtv_kernel<<<(N + 255) / 256, 256, 0, ctx->stream>>>(T, N, pw, pv);
+    chol_mv_kernel<<<N, 256, 0, ctx->stream>>>(T, N, pv, sc, pw);         // y = T_k v
+    chol_mv_kernel<<<N, 256, 0, ctx->stream>>>(tmp, N, pw, nullptr, pv);  // w = T^T y
     chol_normalize_kernel<<<1, 256, 0, ctx->stream>>>(pv, N, pv, sc);
   }
   chol_scale_cols_kernel<<<dim3((N + 31) / 32, (N + 7) / 8), blk, 0, ctx->stream>>>(T, N, dinv);
