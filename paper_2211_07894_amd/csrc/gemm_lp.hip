@@ -64,6 +64,32 @@ __device__ inline void split(const float (&x)[8], bf8 (&p)[NP]) {
   }
 }
 
+// Exact three-piece split of 8 FP32 values by truncation: hi keeps the top 16
+// bits of x (sign, exponent, 7 fraction bits), mid those of x - hi, lo those of
+// x - hi - mid; each remainder is exact (Sterbenz) and the last has at most 8
+// significant bits, so hi + mid + lo = x.  |mid| < 2^-7 |x|, |lo| < 2^-15 |x|.
+// Integer masks and FP32 subtractions only, with the bf16 pairs packed directly.
+__device__ inline void split3_trunc(const float (&x)[8], bf8 (&p)[3]) {
+  typedef unsigned u4 __attribute__((ext_vector_type(4)));
+  u4 h, m, l;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const unsigned b0 = __float_as_uint(x[2 * e]), b1 = __float_as_uint(x[2 * e + 1]);
+    const float r0 = x[2 * e] - __uint_as_float(b0 & 0xffff0000u);
+    const float r1 = x[2 * e + 1] - __uint_as_float(b1 & 0xffff0000u);
+    const unsigned c0 = __float_as_uint(r0), c1 = __float_as_uint(r1);
+    const float s0 = r0 - __uint_as_float(c0 & 0xffff0000u);
+    const float s1 = r1 - __uint_as_float(c1 & 0xffff0000u);
+    const unsigned d0 = __float_as_uint(s0), d1 = __float_as_uint(s1);
+    h[e] = (b0 >> 16) | (b1 & 0xffff0000u);
+    m[e] = (c0 >> 16) | (c1 & 0xffff0000u);
+    l[e] = (d0 >> 16) | (d1 & 0xffff0000u);
+  }
+  p[0] = __builtin_bit_cast(bf8, h);
+  p[1] = __builtin_bit_cast(bf8, m);
+  p[2] = __builtin_bit_cast(bf8, l);
+}
+
 // Lane-local fragment of rows (base + 16i + lane%16), k = 8(lane/16) .. +7.
 __device__ inline void frag(const float* S, int base, int lane, float (&v)[4][8]) {
   const int r = lane & 15, g = lane >> 4;
@@ -459,6 +485,30 @@ __device__ inline void kt_step_pipe(PipeFrag& f, double scale, double (&acc)[2][
 // Keeps the compiler from moving memory accesses across this point.
 __device__ inline void compiler_fence() { asm volatile("" ::: "memory"); }
 
+// FP32 partial sums of the BF16X3 kernels are added into FP64 every kFlush
+// K-tiles (kFlush * KT = 128 terms of each product).
+constexpr int kFlush = 4;
+static_assert(kFlush * KT == BT, "flush groups must match the diagonal blocks");
+
+__device__ inline void zero_f32(f4 (&cc)[2][4]) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) cc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+}
+
+// acc += f * cc, cc = 0.
+__device__ inline void flush_pipe(f4 (&cc)[2][4], double f, double (&acc)[2][4][4]) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[i][j][v] += f * (double)cc[i][j][v];
+      cc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+}
+
 __device__ inline void zero_pipe(double (&acc)[2][4][4]) {
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -794,9 +844,11 @@ __global__ __launch_bounds__(PT, 1) void tn_sym_p3_kernel(
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_pipe[];
   constexpr int SB = TB + 3 * PB + 1024;   // A (FP32), B pieces, weights
   const int ntiles = ntb * (ntb + 1) / 2;
-  int group, tile;
-  xcd_map(blockIdx.x, nsplit * batch, ntiles, group, tile);
-  const int sp = group % nsplit, b = group / nsplit;
+  // the directions of one (split, tile) run together on one XCD: they stage the
+  // same operand tiles (only the weights differ), so L2 serves all but the first
+  int group, b;
+  xcd_map(blockIdx.x, nsplit * ntiles, batch, group, b);
+  const int sp = group / ntiles, tile = group % ntiles;
   int ti = 0, rem = tile;
   while (rem >= ntb - ti) { rem -= ntb - ti; ++ti; }
   const int tj = ti + rem;
@@ -823,53 +875,52 @@ __global__ __launch_bounds__(PT, 1) void tn_sym_p3_kernel(
   };
   double acc[2][4][4];
   zero_pipe(acc);
+  f4 cc[2][4];
+  zero_f32(cc);
   issue(0);
   issue(1);
-  for (int t = 0; t < nk; ++t) {
-    if (wid == 0) wait_stage<6>(); else wait_stage<5>();
-    const unsigned char* st = smem_pipe + (t % NST) * SB;
-    float a[2][8];
-    frag_sw<2>(st, wr * 32, lane, a);
-    bf8 pb[4][3];
+  for (int t0 = 0; t0 < nk; t0 += kFlush) {
+    const int t1 = min(nk, t0 + kFlush);
+    for (int t = t0; t < t1; ++t) {
+      if (wid == 0) wait_stage<6>(); else wait_stage<5>();
+      const unsigned char* st = smem_pipe + (t % NST) * SB;
+      float a[2][8];
+      frag_sw<2>(st, wr * 32, lane, a);
+      bf8 pb[4][3];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      bf8 v[4];
-      frag_piece<4>(st + TB + q * PB, wc * 64, lane, v);
+      for (int q = 0; q < 3; ++q) {
+        bf8 v[4];
+        frag_piece<4>(st + TB + q * PB, wc * 64, lane, v);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) pb[j][q] = v[j];
-    }
-    float wf[8];
-    {
-      const int g = lane >> 4;
-#pragma unroll
-      for (int h = 0; h < 4; ++h) {
-        const f4 x = *reinterpret_cast<const f4*>(st + TB + 3 * PB + (4 * g + h) * 16);
-        const d2v y = __builtin_bit_cast(d2v, x);
-        wf[2 * h] = (float)y[0];
-        wf[2 * h + 1] = (float)y[1];
+        for (int j = 0; j < 4; ++j) pb[j][q] = v[j];
       }
+      float wf[8];
+      {
+        const int g = lane >> 4;
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          const f4 x = *reinterpret_cast<const f4*>(st + TB + 3 * PB + (4 * g + h) * 16);
+          const d2v y = __builtin_bit_cast(d2v, x);
+          wf[2 * h] = (float)y[0];
+          wf[2 * h + 1] = (float)y[1];
+        }
+      }
+      compiler_fence();
+      issue(t + 2);
+      bf8 pa[2][3];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) a[i][e] *= wf[e];
+        split3_trunc(a[i], pa[i]);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) cc[i][j] = mfma6(pa[i], pb[j], cc[i][j]);
+      }
+      flush_pipe(cc, 1.0, acc);
     }
-    compiler_fence();
-    issue(t + 2);
-    bf8 pa[2][3];
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) a[i][e] *= wf[e];
-      split<3>(a[i], pa[i]);
-    }
-    f4 cc[2][4];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) cc[i][j] = mfma6(pa[i], pb[j], f4{0.f, 0.f, 0.f, 0.f});
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[i][j][v] += (double)cc[i][j][v];
-  }
   wait_stage<0>();
   double* out = part + (((int64_t)b * nsplit + sp) * ntiles + tile) * (BT * BT);
 #pragma unroll
@@ -894,6 +945,9 @@ __global__ __launch_bounds__(PT, 1) void backproj_p3_kernel(
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_pipe[];
   constexpr int SB = 6 * PB;
   double* red = reinterpret_cast<double*>(smem_pipe + NST * SB);   // [PW][64]
+  // the directions of one block of points run together on one XCD: they stage
+  // the same tiles of the Psi^T pieces (each direction's Gamma, 6 MB at N = 1024,
+  // is re-read from the last-level cache)
   int pblk, b;
   xcd_map(blockIdx.x, (int)((M + BT - 1) / BT), batch, pblk, b);
   const int c = b % nspin;
@@ -921,33 +975,36 @@ __global__ __launch_bounds__(PT, 1) void backproj_p3_kernel(
     };
     double acc[2][4][4];
     zero_pipe(acc);
+    f4 cc[2][4];
+    zero_f32(cc);
     issue(0);
     issue(1);
-    for (int t = 0; t < nk; ++t) {
-      wait_stage<6>();
-      const unsigned char* st = smem_pipe + (t % NST) * SB;
-      bf8 pa[2][3], pb[4][3];
+    for (int t0 = 0; t0 < nk; t0 += kFlush) {
+      const int t1 = min(nk, t0 + kFlush);
+      for (int t = t0; t < t1; ++t) {
+        wait_stage<6>();
+        const unsigned char* st = smem_pipe + (t % NST) * SB;
+        bf8 pa[2][3], pb[4][3];
 #pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        bf8 va[2], vb[4];
-        frag_piece<2>(st + q * PB, wr * 32, lane, va);
-        frag_piece<4>(st + (3 + q) * PB, wc * 64, lane, vb);
+        for (int q = 0; q < 3; ++q) {
+          bf8 va[2], vb[4];
+          frag_piece<2>(st + q * PB, wr * 32, lane, va);
+          frag_piece<4>(st + (3 + q) * PB, wc * 64, lane, vb);
 #pragma unroll
-        for (int i = 0; i < 2; ++i) pa[i][q] = va[i];
+          for (int i = 0; i < 2; ++i) pa[i][q] = va[i];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) pb[j][q] = vb[j];
-      }
-      compiler_fence();
-      issue(t + 2);
-      const double f = (t * KT >= BT) ? 2.0 : 1.0;
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const f4 cc = mfma6(pa[i], pb[j], f4{0.f, 0.f, 0.f, 0.f});
-#pragma unroll
-          for (int v = 0; v < 4; ++v) acc[i][j][v] += f * (double)cc[v];
+          for (int j = 0; j < 4; ++j) pb[j][q] = vb[j];
         }
+        compiler_fence();
+        issue(t + 2);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) cc[i][j] = mfma6(pa[i], pb[j], cc[i][j]);
+      }
+      // a flush group of kFlush K-tiles (kFlush KT = BT) lies wholly on or off
+      // the diagonal block
+      flush_pipe(cc, t0 * KT >= BT ? 2.0 : 1.0, acc);
     }
     wait_stage<0>();
     float av[2][4][4];
