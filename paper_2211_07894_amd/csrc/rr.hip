@@ -16,7 +16,8 @@
 // each 64 x 64 pair problem in LDS with one or two sweeps of cyclic Jacobi
 // (1024 threads, one 2 x 2 block of the pair rotation per thread; rotations
 // t = sign(z)/(|z| + sqrt(1 + z^2)), z = (a_qq - a_pp)/(2 a_pq)); a second kernel
-// applies the pair rotations to A and to the eigenvector matrix as 64 x 64 GEMMs.
+// applies the pair rotations to A and to the eigenvector matrix as 64 x 64 GEMMs
+// on FP64 matrix cores.
 // Rotations are applied above 1e-16 ||A||_F; sweeps stop when an outer sweep
 // leaves no off-diagonal entry above 1e-13 ||A||_F (a reduction after the sweep
 // and one host read of its flag), about ten times the rounding left by the
@@ -190,26 +191,45 @@ __global__ __launch_bounds__(256) void jac_offmax_kernel(const double* __restric
   if (big) *flag = 1;
 }
 
-// 64x64x64 product C = op(X) Y with X, Y, C in LDS (pitch JP); thread (tr, tc)
-// owns a 4x4 micro-tile.  transX: C = X^T Y.
-__device__ inline void lds_gemm64(const double* X, const double* Y, double acc[4][4], bool transX) {
-  const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// 64 x 64 x 64 product C = op(X) Y with X, Y in LDS (pitch JP), on FP64 matrix
+// cores (v_mfma_f64_16x16x4f64: lane l supplies A[l%16][l/16] and B[l/16][l%16],
+// and register v of lane l holds D[4v + l/16][l%16]).  Wave w of the 256 threads
+// owns the 32 x 32 quadrant (w / 2, w % 2): acc[I][J] is its 16 x 16 tile (I, J).
+// transX: C = X^T Y.
+__device__ inline void lds_gemm64(const double* X, const double* Y, d4 (&acc)[2][2],
+                                  bool transX) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r0 = (w >> 1) * 32, c0 = (w & 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int I = 0; I < 2; ++I)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  for (int k = 0; k < JS; ++k) {
-    double a[4], b[4];
+    for (int J = 0; J < 2; ++J) acc[I][J] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int k = 0; k < JS; k += 4) {
+    double a[2], b[2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-      a[i] = transX ? X[k * JP + tr * 4 + i] : X[(tr * 4 + i) * JP + k];
+    for (int I = 0; I < 2; ++I) {
+      const int row = r0 + I * 16 + li;
+      a[I] = transX ? X[(k + lk) * JP + row] : X[row * JP + k + lk];
+    }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) b[j] = Y[k * JP + tc * 4 + j];
+    for (int J = 0; J < 2; ++J) b[J] = Y[(k + lk) * JP + c0 + J * 16 + li];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int I = 0; I < 2; ++I)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+      for (int J = 0; J < 2; ++J)
+        acc[I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[I], b[J], acc[I][J], 0, 0, 0);
   }
+}
+
+// Row and column (within the 64 x 64 tile) of register v of the lane's tile (I, J).
+__device__ inline int acc_row(int I, int v) {
+  return ((threadIdx.x >> 6) >> 1) * 32 + I * 16 + 4 * v + ((threadIdx.x & 63) >> 4);
+}
+__device__ inline int acc_col(int J) {
+  return ((threadIdx.x >> 6) & 1) * 32 + J * 16 + (threadIdx.x & 15);
 }
 
 // blocks [0, P*P): A(pair P rows, pair R cols) <- U_P^T A U_R
@@ -222,8 +242,7 @@ __global__ __launch_bounds__(256) void jac_update_kernel(double* __restrict__ A,
   __shared__ double UR[JS * JP];
   const int np = nb / 2;
   int id = blockIdx.x;
-  const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
-  double acc[4][4];
+  d4 acc[2][2];
   if (id < np * np) {
     const int P = id / np, R = id - P * np;
     const int p1 = rr_pos(P, t, nb), q1 = rr_pos(nb - 1 - P, t, nb);
@@ -242,22 +261,26 @@ __global__ __launch_bounds__(256) void jac_update_kernel(double* __restrict__ A,
     lds_gemm64(UL, X, acc, true);   // U_P^T A
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int I = 0; I < 2; ++I)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) X[(tr * 4 + i) * JP + tc * 4 + j] = acc[i][j];
+      for (int J = 0; J < 2; ++J)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) X[acc_row(I, v) * JP + acc_col(J)] = acc[I][J][v];
     __syncthreads();
     lds_gemm64(X, UR, acc, false);  // (U_P^T A) U_R
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int a = tr * 4 + i;
-      const int ga = a < JB ? p1 * JB + a : q1 * JB + (a - JB);
+    for (int I = 0; I < 2; ++I)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int c = tc * 4 + j;
-        const int gc = c < JB ? p2 * JB + c : q2 * JB + (c - JB);
-        A[(int64_t)ga * Np + gc] = acc[i][j];
+      for (int v = 0; v < 4; ++v) {
+        const int a = acc_row(I, v);
+        const int ga = a < JB ? p1 * JB + a : q1 * JB + (a - JB);
+#pragma unroll
+        for (int J = 0; J < 2; ++J) {
+          const int c = acc_col(J);
+          const int gc = c < JB ? p2 * JB + c : q2 * JB + (c - JB);
+          A[(int64_t)ga * Np + gc] = acc[I][J][v];
+        }
       }
-    }
   } else {
     id -= np * np;
     const int P = id % np, rb = id / np;
@@ -272,15 +295,17 @@ __global__ __launch_bounds__(256) void jac_update_kernel(double* __restrict__ A,
     __syncthreads();
     lds_gemm64(X, UL, acc, false);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int a = tr * 4 + i;
+    for (int I = 0; I < 2; ++I)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int c = tc * 4 + j;
-        const int gc = c < JB ? p1 * JB + c : q1 * JB + (c - JB);
-        V[(int64_t)(rb * JS + a) * Np + gc] = acc[i][j];
+      for (int v = 0; v < 4; ++v) {
+        const int a = acc_row(I, v);
+#pragma unroll
+        for (int J = 0; J < 2; ++J) {
+          const int c = acc_col(J);
+          const int gc = c < JB ? p1 * JB + c : q1 * JB + (c - JB);
+          V[(int64_t)(rb * JS + a) * Np + gc] = acc[I][J][v];
+        }
       }
-    }
   }
 }
 
