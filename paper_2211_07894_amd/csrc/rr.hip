@@ -13,7 +13,7 @@
 // Eigensolver: two-sided block Jacobi.  The matrix (padded to a multiple of 64
 // with decoupled diagonal entries 1e30) is cut into 32-wide blocks; each outer
 // round pairs blocks by a round-robin tournament and a workgroup diagonalises
-// each 64 x 64 pair problem in LDS with one or two sweeps of cyclic Jacobi
+// each 64 x 64 pair problem in LDS with one sweep of cyclic Jacobi
 // (1024 threads, one 2 x 2 block of the pair rotation per thread; rotations
 // t = sign(z)/(|z| + sqrt(1 + z^2)), z = (a_qq - a_pp)/(2 a_pq)); a second kernel
 // applies the pair rotations to A and to the eigenvector matrix as 64 x 64 GEMMs
@@ -490,8 +490,7 @@ lrdm_status sym_eigh(lrdm_ctx* ctx, const double* S, int lda, int N, const doubl
     for (int t = 0; t < nb - 1; ++t) {
       {
         ProfScope prof_solve(ctx, "jac_solve");
-        jac_solve_kernel<<<nb / 2, 1024, 0, ctx->stream>>>(A, Np, nb, t, normF, Ublk,
-                                                            sweep == 0 ? 2 : 1);
+        jac_solve_kernel<<<nb / 2, 1024, 0, ctx->stream>>>(A, Np, nb, t, normF, Ublk, 1);
       }
       if ((e = hipGetLastError()) != hipSuccess) return fail(e);
       const int np = nb / 2;
