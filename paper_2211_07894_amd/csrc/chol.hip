@@ -85,9 +85,8 @@ __global__ void chol_init_kernel(const double* __restrict__ G, const double* __r
 // registers.  Column j: its entries, as updated so far, go to an LDS column buffer
 // (two alternating buffers), and after one barrier every thread applies
 // S_il -= S_ij S_lj / S_jj to the entries it owns with l > j (nothing for a
-// dependent column).  The inverse is built row by row: X[i][c] =
-// (delta_ic - sum_{l<i} L_il X_lc) / L_ii, the sum split over four threads per c
-// (X[l][c] = 0 for l < c, so the terms below the column start vanish).
+// dependent column).  The inverse is built by substitution on 16 x 16 diagonal
+// blocks and doubling.
 constexpr int kTri = CB * (CB + 1) / 2;          // 2080 lower-triangle entries
 constexpr int kOwn = (kTri + 255) / 256;         // 9 per thread
 
@@ -96,7 +95,7 @@ __global__ __launch_bounds__(256) void chol_diag_kernel(double* __restrict__ A, 
                                                         double* __restrict__ Linv) {
   __shared__ double col[2][CB];
   __shared__ double piv[CB];
-  __shared__ double red[4][CB];
+  __shared__ double tmp[CB * CB / 4];
   __shared__ double L[CB * CP];
   __shared__ double X[CB * CP];
   const int t = threadIdx.x;
@@ -153,19 +152,36 @@ __global__ __launch_bounds__(256) void chol_diag_kernel(double* __restrict__ A, 
     X[i * CP + c] = 0.0;
   }
   __syncthreads();
-  // X = L^{-1}, row by row; thread (c, part) with c = t % 64, part = t / 64
-  {
-    const int c = t & 63, part = t >> 6;
-    for (int i = 0; i < CB; ++i) {
-      double sum = 0.0;
-      for (int l = c + part; l < i; l += 4) sum += L[i * CP + l] * X[l * CP + c];
-      red[part][c] = sum;
-      __syncthreads();
-      if (part == 0 && c <= i)
-        X[i * CP + c] = ((i == c ? 1.0 : 0.0) - (red[0][c] + red[1][c] + red[2][c] + red[3][c])) /
-                        L[i * CP + i];
-      __syncthreads();
+  // X = L^{-1}: the four 16 x 16 diagonal blocks by forward substitution (a
+  // thread per column), then doubling: X21 = -X22 (L21 X11) for neighbouring
+  // super-blocks of 16 and then 32.
+  if (t < CB) {
+    const int b0 = (t >> 4) * 16, c = b0 + (t & 15);
+    for (int i = c; i < b0 + 16; ++i) {
+      double sum = (i == c) ? 1.0 : 0.0;
+      for (int l = c; l < i; ++l) sum -= L[i * CP + l] * X[l * CP + c];
+      X[i * CP + c] = sum / L[i * CP + i];
     }
+  }
+  __syncthreads();
+  for (int h = 16; h < CB; h *= 2) {
+    const int n = (CB / (2 * h)) * h * h;  // elements of all pairs' h x h blocks
+    for (int e = t; e < n; e += 256) {
+      const int pr = e / (h * h), i = (e / h) % h, j = e % h;
+      const int c0 = 2 * h * pr, r0 = c0 + h;
+      double sum = 0.0;
+      for (int l = j; l < h; ++l) sum += L[(r0 + i) * CP + c0 + l] * X[(c0 + l) * CP + c0 + j];
+      tmp[e] = sum;
+    }
+    __syncthreads();
+    for (int e = t; e < n; e += 256) {
+      const int pr = e / (h * h), i = (e / h) % h, j = e % h;
+      const int c0 = 2 * h * pr, r0 = c0 + h;
+      double sum = 0.0;
+      for (int l = 0; l <= i; ++l) sum += X[(r0 + i) * CP + r0 + l] * tmp[pr * h * h + l * h + j];
+      X[(r0 + i) * CP + c0 + j] = -sum;
+    }
+    __syncthreads();
   }
   double* Li = Linv + (int64_t)kb * CB * CB;
   for (int e = t; e < CB * CB; e += 256) {

@@ -222,6 +222,8 @@ inline T __shfl_xor(T v, int m, int = 64) {
 inline int atomicOr(int* p, int v) {
   return std::atomic_ref<int>(*p).fetch_or(v);
 }
+inline unsigned __float_as_uint(float x) { return __builtin_bit_cast(unsigned, x); }
+inline float __uint_as_float(unsigned x) { return __builtin_bit_cast(float, x); }
 
 // ------------------------------------------------------------------ device math
 using std::exp;
