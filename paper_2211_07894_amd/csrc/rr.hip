@@ -15,7 +15,8 @@
 // round pairs blocks by a round-robin tournament and a workgroup diagonalises
 // each 64 x 64 pair problem in LDS with one sweep of cyclic Jacobi
 // (1024 threads, one 2 x 2 block of the pair rotation per thread; rotations
-// t = sign(z)/(|z| + sqrt(1 + z^2)), z = (a_qq - a_pp)/(2 a_pq)); a second kernel
+// t = sign(z)/(|z| + sqrt(1 + z^2)), z = (a_qq - a_pp)/(2 a_pq), the angle in FP32
+// and (c, s) normalised in FP64); a second kernel
 // applies the pair rotations to A and to the eigenvector matrix as 64 x 64 GEMMs
 // on FP64 matrix cores.
 // Rotations are applied above 1e-16 ||A||_F; sweeps stop when an outer sweep
@@ -91,8 +92,8 @@ __global__ __launch_bounds__(1024) void jac_solve_kernel(const double* __restric
                                                         double* __restrict__ Ublk, int max_inner) {
   __shared__ double S[JS * JP];
   __shared__ double U[JS * JP];
-  __shared__ double rc[JB], rs[JB], rt[JB];
-  __shared__ int rp[JB], rq[JB];
+  __shared__ double2 rcs[JB];   // (c, s) of the round's rotations
+  __shared__ int2 rpq[JB];      // (p, q)
   __shared__ int any_rot;
   const int pair = blockIdx.x;
   const int bp = rr_pos(pair, t, nb), bq = rr_pos(nb - 1 - pair, t, nb);
@@ -111,38 +112,37 @@ __global__ __launch_bounds__(1024) void jac_solve_kernel(const double* __restric
     __syncthreads();
     for (int r = 0; r < JS - 1; ++r) {
       if (threadIdx.x < JB) {
+        // The angle only steers convergence: any (c, s) with c^2 + s^2 = 1 is an
+        // exact rotation, and every entry, the 2 x 2 diagonal block included, is
+        // updated with the full formulas below.  So t is formed in FP32
+        // (z = (a_qq - a_pp)/(2 a_pq), t = sign(z)/(|z| + sqrt(1 + z^2))), which
+        // leaves a residual of about 1e-7 a_pq for the next sweep, and (c, s) is
+        // normalised in FP64.  |z| beyond the FP32 range gives t = 0 (no rotation).
         const int i = threadIdx.x;
         const int p = rr_pos(i, r, JS), q = rr_pos(JS - 1 - i, r, JS);
         const double apq = S[p * JP + q], app = S[p * JP + p], aqq = S[q * JP + q];
-        double c = 1.0, s = 0.0, tt = 0.0;
+        double c = 1.0, s = 0.0;
         if (fabs(apq) > thr_apply) {
-          const double z = (aqq - app) / (2.0 * apq);
-          tt = (z >= 0.0 ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
-          c = 1.0 / sqrt(1.0 + tt * tt);
-          s = tt * c;
+          const float z = (float)(aqq - app) * __builtin_amdgcn_rcpf((float)(2.0 * apq));
+          const float az = fabsf(z);
+          const float tf = __builtin_amdgcn_rcpf(az + sqrtf(1.0f + az * az));
+          const double td = (z >= 0.0f ? 1.0 : -1.0) * (double)tf;
+          c = 1.0 / sqrt(1.0 + td * td);
+          s = td * c;
           if (fabs(apq) > thr_flag) any_rot = 1;
         }
-        rp[i] = p;
-        rq[i] = q;
-        rc[i] = c;
-        rs[i] = s;
-        rt[i] = tt;
+        rpq[i] = make_int2(p, q);
+        rcs[i] = make_double2(c, s);
       }
       __syncthreads();
-      // S <- J^T S J on the 32 x 32 pair blocks
+      // S <- J^T S J on the 32 x 32 pair blocks (rows, then columns)
       for (int blk = threadIdx.x; blk < JB * JB; blk += blockDim.x) {
         const int al = blk >> 5, be = blk & 31;
-        const int p1 = rp[al], q1 = rq[al], p2 = rp[be], q2 = rq[be];
-        const double ca = rc[al], sa = rs[al], cb = rc[be], sb = rs[be];
-        if (al == be) {
-          if (sa != 0.0) {
-            const double apq = S[p1 * JP + q1], ta = rt[al];
-            S[p1 * JP + p1] -= ta * apq;
-            S[q1 * JP + q1] += ta * apq;
-            S[p1 * JP + q1] = 0.0;
-            S[q1 * JP + p1] = 0.0;
-          }
-        } else if (sa != 0.0 || sb != 0.0) {
+        const double2 ra = rcs[al], rb = rcs[be];
+        if (ra.y != 0.0 || rb.y != 0.0) {
+          const int2 ia = rpq[al], ib = rpq[be];
+          const int p1 = ia.x, q1 = ia.y, p2 = ib.x, q2 = ib.y;
+          const double ca = ra.x, sa = ra.y, cb = rb.x, sb = rb.y;
           const double b00 = S[p1 * JP + p2], b01 = S[p1 * JP + q2];
           const double b10 = S[q1 * JP + p2], b11 = S[q1 * JP + q2];
           const double x00 = ca * b00 - sa * b10, x01 = ca * b01 - sa * b11;
@@ -153,16 +153,19 @@ __global__ __launch_bounds__(1024) void jac_solve_kernel(const double* __restric
           S[q1 * JP + q2] = x10 * sb + x11 * cb;
         }
       }
-      // U <- U J
-      for (int e = threadIdx.x; e < JS * JB; e += blockDim.x) {
-        const int row = e >> 5, al = e & 31;
-        const double s = rs[al];
-        if (s != 0.0) {
-          const double c = rc[al];
-          const int p = rp[al], q = rq[al];
-          const double up = U[row * JP + p], uq = U[row * JP + q];
-          U[row * JP + p] = c * up - s * uq;
-          U[row * JP + q] = s * up + c * uq;
+      // U <- U J: thread t takes pair t % 32 in rows t / 32 and t / 32 + 32
+      {
+        const int al = threadIdx.x & 31;
+        const double2 ra = rcs[al];
+        if (ra.y != 0.0) {
+          const int2 ia = rpq[al];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int row = (threadIdx.x >> 5) + 32 * h;
+            const double up = U[row * JP + ia.x], uq = U[row * JP + ia.y];
+            U[row * JP + ia.x] = ra.x * up - ra.y * uq;
+            U[row * JP + ia.y] = ra.y * up + ra.x * uq;
+          }
         }
       }
       __syncthreads();

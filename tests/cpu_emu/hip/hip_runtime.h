@@ -58,6 +58,10 @@ struct uint3 {
 struct double2 { double x, y; };
 struct float2 { float x, y; };
 struct float4 { float x, y, z, w; };
+struct int2 { int x, y; };
+inline double2 make_double2(double x, double y) { return double2{x, y}; }
+inline int2 make_int2(int x, int y) { return int2{x, y}; }
+inline float4 make_float4(float x, float y, float z, float w) { return float4{x, y, z, w}; }
 
 extern thread_local uint3 threadIdx;
 extern thread_local uint3 blockIdx;
@@ -223,6 +227,9 @@ inline int atomicOr(int* p, int v) {
   return std::atomic_ref<int>(*p).fetch_or(v);
 }
 inline unsigned __float_as_uint(float x) { return __builtin_bit_cast(unsigned, x); }
+// v_rcp_f32 stand-in (the hardware result is within 1 ulp of this)
+inline float lrdm_emu_rcpf(float x) { return 1.0f / x; }
+#define __builtin_amdgcn_rcpf lrdm_emu_rcpf
 inline float __uint_as_float(unsigned x) { return __builtin_bit_cast(float, x); }
 
 // ------------------------------------------------------------------ device math
