@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--warm-passes", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-peaks", action="store_true",
+                    help="skip the copy and GEMM measurements of the achievable peaks")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run three 1 GiB device copies first: a kernel of known traffic for "
                          "scaling hardware byte counters")
@@ -142,9 +144,11 @@ def main():
         t_out = torch.empty((r, 1) + grid.shape, dtype=torch.float64, device=dev)
         ctx = L.context()
 
+        e_resp = torch.empty(N, dtype=torch.float64, device=dev)
+
         def step():
             L.chfsi_filter(grid, V, Xf, c, *filt, prec=form, out=Yf)
-            e = L.subspace_rayleigh_ritz(grid, V, Yf, prec=form)
+            e = L.subspace_rayleigh_ritz(grid, V, Yf, prec=form, eps=e_resp)
             L.residual_derivative(grid, Yf[None], e[None], occ, U, prec=form, out=t_out)
             return e
 
@@ -168,6 +172,13 @@ def main():
         kern = {k: ctx.profile_read(k) for k in
                 ["cheb_step", "hpsi", "proj", "gram", "backproj", "nn", "eigh", "chol", "jac_sweep", "jac_solve", "jac_update", "hartree"]}
         ms_step = 1e3 * elapsed / args.steps
+        # response only (r directions on this form's Ritz pairs): r / T_resp
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            L.residual_derivative(grid, Yf[None], e_resp[None], occ, U, prec=form, out=t_out)
+        torch.cuda.synchronize()
+        ms_resp = 1e3 * (time.perf_counter() - t0) / args.steps
         # errors in delta rho = t + u relative to the FP64 form: per stage (this
         # form's residual derivative on the FP64 Ritz pairs cast to its storage)
         # and end to end (its own filter and Rayleigh-Ritz)
@@ -184,7 +195,8 @@ def main():
             rel = float((torch.linalg.vector_norm(t_stage - ref["t"]) / drho_norm).item())
             rel_e2e = float((torch.linalg.vector_norm(t_out - ref["t"]) / drho_norm).item())
         results[form] = dict(ms_per_step=ms_step, value=r * args.steps / elapsed, kernels=kern,
-                             rel_err_vs_fp64=rel, rel_err_end_to_end=rel_e2e)
+                             rel_err_vs_fp64=rel, rel_err_end_to_end=rel_e2e,
+                             ms_response=ms_resp, response_value=1e3 * r / ms_resp)
         log(f"form {form}: {ms_step:.1f} ms/step, {r * args.steps / elapsed:.2f} directions/s; "
             + ", ".join(f"{k} {v[0] / max(v[1], 1):.3f}ms x{v[1]}" for k, v in kern.items() if v[1]))
         del Xf, Yf
@@ -231,6 +243,17 @@ def main():
                     avg_launch_ms=round(1e3 * avg_s, 4), launches=launches,
                     work_per_launch=work, source=src)
 
+    # ---- achievable peaks measured on this device (STREAM-style copy; large
+    # library GEMMs on the matrix cores), so the fraction is stated both ways
+    if not args.no_peaks:
+        measured = measure_peaks(torch, dev)
+        key = "hbm_GBs" if bound == "hbm" else {"fp64": "fp64", "fp32": "fp32"}.get(head, "bf16")
+        roofline["measured_peak"] = measured.get(key)
+        if roofline["measured_peak"]:
+            roofline["frac_of_measured"] = round(achieved / roofline["measured_peak"], 4)
+            roofline["executed_frac_of_measured"] = round(ex_rate / roofline["measured_peak"], 4)
+        roofline["measured_peaks"] = measured
+
     # ---- CPU baseline: the oracle on a bounded sample of the same workload
     cpu = None
     if not args.no_cpu_baseline:
@@ -256,6 +279,8 @@ def main():
         "rel_err_vs_fp64": hr["rel_err_vs_fp64"],
         "rel_err_end_to_end": hr["rel_err_end_to_end"],
         "forms": {f: {"value": round(v["value"], 4), "ms_per_step": round(v["ms_per_step"], 3),
+                      "response_value": round(v["response_value"], 3),
+                      "ms_response": round(v["ms_response"], 3),
                       "rel_err_vs_fp64": v["rel_err_vs_fp64"],
                       "rel_err_end_to_end": v["rel_err_end_to_end"],
                       "kernel_ms": {k: round(x[0] / max(x[1], 1), 4) for k, x in v["kernels"].items() if x[1]}}
@@ -264,6 +289,41 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def measure_peaks(torch, dev):
+    """Achievable rates on this device, for stating each roofline fraction against
+    both the nominal and the measured peak: a 1 GiB device-to-device copy (2 GiB of
+    traffic, STREAM copy), and large square GEMMs (torch.matmul, the vendor library)
+    in BF16, FP32 and FP64 on the matrix cores.  Measurement infrastructure only."""
+    out = {}
+
+    def rate(fn, work, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return work / (e0.elapsed_time(e1) / 1e3 / reps)
+
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    out["hbm_GBs"] = round(rate(lambda: b.copy_(a), 8.0 * n) / 1e9, 1)
+    del a, b
+    for key, dt, k in (("bf16", torch.bfloat16, 8192), ("fp32", torch.float32, 8192),
+                       ("fp64", torch.float64, 8192)):
+        x = torch.randn(k, k, device=dev).to(dt)
+        y = torch.randn(k, k, device=dev).to(dt)
+        out[key] = round(rate(lambda: torch.matmul(x, y), 2.0 * k ** 3, reps=3) / 1e12, 1)
+        del x, y
+    torch.cuda.synchronize()
+    log("measured peaks: " + ", ".join(f"{k} {v}" for k, v in out.items()))
+    return out
 
 
 def cpu_baseline(wl, filt):
