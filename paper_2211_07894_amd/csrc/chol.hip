@@ -313,16 +313,40 @@ __global__ __launch_bounds__(256) void chol_bgemm_kernel(int m, int n, int k, do
 
 // Live-row permutation: perm[r] = index of the r-th independent row (r < k), the
 // dependent rows after them; sc[2] = k.  One thread (N is at most a few thousand).
-__global__ void chol_perm_kernel(const int* __restrict__ dead, int N, int* __restrict__ perm,
-                                 double* __restrict__ sc) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  int r = 0;
-  for (int i = 0; i < N; ++i)
-    if (!dead[i]) perm[r++] = i;
-  const int k = r;
-  for (int i = 0; i < N; ++i)
-    if (dead[i]) perm[r++] = i;
-  sc[2] = (double)k;
+__global__ __launch_bounds__(1024) void chol_perm_kernel(const int* __restrict__ dead, int N,
+                                                        int* __restrict__ perm,
+                                                        double* __restrict__ sc) {
+  // one block of 1024 threads: chunks of 1024 rows, a scan of the live flags per
+  // chunk; live rows go to their rank, dependent rows after the k live ones
+  __shared__ int scan[1024];
+  __shared__ int base_live, total_live;
+  const int t = threadIdx.x;
+  if (t == 0) {
+    int k = 0;
+    for (int i = 0; i < N; ++i) k += dead[i] ? 0 : 1;   // N reads, once
+    total_live = k;
+    base_live = 0;
+  }
+  __syncthreads();
+  const int k = total_live;
+  for (int c0 = 0; c0 < N; c0 += 1024) {
+    const int i = c0 + t;
+    const int live = (i < N && !dead[i]) ? 1 : 0;
+    scan[t] = live;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      const int v = t >= off ? scan[t - off] : 0;
+      __syncthreads();
+      scan[t] += v;
+      __syncthreads();
+    }
+    const int before_live = base_live + scan[t] - live;   // live rows before i
+    if (i < N) perm[live ? before_live : k + (i - before_live)] = i;
+    __syncthreads();
+    if (t == 1023) base_live += scan[1023];
+    __syncthreads();
+  }
+  if (t == 0) sc[2] = (double)k;
 }
 
 // T[r][j] = X[perm[r]][j] (unscaled).
@@ -493,7 +517,7 @@ lrdm_status chol_orth(lrdm_ctx* ctx, const double* G, int N, double tau, double*
       if ((e = hipGetLastError()) != hipSuccess) return fail(e);
     }
   }
-  chol_perm_kernel<<<1, 64, 0, ctx->stream>>>(dead, N, perm, sc);
+  chol_perm_kernel<<<1, 1024, 0, ctx->stream>>>(dead, N, perm, sc);
   chol_rows_kernel<<<dim3((N + 31) / 32, (N + 7) / 8), blk, 0, ctx->stream>>>(X, Np, N, perm, sc,
                                                                               T);
   // ||Gs^{-1}||_2 on the independent rows = ||T_k^T T_k||_2 (unscaled T): power iteration

@@ -334,10 +334,15 @@ __global__ void jac_init_kernel(const double* __restrict__ src, int lda, int N, 
 
 // Ascending order of diag(A) by rank (ties by index, NaN last): always a
 // permutation, so the gather below stays in bounds whatever the data.
+// The diagonal is staged in LDS (Np doubles of dynamic shared memory).
 __global__ void jac_rank_kernel(const double* __restrict__ A, int Np, int* __restrict__ perm) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char diag_raw[];
+  double* diag_lds = reinterpret_cast<double*>(diag_raw);
+  for (int i = threadIdx.x; i < Np; i += blockDim.x) diag_lds[i] = A[(int64_t)i * (Np + 1)];
+  __syncthreads();
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= Np) return;
-  perm[order_rank(A, Np + 1, Np, k)] = k;
+  perm[order_rank(diag_lds, 1, Np, k)] = k;
 }
 
 __global__ void jac_gather_kernel(const double* __restrict__ A, const double* __restrict__ V,
@@ -518,7 +523,7 @@ lrdm_status sym_eigh(lrdm_ctx* ctx, const double* S, int lda, int N, const doubl
       return LRDM_ENOTCONV;
     }
   }
-  jac_rank_kernel<<<(Np + 255) / 256, 256, 0, ctx->stream>>>(A, Np, perm);
+  jac_rank_kernel<<<(Np + 255) / 256, 256, (size_t)Np * sizeof(double), ctx->stream>>>(A, Np, perm);
   if ((e = hipGetLastError()) != hipSuccess) return fail(e);
   dim3 blk(32, 8), grd((N + 31) / 32, (N + 7) / 8);
   jac_gather_kernel<<<grd, blk, 0, ctx->stream>>>(A, V, Np, N, perm, evals, evecs);
