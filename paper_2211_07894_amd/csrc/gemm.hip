@@ -328,15 +328,18 @@ __global__ __launch_bounds__(256, 2) void backproj_f64_kernel(
 }
 
 // ------------------------------------------------------------------ nn
-// Out[i][p] = sum_j Wt[j][i] B[j][p]; grid x = point block, y = row block.
+// Out[i][p] = sum_j Wt[j][i] B[j][p]; 1-D grid over (point block, row block), the
+// row blocks of one point block together on one XCD (they read the same slice of B).
 template <typename T>
 __global__ __launch_bounds__(256, 2) void nn_f64_kernel(const double* __restrict__ Wt,
                                                         const T* __restrict__ B,
                                                         T* __restrict__ Out, int N, int64_t M) {
   __shared__ double Ws[KT * LDP];
   __shared__ double Bs[KT * LDP];
-  const int64_t p0 = (int64_t)blockIdx.x * BT;
-  const int i0 = blockIdx.y * BT;
+  int pblk, rblk;
+  xcd_map(blockIdx.x, (int)((M + BT - 1) / BT), (N + BT - 1) / BT, pblk, rblk);
+  const int64_t p0 = (int64_t)pblk * BT;
+  const int i0 = rblk * BT;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int wr = wid >> 1, wc = wid & 1;
   d4 acc[4][4];
@@ -535,7 +538,7 @@ hipError_t launch_backproj<double>(lrdm_ctx* ctx, const double* A, const double*
 
 template <typename S>
 hipError_t launch_nn_f64(lrdm_ctx* ctx, const double* Wt, const S* B, S* Out, int N, int64_t M) {
-  dim3 grd((unsigned)((M + BT - 1) / BT), (N + BT - 1) / BT);
+  const unsigned grd = (unsigned)((M + BT - 1) / BT) * (unsigned)((N + BT - 1) / BT);
   ProfScope prof(ctx, "nn");
   nn_f64_kernel<S><<<grd, 256, 0, ctx->stream>>>(Wt, B, Out, N, M);
   return hipGetLastError();
