@@ -240,9 +240,10 @@ __device__ inline int acc_col(int J) {
 __global__ __launch_bounds__(256) void jac_update_kernel(double* __restrict__ A,
                                                          double* __restrict__ V, int Np, int nb,
                                                          int t, const double* __restrict__ Ublk) {
+  // two 64 x 64 tiles of LDS (66 KB), so that two workgroups share a CU; U_R
+  // takes U_P's place once U_P^T A is formed
   __shared__ double X[JS * JP];
   __shared__ double UL[JS * JP];
-  __shared__ double UR[JS * JP];
   const int np = nb / 2;
   int id = blockIdx.x;
   d4 acc[2][2];
@@ -258,7 +259,6 @@ __global__ __launch_bounds__(256) void jac_update_kernel(double* __restrict__ A,
       const int gc = c < JB ? p2 * JB + c : q2 * JB + (c - JB);
       X[a * JP + c] = A[(int64_t)ga * Np + gc];
       UL[a * JP + c] = UPg[e];
-      UR[a * JP + c] = URg[e];
     }
     __syncthreads();
     lds_gemm64(UL, X, acc, true);   // U_P^T A
@@ -269,8 +269,12 @@ __global__ __launch_bounds__(256) void jac_update_kernel(double* __restrict__ A,
       for (int J = 0; J < 2; ++J)
 #pragma unroll
         for (int v = 0; v < 4; ++v) X[acc_row(I, v) * JP + acc_col(J)] = acc[I][J][v];
+    for (int e = threadIdx.x; e < JS * JS; e += blockDim.x) {
+      const int a = e / JS, c = e - a * JS;
+      UL[a * JP + c] = URg[e];
+    }
     __syncthreads();
-    lds_gemm64(X, UR, acc, false);  // (U_P^T A) U_R
+    lds_gemm64(X, UL, acc, false);  // (U_P^T A) U_R
 #pragma unroll
     for (int I = 0; I < 2; ++I)
 #pragma unroll
