@@ -331,9 +331,12 @@ __global__ __launch_bounds__(256, 2) void backproj_f64_kernel(
 // Out[i][p] = sum_j Wt[j][i] B[j][p]; 1-D grid over (point block, row block), the
 // row blocks of one point block together on one XCD (they read the same slice of B).
 template <typename T>
+// upper: Wt is upper triangular (Wt[j][i] = 0 for j > i), so row block i0 needs
+// only k < i0 + BT.
 __global__ __launch_bounds__(256, 2) void nn_f64_kernel(const double* __restrict__ Wt,
                                                         const T* __restrict__ B,
-                                                        T* __restrict__ Out, int N, int64_t M) {
+                                                        T* __restrict__ Out, int N, int64_t M,
+                                                        int upper) {
   __shared__ double Ws[KT * LDP];
   __shared__ double Bs[KT * LDP];
   int pblk, rblk;
@@ -349,14 +352,15 @@ __global__ __launch_bounds__(256, 2) void nn_f64_kernel(const double* __restrict
     for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
   RowLoad<double> lw;
   RowLoad<T> lb;
+  const int kmax = upper ? min(N, i0 + BT) : N;
   lw.load(Wt, N, N, N, 0, i0, 1.0);
   lb.load(B, M, N, M, 0, p0, 1.0);
-  for (int j0 = 0; j0 < N; j0 += KT) {
+  for (int j0 = 0; j0 < kmax; j0 += KT) {
     __syncthreads();
     lw.store(Ws);
     lb.store(Bs);
     __syncthreads();
-    if (j0 + KT < N) {
+    if (j0 + KT < kmax) {
       lw.load(Wt, N, N, N, j0 + KT, i0, 1.0);
       lb.load(B, M, N, M, j0 + KT, p0, 1.0);
     }
@@ -537,16 +541,17 @@ hipError_t launch_backproj<double>(lrdm_ctx* ctx, const double* A, const double*
 }
 
 template <typename S>
-hipError_t launch_nn_f64(lrdm_ctx* ctx, const double* Wt, const S* B, S* Out, int N, int64_t M) {
+hipError_t launch_nn_f64(lrdm_ctx* ctx, const double* Wt, const S* B, S* Out, int N, int64_t M,
+                         bool upper) {
   const unsigned grd = (unsigned)((M + BT - 1) / BT) * (unsigned)((N + BT - 1) / BT);
   ProfScope prof(ctx, "nn");
-  nn_f64_kernel<S><<<grd, 256, 0, ctx->stream>>>(Wt, B, Out, N, M);
+  nn_f64_kernel<S><<<grd, 256, 0, ctx->stream>>>(Wt, B, Out, N, M, upper ? 1 : 0);
   return hipGetLastError();
 }
 template hipError_t launch_nn_f64<double>(lrdm_ctx*, const double*, const double*, double*, int,
-                                          int64_t);
+                                          int64_t, bool);
 template hipError_t launch_nn_f64<float>(lrdm_ctx*, const double*, const float*, float*, int,
-                                         int64_t);
+                                         int64_t, bool);
 
 template <typename T>
 hipError_t launch_adj_psi(lrdm_ctx* ctx, const double* X1, const double* w1, const double* X2,

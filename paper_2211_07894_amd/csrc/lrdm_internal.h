@@ -140,9 +140,11 @@ hipError_t launch_backproj(lrdm_ctx* ctx, const T* A, const double* G, int N, in
                            double* out);
 
 // Out[i][p] = sum_j Wt[j][i] B[j][p]  (Out = Wt^T B), Wt double N x N, FP64
-// arithmetic for either storage type of B and Out.
+// arithmetic for either storage type of B and Out.  upper: Wt is upper triangular
+// (Out = L B with L lower triangular), and the zero blocks are skipped.
 template <typename S>
-hipError_t launch_nn_f64(lrdm_ctx* ctx, const double* Wt, const S* B, S* Out, int N, int64_t M);
+hipError_t launch_nn_f64(lrdm_ctx* ctx, const double* Wt, const S* B, S* Out, int N, int64_t M,
+                         bool upper = false);
 
 // Adjoint rotation (gemm.hip): Out_c = scale * sum_m (X_m Psi_c) o w_m over two lists
 // of nx symmetric matrices [nx][nspin][N][N] with weights [nx][nspin][M], FP64

@@ -597,7 +597,8 @@ lrdm_status rayleigh_ritz(lrdm_ctx* ctx, const Grid3& g, const double* V, T* Psi
         return LRDM_ENOTCONV;
       }
       transpose_kernel<<<grd, blk, 0, ctx->stream>>>(Tm, N, Wt);
-      if ((e = launch_nn_f64<T>(ctx, Wt, B, spare, N, M)) != hipSuccess)
+      // with every row independent the factor is lower triangular (no reordering)
+      if ((e = launch_nn_f64<T>(ctx, Wt, B, spare, N, M, ci.live == N)) != hipSuccess)
         return fail("rotation", e);
       if (pass > 1 && ci.live < N) {
         fill_rows_kernel<T><<<dim3((unsigned)((M + 255) / 256), N - ci.live), 256, 0,
