@@ -175,7 +175,18 @@ lrdm_status chfsi_filter(lrdm_ctx* ctx, const lrdm_grid* grid, const double* V,
  * filtered block, project H, diagonalise the N x N projection in FP64 on the
  * GPU and rotate.  Psi [N][nz][ny][nx]: in = filtered block, out = Ritz
  * vectors (l2-orthonormal); eps [N] double, ascending.  Each channel of a
- * spin-polarised system is a separate call with its own V. */
+ * spin-polarised system is a separate call with its own V.
+ * Orthonormalisation: column-scaled Cholesky QR in FP64 arithmetic, one pass
+ * for a well-conditioned block, a second pass over the explicitly formed basis
+ * for an ill-conditioned one.  Rows numerically dependent on the rows before
+ * them are resolved through their explicit residuals; rows still dependent
+ * after that (exact copies, zero rows) are replaced by fixed pseudo-random rows,
+ * so the output is orthonormal for any input.  The Ritz pairs of such completed
+ * directions are not determined by the input.  Synchronises the stream (the
+ * pass count and the eigensolver's stop are decided on the host).  Errors:
+ * EINVAL (arguments), ENOMEM (workspace), EDEVICE, ENOTCONV (eigensolver
+ * without convergence in 40 sweeps, checking mode, or a block that five passes
+ * could not orthonormalise). */
 lrdm_status subspace_rayleigh_ritz(lrdm_ctx* ctx, const lrdm_grid* grid, const double* V,
                                    void* Psi, int32_t N, lrdm_prec prec, double* eps);
 
