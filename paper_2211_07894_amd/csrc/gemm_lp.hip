@@ -64,30 +64,32 @@ __device__ inline void split(const float (&x)[8], bf8 (&p)[NP]) {
   }
 }
 
-// Exact three-piece split of 8 FP32 values by truncation: hi keeps the top 16
-// bits of x (sign, exponent, 7 fraction bits), mid those of x - hi, lo those of
-// x - hi - mid; each remainder is exact (Sterbenz) and the last has at most 8
-// significant bits, so hi + mid + lo = x.  |mid| < 2^-7 |x|, |lo| < 2^-15 |x|.
-// Integer masks and FP32 subtractions only, with the bf16 pairs packed directly.
-__device__ inline void split3_trunc(const float (&x)[8], bf8 (&p)[3]) {
+// Exact three-piece split of 8 FP32 values with round-to-nearest pieces (as the
+// pre-split operands): pairs of values are converted together (one packed
+// conversion per pair and piece), and each piece is widened back by placing its
+// 16 bits in the high half of an FP32.  |mid| <= 2^-9 |x|, |lo| <= 2^-17 |x|.
+__device__ inline void split3_rne(const float (&x)[8], bf8 (&p)[3]) {
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  typedef __bf16 b2 __attribute__((ext_vector_type(2)));
   typedef unsigned u4 __attribute__((ext_vector_type(4)));
-  u4 h, m, l;
+  u4 w[3];
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
-    const unsigned b0 = __float_as_uint(x[2 * e]), b1 = __float_as_uint(x[2 * e + 1]);
-    const float r0 = x[2 * e] - __uint_as_float(b0 & 0xffff0000u);
-    const float r1 = x[2 * e + 1] - __uint_as_float(b1 & 0xffff0000u);
-    const unsigned c0 = __float_as_uint(r0), c1 = __float_as_uint(r1);
-    const float s0 = r0 - __uint_as_float(c0 & 0xffff0000u);
-    const float s1 = r1 - __uint_as_float(c1 & 0xffff0000u);
-    const unsigned d0 = __float_as_uint(s0), d1 = __float_as_uint(s1);
-    h[e] = (b0 >> 16) | (b1 & 0xffff0000u);
-    m[e] = (c0 >> 16) | (c1 & 0xffff0000u);
-    l[e] = (d0 >> 16) | (d1 & 0xffff0000u);
+    f2 r = {x[2 * e], x[2 * e + 1]};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const b2 h = __builtin_convertvector(r, b2);
+      const unsigned hb = __builtin_bit_cast(unsigned, h);
+      w[q][e] = hb;
+      if (q < 2) {
+        const f2 hf = {__uint_as_float(hb << 16), __uint_as_float(hb & 0xffff0000u)};
+        r = r - hf;
+      }
+    }
   }
-  p[0] = __builtin_bit_cast(bf8, h);
-  p[1] = __builtin_bit_cast(bf8, m);
-  p[2] = __builtin_bit_cast(bf8, l);
+  p[0] = __builtin_bit_cast(bf8, w[0]);
+  p[1] = __builtin_bit_cast(bf8, w[1]);
+  p[2] = __builtin_bit_cast(bf8, w[2]);
 }
 
 // Lane-local fragment of rows (base + 16i + lane%16), k = 8(lane/16) .. +7.
@@ -488,7 +490,7 @@ __device__ inline void compiler_fence() { asm volatile("" ::: "memory"); }
 // FP32 partial sums of the BF16X3 kernels are added into FP64 every kFlush
 // K-tiles (kFlush * KT = 128 terms of each product).
 constexpr int kFlush = 4;
-static_assert(kFlush * KT == BT, "flush groups must match the diagonal blocks");
+static_assert(BT % (kFlush * KT) == 0, "flush groups must not straddle the diagonal blocks");
 
 __device__ inline void zero_f32(f4 (&cc)[2][4]) {
 #pragma unroll
@@ -912,7 +914,7 @@ __global__ __launch_bounds__(PT, 1) void tn_sym_p3_kernel(
       for (int i = 0; i < 2; ++i) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) a[i][e] *= wf[e];
-        split3_trunc(a[i], pa[i]);
+        split3_rne(a[i], pa[i]);
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
