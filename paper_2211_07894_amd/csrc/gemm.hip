@@ -340,7 +340,9 @@ __global__ __launch_bounds__(256, 2) void nn_f64_kernel(const double* __restrict
   __shared__ double Ws[KT * LDP];
   __shared__ double Bs[KT * LDP];
   int pblk, rblk;
-  xcd_map(blockIdx.x, (int)((M + BT - 1) / BT), (N + BT - 1) / BT, pblk, rblk);
+  const int nrb = (N + BT - 1) / BT;
+  xcd_map(blockIdx.x, (int)((M + BT - 1) / BT), nrb, pblk, rblk);
+  if (upper) rblk = nrb - 1 - rblk;   // the longest row blocks first
   const int64_t p0 = (int64_t)pblk * BT;
   const int i0 = rblk * BT;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;

@@ -158,22 +158,25 @@ hipError_t launch_stencil(lrdm_ctx* ctx, const Grid3& g, const double* V, const 
 template <typename T, int W>
 using vec_t = T __attribute__((ext_vector_type(W)));
 
-// Vectorised recurrence step; W points per 16-byte group, Q groups per thread.
-template <typename T, int Q>
-__global__ __launch_bounds__(1024) void cheb_vec_kernel(const T* __restrict__ Yin, const T* Yold,
+// Vectorised step; W points per 16-byte group of the input type TI, Q groups per
+// thread; arithmetic, V and Yout in T (T = TI for the recurrence, T = double for
+// H Y of an FP32 block).
+template <typename TI, typename T, int Q>
+__global__ __launch_bounds__(1024) void cheb_vec_kernel(const TI* __restrict__ Yin, const TI* Yold,
                                                        T* Yout, const T* __restrict__ Vt, int nx,
                                                        int ny, int nz, int zrun, T wx, T wy, T wz,
                                                        T dshift, T alpha, T beta) {
-  constexpr int W = 16 / sizeof(T);
+  constexpr int W = 16 / sizeof(TI);
   using V = vec_t<T, W>;
+  using VI = vec_t<TI, W>;
   extern __shared__ unsigned char smem_raw[];
   V* plane = reinterpret_cast<V*>(smem_raw);
   const int P = nx * ny, G = P / W, nxg = nx / W;
   const int64_t MG = (int64_t)G * nz;
   const int z0 = blockIdx.y * zrun;
   const int z1 = min(nz, z0 + zrun);
-  const V* yin = reinterpret_cast<const V*>(Yin) + (int64_t)blockIdx.x * MG;
-  const V* yold = Yold ? reinterpret_cast<const V*>(Yold) + (int64_t)blockIdx.x * MG : nullptr;
+  const VI* yin = reinterpret_cast<const VI*>(Yin) + (int64_t)blockIdx.x * MG;
+  const VI* yold = Yold ? reinterpret_cast<const VI*>(Yold) + (int64_t)blockIdx.x * MG : nullptr;
   V* yout = reinterpret_cast<V*>(Yout) + (int64_t)blockIdx.x * MG;
   const V* vg = reinterpret_cast<const V*>(Vt);
   const V zero = V(T(0));
@@ -189,15 +192,15 @@ __global__ __launch_bounds__(1024) void cheb_vec_kernel(const T* __restrict__ Yi
       const int gi = threadIdx.x + j * blockDim.x;
       prev[j] = cur[j] = next[j] = ahead[j] = o0[j] = o1[j] = v0[j] = v1[j] = zero;
       if (gi < G) {
-        prev[j] = yin[(int64_t)zm * G + gi];
-        cur[j] = yin[(int64_t)z0 * G + gi];
-        next[j] = yin[(int64_t)zp * G + gi];
+        prev[j] = __builtin_convertvector(yin[(int64_t)zm * G + gi], V);
+        cur[j] = __builtin_convertvector(yin[(int64_t)z0 * G + gi], V);
+        next[j] = __builtin_convertvector(yin[(int64_t)zp * G + gi], V);
         v0[j] = vg[(int64_t)z0 * G + gi];
-        if (yold) o0[j] = yold[(int64_t)z0 * G + gi];
+        if (yold) o0[j] = __builtin_convertvector(yold[(int64_t)z0 * G + gi], V);
         if (m1) {
-          ahead[j] = yin[(int64_t)zpp * G + gi];
+          ahead[j] = __builtin_convertvector(yin[(int64_t)zpp * G + gi], V);
           v1[j] = vg[(int64_t)(z0 + 1) * G + gi];
-          if (yold) o1[j] = yold[(int64_t)(z0 + 1) * G + gi];
+          if (yold) o1[j] = __builtin_convertvector(yold[(int64_t)(z0 + 1) * G + gi], V);
         }
       }
     }
@@ -215,11 +218,13 @@ __global__ __launch_bounds__(1024) void cheb_vec_kernel(const T* __restrict__ Yi
     // loads two planes ahead, issued before this plane's arithmetic
     const bool more2 = z + 2 < z1;
     const int zy = (z + 3 >= nz) ? z + 3 - nz : z + 3;
-    V ny_[Q], nv[Q], no[Q];
+    VI ny_[Q], no[Q];
+    V nv[Q];
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
       const int gi = threadIdx.x + j * blockDim.x;
-      ny_[j] = nv[j] = no[j] = zero;
+      ny_[j] = no[j] = VI(TI(0));
+      nv[j] = zero;
       if (gi < G && more2) {
         ny_[j] = yin[(int64_t)zy * G + gi];
         nv[j] = vg[(int64_t)(z + 2) * G + gi];
@@ -253,9 +258,9 @@ __global__ __launch_bounds__(1024) void cheb_vec_kernel(const T* __restrict__ Yi
       prev[j] = cur[j];
       cur[j] = next[j];
       next[j] = ahead[j];
-      ahead[j] = ny_[j];
+      ahead[j] = __builtin_convertvector(ny_[j], V);
       o0[j] = o1[j];
-      o1[j] = no[j];
+      o1[j] = __builtin_convertvector(no[j], V);
       v0[j] = v1[j];
       v1[j] = nv[j];
     }
@@ -263,19 +268,20 @@ __global__ __launch_bounds__(1024) void cheb_vec_kernel(const T* __restrict__ Yi
   }
 }
 
-template <typename T, int Q>
-hipError_t launch_vec(lrdm_ctx* ctx, const Grid3& g, const T* Vt, const T* Yin, const T* Yold,
-                      T* Yout, int N, int threads, int zrun, double alpha, double c0, double beta) {
+template <typename TI, typename T, int Q>
+hipError_t launch_vec(lrdm_ctx* ctx, const char* scope, const Grid3& g, const T* Vt, const TI* Yin,
+                      const TI* Yold, T* Yout, int N, int threads, int zrun, double alpha,
+                      double c0, double beta) {
   const int P = g.nx * g.ny;
   const size_t smem = 2 * (size_t)P * sizeof(T);
   const T wx = T(-0.5 / (g.hx * g.hx)), wy = T(-0.5 / (g.hy * g.hy)), wz = T(-0.5 / (g.hz * g.hz));
   const T dshift = T(1.0 / (g.hx * g.hx) + 1.0 / (g.hy * g.hy) + 1.0 / (g.hz * g.hz) - c0);
   dim3 grd(N, (g.nz + zrun - 1) / zrun);
   if (smem > 65536)
-    LRDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&cheb_vec_kernel<T, Q>),
+    LRDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&cheb_vec_kernel<TI, T, Q>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
-  ProfScope prof(ctx, "cheb_step");
-  cheb_vec_kernel<T, Q><<<grd, threads, smem, ctx->stream>>>(
+  ProfScope prof(ctx, scope);
+  cheb_vec_kernel<TI, T, Q><<<grd, threads, smem, ctx->stream>>>(
       Yin, beta != 0.0 ? Yold : nullptr, Yout, Vt, g.nx, g.ny, g.nz, zrun, wx, wy, wz, dshift,
       T(alpha), T(beta));
   return hipGetLastError();
@@ -313,8 +319,10 @@ hipError_t launch_cheb_step_vec(lrdm_ctx* ctx, const Grid3& g, const T* Vt, cons
   while ((int64_t)N * runs < 1024 && g.nz / (runs * 2) >= 8) runs *= 2;
   const int zrun = (g.nz + runs - 1) / runs;
   if (G <= threads)
-    return launch_vec<T, 1>(ctx, g, Vt, Yin, Yold, Yout, N, threads, zrun, alpha, c0, beta);
-  return launch_vec<T, 2>(ctx, g, Vt, Yin, Yold, Yout, N, threads, zrun, alpha, c0, beta);
+    return launch_vec<T, T, 1>(ctx, "cheb_step", g, Vt, Yin, Yold, Yout, N, threads, zrun, alpha,
+                               c0, beta);
+  return launch_vec<T, T, 2>(ctx, "cheb_step", g, Vt, Yin, Yold, Yout, N, threads, zrun, alpha,
+                             c0, beta);
 }
 
 template bool cheb_vec_ok<double>(const Grid3&);
@@ -338,6 +346,17 @@ hipError_t launch_cheb_step(lrdm_ctx* ctx, const Grid3& g, const double* V, cons
 template <typename T>
 hipError_t launch_hpsi_f64(lrdm_ctx* ctx, const Grid3& g, const double* V, const T* Y, double* HY,
                            int N) {
+  constexpr int W = 16 / sizeof(T);
+  auto aligned = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  const int G = g.nx * g.ny / W;
+  if (cheb_vec_ok<T>(g) && G <= 1024 && aligned(Y) && aligned(HY) && aligned(V)) {
+    const int threads = ((G + 63) / 64) * 64;
+    int runs = 1;
+    while ((int64_t)N * runs < 1024 && g.nz / (runs * 2) >= 8) runs *= 2;
+    const int zrun = (g.nz + runs - 1) / runs;
+    return launch_vec<T, double, 1>(ctx, "hpsi", g, V, Y, nullptr, HY, N, threads, zrun, 1.0, 0.0,
+                                    0.0);
+  }
   return launch_stencil<T, double>(ctx, g, V, Y, nullptr, HY, N, 1.0, 0.0, 0.0);
 }
 
