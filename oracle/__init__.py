@@ -32,4 +32,11 @@ from .lrdm_oracle import (  # noqa: F401
     fermi_derivatives,
     second_divided_differences,
     density_response_vjp,
+    inner,
+    lowrank_preconditioner,
+    damping,
+    effective_potential,
+    lowest_states,
+    scf_residual,
+    lrdm_scf,
 )

@@ -286,6 +286,113 @@ def residual_derivative(Psi: np.ndarray, eps: np.ndarray, grid: Grid, n_electron
 
 
 # ---------------------------------------------------------------------------
+# Low-rank approximation of J and the damped quasi-Newton step (Sec. II B,
+# Eqs. (4), (7)-(10)) on a model SCF map rho -> F[V_eff[rho]] (Sec. II A)
+# ---------------------------------------------------------------------------
+def inner(a: np.ndarray, b: np.ndarray, grid: Grid) -> float:
+    """<a, b>, the integral of a b over the cell (Sec. II A), as dv times the sum
+    over grid points; for a spin-polarised pair the sum also runs over both
+    channels (the direct-sum inner product of Sec. II D)."""
+    return grid.dv * float(np.sum(a * b))
+
+
+def lowrank_preconditioner(R: np.ndarray, apply_t, grid: Grid, s_tol: float, r_max: int):
+    """drho_bar = P^lr_r R (Eq. (9)) with the rank r chosen adaptively (Eq. (10)).
+
+    u_1 = R / ||R||.  For each direction u_i, t_i = apply_t(u_i) is the directional
+    derivative of the residual along u_i (Eq. (7)).  With the t's so far,
+    S_ij = <t_i, t_j>, c_j = <t_j, R>, y = S^{-1} c and
+    s_rel = ||sum_i t_i y_i - R|| / ||R||.  Stop when s_rel < s_tol or r = r_max;
+    otherwise the next direction is t_i minus its projections on u_1..u_i (all
+    taken from t_i itself), normalised (Eq. (8)).
+
+    Returns (drho_bar = sum_i y_i u_i, U [r][...], T [r][...], s_rel after each
+    rank [r]).  A zero residual gives drho_bar = 0 and rank 0."""
+    nR = np.sqrt(inner(R, R, grid))
+    if nR == 0.0:
+        return np.zeros_like(R), np.zeros((0,) + R.shape), np.zeros((0,) + R.shape), np.zeros(0)
+    U = [R / nR]
+    T = []
+    hist = []
+    while True:
+        T.append(apply_t(U[-1]))
+        r = len(T)
+        S = np.array([[inner(T[i], T[j], grid) for j in range(r)] for i in range(r)])
+        c = np.array([inner(T[j], R, grid) for j in range(r)])
+        y = np.linalg.solve(S, c)
+        fit = sum(y[i] * T[i] for i in range(r))
+        hist.append(np.sqrt(inner(fit - R, fit - R, grid)) / nR)
+        if hist[-1] < s_tol or r == r_max:
+            break
+        u = T[-1]
+        u = u - sum(inner(u, U[k], grid) * U[k] for k in range(r))
+        U.append(u / np.sqrt(inner(u, u, grid)))
+    drho = sum(y[i] * U[i] for i in range(r))
+    return drho, np.array(U), np.array(T), np.array(hist)
+
+
+def damping(norm_R: float, far: float = 0.1, near: float = 0.5, switch: float = 1.0) -> float:
+    """alpha of the quasi-Newton step (Eq. (4)) as Sec. II B sets it: the small
+    value while ||R|| is at or above a threshold of order one, the larger below."""
+    return far if norm_R >= switch else near
+
+
+def effective_potential(V_ext: np.ndarray, rho: np.ndarray, grid: Grid) -> np.ndarray:
+    """V_eff[rho] = V_ext + V_H[rho] (Eq. (1)) with V_H = K_c applied to the total
+    density (no exchange-correlation term: the kernel is K = K_c, as in the
+    response).  rho: [nspin][nz][ny][nx] or [nz][ny][nx]."""
+    return V_ext + hartree_kernel(rho.reshape((-1,) + grid.shape).sum(axis=0), grid)
+
+
+def lowest_states(V: np.ndarray, grid: Grid, N: int):
+    """The N lowest eigenpairs of H = -1/2 Lap_h + V by dense diagonalisation of
+    the M x M matrix (tiny grids only).  Returns (eps [N], Psi [N][nz][ny][nx])."""
+    M = grid.M
+    Hd = hamiltonian_apply(np.eye(M).reshape((M,) + grid.shape), V, grid).reshape(M, M)
+    w, Q = np.linalg.eigh(0.5 * (Hd + Hd.T))
+    return w[:N], Q[:, :N].T.reshape((N,) + grid.shape).copy()
+
+
+def scf_residual(rho: np.ndarray, V_ext: np.ndarray, grid: Grid, N: int, n_electrons: float,
+                 kT: float, nspin: int = 1):
+    """R[rho] = F[V_eff[rho]] - rho (Sec. II A): the output density of the N lowest
+    states of H[V_eff[rho]] minus the input.  Without an exchange-correlation
+    term both channels of a spin-polarised pair see the same potential.
+    Returns (R [nspin][nz][ny][nx], Psi [nspin][N][...], eps [nspin][N])."""
+    rho = rho.reshape((nspin,) + grid.shape)
+    eps, Psi = lowest_states(effective_potential(V_ext, rho, grid), grid, N)
+    Psi = np.stack([Psi] * nspin)
+    eps = np.stack([eps] * nspin)
+    rho_out, _ = density(Psi, eps, grid, n_electrons, kT, nspin)
+    return rho_out - rho, Psi, eps
+
+
+def lrdm_scf(rho0: np.ndarray, V_ext: np.ndarray, grid: Grid, N: int, n_electrons: float,
+             kT: float, nspin: int = 1, s_tol: float = 0.3, r_max: int = 20,
+             tol: float = 1e-9, max_iter: int = 50):
+    """SCF by the damped quasi-Newton step rho <- rho - alpha P^lr_r R (Eq. (4),
+    Sec. II B) with the directional derivatives of Eq. (7) from the subspace
+    density response.  Returns (rho, [(||R||, rank, s_rel, alpha) per step])."""
+    rho = rho0.reshape((nspin,) + grid.shape).copy()
+    log = []
+    for _ in range(max_iter):
+        R, Psi, eps = scf_residual(rho, V_ext, grid, N, n_electrons, kT, nspin)
+        nR = np.sqrt(inner(R, R, grid))
+        if nR < tol:
+            log.append((nR, 0, 0.0, 0.0))
+            break
+
+        def apply_t(u):
+            return residual_derivative(Psi, eps, grid, n_electrons, kT, u[None], nspin)[0][0]
+
+        drho, U, _, hist = lowrank_preconditioner(R, apply_t, grid, s_tol, r_max)
+        alpha = damping(nR)
+        rho = rho - alpha * drho
+        log.append((nR, len(U), float(hist[-1]), alpha))
+    return rho, log
+
+
+# ---------------------------------------------------------------------------
 # The paper's recursive Fermi-operator expansion (Eqs. (23)-(24))
 # ---------------------------------------------------------------------------
 def recursive_fermi_response(eps: np.ndarray, mu: float, kT: float, Hp: np.ndarray,

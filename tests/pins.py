@@ -508,3 +508,113 @@ def pin_vjp_self_adjoint():
         ref = O.density_response(Psi, eps, g, ne, kT, G, nspin)[0]
         worst = max(worst, float(np.linalg.norm(gdV - ref) / np.linalg.norm(ref)))
     return worst
+
+
+# ------------------------------------------------------------------ low-rank step
+def _linear_residual(n=(5, 4, 2), L=(2.5, 2.0, 1.0), seed=11, strength=0.6):
+    """A linear residual map t = J u with J = -(I + strength A), A a seeded
+    nonsymmetric Gaussian matrix scaled by 1/sqrt(M)."""
+    g = O.Grid(n, L)
+    rng = np.random.default_rng(seed)
+    M = g.M
+    J = -(np.eye(M) + strength * rng.standard_normal((M, M)) / np.sqrt(M))
+    R = rng.standard_normal(g.shape)
+
+    def apply_t(u):
+        return (J @ u.ravel()).reshape(u.shape)
+    return g, J, R, apply_t
+
+
+def pin_lowrank_krylov_lstsq(ranks=(1, 2, 3, 4, 5)):
+    """For a linear residual map, P^lr_r R is the minimiser of ||J x - R|| over the
+    Krylov space span{R, J R, ..., J^{r-1} R} (the GMRES iterate from zero):
+    here found by numpy's least squares on the monomial Krylov basis, with no
+    Gram-Schmidt and no S.  s_rel is that minimum over ||R||."""
+    g, J, R, apply_t = _linear_residual()
+    b = R.ravel()
+    err = 0.0
+    for r in ranks:
+        drho, _, _, hist = O.lowrank_preconditioner(R, apply_t, g, 0.0, r)
+        K = np.stack([np.linalg.matrix_power(J, k) @ b for k in range(r)], axis=1)
+        y = np.linalg.lstsq(J @ K, b, rcond=None)[0]
+        x = K @ y
+        err = max(err, _rel(drho.ravel(), x),
+                  abs(hist[-1] - np.linalg.norm(J @ x - b) / np.linalg.norm(b)))
+    return err
+
+
+def pin_lowrank_full_rank_newton():
+    """At full rank (r = M) the low-rank step is the Newton step J^{-1} R and
+    s_rel vanishes."""
+    g, J, R, apply_t = _linear_residual(n=(3, 2, 2), L=(1.5, 1.0, 1.0), seed=5, strength=0.4)
+    drho, _, _, hist = O.lowrank_preconditioner(R, apply_t, g, 0.0, g.M)
+    return max(_rel(drho.ravel(), np.linalg.solve(J, R.ravel())), hist[-1])
+
+
+def pin_lowrank_directions():
+    """The directions are orthonormal in the cell integral (Eq. (7)), t_i = J u_i,
+    s_rel does not grow with the rank, and the adaptive rank is the first rank
+    whose s_rel is below the tolerance (Eq. (10))."""
+    g, J, R, apply_t = _linear_residual()
+    _, U, T, hist = O.lowrank_preconditioner(R, apply_t, g, 0.0, 8)
+    Um = U.reshape(len(U), -1)
+    err = np.abs(g.dv * Um @ Um.T - np.eye(len(U))).max()
+    err = max(err, max(_rel(T[i].ravel(), J @ Um[i]) for i in range(len(U))))
+    err = max(err, float(np.max(np.diff(hist), initial=0.0)) if len(hist) > 1 else 0.0)
+    k = 3
+    tol = 0.5 * (hist[k - 1] + hist[k])       # between the s_rel of ranks k and k + 1
+    _, U2, _, _ = O.lowrank_preconditioner(R, apply_t, g, tol, 8)
+    return max(err, 0.0 if len(U2) == k + 1 else 1.0)
+
+
+def _scf_case(nspin=1, n=(4, 4, 4), L=(4.0, 4.0, 4.0), N=None, ne=8.0, kT=0.1, seed=2):
+    g = O.Grid(n, L)
+    V = small_wells(n, L, seed, nwells=2, depth=(1.0, 1.5))
+    N = g.M if N is None else N
+    eps0, Psi0 = O.lowest_states(V, g, N)
+    rho, _ = O.density(np.stack([Psi0] * nspin), np.stack([eps0] * nspin), g, ne, kT, nspin)
+    return g, V, N, ne, kT, rho
+
+
+def pin_scf_derivative_fd(nspin=1):
+    """In the full space (N = M), t = chi0 K_c u - u (Eq. (7)) equals the
+    derivative of the SCF residual R[rho] = F[V_eff[rho]] - rho along u, taken
+    by Richardson-extrapolated central differences of the dense-diagonalisation
+    residual (no divided-difference code on that side)."""
+    g, V, N, ne, kT, rho = _scf_case(nspin)
+    rng = np.random.default_rng(7 + nspin)
+    u = rng.standard_normal((nspin,) + g.shape)
+    u -= u.mean(axis=(1, 2, 3), keepdims=True)
+    u /= np.sqrt(O.inner(u, u, g))
+    _, Psi, eps = O.scf_residual(rho, V, g, N, ne, kT, nspin)
+    t = O.residual_derivative(Psi, eps, g, ne, kT, u[None], nspin)[0][0]
+
+    def central(lam):
+        Rp = O.scf_residual(rho + lam * u, V, g, N, ne, kT, nspin)[0]
+        Rm = O.scf_residual(rho - lam * u, V, g, N, ne, kT, nspin)[0]
+        return (Rp - Rm) / (2 * lam)
+    lam = 2e-3
+    fd = (4 * central(lam / 2) - central(lam)) / 3
+    return _rel(t, fd)
+
+
+def scf_fixed_points(n=(6, 6, 6), L=(6.0, 6.0, 6.0), N=40, ne=12.0, kT=0.05, seed=3):
+    """The LRDM SCF (Eq. (4) with P^lr_r, Sec. II B) against plain damped mixing
+    rho <- rho + 0.1 R, both from a uniform density.  Returns (max difference of
+    the two fixed points, LRDM steps, mixing steps, largest |integral of rho -
+    N_e| over the LRDM iterates, final ||R|| of each)."""
+    g = O.Grid(n, L)
+    V = small_wells(n, L, seed, nwells=3, depth=(1.0, 2.0))
+    rho0 = np.full((1,) + g.shape, ne / (g.M * g.dv))
+    rho_l, log = O.lrdm_scf(rho0, V, g, N, ne, kT, 1, s_tol=0.3, r_max=20, tol=1e-10,
+                            max_iter=60)
+    rho_m = rho0.copy()
+    steps = 0
+    for steps in range(1, 400):
+        R = O.scf_residual(rho_m, V, g, N, ne, kT)[0]
+        nR = np.sqrt(O.inner(R, R, g))
+        if nR < 1e-10:
+            break
+        rho_m = rho_m + 0.1 * R
+    count = abs(g.dv * rho_l.sum() - ne)
+    return (float(np.abs(rho_l - rho_m).max()), len(log), steps, count, log[-1][0], nR)

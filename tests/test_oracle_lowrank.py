@@ -1,0 +1,57 @@
+"""Pins of the oracle's low-rank step (Sec. II B, Eqs. (4), (7)-(10)) and of the
+model SCF map it preconditions (Sec. II A)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from tests import pins as P
+
+
+def test_lowrank_step_is_krylov_least_squares():
+    assert P.pin_lowrank_krylov_lstsq() < 1e-11
+
+
+def test_lowrank_full_rank_is_newton_step():
+    assert P.pin_lowrank_full_rank_newton() < 1e-11
+
+
+def test_lowrank_directions_orthonormal_and_adaptive_rank():
+    assert P.pin_lowrank_directions() < 1e-12
+
+
+def test_lowrank_zero_residual():
+    g = O.Grid((2, 2, 2), (1.0, 1.0, 1.0))
+    drho, U, T, hist = O.lowrank_preconditioner(np.zeros(g.shape), lambda u: -u, g, 0.3, 5)
+    assert not drho.any() and len(U) == 0 and len(hist) == 0
+
+
+def test_lowrank_spin_pair_is_direct_sum():
+    """A spin pair behaves as one vector of twice the length (Sec. II D)."""
+    g, J, R, _ = P._linear_residual(n=(3, 2, 2), L=(1.5, 1.0, 1.0), seed=9)
+    M = g.M // 2
+    pair = R.reshape(2, M)
+
+    def t_pair(u):
+        return (J @ u.ravel()).reshape(u.shape)
+    g2 = O.Grid((3, 2, 1), (1.5, 1.0, 0.5))                # same dv, half the points
+    d2, _, _, h2 = O.lowrank_preconditioner(pair, t_pair, g2, 0.0, 4)
+    d1, _, _, h1 = O.lowrank_preconditioner(R, t_pair, g, 0.0, 4)
+    assert np.allclose(d2.ravel(), d1.ravel(), rtol=0, atol=1e-13)
+    assert np.allclose(h1, h2, rtol=1e-13)
+
+
+def test_damping_schedule():
+    assert O.damping(5.0) == 0.1 and O.damping(1.0) == 0.1 and O.damping(0.99) == 0.5
+
+
+@pytest.mark.parametrize("nspin", [1, 2])
+def test_residual_derivative_is_scf_residual_derivative(nspin):
+    assert P.pin_scf_derivative_fd(nspin) < 1e-9
+
+
+def test_lrdm_scf_reaches_the_mixing_fixed_point():
+    diff, lrdm_steps, mix_steps, count, r_lrdm, r_mix = P.scf_fixed_points()
+    assert r_lrdm < 1e-10 and r_mix < 1e-10
+    assert diff < 1e-9
+    assert count < 1e-12
+    assert lrdm_steps < mix_steps / 3

@@ -130,10 +130,57 @@ def m_fermi_omf_subtraction_sign(mp):
     return lambda: P.pin_divided_differences_decimal() < 1e-13 and P.pin_response_subspace_fd() < 1e-8
 
 
+def _bad_lowrank(first=None, gs_sign=-1.0, use_solve=True):
+    """The low-rank step with one planted change."""
+    def bad(R, apply_t, grid, s_tol, r_max):
+        nR = np.sqrt(L.inner(R, R, grid))
+        U = [(first(R, apply_t) if first else R) / nR]
+        U[0] = U[0] / np.sqrt(L.inner(U[0], U[0], grid))
+        T, hist = [], []
+        while True:
+            T.append(apply_t(U[-1]))
+            r = len(T)
+            S = np.array([[L.inner(T[i], T[j], grid) for j in range(r)] for i in range(r)])
+            c = np.array([L.inner(T[j], R, grid) for j in range(r)])
+            y = np.linalg.solve(S, c) if use_solve else c
+            fit = sum(y[i] * T[i] for i in range(r))
+            hist.append(np.sqrt(L.inner(fit - R, fit - R, grid)) / nR)
+            if hist[-1] < s_tol or r == r_max:
+                break
+            u = T[-1]
+            u = u + gs_sign * sum(L.inner(u, U[k], grid) * U[k] for k in range(r))
+            U.append(u / np.sqrt(L.inner(u, u, grid)))
+        return sum(y[i] * U[i] for i in range(r)), np.array(U), np.array(T), np.array(hist)
+    return bad
+
+
+def m_lowrank_gs_sign(mp):
+    _patch(mp, "lowrank_preconditioner", _bad_lowrank(gs_sign=+1.0))
+    return lambda: P.pin_lowrank_krylov_lstsq() < 1e-11 and P.pin_lowrank_directions() < 1e-12
+
+
+def m_lowrank_no_S_inverse(mp):
+    _patch(mp, "lowrank_preconditioner", _bad_lowrank(use_solve=False))
+    return lambda: P.pin_lowrank_krylov_lstsq() < 1e-11
+
+
+def m_lowrank_first_direction(mp):
+    _patch(mp, "lowrank_preconditioner", _bad_lowrank(first=lambda R, t: t(R)))
+    return lambda: P.pin_lowrank_krylov_lstsq() < 1e-11
+
+
+def m_hartree_sign_in_scf(mp):
+    def bad(V_ext, rho, grid):
+        return V_ext - L.hartree_kernel(rho.reshape((-1,) + grid.shape).sum(axis=0), grid)
+    _patch(mp, "effective_potential", bad)
+    return lambda: P.pin_scf_derivative_fd(1) < 1e-9
+
+
 MUTANTS = [m_drop_dmu, m_flip_F, m_shift_F_index, m_spin_factor, m_laplacian_half,
            m_cheb_sigma_sign, m_hartree_no_4pi, m_projection_layout, m_density_no_dv,
            m_rr_no_rotation, m_bisection_direction, m_spin_channel_potential,
-           m_fermi_omf_subtraction_sign]
+           m_fermi_omf_subtraction_sign, m_lowrank_gs_sign, m_lowrank_no_S_inverse,
+           m_lowrank_first_direction, m_hartree_sign_in_scf]
 
 
 @pytest.mark.parametrize("mutant", MUTANTS, ids=[m.__name__ for m in MUTANTS])
