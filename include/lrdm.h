@@ -13,6 +13,10 @@
  *   density_response        delta rho[dV] in span(Psi_R)         (Eqs. (19)-(22))
  *   density_response_backward  its vector-Jacobian product (adjoint)
  *   lrdm_residual_derivative t = chi0 K_c u - u                  (Eqs. (3), (7))
+ *   lrdm_lowrank_step       drho_bar = P^lr_r R, adaptive r, and the damped
+ *                           quasi-Newton update of rho              (Sec. II B, Eqs. (4), (8)-(10))
+ *   lrdm_density, lrdm_effective_potential  the model SCF map rho -> R[rho]
+ *                           around them                             (Sec. II A, Eq. (1))
  *
  * plus the single steps they are made of (stencil Hamiltonian, occupations and
  * divided differences, projected perturbation, Hartree kernel).
@@ -256,6 +260,70 @@ lrdm_status density_response_backward(lrdm_ctx* ctx, const lrdm_grid* grid, cons
                                       const double* dV, int32_t r, lrdm_prec prec,
                                       const double* g_drho, double* g_dV, void* g_Psi,
                                       double* g_eps);
+
+/* ------------------------------------------------- low-rank step and model SCF */
+
+/* Output density of Eq. (1) per channel,
+ *   rho_c(x_p) = (s/dv) sum_i f_c,i Psi_c,ip^2,
+ * with mu and f from eps as in lrdm_fermi_occupations.  With rho_in non-NULL the
+ * output is the SCF residual R[rho_in] = rho - rho_in (Sec. II A) instead.
+ * Psi [nspin][N][M] (double for LRDM_FP64, float otherwise; the sum is FP64);
+ * eps [nspin][N]; rho_in, out [nspin][M] double (out may be rho_in, never Psi or
+ * eps); mu [1] device double, may be NULL. */
+lrdm_status lrdm_density(lrdm_ctx* ctx, const lrdm_grid* grid, const void* Psi,
+                         const double* eps, int32_t N, const lrdm_occ* occ, lrdm_prec prec,
+                         const double* rho_in, double* out, double* mu);
+
+/* Effective potential of the model SCF: V_eff = V_ext + K_c (sum_c rho_c), the
+ * Hartree potential of the total density with the kernel of lrdm_hartree_kernel
+ * (Eq. (1) with no exchange-correlation term, consistent with K = K_c in the
+ * response).  V_ext, V_eff [M]; rho [nspin][M]; all double; V_eff overlaps
+ * neither input.  range (device double [2], may be NULL) receives min and max of
+ * V_eff, e.g. for the Chebyshev filter's upper bound. */
+lrdm_status lrdm_effective_potential(lrdm_ctx* ctx, const lrdm_grid* grid, const double* V_ext,
+                                     const double* rho, int32_t nspin, double* V_eff,
+                                     double* range);
+
+/* Parameters of the low-rank step (Sec. II B).  Values the paper uses:
+ * s_tol 0.3, alpha_far 0.1, alpha_near 0.5, r_switch 1.0. */
+typedef struct {
+  double s_tol;       /* stop at the first rank whose s_rel (Eq. (10)) is below s_tol (>= 0) */
+  int32_t r_max;      /* most directions, 1..64; U and T hold r_max vectors */
+  double alpha_far;   /* damping while ||R|| >= r_switch, in (0, 1] */
+  double alpha_near;  /* damping once ||R|| < r_switch, in (0, 1] */
+  double r_switch;    /* threshold on ||R|| (>= 0) */
+} lrdm_lowrank_params;
+
+/* What a low-rank step did (host struct). */
+typedef struct {
+  int32_t rank;       /* directions used (0 for R = 0) */
+  double s_rel;       /* Eq. (10) at that rank */
+  double norm_R;      /* ||R||, the norm of the cell integral (direct sum over channels) */
+  double alpha;       /* damping chosen from norm_R */
+} lrdm_lowrank_info;
+
+/* One LRDM step (Sec. II B).  Directions u_1 = R/||R|| and, for i > 1, t_{i-1}
+ * orthogonalised against u_1..u_{i-1} and normalised (Eq. (8), in the inner
+ * product <a, b> = dv sum over points and channels); t_i = chi0 K_c u_i - u_i as
+ * in lrdm_residual_derivative (Eq. (7)), one direction per launch sequence.  After
+ * each t_i: S_ij = <t_i, t_j>, c_j = <t_j, R>, y = S^{-1} c (Cholesky on the
+ * GPU), s_rel = ||sum_j y_j t_j - R|| / ||R|| (Eq. (10)); the loop stops when
+ * s_rel < s_tol, at r_max, or when a new direction would vanish (t_i already in
+ * span(u), so the fit is exact).  Output drho = sum_i y_i u_i = P^lr_r R
+ * (Eq. (9)); with rho non-NULL also rho <- rho - alpha drho (Eq. (4)), alpha
+ * from the schedule in params.  The orthogonalisation is applied twice, which
+ * leaves the span and drho unchanged and keeps u orthonormal in floating point.
+ * Psi, eps, N, occ, prec as for lrdm_residual_derivative; R, drho, rho
+ * [nspin][M] double; U, T [r_max][nspin][M] double receive the directions and
+ * their derivatives (the first info->rank are meaningful); no two of R, U, T,
+ * drho, rho overlap.  Synchronises the stream once per direction (the host reads
+ * s_rel to decide the rank).  Errors as for lrdm_residual_derivative, plus
+ * EINVAL for params out of range, ENONFINITE for a non-finite ||R|| and ENOTCONV
+ * when S is not numerically positive definite. */
+lrdm_status lrdm_lowrank_step(lrdm_ctx* ctx, const lrdm_grid* grid, const void* Psi,
+                              const double* eps, int32_t N, const lrdm_occ* occ, lrdm_prec prec,
+                              const double* R, const lrdm_lowrank_params* params, double* U,
+                              double* T, double* drho, double* rho, lrdm_lowrank_info* info);
 
 #ifdef __cplusplus
 }

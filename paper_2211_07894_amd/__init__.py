@@ -22,4 +22,9 @@ from .lrdm import (  # noqa: F401
     density_response_backward,
     density_response_batched,
     DensityResponse,
+    LowRankParams,
+    density,
+    effective_potential,
+    lowrank_step,
 )
+from .scf import lrdm_scf  # noqa: F401,E402

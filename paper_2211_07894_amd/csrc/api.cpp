@@ -1,6 +1,7 @@
 // extern "C" entry points of liblrdm (declared in include/lrdm.h): argument
 // validation, workspace sizing and the sequence of kernel launches of each call.
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -715,3 +716,218 @@ extern "C" lrdm_status density_response_batched(lrdm_ctx* ctx, const lrdm_system
   });
 }
 
+
+// ============================================================ low-rank step and model SCF
+
+extern "C" lrdm_status lrdm_density(lrdm_ctx* ctx, const lrdm_grid* grid, const void* Psi,
+                                    const double* eps, int32_t N, const lrdm_occ* occ,
+                                    lrdm_prec prec, const double* rho_in, double* out,
+                                    double* mu) {
+  LRDM_CHECK(ctx, check_grid(grid));
+  LRDM_CHECK(ctx, check_block(grid, N));
+  LRDM_CHECK(ctx, check_occ(occ, N));
+  LRDM_CHECK(ctx, check_prec(prec));
+  LRDM_NONNULL(ctx, Psi, "Psi");
+  LRDM_NONNULL(ctx, eps, "eps");
+  LRDM_NONNULL(ctx, out, "out");
+  const Grid3 g = make_grid3(grid);
+  const int ns = occ->nspin;
+  const size_t obytes = (size_t)ns * g.M * sizeof(double);
+  if (overlaps(out, obytes, Psi, (size_t)ns * N * g.M * prec_bytes(prec)) ||
+      overlaps(out, obytes, eps, (size_t)ns * N * sizeof(double)))
+    return fail(ctx, LRDM_EINVAL, "out must not overlap Psi or eps");
+  const size_t vec = ws_align((size_t)ns * N * sizeof(double));
+  lrdm_status st = begin(ctx, ws_align(8) + 3 * vec + density_workspace_bytes(N, g.M, ns));
+  if (st != LRDM_OK) return st;
+  return guarded(ctx, [&]() -> lrdm_status {
+    double* mu_d = mu ? mu : static_cast<double*>(ws_take(ctx, 8));
+    double* f = static_cast<double*>(ws_take(ctx, vec));
+    double* omf = static_cast<double*>(ws_take(ctx, vec));
+    double* fp = static_cast<double*>(ws_take(ctx, vec));
+    double* part = static_cast<double*>(ws_take(ctx, density_workspace_bytes(N, g.M, ns)));
+    hipError_t e = launch_fermi(ctx, eps, N, ns, occ->kT, occ->n_electrons, mu_d, f, omf, fp,
+                                nullptr);
+    const double scale = (ns == 1 ? 2.0 : 1.0) / g.dv;
+    if (e == hipSuccess)
+      e = (prec == LRDM_FP64)
+          ? launch_density<double>(ctx, static_cast<const double*>(Psi), f, N, g.M, ns, scale,
+                                   rho_in, out, part)
+          : launch_density<float>(ctx, static_cast<const float*>(Psi), f, N, g.M, ns, scale,
+                                  rho_in, out, part);
+    if (e == hipSuccess && ctx->checks) e = launch_check_finite(ctx, out, (int64_t)ns * g.M);
+    return e == hipSuccess ? LRDM_OK : fail_hip(ctx, "lrdm_density", e);
+  });
+}
+
+extern "C" lrdm_status lrdm_effective_potential(lrdm_ctx* ctx, const lrdm_grid* grid,
+                                                const double* V_ext, const double* rho,
+                                                int32_t nspin, double* V_eff, double* range) {
+  LRDM_CHECK(ctx, check_grid(grid));
+  if (nspin != 1 && nspin != 2) return fail(ctx, LRDM_EINVAL, "nspin must be 1 or 2");
+  LRDM_NONNULL(ctx, V_ext, "V_ext");
+  LRDM_NONNULL(ctx, rho, "rho");
+  LRDM_NONNULL(ctx, V_eff, "V_eff");
+  const Grid3 g = make_grid3(grid);
+  const size_t vb = (size_t)g.M * sizeof(double);
+  if (overlaps(V_eff, vb, V_ext, vb) || overlaps(V_eff, vb, rho, nspin * vb))
+    return fail(ctx, LRDM_EINVAL, "V_eff must not overlap V_ext or rho");
+  const size_t scratch = 2 * vb;
+  lrdm_status st = begin(ctx, ws_align(scratch) + hartree_workspace_bytes(g));
+  if (st != LRDM_OK) return st;
+  return guarded(ctx, [&]() -> lrdm_status {
+    double* s = static_cast<double*>(ws_take(ctx, scratch));
+    hipError_t e = launch_hartree(ctx, g, rho, nspin, V_eff, 1, 1, s);
+    if (e == hipSuccess) e = launch_axpy(ctx, 1.0, V_ext, g.M, V_eff);
+    if (e == hipSuccess && range) e = launch_minmax(ctx, V_eff, g.M, range);
+    return e == hipSuccess ? LRDM_OK : fail_hip(ctx, "lrdm_effective_potential", e);
+  });
+}
+
+namespace {
+
+// Slots of the small host-read block of lrdm_lowrank_step.
+enum { LR_NR2 = 0, LR_FIT2 = 1, LR_UNEW2 = 2, LR_T2 = 3, LR_SLOTS = 4 };
+
+template <typename T>
+lrdm_status run_lowrank(lrdm_ctx* ctx, const Grid3& g, const T* Psi, const double* eps, int N,
+                        const lrdm_occ* occ, lrdm_prec prec, const double* R,
+                        const lrdm_lowrank_params* prm, double* U, double* Tm, double* drho,
+                        double* rho, lrdm_lowrank_info* info) {
+  const int ns = occ->nspin;
+  const int64_t n = (int64_t)ns * g.M;
+  const double dv = g.dv;
+  const int K = kMaxLowRank;
+  auto hip_fail = [&](const char* where, hipError_t e) { return fail_hip(ctx, where, e); };
+#define LR_HIP(where, call)                      \
+  do {                                           \
+    hipError_t e_ = (call);                      \
+    if (e_ != hipSuccess) return hip_fail(where, e_); \
+  } while (0)
+  double* S = static_cast<double*>(ws_take(ctx, (size_t)K * K * sizeof(double)));
+  double* c = static_cast<double*>(ws_take(ctx, K * sizeof(double)));
+  double* y = static_cast<double*>(ws_take(ctx, K * sizeof(double)));
+  double* gco = static_cast<double*>(ws_take(ctx, K * sizeof(double)));
+  double* sc = static_cast<double*>(ws_take(ctx, LR_SLOTS * sizeof(double)));
+  int* flag = static_cast<int*>(ws_take(ctx, sizeof(int)));
+  double* part = static_cast<double*>(ws_take(ctx, dots_workspace_bytes(K)));
+  double* w = static_cast<double*>(ws_take(ctx, (size_t)n * sizeof(double)));
+  double* dV = static_cast<double*>(ws_take(ctx, (size_t)n * sizeof(double)));
+  double* hs = static_cast<double*>(ws_take(ctx, 2 * (size_t)g.M * sizeof(double)));
+  const size_t mark = ctx->ws_top;
+
+  // ||R||
+  double h[LR_SLOTS] = {0, 0, 0, 0};
+  LR_HIP("lowrank norm", launch_dots(ctx, R, 0, 1, R, n, dv, sc + LR_NR2, 1, part));
+  LR_HIP("lowrank read", hipMemcpyAsync(h, sc, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+  LR_HIP("lowrank sync", hipStreamSynchronize(ctx->stream));
+  if (!std::isfinite(h[LR_NR2])) return fail(ctx, LRDM_ENONFINITE, "||R|| is not finite");
+  const double nR = std::sqrt(h[LR_NR2]);
+  info->norm_R = nR;
+  info->alpha = nR >= prm->r_switch ? prm->alpha_far : prm->alpha_near;
+  if (nR == 0.0) {
+    info->rank = 0;
+    info->s_rel = 0.0;
+    LR_HIP("lowrank zero", launch_combine(ctx, nullptr, 0.0, U, n, y, 0, 1.0, n, drho));
+    return LRDM_OK;
+  }
+  LR_HIP("lowrank u1", launch_normalize(ctx, R, sc + LR_NR2, n, U));
+  int rank = 0;
+  double s_rel = 1.0;
+  for (int i = 0; i < prm->r_max; ++i) {
+    double* ui = U + (size_t)i * n;
+    double* ti = Tm + (size_t)i * n;
+    ctx->ws_top = mark;        // the response's slices are reused by every direction
+    LR_HIP("lowrank hartree", launch_hartree(ctx, g, ui, ns, dV, ns, 1, hs));
+    LR_HIP("lowrank response",
+           run_response<T>(ctx, g, Psi, eps, N, occ, dV, 1, prec, ui, ti, nullptr, nullptr));
+    // row i of S, c_i, the coefficients and the fit residual of Eq. (10)
+    LR_HIP("lowrank S", launch_dots(ctx, Tm, n, i + 1, ti, n, dv, S + (size_t)i * K, 1, part));
+    LR_HIP("lowrank c", launch_dots(ctx, ti, 0, 1, R, n, dv, c + i, 1, part));
+    LR_HIP("lowrank solve", launch_lowrank_solve(ctx, S, K, c, i + 1, y, flag));
+    LR_HIP("lowrank fit", launch_combine(ctx, R, -1.0, Tm, n, y, i + 1, 1.0, n, w));
+    LR_HIP("lowrank fit norm", launch_dots(ctx, w, 0, 1, w, n, dv, sc + LR_FIT2, 1, part));
+    const bool more = i + 1 < prm->r_max;
+    if (more) {
+      // the next direction (Eq. (8)), formed before the host decides so that one
+      // synchronisation per direction suffices; projections removed twice
+      double* un = U + (size_t)(i + 1) * n;
+      LR_HIP("lowrank gs", launch_dots(ctx, U, n, i + 1, ti, n, dv, gco, 1, part));
+      LR_HIP("lowrank gs", launch_combine(ctx, ti, 1.0, U, n, gco, i + 1, -1.0, n, un));
+      LR_HIP("lowrank gs2", launch_dots(ctx, U, n, i + 1, un, n, dv, gco, 1, part));
+      LR_HIP("lowrank gs2", launch_combine(ctx, un, 1.0, U, n, gco, i + 1, -1.0, n, un));
+      LR_HIP("lowrank unorm", launch_dots(ctx, un, 0, 1, un, n, dv, sc + LR_UNEW2, 1, part));
+      LR_HIP("lowrank tnorm", launch_dots(ctx, ti, 0, 1, ti, n, dv, sc + LR_T2, 1, part));
+    }
+    int hflag = 0;
+    LR_HIP("lowrank read", hipMemcpyAsync(h, sc, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    LR_HIP("lowrank read", hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost,
+                                          ctx->stream));
+    LR_HIP("lowrank sync", hipStreamSynchronize(ctx->stream));
+    if (hflag)
+      return fail(ctx, LRDM_ENOTCONV,
+                  "lrdm_lowrank_step: the Gram matrix of the directional derivatives is not "
+                  "numerically positive definite");
+    rank = i + 1;
+    s_rel = std::sqrt(h[LR_FIT2]) / nR;
+    if (!std::isfinite(s_rel)) return fail(ctx, LRDM_ENONFINITE, "s_rel is not finite");
+    if (s_rel < prm->s_tol || !more) break;
+    // t_i inside span(u_1..u_i): the Krylov space is exhausted and the fit exact
+    if (!(h[LR_UNEW2] > 1e-26 * h[LR_T2])) break;
+    double* un = U + (size_t)(i + 1) * n;
+    LR_HIP("lowrank normalize", launch_normalize(ctx, un, sc + LR_UNEW2, n, un));
+  }
+  LR_HIP("lowrank drho", launch_combine(ctx, nullptr, 0.0, U, n, y, rank, 1.0, n, drho));
+  if (rho) LR_HIP("lowrank update", launch_axpy(ctx, -info->alpha, drho, n, rho));
+  if (ctx->checks) LR_HIP("lowrank check", launch_check_finite(ctx, drho, n));
+  info->rank = rank;
+  info->s_rel = s_rel;
+  return LRDM_OK;
+#undef LR_HIP
+}
+
+}  // namespace
+
+extern "C" lrdm_status lrdm_lowrank_step(lrdm_ctx* ctx, const lrdm_grid* grid, const void* Psi,
+                                         const double* eps, int32_t N, const lrdm_occ* occ,
+                                         lrdm_prec prec, const double* R,
+                                         const lrdm_lowrank_params* params, double* U, double* T,
+                                         double* drho, double* rho, lrdm_lowrank_info* info) {
+  LRDM_CHECK(ctx, check_grid(grid));
+  LRDM_CHECK(ctx, check_block(grid, N));
+  LRDM_CHECK(ctx, check_occ(occ, N));
+  LRDM_CHECK(ctx, check_prec(prec));
+  LRDM_CHECK(ctx, check_lowrank(params));
+  LRDM_NONNULL(ctx, Psi, "Psi");
+  LRDM_NONNULL(ctx, eps, "eps");
+  LRDM_NONNULL(ctx, R, "R");
+  LRDM_NONNULL(ctx, U, "U");
+  LRDM_NONNULL(ctx, T, "T");
+  LRDM_NONNULL(ctx, drho, "drho");
+  LRDM_NONNULL(ctx, info, "info");
+  const Grid3 g = make_grid3(grid);
+  const int ns = occ->nspin;
+  const size_t vb = (size_t)ns * g.M * sizeof(double);
+  const size_t ub = (size_t)params->r_max * vb;
+  struct Span {
+    const void* p;
+    size_t n;
+  } spans[5] = {{R, vb}, {U, ub}, {T, ub}, {drho, vb}, {rho, rho ? vb : 0}};
+  for (int a = 0; a < 5; ++a)
+    for (int b = a + 1; b < 5; ++b)
+      if (spans[a].n && spans[b].n && overlaps(spans[a].p, spans[a].n, spans[b].p, spans[b].n))
+        return fail(ctx, LRDM_EINVAL, "R, U, T, drho and rho must not overlap");
+  const int K = kMaxLowRank;
+  const size_t small = ws_align((size_t)K * K * 8) + 3 * ws_align(K * 8) + ws_align(LR_SLOTS * 8) +
+                       ws_align(sizeof(int)) + dots_workspace_bytes(K);
+  const size_t bytes = small + 2 * ws_align(vb) + ws_align(2 * (size_t)g.M * 8) +
+                       hartree_workspace_bytes(g) + response_bytes(N, g.M, 1, ns, prec);
+  lrdm_status st = begin(ctx, bytes);
+  if (st != LRDM_OK) return st;
+  return guarded(ctx, [&]() -> lrdm_status {
+    return (prec == LRDM_FP64)
+        ? run_lowrank<double>(ctx, g, static_cast<const double*>(Psi), eps, N, occ, prec, R,
+                              params, U, T, drho, rho, info)
+        : run_lowrank<float>(ctx, g, static_cast<const float*>(Psi), eps, N, occ, prec, R,
+                             params, U, T, drho, rho, info);
+  });
+}

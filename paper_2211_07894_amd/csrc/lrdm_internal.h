@@ -51,6 +51,7 @@ const char* check_occ(const lrdm_occ* occ, int32_t N);
 const char* check_prec(int prec);
 const char* check_rank(int32_t r);
 const char* check_filter(int32_t degree, double a, double b, double a0);
+const char* check_lowrank(const lrdm_lowrank_params* p);
 const char* check_ptr(const void* p, const char* name);
 
 inline int64_t grid_points(const lrdm_grid* g) {
@@ -194,6 +195,43 @@ hipError_t launch_hartree(lrdm_ctx* ctx, const Grid3& g, const double* u, int u_
 size_t hartree_workspace_bytes(const Grid3& g);
 
 hipError_t launch_check_finite(lrdm_ctx* ctx, const double* x, int64_t n);
+
+// Low-rank preconditioner pieces and the output density (lowrank.hip).
+constexpr int kMaxLowRank = 64;
+// State-range splits of the density sum: enough blocks to fill the chip.
+inline int density_splits(int N, int64_t M, int nspin) {
+  const int64_t bx = (M + 255) / 256;
+  int s = 1;
+  while (bx * nspin * s < 2048 && s < 16 && 2 * s <= N) s *= 2;
+  return s;
+}
+size_t density_workspace_bytes(int N, int64_t M, int nspin);
+// out[c][p] = scale sum_i f[c][i] Psi[c][i][p]^2 - (rho_in ? rho_in[c][p] : 0);
+// part: density_workspace_bytes of scratch.
+template <typename T>
+hipError_t launch_density(lrdm_ctx* ctx, const T* Psi, const double* f, int N, int64_t M,
+                          int nspin, double scale, const double* rho_in, double* out,
+                          double* part);
+size_t dots_workspace_bytes(int k);
+// out[j * stride] = scale sum_i A[j][i] x[i] for j < k (rows lda apart), in a fixed
+// order; part: dots_workspace_bytes(k) of scratch.
+hipError_t launch_dots(lrdm_ctx* ctx, const double* A, int64_t lda, int k, const double* x,
+                       int64_t n, double scale, double* out, int stride, double* part);
+// y = beta x + sgn sum_{k < nk} coef[k] A[k] (x may be NULL, y may be x).
+hipError_t launch_combine(lrdm_ctx* ctx, const double* x, double beta, const double* A,
+                          int64_t lda, const double* coef, int nk, double sgn, int64_t n,
+                          double* y);
+// y = x / sqrt(nrm2[0]).
+hipError_t launch_normalize(lrdm_ctx* ctx, const double* x, const double* nrm2, int64_t n,
+                            double* y);
+// y += a x.
+hipError_t launch_axpy(lrdm_ctx* ctx, double a, const double* x, int64_t n, double* y);
+// range[0], range[1] = min and max of x[0..n).
+hipError_t launch_minmax(lrdm_ctx* ctx, const double* x, int64_t n, double* range);
+// y = S^{-1} c for the r x r lower triangle of S (leading dimension ld); *flag = 1
+// (and y = 0) when S is not numerically positive definite.
+hipError_t launch_lowrank_solve(lrdm_ctx* ctx, const double* S, int ld, const double* c, int r,
+                                double* y, int* flag);
 
 // Records a start/stop hipEvent pair on ctx->stream around its scope when the
 // context is profiling (see lrdm_profile).

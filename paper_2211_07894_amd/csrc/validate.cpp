@@ -53,6 +53,19 @@ const char* check_rank(int32_t r) {
   return nullptr;
 }
 
+const char* check_lowrank(const lrdm_lowrank_params* p) {
+  if (!p) return "params is NULL";
+  if (!std::isfinite(p->s_tol) || p->s_tol < 0.0) return "params: s_tol must be finite and >= 0";
+  if (p->r_max < 1 || p->r_max > 64) return "params: r_max must be in 1..64";
+  if (!std::isfinite(p->alpha_far) || !(p->alpha_far > 0.0 && p->alpha_far <= 1.0))
+    return "params: alpha_far must be in (0, 1]";
+  if (!std::isfinite(p->alpha_near) || !(p->alpha_near > 0.0 && p->alpha_near <= 1.0))
+    return "params: alpha_near must be in (0, 1]";
+  if (!std::isfinite(p->r_switch) || p->r_switch < 0.0)
+    return "params: r_switch must be finite and >= 0";
+  return nullptr;
+}
+
 const char* check_filter(int32_t degree, double a, double b, double a0) {
   if (degree < 1) return "degree must be >= 1";
   if (degree > 10000) return "degree must be <= 10000";

@@ -30,6 +30,7 @@ EXPORTED = [
     "lrdm_projected_perturbation", "lrdm_hartree_kernel", "chfsi_filter",
     "subspace_rayleigh_ritz", "density_response", "lrdm_residual_derivative",
     "density_response_backward", "density_response_batched",
+    "lrdm_density", "lrdm_effective_potential", "lrdm_lowrank_step",
 ]
 
 
@@ -52,6 +53,17 @@ class c_system(ctypes.Structure):
                 ("N", ctypes.c_int32), ("occ", c_occ), ("dV", ctypes.c_void_p),
                 ("r", ctypes.c_int32), ("drho", ctypes.c_void_p), ("mu", ctypes.c_void_p),
                 ("dmu", ctypes.c_void_p)]
+
+
+class c_lowrank_params(ctypes.Structure):
+    _fields_ = [("s_tol", ctypes.c_double), ("r_max", ctypes.c_int32),
+                ("alpha_far", ctypes.c_double), ("alpha_near", ctypes.c_double),
+                ("r_switch", ctypes.c_double)]
+
+
+class c_lowrank_info(ctypes.Structure):
+    _fields_ = [("rank", ctypes.c_int32), ("s_rel", ctypes.c_double),
+                ("norm_R", ctypes.c_double), ("alpha", ctypes.c_double)]
 
 
 @dataclass(frozen=True)
@@ -120,6 +132,11 @@ def library() -> ctypes.CDLL:
                 "density_response_backward": [vp, G, vp, vp, i32, O, vp, i32, ctypes.c_int, vp,
                                               vp, vp, vp],
                 "density_response_batched": [vp, ctypes.POINTER(c_system), i32, ctypes.c_int],
+                "lrdm_density": [vp, G, vp, vp, i32, O, ctypes.c_int, vp, vp, vp],
+                "lrdm_effective_potential": [vp, G, vp, vp, i32, vp, vp],
+                "lrdm_lowrank_step": [vp, G, vp, vp, i32, O, ctypes.c_int, vp,
+                                      ctypes.POINTER(c_lowrank_params), vp, vp, vp, vp,
+                                      ctypes.POINTER(c_lowrank_info)],
             }
             for name, args in sig.items():
                 fn = getattr(lib, name)
@@ -435,3 +452,82 @@ class DensityResponse(torch.autograd.Function):
             g_dV = g_dV.reshape(dV.shape)
         return g_Psi, g_eps, g_dV, None, None, None
 
+
+
+# ------------------------------------------------------------------ low-rank step and model SCF
+@dataclass(frozen=True)
+class LowRankParams:
+    """Parameters of the low-rank step (lrdm_lowrank_params); defaults are the
+    paper's values (Sec. II B)."""
+    s_tol: float = 0.3
+    r_max: int = 20
+    alpha_far: float = 0.1
+    alpha_near: float = 0.5
+    r_switch: float = 1.0
+
+    def c(self) -> c_lowrank_params:
+        return c_lowrank_params(float(self.s_tol), int(self.r_max), float(self.alpha_far),
+                                float(self.alpha_near), float(self.r_switch))
+
+
+def density(grid: Grid, Psi, eps, occ: Occupation, prec="fp64", rho_in=None, out=None, mu=None):
+    """rho [nspin][M] of Eq. (1), or the residual rho - rho_in when rho_in is
+    given; returns (out, mu [1])."""
+    ns = occ.nspin
+    N = eps.numel() // ns
+    dev = Psi.device
+    out = torch.empty((ns,) + grid.shape, dtype=torch.float64, device=dev) if out is None else out
+    mu = torch.empty(1, dtype=torch.float64, device=dev) if mu is None else mu
+    ctx = context(dev.index)
+    g = grid.c()
+    o = occ.c()
+    ctx.check(ctx.lib.lrdm_density(
+        ctx.ptr, ctypes.byref(g), _ptr(Psi, "Psi", _block_dtype(prec), ns * N * grid.M),
+        _ptr(eps, "eps", torch.float64, ns * N), N, ctypes.byref(o), _prec(prec),
+        _opt_ptr(rho_in, "rho_in", torch.float64, ns * grid.M),
+        _ptr(out, "out", torch.float64, ns * grid.M), _ptr(mu, "mu", torch.float64, 1)))
+    return out, mu
+
+
+def effective_potential(grid: Grid, V_ext, rho, out=None, vrange=None):
+    """V_eff = V_ext + K_c sum_c rho_c; vrange (device double [2], optional)
+    receives its min and max.  Returns V_eff [M]."""
+    ns = rho.numel() // grid.M
+    out = torch.empty(grid.shape, dtype=torch.float64, device=rho.device) if out is None else out
+    ctx = context(rho.device.index)
+    g = grid.c()
+    ctx.check(ctx.lib.lrdm_effective_potential(
+        ctx.ptr, ctypes.byref(g), _ptr(V_ext, "V_ext", torch.float64, grid.M),
+        _ptr(rho, "rho", torch.float64, ns * grid.M), ns,
+        _ptr(out, "V_eff", torch.float64, grid.M), _opt_ptr(vrange, "vrange", torch.float64, 2)))
+    return out
+
+
+def lowrank_step(grid: Grid, Psi, eps, occ: Occupation, R, params: LowRankParams = LowRankParams(),
+                 prec="fp64", rho=None, U=None, T=None, drho=None):
+    """drho_bar = P^lr_r R with the adaptive rank, and rho -= alpha drho_bar when
+    rho is given (lrdm_lowrank_step).  Returns (drho, U[:rank], T[:rank], info)
+    with info a dict of rank, s_rel, norm_R and alpha."""
+    ns = occ.nspin
+    N = eps.numel() // ns
+    n = ns * grid.M
+    dev = Psi.device
+    shape = (ns,) + grid.shape
+    U = torch.empty((params.r_max,) + shape, dtype=torch.float64, device=dev) if U is None else U
+    T = torch.empty((params.r_max,) + shape, dtype=torch.float64, device=dev) if T is None else T
+    drho = torch.empty(shape, dtype=torch.float64, device=dev) if drho is None else drho
+    info = c_lowrank_info()
+    p = params.c()
+    ctx = context(dev.index)
+    g = grid.c()
+    o = occ.c()
+    ctx.check(ctx.lib.lrdm_lowrank_step(
+        ctx.ptr, ctypes.byref(g), _ptr(Psi, "Psi", _block_dtype(prec), ns * N * grid.M),
+        _ptr(eps, "eps", torch.float64, ns * N), N, ctypes.byref(o), _prec(prec),
+        _ptr(R, "R", torch.float64, n), ctypes.byref(p),
+        _ptr(U, "U", torch.float64, params.r_max * n), _ptr(T, "T", torch.float64, params.r_max * n),
+        _ptr(drho, "drho", torch.float64, n), _opt_ptr(rho, "rho", torch.float64, n),
+        ctypes.byref(info)))
+    r = int(info.rank)
+    return drho, U[:r], T[:r], dict(rank=r, s_rel=float(info.s_rel), norm_R=float(info.norm_R),
+                                    alpha=float(info.alpha))

@@ -288,6 +288,42 @@ void scenario_backward(lrdm_ctx* ctx, lrdm_grid g, int N, int nspin, int r, lrdm
   if (!(err < (prec == LRDM_FP64 ? 1e-12 : 1e-5))) ++failures;
 }
 
+
+void scenario_lowrank(lrdm_ctx* ctx, lrdm_grid g, int N, int nspin, int r_max, lrdm_prec prec) {
+  const int64_t M = (int64_t)g.n[0] * g.n[1] * g.n[2];
+  std::vector<double> Psi0;
+  for (int c = 0; c < nspin; ++c) {
+    auto P = orthonormal(N, M, 21 + c);
+    Psi0.insert(Psi0.end(), P.begin(), P.end());
+  }
+  Block Psi(Psi0, prec);
+  std::vector<double> eps((size_t)nspin * N);
+  for (int c = 0; c < nspin; ++c)
+    for (int i = 0; i < N; ++i) eps[(size_t)c * N + i] = -1.0 + 1.5 * i / N + 0.001 * c;
+  lrdm_occ occ{nspin, 0.02, 0.8 * N};
+  const size_t n = (size_t)nspin * M;
+  std::vector<double> rho(n, 0.01), R(n), mu(1), Vext(M, -0.3), Veff(M), range(2);
+  char name[160];
+  std::snprintf(name, sizeof name, "lrdm_density %s N=%d nspin=%d grid %dx%dx%d", prec_name(prec),
+                N, nspin, g.n[0], g.n[1], g.n[2]);
+  check(lrdm_density(ctx, &g, Psi.data(), eps.data(), N, &occ, prec, rho.data(), R.data(),
+                     mu.data()), ctx, name);
+  check(lrdm_effective_potential(ctx, &g, Vext.data(), rho.data(), nspin, Veff.data(),
+                                 range.data()), ctx, "lrdm_effective_potential");
+  lrdm_lowrank_params prm{0.0, r_max, 0.1, 0.5, 1.0};
+  std::vector<double> U((size_t)r_max * n), T((size_t)r_max * n), drho(n);
+  lrdm_lowrank_info info{};
+  std::snprintf(name, sizeof name, "lrdm_lowrank_step %s N=%d nspin=%d r_max=%d", prec_name(prec),
+                N, nspin, r_max);
+  check(lrdm_lowrank_step(ctx, &g, Psi.data(), eps.data(), N, &occ, prec, R.data(), &prm,
+                          U.data(), T.data(), drho.data(), rho.data(), &info), ctx, name);
+  std::printf("     rank %d s_rel %.3e ||R|| %.3e alpha %.2f\n", info.rank, info.s_rel, info.norm_R,
+              info.alpha);
+  if (!finite(drho) || info.rank != r_max) {
+    std::printf("FAIL lowrank step\n");
+    ++failures;
+  }
+}
 }  // namespace
 
 int main(int argc, char** argv) {
@@ -328,6 +364,11 @@ int main(int argc, char** argv) {
   if (which == "lprr") {
     scenario_chfsi(ctx, grid(10, 9, 8, 0.45), 150, 5, LRDM_FP32);
     scenario_chfsi(ctx, grid(12, 12, 12, 0.45), 130, 4, LRDM_BF16X3);
+  }
+  if (which == "all" || which == "lowrank") {
+    scenario_lowrank(ctx, grid(7, 9, 11, 0.5), 70, 1, 4, LRDM_FP64);
+    scenario_lowrank(ctx, grid(9, 8, 7, 0.5), 40, 2, 3, LRDM_FP32);
+    scenario_lowrank(ctx, grid(7, 9, 11, 0.5), 70, 1, 3, LRDM_BF16X3);
   }
   if (which == "all" || which == "full") scenario_full_n(ctx);
   check(lrdm_destroy(ctx), nullptr, "lrdm_destroy");

@@ -97,3 +97,47 @@ def test_rank_and_plane_limits(lib):
     assert st == -1 and "r (number of directions)" in _err(lib)
     st = lib.lrdm_hartree_kernel(None, ctypes.byref(_grid((100, 100, 8), (4.0, 4.0, 4.0))), P, P, 1)
     assert st == -1 and "8192 points" in _err(lib)
+
+
+@pytest.mark.parametrize("field,value,msg", [
+    ("s_tol", -0.1, "s_tol must be finite"),
+    ("r_max", 0, "r_max must be in 1..64"),
+    ("r_max", 65, "r_max must be in 1..64"),
+    ("alpha_far", 0.0, "alpha_far must be in (0, 1]"),
+    ("alpha_near", 1.5, "alpha_near must be in (0, 1]"),
+    ("r_switch", float("nan"), "r_switch must be finite"),
+])
+def test_lowrank_params_validation(lib, field, value, msg):
+    p = B.LowRankParams().c()
+    setattr(p, field, value)
+    o = B.c_occ(1, 0.01, 20.0)
+    info = B.c_lowrank_info()
+    st = lib.lrdm_lowrank_step(None, ctypes.byref(_grid()), P, P, 32, ctypes.byref(o), 0, P,
+                               ctypes.byref(p), ctypes.c_void_p(0x10000000),
+                               ctypes.c_void_p(0x20000000), ctypes.c_void_p(0x30000000), None,
+                               ctypes.byref(info))
+    assert st == -1 and msg in _err(lib)
+
+
+def test_lowrank_buffers_must_not_overlap(lib):
+    p = B.LowRankParams(r_max=4).c()
+    o = B.c_occ(1, 0.01, 20.0)
+    info = B.c_lowrank_info()
+    # U holds 4 vectors of 512 doubles; T starts inside it
+    U = 0x10000000
+    st = lib.lrdm_lowrank_step(None, ctypes.byref(_grid()), P, P, 32, ctypes.byref(o), 0,
+                               ctypes.c_void_p(0x40000000), ctypes.byref(p), ctypes.c_void_p(U),
+                               ctypes.c_void_p(U + 8 * 512), ctypes.c_void_p(0x30000000), None,
+                               ctypes.byref(info))
+    assert st == -1 and "must not overlap" in _err(lib)
+
+
+def test_density_and_potential_validation(lib):
+    o = B.c_occ(1, 0.01, 20.0)
+    st = lib.lrdm_density(None, ctypes.byref(_grid()), P, P, 32, ctypes.byref(o), 0, None, None, None)
+    assert st == -1 and "out is NULL" in _err(lib)
+    st = lib.lrdm_effective_potential(None, ctypes.byref(_grid()), P, P, 3, P, None)
+    assert st == -1 and "nspin must be 1 or 2" in _err(lib)
+    st = lib.lrdm_effective_potential(None, ctypes.byref(_grid()), P, ctypes.c_void_p(0x2000), 1,
+                                      ctypes.c_void_p(0x2000 + 8), None)
+    assert st == -1 and "must not overlap" in _err(lib)

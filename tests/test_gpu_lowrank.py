@@ -1,0 +1,172 @@
+"""The LRDM step around the hot path (Sec. II B) and the model SCF map it acts on
+(Sec. II A) against the FP64 oracle: output density and residual, effective
+potential, the low-rank step (directions, derivatives, rank, s_rel, drho_bar and
+the damped update) and a whole SCF run to its fixed point."""
+import numpy as np
+import pytest
+
+import oracle as O
+from inputs import grf_directions, random_block
+from tests.gpu_common import oracle_subspace, rel, to_dev, to_host
+from tests.pins import small_wells
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU hosts
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2211_07894_amd as L  # noqa: E402
+
+
+def _grid(g: O.Grid):
+    return L.Grid(tuple(g.n), tuple(g.L))
+
+
+@pytest.fixture(scope="module")
+def c24():
+    return oracle_subspace("c24_n32", passes=2)
+
+
+def _spin_system(c24, nspin):
+    wl, g, V, eps, Psi = c24
+    Psi2 = np.stack([Psi] * nspin)
+    eps2 = np.stack([eps + 0.003 * c for c in range(nspin)])
+    return wl, g, V, Psi2, eps2
+
+
+@pytest.mark.parametrize("nspin", [1, 2])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_density_and_residual(c24, nspin, prec):
+    wl, g, V, Psi2, eps2 = _spin_system(c24, nspin)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    Psi_d = to_dev(Psi2, dt)
+    Psi_h = to_host(Psi_d)                     # the form's own storage, in FP64
+    occ = L.Occupation(nspin, wl.kT, wl.n_electrons)
+    rho, mu = L.density(_grid(g), Psi_d, to_dev(eps2), occ, prec=prec)
+    ref, mu_o = O.density(Psi_h, eps2, g, wl.n_electrons, wl.kT, nspin)
+    assert rel(to_host(rho), ref) < 1e-12
+    assert abs(float(to_host(mu)[0]) - mu_o) < 1e-12
+    assert abs(g.dv * float(to_host(rho).sum()) - wl.n_electrons) < 1e-9
+    rho_in = np.random.default_rng(3).uniform(0, 0.01, ref.shape)
+    R_d = to_dev(rho_in)                      # in place: out is rho_in
+    L.density(_grid(g), Psi_d, to_dev(eps2), occ, prec=prec, rho_in=R_d, out=R_d)
+    assert rel(to_host(R_d), ref - rho_in) < 1e-12
+
+
+@pytest.mark.parametrize("nspin", [1, 2])
+def test_effective_potential(c24, nspin):
+    wl, g, V, _, _ = c24
+    rho = np.random.default_rng(5 + nspin).uniform(0, 0.02, (nspin,) + g.shape)
+    vr = torch.empty(2, dtype=torch.float64, device="cuda")
+    Veff = L.effective_potential(_grid(g), to_dev(V), to_dev(rho), vrange=vr)
+    ref = O.effective_potential(V, rho, g)
+    assert rel(to_host(Veff), ref) < 1e-12
+    lo, hi = vr.tolist()
+    assert lo == float(to_host(Veff).min()) and hi == float(to_host(Veff).max())
+
+
+def _oracle_step(wl, g, Psi2, eps2, nspin, R, s_tol, r_max):
+    def apply_t(u):
+        return O.residual_derivative(Psi2, eps2, g, wl.n_electrons, wl.kT, u[None], nspin)[0][0]
+    return O.lowrank_preconditioner(R, apply_t, g, s_tol, r_max)
+
+
+def _residual_like(wl, nspin, scale=0.7):
+    return scale * grf_directions(wl.system_id, wl.n, wl.L, 1, nspin=nspin)[0]
+
+
+@pytest.mark.parametrize("nspin", [1, 2])
+@pytest.mark.parametrize("s_tol,r_max", [(0.3, 20), (0.0, 6)])
+def test_lowrank_step_fp64(c24, nspin, s_tol, r_max):
+    """Same Ritz pairs and residual on both sides; the oracle follows Eqs. (7)-(10)
+    with one classical Gram-Schmidt pass, the GPU applies it twice (same span)."""
+    wl, g, V, Psi2, eps2 = _spin_system(c24, nspin)
+    R = _residual_like(wl, nspin)
+    d_o, U_o, T_o, hist = _oracle_step(wl, g, Psi2, eps2, nspin, R, s_tol, r_max)
+    occ = L.Occupation(nspin, wl.kT, wl.n_electrons)
+    rho0 = np.random.default_rng(9).uniform(0, 0.01, R.shape)
+    rho = to_dev(rho0)
+    prm = L.LowRankParams(s_tol=s_tol, r_max=r_max)
+    drho, U, T, info = L.lowrank_step(_grid(g), to_dev(Psi2), to_dev(eps2), occ, to_dev(R), prm,
+                                      rho=rho)
+    r = len(U_o)
+    print(f"nspin {nspin} s_tol {s_tol}: rank {info['rank']} (oracle {r}), "
+          f"s_rel {info['s_rel']:.3e} (oracle {hist[-1]:.3e})")
+    assert info["rank"] == r
+    assert abs(info["s_rel"] - hist[-1]) < 1e-10
+    assert abs(info["norm_R"] - np.sqrt(O.inner(R, R, g))) < 1e-12 * info["norm_R"]
+    assert info["alpha"] == O.damping(info["norm_R"])
+    assert rel(to_host(drho), d_o) < 1e-10
+    Uh, Th = to_host(U), to_host(T)
+    for i in range(r):
+        assert rel(Uh[i], U_o[i]) < 1e-9
+        assert rel(Th[i], T_o[i]) < 1e-9
+    Um = Uh.reshape(r, -1)
+    assert np.abs(g.dv * Um @ Um.T - np.eye(r)).max() < 1e-12
+    assert rel(to_host(rho), rho0 - info["alpha"] * d_o) < 1e-12
+
+
+@pytest.mark.parametrize("prec,bound", [("fp32", 1e-4), ("bf16x3", 1e-5)])
+def test_lowrank_step_low_precision(c24, prec, bound):
+    """The FP32 forms on their own storage of the Ritz vectors: drho_bar within ten
+    times the per-stage response bound (the step solves a small least-squares
+    problem in the t's, whose conditioning is of order one at these ranks)."""
+    wl, g, V, Psi2, eps2 = _spin_system(c24, 1)
+    Psi_d = to_dev(Psi2, torch.float32)
+    R = _residual_like(wl, 1)
+    d_o, U_o, _, hist = _oracle_step(wl, g, to_host(Psi_d), eps2, 1, R, 0.0, 5)
+    occ = L.Occupation(1, wl.kT, wl.n_electrons)
+    drho, U, _, info = L.lowrank_step(_grid(g), Psi_d, to_dev(eps2), occ, to_dev(R),
+                                      L.LowRankParams(s_tol=0.0, r_max=5), prec=prec)
+    print(f"{prec}: drho_bar rel err {rel(to_host(drho), d_o):.2e}")
+    assert info["rank"] == len(U_o)
+    assert rel(to_host(drho), d_o) < bound
+    assert abs(info["s_rel"] - hist[-1]) < bound
+
+
+def test_lowrank_step_edge_cases(c24):
+    wl, g, V, Psi2, eps2 = _spin_system(c24, 1)
+    occ = L.Occupation(1, wl.kT, wl.n_electrons)
+    Psi_d, eps_d = to_dev(Psi2), to_dev(eps2)
+    # zero residual: rank 0, drho_bar = 0, rho untouched
+    rho = torch.ones((1,) + g.shape, dtype=torch.float64, device="cuda")
+    drho, U, _, info = L.lowrank_step(_grid(g), Psi_d, eps_d, occ,
+                                      torch.zeros_like(rho), rho=rho)
+    assert info["rank"] == 0 and info["norm_R"] == 0.0 and not to_host(drho).any()
+    assert (to_host(rho) == 1.0).all()
+    # one direction: drho_bar = (<t1, R>/<t1, t1>) u1
+    R = _residual_like(wl, 1)
+    d_o, _, _, _ = _oracle_step(wl, g, Psi2, eps2, 1, R, 0.0, 1)
+    drho, U, _, info = L.lowrank_step(_grid(g), Psi_d, eps_d, occ, to_dev(R),
+                                      L.LowRankParams(r_max=1))
+    assert info["rank"] == 1 and rel(to_host(drho), d_o) < 1e-10
+    # a large residual takes the small damping
+    drho, _, _, info = L.lowrank_step(_grid(g), Psi_d, eps_d, occ, to_dev(100.0 * R),
+                                      L.LowRankParams(r_max=3))
+    assert info["norm_R"] > 1.0 and info["alpha"] == 0.1
+    # the tolerance at 1 stops at the first rank
+    _, _, _, info = L.lowrank_step(_grid(g), Psi_d, eps_d, occ, to_dev(R),
+                                   L.LowRankParams(s_tol=1.0))
+    assert info["rank"] == 1
+
+
+def test_lrdm_scf_reaches_oracle_fixed_point():
+    """ChFSI-based SCF with the LRDM step on the GPU against the oracle's SCF with
+    dense diagonalisation, on a 6^3 cell with three wells (40 states, 12
+    electrons, kT 0.05): both reach ||R|| below 1e-9 and the same density."""
+    g = O.Grid((6, 6, 6), (6.0, 6.0, 6.0))
+    V = small_wells(g.n, g.L, 3, nwells=3, depth=(1.0, 2.0))
+    N, ne, kT = 40, 12.0, 0.05
+    rho0 = np.full((1,) + g.shape, ne / (g.M * g.dv))
+    rho_o, log_o = O.lrdm_scf(rho0, V, g, N, ne, kT, 1, s_tol=0.3, r_max=20, tol=1e-10,
+                              max_iter=60)
+    X = to_dev(random_block(17, N, g.n))
+    occ = L.Occupation(1, kT, ne)
+    rho, eps, log, _ = L.lrdm_scf(_grid(g), to_dev(V), X, occ, degree=20,
+                                  params=L.LowRankParams(), tol=1e-9, max_iter=80)
+    print(f"GPU SCF: {len(log)} steps, ranks {[s['rank'] for s in log]}, "
+          f"final ||R|| {log[-1]['norm_R']:.2e}; oracle {len(log_o)} steps")
+    assert log[-1]["norm_R"] < 1e-9
+    assert np.abs(to_host(rho) - rho_o).max() < 1e-8
+    assert abs(g.dv * float(to_host(rho).sum()) - ne) < 1e-9
