@@ -47,7 +47,10 @@ def test_density_and_residual(c24, nspin, prec):
     ref, mu_o = O.density(Psi_h, eps2, g, wl.n_electrons, wl.kT, nspin)
     assert rel(to_host(rho), ref) < 1e-12
     assert abs(float(to_host(mu)[0]) - mu_o) < 1e-12
-    assert abs(g.dv * float(to_host(rho).sum()) - wl.n_electrons) < 1e-9
+    count = g.dv * float(to_host(rho).sum())
+    assert abs(count - g.dv * float(ref.sum())) < 1e-10
+    if prec == "fp64":      # the FP32-rounded block is orthonormal only to about 1e-8
+        assert abs(count - wl.n_electrons) < 1e-9
     rho_in = np.random.default_rng(3).uniform(0, 0.01, ref.shape)
     R_d = to_dev(rho_in)                      # in place: out is rho_in
     L.density(_grid(g), Psi_d, to_dev(eps2), occ, prec=prec, rho_in=R_d, out=R_d)
