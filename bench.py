@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-peaks", action="store_true",
                     help="skip the copy and GEMM measurements of the achievable peaks")
+    ap.add_argument("--no-lrdm-step", action="store_true",
+                    help="skip timing the low-rank step around the path")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run three 1 GiB device copies first: a kernel of known traffic for "
                          "scaling hardware byte counters")
@@ -194,7 +196,38 @@ def main():
                                             prec=form)
             rel = float((torch.linalg.vector_norm(t_stage - ref["t"]) / drho_norm).item())
             rel_e2e = float((torch.linalg.vector_norm(t_out - ref["t"]) / drho_norm).item())
+        # the LRDM step around the path (Sec. II B): the model-SCF residual at a
+        # uniform input density on this form's Ritz pairs, then low-rank steps with
+        # the paper's parameters (one direction per response launch, adaptive rank)
+        lrdm = None
+        if not args.no_lrdm_step:
+            vol = float(wl.L[0] * wl.L[1] * wl.L[2])
+            rho_in = torch.full((1,) + grid.shape, wl.n_electrons / vol, dtype=torch.float64,
+                                device=dev)
+            Rres = torch.empty_like(rho_in)
+            L.density(grid, Yf, e_resp, occ, prec=form, rho_in=rho_in, out=Rres)
+            prm = L.LowRankParams()
+            Ub = torch.empty((prm.r_max, 1) + grid.shape, dtype=torch.float64, device=dev)
+            Tb = torch.empty_like(Ub)
+            db = torch.empty_like(Rres)
+            L.lowrank_step(grid, Yf, e_resp, occ, Rres, prm, prec=form, U=Ub, T=Tb, drho=db)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                _, _, _, info = L.lowrank_step(grid, Yf, e_resp, occ, Rres, prm, prec=form, U=Ub,
+                                               T=Tb, drho=db)
+            torch.cuda.synchronize()
+            ms_lr = 1e3 * (time.perf_counter() - t0) / args.steps
+            lrdm = dict(ms_per_step=round(ms_lr, 3), rank=info["rank"],
+                        s_rel=round(info["s_rel"], 4), norm_R=round(info["norm_R"], 4),
+                        alpha=info["alpha"],
+                        ms_per_direction=round(ms_lr / max(info["rank"], 1), 3),
+                        ms_per_direction_batched=round(ms_resp / r, 3))
+            log(f"form {form}: LRDM step {ms_lr:.1f} ms, rank {info['rank']}, "
+                f"s_rel {info['s_rel']:.3f}, ||R|| {info['norm_R']:.3f}")
+            del Ub, Tb, db, Rres, rho_in
         results[form] = dict(ms_per_step=ms_step, value=r * args.steps / elapsed, kernels=kern,
+                             lrdm_step=lrdm,
                              rel_err_vs_fp64=rel, rel_err_end_to_end=rel_e2e,
                              ms_response=ms_resp, response_value=1e3 * r / ms_resp)
         log(f"form {form}: {ms_step:.1f} ms/step, {r * args.steps / elapsed:.2f} directions/s; "
@@ -283,6 +316,7 @@ def main():
                       "ms_response": round(v["ms_response"], 3),
                       "rel_err_vs_fp64": v["rel_err_vs_fp64"],
                       "rel_err_end_to_end": v["rel_err_end_to_end"],
+                      "lrdm_step": v["lrdm_step"],
                       "kernel_ms": {k: round(x[0] / max(x[1], 1), 4) for k, x in v["kernels"].items() if x[1]}}
                   for f, v in results.items()},
         "roofline": roofline,
