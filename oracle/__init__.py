@@ -29,6 +29,7 @@ from .lrdm_oracle import (  # noqa: F401
     residual_derivative,
     spin_factor,
     recursive_fermi_response,
+    density_response_recursive,
     fermi_derivatives,
     second_divided_differences,
     density_response_vjp,

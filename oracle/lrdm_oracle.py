@@ -419,6 +419,36 @@ def recursive_fermi_response(eps: np.ndarray, mu: float, kT: float, Hp: np.ndarr
     return x, xp
 
 
+def density_response_recursive(Psi: np.ndarray, eps: np.ndarray, grid: Grid,
+                               n_electrons: float, kT: float, dV: np.ndarray, depth: int,
+                               nspin: int = 1):
+    """delta rho_k with the paper's recursive expansion of depth T in place of the
+    exact Fermi-Dirac function (Eqs. (23)-(24)): the response of
+    P_T(...P_0(D + lam H' - (mu + lam mu') I)) at lam = 0, i.e. the recursion's
+    response to H' minus mu' times its response to the identity, with mu at the
+    Fermi-Dirac electron count and mu' from the traceless condition (summed over
+    both channels).  Shapes as for density_response; returns (drho, mu, dmu)."""
+    Psi = Psi.reshape((nspin,) + Psi.shape[-4:])
+    eps = np.asarray(eps, dtype=np.float64).reshape(nspin, -1)
+    dV = dV.reshape((-1, nspin) + grid.shape)
+    r = dV.shape[0]
+    N = eps.shape[1]
+    s = spin_factor(nspin)
+    mu, _ = fermi_level(eps, n_electrons, kT, nspin)
+    XI = [recursive_fermi_response(eps[c], mu, kT, np.eye(N), depth)[1] for c in range(nspin)]
+    drho = np.empty_like(dV)
+    dmu = np.empty(r)
+    for k in range(r):
+        XH = [recursive_fermi_response(eps[c], mu, kT,
+                                       projected_perturbation(Psi[c], dV[k, c]), depth)[1]
+              for c in range(nspin)]
+        den = sum(np.trace(XI[c]) for c in range(nspin))
+        dmu[k] = sum(np.trace(XH[c]) for c in range(nspin)) / den if abs(den) >= 1e-300 else 0.0
+        for c in range(nspin):
+            drho[k, c] = density_from_matrix(Psi[c], XH[c] - dmu[k] * XI[c], grid.dv, s)
+    return drho, mu, dmu
+
+
 # ---------------------------------------------------------------------------
 # Adjoint of the subspace density response (vector-Jacobian product)
 # ---------------------------------------------------------------------------

@@ -618,3 +618,59 @@ def scf_fixed_points(n=(6, 6, 6), L=(6.0, 6.0, 6.0), N=40, ne=12.0, kT=0.05, see
         rho_m = rho_m + 0.1 * R
     count = abs(g.dv * rho_l.sum() - ne)
     return (float(np.abs(rho_l - rho_m).max()), len(log), steps, count, log[-1][0], nR)
+
+
+# ------------------------------------------------------------------ recursive Fermi expansion
+def _matrix_recursion(A, mu, kT, depth):
+    """P_T(...P_0(A - mu I)) for a full symmetric matrix A, with explicit matrix
+    products and inverses (Eqs. (23)-(24) as written, no diagonal shortcut)."""
+    N = A.shape[0]
+    X = 0.5 * np.eye(N) - (2.0 ** (-(depth + 2))) * (A - mu * np.eye(N)) / kT
+    for _ in range(depth):
+        X2 = X @ X
+        IX = np.eye(N) - X
+        X = X2 @ np.linalg.inv(X2 + IX @ IX)
+    return X
+
+
+def pin_recursive_response_fd(depth=8):
+    """The oracle's first-order perturbation of the recursion at diagonal D equals
+    the Richardson central difference in lam of the full-matrix recursion applied
+    to D + lam H' (fixed mu)."""
+    rng = np.random.default_rng(31)
+    N = 12
+    eps = np.sort(rng.uniform(-0.2, 0.2, N))
+    eps[5] = eps[4]                                  # a degenerate pair
+    A = rng.standard_normal((N, N))
+    Hp = 0.5 * (A + A.T)
+    mu, kT = 0.01, 0.03
+    _, xp = O.recursive_fermi_response(eps, mu, kT, Hp, depth)
+    D = np.diag(eps)
+
+    def central(lam):
+        return (_matrix_recursion(D + lam * Hp, mu, kT, depth)
+                - _matrix_recursion(D - lam * Hp, mu, kT, depth)) / (2 * lam)
+    lam = 1e-4
+    fd = (4 * central(lam / 2) - central(lam)) / 3
+    return _rel(xp, fd)
+
+
+def pin_recursive_density_response(depths=(6, 10, 16, 24)):
+    """delta rho with the recursive expansion: its integral vanishes (the
+    traceless condition conserves the electron count) and it converges to the
+    exact divided-difference response as T grows.  Returns (largest |integral|,
+    relative errors vs the exact response per depth)."""
+    g, N, ne, kT = O.Grid((5, 4, 4), (2.5, 2.0, 2.0)), 12, 8.0, 0.05
+    rng = np.random.default_rng(41)
+    Q, _ = np.linalg.qr(rng.standard_normal((g.M, N)))
+    Psi = Q.T.reshape((N,) + g.shape)
+    eps = np.sort(rng.uniform(-0.6, 0.4, N))
+    dV = rng.standard_normal((2, 1) + g.shape)
+    exact, _, _ = O.density_response(Psi, eps, g, ne, kT, dV, 1)
+    errs = []
+    integral = 0.0
+    for T in depths:
+        d, _, _ = O.density_response_recursive(Psi, eps, g, ne, kT, dV, T, 1)
+        integral = max(integral, float(np.abs(g.dv * d.sum(axis=(1, 2, 3, 4))).max()))
+        errs.append(_rel(d, exact))
+    return integral, errs

@@ -176,11 +176,28 @@ def m_hartree_sign_in_scf(mp):
     return lambda: P.pin_scf_derivative_fd(1) < 1e-9
 
 
+
+def m_recursion_drop_denominator_term(mp):
+    def bad(eps, mu, kT, Hp, depth):
+        x = 0.5 - (2.0 ** (-(depth + 2))) * (np.asarray(eps) - mu) / kT
+        xp = -(2.0 ** (-(depth + 2))) * Hp / kT
+        for _ in range(depth):
+            x2 = x * x
+            y = x2 + (1.0 - x) ** 2
+            x2p = x[:, None] * xp + xp * x[None, :]
+            xp = x2p / y[None, :]                    # the Y' term dropped
+            x = x2 / y
+        return x, xp
+    _patch(mp, "recursive_fermi_response", bad)
+    return lambda: P.pin_recursive_response_fd() < 1e-9
+
+
 MUTANTS = [m_drop_dmu, m_flip_F, m_shift_F_index, m_spin_factor, m_laplacian_half,
            m_cheb_sigma_sign, m_hartree_no_4pi, m_projection_layout, m_density_no_dv,
            m_rr_no_rotation, m_bisection_direction, m_spin_channel_potential,
            m_fermi_omf_subtraction_sign, m_lowrank_gs_sign, m_lowrank_no_S_inverse,
-           m_lowrank_first_direction, m_hartree_sign_in_scf]
+           m_lowrank_first_direction, m_hartree_sign_in_scf,
+           m_recursion_drop_denominator_term]
 
 
 @pytest.mark.parametrize("mutant", MUTANTS, ids=[m.__name__ for m in MUTANTS])

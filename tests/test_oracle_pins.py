@@ -90,3 +90,15 @@ def test_recursive_fermi_expansion_converges_to_divided_differences():
     errs = P.recursion_errors()
     assert all(b < a for a, b in zip(errs, errs[1:]))
     assert errs[-1] < 1e-7
+
+
+def test_recursive_expansion_response_matches_full_matrix_fd():
+    """First-order perturbation of the recursion (Eqs. (23)-(24)) against central
+    differences of the recursion run on full perturbed matrices."""
+    assert P.pin_recursive_response_fd() < 1e-9
+
+
+def test_recursive_density_response_traceless_and_convergent():
+    integral, errs = P.pin_recursive_density_response()
+    assert integral < 1e-13
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 1e-9 and errs[3] < 1e-8
