@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-peaks", action="store_true",
                     help="skip the copy and GEMM measurements of the achievable peaks")
+    ap.add_argument("--fermi-depths", default="6,8,10,12,16",
+                    help="depths of the recursive Fermi expansion compared with the exact "
+                         "divided differences on the FP64 form ('' to skip)")
     ap.add_argument("--no-lrdm-step", action="store_true",
                     help="skip timing the low-rank step around the path")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -226,8 +229,30 @@ def main():
             log(f"form {form}: LRDM step {ms_lr:.1f} ms, rank {info['rank']}, "
                 f"s_rel {info['s_rel']:.3f}, ||R|| {info['norm_R']:.3f}")
             del Ub, Tb, db, Rres, rho_in
+        # the paper's recursive Fermi expansion against the exact divided
+        # differences (Eqs. (23)-(24)), on the FP64 form so that the expansion error
+        # is not hidden by storage rounding: relative error of delta rho = t + u
+        expansion = None
+        depths = [int(x) for x in args.fermi_depths.split(",") if x.strip()]
+        if form == "fp64" and depths:
+            expansion = {}
+            t_exact = t_out.clone()
+            drho_norm = torch.linalg.vector_norm(t_exact + U)
+            t_rec = torch.empty_like(t_exact)
+            try:
+                for T in depths:
+                    ctx.set_fermi_expansion(T)
+                    L.residual_derivative(grid, Yf[None], e_resp[None], occ, U, prec=form,
+                                          out=t_rec)
+                    expansion[str(T)] = float(
+                        (torch.linalg.vector_norm(t_rec - t_exact) / drho_norm).item())
+            finally:
+                ctx.set_fermi_expansion(0)
+            log("recursive Fermi expansion, delta rho error vs exact: "
+                + ", ".join(f"T={k} {v:.2e}" for k, v in expansion.items()))
+            del t_exact, t_rec
         results[form] = dict(ms_per_step=ms_step, value=r * args.steps / elapsed, kernels=kern,
-                             lrdm_step=lrdm,
+                             lrdm_step=lrdm, fermi_expansion=expansion,
                              rel_err_vs_fp64=rel, rel_err_end_to_end=rel_e2e,
                              ms_response=ms_resp, response_value=1e3 * r / ms_resp)
         log(f"form {form}: {ms_step:.1f} ms/step, {r * args.steps / elapsed:.2f} directions/s; "
@@ -319,6 +344,7 @@ def main():
                       "lrdm_step": v["lrdm_step"],
                       "kernel_ms": {k: round(x[0] / max(x[1], 1), 4) for k, x in v["kernels"].items() if x[1]}}
                   for f, v in results.items()},
+        "fermi_expansion_rel_err": results.get("fp64", {}).get("fermi_expansion"),
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

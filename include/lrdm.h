@@ -107,6 +107,19 @@ lrdm_status lrdm_set_stream(lrdm_ctx* ctx, void* hip_stream);
  * device-side check failed (bisection bracket, eigensolver sweeps, NaN/Inf). */
 lrdm_status lrdm_set_checks(lrdm_ctx* ctx, int level);
 
+/* Form of the Fermi function in the response multiplier for the calls that
+ * follow on this context (density_response, lrdm_residual_derivative,
+ * density_response_batched, lrdm_lowrank_step).  depth 0 (the default) uses the
+ * exact Fermi-Dirac divided differences of Eq. (22).  depth T in 1..64 uses the
+ * paper's recursive expansion of depth T instead (Eqs. (23)-(24)): X_0 =
+ * 1/2 - 2^{-(T+2)} (D - mu)/kT, X_n = X^2 (X^2 + (1 - X)^2)^{-1}, whose
+ * first-order response on the diagonal D is the Hadamard multiplier
+ * M_ij = -(2^{-(T+2)}/kT) prod_n g[x_i^(n), x_j^(n)] (g the step map, g[a, b] its
+ * divided difference); M and its diagonal replace F and f' in Gamma and mu'.
+ * mu stays at the Fermi-Dirac electron count.  While depth > 0,
+ * density_response_backward returns LRDM_EUNSUPPORTED. */
+lrdm_status lrdm_set_fermi_expansion(lrdm_ctx* ctx, int32_t depth);
+
 /* Bytes of device workspace the context currently holds. */
 size_t lrdm_workspace_bytes(const lrdm_ctx* ctx);
 

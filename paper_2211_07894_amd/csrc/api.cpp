@@ -262,6 +262,13 @@ extern "C" lrdm_status lrdm_set_checks(lrdm_ctx* ctx, int level) {
   return LRDM_OK;
 }
 
+extern "C" lrdm_status lrdm_set_fermi_expansion(lrdm_ctx* ctx, int32_t depth) {
+  if (!ctx) return fail(nullptr, LRDM_EINVAL, "ctx is NULL");
+  if (depth < 0 || depth > 64) return fail(ctx, LRDM_EINVAL, "depth must be in 0..64");
+  ctx->fermi_depth = depth;
+  return LRDM_OK;
+}
+
 extern "C" size_t lrdm_workspace_bytes(const lrdm_ctx* ctx) { return ctx ? ctx->ws_cap : 0; }
 
 extern "C" lrdm_status lrdm_profile(lrdm_ctx* ctx, int enable) {
@@ -450,7 +457,13 @@ hipError_t run_response(lrdm_ctx* ctx, const Grid3& g, const T* Psi, const doubl
   double* fp = static_cast<double*>(ws_take(ctx, vec));
   double* F = static_cast<double*>(ws_take(ctx, (size_t)ns * N * N * sizeof(double)));
   double* Hp = static_cast<double*>(ws_take(ctx, (size_t)batch * N * N * sizeof(double)));
-  LRDM_HIP(launch_fermi(ctx, eps, N, ns, occ->kT, occ->n_electrons, mu_d, f, omf, fp, F));
+  const int depth = ctx->fermi_depth;
+  LRDM_HIP(launch_fermi(ctx, eps, N, ns, occ->kT, occ->n_electrons, mu_d, f, omf, fp,
+                        depth > 0 ? nullptr : F));
+  // with the recursive expansion its multiplier and diagonal take the places of
+  // F and f' in Gamma = F o H' - mu' diag(f') and in mu'
+  if (depth > 0)
+    LRDM_HIP(launch_recursive_multiplier(ctx, eps, mu_d, N, ns, occ->kT, depth, F, fp));
   LRDM_HIP(launch_tn_sym<T>(ctx, Psi, nullptr, dV, g.M, N, g.M, ns, batch, prec, Hp));
   LRDM_HIP(launch_gamma(ctx, Hp, F, fp, N, ns, r, dmu_d));
   const double s = (ns == 1) ? 2.0 : 1.0;
@@ -652,6 +665,10 @@ extern "C" lrdm_status density_response_backward(lrdm_ctx* ctx, const lrdm_grid*
   const size_t blk = (size_t)ns * N * g.M * prec_bytes(prec);
   if (g_Psi && overlaps(Psi, blk, g_Psi, blk))
     return fail(ctx, LRDM_EINVAL, "g_Psi must not overlap Psi");
+  if (ctx && ctx->fermi_depth > 0)
+    return fail(ctx, LRDM_EUNSUPPORTED,
+                "density_response_backward differentiates the exact Fermi-Dirac form only "
+                "(the context is set to the recursive expansion)");
   lrdm_status st = begin(ctx, backward_bytes(N, g.M, r, ns, prec));
   if (st != LRDM_OK) return st;
   return guarded(ctx, [&]() -> lrdm_status {

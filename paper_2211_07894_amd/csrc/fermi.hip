@@ -108,6 +108,40 @@ __global__ void divided_diff_kernel(const double* __restrict__ eps, const double
   F[((size_t)c * N + i) * N + j] = -(fc[lo] * oc[hi] * phi) / kT;
 }
 
+// The paper's recursive Fermi expansion of depth T (Eqs. (23)-(24)) as a Hadamard
+// multiplier.  On the diagonal subspace Hamiltonian every step
+// g(x) = x^2 / (x^2 + (1 - x)^2) acts on each diagonal entry, so the first-order
+// response of the composition is, entry by entry, the product of the divided
+// differences g[a, b] = (a + b - 2ab) / (y(a) y(b)), y(x) = x^2 + (1 - x)^2, over
+// the T steps, times the slope -2^{-(T+2)}/kT of the first map:
+//   M_ij = -(2^{-(T+2)}/kT) prod_n g[x_i^(n), x_j^(n)],
+//   x^(0) = 1/2 - 2^{-(T+2)} (eps - mu)/kT,  x^(n+1) = g(x^(n)).
+// diag receives M_ii (the response to mu, used for mu').  Symmetric bit for bit:
+// every operation is commutative in (i, j).
+__global__ void recursive_multiplier_kernel(const double* __restrict__ eps,
+                                            const double* __restrict__ mu, int N, double kT,
+                                            int T, double* __restrict__ M,
+                                            double* __restrict__ diag) {
+  const int c = blockIdx.z;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= N || j >= N) return;
+  const double* e = eps + (size_t)c * N;
+  const double scale = ldexp(1.0, -(T + 2)) / kT;
+  double xi = 0.5 - scale * (e[i] - mu[0]);
+  double xj = 0.5 - scale * (e[j] - mu[0]);
+  double m = -scale;
+  for (int n = 0; n < T; ++n) {
+    const double yi = xi * xi + (1.0 - xi) * (1.0 - xi);
+    const double yj = xj * xj + (1.0 - xj) * (1.0 - xj);
+    m *= (xi + xj - 2.0 * (xi * xj)) / (yi * yj);
+    xi = (xi * xi) / yi;
+    xj = (xj * xj) / yj;
+  }
+  M[((size_t)c * N + i) * N + j] = m;
+  if (i == j) diag[(size_t)c * N + i] = m;
+}
+
 // One block per direction: mu'_k = sum_{c,i} f'_ci Hp_kc,ii / sum_{c,i} f'_ci.
 __global__ __launch_bounds__(kFermiThreads) void dmu_kernel(const double* __restrict__ Hp,
                                                             const double* __restrict__ fprime,
@@ -168,6 +202,14 @@ hipError_t launch_fermi(lrdm_ctx* ctx, const double* eps, int N, int nspin, doub
     LRDM_HIP(hipGetLastError());
   }
   return hipSuccess;
+}
+
+hipError_t launch_recursive_multiplier(lrdm_ctx* ctx, const double* eps, const double* mu, int N,
+                                      int nspin, double kT, int depth, double* M, double* diag) {
+  dim3 blk(32, 8);
+  dim3 grd((N + 31) / 32, (N + 7) / 8, nspin);
+  recursive_multiplier_kernel<<<grd, blk, 0, ctx->stream>>>(eps, mu, N, kT, depth, M, diag);
+  return hipGetLastError();
 }
 
 hipError_t launch_gamma(lrdm_ctx* ctx, double* Hp, const double* F, const double* fprime, int N,

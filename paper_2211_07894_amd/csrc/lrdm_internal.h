@@ -24,6 +24,7 @@ struct lrdm_ctx {
   size_t ws_cap = 0;
   size_t ws_top = 0;         // bump pointer inside one call
   int checks = 0;
+  int fermi_depth = 0;       // 0: exact divided differences; T > 0: recursive expansion
   int* dstatus = nullptr;    // device status words (LRDM_DS_*), then the zero page
   const float* zeros = nullptr;  // 128 bytes of device zeros (source of padding loads)
   std::string err;
@@ -103,6 +104,11 @@ hipError_t launch_hpsi_f64(lrdm_ctx* ctx, const Grid3& g, const double* V, const
 hipError_t launch_fermi(lrdm_ctx* ctx, const double* eps, int N, int nspin, double kT,
                         double n_electrons, double* mu, double* f, double* omf, double* fprime,
                         double* F);
+
+// The recursive expansion's multiplier M [nspin][N][N] and its diagonal [nspin][N]
+// (depth T, mu on the device).
+hipError_t launch_recursive_multiplier(lrdm_ctx* ctx, const double* eps, const double* mu, int N,
+                                      int nspin, double kT, int depth, double* M, double* diag);
 
 // H[b] = A_c diag(w_b) B_c^T for b < batch, c = b % nspin, over the grid index;
 // only the upper triangle is formed and mirrored (the callers' products are

@@ -30,7 +30,7 @@ EXPORTED = [
     "lrdm_projected_perturbation", "lrdm_hartree_kernel", "chfsi_filter",
     "subspace_rayleigh_ritz", "density_response", "lrdm_residual_derivative",
     "density_response_backward", "density_response_batched",
-    "lrdm_density", "lrdm_effective_potential", "lrdm_lowrank_step",
+    "lrdm_density", "lrdm_effective_potential", "lrdm_lowrank_step", "lrdm_set_fermi_expansion",
 ]
 
 
@@ -117,6 +117,7 @@ def library() -> ctypes.CDLL:
                 "lrdm_destroy": [vp],
                 "lrdm_set_stream": [vp, vp],
                 "lrdm_set_checks": [vp, ctypes.c_int],
+                "lrdm_set_fermi_expansion": [vp, i32],
                 "lrdm_workspace_bytes": [vp],
                 "lrdm_profile": [vp, ctypes.c_int],
                 "lrdm_profile_read": [vp, ctypes.c_char_p, ctypes.POINTER(f64), ctypes.POINTER(ctypes.c_int64)],
@@ -164,6 +165,11 @@ class Context:
     def check(self, st: int):
         if st != LRDM_OK:
             raise LrdmError(st, self.lib.lrdm_last_error(self.ptr).decode())
+
+    def set_fermi_expansion(self, depth: int):
+        """0: exact Fermi-Dirac divided differences; T > 0: the recursive
+        expansion of depth T in the response multiplier."""
+        self.check(self.lib.lrdm_set_fermi_expansion(self.ptr, int(depth)))
 
     def set_checks(self, level: int):
         self.check(self.lib.lrdm_set_checks(self.ptr, int(level)))

@@ -141,3 +141,7 @@ def test_density_and_potential_validation(lib):
     st = lib.lrdm_effective_potential(None, ctypes.byref(_grid()), P, ctypes.c_void_p(0x2000), 1,
                                       ctypes.c_void_p(0x2000 + 8), None)
     assert st == -1 and "must not overlap" in _err(lib)
+
+
+def test_fermi_expansion_needs_a_context(lib):
+    assert lib.lrdm_set_fermi_expansion(None, 8) == -1 and "ctx is NULL" in _err(lib)
