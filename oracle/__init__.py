@@ -40,4 +40,8 @@ from .lrdm_oracle import (  # noqa: F401
     lowest_states,
     scf_residual,
     lrdm_scf,
+    lowrank_accumulate,
+    linearity_indicator,
+    predicted_residual,
+    lrdma_scf,
 )

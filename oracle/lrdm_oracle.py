@@ -331,6 +331,64 @@ def lowrank_preconditioner(R: np.ndarray, apply_t, grid: Grid, s_tol: float, r_m
     return drho, np.array(U), np.array(T), np.array(hist)
 
 
+def lowrank_accumulate(R: np.ndarray, apply_t, grid: Grid, s_tol: float, U_prev, T_prev,
+                       r_add_max: int):
+    """The accumulated low-rank step of LRDMA (Sec. II B 1, Eq. (14)).
+
+    U_prev, T_prev: directions and derivatives kept from earlier SCF steps (the u's
+    orthonormal).  If they already fit R to s_rel < s_tol (Eq. (10)), nothing is
+    added.  Otherwise new directions are added one at a time: the first is R with
+    its projections on all earlier directions removed, normalised; each later one
+    is the newest t with its projections on all directions removed, normalised
+    (Eq. (8) against the whole history); each new t comes from apply_t at the
+    current density.  Adding stops when s_rel < s_tol or r_add_max were added
+    (r_add_max = 0: only the kept directions are fitted).  P^lr R (Eq. (9)) then
+    uses every direction, kept and new.
+
+    Returns (drho_bar, U, T, s_rel, added, fit) with fit = sum_i y_i t_i, the
+    low-rank approximation of J applied to drho_bar (I_r^t R)."""
+    U = [u for u in U_prev]
+    T = [t for t in T_prev]
+    nR = np.sqrt(inner(R, R, grid))
+
+    def solve():
+        r = len(T)
+        S = np.array([[inner(T[i], T[j], grid) for j in range(r)] for i in range(r)])
+        c = np.array([inner(T[j], R, grid) for j in range(r)])
+        y = np.linalg.solve(S, c)
+        fit = sum(y[i] * T[i] for i in range(r))
+        return y, fit, np.sqrt(inner(fit - R, fit - R, grid)) / nR
+
+    added = 0
+    if T:
+        y, fit, s_rel = solve()
+        if s_rel < s_tol or r_add_max == 0:
+            return sum(y[i] * U[i] for i in range(len(U))), np.array(U), np.array(T), s_rel, 0, fit
+    v = R
+    while True:
+        u = v - sum(inner(v, U[k], grid) * U[k] for k in range(len(U)))
+        U.append(u / np.sqrt(inner(u, u, grid)))
+        T.append(apply_t(U[-1]))
+        added += 1
+        y, fit, s_rel = solve()
+        if s_rel < s_tol or added == r_add_max:
+            break
+        v = T[-1]
+    return sum(y[i] * U[i] for i in range(len(U))), np.array(U), np.array(T), s_rel, added, fit
+
+
+def predicted_residual(R: np.ndarray, fit: np.ndarray, alpha: float) -> np.ndarray:
+    """R_lin for the next step, R - alpha I_r^t R (Eq. (12)), from this step's
+    residual, the low-rank fit I_r^t R = sum_i y_i t_i and the damping."""
+    return R - alpha * fit
+
+
+def linearity_indicator(norm_R_lin: float, norm_R: float) -> float:
+    """beta = | ||R_lin|| / ||R|| - 1 | (Eq. (13)), with R_lin the residual the last
+    step's low-rank model predicted for this step (Eq. (12))."""
+    return abs(norm_R_lin / norm_R - 1.0)
+
+
 def damping(norm_R: float, far: float = 0.1, near: float = 0.5, switch: float = 1.0) -> float:
     """alpha of the quasi-Newton step (Eq. (4)) as Sec. II B sets it: the small
     value while ||R|| is at or above a threshold of order one, the larger below."""
@@ -389,6 +447,75 @@ def lrdm_scf(rho0: np.ndarray, V_ext: np.ndarray, grid: Grid, N: int, n_electron
         alpha = damping(nR)
         rho = rho - alpha * drho
         log.append((nR, len(U), float(hist[-1]), alpha))
+    return rho, log
+
+
+def lrdma_scf(rho0: np.ndarray, V_ext: np.ndarray, grid: Grid, N: int, n_electrons: float,
+              kT: float, nspin: int = 1, s_tol: float = 0.3, beta_tol: float = 0.1,
+              r_iter_max: int = 5, r_switch: float = 1.0, r_max: int = 20, tol: float = 1e-9,
+              max_iter: int = 50):
+    """SCF with the accumulated low-rank step (LRDMA, Sec. II B 1).
+
+    At each step, with R = R[rho]:
+      * no history, or a clearing pending from the last step (CT): build afresh;
+      * beta = |||R_lin|| / ||R|| - 1| > beta_tol: clear (CL) and build afresh;
+      * else if the kept approximation fits R (s_rel < s_tol): use it as it is;
+      * else if ||R|| > r_switch: clear (CR) and build afresh;
+      * else accumulate up to r_iter_max new directions on the kept ones; if s_rel
+        is still above s_tol, clear before the next step (CT).
+    Building afresh is the LRDM step of Eqs. (8)-(10) (up to r_max directions);
+    r_max also caps the accumulated rank (a full history is cleared, as CT).
+    R_lin = R - alpha I_r^t R with I_r^t R = sum_i y_i t_i (Eq. (12)) is the
+    residual this step's approximation and alpha predict for the next step.
+    Returns (rho, log of (||R||, rank, added, event, s_rel, alpha, beta))."""
+    rho = rho0.reshape((nspin,) + grid.shape).copy()
+    U, T = [], []
+    norm_R_lin = None
+    clear_next = False
+    log = []
+    for _ in range(max_iter):
+        R, Psi, eps = scf_residual(rho, V_ext, grid, N, n_electrons, kT, nspin)
+        nR = np.sqrt(inner(R, R, grid))
+        if nR < tol:
+            log.append((nR, len(U), 0, "done", 0.0, 0.0, None))
+            break
+
+        def apply_t(u):
+            return residual_derivative(Psi, eps, grid, n_electrons, kT, u[None], nspin)[0][0]
+
+        beta = None if norm_R_lin is None else linearity_indicator(norm_R_lin, nR)
+        event = "fresh"
+        if len(U) >= r_max:                          # no room to accumulate: start again
+            clear_next = True
+        if U and not clear_next:
+            if beta > beta_tol:
+                event = "CL"
+            else:
+                event = "keep"
+        elif U and clear_next:
+            event = "CT"
+        if event == "keep":
+            drho, U2, T2, s_rel, added, fit = lowrank_accumulate(R, apply_t, grid, s_tol, U, T, 0)
+            if s_rel < s_tol:
+                event, U, T = "reuse", list(U2), list(T2)
+            elif nR > r_switch:
+                event = "CR"
+            else:
+                drho, U2, T2, s_rel, added, fit = lowrank_accumulate(
+                    R, apply_t, grid, s_tol, U, T, min(r_iter_max, r_max - len(U)))
+                U, T = list(U2), list(T2)
+                event = "accumulate"
+                clear_next = s_rel >= s_tol
+        if event in ("fresh", "CL", "CR", "CT"):
+            drho, U2, T2, s_rel, added, fit = lowrank_accumulate(R, apply_t, grid, s_tol, [], [],
+                                                                 r_max)
+            U, T = list(U2), list(T2)
+            clear_next = False
+        alpha = damping(nR, switch=r_switch)
+        rho = rho - alpha * drho
+        R_lin = predicted_residual(R, fit, alpha)
+        norm_R_lin = np.sqrt(inner(R_lin, R_lin, grid))
+        log.append((nR, len(U), added if event != "reuse" else 0, event, s_rel, alpha, beta))
     return rho, log
 
 

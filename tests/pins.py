@@ -674,3 +674,57 @@ def pin_recursive_density_response(depths=(6, 10, 16, 24)):
         integral = max(integral, float(np.abs(g.dv * d.sum(axis=(1, 2, 3, 4))).max()))
         errs.append(_rel(d, exact))
     return integral, errs
+
+
+# ------------------------------------------------------------------ accumulated low-rank step
+def pin_accumulate_union_lstsq():
+    """For a linear residual map, the accumulated step over kept directions (from
+    an earlier residual) plus new ones equals the least-squares minimiser of
+    ||J x - R|| over the span of all of them: U lstsq(J U, R), with J U formed
+    from the matrix (no S, no Gram-Schmidt).  Also checks the kept directions
+    enter unchanged and the new ones are orthonormal to them."""
+    g, J, R0, apply_t = _linear_residual(seed=13)
+    _, U0, T0, _ = O.lowrank_preconditioner(R0, apply_t, g, 0.0, 3)
+    R1 = np.random.default_rng(14).standard_normal(R0.shape)
+    drho, U, T, s_rel, added, fit = O.lowrank_accumulate(R1, apply_t, g, 0.0, list(U0), list(T0), 4)
+    Um = U.reshape(len(U), -1).T
+    JU = J @ Um
+    y = np.linalg.lstsq(JU, R1.ravel(), rcond=None)[0]
+    err = _rel(drho.ravel(), Um @ y)
+    err = max(err, abs(s_rel - np.linalg.norm(JU @ y - R1.ravel()) / np.linalg.norm(R1.ravel())))
+    err = max(err, _rel(fit.ravel(), JU @ y), float(added != 4))
+    err = max(err, _rel(U[:3], U0), np.abs(g.dv * Um.T @ Um - np.eye(len(U))).max())
+    return err
+
+
+def pin_accumulate_empty_history():
+    """With no history the accumulated step is the LRDM step of Eqs. (8)-(10)."""
+    g, J, R, apply_t = _linear_residual()
+    d1, U1, _, h1 = O.lowrank_preconditioner(R, apply_t, g, 0.3, 10)
+    d2, U2, _, s2, added, _ = O.lowrank_accumulate(R, apply_t, g, 0.3, [], [], 10)
+    return max(_rel(d2, d1), abs(s2 - h1[-1]), float(added != len(U1)))
+
+
+def pin_linear_prediction():
+    """Eq. (12): for a linear residual map with exact directional derivatives the
+    predicted residual R - alpha I_r^t R equals the residual after the step
+    rho - alpha drho_bar, so beta of Eq. (13) vanishes."""
+    g, J, R0, apply_t = _linear_residual(seed=17)
+    alpha = 0.5
+    drho, _, _, _, _, fit = O.lowrank_accumulate(R0, apply_t, g, 0.3, [], [], 5)
+    R_lin = O.predicted_residual(R0, fit, alpha)
+    R1 = R0 + apply_t(-alpha * drho)                 # R[rho - alpha drho] of the linear map
+    beta = O.linearity_indicator(np.sqrt(O.inner(R_lin, R_lin, g)), np.sqrt(O.inner(R1, R1, g)))
+    return max(_rel(R_lin, R1), beta)
+
+
+def lrdma_vs_lrdm(n=(8, 8, 8), L=(9.0, 9.0, 9.0), N=60, ne=16.0, kT=0.02, seed=5):
+    """LRDMA and LRDM SCF from a uniform density: (max density difference of their
+    fixed points, LRDMA directions, LRDM directions, LRDMA events, final ||R||)."""
+    g = O.Grid(n, L)
+    V = small_wells(n, L, seed, nwells=4, depth=(1.0, 2.0))
+    rho0 = np.full((1,) + g.shape, ne / (g.M * g.dv))
+    rho_a, log_a = O.lrdma_scf(rho0, V, g, N, ne, kT, 1, tol=1e-9, max_iter=80)
+    rho_l, log_l = O.lrdm_scf(rho0, V, g, N, ne, kT, 1, tol=1e-9, max_iter=80)
+    return (float(np.abs(rho_a - rho_l).max()), sum(x[2] for x in log_a),
+            sum(x[1] for x in log_l), [x[3] for x in log_a], log_a[-1][0])

@@ -55,3 +55,27 @@ def test_lrdm_scf_reaches_the_mixing_fixed_point():
     assert diff < 1e-9
     assert count < 1e-12
     assert lrdm_steps < mix_steps / 3
+
+
+def test_accumulated_step_is_least_squares_over_all_directions():
+    assert P.pin_accumulate_union_lstsq() < 1e-11
+
+
+def test_accumulated_step_without_history_is_the_lrdm_step():
+    assert P.pin_accumulate_empty_history() < 1e-12
+
+
+def test_linear_prediction_and_indicator():
+    assert P.pin_linear_prediction() < 1e-12
+
+
+def test_linearity_indicator_definition():
+    assert O.linearity_indicator(1.2, 1.0) == pytest.approx(0.2)
+    assert O.linearity_indicator(0.9, 1.0) == pytest.approx(0.1)
+
+
+def test_lrdma_reaches_lrdm_fixed_point_with_fewer_directions():
+    diff, dirs_a, dirs_l, events, final = P.lrdma_vs_lrdm()
+    assert final < 1e-9 and diff < 1e-8
+    assert dirs_a < dirs_l
+    assert "accumulate" in events and "reuse" in events

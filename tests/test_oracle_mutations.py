@@ -192,12 +192,34 @@ def m_recursion_drop_denominator_term(mp):
     return lambda: P.pin_recursive_response_fd() < 1e-9
 
 
+
+def m_accumulate_first_direction_not_orthogonalised(mp):
+    orig = ORIG["lowrank_accumulate"]
+
+    def bad(R, apply_t, grid, s_tol, U_prev, T_prev, r_add_max):
+        if not U_prev:
+            return orig(R, apply_t, grid, s_tol, U_prev, T_prev, r_add_max)
+        # the history is fitted, but the new directions ignore it
+        d, U, T, s, a, f = orig(R, apply_t, grid, s_tol, [], [], r_add_max)
+        U = np.concatenate([np.array(U_prev), U])
+        T = np.concatenate([np.array(T_prev), T])
+        return d, U, T, s, a, f
+    _patch(mp, "lowrank_accumulate", bad)
+    return lambda: P.pin_accumulate_union_lstsq() < 1e-11
+
+
+def m_predicted_residual_sign(mp):
+    _patch(mp, "predicted_residual", lambda R, fit, alpha: R + alpha * fit)
+    return lambda: P.pin_linear_prediction() < 1e-12
+
+
 MUTANTS = [m_drop_dmu, m_flip_F, m_shift_F_index, m_spin_factor, m_laplacian_half,
            m_cheb_sigma_sign, m_hartree_no_4pi, m_projection_layout, m_density_no_dv,
            m_rr_no_rotation, m_bisection_direction, m_spin_channel_potential,
            m_fermi_omf_subtraction_sign, m_lowrank_gs_sign, m_lowrank_no_S_inverse,
            m_lowrank_first_direction, m_hartree_sign_in_scf,
-           m_recursion_drop_denominator_term]
+           m_recursion_drop_denominator_term, m_accumulate_first_direction_not_orthogonalised,
+           m_predicted_residual_sign]
 
 
 @pytest.mark.parametrize("mutant", MUTANTS, ids=[m.__name__ for m in MUTANTS])
