@@ -13,8 +13,9 @@
  *   density_response        delta rho[dV] in span(Psi_R)         (Eqs. (19)-(22))
  *   density_response_backward  its vector-Jacobian product (adjoint)
  *   lrdm_residual_derivative t = chi0 K_c u - u                  (Eqs. (3), (7))
- *   lrdm_lowrank_step       drho_bar = P^lr_r R, adaptive r, and the damped
- *                           quasi-Newton update of rho              (Sec. II B, Eqs. (4), (8)-(10))
+ *   lrdm_lowrank_step       drho_bar = P^lr_r R, adaptive r, the damped
+ *                           quasi-Newton update of rho, and the accumulated
+ *                           variant over kept directions   (Sec. II B, Eqs. (4), (8)-(14))
  *   lrdm_density, lrdm_effective_potential  the model SCF map rho -> R[rho]
  *                           around them                             (Sec. II A, Eq. (1))
  *
@@ -298,45 +299,61 @@ lrdm_status lrdm_effective_potential(lrdm_ctx* ctx, const lrdm_grid* grid, const
                                      double* range);
 
 /* Parameters of the low-rank step (Sec. II B).  Values the paper uses:
- * s_tol 0.3, alpha_far 0.1, alpha_near 0.5, r_switch 1.0. */
+ * s_tol 0.3, alpha_far 0.1, alpha_near 0.5, r_switch 1.0, and for the
+ * accumulated variant at most 5 new directions per SCF step. */
 typedef struct {
   double s_tol;       /* stop at the first rank whose s_rel (Eq. (10)) is below s_tol (>= 0) */
-  int32_t r_max;      /* most directions, 1..64; U and T hold r_max vectors */
+  int32_t r_max;      /* capacity of U and T in directions, 1..64 (kept + new) */
   double alpha_far;   /* damping while ||R|| >= r_switch, in (0, 1] */
   double alpha_near;  /* damping once ||R|| < r_switch, in (0, 1] */
   double r_switch;    /* threshold on ||R|| (>= 0) */
+  int32_t r_add_max;  /* new directions this call: k > 0 at most k, 0 up to r_max,
+                         -1 none (fit R with the kept directions only) */
 } lrdm_lowrank_params;
 
 /* What a low-rank step did (host struct). */
 typedef struct {
-  int32_t rank;       /* directions used (0 for R = 0) */
+  int32_t rank;       /* directions used, kept + new (0 for R = 0 without kept ones) */
+  int32_t added;      /* new directions computed by this call */
   double s_rel;       /* Eq. (10) at that rank */
   double norm_R;      /* ||R||, the norm of the cell integral (direct sum over channels) */
   double alpha;       /* damping chosen from norm_R */
+  double norm_R_lin;  /* ||R - alpha I_r^t R||: the residual the approximation predicts
+                         after the update (Eq. (12)); its ratio to the next ||R|| gives
+                         the linearity indicator beta of Eq. (13) */
 } lrdm_lowrank_info;
 
-/* One LRDM step (Sec. II B).  Directions u_1 = R/||R|| and, for i > 1, t_{i-1}
- * orthogonalised against u_1..u_{i-1} and normalised (Eq. (8), in the inner
- * product <a, b> = dv sum over points and channels); t_i = chi0 K_c u_i - u_i as
- * in lrdm_residual_derivative (Eq. (7)), one direction per launch sequence.  After
- * each t_i: S_ij = <t_i, t_j>, c_j = <t_j, R>, y = S^{-1} c (Cholesky on the
- * GPU), s_rel = ||sum_j y_j t_j - R|| / ||R|| (Eq. (10)); the loop stops when
- * s_rel < s_tol, at r_max, or when a new direction would vanish (t_i already in
- * span(u), so the fit is exact).  Output drho = sum_i y_i u_i = P^lr_r R
- * (Eq. (9)); with rho non-NULL also rho <- rho - alpha drho (Eq. (4)), alpha
- * from the schedule in params.  The orthogonalisation is applied twice, which
- * leaves the span and drho unchanged and keeps u orthonormal in floating point.
- * Psi, eps, N, occ, prec as for lrdm_residual_derivative; R, drho, rho
- * [nspin][M] double; U, T [r_max][nspin][M] double receive the directions and
- * their derivatives (the first info->rank are meaningful); no two of R, U, T,
- * drho, rho overlap.  Synchronises the stream once per direction (the host reads
- * s_rel to decide the rank).  Errors as for lrdm_residual_derivative, plus
- * EINVAL for params out of range, ENONFINITE for a non-finite ||R|| and ENOTCONV
- * when S is not numerically positive definite. */
+/* One LRDM step (Sec. II B) or, with kept directions, one accumulated LRDMA
+ * step (Sec. II B 1, Eq. (14)).  In the inner product <a, b> = dv sum over
+ * points and channels:
+ *  - the first r_keep rows of U and T hold directions (orthonormal) and their
+ *    derivatives kept from earlier SCF steps; they are fitted to R first, and if
+ *    s_rel < s_tol already (or r_add_max = -1) nothing is added;
+ *  - otherwise new directions are added one at a time: the first is R with its
+ *    components along the kept u's removed (for r_keep = 0, R/||R||), each later
+ *    one the newest t with its components along all u's removed (Eq. (8)), both
+ *    normalised; each new t = chi0 K_c u - u is computed as in
+ *    lrdm_residual_derivative (Eq. (7)), one direction per launch sequence;
+ *  - after each t: S_ij = <t_i, t_j>, c_j = <t_j, R>, y = S^{-1} c (Cholesky on
+ *    the GPU) and s_rel = ||sum_j y_j t_j - R|| / ||R|| (Eq. (10)); adding stops
+ *    when s_rel < s_tol, at r_add_max new, at r_max in all, or when a new
+ *    direction would vanish (the fit is then exact);
+ *  - drho = sum_i y_i u_i = P^lr_r R (Eq. (9)) over all directions; with rho
+ *    non-NULL also rho <- rho - alpha drho (Eq. (4)), alpha from the schedule.
+ * The orthogonalisation is applied twice, which leaves the span and drho
+ * unchanged and keeps u orthonormal in floating point.  Psi, eps, N, occ, prec
+ * as for lrdm_residual_derivative; R, drho, rho [nspin][M] double; U, T
+ * [r_max][nspin][M] double, rows r_keep.. written (the first info->rank are
+ * meaningful); no two of R, U, T, drho, rho overlap.  Synchronises the stream
+ * once per new direction and once for the kept fit.  Errors as for
+ * lrdm_residual_derivative, plus EINVAL for params out of range or r_keep
+ * outside 0..r_max, ENONFINITE for a non-finite ||R|| and ENOTCONV when S is
+ * not numerically positive definite. */
 lrdm_status lrdm_lowrank_step(lrdm_ctx* ctx, const lrdm_grid* grid, const void* Psi,
                               const double* eps, int32_t N, const lrdm_occ* occ, lrdm_prec prec,
-                              const double* R, const lrdm_lowrank_params* params, double* U,
-                              double* T, double* drho, double* rho, lrdm_lowrank_info* info);
+                              const double* R, const lrdm_lowrank_params* params, int32_t r_keep,
+                              double* U, double* T, double* drho, double* rho,
+                              lrdm_lowrank_info* info);
 
 #ifdef __cplusplus
 }

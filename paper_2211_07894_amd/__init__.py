@@ -27,4 +27,4 @@ from .lrdm import (  # noqa: F401
     effective_potential,
     lowrank_step,
 )
-from .scf import lrdm_scf  # noqa: F401,E402
+from .scf import lrdm_scf, lrdma_scf  # noqa: F401,E402

@@ -803,21 +803,23 @@ extern "C" lrdm_status lrdm_effective_potential(lrdm_ctx* ctx, const lrdm_grid* 
 namespace {
 
 // Slots of the small host-read block of lrdm_lowrank_step.
-enum { LR_NR2 = 0, LR_FIT2 = 1, LR_UNEW2 = 2, LR_T2 = 3, LR_SLOTS = 4 };
+enum { LR_NR2 = 0, LR_FIT2 = 1, LR_UNEW2 = 2, LR_V2 = 3, LR_RW = 4, LR_SLOTS = 5 };
 
 template <typename T>
 lrdm_status run_lowrank(lrdm_ctx* ctx, const Grid3& g, const T* Psi, const double* eps, int N,
                         const lrdm_occ* occ, lrdm_prec prec, const double* R,
-                        const lrdm_lowrank_params* prm, double* U, double* Tm, double* drho,
-                        double* rho, lrdm_lowrank_info* info) {
+                        const lrdm_lowrank_params* prm, int r_keep, double* U, double* Tm,
+                        double* drho, double* rho, lrdm_lowrank_info* info) {
   const int ns = occ->nspin;
   const int64_t n = (int64_t)ns * g.M;
   const double dv = g.dv;
   const int K = kMaxLowRank;
+  const int r_cap = prm->r_max;
+  const int add_cap = prm->r_add_max > 0 ? prm->r_add_max : r_cap;
   auto hip_fail = [&](const char* where, hipError_t e) { return fail_hip(ctx, where, e); };
-#define LR_HIP(where, call)                      \
-  do {                                           \
-    hipError_t e_ = (call);                      \
+#define LR_HIP(where, call)                           \
+  do {                                                \
+    hipError_t e_ = (call);                           \
     if (e_ != hipSuccess) return hip_fail(where, e_); \
   } while (0)
   double* S = static_cast<double*>(ws_take(ctx, (size_t)K * K * sizeof(double)));
@@ -831,51 +833,10 @@ lrdm_status run_lowrank(lrdm_ctx* ctx, const Grid3& g, const T* Psi, const doubl
   double* dV = static_cast<double*>(ws_take(ctx, (size_t)n * sizeof(double)));
   double* hs = static_cast<double*>(ws_take(ctx, 2 * (size_t)g.M * sizeof(double)));
   const size_t mark = ctx->ws_top;
-
-  // ||R||
-  double h[LR_SLOTS] = {0, 0, 0, 0};
-  LR_HIP("lowrank norm", launch_dots(ctx, R, 0, 1, R, n, dv, sc + LR_NR2, 1, part));
-  LR_HIP("lowrank read", hipMemcpyAsync(h, sc, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
-  LR_HIP("lowrank sync", hipStreamSynchronize(ctx->stream));
-  if (!std::isfinite(h[LR_NR2])) return fail(ctx, LRDM_ENONFINITE, "||R|| is not finite");
-  const double nR = std::sqrt(h[LR_NR2]);
-  info->norm_R = nR;
-  info->alpha = nR >= prm->r_switch ? prm->alpha_far : prm->alpha_near;
-  if (nR == 0.0) {
-    info->rank = 0;
-    info->s_rel = 0.0;
-    LR_HIP("lowrank zero", launch_combine(ctx, nullptr, 0.0, U, n, y, 0, 1.0, n, drho));
-    return LRDM_OK;
-  }
-  LR_HIP("lowrank u1", launch_normalize(ctx, R, sc + LR_NR2, n, U));
-  int rank = 0;
-  double s_rel = 1.0;
-  for (int i = 0; i < prm->r_max; ++i) {
-    double* ui = U + (size_t)i * n;
-    double* ti = Tm + (size_t)i * n;
-    ctx->ws_top = mark;        // the response's slices are reused by every direction
-    LR_HIP("lowrank hartree", launch_hartree(ctx, g, ui, ns, dV, ns, 1, hs));
-    LR_HIP("lowrank response",
-           run_response<T>(ctx, g, Psi, eps, N, occ, dV, 1, prec, ui, ti, nullptr, nullptr));
-    // row i of S, c_i, the coefficients and the fit residual of Eq. (10)
-    LR_HIP("lowrank S", launch_dots(ctx, Tm, n, i + 1, ti, n, dv, S + (size_t)i * K, 1, part));
-    LR_HIP("lowrank c", launch_dots(ctx, ti, 0, 1, R, n, dv, c + i, 1, part));
-    LR_HIP("lowrank solve", launch_lowrank_solve(ctx, S, K, c, i + 1, y, flag));
-    LR_HIP("lowrank fit", launch_combine(ctx, R, -1.0, Tm, n, y, i + 1, 1.0, n, w));
-    LR_HIP("lowrank fit norm", launch_dots(ctx, w, 0, 1, w, n, dv, sc + LR_FIT2, 1, part));
-    const bool more = i + 1 < prm->r_max;
-    if (more) {
-      // the next direction (Eq. (8)), formed before the host decides so that one
-      // synchronisation per direction suffices; projections removed twice
-      double* un = U + (size_t)(i + 1) * n;
-      LR_HIP("lowrank gs", launch_dots(ctx, U, n, i + 1, ti, n, dv, gco, 1, part));
-      LR_HIP("lowrank gs", launch_combine(ctx, ti, 1.0, U, n, gco, i + 1, -1.0, n, un));
-      LR_HIP("lowrank gs2", launch_dots(ctx, U, n, i + 1, un, n, dv, gco, 1, part));
-      LR_HIP("lowrank gs2", launch_combine(ctx, un, 1.0, U, n, gco, i + 1, -1.0, n, un));
-      LR_HIP("lowrank unorm", launch_dots(ctx, un, 0, 1, un, n, dv, sc + LR_UNEW2, 1, part));
-      LR_HIP("lowrank tnorm", launch_dots(ctx, ti, 0, 1, ti, n, dv, sc + LR_T2, 1, part));
-    }
-    int hflag = 0;
+  double h[LR_SLOTS] = {0, 0, 0, 0, 0};
+  int hflag = 0;
+  // host read of the scalar block and the solve flag (one synchronisation)
+  auto read = [&]() -> lrdm_status {
     LR_HIP("lowrank read", hipMemcpyAsync(h, sc, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
     LR_HIP("lowrank read", hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost,
                                           ctx->stream));
@@ -884,20 +845,104 @@ lrdm_status run_lowrank(lrdm_ctx* ctx, const Grid3& g, const T* Psi, const doubl
       return fail(ctx, LRDM_ENOTCONV,
                   "lrdm_lowrank_step: the Gram matrix of the directional derivatives is not "
                   "numerically positive definite");
+    return LRDM_OK;
+  };
+  // S row i, c_i, y = S^{-1} c over i + 1 derivatives, the fit residual
+  // w = sum_j y_j t_j - R (Eq. (10)) with its norm and <R, w>
+  auto fit = [&](int i) -> hipError_t {
+    const double* ti = Tm + (size_t)i * n;
+    LRDM_HIP(launch_dots(ctx, Tm, n, i + 1, ti, n, dv, S + (size_t)i * K, 1, part));
+    LRDM_HIP(launch_dots(ctx, ti, 0, 1, R, n, dv, c + i, 1, part));
+    LRDM_HIP(launch_lowrank_solve(ctx, S, K, c, i + 1, y, flag));
+    LRDM_HIP(launch_combine(ctx, R, -1.0, Tm, n, y, i + 1, 1.0, n, w));
+    LRDM_HIP(launch_dots(ctx, w, 0, 1, w, n, dv, sc + LR_FIT2, 1, part));
+    return launch_dots(ctx, w, 0, 1, R, n, dv, sc + LR_RW, 1, part);
+  };
+  // un = v - sum_{k<m} <v, u_k> u_k, twice, and |un|^2, |v|^2
+  auto orthogonalise = [&](const double* v, int m, double* un) -> hipError_t {
+    LRDM_HIP(launch_dots(ctx, U, n, m, v, n, dv, gco, 1, part));
+    LRDM_HIP(launch_combine(ctx, v, 1.0, U, n, gco, m, -1.0, n, un));
+    LRDM_HIP(launch_dots(ctx, U, n, m, un, n, dv, gco, 1, part));
+    LRDM_HIP(launch_combine(ctx, un, 1.0, U, n, gco, m, -1.0, n, un));
+    LRDM_HIP(launch_dots(ctx, un, 0, 1, un, n, dv, sc + LR_UNEW2, 1, part));
+    return launch_dots(ctx, v, 0, 1, v, n, dv, sc + LR_V2, 1, part);
+  };
+
+  // ||R||
+  LR_HIP("lowrank norm", launch_dots(ctx, R, 0, 1, R, n, dv, sc + LR_NR2, 1, part));
+  LR_HIP("lowrank read", hipMemcpyAsync(h, sc, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+  LR_HIP("lowrank sync", hipStreamSynchronize(ctx->stream));
+  if (!std::isfinite(h[LR_NR2])) return fail(ctx, LRDM_ENONFINITE, "||R|| is not finite");
+  const double nR = std::sqrt(h[LR_NR2]);
+  const double alpha = nR >= prm->r_switch ? prm->alpha_far : prm->alpha_near;
+  info->norm_R = nR;
+  info->alpha = alpha;
+  info->added = 0;
+  if (nR == 0.0) {
+    info->rank = r_keep;
+    info->s_rel = 0.0;
+    info->norm_R_lin = 0.0;
+    LR_HIP("lowrank zero", launch_combine(ctx, nullptr, 0.0, U, n, y, 0, 1.0, n, drho));
+    return LRDM_OK;
+  }
+  int rank = r_keep;
+  double s_rel = 1.0;
+  bool grow = prm->r_add_max >= 0;
+  if (r_keep > 0) {
+    // the kept directions first: rebuild S over their derivatives, fit R
+    for (int i = 0; i < r_keep; ++i) LR_HIP("lowrank kept", fit(i));
+    lrdm_status st = read();
+    if (st != LRDM_OK) return st;
+    s_rel = std::sqrt(h[LR_FIT2]) / nR;
+    grow = grow && !(s_rel < prm->s_tol) && r_keep < r_cap;
+  }
+  if (grow) {
+    // the first new direction: R without its components along the kept ones
+    double* un = U + (size_t)r_keep * n;
+    LR_HIP("lowrank first", orthogonalise(R, r_keep, un));
+    if (r_keep > 0) {
+      lrdm_status st = read();
+      if (st != LRDM_OK) return st;
+      grow = h[LR_UNEW2] > 1e-26 * h[LR_V2];    // R already in span(U): nothing new
+    } else {
+      h[LR_UNEW2] = h[LR_NR2];
+    }
+    if (grow) LR_HIP("lowrank normalize", launch_normalize(ctx, un, sc + LR_UNEW2, n, un));
+  }
+  for (int i = r_keep; grow && i < r_cap; ++i) {
+    double* ui = U + (size_t)i * n;
+    double* ti = Tm + (size_t)i * n;
+    ctx->ws_top = mark;        // the response's slices are reused by every direction
+    LR_HIP("lowrank hartree", launch_hartree(ctx, g, ui, ns, dV, ns, 1, hs));
+    LR_HIP("lowrank response",
+           run_response<T>(ctx, g, Psi, eps, N, occ, dV, 1, prec, ui, ti, nullptr, nullptr));
+    LR_HIP("lowrank fit", fit(i));
+    const int added = i - r_keep + 1;
+    const bool more = i + 1 < r_cap && added < add_cap;
+    // the next direction (Eq. (8)), formed before the host decides so that one
+    // synchronisation per direction suffices
+    if (more) LR_HIP("lowrank next", orthogonalise(ti, i + 1, U + (size_t)(i + 1) * n));
+    lrdm_status st = read();
+    if (st != LRDM_OK) return st;
     rank = i + 1;
+    info->added = added;
     s_rel = std::sqrt(h[LR_FIT2]) / nR;
     if (!std::isfinite(s_rel)) return fail(ctx, LRDM_ENONFINITE, "s_rel is not finite");
     if (s_rel < prm->s_tol || !more) break;
-    // t_i inside span(u_1..u_i): the Krylov space is exhausted and the fit exact
-    if (!(h[LR_UNEW2] > 1e-26 * h[LR_T2])) break;
+    // t_i inside span(u_1..u_{i+1}): the Krylov space is exhausted and the fit exact
+    if (!(h[LR_UNEW2] > 1e-26 * h[LR_V2])) break;
     double* un = U + (size_t)(i + 1) * n;
     LR_HIP("lowrank normalize", launch_normalize(ctx, un, sc + LR_UNEW2, n, un));
   }
+  // drho_bar = sum_i y_i u_i (Eq. (9)); R_lin = (1 - alpha) R - alpha w (Eq. (12))
   LR_HIP("lowrank drho", launch_combine(ctx, nullptr, 0.0, U, n, y, rank, 1.0, n, drho));
-  if (rho) LR_HIP("lowrank update", launch_axpy(ctx, -info->alpha, drho, n, rho));
+  if (rho) LR_HIP("lowrank update", launch_axpy(ctx, -alpha, drho, n, rho));
   if (ctx->checks) LR_HIP("lowrank check", launch_check_finite(ctx, drho, n));
+  const double lin2 = (1.0 - alpha) * (1.0 - alpha) * h[LR_NR2] -
+                      2.0 * alpha * (1.0 - alpha) * h[LR_RW] + alpha * alpha * h[LR_FIT2];
   info->rank = rank;
   info->s_rel = s_rel;
+  info->norm_R_lin = std::sqrt(std::max(lin2, 0.0));
   return LRDM_OK;
 #undef LR_HIP
 }
@@ -907,8 +952,9 @@ lrdm_status run_lowrank(lrdm_ctx* ctx, const Grid3& g, const T* Psi, const doubl
 extern "C" lrdm_status lrdm_lowrank_step(lrdm_ctx* ctx, const lrdm_grid* grid, const void* Psi,
                                          const double* eps, int32_t N, const lrdm_occ* occ,
                                          lrdm_prec prec, const double* R,
-                                         const lrdm_lowrank_params* params, double* U, double* T,
-                                         double* drho, double* rho, lrdm_lowrank_info* info) {
+                                         const lrdm_lowrank_params* params, int32_t r_keep,
+                                         double* U, double* T, double* drho, double* rho,
+                                         lrdm_lowrank_info* info) {
   LRDM_CHECK(ctx, check_grid(grid));
   LRDM_CHECK(ctx, check_block(grid, N));
   LRDM_CHECK(ctx, check_occ(occ, N));
@@ -921,6 +967,8 @@ extern "C" lrdm_status lrdm_lowrank_step(lrdm_ctx* ctx, const lrdm_grid* grid, c
   LRDM_NONNULL(ctx, T, "T");
   LRDM_NONNULL(ctx, drho, "drho");
   LRDM_NONNULL(ctx, info, "info");
+  if (r_keep < 0 || r_keep > params->r_max)
+    return fail(ctx, LRDM_EINVAL, "r_keep must be in 0..r_max");
   const Grid3 g = make_grid3(grid);
   const int ns = occ->nspin;
   const size_t vb = (size_t)ns * g.M * sizeof(double);
@@ -943,8 +991,8 @@ extern "C" lrdm_status lrdm_lowrank_step(lrdm_ctx* ctx, const lrdm_grid* grid, c
   return guarded(ctx, [&]() -> lrdm_status {
     return (prec == LRDM_FP64)
         ? run_lowrank<double>(ctx, g, static_cast<const double*>(Psi), eps, N, occ, prec, R,
-                              params, U, T, drho, rho, info)
+                              params, r_keep, U, T, drho, rho, info)
         : run_lowrank<float>(ctx, g, static_cast<const float*>(Psi), eps, N, occ, prec, R,
-                             params, U, T, drho, rho, info);
+                             params, r_keep, U, T, drho, rho, info);
   });
 }

@@ -58,12 +58,13 @@ class c_system(ctypes.Structure):
 class c_lowrank_params(ctypes.Structure):
     _fields_ = [("s_tol", ctypes.c_double), ("r_max", ctypes.c_int32),
                 ("alpha_far", ctypes.c_double), ("alpha_near", ctypes.c_double),
-                ("r_switch", ctypes.c_double)]
+                ("r_switch", ctypes.c_double), ("r_add_max", ctypes.c_int32)]
 
 
 class c_lowrank_info(ctypes.Structure):
-    _fields_ = [("rank", ctypes.c_int32), ("s_rel", ctypes.c_double),
-                ("norm_R", ctypes.c_double), ("alpha", ctypes.c_double)]
+    _fields_ = [("rank", ctypes.c_int32), ("added", ctypes.c_int32), ("s_rel", ctypes.c_double),
+                ("norm_R", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("norm_R_lin", ctypes.c_double)]
 
 
 @dataclass(frozen=True)
@@ -136,7 +137,7 @@ def library() -> ctypes.CDLL:
                 "lrdm_density": [vp, G, vp, vp, i32, O, ctypes.c_int, vp, vp, vp],
                 "lrdm_effective_potential": [vp, G, vp, vp, i32, vp, vp],
                 "lrdm_lowrank_step": [vp, G, vp, vp, i32, O, ctypes.c_int, vp,
-                                      ctypes.POINTER(c_lowrank_params), vp, vp, vp, vp,
+                                      ctypes.POINTER(c_lowrank_params), i32, vp, vp, vp, vp,
                                       ctypes.POINTER(c_lowrank_info)],
             }
             for name, args in sig.items():
@@ -470,10 +471,11 @@ class LowRankParams:
     alpha_far: float = 0.1
     alpha_near: float = 0.5
     r_switch: float = 1.0
+    r_add_max: int = 0           # 0: up to r_max; k > 0: at most k new; -1: kept ones only
 
     def c(self) -> c_lowrank_params:
         return c_lowrank_params(float(self.s_tol), int(self.r_max), float(self.alpha_far),
-                                float(self.alpha_near), float(self.r_switch))
+                                float(self.alpha_near), float(self.r_switch), int(self.r_add_max))
 
 
 def density(grid: Grid, Psi, eps, occ: Occupation, prec="fp64", rho_in=None, out=None, mu=None):
@@ -510,10 +512,12 @@ def effective_potential(grid: Grid, V_ext, rho, out=None, vrange=None):
 
 
 def lowrank_step(grid: Grid, Psi, eps, occ: Occupation, R, params: LowRankParams = LowRankParams(),
-                 prec="fp64", rho=None, U=None, T=None, drho=None):
+                 prec="fp64", rho=None, U=None, T=None, drho=None, r_keep: int = 0):
     """drho_bar = P^lr_r R with the adaptive rank, and rho -= alpha drho_bar when
-    rho is given (lrdm_lowrank_step).  Returns (drho, U[:rank], T[:rank], info)
-    with info a dict of rank, s_rel, norm_R and alpha."""
+    rho is given (lrdm_lowrank_step).  With r_keep > 0 the first r_keep rows of
+    U and T are directions kept from earlier steps (LRDMA).  Returns (drho,
+    U[:rank], T[:rank], info) with info a dict of rank, added, s_rel, norm_R,
+    alpha and norm_R_lin."""
     ns = occ.nspin
     N = eps.numel() // ns
     n = ns * grid.M
@@ -530,10 +534,11 @@ def lowrank_step(grid: Grid, Psi, eps, occ: Occupation, R, params: LowRankParams
     ctx.check(ctx.lib.lrdm_lowrank_step(
         ctx.ptr, ctypes.byref(g), _ptr(Psi, "Psi", _block_dtype(prec), ns * N * grid.M),
         _ptr(eps, "eps", torch.float64, ns * N), N, ctypes.byref(o), _prec(prec),
-        _ptr(R, "R", torch.float64, n), ctypes.byref(p),
+        _ptr(R, "R", torch.float64, n), ctypes.byref(p), int(r_keep),
         _ptr(U, "U", torch.float64, params.r_max * n), _ptr(T, "T", torch.float64, params.r_max * n),
         _ptr(drho, "drho", torch.float64, n), _opt_ptr(rho, "rho", torch.float64, n),
         ctypes.byref(info)))
     r = int(info.rank)
-    return drho, U[:r], T[:r], dict(rank=r, s_rel=float(info.s_rel), norm_R=float(info.norm_R),
-                                    alpha=float(info.alpha))
+    return drho, U[:r], T[:r], dict(rank=r, added=int(info.added), s_rel=float(info.s_rel),
+                                    norm_R=float(info.norm_R), alpha=float(info.alpha),
+                                    norm_R_lin=float(info.norm_R_lin))

@@ -2,6 +2,7 @@
 // internal launchers at full size) on host memory under AddressSanitizer.
 // Exit status 0 and "EMU OK" when every call returned LRDM_OK with finite
 // outputs; ASan aborts the process on any out-of-bounds access.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -310,18 +311,45 @@ void scenario_lowrank(lrdm_ctx* ctx, lrdm_grid g, int N, int nspin, int r_max, l
                      mu.data()), ctx, name);
   check(lrdm_effective_potential(ctx, &g, Vext.data(), rho.data(), nspin, Veff.data(),
                                  range.data()), ctx, "lrdm_effective_potential");
-  lrdm_lowrank_params prm{0.0, r_max, 0.1, 0.5, 1.0};
+  lrdm_lowrank_params prm{0.0, r_max, 0.1, 0.5, 1.0, 0};
   std::vector<double> U((size_t)r_max * n), T((size_t)r_max * n), drho(n);
   lrdm_lowrank_info info{};
   std::snprintf(name, sizeof name, "lrdm_lowrank_step %s N=%d nspin=%d r_max=%d", prec_name(prec),
                 N, nspin, r_max);
-  check(lrdm_lowrank_step(ctx, &g, Psi.data(), eps.data(), N, &occ, prec, R.data(), &prm,
+  check(lrdm_lowrank_step(ctx, &g, Psi.data(), eps.data(), N, &occ, prec, R.data(), &prm, 0,
                           U.data(), T.data(), drho.data(), rho.data(), &info), ctx, name);
   std::printf("     rank %d s_rel %.3e ||R|| %.3e alpha %.2f\n", info.rank, info.s_rel, info.norm_R,
               info.alpha);
   if (!finite(drho) || info.rank != r_max) {
     std::printf("FAIL lowrank step\n");
     ++failures;
+  }
+  // accumulate on the kept directions with a changed residual (LRDMA): the kept
+  // rows stay, at most two are added, capacity r_max + 2
+  {
+    lrdm_lowrank_params acc{0.0, r_max + 2, 0.1, 0.5, 1.0, 2};
+    std::vector<double> U2((size_t)(r_max + 2) * n), T2((size_t)(r_max + 2) * n);
+    std::copy(U.begin(), U.end(), U2.begin());
+    std::copy(T.begin(), T.end(), T2.begin());
+    std::vector<double> R2(R);
+    for (size_t i = 0; i < n; ++i) R2[i] += 0.01 * std::sin(0.37 * (double)i);
+    check(lrdm_lowrank_step(ctx, &g, Psi.data(), eps.data(), N, &occ, prec, R2.data(), &acc,
+                            r_max, U2.data(), T2.data(), drho.data(), nullptr, &info),
+          ctx, "lrdm_lowrank_step accumulate");
+    std::printf("     accumulated: rank %d added %d s_rel %.3e ||R_lin|| %.3e\n", info.rank,
+                info.added, info.s_rel, info.norm_R_lin);
+    if (!finite(drho) || info.rank != r_max + 2 || info.added != 2) {
+      std::printf("FAIL accumulate step\n");
+      ++failures;
+    }
+    acc.r_add_max = -1;
+    check(lrdm_lowrank_step(ctx, &g, Psi.data(), eps.data(), N, &occ, prec, R2.data(), &acc,
+                            r_max + 2, U2.data(), T2.data(), drho.data(), nullptr, &info),
+          ctx, "lrdm_lowrank_step kept fit only");
+    if (info.added != 0 || info.rank != r_max + 2) {
+      std::printf("FAIL kept-only step\n");
+      ++failures;
+    }
   }
 }
 }  // namespace

@@ -106,6 +106,7 @@ def test_rank_and_plane_limits(lib):
     ("alpha_far", 0.0, "alpha_far must be in (0, 1]"),
     ("alpha_near", 1.5, "alpha_near must be in (0, 1]"),
     ("r_switch", float("nan"), "r_switch must be finite"),
+    ("r_add_max", -2, "r_add_max must be in -1..64"),
 ])
 def test_lowrank_params_validation(lib, field, value, msg):
     p = B.LowRankParams().c()
@@ -113,7 +114,7 @@ def test_lowrank_params_validation(lib, field, value, msg):
     o = B.c_occ(1, 0.01, 20.0)
     info = B.c_lowrank_info()
     st = lib.lrdm_lowrank_step(None, ctypes.byref(_grid()), P, P, 32, ctypes.byref(o), 0, P,
-                               ctypes.byref(p), ctypes.c_void_p(0x10000000),
+                               ctypes.byref(p), 0, ctypes.c_void_p(0x10000000),
                                ctypes.c_void_p(0x20000000), ctypes.c_void_p(0x30000000), None,
                                ctypes.byref(info))
     assert st == -1 and msg in _err(lib)
@@ -126,7 +127,7 @@ def test_lowrank_buffers_must_not_overlap(lib):
     # U holds 4 vectors of 512 doubles; T starts inside it
     U = 0x10000000
     st = lib.lrdm_lowrank_step(None, ctypes.byref(_grid()), P, P, 32, ctypes.byref(o), 0,
-                               ctypes.c_void_p(0x40000000), ctypes.byref(p), ctypes.c_void_p(U),
+                               ctypes.c_void_p(0x40000000), ctypes.byref(p), 0, ctypes.c_void_p(U),
                                ctypes.c_void_p(U + 8 * 512), ctypes.c_void_p(0x30000000), None,
                                ctypes.byref(info))
     assert st == -1 and "must not overlap" in _err(lib)
@@ -145,3 +146,14 @@ def test_density_and_potential_validation(lib):
 
 def test_fermi_expansion_needs_a_context(lib):
     assert lib.lrdm_set_fermi_expansion(None, 8) == -1 and "ctx is NULL" in _err(lib)
+
+
+def test_lowrank_keep_range(lib):
+    p = B.LowRankParams(r_max=4).c()
+    o = B.c_occ(1, 0.01, 20.0)
+    info = B.c_lowrank_info()
+    st = lib.lrdm_lowrank_step(None, ctypes.byref(_grid()), P, P, 32, ctypes.byref(o), 0,
+                               ctypes.c_void_p(0x40000000), ctypes.byref(p), 5,
+                               ctypes.c_void_p(0x10000000), ctypes.c_void_p(0x20000000),
+                               ctypes.c_void_p(0x30000000), None, ctypes.byref(info))
+    assert st == -1 and "r_keep must be in 0..r_max" in _err(lib)

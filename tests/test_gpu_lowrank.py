@@ -173,3 +173,63 @@ def test_lrdm_scf_reaches_oracle_fixed_point():
     assert log[-1]["norm_R"] < 1e-9
     assert np.abs(to_host(rho) - rho_o).max() < 1e-8
     assert abs(g.dv * float(to_host(rho).sum()) - ne) < 1e-9
+
+
+@pytest.mark.parametrize("s_tol,add", [(0.0, 2), (0.3, 5), (0.0, -1)])
+def test_lowrank_accumulate_fp64(c24, s_tol, add):
+    """LRDMA step (Eq. (14)): three directions kept from an earlier residual, a
+    new residual, at most `add` new directions (-1: the kept ones only), against
+    the oracle's accumulated step; also the predicted residual of Eq. (12)."""
+    wl, g, V, Psi2, eps2 = _spin_system(c24, 1)
+    D = grf_directions(wl.system_id, wl.n, wl.L, 2, nspin=1)
+    R0, R1 = 0.7 * D[0], 0.5 * D[0] + 0.3 * D[1]
+
+    def apply_t(u):
+        return O.residual_derivative(Psi2, eps2, g, wl.n_electrons, wl.kT, u[None], 1)[0][0]
+    _, U0, T0, _ = O.lowrank_preconditioner(R0, apply_t, g, 0.0, 3)
+    d_o, U_o, _, s_o, added_o, fit_o = O.lowrank_accumulate(R1, apply_t, g, s_tol, list(U0),
+                                                           list(T0), max(add, 0))
+    r_max = 8
+    U = torch.zeros((r_max, 1) + g.shape, dtype=torch.float64, device="cuda")
+    T = torch.zeros_like(U)
+    U[:3] = to_dev(U0)
+    T[:3] = to_dev(T0)
+    occ = L.Occupation(1, wl.kT, wl.n_electrons)
+    prm = L.LowRankParams(s_tol=s_tol, r_max=r_max, r_add_max=add)
+    drho, Ug, _, info = L.lowrank_step(_grid(g), to_dev(Psi2), to_dev(eps2), occ, to_dev(R1), prm,
+                                       U=U, T=T, r_keep=3)
+    nR = np.sqrt(O.inner(R1, R1, g))
+    R_lin = O.predicted_residual(R1, fit_o, O.damping(nR))
+    print(f"accumulate s_tol {s_tol} add {add}: rank {info['rank']} added {info['added']} "
+          f"s_rel {info['s_rel']:.4e} (oracle {s_o:.4e})")
+    assert info["rank"] == len(U_o) and info["added"] == added_o
+    assert abs(info["s_rel"] - s_o) < 1e-10
+    assert rel(to_host(drho), d_o) < 1e-10
+    assert abs(info["norm_R_lin"] - np.sqrt(O.inner(R_lin, R_lin, g))) < 1e-10 * nR
+    assert rel(to_host(Ug[:3]), U0) == 0.0          # kept rows untouched
+
+
+def test_lrdma_scf_fixed_point_and_fewer_directions():
+    """LRDMA SCF on the GPU (ChFSI, accumulated step, CL/CR/CT events) reaches the
+    oracle's fixed point on the 6^3 cell and computes fewer directions than the
+    GPU LRDM SCF from the same start."""
+    g = O.Grid((6, 6, 6), (6.0, 6.0, 6.0))
+    V = small_wells(g.n, g.L, 3, nwells=3, depth=(1.0, 2.0))
+    N, ne, kT = 40, 12.0, 0.05
+    rho0 = np.full((1,) + g.shape, ne / (g.M * g.dv))
+    rho_o, _ = O.lrdm_scf(rho0, V, g, N, ne, kT, 1, s_tol=0.3, r_max=20, tol=1e-10, max_iter=60)
+    occ = L.Occupation(1, kT, ne)
+    rho_a, _, log_a, _ = L.lrdma_scf(_grid(g), to_dev(V), to_dev(random_block(17, N, g.n)), occ,
+                                     degree=20, tol=1e-9, max_iter=100)
+    _, _, log_l, _ = L.lrdm_scf(_grid(g), to_dev(V), to_dev(random_block(17, N, g.n)), occ,
+                                degree=20, tol=1e-9, max_iter=100)
+    dirs_a = sum(s["added"] for s in log_a)
+    dirs_l = sum(s["rank"] for s in log_l)
+    events = [s["event"] for s in log_a]
+    print(f"LRDMA: {len(log_a)} steps, {dirs_a} directions, events "
+          f"{ {e: events.count(e) for e in set(events)} }; LRDM: {len(log_l)} steps, "
+          f"{dirs_l} directions")
+    assert log_a[-1]["norm_R"] < 1e-9
+    assert np.abs(to_host(rho_a) - rho_o).max() < 1e-8
+    assert dirs_a < dirs_l
+    assert "accumulate" in events or "reuse" in events
