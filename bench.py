@@ -48,6 +48,9 @@ def parse():
     ap.add_argument("--fermi-depths", default="6,8,10,12,16",
                     help="depths of the recursive Fermi expansion compared with the exact "
                          "divided differences on the FP64 form ('' to skip)")
+    ap.add_argument("--scf-steps", type=int, default=12,
+                    help="SCF steps of the model SCF run with the LRDM and the LRDMA step on "
+                         "the headline form (0 to skip)")
     ap.add_argument("--no-lrdm-step", action="store_true",
                     help="skip timing the low-rank step around the path")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -229,6 +232,29 @@ def main():
             log(f"form {form}: LRDM step {ms_lr:.1f} ms, rank {info['rank']}, "
                 f"s_rel {info['s_rel']:.3f}, ||R|| {info['norm_R']:.3f}")
             del Ub, Tb, db, Rres, rho_in
+        # the model SCF around the path (Sec. II A-B) with the LRDM and the LRDMA
+        # step, from the uniform density, on the headline form's warm block
+        scf = None
+        head_form = next(f for f in ("bf16x3", "fp32", "fp64") if f in forms)
+        if form == head_form and args.scf_steps > 0:
+            scf = {}
+            for name, driver in (("lrdm", L.lrdm_scf), ("lrdma", L.lrdma_scf)):
+                X0 = Yf.clone()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, _, slog, _ = driver(grid, V, X0, occ, c, prec=form, tol=1e-6,
+                                       max_iter=args.scf_steps, first_passes=1)
+                torch.cuda.synchronize()
+                dt_s = time.perf_counter() - t0
+                dirs = sum(x["added"] if name == "lrdma" else x["rank"] for x in slog)
+                scf[name] = dict(steps=len(slog), seconds=round(dt_s, 3), directions=dirs,
+                                 norm_R=[round(x["norm_R"], 6) for x in slog],
+                                 ranks=[x["rank"] for x in slog])
+                if name == "lrdma":
+                    scf[name]["events"] = [x["event"] for x in slog]
+                log(f"model SCF ({name}, {form}): {len(slog)} steps in {dt_s:.2f}s, "
+                    f"{dirs} directions, ||R|| {slog[0]['norm_R']:.3e} -> {slog[-1]['norm_R']:.3e}")
+                del X0
         # the paper's recursive Fermi expansion against the exact divided
         # differences (Eqs. (23)-(24)), on the FP64 form so that the expansion error
         # is not hidden by storage rounding: relative error of delta rho = t + u
@@ -252,7 +278,7 @@ def main():
                 + ", ".join(f"T={k} {v:.2e}" for k, v in expansion.items()))
             del t_exact, t_rec
         results[form] = dict(ms_per_step=ms_step, value=r * args.steps / elapsed, kernels=kern,
-                             lrdm_step=lrdm, fermi_expansion=expansion,
+                             lrdm_step=lrdm, fermi_expansion=expansion, model_scf=scf,
                              rel_err_vs_fp64=rel, rel_err_end_to_end=rel_e2e,
                              ms_response=ms_resp, response_value=1e3 * r / ms_resp)
         log(f"form {form}: {ms_step:.1f} ms/step, {r * args.steps / elapsed:.2f} directions/s; "
@@ -345,6 +371,7 @@ def main():
                       "kernel_ms": {k: round(x[0] / max(x[1], 1), 4) for k, x in v["kernels"].items() if x[1]}}
                   for f, v in results.items()},
         "fermi_expansion_rel_err": results.get("fp64", {}).get("fermi_expansion"),
+        "model_scf": results[head].get("model_scf"),
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
