@@ -271,18 +271,103 @@ def hartree_kernel(u: np.ndarray, grid: Grid) -> np.ndarray:
 
 
 def residual_derivative(Psi: np.ndarray, eps: np.ndarray, grid: Grid, n_electrons: float,
-                        kT: float, u: np.ndarray, nspin: int = 1):
-    """t_k = d/dlam R[rho + lam u_k] = chi0 K u_k - u_k (Eqs. (3), (7)) with K = K_c:
-    the Hartree potential couples to the total density, so every channel sees
-    dV = K_c (sum_sigma u_sigma).  u, t: [r][nspin][nz][ny][nx]."""
+                        kT: float, u: np.ndarray, nspin: int = 1, fxc=None):
+    """t_k = d/dlam R[rho + lam u_k] = chi0 K u_k - u_k (Eqs. (3), (7)).  K = K_c by
+    default: the Hartree potential couples to the total density, so every channel
+    sees dV = K_c (sum_sigma u_sigma).  With fxc [nspin][nspin][nz][ny][nx] (the
+    LDA kernel, lda_xc) K = K_c + K_xc, and channel c also sees the local term
+    sum_c' fxc[c][c'] u_c'.  u, t: [r][nspin][nz][ny][nx]."""
     u = u.reshape((-1, nspin) + grid.shape)
     dV = np.empty_like(u)
     for k in range(u.shape[0]):
         vh = hartree_kernel(u[k].sum(axis=0), grid)
         for c in range(nspin):
             dV[k, c] = vh
+            if fxc is not None:
+                dV[k, c] = dV[k, c] + sum(fxc[c][d] * u[k, d] for d in range(nspin))
     drho, mu, dmu = density_response(Psi, eps, grid, n_electrons, kT, dV, nspin)
     return drho - u, mu, dmu
+
+
+# ---------------------------------------------------------------------------
+# LDA exchange-correlation (the K_xc part of K in Eq. (3), Sec. II D for spin)
+# ---------------------------------------------------------------------------
+# Perdew-Zunger (1981) fit of the Ceperley-Alder correlation energy per electron,
+# eps_c(rs) = gamma / (1 + beta1 sqrt(rs) + beta2 rs) for rs >= 1 and
+# A ln rs + B + C rs ln rs + D rs for rs < 1, unpolarised (U) and fully
+# polarised (P) gas, interpolated in the spin polarisation zeta with the
+# von Barth-Hedin function f(zeta).
+PZ81 = {
+    "U": dict(gamma=-0.1423, beta1=1.0529, beta2=0.3334, A=0.0311, B=-0.048, C=0.0020, D=-0.0116),
+    "P": dict(gamma=-0.0843, beta1=1.3981, beta2=0.2611, A=0.01555, B=-0.0269, C=0.0007,
+              D=-0.0048),
+}
+XC_RHO_MIN = 1e-12      # points where a channel density is below this carry no xc term
+
+
+def pz81_eps_c(rs, kind):
+    """eps_c(rs) of the Perdew-Zunger fit for the unpolarised ("U") or fully
+    polarised ("P") gas; works on numpy arrays and torch tensors."""
+    c = PZ81[kind]
+    lib = torch_or_numpy(rs)
+    low = c["gamma"] / (1.0 + c["beta1"] * lib.sqrt(rs) + c["beta2"] * rs)
+    lnrs = lib.log(rs)
+    high = c["A"] * lnrs + c["B"] + c["C"] * rs * lnrs + c["D"] * rs
+    return lib.where(rs >= 1.0, low, high)
+
+
+def torch_or_numpy(x):
+    import torch
+    return torch if isinstance(x, torch.Tensor) else np
+
+
+def lda_energy_density(rho):
+    """LDA exchange-correlation energy per volume e_xc at each point.
+    rho: [nspin][...] with nspin = 1 (total density) or 2 (spin densities).
+    Exchange: Slater, -(3/4)(3/pi)^{1/3} rho^{4/3} for the total density, or the
+    spin-scaled sum -(3/4)(6/pi)^{1/3} sum_sigma rho_sigma^{4/3}.
+    Correlation: rho eps_c(rs, zeta) with rs = (3/(4 pi rho))^{1/3},
+    eps_c = eps_c^U + f(zeta)(eps_c^P - eps_c^U),
+    f(zeta) = ((1+zeta)^{4/3} + (1-zeta)^{4/3} - 2) / (2^{4/3} - 2).
+    Works on numpy arrays and torch tensors (for the derivatives)."""
+    lib = torch_or_numpy(rho)
+    nspin = rho.shape[0]
+    n = rho.sum(axis=0) if lib is np else rho.sum(dim=0)
+    rs = (3.0 / (4.0 * np.pi * n)) ** (1.0 / 3.0)
+    if nspin == 1:
+        ex = -0.75 * (3.0 / np.pi) ** (1.0 / 3.0) * n ** (4.0 / 3.0)
+        ec = n * pz81_eps_c(rs, "U")
+    else:
+        ex = -0.75 * (6.0 / np.pi) ** (1.0 / 3.0) * (rho[0] ** (4.0 / 3.0) + rho[1] ** (4.0 / 3.0))
+        zeta = (rho[0] - rho[1]) / n
+        fz = ((1 + zeta) ** (4.0 / 3.0) + (1 - zeta) ** (4.0 / 3.0) - 2.0) / (2 ** (4.0 / 3.0) - 2.0)
+        eu, ep = pz81_eps_c(rs, "U"), pz81_eps_c(rs, "P")
+        ec = n * (eu + fz * (ep - eu))
+    return ex + ec
+
+
+def lda_xc(rho: np.ndarray):
+    """Potential and kernel of the LDA: V_sigma = d e_xc / d rho_sigma and
+    f_{sigma sigma'} = d^2 e_xc / d rho_sigma d rho_sigma' at every point, by
+    double-precision automatic differentiation (torch, CPU) of
+    lda_energy_density.  Points where any channel density is below XC_RHO_MIN
+    get zero.  rho: [nspin][...].  Returns (V [nspin][...],
+    f [nspin][nspin][...])."""
+    import torch
+    r = torch.tensor(np.asarray(rho, dtype=np.float64), requires_grad=True)
+    nspin = r.shape[0]
+    live = torch.all(r.detach() >= XC_RHO_MIN, dim=0)
+    safe = torch.where(live, r, torch.ones_like(r))          # keeps the derivatives finite
+    e = lda_energy_density(safe)
+    (V,) = torch.autograd.grad(e.sum(), r, create_graph=True)
+    f = torch.empty((nspin,) + tuple(r.shape), dtype=torch.float64)
+    for a in range(nspin):
+        (row,) = torch.autograd.grad(V[a].sum(), r, retain_graph=True)
+        f[a] = row
+    zero = torch.zeros((), dtype=torch.float64)
+    V = torch.where(live, V, zero)
+    f = torch.where(live, f, zero)
+    return V.detach().numpy(), f.detach().numpy()
 
 
 # ---------------------------------------------------------------------------
@@ -395,11 +480,16 @@ def damping(norm_R: float, far: float = 0.1, near: float = 0.5, switch: float = 
     return far if norm_R >= switch else near
 
 
-def effective_potential(V_ext: np.ndarray, rho: np.ndarray, grid: Grid) -> np.ndarray:
+def effective_potential(V_ext: np.ndarray, rho: np.ndarray, grid: Grid, xc: bool = False):
     """V_eff[rho] = V_ext + V_H[rho] (Eq. (1)) with V_H = K_c applied to the total
-    density (no exchange-correlation term: the kernel is K = K_c, as in the
-    response).  rho: [nspin][nz][ny][nx] or [nz][ny][nx]."""
-    return V_ext + hartree_kernel(rho.reshape((-1,) + grid.shape).sum(axis=0), grid)
+    density; with xc also + V_xc,sigma of the LDA (lda_xc), one potential per
+    channel.  rho: [nspin][nz][ny][nx] or [nz][ny][nx].  Returns [nz][ny][nx]
+    without xc, [nspin][nz][ny][nx] with it."""
+    rho = rho.reshape((-1,) + grid.shape)
+    v = V_ext + hartree_kernel(rho.sum(axis=0), grid)
+    if not xc:
+        return v
+    return v[None] + lda_xc(rho)[0]
 
 
 def lowest_states(V: np.ndarray, grid: Grid, N: int):
@@ -412,36 +502,42 @@ def lowest_states(V: np.ndarray, grid: Grid, N: int):
 
 
 def scf_residual(rho: np.ndarray, V_ext: np.ndarray, grid: Grid, N: int, n_electrons: float,
-                 kT: float, nspin: int = 1):
-    """R[rho] = F[V_eff[rho]] - rho (Sec. II A): the output density of the N lowest
-    states of H[V_eff[rho]] minus the input.  Without an exchange-correlation
-    term both channels of a spin-polarised pair see the same potential.
-    Returns (R [nspin][nz][ny][nx], Psi [nspin][N][...], eps [nspin][N])."""
+                 kT: float, nspin: int = 1, xc: bool = False):
+    """R[rho] = F[V_eff[rho]] - rho (Sec. II A, Sec. II D for two channels): the
+    output density of the N lowest states of H[V_eff[rho]] in each channel minus
+    the input.  Without the exchange-correlation term both channels see the same
+    potential.  Returns (R [nspin][nz][ny][nx], Psi [nspin][N][...], eps [nspin][N])."""
     rho = rho.reshape((nspin,) + grid.shape)
-    eps, Psi = lowest_states(effective_potential(V_ext, rho, grid), grid, N)
-    Psi = np.stack([Psi] * nspin)
-    eps = np.stack([eps] * nspin)
+    V = effective_potential(V_ext, rho, grid, xc)
+    if not xc:
+        V = np.stack([V] * nspin)
+    states = [lowest_states(V[c], grid, N) for c in range(nspin)]
+    eps = np.stack([e for e, _ in states])
+    Psi = np.stack([p for _, p in states])
     rho_out, _ = density(Psi, eps, grid, n_electrons, kT, nspin)
     return rho_out - rho, Psi, eps
 
 
 def lrdm_scf(rho0: np.ndarray, V_ext: np.ndarray, grid: Grid, N: int, n_electrons: float,
              kT: float, nspin: int = 1, s_tol: float = 0.3, r_max: int = 20,
-             tol: float = 1e-9, max_iter: int = 50):
+             tol: float = 1e-9, max_iter: int = 50, xc: bool = False):
     """SCF by the damped quasi-Newton step rho <- rho - alpha P^lr_r R (Eq. (4),
     Sec. II B) with the directional derivatives of Eq. (7) from the subspace
-    density response.  Returns (rho, [(||R||, rank, s_rel, alpha) per step])."""
+    density response (K = K_c, plus the LDA kernel at rho with xc).  Returns (rho,
+    [(||R||, rank, s_rel, alpha) per step])."""
     rho = rho0.reshape((nspin,) + grid.shape).copy()
     log = []
     for _ in range(max_iter):
-        R, Psi, eps = scf_residual(rho, V_ext, grid, N, n_electrons, kT, nspin)
+        R, Psi, eps = scf_residual(rho, V_ext, grid, N, n_electrons, kT, nspin, xc)
         nR = np.sqrt(inner(R, R, grid))
         if nR < tol:
             log.append((nR, 0, 0.0, 0.0))
             break
+        fxc = lda_xc(rho)[1] if xc else None
 
         def apply_t(u):
-            return residual_derivative(Psi, eps, grid, n_electrons, kT, u[None], nspin)[0][0]
+            return residual_derivative(Psi, eps, grid, n_electrons, kT, u[None], nspin,
+                                       fxc)[0][0]
 
         drho, U, _, hist = lowrank_preconditioner(R, apply_t, grid, s_tol, r_max)
         alpha = damping(nR)
@@ -453,7 +549,7 @@ def lrdm_scf(rho0: np.ndarray, V_ext: np.ndarray, grid: Grid, N: int, n_electron
 def lrdma_scf(rho0: np.ndarray, V_ext: np.ndarray, grid: Grid, N: int, n_electrons: float,
               kT: float, nspin: int = 1, s_tol: float = 0.3, beta_tol: float = 0.1,
               r_iter_max: int = 5, r_switch: float = 1.0, r_max: int = 20, tol: float = 1e-9,
-              max_iter: int = 50):
+              max_iter: int = 50, xc: bool = False):
     """SCF with the accumulated low-rank step (LRDMA, Sec. II B 1).
 
     At each step, with R = R[rho]:
@@ -474,14 +570,16 @@ def lrdma_scf(rho0: np.ndarray, V_ext: np.ndarray, grid: Grid, N: int, n_electro
     clear_next = False
     log = []
     for _ in range(max_iter):
-        R, Psi, eps = scf_residual(rho, V_ext, grid, N, n_electrons, kT, nspin)
+        R, Psi, eps = scf_residual(rho, V_ext, grid, N, n_electrons, kT, nspin, xc)
         nR = np.sqrt(inner(R, R, grid))
         if nR < tol:
             log.append((nR, len(U), 0, "done", 0.0, 0.0, None))
             break
+        fxc = lda_xc(rho)[1] if xc else None
 
         def apply_t(u):
-            return residual_derivative(Psi, eps, grid, n_electrons, kT, u[None], nspin)[0][0]
+            return residual_derivative(Psi, eps, grid, n_electrons, kT, u[None], nspin,
+                                       fxc)[0][0]
 
         beta = None if norm_R_lin is None else linearity_indicator(norm_R_lin, nR)
         event = "fresh"

@@ -728,3 +728,86 @@ def lrdma_vs_lrdm(n=(8, 8, 8), L=(9.0, 9.0, 9.0), N=60, ne=16.0, kT=0.02, seed=5
     rho_l, log_l = O.lrdm_scf(rho0, V, g, N, ne, kT, 1, tol=1e-9, max_iter=80)
     return (float(np.abs(rho_a - rho_l).max()), sum(x[2] for x in log_a),
             sum(x[1] for x in log_l), [x[3] for x in log_a], log_a[-1][0])
+
+
+# ------------------------------------------------------------------ LDA exchange-correlation
+def pin_pz81_continuity():
+    """The Perdew-Zunger fit joins its two branches at rs = 1 with a continuous
+    value and slope (that is how its constants were chosen), for the
+    unpolarised and the polarised gas: returns the largest relative jump."""
+    err = 0.0
+    for kind in ("U", "P"):
+        lo = O.pz81_eps_c(np.array([1.0 + 1e-9]), kind)[0]
+        hi = O.pz81_eps_c(np.array([1.0 - 1e-9]), kind)[0]
+        d_lo = (O.pz81_eps_c(np.array([1.0 + 1e-5]), kind)[0] - lo) / (1e-5 - 1e-9)
+        d_hi = (hi - O.pz81_eps_c(np.array([1.0 - 1e-5]), kind)[0]) / (1e-5 - 1e-9)
+        err = max(err, abs(lo - hi) / abs(lo), abs(d_lo - d_hi) / abs(d_lo))
+    return err
+
+
+def pin_lda_exchange_uniform_gas():
+    """The exchange part of the LDA energy per electron is the uniform-gas value
+    -(3/4)(9/(4 pi^2))^{1/3} / rs = -0.458165... / rs (one channel), and the
+    spin-scaled form gives the same at zero polarisation and 2^{1/3} times it
+    when fully polarised."""
+    rs = np.array([0.5, 1.0, 2.0, 5.0])
+    n = 3.0 / (4.0 * np.pi * rs ** 3)
+    ex_ref = -0.75 * (9.0 / (4.0 * np.pi ** 2)) ** (1.0 / 3.0) / rs
+    ex1 = O.lda_energy_density(n[None]) / n - O.pz81_eps_c(rs, "U")
+    ex2 = O.lda_energy_density(np.stack([n / 2, n / 2])) / n - O.pz81_eps_c(rs, "U")
+    # fully polarised: exchange of the channel density at twice the unpolarised value
+    eps_full = O.lda_energy_density(np.stack([n, np.zeros_like(n)])) / n - O.pz81_eps_c(rs, "P")
+    return max(_rel(ex1, ex_ref), _rel(ex2, ex_ref), _rel(eps_full, 2 ** (1 / 3) * ex_ref))
+
+
+def pin_lda_derivatives_fd():
+    """V and f of lda_xc against central differences of the energy density and
+    of V, one and two channels; and the spin identities at zero polarisation:
+    V_up = V of the total density, f_up,up + f_up,down = 2 f of the total."""
+    rng = np.random.default_rng(8)
+    rho1 = rng.uniform(1e-3, 0.5, (1, 7))
+    rho2 = rng.uniform(1e-3, 0.3, (2, 7))
+    err = 0.0
+    for rho in (rho1, rho2):
+        V, f = O.lda_xc(rho)
+        ns = rho.shape[0]
+        for a in range(ns):
+            h = 1e-6 * rho[a]
+            up, dn = rho.copy(), rho.copy()
+            up[a] += h
+            dn[a] -= h
+            dE = (O.lda_energy_density(up) - O.lda_energy_density(dn)) / (2 * h)
+            err = max(err, _rel(V[a], dE))
+            Vu, _ = O.lda_xc(up)
+            Vd, _ = O.lda_xc(dn)
+            for b in range(ns):
+                err = max(err, _rel(f[b][a], (Vu[b] - Vd[b]) / (2 * h)))
+    n = rho1[0]
+    V1, f1 = O.lda_xc(rho1)
+    V2, f2 = O.lda_xc(np.stack([n / 2, n / 2]))
+    err = max(err, _rel(V2[0], V1[0]), _rel(f2[0][0] + f2[0][1], 2 * f1[0][0]))
+    return err
+
+
+def pin_scf_derivative_fd_xc(nspin=1):
+    """With the LDA term, t = chi0 (K_c + K_xc) u - u equals the Richardson central
+    difference of the dense-diagonalisation SCF residual with V_eff = V_ext + V_H
+    + V_xc (full space, N = M); for two channels at an unequal spin split."""
+    g, V, N, ne, kT, rho = _scf_case(nspin)
+    if nspin == 2:
+        rho = np.stack([1.3 * rho[0], 0.7 * rho[1]])
+    rng = np.random.default_rng(27 + nspin)
+    u = rng.standard_normal((nspin,) + g.shape)
+    u -= u.mean(axis=(1, 2, 3), keepdims=True)
+    u /= np.sqrt(O.inner(u, u, g))
+    _, Psi, eps = O.scf_residual(rho, V, g, N, ne, kT, nspin, xc=True)
+    fxc = O.lda_xc(rho)[1]
+    t = O.residual_derivative(Psi, eps, g, ne, kT, u[None], nspin, fxc)[0][0]
+
+    def central(lam):
+        Rp = O.scf_residual(rho + lam * u, V, g, N, ne, kT, nspin, xc=True)[0]
+        Rm = O.scf_residual(rho - lam * u, V, g, N, ne, kT, nspin, xc=True)[0]
+        return (Rp - Rm) / (2 * lam)
+    lam = 2e-3
+    fd = (4 * central(lam / 2) - central(lam)) / 3
+    return _rel(t, fd)

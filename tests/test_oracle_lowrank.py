@@ -79,3 +79,25 @@ def test_lrdma_reaches_lrdm_fixed_point_with_fewer_directions():
     assert final < 1e-9 and diff < 1e-8
     assert dirs_a < dirs_l
     assert "accumulate" in events and "reuse" in events
+
+
+def test_pz81_branches_join_at_rs_1():
+    assert P.pin_pz81_continuity() < 2e-3
+
+
+def test_lda_exchange_is_the_uniform_gas_value():
+    assert P.pin_lda_exchange_uniform_gas() < 1e-14
+
+
+def test_lda_potential_and_kernel_are_the_derivatives():
+    assert P.pin_lda_derivatives_fd() < 1e-7
+
+
+def test_lda_zero_below_density_threshold():
+    V, f = O.lda_xc(np.array([[1e-13, 0.1], [0.2, 0.1]]))
+    assert (V[:, 0] == 0).all() and (f[:, :, 0] == 0).all() and (V[:, 1] != 0).all()
+
+
+@pytest.mark.parametrize("nspin", [1, 2])
+def test_residual_derivative_with_lda_is_scf_residual_derivative(nspin):
+    assert P.pin_scf_derivative_fd_xc(nspin) < 1e-9

@@ -213,13 +213,28 @@ def m_predicted_residual_sign(mp):
     return lambda: P.pin_linear_prediction() < 1e-12
 
 
+
+def m_pz81_constant(mp):
+    bad = {k: dict(v) for k, v in L.PZ81.items()}
+    bad["U"]["gamma"] = -0.1523
+    mp.setattr(L, "PZ81", bad)
+    return lambda: P.pin_pz81_continuity() < 2e-3
+
+
+def m_residual_derivative_drops_xc(mp):
+    orig = ORIG["residual_derivative"]
+    _patch(mp, "residual_derivative",
+           lambda Psi, eps, grid, ne, kT, u, nspin=1, fxc=None: orig(Psi, eps, grid, ne, kT, u, nspin))
+    return lambda: P.pin_scf_derivative_fd_xc(1) < 1e-9
+
+
 MUTANTS = [m_drop_dmu, m_flip_F, m_shift_F_index, m_spin_factor, m_laplacian_half,
            m_cheb_sigma_sign, m_hartree_no_4pi, m_projection_layout, m_density_no_dv,
            m_rr_no_rotation, m_bisection_direction, m_spin_channel_potential,
            m_fermi_omf_subtraction_sign, m_lowrank_gs_sign, m_lowrank_no_S_inverse,
            m_lowrank_first_direction, m_hartree_sign_in_scf,
            m_recursion_drop_denominator_term, m_accumulate_first_direction_not_orthogonalised,
-           m_predicted_residual_sign]
+           m_predicted_residual_sign, m_pz81_constant, m_residual_derivative_drops_xc]
 
 
 @pytest.mark.parametrize("mutant", MUTANTS, ids=[m.__name__ for m in MUTANTS])
