@@ -18,6 +18,8 @@
  *                           variant over kept directions   (Sec. II B, Eqs. (4), (8)-(14))
  *   lrdm_density, lrdm_effective_potential  the model SCF map rho -> R[rho]
  *                           around them                             (Sec. II A, Eq. (1))
+ *   lrdm_lda_xc, lrdm_residual_derivative_xc  the LDA potential and kernel K_xc,
+ *                           and t with K = K_c + K_xc                (Eq. (3), Sec. II D)
  *
  * plus the single steps they are made of (stencil Hamiltonian, occupations and
  * divided differences, projected perturbation, Hartree kernel).
@@ -289,14 +291,35 @@ lrdm_status lrdm_density(lrdm_ctx* ctx, const lrdm_grid* grid, const void* Psi,
                          const double* rho_in, double* out, double* mu);
 
 /* Effective potential of the model SCF: V_eff = V_ext + K_c (sum_c rho_c), the
- * Hartree potential of the total density with the kernel of lrdm_hartree_kernel
- * (Eq. (1) with no exchange-correlation term, consistent with K = K_c in the
- * response).  V_ext, V_eff [M]; rho [nspin][M]; all double; V_eff overlaps
- * neither input.  range (device double [2], may be NULL) receives min and max of
- * V_eff, e.g. for the Chebyshev filter's upper bound. */
+ * Hartree potential of the total density with the kernel of lrdm_hartree_kernel,
+ * plus, when vxc is non-NULL, the exchange-correlation potential of each channel
+ * (Eq. (1); vxc from lrdm_lda_xc).  V_ext [M]; rho, vxc [nspin][M]; V_eff [M]
+ * without vxc, [nspin][M] with it; all double; V_eff overlaps no input.  range
+ * (device double [2], may be NULL) receives min and max of V_eff over all its
+ * channels, e.g. for the Chebyshev filter's upper bound. */
 lrdm_status lrdm_effective_potential(lrdm_ctx* ctx, const lrdm_grid* grid, const double* V_ext,
-                                     const double* rho, int32_t nspin, double* V_eff,
-                                     double* range);
+                                     const double* rho, int32_t nspin, const double* vxc,
+                                     double* V_eff, double* range);
+
+/* Local-density exchange-correlation at every grid point (the K_xc part of K in
+ * Eq. (3), Sec. II D for two channels): with e(rho) the LDA energy per volume,
+ * Slater exchange (spin-scaled for two channels) plus the Perdew-Zunger (1981)
+ * fit of the Ceperley-Alder correlation energy, interpolated between the
+ * unpolarised and the fully polarised gas with the von Barth-Hedin function,
+ *   vxc[s] = de/drho_s,  fxc[s][t] = d^2 e / drho_s drho_t.
+ * nspin 1 takes the total density.  Points where a channel density is below
+ * 1e-12 get vxc = fxc = 0.  rho, vxc [nspin][M], fxc [nspin][nspin][M], double;
+ * vxc or fxc may be NULL; no overlaps. */
+lrdm_status lrdm_lda_xc(lrdm_ctx* ctx, const lrdm_grid* grid, const double* rho, int32_t nspin,
+                        double* vxc, double* fxc);
+
+/* lrdm_residual_derivative with K = K_c + K_xc: channel c of direction k sees
+ * dV_k,c = K_c (sum_s u_k,s) + sum_d fxc[c][d] u_k,d, with fxc [nspin][nspin][M]
+ * the LDA kernel at the current density (lrdm_lda_xc). */
+lrdm_status lrdm_residual_derivative_xc(lrdm_ctx* ctx, const lrdm_grid* grid, const void* Psi,
+                                        const double* eps, int32_t N, const lrdm_occ* occ,
+                                        const double* u, int32_t r, lrdm_prec prec,
+                                        const double* fxc, double* t);
 
 /* Parameters of the low-rank step (Sec. II B).  Values the paper uses:
  * s_tol 0.3, alpha_far 0.1, alpha_near 0.5, r_switch 1.0, and for the
@@ -332,8 +355,10 @@ typedef struct {
  *  - otherwise new directions are added one at a time: the first is R with its
  *    components along the kept u's removed (for r_keep = 0, R/||R||), each later
  *    one the newest t with its components along all u's removed (Eq. (8)), both
- *    normalised; each new t = chi0 K_c u - u is computed as in
- *    lrdm_residual_derivative (Eq. (7)), one direction per launch sequence;
+ *    normalised; each new t = chi0 K u - u is computed as in
+ *    lrdm_residual_derivative (Eq. (7); K = K_c, or K_c + K_xc with fxc
+ *    non-NULL as in lrdm_residual_derivative_xc), one direction per launch
+ *    sequence;
  *  - after each t: S_ij = <t_i, t_j>, c_j = <t_j, R>, y = S^{-1} c (Cholesky on
  *    the GPU) and s_rel = ||sum_j y_j t_j - R|| / ||R|| (Eq. (10)); adding stops
  *    when s_rel < s_tol, at r_add_max new, at r_max in all, or when a new
@@ -352,7 +377,7 @@ typedef struct {
 lrdm_status lrdm_lowrank_step(lrdm_ctx* ctx, const lrdm_grid* grid, const void* Psi,
                               const double* eps, int32_t N, const lrdm_occ* occ, lrdm_prec prec,
                               const double* R, const lrdm_lowrank_params* params, int32_t r_keep,
-                              double* U, double* T, double* drho, double* rho,
+                              const double* fxc, double* U, double* T, double* drho, double* rho,
                               lrdm_lowrank_info* info);
 
 #ifdef __cplusplus

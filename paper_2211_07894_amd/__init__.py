@@ -26,5 +26,6 @@ from .lrdm import (  # noqa: F401
     density,
     effective_potential,
     lowrank_step,
+    lda_xc,
 )
 from .scf import lrdm_scf, lrdma_scf  # noqa: F401,E402

@@ -611,10 +611,12 @@ extern "C" lrdm_status density_response(lrdm_ctx* ctx, const lrdm_grid* grid, co
   });
 }
 
-extern "C" lrdm_status lrdm_residual_derivative(lrdm_ctx* ctx, const lrdm_grid* grid,
-                                                const void* Psi, const double* eps, int32_t N,
-                                                const lrdm_occ* occ, const double* u, int32_t r,
-                                                lrdm_prec prec, double* t) {
+namespace {
+
+lrdm_status residual_derivative_impl(lrdm_ctx* ctx, const lrdm_grid* grid, const void* Psi,
+                                     const double* eps, int32_t N, const lrdm_occ* occ,
+                                     const double* u, int32_t r, lrdm_prec prec,
+                                     const double* fxc, double* t) {
   LRDM_CHECK(ctx, check_grid(grid));
   LRDM_CHECK(ctx, check_block(grid, N));
   LRDM_CHECK(ctx, check_occ(occ, N));
@@ -637,6 +639,10 @@ extern "C" lrdm_status lrdm_residual_derivative(lrdm_ctx* ctx, const lrdm_grid* 
     double* s = static_cast<double*>(ws_take(ctx, scratch));
     hipError_t e = launch_hartree(ctx, g, u, ns, dV, ns, r, s);
     if (e != hipSuccess) return fail_hip(ctx, "hartree", e);
+    if (fxc) {
+      e = launch_xc_apply(ctx, fxc, u, ns, r, g.M, dV);
+      if (e != hipSuccess) return fail_hip(ctx, "xc kernel", e);
+    }
     e = (prec == LRDM_FP64)
         ? run_response<double>(ctx, g, static_cast<const double*>(Psi), eps, N, occ, dV, r, prec,
                                u, t, nullptr, nullptr)
@@ -644,6 +650,24 @@ extern "C" lrdm_status lrdm_residual_derivative(lrdm_ctx* ctx, const lrdm_grid* 
                               t, nullptr, nullptr);
     return e == hipSuccess ? LRDM_OK : fail_hip(ctx, "residual_derivative", e);
   });
+}
+
+}  // namespace
+
+extern "C" lrdm_status lrdm_residual_derivative(lrdm_ctx* ctx, const lrdm_grid* grid,
+                                                const void* Psi, const double* eps, int32_t N,
+                                                const lrdm_occ* occ, const double* u, int32_t r,
+                                                lrdm_prec prec, double* t) {
+  return residual_derivative_impl(ctx, grid, Psi, eps, N, occ, u, r, prec, nullptr, t);
+}
+
+extern "C" lrdm_status lrdm_residual_derivative_xc(lrdm_ctx* ctx, const lrdm_grid* grid,
+                                                   const void* Psi, const double* eps, int32_t N,
+                                                   const lrdm_occ* occ, const double* u,
+                                                   int32_t r, lrdm_prec prec, const double* fxc,
+                                                   double* t) {
+  LRDM_NONNULL(ctx, fxc, "fxc");
+  return residual_derivative_impl(ctx, grid, Psi, eps, N, occ, u, r, prec, fxc, t);
 }
 
 extern "C" lrdm_status density_response_backward(lrdm_ctx* ctx, const lrdm_grid* grid,
@@ -778,7 +802,8 @@ extern "C" lrdm_status lrdm_density(lrdm_ctx* ctx, const lrdm_grid* grid, const 
 
 extern "C" lrdm_status lrdm_effective_potential(lrdm_ctx* ctx, const lrdm_grid* grid,
                                                 const double* V_ext, const double* rho,
-                                                int32_t nspin, double* V_eff, double* range) {
+                                                int32_t nspin, const double* vxc, double* V_eff,
+                                                double* range) {
   LRDM_CHECK(ctx, check_grid(grid));
   if (nspin != 1 && nspin != 2) return fail(ctx, LRDM_EINVAL, "nspin must be 1 or 2");
   LRDM_NONNULL(ctx, V_ext, "V_ext");
@@ -786,17 +811,42 @@ extern "C" lrdm_status lrdm_effective_potential(lrdm_ctx* ctx, const lrdm_grid* 
   LRDM_NONNULL(ctx, V_eff, "V_eff");
   const Grid3 g = make_grid3(grid);
   const size_t vb = (size_t)g.M * sizeof(double);
-  if (overlaps(V_eff, vb, V_ext, vb) || overlaps(V_eff, vb, rho, nspin * vb))
-    return fail(ctx, LRDM_EINVAL, "V_eff must not overlap V_ext or rho");
+  const int nout = vxc ? nspin : 1;
+  if (overlaps(V_eff, nout * vb, V_ext, vb) || overlaps(V_eff, nout * vb, rho, nspin * vb) ||
+      (vxc && overlaps(V_eff, nout * vb, vxc, nspin * vb)))
+    return fail(ctx, LRDM_EINVAL, "V_eff must not overlap V_ext, rho or vxc");
   const size_t scratch = 2 * vb;
   lrdm_status st = begin(ctx, ws_align(scratch) + hartree_workspace_bytes(g));
   if (st != LRDM_OK) return st;
   return guarded(ctx, [&]() -> lrdm_status {
     double* s = static_cast<double*>(ws_take(ctx, scratch));
-    hipError_t e = launch_hartree(ctx, g, rho, nspin, V_eff, 1, 1, s);
-    if (e == hipSuccess) e = launch_axpy(ctx, 1.0, V_ext, g.M, V_eff);
-    if (e == hipSuccess && range) e = launch_minmax(ctx, V_eff, g.M, range);
+    // V_H into every output channel, then + V_ext (and + vxc per channel)
+    hipError_t e = launch_hartree(ctx, g, rho, nspin, V_eff, nout, 1, s);
+    for (int c = 0; e == hipSuccess && c < nout; ++c) {
+      e = launch_axpy(ctx, 1.0, V_ext, g.M, V_eff + (size_t)c * g.M);
+      if (e == hipSuccess && vxc)
+        e = launch_axpy(ctx, 1.0, vxc + (size_t)c * g.M, g.M, V_eff + (size_t)c * g.M);
+    }
+    if (e == hipSuccess && range) e = launch_minmax(ctx, V_eff, (int64_t)nout * g.M, range);
     return e == hipSuccess ? LRDM_OK : fail_hip(ctx, "lrdm_effective_potential", e);
+  });
+}
+
+extern "C" lrdm_status lrdm_lda_xc(lrdm_ctx* ctx, const lrdm_grid* grid, const double* rho,
+                                   int32_t nspin, double* vxc, double* fxc) {
+  LRDM_CHECK(ctx, check_grid(grid));
+  if (nspin != 1 && nspin != 2) return fail(ctx, LRDM_EINVAL, "nspin must be 1 or 2");
+  LRDM_NONNULL(ctx, rho, "rho");
+  const Grid3 g = make_grid3(grid);
+  const size_t rb = (size_t)nspin * g.M * sizeof(double);
+  if ((vxc && overlaps(vxc, rb, rho, rb)) || (fxc && overlaps(fxc, nspin * rb, rho, rb)) ||
+      (vxc && fxc && overlaps(vxc, rb, fxc, nspin * rb)))
+    return fail(ctx, LRDM_EINVAL, "rho, vxc and fxc must not overlap");
+  lrdm_status st = begin(ctx, 0);
+  if (st != LRDM_OK) return st;
+  return guarded(ctx, [&]() -> lrdm_status {
+    hipError_t e = launch_lda_xc(ctx, rho, nspin, g.M, vxc, fxc);
+    return e == hipSuccess ? LRDM_OK : fail_hip(ctx, "lrdm_lda_xc", e);
   });
 }
 
@@ -808,8 +858,9 @@ enum { LR_NR2 = 0, LR_FIT2 = 1, LR_UNEW2 = 2, LR_V2 = 3, LR_RW = 4, LR_SLOTS = 5
 template <typename T>
 lrdm_status run_lowrank(lrdm_ctx* ctx, const Grid3& g, const T* Psi, const double* eps, int N,
                         const lrdm_occ* occ, lrdm_prec prec, const double* R,
-                        const lrdm_lowrank_params* prm, int r_keep, double* U, double* Tm,
-                        double* drho, double* rho, lrdm_lowrank_info* info) {
+                        const lrdm_lowrank_params* prm, int r_keep, const double* fxc,
+                        double* U, double* Tm, double* drho, double* rho,
+                        lrdm_lowrank_info* info) {
   const int ns = occ->nspin;
   const int64_t n = (int64_t)ns * g.M;
   const double dv = g.dv;
@@ -914,6 +965,7 @@ lrdm_status run_lowrank(lrdm_ctx* ctx, const Grid3& g, const T* Psi, const doubl
     double* ti = Tm + (size_t)i * n;
     ctx->ws_top = mark;        // the response's slices are reused by every direction
     LR_HIP("lowrank hartree", launch_hartree(ctx, g, ui, ns, dV, ns, 1, hs));
+    if (fxc) LR_HIP("lowrank xc", launch_xc_apply(ctx, fxc, ui, ns, 1, g.M, dV));
     LR_HIP("lowrank response",
            run_response<T>(ctx, g, Psi, eps, N, occ, dV, 1, prec, ui, ti, nullptr, nullptr));
     LR_HIP("lowrank fit", fit(i));
@@ -953,8 +1005,8 @@ extern "C" lrdm_status lrdm_lowrank_step(lrdm_ctx* ctx, const lrdm_grid* grid, c
                                          const double* eps, int32_t N, const lrdm_occ* occ,
                                          lrdm_prec prec, const double* R,
                                          const lrdm_lowrank_params* params, int32_t r_keep,
-                                         double* U, double* T, double* drho, double* rho,
-                                         lrdm_lowrank_info* info) {
+                                         const double* fxc, double* U, double* T, double* drho,
+                                         double* rho, lrdm_lowrank_info* info) {
   LRDM_CHECK(ctx, check_grid(grid));
   LRDM_CHECK(ctx, check_block(grid, N));
   LRDM_CHECK(ctx, check_occ(occ, N));
@@ -991,8 +1043,8 @@ extern "C" lrdm_status lrdm_lowrank_step(lrdm_ctx* ctx, const lrdm_grid* grid, c
   return guarded(ctx, [&]() -> lrdm_status {
     return (prec == LRDM_FP64)
         ? run_lowrank<double>(ctx, g, static_cast<const double*>(Psi), eps, N, occ, prec, R,
-                              params, r_keep, U, T, drho, rho, info)
+                              params, r_keep, fxc, U, T, drho, rho, info)
         : run_lowrank<float>(ctx, g, static_cast<const float*>(Psi), eps, N, occ, prec, R,
-                             params, r_keep, U, T, drho, rho, info);
+                             params, r_keep, fxc, U, T, drho, rho, info);
   });
 }

@@ -232,6 +232,12 @@ hipError_t launch_normalize(lrdm_ctx* ctx, const double* x, const double* nrm2, 
                             double* y);
 // y += a x.
 hipError_t launch_axpy(lrdm_ctx* ctx, double a, const double* x, int64_t n, double* y);
+// LDA potential vxc [nspin][M] and kernel fxc [nspin][nspin][M] from rho [nspin][M]
+// (xc.hip; either output may be NULL), and dV[k][c] += sum_d fxc[c][d] u[k][d].
+hipError_t launch_lda_xc(lrdm_ctx* ctx, const double* rho, int nspin, int64_t M, double* vxc,
+                         double* fxc);
+hipError_t launch_xc_apply(lrdm_ctx* ctx, const double* fxc, const double* u, int nspin, int r,
+                           int64_t M, double* dV);
 // range[0], range[1] = min and max of x[0..n).
 hipError_t launch_minmax(lrdm_ctx* ctx, const double* x, int64_t n, double* range);
 // y = S^{-1} c for the r x r lower triangle of S (leading dimension ld); *flag = 1

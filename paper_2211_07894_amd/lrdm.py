@@ -31,6 +31,7 @@ EXPORTED = [
     "subspace_rayleigh_ritz", "density_response", "lrdm_residual_derivative",
     "density_response_backward", "density_response_batched",
     "lrdm_density", "lrdm_effective_potential", "lrdm_lowrank_step", "lrdm_set_fermi_expansion",
+    "lrdm_lda_xc", "lrdm_residual_derivative_xc",
 ]
 
 
@@ -135,9 +136,12 @@ def library() -> ctypes.CDLL:
                                               vp, vp, vp],
                 "density_response_batched": [vp, ctypes.POINTER(c_system), i32, ctypes.c_int],
                 "lrdm_density": [vp, G, vp, vp, i32, O, ctypes.c_int, vp, vp, vp],
-                "lrdm_effective_potential": [vp, G, vp, vp, i32, vp, vp],
+                "lrdm_effective_potential": [vp, G, vp, vp, i32, vp, vp, vp],
+                "lrdm_lda_xc": [vp, G, vp, i32, vp, vp],
+                "lrdm_residual_derivative_xc": [vp, G, vp, vp, i32, O, vp, i32, ctypes.c_int, vp,
+                                                vp],
                 "lrdm_lowrank_step": [vp, G, vp, vp, i32, O, ctypes.c_int, vp,
-                                      ctypes.POINTER(c_lowrank_params), i32, vp, vp, vp, vp,
+                                      ctypes.POINTER(c_lowrank_params), i32, vp, vp, vp, vp, vp,
                                       ctypes.POINTER(c_lowrank_info)],
             }
             for name, args in sig.items():
@@ -352,8 +356,10 @@ def density_response(grid: Grid, Psi, eps, occ: Occupation, dV, prec="fp64", out
     return drho, mu, dmu
 
 
-def residual_derivative(grid: Grid, Psi, eps, occ: Occupation, u, prec="fp64", out=None):
-    """t_k = drho[K_c sum_sigma u_k,sigma] - u_k; u, t [r][nspin][M]."""
+def residual_derivative(grid: Grid, Psi, eps, occ: Occupation, u, prec="fp64", out=None,
+                        fxc=None):
+    """t_k = drho[K u_k] - u_k; u, t [r][nspin][M].  K = K_c, or K_c + K_xc with
+    the LDA kernel fxc [nspin][nspin][M] (lda_xc)."""
     ns = occ.nspin
     N = eps.numel() // ns
     r = u.numel() // (ns * grid.M)
@@ -361,11 +367,16 @@ def residual_derivative(grid: Grid, Psi, eps, occ: Occupation, u, prec="fp64", o
     ctx = context(Psi.device.index)
     g = grid.c()
     o = occ.c()
-    ctx.check(ctx.lib.lrdm_residual_derivative(
-        ctx.ptr, ctypes.byref(g), _ptr(Psi, "Psi", _block_dtype(prec), ns * N * grid.M),
-        _ptr(eps, "eps", torch.float64, ns * N), N, ctypes.byref(o),
-        _ptr(u, "u", torch.float64, r * ns * grid.M), r, _prec(prec),
-        _ptr(t, "t", torch.float64, r * ns * grid.M)))
+    args = [ctx.ptr, ctypes.byref(g), _ptr(Psi, "Psi", _block_dtype(prec), ns * N * grid.M),
+            _ptr(eps, "eps", torch.float64, ns * N), N, ctypes.byref(o),
+            _ptr(u, "u", torch.float64, r * ns * grid.M), r, _prec(prec)]
+    if fxc is None:
+        ctx.check(ctx.lib.lrdm_residual_derivative(*args, _ptr(t, "t", torch.float64,
+                                                                r * ns * grid.M)))
+    else:
+        ctx.check(ctx.lib.lrdm_residual_derivative_xc(
+            *args, _ptr(fxc, "fxc", torch.float64, ns * ns * grid.M),
+            _ptr(t, "t", torch.float64, r * ns * grid.M)))
     return t
 
 
@@ -497,27 +508,49 @@ def density(grid: Grid, Psi, eps, occ: Occupation, prec="fp64", rho_in=None, out
     return out, mu
 
 
-def effective_potential(grid: Grid, V_ext, rho, out=None, vrange=None):
-    """V_eff = V_ext + K_c sum_c rho_c; vrange (device double [2], optional)
-    receives its min and max.  Returns V_eff [M]."""
+def effective_potential(grid: Grid, V_ext, rho, out=None, vrange=None, vxc=None):
+    """V_eff = V_ext + K_c sum_c rho_c [M], or with vxc [nspin][M] (lda_xc)
+    V_eff [nspin][M] = that + vxc per channel; vrange (device double [2],
+    optional) receives its min and max."""
     ns = rho.numel() // grid.M
-    out = torch.empty(grid.shape, dtype=torch.float64, device=rho.device) if out is None else out
+    nout = ns if vxc is not None else 1
+    shape = (nout,) + grid.shape if vxc is not None else grid.shape
+    out = torch.empty(shape, dtype=torch.float64, device=rho.device) if out is None else out
     ctx = context(rho.device.index)
     g = grid.c()
     ctx.check(ctx.lib.lrdm_effective_potential(
         ctx.ptr, ctypes.byref(g), _ptr(V_ext, "V_ext", torch.float64, grid.M),
         _ptr(rho, "rho", torch.float64, ns * grid.M), ns,
-        _ptr(out, "V_eff", torch.float64, grid.M), _opt_ptr(vrange, "vrange", torch.float64, 2)))
+        _opt_ptr(vxc, "vxc", torch.float64, ns * grid.M),
+        _ptr(out, "V_eff", torch.float64, nout * grid.M),
+        _opt_ptr(vrange, "vrange", torch.float64, 2)))
     return out
 
 
+def lda_xc(grid: Grid, rho, vxc=None, fxc=None):
+    """LDA potential vxc [nspin][M] and kernel fxc [nspin][nspin][M] at rho
+    [nspin][M] (lrdm_lda_xc)."""
+    ns = rho.numel() // grid.M
+    dev = rho.device
+    vxc = torch.empty((ns,) + grid.shape, dtype=torch.float64, device=dev) if vxc is None else vxc
+    fxc = (torch.empty((ns, ns) + grid.shape, dtype=torch.float64, device=dev)
+           if fxc is None else fxc)
+    ctx = context(dev.index)
+    g = grid.c()
+    ctx.check(ctx.lib.lrdm_lda_xc(ctx.ptr, ctypes.byref(g),
+                                  _ptr(rho, "rho", torch.float64, ns * grid.M), ns,
+                                  _ptr(vxc, "vxc", torch.float64, ns * grid.M),
+                                  _ptr(fxc, "fxc", torch.float64, ns * ns * grid.M)))
+    return vxc, fxc
+
+
 def lowrank_step(grid: Grid, Psi, eps, occ: Occupation, R, params: LowRankParams = LowRankParams(),
-                 prec="fp64", rho=None, U=None, T=None, drho=None, r_keep: int = 0):
+                 prec="fp64", rho=None, U=None, T=None, drho=None, r_keep: int = 0, fxc=None):
     """drho_bar = P^lr_r R with the adaptive rank, and rho -= alpha drho_bar when
     rho is given (lrdm_lowrank_step).  With r_keep > 0 the first r_keep rows of
-    U and T are directions kept from earlier steps (LRDMA).  Returns (drho,
-    U[:rank], T[:rank], info) with info a dict of rank, added, s_rel, norm_R,
-    alpha and norm_R_lin."""
+    U and T are directions kept from earlier steps (LRDMA); fxc [nspin][nspin][M]
+    adds the LDA kernel to K.  Returns (drho, U[:rank], T[:rank], info) with info
+    a dict of rank, added, s_rel, norm_R, alpha and norm_R_lin."""
     ns = occ.nspin
     N = eps.numel() // ns
     n = ns * grid.M
@@ -535,6 +568,7 @@ def lowrank_step(grid: Grid, Psi, eps, occ: Occupation, R, params: LowRankParams
         ctx.ptr, ctypes.byref(g), _ptr(Psi, "Psi", _block_dtype(prec), ns * N * grid.M),
         _ptr(eps, "eps", torch.float64, ns * N), N, ctypes.byref(o), _prec(prec),
         _ptr(R, "R", torch.float64, n), ctypes.byref(p), int(r_keep),
+        _opt_ptr(fxc, "fxc", torch.float64, ns * ns * grid.M),
         _ptr(U, "U", torch.float64, params.r_max * n), _ptr(T, "T", torch.float64, params.r_max * n),
         _ptr(drho, "drho", torch.float64, n), _opt_ptr(rho, "rho", torch.float64, n),
         ctypes.byref(info)))

@@ -1,87 +1,135 @@
-"""Model SCF driven by the LRDM step (Sec. II A-C): rho -> V_eff[rho] ->
-ChFSI (filter + Rayleigh-Ritz) -> R[rho] = F[V_eff[rho]] - rho -> the low-rank
-quasi-Newton update rho <- rho - alpha P^lr_r R.
+"""Model SCF driven by the LRDM step (Sec. II A-D): rho -> V_eff[rho] ->
+ChFSI (filter + Rayleigh-Ritz, per channel) -> R[rho] = F[V_eff[rho]] - rho ->
+the low-rank quasi-Newton update rho <- rho - alpha P^lr_r R.
 
 Every step runs in the library's kernels (lrdm_effective_potential,
-chfsi_filter, subspace_rayleigh_ritz, lrdm_density, lrdm_lowrank_step); this
-module only holds the buffers and reads back the few scalars the loop decides
-on (the potential's range for the filter's upper bound, the extreme Ritz values
-for its other bounds, and the step's ||R||, rank and s_rel).
+lrdm_lda_xc, chfsi_filter, subspace_rayleigh_ritz, lrdm_density,
+lrdm_lowrank_step); this module only holds the buffers and reads back the few
+scalars the loop decides on (the potential's range for the filter's upper
+bound, the extreme Ritz values for its other bounds, and the step's ||R||,
+rank, s_rel and predicted residual).
 """
 from __future__ import annotations
 
 import torch
 
 from .lrdm import (Grid, LowRankParams, Occupation, chfsi_filter, density, effective_potential,
-                   lowrank_step, subspace_rayleigh_ritz)
+                   lda_xc, lowrank_step, subspace_rayleigh_ritz)
+
+
+class _ModelSCF:
+    """Buffers and the eigen-part of one SCF step of the model
+    V_eff = V_ext + V_H[rho] (+ V_xc[rho] of the LDA with xc)."""
+
+    def __init__(self, grid: Grid, V_ext, X, occ: Occupation, degree: int, prec: str, xc: bool,
+                 rho0, r_max: int, first_passes: int):
+        ns = occ.nspin
+        if X.shape[0] != ns:
+            raise ValueError("X must be [nspin][N][nz][ny][nx]")
+        if ns == 2 and not xc:
+            raise ValueError("two channels need the exchange-correlation term to differ")
+        self.grid, self.V_ext, self.occ, self.degree, self.prec, self.xc = (
+            grid, V_ext, occ, degree, prec, xc)
+        self.first_passes = first_passes
+        dev = X.device
+        self.N = X.shape[1]
+        hx, hy, hz = (grid.L[d] / grid.n[d] for d in range(3))
+        self.lap_top = 2.0 / hx ** 2 + 2.0 / hy ** 2 + 2.0 / hz ** 2
+        vol = grid.L[0] * grid.L[1] * grid.L[2]
+        shape = (ns,) + grid.shape
+        f64 = dict(dtype=torch.float64, device=dev)
+        if rho0 is None:
+            self.rho = torch.full(shape, occ.n_electrons / vol / ns, **f64)
+        else:
+            self.rho = rho0.reshape(shape).clone()
+        self.V = torch.empty(shape if xc else grid.shape, **f64)
+        self.vr = torch.empty(2, **f64)
+        self.vxc = torch.empty(shape, **f64) if xc else None
+        self.fxc = torch.empty((ns, ns) + grid.shape, **f64) if xc else None
+        self.R = torch.empty(shape, **f64)
+        self.U = torch.empty((r_max,) + shape, **f64)
+        self.T = torch.empty_like(self.U)
+        self.drho = torch.empty(shape, **f64)
+        self.eps = torch.empty((ns, self.N), **f64)
+        self.X = X
+        self.Y = torch.empty_like(X)
+        self.bounds = [None] * ns
+        self.it = 0
+
+    def residual(self):
+        """V_eff, one ChFSI pass per channel (first_passes on the first step), and
+        R = rho_out - rho into self.R; the LDA kernel at rho into self.fxc."""
+        g, ns = self.grid, self.occ.nspin
+        if self.xc:
+            lda_xc(g, self.rho, vxc=self.vxc, fxc=self.fxc)
+        effective_potential(g, self.V_ext, self.rho, out=self.V, vrange=self.vr, vxc=self.vxc)
+        vmin, vmax = self.vr.tolist()
+        b = self.lap_top + vmax
+        for p in range(self.first_passes if self.it == 0 else 1):
+            deg = 10 if (self.it == 0 and p == 0) else self.degree
+            for c in range(ns):
+                if self.bounds[c] is None:
+                    a0 = vmin - 0.1
+                    self.bounds[c] = (a0 + 0.25 * (b - a0), a0)
+                a, a0 = self.bounds[c]
+                Vc = self.V[c] if self.xc else self.V
+                chfsi_filter(g, Vc, self.X[c], deg, a, b, a0, prec=self.prec, out=self.Y[c])
+                subspace_rayleigh_ritz(g, Vc, self.Y[c], prec=self.prec, eps=self.eps[c])
+                lo, hi = self.eps[c, 0].item(), self.eps[c, -1].item()
+                self.bounds[c] = (hi, lo - 0.1)
+            self.X, self.Y = self.Y, self.X
+        self.it += 1
+        density(g, self.X, self.eps, self.occ, prec=self.prec, rho_in=self.rho, out=self.R)
+
+    def step(self, params: LowRankParams, r_keep: int, r_add_max: int, update: bool):
+        p = LowRankParams(s_tol=params.s_tol, r_max=params.r_max, alpha_far=params.alpha_far,
+                          alpha_near=params.alpha_near, r_switch=params.r_switch,
+                          r_add_max=r_add_max)
+        return lowrank_step(self.grid, self.X, self.eps, self.occ, self.R, p, prec=self.prec,
+                            rho=self.rho if update else None, U=self.U, T=self.T, drho=self.drho,
+                            r_keep=r_keep, fxc=self.fxc)[3]
+
+
+def _block(X, occ):
+    return X if X.dim() == 5 else X.reshape((occ.nspin,) + tuple(X.shape))
 
 
 def lrdm_scf(grid: Grid, V_ext, X, occ: Occupation, degree: int, prec: str = "fp64",
              params: LowRankParams = LowRankParams(), rho0=None, tol: float = 1e-8,
-             max_iter: int = 50, first_passes: int = 4):
-    """Solve R[rho] = 0 for the model V_eff = V_ext + V_H[rho] (one channel).
+             max_iter: int = 50, first_passes: int = 4, xc: bool = False):
+    """Solve R[rho] = 0 for the model V_eff = V_ext + V_H[rho] (+ V_xc[rho], LDA,
+    with xc) by the LRDM step (K = K_c, + K_xc with xc).
 
-    X [N][nz][ny][nx] is the starting block (double for fp64, float otherwise);
-    it and one buffer like it alternate as filter input and output.  Each SCF step applies one
-    Chebyshev filter of the given degree followed by Rayleigh-Ritz (the first
-    step applies first_passes of them, degree 10 for the first), with the
-    filter's bounds b = sum_d 2/h_d^2 + max V_eff (an upper bound of the
-    spectrum), a = the largest and a0 = the smallest Ritz value minus 0.1.
-    rho0 defaults to the uniform density N_e / volume.  Stops once the step
-    reports ||R|| < tol (rho then carries that step's update too).
+    X [N][nz][ny][nx] (one channel) or [nspin][N][nz][ny][nx] is the starting
+    block (double for fp64, float otherwise); it and one buffer like it
+    alternate as filter input and output.  Each SCF step applies, per channel,
+    one Chebyshev filter of the given degree and Rayleigh-Ritz (the first step
+    applies first_passes of them, degree 10 for the first), with the filter's
+    bounds b = sum_d 2/h_d^2 + max V_eff (an upper bound of the spectrum), a =
+    the largest and a0 = the smallest Ritz value minus 0.1.  rho0 defaults to
+    the uniform density, split evenly over the channels.  Two channels need xc
+    (without it they would not differ).  Stops once the step reports
+    ||R|| < tol (rho then carries that step's update too).
 
-    Returns (rho [1][nz][ny][nx], eps [N], log, Psi): log holds one dict per
-    step with norm_R, rank, s_rel and alpha; Psi [N][nz][ny][nx] is the last
-    block of Ritz vectors (one of the two alternating buffers)."""
-    if occ.nspin != 1:
-        raise ValueError("the model SCF has no exchange-correlation term and runs one channel")
-    dev = X.device
-    N = X.shape[0]
-    hx, hy, hz = (grid.L[d] / grid.n[d] for d in range(3))
-    lap_top = 2.0 / hx ** 2 + 2.0 / hy ** 2 + 2.0 / hz ** 2
-    vol = grid.L[0] * grid.L[1] * grid.L[2]
-    shape = (1,) + grid.shape
-    if rho0 is None:
-        rho = torch.full(shape, occ.n_electrons / vol, dtype=torch.float64, device=dev)
-    else:
-        rho = rho0.reshape(shape).clone()
-    V = torch.empty(grid.shape, dtype=torch.float64, device=dev)
-    vr = torch.empty(2, dtype=torch.float64, device=dev)
-    R = torch.empty(shape, dtype=torch.float64, device=dev)
-    U = torch.empty((params.r_max,) + shape, dtype=torch.float64, device=dev)
-    T = torch.empty_like(U)
-    drho = torch.empty(shape, dtype=torch.float64, device=dev)
-    eps = torch.empty(N, dtype=torch.float64, device=dev)
-    Y = torch.empty_like(X)
-    a = a0 = None
+    Returns (rho [nspin][nz][ny][nx], eps [nspin][N], log, Psi): log holds one
+    dict per step with norm_R, rank, s_rel and alpha; Psi [nspin][N][...] is
+    the last block of Ritz vectors (one of the two alternating buffers)."""
+    m = _ModelSCF(grid, V_ext, _block(X, occ), occ, degree, prec, xc, rho0, params.r_max,
+                  first_passes)
     log = []
-    for it in range(max_iter):
-        effective_potential(grid, V_ext, rho, out=V, vrange=vr)
-        vmin, vmax = vr.tolist()
-        b = lap_top + vmax
-        if a is None:
-            a0 = vmin - 0.1
-            a = a0 + 0.25 * (b - a0)
-        passes = first_passes if it == 0 else 1
-        for p in range(passes):
-            chfsi_filter(grid, V, X, 10 if (it == 0 and p == 0) else degree, a, b, a0, prec=prec,
-                         out=Y)
-            subspace_rayleigh_ritz(grid, V, Y, prec=prec, eps=eps)
-            X, Y = Y, X
-            lo, hi = eps[0].item(), eps[-1].item()
-            a, a0 = hi, lo - 0.1
-        density(grid, X, eps, occ, prec=prec, rho_in=rho, out=R)
-        _, _, _, info = lowrank_step(grid, X, eps, occ, R, params, prec=prec, rho=rho, U=U, T=T,
-                                     drho=drho)
+    for _ in range(max_iter):
+        m.residual()
+        info = m.step(params, 0, 0, True)
         log.append(info)
         if info["norm_R"] < tol:
             break
-    return rho, eps, log, X
+    return m.rho, m.eps, log, m.X
 
 
 def lrdma_scf(grid: Grid, V_ext, X, occ: Occupation, degree: int, prec: str = "fp64",
               params: LowRankParams = LowRankParams(), beta_tol: float = 0.1, r_iter_max: int = 5,
-              rho0=None, tol: float = 1e-8, max_iter: int = 50, first_passes: int = 4):
+              rho0=None, tol: float = 1e-8, max_iter: int = 50, first_passes: int = 4,
+              xc: bool = False):
     """The model SCF of lrdm_scf with the accumulated low-rank step (LRDMA,
     Sec. II B 1).  At each SCF step, with R = R[rho]:
       * no kept directions, or a clearing pending (CT): build afresh;
@@ -94,61 +142,23 @@ def lrdma_scf(grid: Grid, V_ext, X, occ: Occupation, degree: int, prec: str = "f
     history (params.r_max kept) is cleared as CT.  R_lin is the residual the
     last step's approximation predicted (Eq. (12)), returned by the step.
 
-    Returns (rho, eps, log, Psi): log holds one dict per step with norm_R, rank
-    (directions in use), added, event, s_rel, alpha and beta."""
-    if occ.nspin != 1:
-        raise ValueError("the model SCF has no exchange-correlation term and runs one channel")
-    dev = X.device
-    N = X.shape[0]
-    hx, hy, hz = (grid.L[d] / grid.n[d] for d in range(3))
-    lap_top = 2.0 / hx ** 2 + 2.0 / hy ** 2 + 2.0 / hz ** 2
-    vol = grid.L[0] * grid.L[1] * grid.L[2]
-    shape = (1,) + grid.shape
-    rho = (torch.full(shape, occ.n_electrons / vol, dtype=torch.float64, device=dev)
-           if rho0 is None else rho0.reshape(shape).clone())
-    V = torch.empty(grid.shape, dtype=torch.float64, device=dev)
-    vr = torch.empty(2, dtype=torch.float64, device=dev)
-    R = torch.empty(shape, dtype=torch.float64, device=dev)
-    U = torch.empty((params.r_max,) + shape, dtype=torch.float64, device=dev)
-    T = torch.empty_like(U)
-    drho = torch.empty(shape, dtype=torch.float64, device=dev)
-    eps = torch.empty(N, dtype=torch.float64, device=dev)
-    Y = torch.empty_like(X)
-    a = a0 = None
+    Returns (rho, eps, log, Psi) as lrdm_scf; each log entry also has added,
+    event and beta."""
+    m = _ModelSCF(grid, V_ext, _block(X, occ), occ, degree, prec, xc, rho0, params.r_max,
+                  first_passes)
     kept = 0
     norm_R_lin = None
     clear_next = False
     log = []
-
-    def step(r_keep, r_add_max, update):
-        p = LowRankParams(s_tol=params.s_tol, r_max=params.r_max, alpha_far=params.alpha_far,
-                          alpha_near=params.alpha_near, r_switch=params.r_switch,
-                          r_add_max=r_add_max)
-        return lowrank_step(grid, X, eps, occ, R, p, prec=prec, rho=rho if update else None,
-                            U=U, T=T, drho=drho, r_keep=r_keep)[3]
-
-    for it in range(max_iter):
-        effective_potential(grid, V_ext, rho, out=V, vrange=vr)
-        vmin, vmax = vr.tolist()
-        b = lap_top + vmax
-        if a is None:
-            a0 = vmin - 0.1
-            a = a0 + 0.25 * (b - a0)
-        for p in range(first_passes if it == 0 else 1):
-            chfsi_filter(grid, V, X, 10 if (it == 0 and p == 0) else degree, a, b, a0, prec=prec,
-                         out=Y)
-            subspace_rayleigh_ritz(grid, V, Y, prec=prec, eps=eps)
-            X, Y = Y, X
-            lo, hi = eps[0].item(), eps[-1].item()
-            a, a0 = hi, lo - 0.1
-        density(grid, X, eps, occ, prec=prec, rho_in=rho, out=R)
+    for _ in range(max_iter):
+        m.residual()
         if kept >= params.r_max:
             clear_next = True
         beta = None
         event = "fresh" if kept == 0 else ("CT" if clear_next else None)
         info = None
         if event is None:
-            probe = step(kept, -1, False)            # the kept directions against this R
+            probe = m.step(params, kept, -1, False)     # the kept directions against this R
             if probe["norm_R"] < tol:
                 log.append(dict(probe, event="done", beta=None, added=0))
                 break
@@ -157,20 +167,20 @@ def lrdma_scf(grid: Grid, V_ext, X, occ: Occupation, degree: int, prec: str = "f
                 event = "CL"
             elif probe["s_rel"] < params.s_tol:
                 event = "reuse"
-                info = step(kept, -1, True)
+                info = m.step(params, kept, -1, True)
             elif probe["norm_R"] > params.r_switch:
                 event = "CR"
             else:
                 event = "accumulate"
-                info = step(kept, min(r_iter_max, params.r_max - kept), True)
+                info = m.step(params, kept, min(r_iter_max, params.r_max - kept), True)
                 kept = info["rank"]
                 clear_next = info["s_rel"] >= params.s_tol
         if info is None:
-            info = step(0, 0, True)
+            info = m.step(params, 0, 0, True)
             kept = info["rank"]
             clear_next = False
         norm_R_lin = info["norm_R_lin"]
         log.append(dict(info, event=event, beta=beta))
         if info["norm_R"] < tol:
             break
-    return rho, eps, log, X
+    return m.rho, m.eps, log, m.X

@@ -309,14 +309,14 @@ void scenario_lowrank(lrdm_ctx* ctx, lrdm_grid g, int N, int nspin, int r_max, l
                 N, nspin, g.n[0], g.n[1], g.n[2]);
   check(lrdm_density(ctx, &g, Psi.data(), eps.data(), N, &occ, prec, rho.data(), R.data(),
                      mu.data()), ctx, name);
-  check(lrdm_effective_potential(ctx, &g, Vext.data(), rho.data(), nspin, Veff.data(),
+  check(lrdm_effective_potential(ctx, &g, Vext.data(), rho.data(), nspin, nullptr, Veff.data(),
                                  range.data()), ctx, "lrdm_effective_potential");
   lrdm_lowrank_params prm{0.0, r_max, 0.1, 0.5, 1.0, 0};
   std::vector<double> U((size_t)r_max * n), T((size_t)r_max * n), drho(n);
   lrdm_lowrank_info info{};
   std::snprintf(name, sizeof name, "lrdm_lowrank_step %s N=%d nspin=%d r_max=%d", prec_name(prec),
                 N, nspin, r_max);
-  check(lrdm_lowrank_step(ctx, &g, Psi.data(), eps.data(), N, &occ, prec, R.data(), &prm, 0,
+  check(lrdm_lowrank_step(ctx, &g, Psi.data(), eps.data(), N, &occ, prec, R.data(), &prm, 0, nullptr,
                           U.data(), T.data(), drho.data(), rho.data(), &info), ctx, name);
   std::printf("     rank %d s_rel %.3e ||R|| %.3e alpha %.2f\n", info.rank, info.s_rel, info.norm_R,
               info.alpha);
@@ -334,7 +334,7 @@ void scenario_lowrank(lrdm_ctx* ctx, lrdm_grid g, int N, int nspin, int r_max, l
     std::vector<double> R2(R);
     for (size_t i = 0; i < n; ++i) R2[i] += 0.01 * std::sin(0.37 * (double)i);
     check(lrdm_lowrank_step(ctx, &g, Psi.data(), eps.data(), N, &occ, prec, R2.data(), &acc,
-                            r_max, U2.data(), T2.data(), drho.data(), nullptr, &info),
+                            r_max, nullptr, U2.data(), T2.data(), drho.data(), nullptr, &info),
           ctx, "lrdm_lowrank_step accumulate");
     std::printf("     accumulated: rank %d added %d s_rel %.3e ||R_lin|| %.3e\n", info.rank,
                 info.added, info.s_rel, info.norm_R_lin);
@@ -344,7 +344,7 @@ void scenario_lowrank(lrdm_ctx* ctx, lrdm_grid g, int N, int nspin, int r_max, l
     }
     acc.r_add_max = -1;
     check(lrdm_lowrank_step(ctx, &g, Psi.data(), eps.data(), N, &occ, prec, R2.data(), &acc,
-                            r_max + 2, U2.data(), T2.data(), drho.data(), nullptr, &info),
+                            r_max + 2, nullptr, U2.data(), T2.data(), drho.data(), nullptr, &info),
           ctx, "lrdm_lowrank_step kept fit only");
     if (info.added != 0 || info.rank != r_max + 2) {
       std::printf("FAIL kept-only step\n");

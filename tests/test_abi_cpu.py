@@ -114,7 +114,7 @@ def test_lowrank_params_validation(lib, field, value, msg):
     o = B.c_occ(1, 0.01, 20.0)
     info = B.c_lowrank_info()
     st = lib.lrdm_lowrank_step(None, ctypes.byref(_grid()), P, P, 32, ctypes.byref(o), 0, P,
-                               ctypes.byref(p), 0, ctypes.c_void_p(0x10000000),
+                               ctypes.byref(p), 0, None, ctypes.c_void_p(0x10000000),
                                ctypes.c_void_p(0x20000000), ctypes.c_void_p(0x30000000), None,
                                ctypes.byref(info))
     assert st == -1 and msg in _err(lib)
@@ -127,7 +127,7 @@ def test_lowrank_buffers_must_not_overlap(lib):
     # U holds 4 vectors of 512 doubles; T starts inside it
     U = 0x10000000
     st = lib.lrdm_lowrank_step(None, ctypes.byref(_grid()), P, P, 32, ctypes.byref(o), 0,
-                               ctypes.c_void_p(0x40000000), ctypes.byref(p), 0, ctypes.c_void_p(U),
+                               ctypes.c_void_p(0x40000000), ctypes.byref(p), 0, None, ctypes.c_void_p(U),
                                ctypes.c_void_p(U + 8 * 512), ctypes.c_void_p(0x30000000), None,
                                ctypes.byref(info))
     assert st == -1 and "must not overlap" in _err(lib)
@@ -137,10 +137,10 @@ def test_density_and_potential_validation(lib):
     o = B.c_occ(1, 0.01, 20.0)
     st = lib.lrdm_density(None, ctypes.byref(_grid()), P, P, 32, ctypes.byref(o), 0, None, None, None)
     assert st == -1 and "out is NULL" in _err(lib)
-    st = lib.lrdm_effective_potential(None, ctypes.byref(_grid()), P, P, 3, P, None)
+    st = lib.lrdm_effective_potential(None, ctypes.byref(_grid()), P, P, 3, None, P, None)
     assert st == -1 and "nspin must be 1 or 2" in _err(lib)
     st = lib.lrdm_effective_potential(None, ctypes.byref(_grid()), P, ctypes.c_void_p(0x2000), 1,
-                                      ctypes.c_void_p(0x2000 + 8), None)
+                                      None, ctypes.c_void_p(0x2000 + 8), None)
     assert st == -1 and "must not overlap" in _err(lib)
 
 
@@ -153,7 +153,19 @@ def test_lowrank_keep_range(lib):
     o = B.c_occ(1, 0.01, 20.0)
     info = B.c_lowrank_info()
     st = lib.lrdm_lowrank_step(None, ctypes.byref(_grid()), P, P, 32, ctypes.byref(o), 0,
-                               ctypes.c_void_p(0x40000000), ctypes.byref(p), 5,
+                               ctypes.c_void_p(0x40000000), ctypes.byref(p), 5, None,
                                ctypes.c_void_p(0x10000000), ctypes.c_void_p(0x20000000),
                                ctypes.c_void_p(0x30000000), None, ctypes.byref(info))
     assert st == -1 and "r_keep must be in 0..r_max" in _err(lib)
+
+
+def test_lda_validation(lib):
+    st = lib.lrdm_lda_xc(None, ctypes.byref(_grid()), P, 3, None, None)
+    assert st == -1 and "nspin must be 1 or 2" in _err(lib)
+    st = lib.lrdm_lda_xc(None, ctypes.byref(_grid()), ctypes.c_void_p(0x2000), 1,
+                         ctypes.c_void_p(0x2000 + 8), None)
+    assert st == -1 and "must not overlap" in _err(lib)
+    o = B.c_occ(1, 0.01, 20.0)
+    st = lib.lrdm_residual_derivative_xc(None, ctypes.byref(_grid()), P, P, 32, ctypes.byref(o), P,
+                                         1, 0, None, P)
+    assert st == -1 and "fxc is NULL" in _err(lib)
