@@ -1062,6 +1062,100 @@ __global__ __launch_bounds__(PT, 1) void backproj_p3_kernel(
 
 }  // namespace
 
+// Rotation, BF16X3: Out[i][p] = sum_j Wt[j][i] B[j][p] over j < N, or j below the
+// end of row block i when `upper` (Wt upper triangular: the blocks past the
+// diagonal block are zero), with both operands pre-split: W3 [3][N][ldk] (FP32
+// rounding of Wt^T, split) and BT3 [3][M][ldk] (B^T split).  One block per
+// (row block of 128, point block of 128); the row blocks of one point block run
+// together on one XCD, where they share the staged tiles of BT3.  FP32 partials
+// over kFlush K-tiles are added into FP64 accumulators; FP32 output.
+__global__ __launch_bounds__(PT, 1) void rotate_p3_kernel(
+    const __bf16* __restrict__ W3, const __bf16* __restrict__ BT3, int N, int64_t M, int ldk,
+    int upper, const float* __restrict__ zeros, float* __restrict__ out) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_pipe[];
+  constexpr int SB = 6 * PB;
+  const int nib = (N + BT - 1) / BT;
+  int pblk, ib;
+  xcd_map(blockIdx.x, (int)((M + BT - 1) / BT), nib, pblk, ib);
+  const int64_t wplane = (int64_t)N * ldk, pplane = M * ldk;
+  const int64_t p0 = (int64_t)pblk * BT;
+  const int i0 = ib * BT;
+  const int kmax = upper ? min(ldk, i0 + BT) : ldk;
+  const int nk = (kmax + KT - 1) / KT;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  auto issue = [&](int t) {
+    unsigned char* st = smem_pipe + (t % NST) * SB;
+    const int64_t j0 = (int64_t)t * KT;
+    const int64_t je = t < nk ? kmax : j0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      dma_piece(W3 + q * wplane, ldk, N, i0, j0, je, zeros, st + q * PB, wid, lane);
+      dma_piece(BT3 + q * pplane, ldk, M, p0, j0, je, zeros, st + (3 + q) * PB, wid, lane);
+    }
+  };
+  double acc[2][4][4];
+  zero_pipe(acc);
+  f4 cc[2][4];
+  zero_f32(cc);
+  issue(0);
+  issue(1);
+  for (int t0 = 0; t0 < nk; t0 += kFlush) {
+    const int t1 = min(nk, t0 + kFlush);
+    for (int t = t0; t < t1; ++t) {
+      wait_stage<6>();
+      const unsigned char* st = smem_pipe + (t % NST) * SB;
+      bf8 pa[2][3], pb[4][3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        bf8 va[2], vb[4];
+        frag_piece<2>(st + q * PB, wr * 32, lane, va);
+        frag_piece<4>(st + (3 + q) * PB, wc * 64, lane, vb);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) pa[i][q] = va[i];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) pb[j][q] = vb[j];
+      }
+      compiler_fence();
+      issue(t + 2);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) cc[i][j] = mfma6(pa[i], pb[j], cc[i][j]);
+    }
+    flush_pipe(cc, 1.0, acc);
+  }
+  wait_stage<0>();
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int gi = i0 + wr * 32 + i * 16 + 4 * (lane >> 4) + v;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t p = p0 + wc * 64 + j * 16 + (lane & 15);
+        if (gi < N && p < M) out[(int64_t)gi * M + p] = (float)acc[i][j][v];
+      }
+    }
+}
+
+// W3[q][i][j] = piece q of (float)Wt[j][i] for j < N, 0 for N <= j < ldk.
+__global__ void wt_split3_kernel(const double* __restrict__ Wt, __bf16* __restrict__ W3, int N,
+                                 int ldk) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per = (int64_t)N * ldk;
+  if (idx >= per) return;
+  const int j = (int)(idx % ldk);
+  const int64_t i = idx / ldk;
+  float x = j < N ? (float)Wt[(int64_t)j * N + i] : 0.f;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const __bf16 h = (__bf16)x;
+    W3[q * per + idx] = h;
+    x -= (float)h;
+  }
+}
+
 static int pad_k(int N) { return (N + KT - 1) / KT * KT; }
 
 size_t backproj_workspace_bytes(int N, int64_t M, int nspin, int batch, lrdm_prec prec) {
@@ -1184,6 +1278,33 @@ hipError_t launch_backproj<float>(lrdm_ctx* ctx, const float* A, const double* G
   ProfScope prof(ctx, "backproj");
   backproj_pipe_kernel<Core::F32><<<grd, PT, smem, ctx->stream>>>(
       A, AT, Gf, N, M, ldk, nspin, batch, scale, sub, ctx->zeros, out);
+  return hipGetLastError();
+}
+
+size_t rotate_bf16x3_bytes(int N, int64_t M) {
+  const int ldk = pad_k(N);
+  return ws_align((size_t)3 * N * ldk * sizeof(__bf16)) +
+         ws_align((size_t)3 * M * ldk * sizeof(__bf16));
+}
+
+hipError_t launch_rotate_bf16x3(lrdm_ctx* ctx, const double* Wt, const float* B, float* Out,
+                                int N, int64_t M, bool upper) {
+  const int ldk = pad_k(N);
+  __bf16* W3 = static_cast<__bf16*>(ws_take(ctx, (size_t)3 * N * ldk * sizeof(__bf16)));
+  __bf16* BT3 = static_cast<__bf16*>(ws_take(ctx, (size_t)3 * M * ldk * sizeof(__bf16)));
+  ProfScope prof(ctx, "nn");
+  const int64_t nW = (int64_t)N * ldk;
+  wt_split3_kernel<<<(unsigned)((nW + 255) / 256), 256, 0, ctx->stream>>>(Wt, W3, N, ldk);
+  LRDM_HIP(hipGetLastError());
+  dim3 gt((unsigned)((M + 63) / 64), (unsigned)(ldk / 64 + (ldk % 64 ? 1 : 0)), 1);
+  transpose_split3_kernel<<<gt, 256, 0, ctx->stream>>>(B, BT3, N, M, ldk);
+  LRDM_HIP(hipGetLastError());
+  const int smem = NST * 6 * PB;
+  LRDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&rotate_p3_kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, smem));
+  const unsigned grd = (unsigned)((M + BT - 1) / BT * ((N + BT - 1) / BT));
+  rotate_p3_kernel<<<grd, PT, smem, ctx->stream>>>(W3, BT3, N, M, ldk, upper ? 1 : 0, ctx->zeros,
+                                                   Out);
   return hipGetLastError();
 }
 

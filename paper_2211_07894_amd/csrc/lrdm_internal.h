@@ -105,6 +105,14 @@ hipError_t launch_fermi(lrdm_ctx* ctx, const double* eps, int N, int nspin, doub
                         double n_electrons, double* mu, double* f, double* omf, double* fprime,
                         double* F);
 
+// Rotation Out = Wt^T B of an FP32 block in the BF16X3 form (both operands split
+// into three BF16 pieces, six products, FP32 partials summed in FP64); `upper`: Wt
+// upper triangular.  Out may be B (B is consumed by the split before the product).
+// Takes rotate_bf16x3_bytes of workspace.
+size_t rotate_bf16x3_bytes(int N, int64_t M);
+hipError_t launch_rotate_bf16x3(lrdm_ctx* ctx, const double* Wt, const float* B, float* Out,
+                                int N, int64_t M, bool upper);
+
 // The recursive expansion's multiplier M [nspin][N][N] and its diagonal [nspin][N]
 // (depth T, mu on the device).
 hipError_t launch_recursive_multiplier(lrdm_ctx* ctx, const double* eps, const double* mu, int N,

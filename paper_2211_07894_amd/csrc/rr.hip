@@ -550,6 +550,7 @@ size_t rr_workspace_bytes(int N, int64_t M, lrdm_prec prec) {
                               ws_align((size_t)(nb / 2) * JS * JS * 8) + ws_align(256) +
                               ws_align((size_t)Np * 4) + ws_align(kFrobBlocks * sizeof(double)));
   inner = std::max(inner, ws_align(tn_workspace_bytes(N, M, 1, prec)));
+  if (prec == LRDM_BF16X3) inner = std::max(inner, rotate_bf16x3_bytes(N, M));
   return b + inner;
 }
 
@@ -590,6 +591,17 @@ lrdm_status rayleigh_ritz(lrdm_ctx* ctx, const Grid3& g, const double* V, T* Psi
   T* B = Psi;
   T* spare = Z;
   CholInfo ci;
+  // Out = Wt^T Bsrc: FP64 matrix cores, or in the BF16X3 form the split-operand
+  // product on BF16 matrix cores (its scratch in the region after `mark`)
+  auto rotate = [&](const T* Bsrc, T* Out, bool upper) -> hipError_t {
+    if constexpr (sizeof(T) == sizeof(float)) {
+      if (prec == LRDM_BF16X3) {
+        ctx->ws_top = mark;
+        return launch_rotate_bf16x3(ctx, Wt, Bsrc, Out, N, M, upper);
+      }
+    }
+    return launch_nn_f64<T>(ctx, Wt, Bsrc, Out, N, M, upper);
+  };
   for (int pass = 0;; ++pass) {
     if (pass > 0) {
       if (pass == kMaxOrthPasses) {
@@ -598,8 +610,7 @@ lrdm_status rayleigh_ritz(lrdm_ctx* ctx, const Grid3& g, const double* V, T* Psi
       }
       transpose_kernel<<<grd, blk, 0, ctx->stream>>>(Tm, N, Wt);
       // with every row independent the factor is lower triangular (no reordering)
-      if ((e = launch_nn_f64<T>(ctx, Wt, B, spare, N, M, ci.live == N)) != hipSuccess)
-        return fail("rotation", e);
+      if ((e = rotate(B, spare, ci.live == N)) != hipSuccess) return fail("rotation", e);
       if (pass > 1 && ci.live < N) {
         fill_rows_kernel<T><<<dim3((unsigned)((M + 255) / 256), N - ci.live), 256, 0,
                               ctx->stream>>>(spare, N, M, ci.live);
@@ -631,8 +642,8 @@ lrdm_status rayleigh_ritz(lrdm_ctx* ctx, const Grid3& g, const double* V, T* Psi
   // Psi_R = Q^T T B: the rotation kernel computes Wt^T B with Wt = T^T Q
   if ((e = small_gemm(ctx, true, false, N, N, N, 1.0, Tm, N, Ug, N, 0.0, Wt, N)) != hipSuccess)
     return fail("gemm", e);
-  if (B != Psi) {
-    if ((e = launch_nn_f64<T>(ctx, Wt, B, Psi, N, M)) != hipSuccess) return fail("rotation", e);
+  if (B != Psi || (sizeof(T) == sizeof(float) && prec == LRDM_BF16X3)) {
+    if ((e = rotate(B, Psi, false)) != hipSuccess) return fail("rotation", e);
     return LRDM_OK;
   }
   T* PR = reinterpret_cast<T*>(HY);

@@ -388,6 +388,8 @@ int main(int argc, char** argv) {
   if (which == "all" || which == "rank") {
     scenario_rr_dependent(ctx, grid(10, 9, 8, 0.45), 150, LRDM_FP64);
     scenario_rr_dependent(ctx, grid(7, 9, 11, 0.5), 70, LRDM_FP32);
+    // BF16X3 rotations (split operands) on the multi-pass route, M = 693 ragged
+    scenario_rr_dependent(ctx, grid(7, 9, 11, 0.5), 70, LRDM_BF16X3);
   }
   if (which == "lprr") {
     scenario_chfsi(ctx, grid(10, 9, 8, 0.45), 150, 5, LRDM_FP32);

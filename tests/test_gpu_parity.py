@@ -220,7 +220,7 @@ def test_rayleigh_ritz_ill_conditioned_block(degree):
     _ritz_checks(Yd, e, V, g, N)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_rayleigh_ritz_dependent_rows(prec):
     """Exact copies, an exact combination, a near copy (1e-13) and a zero row: the
     Ritz vectors are still orthonormal (dependent directions completed by fixed
