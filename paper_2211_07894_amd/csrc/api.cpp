@@ -883,6 +883,20 @@ lrdm_status run_lowrank(lrdm_ctx* ctx, const Grid3& g, const T* Psi, const doubl
   double* w = static_cast<double*>(ws_take(ctx, (size_t)n * sizeof(double)));
   double* dV = static_cast<double*>(ws_take(ctx, (size_t)n * sizeof(double)));
   double* hs = static_cast<double*>(ws_take(ctx, 2 * (size_t)g.M * sizeof(double)));
+  // every direction's response reads the same block: in the BF16X3 form split it
+  // once here (the context hands the pieces to the projection and back-projection)
+  struct PiecesGuard {
+    lrdm_ctx* c;
+    ~PiecesGuard() { c->pieces = lrdm_psi_pieces{}; }
+  } pieces_guard{ctx};
+  if constexpr (sizeof(T) == sizeof(float)) {
+    if (prec == LRDM_BF16X3) {
+      void* p3 = ws_take(ctx, psi_pieces_p3_bytes(N, g.M, ns));
+      void* pt3 = ws_take(ctx, psi_pieces_pt3_bytes(N, g.M, ns));
+      LR_HIP("lowrank split", launch_psi_pieces(ctx, Psi, N, g.M, ns, p3, pt3));
+      ctx->pieces = lrdm_psi_pieces{Psi, N, g.M, ns, p3, pt3};
+    }
+  }
   const size_t mark = ctx->ws_top;
   double h[LR_SLOTS] = {0, 0, 0, 0, 0};
   int hflag = 0;
@@ -1036,7 +1050,9 @@ extern "C" lrdm_status lrdm_lowrank_step(lrdm_ctx* ctx, const lrdm_grid* grid, c
   const int K = kMaxLowRank;
   const size_t small = ws_align((size_t)K * K * 8) + 3 * ws_align(K * 8) + ws_align(LR_SLOTS * 8) +
                        ws_align(sizeof(int)) + dots_workspace_bytes(K);
-  const size_t bytes = small + 2 * ws_align(vb) + ws_align(2 * (size_t)g.M * 8) +
+  const size_t pieces = prec == LRDM_BF16X3
+      ? psi_pieces_p3_bytes(N, g.M, ns) + psi_pieces_pt3_bytes(N, g.M, ns) : 0;
+  const size_t bytes = small + 2 * ws_align(vb) + ws_align(2 * (size_t)g.M * 8) + pieces +
                        hartree_workspace_bytes(g) + response_bytes(N, g.M, 1, ns, prec);
   lrdm_status st = begin(ctx, bytes);
   if (st != LRDM_OK) return st;

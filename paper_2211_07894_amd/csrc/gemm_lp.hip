@@ -1188,13 +1188,21 @@ hipError_t launch_tn_sym<float>(lrdm_ctx* ctx, const float* A, const float* B, c
   const bool pipe = (M % 4 == 0) && a16(A) && a16(B) && (!w || (a16(w) && w_stride % 2 == 0));
   const unsigned grd = (unsigned)(ntiles * ns * batch);
   if (pipe && w && B == A && prec == LRDM_BF16X3 && M % 8 == 0 && nspin <= 2) {
-    // pieces of Psi once per call, then the weighted A side split in the kernel
-    __bf16* P3 = static_cast<__bf16*>(ws_take(ctx, tn_split_bytes(N, M, prec)));
-    const int64_t n = (int64_t)N * M;
-    for (int c = 0; c < nspin; ++c) {
-      split3_kernel<<<(unsigned)((n + 255) / 256), 256, 0, ctx->stream>>>(A + c * n, n,
-                                                                          P3 + c * 3 * n);
-      LRDM_HIP(hipGetLastError());
+    // pieces of Psi once per call (or those the context holds for this block), then
+    // the weighted A side split in the kernel
+    const lrdm_psi_pieces& pc = ctx->pieces;
+    const __bf16* P3 = nullptr;
+    if (pc.psi == A && pc.p3 && pc.N == N && pc.M == M && pc.nspin == nspin) {
+      P3 = static_cast<const __bf16*>(pc.p3);
+    } else {
+      __bf16* P = static_cast<__bf16*>(ws_take(ctx, tn_split_bytes(N, M, prec)));
+      const int64_t n = (int64_t)N * M;
+      for (int c = 0; c < nspin; ++c) {
+        split3_kernel<<<(unsigned)((n + 255) / 256), 256, 0, ctx->stream>>>(A + c * n, n,
+                                                                            P + c * 3 * n);
+        LRDM_HIP(hipGetLastError());
+      }
+      P3 = P;
     }
     const int smem = NST * (TB + 3 * PB + 1024);
     LRDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&tn_sym_p3_kernel),
@@ -1251,12 +1259,20 @@ hipError_t launch_backproj<float>(lrdm_ctx* ctx, const float* A, const double* G
   if (prec == LRDM_BF16X3) {
     const int64_t nG = (int64_t)batch * N * ldk;
     __bf16* G3 = static_cast<__bf16*>(ws_take(ctx, (size_t)nG * 3 * sizeof(__bf16)));
-    __bf16* PT3 = static_cast<__bf16*>(ws_take(ctx, (size_t)nspin * M * ldk * 3 * sizeof(__bf16)));
     gamma_split3_kernel<<<(unsigned)((nG + 255) / 256), 256, 0, ctx->stream>>>(G, G3, N, ldk,
                                                                               batch);
     LRDM_HIP(hipGetLastError());
-    transpose_split3_kernel<<<gt, 256, 0, ctx->stream>>>(A, PT3, N, M, ldk);
-    LRDM_HIP(hipGetLastError());
+    const lrdm_psi_pieces& pc = ctx->pieces;
+    const __bf16* PT3 = nullptr;
+    if (pc.psi == A && pc.pt3 && pc.N == N && pc.M == M && pc.nspin == nspin) {
+      PT3 = static_cast<const __bf16*>(pc.pt3);
+    } else {
+      __bf16* P = static_cast<__bf16*>(
+          ws_take(ctx, (size_t)nspin * M * ldk * 3 * sizeof(__bf16)));
+      transpose_split3_kernel<<<gt, 256, 0, ctx->stream>>>(A, P, N, M, ldk);
+      LRDM_HIP(hipGetLastError());
+      PT3 = P;
+    }
     const int smem = NST * 6 * PB + PW * 64 * (int)sizeof(double);
     LRDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&backproj_p3_kernel),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, smem));
@@ -1305,6 +1321,29 @@ hipError_t launch_rotate_bf16x3(lrdm_ctx* ctx, const double* Wt, const float* B,
   const unsigned grd = (unsigned)((M + BT - 1) / BT * ((N + BT - 1) / BT));
   rotate_p3_kernel<<<grd, PT, smem, ctx->stream>>>(W3, BT3, N, M, ldk, upper ? 1 : 0, ctx->zeros,
                                                    Out);
+  return hipGetLastError();
+}
+
+size_t psi_pieces_p3_bytes(int N, int64_t M, int nspin) {
+  return ws_align((size_t)nspin * 3 * N * M * sizeof(__bf16));
+}
+
+size_t psi_pieces_pt3_bytes(int N, int64_t M, int nspin) {
+  return ws_align((size_t)nspin * 3 * M * pad_k(N) * sizeof(__bf16));
+}
+
+hipError_t launch_psi_pieces(lrdm_ctx* ctx, const float* Psi, int N, int64_t M, int nspin,
+                             void* p3, void* pt3) {
+  const int ldk = pad_k(N);
+  const int64_t n = (int64_t)N * M;
+  __bf16* P3 = static_cast<__bf16*>(p3);
+  for (int c = 0; c < nspin; ++c) {
+    split3_kernel<<<(unsigned)((n + 255) / 256), 256, 0, ctx->stream>>>(Psi + c * n, n,
+                                                                        P3 + c * 3 * n);
+    LRDM_HIP(hipGetLastError());
+  }
+  dim3 gt((unsigned)((M + 63) / 64), (unsigned)(ldk / 64 + (ldk % 64 ? 1 : 0)), nspin);
+  transpose_split3_kernel<<<gt, 256, 0, ctx->stream>>>(Psi, static_cast<__bf16*>(pt3), N, M, ldk);
   return hipGetLastError();
 }
 

@@ -16,6 +16,19 @@ struct lrdm_prof_rec {
   hipEvent_t start, stop;
 };
 
+// Pre-split BF16 pieces of one FP32 block, in use while `psi` is set: the BF16X3
+// projection and back-projection of that block (same N, M, nspin) read them
+// instead of splitting the block again.  Set for the duration of a low-rank step,
+// whose directions all share the block.
+struct lrdm_psi_pieces {
+  const void* psi = nullptr;
+  int N = 0;
+  int64_t M = 0;
+  int nspin = 0;
+  const void* p3 = nullptr;    // [nspin][3][N][M]
+  const void* pt3 = nullptr;   // [nspin][3][M][ldk]
+};
+
 struct lrdm_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -25,6 +38,7 @@ struct lrdm_ctx {
   size_t ws_top = 0;         // bump pointer inside one call
   int checks = 0;
   int fermi_depth = 0;       // 0: exact divided differences; T > 0: recursive expansion
+  lrdm_psi_pieces pieces;
   int* dstatus = nullptr;    // device status words (LRDM_DS_*), then the zero page
   const float* zeros = nullptr;  // 128 bytes of device zeros (source of padding loads)
   std::string err;
@@ -104,6 +118,14 @@ hipError_t launch_hpsi_f64(lrdm_ctx* ctx, const Grid3& g, const double* V, const
 hipError_t launch_fermi(lrdm_ctx* ctx, const double* eps, int N, int nspin, double kT,
                         double n_electrons, double* mu, double* f, double* omf, double* fprime,
                         double* F);
+
+// The pieces of an FP32 block Psi [nspin][N][M] that the BF16X3 projection and
+// back-projection read (see lrdm_psi_pieces), into p3 and pt3 of
+// psi_pieces_bytes in all.
+size_t psi_pieces_p3_bytes(int N, int64_t M, int nspin);
+size_t psi_pieces_pt3_bytes(int N, int64_t M, int nspin);
+hipError_t launch_psi_pieces(lrdm_ctx* ctx, const float* Psi, int N, int64_t M, int nspin,
+                             void* p3, void* pt3);
 
 // Rotation Out = Wt^T B of an FP32 block in the BF16X3 form (both operands split
 // into three BF16 pieces, six products, FP32 partials summed in FP64); `upper`: Wt

@@ -399,6 +399,8 @@ int main(int argc, char** argv) {
     scenario_lowrank(ctx, grid(7, 9, 11, 0.5), 70, 1, 4, LRDM_FP64);
     scenario_lowrank(ctx, grid(9, 8, 7, 0.5), 40, 2, 3, LRDM_FP32);
     scenario_lowrank(ctx, grid(7, 9, 11, 0.5), 70, 1, 3, LRDM_BF16X3);
+    // M a multiple of 8: the projection reads the step's pre-split pieces
+    scenario_lowrank(ctx, grid(8, 8, 6, 0.5), 40, 2, 3, LRDM_BF16X3);
   }
   if (which == "all" || which == "full") scenario_full_n(ctx);
   check(lrdm_destroy(ctx), nullptr, "lrdm_destroy");
