@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--scf-steps", type=int, default=12,
                     help="SCF steps of the model SCF run with the LRDM and the LRDMA step on "
                          "the headline form (0 to skip)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default K-split counts of the projection contractions")
     ap.add_argument("--no-lrdm-step", action="store_true",
                     help="skip timing the low-rank step around the path")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -153,6 +155,9 @@ def main():
         ctx = L.context()
 
         e_resp = torch.empty(N, dtype=torch.float64, device=dev)
+        # K-split counts of the projection contractions for this form's shapes
+        # (response, single direction, Gram), chosen by timing on this device
+        tuned = None if args.no_autotune else L.autotune(grid, N, 1, r, prec=form)
 
         def step():
             L.chfsi_filter(grid, V, Xf, c, *filt, prec=form, out=Yf)
@@ -279,6 +284,7 @@ def main():
             del t_exact, t_rec
         results[form] = dict(ms_per_step=ms_step, value=r * args.steps / elapsed, kernels=kern,
                              lrdm_step=lrdm, fermi_expansion=expansion, model_scf=scf,
+                             autotune=tuned,
                              rel_err_vs_fp64=rel, rel_err_end_to_end=rel_e2e,
                              ms_response=ms_resp, response_value=1e3 * r / ms_resp)
         log(f"form {form}: {ms_step:.1f} ms/step, {r * args.steps / elapsed:.2f} directions/s; "
@@ -368,6 +374,7 @@ def main():
                       "rel_err_vs_fp64": v["rel_err_vs_fp64"],
                       "rel_err_end_to_end": v["rel_err_end_to_end"],
                       "lrdm_step": v["lrdm_step"],
+                      "autotune_splits": (v["autotune"] or {}).get("splits"),
                       "kernel_ms": {k: round(x[0] / max(x[1], 1), 4) for k, x in v["kernels"].items() if x[1]}}
                   for f, v in results.items()},
         "fermi_expansion_rel_err": results.get("fp64", {}).get("fermi_expansion"),

@@ -380,6 +380,23 @@ lrdm_status lrdm_lowrank_step(lrdm_ctx* ctx, const lrdm_grid* grid, const void* 
                               const double* fxc, double* U, double* T, double* drho, double* rho,
                               lrdm_lowrank_info* info);
 
+/* ---------------------------------------------------------------- autotuner */
+
+/* Chooses the K-split count of the projection contraction (the number of point
+ * ranges whose FP64 partial sums are added afterwards) for three shapes at this
+ * grid, N, nspin, r and form: the response's projection of r*nspin directions,
+ * the single-direction projection of lrdm_lowrank_step, and the unweighted Gram
+ * product of subspace_rayleigh_ritz (FP64 arithmetic).  Each is timed (one
+ * warm-up, three timed launches, hipEvents) at the default count and at 1/4, 1/2
+ * and 2 times it (within 1..the workspace's cap), on scratch blocks the call
+ * allocates and frees, and the fastest is kept on this context for later calls of
+ * the same shape.  splits (host int[3], may be NULL) receives the chosen counts;
+ * timings (host double[12], may be NULL) the milliseconds per candidate, 0 where
+ * not tried.  Synchronises.  For the callers that tune once at set-up, not for
+ * those that cannot allocate. */
+lrdm_status lrdm_autotune(lrdm_ctx* ctx, const lrdm_grid* grid, int32_t N, int32_t nspin,
+                          int32_t r, lrdm_prec prec, int32_t* splits, double* timings);
+
 #ifdef __cplusplus
 }
 #endif

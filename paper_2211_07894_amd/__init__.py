@@ -27,5 +27,6 @@ from .lrdm import (  # noqa: F401
     effective_potential,
     lowrank_step,
     lda_xc,
+    autotune,
 )
 from .scf import lrdm_scf, lrdma_scf  # noqa: F401,E402

@@ -1064,3 +1064,117 @@ extern "C" lrdm_status lrdm_lowrank_step(lrdm_ctx* ctx, const lrdm_grid* grid, c
                              params, r_keep, fxc, U, T, drho, rho, info);
   });
 }
+
+// ============================================================ autotuner
+
+namespace {
+
+// Times `launch` (enqueued on ctx's stream) once to warm up and then `reps` times
+// between two events; milliseconds per launch.
+template <typename F>
+hipError_t time_launch(lrdm_ctx* ctx, F&& launch, int reps, double* ms) {
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  if (e == hipSuccess) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(a, ctx->stream);
+  for (int i = 0; e == hipSuccess && i < reps; ++i) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(b, ctx->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(b);
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+  if (a) hipEventDestroy(a);
+  if (b) hipEventDestroy(b);
+  *ms = (double)t / reps;
+  return e;
+}
+
+}  // namespace
+
+extern "C" lrdm_status lrdm_autotune(lrdm_ctx* ctx, const lrdm_grid* grid, int32_t N,
+                                     int32_t nspin, int32_t r, lrdm_prec prec, int32_t* splits,
+                                     double* timings) {
+  LRDM_CHECK(ctx, check_grid(grid));
+  LRDM_CHECK(ctx, check_block(grid, N));
+  LRDM_CHECK(ctx, check_rank(r));
+  LRDM_CHECK(ctx, check_prec(prec));
+  if (nspin != 1 && nspin != 2) return fail(ctx, LRDM_EINVAL, "nspin must be 1 or 2");
+  const Grid3 g = make_grid3(grid);
+  const int batch = r * nspin;
+  const size_t el = prec_bytes(prec);
+  const size_t ws = std::max({tn_workspace_bytes(N, g.M, batch, prec),
+                              tn_workspace_bytes(N, g.M, nspin, prec),
+                              tn_workspace_bytes(N, g.M, 1, LRDM_FP64)});
+  lrdm_status st = begin(ctx, ws);
+  if (st != LRDM_OK) return st;
+  void* A = nullptr;
+  double* w = nullptr;
+  double* H = nullptr;
+  struct Free {
+    void** p[3];
+    ~Free() {
+      for (void** q : p)
+        if (*q) hipFree(*q);
+    }
+  } release{{&A, reinterpret_cast<void**>(&w), reinterpret_cast<void**>(&H)}};
+  if (hipMalloc(&A, (size_t)nspin * N * g.M * el) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&w), (size_t)batch * g.M * sizeof(double)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&H), (size_t)batch * N * N * sizeof(double)) != hipSuccess)
+    return fail(ctx, LRDM_ENOMEM, "lrdm_autotune: scratch allocation failed");
+  return guarded(ctx, [&]() -> lrdm_status {
+    hipError_t e = launch_pattern(ctx, A, (int64_t)nspin * N * g.M, prec == LRDM_FP64);
+    if (e == hipSuccess) e = launch_pattern(ctx, w, (int64_t)batch * g.M, true);
+    if (e != hipSuccess) return fail_hip(ctx, "lrdm_autotune", e);
+    const int ntb = (N + 127) / 128;
+    const int ntiles = ntb * (ntb + 1) / 2;
+    const int arith = prec == LRDM_FP64 ? TN_ARITH_F64
+                                        : (prec == LRDM_FP32 ? TN_ARITH_F32 : TN_ARITH_BF16X3);
+    // three contractions: the response's projection of all directions, the
+    // single-direction projection of the low-rank step, and the Gram matrix of
+    // Rayleigh-Ritz (FP64 arithmetic, unweighted)
+    struct Kind {
+      int b, arith;
+      bool weighted;
+    } kinds[3] = {{batch, arith, true}, {nspin, arith, true}, {1, TN_ARITH_F64, false}};
+    for (int k = 0; k < 3; ++k) {
+      const Kind& kd = kinds[k];
+      const int h = tn_splits(ntiles * kd.b, g.M);
+      const int cap = tn_split_cap(ntiles * kd.b, g.M);
+      const std::array<int64_t, 5> key{N, g.M, kd.b, kd.arith, kd.weighted ? 1 : 0};
+      int best = h;
+      double best_ms = 1e300;
+      const int cand[4] = {h / 4, h / 2, h, 2 * h};
+      for (int c = 0; c < 4; ++c) {
+        const int s = cand[c];
+        if (timings) timings[k * 4 + c] = 0.0;
+        if (s < 1 || s > cap || (c > 0 && s == cand[c - 1])) continue;
+        ctx->tn_tuned[key] = s;
+        auto launch = [&]() -> hipError_t {
+          ctx->ws_top = 0;
+          if (!kd.weighted)
+            return prec == LRDM_FP64
+                ? launch_tn_sym_f64<double, double>(ctx, static_cast<const double*>(A), nullptr,
+                                                    nullptr, 0, N, g.M, 1, 1, H)
+                : launch_tn_sym_f64<float, float>(ctx, static_cast<const float*>(A), nullptr,
+                                                  nullptr, 0, N, g.M, 1, 1, H);
+          return prec == LRDM_FP64
+              ? launch_tn_sym<double>(ctx, static_cast<const double*>(A), nullptr, w, g.M, N,
+                                      g.M, nspin, kd.b, prec, H)
+              : launch_tn_sym<float>(ctx, static_cast<const float*>(A), nullptr, w, g.M, N,
+                                     g.M, nspin, kd.b, prec, H);
+        };
+        double ms = 0.0;
+        e = time_launch(ctx, launch, 3, &ms);
+        if (e != hipSuccess) return fail_hip(ctx, "lrdm_autotune", e);
+        if (timings) timings[k * 4 + c] = ms;
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = s;
+        }
+      }
+      ctx->tn_tuned[key] = best;
+      if (splits) splits[k] = best;
+    }
+    return LRDM_OK;
+  });
+}

@@ -481,8 +481,17 @@ __global__ __launch_bounds__(256, 2) void adj_psi_f64_kernel(
 size_t tn_part_bytes(int N, int64_t M, int batch) {
   const int ntb = (N + BT - 1) / BT;
   const int ntiles = ntb * (ntb + 1) / 2;
-  const int ns = tn_splits(ntiles * batch, M);
+  const int ns = tn_split_cap(ntiles * batch, M);
   return (size_t)batch * ns * ntiles * BT * BT * sizeof(double);
+}
+
+int tn_split_count(const lrdm_ctx* ctx, int N, int64_t M, int batch, int arith, bool weighted) {
+  const int ntb = (N + BT - 1) / BT;
+  const int ntiles = ntb * (ntb + 1) / 2;
+  const auto it = ctx->tn_tuned.find({N, M, batch, arith, weighted ? 1 : 0});
+  if (it != ctx->tn_tuned.end() && it->second >= 1 && it->second <= tn_split_cap(ntiles * batch, M))
+    return it->second;
+  return tn_splits(ntiles * batch, M);
 }
 
 size_t tn_workspace_bytes(int N, int64_t M, int batch, lrdm_prec prec) {
@@ -495,7 +504,7 @@ hipError_t launch_tn_sym_f64(lrdm_ctx* ctx, const SA* A, const SB* B, const doub
                              double* H) {
   const int ntb = (N + BT - 1) / BT;
   const int ntiles = ntb * (ntb + 1) / 2;
-  const int ns = tn_splits(ntiles * batch, M);
+  const int ns = tn_split_count(ctx, N, M, batch, TN_ARITH_F64, w != nullptr);
   int64_t kchunk = (M + ns - 1) / ns;
   kchunk = (kchunk + KT - 1) / KT * KT;
   double* part = static_cast<double*>(ws_take(ctx, tn_part_bytes(N, M, batch)));

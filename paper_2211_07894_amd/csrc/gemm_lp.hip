@@ -1178,7 +1178,8 @@ hipError_t launch_tn_sym<float>(lrdm_ctx* ctx, const float* A, const float* B, c
     return launch_tn_sym_f64<float, float>(ctx, A, B, w, w_stride, N, M, nspin, batch, H);
   const int ntb = (N + BT - 1) / BT;
   const int ntiles = ntb * (ntb + 1) / 2;
-  const int ns = tn_splits(ntiles * batch, M);
+  const int ns = tn_split_count(ctx, N, M, batch,
+                                prec == LRDM_BF16X3 ? TN_ARITH_BF16X3 : TN_ARITH_F32, w != nullptr);
   int64_t kchunk = (M + ns - 1) / ns;
   kchunk = (kchunk + KT - 1) / KT * KT;
   double* part = static_cast<double*>(ws_take(ctx, tn_part_bytes(N, M, batch)));

@@ -193,6 +193,18 @@ __global__ __launch_bounds__(kThreads) void minmax_kernel(const double* __restri
   }
 }
 
+// x[i] = a value in [-1, 1) from an integer hash of i (scratch data for timing).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void pattern_kernel(T* __restrict__ x, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  uint64_t z = (uint64_t)i * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+  z ^= z >> 29;
+  z *= 0xBF58476D1CE4E5B9ull;
+  z ^= z >> 32;
+  x[i] = (T)((double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0);
+}
+
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
 }  // namespace
@@ -252,6 +264,15 @@ hipError_t launch_normalize(lrdm_ctx* ctx, const double* x, const double* nrm2, 
 hipError_t launch_axpy(lrdm_ctx* ctx, double a, const double* x, int64_t n, double* y) {
   if (n <= 0) return hipSuccess;
   axpy_kernel<<<blocks_for(n), kThreads, 0, ctx->stream>>>(a, x, n, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_pattern(lrdm_ctx* ctx, void* x, int64_t n, bool is_double) {
+  if (n <= 0) return hipSuccess;
+  if (is_double)
+    pattern_kernel<double><<<blocks_for(n), kThreads, 0, ctx->stream>>>(static_cast<double*>(x), n);
+  else
+    pattern_kernel<float><<<blocks_for(n), kThreads, 0, ctx->stream>>>(static_cast<float*>(x), n);
   return hipGetLastError();
 }
 

@@ -4,8 +4,10 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cstddef>
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -39,6 +41,9 @@ struct lrdm_ctx {
   int checks = 0;
   int fermi_depth = 0;       // 0: exact divided differences; T > 0: recursive expansion
   lrdm_psi_pieces pieces;
+  // K-split counts of the projection contraction chosen by lrdm_autotune, keyed by
+  // (N, M, batch, arithmetic, weighted)
+  std::map<std::array<int64_t, 5>, int> tn_tuned;
   int* dstatus = nullptr;    // device status words (LRDM_DS_*), then the zero page
   const float* zeros = nullptr;  // 128 bytes of device zeros (source of padding loads)
   std::string err;
@@ -154,6 +159,19 @@ inline int tn_splits(int tiles_x_batch, int64_t M) {
   while (tiles_x_batch * s < 2048 && M / (2 * s) >= 4096) s *= 2;
   return s;
 }
+// The largest split count the partial-sum workspace is sized for: twice the
+// default, as long as each split keeps at least 2048 grid points.
+inline int tn_split_cap(int tiles_x_batch, int64_t M) {
+  const int h = tn_splits(tiles_x_batch, M);
+  int c = 2 * h;
+  while (c > h && M / c < 2048) c /= 2;
+  return c;
+}
+// Arithmetic of a projection contraction, part of the autotuner's key.
+enum { TN_ARITH_F64 = 0, TN_ARITH_F32 = 1, TN_ARITH_BF16X3 = 2 };
+// The split count a projection launch uses: the autotuned one for this shape if
+// lrdm_autotune chose one, else tn_splits.
+int tn_split_count(const lrdm_ctx* ctx, int N, int64_t M, int batch, int arith, bool weighted);
 // T is the storage type of A and B; prec selects the arithmetic (LRDM_FP64: FP64
 // matrix cores on either storage type; LRDM_FP32 / LRDM_BF16X3: FP32 storage only).
 template <typename T>
@@ -268,6 +286,8 @@ hipError_t launch_lda_xc(lrdm_ctx* ctx, const double* rho, int nspin, int64_t M,
                          double* fxc);
 hipError_t launch_xc_apply(lrdm_ctx* ctx, const double* fxc, const double* u, int nspin, int r,
                            int64_t M, double* dV);
+// x[i] = a hashed value in [-1, 1) (scratch contents for timing runs).
+hipError_t launch_pattern(lrdm_ctx* ctx, void* x, int64_t n, bool is_double);
 // range[0], range[1] = min and max of x[0..n).
 hipError_t launch_minmax(lrdm_ctx* ctx, const double* x, int64_t n, double* range);
 // y = S^{-1} c for the r x r lower triangle of S (leading dimension ld); *flag = 1

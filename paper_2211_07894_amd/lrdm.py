@@ -31,7 +31,7 @@ EXPORTED = [
     "subspace_rayleigh_ritz", "density_response", "lrdm_residual_derivative",
     "density_response_backward", "density_response_batched",
     "lrdm_density", "lrdm_effective_potential", "lrdm_lowrank_step", "lrdm_set_fermi_expansion",
-    "lrdm_lda_xc", "lrdm_residual_derivative_xc",
+    "lrdm_lda_xc", "lrdm_residual_derivative_xc", "lrdm_autotune",
 ]
 
 
@@ -138,6 +138,7 @@ def library() -> ctypes.CDLL:
                 "lrdm_density": [vp, G, vp, vp, i32, O, ctypes.c_int, vp, vp, vp],
                 "lrdm_effective_potential": [vp, G, vp, vp, i32, vp, vp, vp],
                 "lrdm_lda_xc": [vp, G, vp, i32, vp, vp],
+                "lrdm_autotune": [vp, G, i32, i32, i32, ctypes.c_int, vp, vp],
                 "lrdm_residual_derivative_xc": [vp, G, vp, vp, i32, O, vp, i32, ctypes.c_int, vp,
                                                 vp],
                 "lrdm_lowrank_step": [vp, G, vp, vp, i32, O, ctypes.c_int, vp,
@@ -576,3 +577,17 @@ def lowrank_step(grid: Grid, Psi, eps, occ: Occupation, R, params: LowRankParams
     return drho, U[:r], T[:r], dict(rank=r, added=int(info.added), s_rel=float(info.s_rel),
                                     norm_R=float(info.norm_R), alpha=float(info.alpha),
                                     norm_R_lin=float(info.norm_R_lin))
+
+
+def autotune(grid: Grid, N: int, nspin: int, r: int, prec="fp64", device=None):
+    """Pick the projection's K-split counts for this shape on the current
+    context (lrdm_autotune).  Returns dict(splits=[response, single direction,
+    Gram], ms=[[4 candidates] x 3], 0 where not tried)."""
+    ctx = context(device)
+    g = grid.c()
+    splits = (ctypes.c_int32 * 3)()
+    ms = (ctypes.c_double * 12)()
+    ctx.check(ctx.lib.lrdm_autotune(ctx.ptr, ctypes.byref(g), int(N), int(nspin), int(r),
+                                    _prec(prec), ctypes.cast(splits, ctypes.c_void_p),
+                                    ctypes.cast(ms, ctypes.c_void_p)))
+    return dict(splits=list(splits), ms=[list(ms[4 * k:4 * k + 4]) for k in range(3)])

@@ -352,6 +352,43 @@ void scenario_lowrank(lrdm_ctx* ctx, lrdm_grid g, int N, int nspin, int r_max, l
     }
   }
 }
+
+// The autotuner: every candidate split count runs the three contractions, and the
+// response keeps its values (to rounding) under the chosen counts.
+void scenario_autotune(lrdm_ctx* ctx, lrdm_grid g, int N, int nspin, int r, lrdm_prec prec) {
+  const int64_t M = (int64_t)g.n[0] * g.n[1] * g.n[2];
+  std::vector<double> Psi0;
+  for (int c = 0; c < nspin; ++c) {
+    auto P = orthonormal(N, M, 31 + c);
+    Psi0.insert(Psi0.end(), P.begin(), P.end());
+  }
+  Block Psi(Psi0, prec);
+  std::vector<double> eps((size_t)nspin * N);
+  for (int c = 0; c < nspin; ++c)
+    for (int i = 0; i < N; ++i) eps[(size_t)c * N + i] = -1.0 + 1.5 * i / N + 0.001 * c;
+  lrdm_occ occ{nspin, 0.02, 0.8 * N};
+  auto dV = randv((size_t)r * nspin * M, 5);
+  std::vector<double> before(dV.size()), after(dV.size());
+  check(density_response(ctx, &g, Psi.data(), eps.data(), N, &occ, dV.data(), r, prec,
+                         before.data(), nullptr, nullptr), ctx, "density_response before tuning");
+  int32_t splits[3];
+  double ms[12];
+  char name[128];
+  std::snprintf(name, sizeof name, "lrdm_autotune %s N=%d nspin=%d r=%d", prec_name(prec), N,
+                nspin, r);
+  check(lrdm_autotune(ctx, &g, N, nspin, r, prec, splits, ms), ctx, name);
+  std::printf("     splits %d %d %d\n", splits[0], splits[1], splits[2]);
+  check(density_response(ctx, &g, Psi.data(), eps.data(), N, &occ, dV.data(), r, prec,
+                         after.data(), nullptr, nullptr), ctx, "density_response after tuning");
+  double num = 0, den = 0;
+  for (size_t i = 0; i < before.size(); ++i) {
+    num += (after[i] - before[i]) * (after[i] - before[i]);
+    den += before[i] * before[i];
+  }
+  const double d = std::sqrt(num / den), tol = prec == LRDM_FP64 ? 1e-13 : 1e-6;
+  std::printf("     response change %.2e (bound %.0e)\n", d, tol);
+  if (!(d < tol)) ++failures;
+}
 }  // namespace
 
 int main(int argc, char** argv) {
@@ -401,6 +438,10 @@ int main(int argc, char** argv) {
     scenario_lowrank(ctx, grid(7, 9, 11, 0.5), 70, 1, 3, LRDM_BF16X3);
     // M a multiple of 8: the projection reads the step's pre-split pieces
     scenario_lowrank(ctx, grid(8, 8, 6, 0.5), 40, 2, 3, LRDM_BF16X3);
+  }
+  if (which == "all" || which == "tune") {
+    scenario_autotune(ctx, grid(20, 18, 13, 0.4), 150, 1, 3, LRDM_FP64);
+    scenario_autotune(ctx, grid(16, 16, 12, 0.4), 130, 2, 2, LRDM_BF16X3);
   }
   if (which == "all" || which == "full") scenario_full_n(ctx);
   check(lrdm_destroy(ctx), nullptr, "lrdm_destroy");

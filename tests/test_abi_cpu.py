@@ -169,3 +169,10 @@ def test_lda_validation(lib):
     st = lib.lrdm_residual_derivative_xc(None, ctypes.byref(_grid()), P, P, 32, ctypes.byref(o), P,
                                          1, 0, None, P)
     assert st == -1 and "fxc is NULL" in _err(lib)
+
+
+def test_autotune_validation(lib):
+    st = lib.lrdm_autotune(None, ctypes.byref(_grid()), 32, 3, 2, 0, None, None)
+    assert st == -1 and "nspin must be 1 or 2" in _err(lib)
+    st = lib.lrdm_autotune(None, ctypes.byref(_grid()), 32, 1, 0, 0, None, None)
+    assert st == -1 and "r (number of directions)" in _err(lib)

@@ -185,3 +185,26 @@ def test_rayleigh_ritz_multitile(form):
     assert np.max(np.abs(e - eps_o)) < 1e-5 * np.max(np.abs(eps_o))
     P = to_host(Yd).reshape(N, -1)
     assert np.max(np.abs(P @ P.T - np.eye(N))) < 1e-5
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32", "bf16x3"])
+def test_autotune_keeps_the_response(c24, form):
+    """The tuned K-split counts change only the order of the partial sums: the
+    response after tuning matches the one before to rounding, and the oracle to
+    the form's bound."""
+    wl, g, V, eps, Psi = c24
+    grid = L.Grid(tuple(g.n), tuple(g.L))
+    occ = L.Occupation(1, wl.kT, wl.n_electrons)
+    dV = grf_directions(wl.system_id, wl.n, wl.L, 4)
+    dt = torch.float64 if form == "fp64" else torch.float32
+    P = to_dev(Psi[None], dt)
+    before, _, _ = L.density_response(grid, P, to_dev(eps[None]), occ, to_dev(dV), prec=form)
+    before = to_host(before)
+    tuned = L.autotune(grid, wl.N, 1, 4, prec=form)
+    print(f"{form}: splits {tuned['splits']}, ms {tuned['ms']}")
+    after, _, _ = L.density_response(grid, P, to_dev(eps[None]), occ, to_dev(dV), prec=form)
+    after = to_host(after)
+    assert rel(after, before) < (1e-13 if form == "fp64" else 1e-7)
+    ref, _, _ = O.density_response(to_host(P), eps[None], g, wl.n_electrons, wl.kT, dV, 1)
+    assert rel(after, ref) < (1e-10 if form == "fp64" else BOUND[form])
+    assert all(s >= 1 for s in tuned["splits"])
