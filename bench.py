@@ -223,17 +223,25 @@ def main():
             db = torch.empty_like(Rres)
             L.lowrank_step(grid, Yf, e_resp, occ, Rres, prm, prec=form, U=Ub, T=Tb, drho=db)
             torch.cuda.synchronize()
+            keys = ["proj", "backproj", "hartree"]
+            ctx.profile(True)
+            for k in keys:
+                ctx.profile_read(k)
             t0 = time.perf_counter()
             for _ in range(args.steps):
                 _, _, _, info = L.lowrank_step(grid, Yf, e_resp, occ, Rres, prm, prec=form, U=Ub,
                                                T=Tb, drho=db)
             torch.cuda.synchronize()
             ms_lr = 1e3 * (time.perf_counter() - t0) / args.steps
+            ctx.profile(False)
+            lr_kern = {k: ctx.profile_read(k) for k in keys}
             lrdm = dict(ms_per_step=round(ms_lr, 3), rank=info["rank"],
                         s_rel=round(info["s_rel"], 4), norm_R=round(info["norm_R"], 4),
                         alpha=info["alpha"],
                         ms_per_direction=round(ms_lr / max(info["rank"], 1), 3),
-                        ms_per_direction_batched=round(ms_resp / r, 3))
+                        ms_per_direction_batched=round(ms_resp / r, 3),
+                        kernel_ms_per_direction={k: round(v[0] / max(v[1], 1), 4)
+                                                 for k, v in lr_kern.items() if v[1]})
             log(f"form {form}: LRDM step {ms_lr:.1f} ms, rank {info['rank']}, "
                 f"s_rel {info['s_rel']:.3f}, ||R|| {info['norm_R']:.3f}")
             del Ub, Tb, db, Rres, rho_in

@@ -442,28 +442,56 @@ hipError_t run_filter(lrdm_ctx* ctx, const Grid3& g, const double* V, const T* X
   return hipSuccess;
 }
 
-// Shared body of density_response and lrdm_residual_derivative.
+// The Fermi-level quantities a response needs: mu, f, 1 - f, the multiplier's
+// diagonal fp (f', or the recursive expansion's) and the multiplier F.
+struct FermiState {
+  double* mu;
+  double* f;
+  double* omf;
+  double* fp;
+  double* F;
+};
+
+// mu by bisection, the occupations and the multiplier (exact divided differences,
+// or with the recursive expansion its multiplier and diagonal in the places of F
+// and f' in Gamma = F o H' - mu' diag(f') and in mu').  mu_out: where mu goes
+// (NULL: into the workspace).
+hipError_t run_fermi(lrdm_ctx* ctx, const double* eps, int N, const lrdm_occ* occ,
+                     double* mu_out, FermiState* st) {
+  const int ns = occ->nspin;
+  const size_t vec = (size_t)ns * N * sizeof(double);
+  st->mu = mu_out ? mu_out : static_cast<double*>(ws_take(ctx, 8));
+  st->f = static_cast<double*>(ws_take(ctx, vec));
+  st->omf = static_cast<double*>(ws_take(ctx, vec));
+  st->fp = static_cast<double*>(ws_take(ctx, vec));
+  st->F = static_cast<double*>(ws_take(ctx, (size_t)ns * N * N * sizeof(double)));
+  const int depth = ctx->fermi_depth;
+  LRDM_HIP(launch_fermi(ctx, eps, N, ns, occ->kT, occ->n_electrons, st->mu, st->f, st->omf,
+                        st->fp, depth > 0 ? nullptr : st->F));
+  if (depth > 0)
+    LRDM_HIP(launch_recursive_multiplier(ctx, eps, st->mu, N, ns, occ->kT, depth, st->F, st->fp));
+  return hipSuccess;
+}
+
+// Shared body of density_response and lrdm_residual_derivative.  fermi: the
+// Fermi quantities of these eps when the caller already has them (NULL: formed
+// here, mu into `mu` when given).
 template <typename T>
 hipError_t run_response(lrdm_ctx* ctx, const Grid3& g, const T* Psi, const double* eps, int N,
                         const lrdm_occ* occ, const double* dV, int r, lrdm_prec prec,
-                        const double* sub, double* out, double* mu, double* dmu) {
+                        const double* sub, double* out, double* mu, double* dmu,
+                        const FermiState* fermi = nullptr) {
   const int ns = occ->nspin;
   const int batch = r * ns;
-  const size_t vec = (size_t)ns * N * sizeof(double);
-  double* mu_d = mu ? mu : static_cast<double*>(ws_take(ctx, 8));
   double* dmu_d = dmu ? dmu : static_cast<double*>(ws_take(ctx, (size_t)r * 8));
-  double* f = static_cast<double*>(ws_take(ctx, vec));
-  double* omf = static_cast<double*>(ws_take(ctx, vec));
-  double* fp = static_cast<double*>(ws_take(ctx, vec));
-  double* F = static_cast<double*>(ws_take(ctx, (size_t)ns * N * N * sizeof(double)));
+  FermiState local;
+  if (!fermi) {
+    LRDM_HIP(run_fermi(ctx, eps, N, occ, mu, &local));
+    fermi = &local;
+  }
+  double* fp = fermi->fp;
+  double* F = fermi->F;
   double* Hp = static_cast<double*>(ws_take(ctx, (size_t)batch * N * N * sizeof(double)));
-  const int depth = ctx->fermi_depth;
-  LRDM_HIP(launch_fermi(ctx, eps, N, ns, occ->kT, occ->n_electrons, mu_d, f, omf, fp,
-                        depth > 0 ? nullptr : F));
-  // with the recursive expansion its multiplier and diagonal take the places of
-  // F and f' in Gamma = F o H' - mu' diag(f') and in mu'
-  if (depth > 0)
-    LRDM_HIP(launch_recursive_multiplier(ctx, eps, mu_d, N, ns, occ->kT, depth, F, fp));
   LRDM_HIP(launch_tn_sym<T>(ctx, Psi, nullptr, dV, g.M, N, g.M, ns, batch, prec, Hp));
   LRDM_HIP(launch_gamma(ctx, Hp, F, fp, N, ns, r, dmu_d));
   const double s = (ns == 1) ? 2.0 : 1.0;
@@ -897,6 +925,9 @@ lrdm_status run_lowrank(lrdm_ctx* ctx, const Grid3& g, const T* Psi, const doubl
       ctx->pieces = lrdm_psi_pieces{Psi, N, g.M, ns, p3, pt3};
     }
   }
+  // the Fermi quantities depend on eps alone: once for every direction
+  FermiState fermi;
+  LR_HIP("lowrank fermi", run_fermi(ctx, eps, N, occ, nullptr, &fermi));
   const size_t mark = ctx->ws_top;
   double h[LR_SLOTS] = {0, 0, 0, 0, 0};
   int hflag = 0;
@@ -981,7 +1012,8 @@ lrdm_status run_lowrank(lrdm_ctx* ctx, const Grid3& g, const T* Psi, const doubl
     LR_HIP("lowrank hartree", launch_hartree(ctx, g, ui, ns, dV, ns, 1, hs));
     if (fxc) LR_HIP("lowrank xc", launch_xc_apply(ctx, fxc, ui, ns, 1, g.M, dV));
     LR_HIP("lowrank response",
-           run_response<T>(ctx, g, Psi, eps, N, occ, dV, 1, prec, ui, ti, nullptr, nullptr));
+           run_response<T>(ctx, g, Psi, eps, N, occ, dV, 1, prec, ui, ti, nullptr, nullptr,
+                           &fermi));
     LR_HIP("lowrank fit", fit(i));
     const int added = i - r_keep + 1;
     const bool more = i + 1 < r_cap && added < add_cap;
