@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--scf-steps", type=int, default=12,
                     help="SCF steps of the model SCF run with the LRDM and the LRDMA step on "
                          "the headline form (0 to skip)")
+    ap.add_argument("--grown", action="store_true",
+                    help="also time the grown forms: 16 uneven batched systems (eager and "
+                         "HIP-graph replay) and the 80^3 / 2048-state forward + adjoint")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default K-split counts of the projection contractions")
     ap.add_argument("--no-lrdm-step", action="store_true",
@@ -352,6 +355,8 @@ def main():
             roofline["executed_frac_of_measured"] = round(ex_rate / roofline["measured_peak"], 4)
         roofline["measured_peaks"] = measured
 
+    grown = grown_forms(torch, L, dev) if args.grown else None
+
     # ---- CPU baseline: the oracle on a bounded sample of the same workload
     cpu = None
     if not args.no_cpu_baseline:
@@ -387,10 +392,93 @@ def main():
                   for f, v in results.items()},
         "fermi_expansion_rel_err": results.get("fp64", {}).get("fermi_expansion"),
         "model_scf": results[head].get("model_scf"),
+        "grown_forms": grown,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def grown_forms(torch, L, dev, reps=5):
+    """Times of the grown forms (FP32 storage):
+    * 16 uneven spin-polarised systems (grids 32^3..56^3, 64-512 states, 4-20
+      directions) in one density_response_batched call, eager and replayed from
+      one captured HIP graph (median of `reps`);
+    * the 80^3 / 2048-state / 20-direction response, forward and adjoint
+      (density_response, density_response_backward with all three gradients).
+    Inputs: per system an orthonormalised seeded Gaussian block (QR on the GPU),
+    sorted seeded energies, dV = K_c(u_up + u_down) of the GRF directions."""
+    import numpy as np
+    from inputs import batched_systems, grf_directions, make_workload
+
+    def ms_of(fn):
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(1e3 * (time.perf_counter() - t0))
+        return float(np.median(ts))
+
+    systems, directions = [], 0
+    for wl in batched_systems(16):
+        grid = L.Grid(tuple(wl.n), tuple(wl.L))
+        blocks = []
+        for c in range(2):
+            X = torch.from_numpy(wl.block(channel=c)).to(dev).reshape(wl.N, wl.M)
+            Q, _ = torch.linalg.qr(X.T)
+            blocks.append(Q.T.contiguous())
+        Psi = torch.stack(blocks).reshape((2, wl.N) + grid.shape).float().contiguous()
+        rng = np.random.default_rng(wl.system_id)
+        eps = np.sort(rng.uniform(-2.0, 0.5, (2, wl.N)), axis=1)
+        eps[1] += 0.01
+        u = torch.from_numpy(grf_directions(wl.system_id, wl.n, wl.L, wl.rank, nspin=2)).to(dev)
+        dV = L.hartree_kernel(grid, (u[:, 0] + u[:, 1]).contiguous())
+        systems.append(dict(grid=grid, Psi=Psi, eps=torch.from_numpy(eps).to(dev),
+                            occ=L.Occupation(2, wl.kT, wl.n_electrons),
+                            dV=torch.stack([dV, dV], dim=1).contiguous()))
+        directions += wl.rank
+    outs = [(torch.empty((si["dV"].shape[0], 2) + si["grid"].shape, dtype=torch.float64,
+                         device=dev),
+             torch.empty(1, dtype=torch.float64, device=dev),
+             torch.empty(si["dV"].shape[0], dtype=torch.float64, device=dev)) for si in systems]
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        L.density_response_batched(systems, prec="fp32", outs=outs)     # sizes the workspace
+        side.synchronize()
+
+        def eager():
+            L.density_response_batched(systems, prec="fp32", outs=outs)
+        eager_ms = ms_of(eager)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=side):
+            L.density_response_batched(systems, prec="fp32", outs=outs)
+        replay_ms = ms_of(graph.replay)
+    del graph
+    log(f"batched 16 systems ({directions} directions x 2 channels): eager {eager_ms:.1f} ms, "
+        f"graph replay {replay_ms:.1f} ms")
+    del systems, outs
+
+    wl = make_workload("c80_n2048")
+    grid, occ = L.Grid(tuple(wl.n), tuple(wl.L)), L.Occupation(1, wl.kT, wl.n_electrons)
+    gen = torch.Generator(device=dev).manual_seed(2211)
+    Psi = torch.randn((wl.N,) + grid.shape, dtype=torch.float32, device=dev, generator=gen)
+    Psi /= torch.linalg.vector_norm(Psi.reshape(wl.N, -1), dim=1).reshape(wl.N, 1, 1, 1)
+    eps = torch.sort(torch.rand(wl.N, dtype=torch.float64, device=dev, generator=gen) * 3 - 2)[0]
+    U = torch.from_numpy(grf_directions(wl.system_id, wl.n, wl.L, wl.rank)).to(dev)
+    dV = L.hartree_kernel(grid, U.reshape((wl.rank,) + grid.shape).contiguous())
+    dV = dV.reshape((wl.rank, 1) + grid.shape).contiguous()
+    G = torch.from_numpy(grf_directions(wl.system_id + 100, wl.n, wl.L, wl.rank)).to(dev)
+    fwd_ms = ms_of(lambda: L.density_response(grid, Psi, eps, occ, dV, prec="fp32"))
+    bwd_ms = ms_of(lambda: L.density_response_backward(grid, Psi, eps, occ, dV, G, prec="fp32"))
+    log(f"80^3 / 2048 states / 20 directions (fp32): forward {fwd_ms:.1f} ms, "
+        f"adjoint {bwd_ms:.1f} ms")
+    return dict(batched=dict(systems=16, directions=directions, eager_ms=round(eager_ms, 3),
+                             graph_replay_ms=round(replay_ms, 3),
+                             directions_per_s=round(1e3 * directions / replay_ms, 2)),
+                adjoint_c80=dict(N=wl.N, M=wl.M, r=wl.rank, forward_ms=round(fwd_ms, 2),
+                                 backward_ms=round(bwd_ms, 2)))
 
 
 def measure_peaks(torch, dev):
