@@ -305,3 +305,45 @@ def test_lrdm_scf_with_lda_reaches_a_fixed_point(nspin, ne, kT):
     assert log[-1]["norm_R"] < 1e-9 and nR < 1e-7
     assert abs(g.dv * rh.sum() - ne) < 1e-9
     assert np.abs(rh - rho_o).max() < 1e-7
+
+
+@pytest.mark.parametrize("prec,nspin", [("fp64", 2), ("bf16x3", 1), ("fp32", 2)])
+def test_lowrank_step_ragged_multitile(prec, nspin):
+    """Ragged sizes: a 20 x 18 x 13 grid (M = 4680, not a multiple of 8) and 150
+    states (two 128-wide tiles, the second ragged), kept directions, and LDA:
+    three directions from scratch, then two more accumulated on them for a
+    changed residual, against the oracle."""
+    g = O.Grid((20, 18, 13), (8.0, 7.2, 5.2))
+    rng = np.random.default_rng(40 + nspin)
+    N, ne, kT = 150, 120.0, 0.02
+    Psi = np.stack([np.linalg.qr(rng.standard_normal((g.M, N)))[0].T.reshape((N,) + g.shape)
+                    for _ in range(nspin)])
+    eps = np.sort(rng.uniform(-1.5, 0.5, (nspin, N)), axis=1)
+    rho = rng.uniform(1e-3, 0.05, (nspin,) + g.shape)
+    fo = O.lda_xc(rho)[1]
+    R0 = 0.3 * rng.standard_normal((nspin,) + g.shape)
+    R1 = R0 + 0.1 * rng.standard_normal((nspin,) + g.shape)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    Psi_d = to_dev(Psi, dt)
+    Ph = to_host(Psi_d)
+
+    def apply_t(u):
+        return O.residual_derivative(Ph, eps, g, ne, kT, u[None], nspin, fo)[0][0]
+    _, U0, T0, _ = O.lowrank_preconditioner(R0, apply_t, g, 0.0, 3)
+    d_o, _, _, s_o, added_o, _ = O.lowrank_accumulate(R1, apply_t, g, 0.0, list(U0), list(T0), 2)
+    grid = _grid(g)
+    occ = L.Occupation(nspin, kT, ne)
+    _, fxc = L.lda_xc(grid, to_dev(rho))
+    U = torch.zeros((6, nspin) + g.shape, dtype=torch.float64, device="cuda")
+    T = torch.zeros_like(U)
+    L.lowrank_step(grid, Psi_d, to_dev(eps), occ, to_dev(R0),
+                   L.LowRankParams(s_tol=0.0, r_max=6, r_add_max=3), prec=prec, U=U, T=T, fxc=fxc)
+    drho, _, _, info = L.lowrank_step(grid, Psi_d, to_dev(eps), occ, to_dev(R1),
+                                      L.LowRankParams(s_tol=0.0, r_max=6, r_add_max=2),
+                                      prec=prec, U=U, T=T, r_keep=3, fxc=fxc)
+    bound = {"fp64": 1e-10, "fp32": 1e-4, "bf16x3": 1e-5}[prec]
+    print(f"{prec} nspin {nspin}: rank {info['rank']} added {info['added']}, drho rel err "
+          f"{rel(to_host(drho), d_o):.2e}")
+    assert info["rank"] == 5 and info["added"] == added_o == 2
+    assert rel(to_host(drho), d_o) < bound
+    assert abs(info["s_rel"] - s_o) < bound
