@@ -347,7 +347,7 @@ __global__ void to_f32_kernel(const double* __restrict__ x, float* __restrict__ 
 // (global_load_lds_dwordx4: lane l of a wave writes 16 bytes at base + 16 l) in a
 // ring of NST stages, so NST - 1 K-tiles are in flight while one is multiplied.
 // A tile row (32 FP32 = eight 16-byte chunks) keeps logical chunk q in slot
-// q ^ (row & 7), which spreads a wave's fragment reads over the LDS banks.
+// q ^ tile_swizzle(row), which spreads a wave's fragment reads over the LDS banks.
 // Chunks outside the operands are fetched from a page of zeros.
 constexpr int PW = 8;                     // waves per block
 constexpr int PT = PW * 64;               // threads per block
@@ -370,6 +370,13 @@ __device__ inline void dma16(const void* src, unsigned char* lds) {
 // This wave's share (2 of 16 copy instructions) of one operand tile: rows
 // [r0, r0+BT) x k in [k0, k0+KT) of the row-major FP32 [nrows][ld] array X.
 // Chunks with a row >= nrows or k >= kend (kend a multiple of 4) read zeros.
+// Slot permutation of the eight 16-byte chunks of an FP32 tile row (128 bytes):
+// chunk q of row r sits in slot q ^ tile_swizzle(r), so 8 consecutive rows reading
+// one chunk fall in distinct 16-byte bank groups.  (A permutation that also
+// separates rows 8 apart removed the remaining bank conflicts of these reads but
+// made the FP32 kernels 2 % slower on the device, so this one stays.)
+__device__ inline int tile_swizzle(int r) { return r & 7; }
+
 __device__ inline void dma_tile(const float* __restrict__ X, int64_t ld, int nrows, int64_t r0,
                                 int64_t k0, int64_t kend, const float* zeros, unsigned char* tile,
                                 int wid, int lane) {
@@ -377,7 +384,7 @@ __device__ inline void dma_tile(const float* __restrict__ X, int64_t ld, int nro
   for (int u = 0; u < 2; ++u) {
     const int ins = wid * 2 + u;                      // 64 chunks = 8 rows each
     const int r = ins * 8 + (lane >> 3);
-    const int q = (lane & 7) ^ ((lane >> 3) & 7);     // logical chunk of slot lane & 7
+    const int q = (lane & 7) ^ tile_swizzle(r);       // logical chunk of slot lane & 7
     const int64_t k = k0 + 4 * q;
     const int64_t gr = r0 + r;
     const float* src = (gr < nrows && k < kend) ? X + gr * ld + k : zeros;
@@ -401,8 +408,9 @@ __device__ inline void frag_sw(const unsigned char* tile, int base, int lane, fl
 #pragma unroll
   for (int i = 0; i < NI; ++i) {
     const int R = base + 16 * i + r16;
-    const f4 x = *reinterpret_cast<const f4*>(tile + (R * 8 + ((2 * g) ^ (R & 7))) * 16);
-    const f4 y = *reinterpret_cast<const f4*>(tile + (R * 8 + ((2 * g + 1) ^ (R & 7))) * 16);
+    const int sw = tile_swizzle(R);
+    const f4 x = *reinterpret_cast<const f4*>(tile + (R * 8 + ((2 * g) ^ sw)) * 16);
+    const f4 y = *reinterpret_cast<const f4*>(tile + (R * 8 + ((2 * g + 1) ^ sw)) * 16);
     v[i][0] = x[0]; v[i][1] = x[1]; v[i][2] = x[2]; v[i][3] = x[3];
     v[i][4] = y[0]; v[i][5] = y[1]; v[i][6] = y[2]; v[i][7] = y[3];
   }
@@ -730,8 +738,7 @@ __global__ __launch_bounds__(256) void transpose_pad_kernel(const float* __restr
 // Psi_jp), splits only that, and reads the pieces of Psi for B.
 //
 // A piece tile is 128 rows x 32 k of BF16 (64 bytes per row, four 16-byte
-// chunks); chunk q of row r sits in slot q ^ ((r >> 2) & 3), so the 16 rows that
-// one fragment read touches fall on distinct bank groups.
+// chunks), the chunks of each row permuted by piece_swizzle below.
 constexpr int PB = BT * KT * 2;           // bytes of one piece tile (8 KB)
 
 // x -> three BF16 planes, rows of length ld: P[q][row][k] for q = hi, mid, lo.
@@ -799,6 +806,12 @@ __global__ void gamma_split3_kernel(const double* __restrict__ G, __bf16* __rest
   }
 }
 
+// Slot permutation of the four 16-byte chunks of a piece row (64 bytes): chunk q
+// of row r sits in slot q ^ piece_swizzle(r).  Rows r and r' that a fragment read
+// serves in one pass then fall in distinct 16-byte bank groups, whether a pass
+// covers 8 rows (128 bytes of banks) or 16 rows (256 bytes).
+__device__ inline int piece_swizzle(int r) { return ((r >> 1) ^ (r >> 2)) & 3; }
+
 // This wave's share (one of eight copy instructions, 16 rows each) of a piece
 // tile: rows [r0, r0+BT) x k in [k0, k0+KT) of the row-major BF16 plane X
 // (row length ld); chunks with row >= nrows or k >= kend (a multiple of 8) read
@@ -807,7 +820,7 @@ __device__ inline void dma_piece(const __bf16* __restrict__ X, int64_t ld, int64
                                  int64_t r0, int64_t k0, int64_t kend, const float* zeros,
                                  unsigned char* tile, int wid, int lane) {
   const int r = wid * 16 + (lane >> 2);
-  const int q = (lane & 3) ^ ((r >> 2) & 3);
+  const int q = (lane & 3) ^ piece_swizzle(r);
   const int64_t k = k0 + 8 * q;
   const int64_t gr = r0 + r;
   const void* src = (gr < nrows && k < kend) ? (const void*)(X + gr * ld + k) : (const void*)zeros;
@@ -821,7 +834,7 @@ __device__ inline void frag_piece(const unsigned char* tile, int base, int lane,
 #pragma unroll
   for (int i = 0; i < NI; ++i) {
     const int R = base + 16 * i + r16;
-    v[i] = *reinterpret_cast<const bf8*>(tile + R * 64 + ((g ^ ((R >> 2) & 3)) * 16));
+    v[i] = *reinterpret_cast<const bf8*>(tile + R * 64 + ((g ^ piece_swizzle(R)) * 16));
   }
 }
 
