@@ -597,7 +597,9 @@ lrdm_status rayleigh_ritz(lrdm_ctx* ctx, const Grid3& g, const double* V, T* Psi
     if constexpr (sizeof(T) == sizeof(float)) {
       if (prec == LRDM_BF16X3) {
         ctx->ws_top = mark;
-        return launch_rotate_bf16x3(ctx, Wt, Bsrc, Out, N, M, upper);
+        const hipError_t err = launch_rotate_bf16x3(ctx, Wt, Bsrc, Out, N, M, upper);
+        ctx->ws_top = mark;   // the split operands are free again once the product is queued
+        return err;
       }
     }
     return launch_nn_f64<T>(ctx, Wt, Bsrc, Out, N, M, upper);

@@ -208,3 +208,29 @@ def test_autotune_keeps_the_response(c24, form):
     ref, _, _ = O.density_response(to_host(P), eps[None], g, wl.n_electrons, wl.kT, dV, 1)
     assert rel(after, ref) < (1e-10 if form == "fp64" else BOUND[form])
     assert all(s >= 1 for s in tuned["splits"])
+
+
+def test_rayleigh_ritz_bf16x3_fresh_context_two_passes():
+    """A context whose first call is a BF16X3 Rayleigh-Ritz of an ill-conditioned
+    FP32 block (two orthonormalisation passes, the split rotation between them):
+    the workspace sized for that call alone must hold the rotation's split
+    operands and then the second Gram product."""
+    g = O.Grid((32, 32, 32), (12.0, 12.0, 12.0))
+    rng = np.random.default_rng(77)
+    V = rng.uniform(-1, 0, g.shape)
+    N = 256
+    e0, X = O.rayleigh_ritz(rng.standard_normal((N,) + g.shape), V, g)
+    b = sum(2.0 / h ** 2 for h in g.h) + V.max()
+    Y = O.chebyshev_filter(X, V, g, 40, e0[-1], b, e0[0] - 0.2)
+    eps_o, _ = O.rayleigh_ritz(Y, V, g)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):                  # a new stream: a fresh context
+        Yd = to_dev(Y, torch.float32)
+        e = to_host(L.subspace_rayleigh_ritz(L.Grid(g.n, g.L), to_dev(V), Yd, prec="bf16x3"))
+        side.synchronize()
+    P = to_host(Yd).reshape(N, -1)
+    assert np.max(np.abs(P @ P.T - np.eye(N))) < 1e-5
+    HP = O.hamiltonian_apply(P.reshape((N,) + g.shape), V, g).reshape(N, -1)
+    assert np.max(np.abs(P @ HP.T - np.diag(e))) < 1e-4 * np.max(np.abs(e))
+    # the lower half is resolved to the storage's precision
+    assert np.max(np.abs(e[:N // 2] - eps_o[:N // 2])) < 1e-5 * np.max(np.abs(eps_o))
