@@ -72,6 +72,68 @@ __global__ void axis_kernel(const double* __restrict__ in, double* __restrict__ 
   out[e] = s;
 }
 
+// The same transform for axes of at most kLdsAxis points, staged through LDS: the
+// axis basis U (n x n) and a tile of the data, so that every value is read from
+// HBM once per pass.
+//  * axis 0 (x, contiguous lines): a block takes 64 lines of n points;
+//  * axes 1 and 2: a block takes, for one index of the slower dimensions, the n
+//    planes of a run of up to 64 consecutive points of the faster ones
+//    (in[j][i] with j along the axis, i contiguous).
+// out[.., k, ..] = sum_j coef(j, k) in[.., j, ..], coef = U[j][k] (forward) or
+// U[k][j] (inverse).
+constexpr int kLdsAxis = 64;
+
+__global__ __launch_bounds__(256) void axis_lds_kernel(const double* __restrict__ in,
+                                                       double* __restrict__ out, int n,
+                                                       int64_t inner, int64_t lines,
+                                                       const double* __restrict__ U,
+                                                       int inverse) {
+  __shared__ double Us[kLdsAxis * kLdsAxis];
+  __shared__ double T[kLdsAxis * (kLdsAxis + 1)];
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int j = e / n, k = e - j * n;
+    Us[j * kLdsAxis + k] = inverse ? U[(int64_t)k * n + j] : U[(int64_t)j * n + k];
+  }
+  if (inner == 1) {
+    // 64 contiguous lines of n points: T[line][j]
+    const int64_t l0 = (int64_t)blockIdx.x * 64;
+    const int nl = (int)min((int64_t)64, lines - l0);
+    const double* src = in + l0 * n;
+    for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
+      const int l = e / n, j = e - l * n;
+      T[l * (kLdsAxis + 1) + j] = src[e];
+    }
+    __syncthreads();
+    double* dst = out + l0 * n;
+    for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
+      const int l = e / n, k = e - l * n;
+      double acc = 0.0;
+      for (int j = 0; j < n; ++j) acc += Us[j * kLdsAxis + k] * T[l * (kLdsAxis + 1) + j];
+      dst[e] = acc;
+    }
+    return;
+  }
+  // a block: one outer index o and a run of up to 64 points i0 .. i0 + w
+  const int64_t chunks = (inner + 63) / 64;
+  const int64_t o = (int64_t)blockIdx.x / chunks;
+  const int64_t i0 = ((int64_t)blockIdx.x - o * chunks) * 64;
+  const int w = (int)min((int64_t)64, inner - i0);
+  const double* src = in + o * n * inner + i0;
+  for (int e = threadIdx.x; e < n * 64; e += blockDim.x) {
+    const int j = e >> 6, i = e & 63;
+    if (i < w) T[j * (kLdsAxis + 1) + i] = src[(int64_t)j * inner + i];
+  }
+  __syncthreads();
+  double* dst = out + o * n * inner + i0;
+  for (int e = threadIdx.x; e < n * 64; e += blockDim.x) {
+    const int k = e >> 6, i = e & 63;
+    if (i >= w) continue;
+    double acc = 0.0;
+    for (int j = 0; j < n; ++j) acc += Us[j * kLdsAxis + k] * T[j * (kLdsAxis + 1) + i];
+    dst[(int64_t)k * inner + i] = acc;
+  }
+}
+
 __global__ void sum_channels_kernel(const double* __restrict__ u, int nspin, int64_t M, int r,
                                     double* __restrict__ out) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -131,17 +193,31 @@ hipError_t launch_hartree(lrdm_ctx* ctx, const Grid3& g, const double* u, int u_
   const unsigned blocks = (unsigned)((total + 255) / 256);
   double* a = scratch;
   double* b = scratch + total;
+  // one pass along `axis`: LDS-staged for axes of at most kLdsAxis points
+  auto pass = [&](const double* in, double* out, int axis, const double* Ud, int inverse) {
+    const int n = axis == 0 ? g.nx : (axis == 1 ? g.ny : g.nz);
+    if (n > kLdsAxis) {
+      axis_kernel<<<blocks, 256, 0, ctx->stream>>>(in, out, g.nx, g.ny, g.nz, axis, Ud, inverse,
+                                                   total);
+      return;
+    }
+    const int64_t inner = axis == 0 ? 1 : (axis == 1 ? g.nx : (int64_t)g.nx * g.ny);
+    const int64_t lines = total / n;                 // lines of n points along the axis
+    const int64_t nblk = axis == 0 ? (lines + 63) / 64 : (lines / inner) * ((inner + 63) / 64);
+    axis_lds_kernel<<<(unsigned)nblk, 256, 0, ctx->stream>>>(in, out, n, inner, lines, Ud,
+                                                             inverse);
+  };
   sum_channels_kernel<<<blocks, 256, 0, ctx->stream>>>(u, u_nspin, g.M, r, a);
-  axis_kernel<<<blocks, 256, 0, ctx->stream>>>(a, b, g.nx, g.ny, g.nz, 0, Ux, 0, total);
-  axis_kernel<<<blocks, 256, 0, ctx->stream>>>(b, a, g.nx, g.ny, g.nz, 1, Uy, 0, total);
-  axis_kernel<<<blocks, 256, 0, ctx->stream>>>(a, b, g.nx, g.ny, g.nz, 2, Uz, 0, total);
+  pass(a, b, 0, Ux, 0);
+  pass(b, a, 1, Uy, 0);
+  pass(a, b, 2, Uz, 0);
   symbol_kernel<<<blocks, 256, 0, ctx->stream>>>(b, g.nx, g.ny, g.nz, lx, ly, lz, total);
-  axis_kernel<<<blocks, 256, 0, ctx->stream>>>(b, a, g.nx, g.ny, g.nz, 2, Uz, 1, total);
-  axis_kernel<<<blocks, 256, 0, ctx->stream>>>(a, b, g.nx, g.ny, g.nz, 1, Uy, 1, total);
+  pass(b, a, 2, Uz, 1);
+  pass(a, b, 1, Uy, 1);
   if (dv_nspin == 1) {
-    axis_kernel<<<blocks, 256, 0, ctx->stream>>>(b, dV, g.nx, g.ny, g.nz, 0, Ux, 1, total);
+    pass(b, dV, 0, Ux, 1);
   } else {
-    axis_kernel<<<blocks, 256, 0, ctx->stream>>>(b, a, g.nx, g.ny, g.nz, 0, Ux, 1, total);
+    pass(b, a, 0, Ux, 1);
     const int64_t tot2 = total * dv_nspin;
     scatter_channels_kernel<<<(unsigned)((tot2 + 255) / 256), 256, 0, ctx->stream>>>(a, g.M, r,
                                                                                     dv_nspin, dV);
