@@ -430,14 +430,26 @@ hipError_t run_filter(lrdm_ctx* ctx, const Grid3& g, const double* V, const T* X
   T* bufA = (degree % 2 == 1) ? Y : W;
   T* bufB = (degree % 2 == 1) ? W : Y;
   LRDM_HIP(step(X, nullptr, bufA, sigma1 / e, 0.0));
+  // steps k and k+1 in one sweep where the vectorised form can own whole z columns
+  const bool pair = vec && cheb_pair_ok<T>(g, N);
   double sigma = sigma1;
-  for (int k = 2; k <= degree; ++k) {
-    const double sigma_new = 1.0 / (2.0 / sigma1 - sigma);
-    const T* ykm1 = (k % 2 == 0) ? bufA : bufB;   // Y_{k-1}
+  for (int k = 2; k <= degree;) {
+    T* ykm1 = (k % 2 == 0) ? bufA : bufB;         // Y_{k-1}
     const T* ykm2 = (k == 2) ? X : ((k % 2 == 0) ? bufB : bufA);  // Y_{k-2}
     T* out = (k % 2 == 1) ? bufA : bufB;          // overwrites Y_{k-2} (k > 2)
-    LRDM_HIP(step(ykm1, ykm2, out, 2.0 * sigma_new / e, -sigma * sigma_new));
-    sigma = sigma_new;
+    const double s1 = 1.0 / (2.0 / sigma1 - sigma);
+    if (pair && k + 1 <= degree) {
+      const double s2 = 1.0 / (2.0 / sigma1 - s1);
+      // Y_{k+1} overwrites Y_{k-1}
+      LRDM_HIP(launch_cheb_pair_vec<T>(ctx, g, Vt, ykm2, ykm1, out, ykm1, N, c0,
+                                       2.0 * s1 / e, -sigma * s1, 2.0 * s2 / e, -s1 * s2));
+      sigma = s2;
+      k += 2;
+    } else {
+      LRDM_HIP(step(ykm1, ykm2, out, 2.0 * s1 / e, -sigma * s1));
+      sigma = s1;
+      k += 1;
+    }
   }
   return hipSuccess;
 }

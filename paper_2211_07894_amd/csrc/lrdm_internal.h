@@ -111,6 +111,18 @@ template <typename T>
 hipError_t launch_cheb_step_vec(lrdm_ctx* ctx, const Grid3& g, const T* Vt, const T* Yin,
                                 const T* Yold, T* Yout, int N, double alpha, double c0,
                                 double beta);
+// Two consecutive steps in one sweep (vectorised form):
+//   Yc = a1 (H - c0) Yb + b1 Ya,   Yd = a2 (H - c0) Yc + b2 Yb,
+// each element as launch_cheb_step_vec forms it.  Usable when cheb_pair_ok(g, N):
+// the vectorised form applies with at most 1024 groups per plane, nz >= 4, and a
+// block can own a whole z column.
+// Yc may equal Ya and Yd may equal Yb.
+template <typename T>
+bool cheb_pair_ok(const Grid3& g, int N);
+template <typename T>
+hipError_t launch_cheb_pair_vec(lrdm_ctx* ctx, const Grid3& g, const T* Vt, const T* Ya,
+                                const T* Yb, T* Yc, T* Yd, int N, double c0, double a1, double b1,
+                                double a2, double b2);
 // b[i] = (float)a[i], i < n.
 hipError_t launch_to_float(lrdm_ctx* ctx, const double* a, int64_t n, float* b);
 

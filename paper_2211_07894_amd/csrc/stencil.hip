@@ -19,6 +19,11 @@
 // the plane it computes, so that about twice the bytes are in flight per CU with
 // fewer registers than the scalar form.  Yout may be the same buffer as Yold
 // (each element is read, then written, by the same thread).
+//
+// Where a block owns a whole z column (N of 1024 and more, or short columns) two
+// consecutive steps run in one sweep: the intermediate block is formed plane by
+// plane and used for the second step while its planes are still in registers
+// and LDS, so two steps move 4 M N s bytes instead of 6.
 #include "lrdm_internal.h"
 
 namespace lrdm {
@@ -287,6 +292,169 @@ hipError_t launch_vec(lrdm_ctx* ctx, const char* scope, const Grid3& g, const T*
   return hipGetLastError();
 }
 
+// One group of W points of a recurrence step: alpha (H - c0) y + beta o at the
+// group gi of the plane pl (LDS, for the x and y neighbours), with c the group's
+// own values and pz, nzv its values on the planes below and above.
+template <typename T, int W>
+__device__ inline vec_t<T, W> step_group(const vec_t<T, W>* pl, int gi, int G, int nx, int ny,
+                                         int nxg, vec_t<T, W> c, vec_t<T, W> pz, vec_t<T, W> nzv,
+                                         vec_t<T, W> vv, vec_t<T, W> o, T wx, T wy, T wz,
+                                         T dshift, T alpha, T beta) {
+  const T* pls = reinterpret_cast<const T*>(pl);
+  const int y = gi / nxg, x0 = (gi - y * nxg) * W;
+  const int q = W * gi;
+  const vec_t<T, W> ym = pl[y == 0 ? gi + G - nxg : gi - nxg];
+  const vec_t<T, W> yp = pl[y == ny - 1 ? gi - G + nxg : gi + nxg];
+  const T left = pls[x0 == 0 ? q + nx - 1 : q - 1];
+  const T right = pls[x0 + W == nx ? q + W - nx : q + W];
+  vec_t<T, W> out;
+#pragma unroll
+  for (int e = 0; e < W; ++e) {
+    const T xl = e == 0 ? left : c[e == 0 ? 0 : e - 1];
+    const T xr = e == W - 1 ? right : c[e == W - 1 ? 0 : e + 1];
+    const T hy = wx * (xl + xr) + wy * (ym[e] + yp[e]) + wz * (pz[e] + nzv[e]) +
+                 (vv[e] + dshift) * c[e];
+    out[e] = alpha * hy + beta * o[e];
+  }
+  return out;
+}
+
+// Two recurrence steps in one sweep, for a block that owns the whole z column of
+// one vector (periodic in z, nz >= 4):
+//   C = a1 (H - c0) B + b1 A,   D = a2 (H - c0) C + b2 B
+// (A, B, C, D = Y_{k-1}, Y_k, Y_{k+1}, Y_{k+2}).  Each element is computed as
+// the single step computes it; C never makes the round trip through HBM before
+// D uses it, so the pair moves 4 M N s bytes instead of 6.  C may be the buffer
+// of A and D that of B: every element of A and B that a thread reads is read by
+// that thread before it writes the same element of C or D, and A on the planes
+// nz-1 and 0 (C written there first) and B on 0 .. 2 are never read again.
+// At plane z the sweep forms C(z+1) (from B(z), B(z+1), B(z+2)) and D(z) (from
+// C(z-1), C(z), C(z+1)); C(nz-1) and C(0), which close the period, are formed
+// before the sweep and kept in registers.  LDS holds the planes B(z+1) and C(z),
+// double-buffered: [2 buffers][B, C][G groups].
+template <typename T, int Q>
+__global__ __launch_bounds__(1024) void cheb_pair_kernel(const T* Ya, const T* Yb, T* Yc, T* Yd,
+                                                        const T* __restrict__ Vt, int nx, int ny,
+                                                        int nz, T wx, T wy, T wz, T dshift, T a1,
+                                                        T b1, T a2, T b2) {
+  constexpr int W = 16 / sizeof(T);
+  using V = vec_t<T, W>;
+  extern __shared__ unsigned char smem_raw[];
+  V* lds = reinterpret_cast<V*>(smem_raw);
+  const int P = nx * ny, G = P / W, nxg = nx / W;
+  const int64_t base = (int64_t)blockIdx.x * G * nz;
+  const V* A = reinterpret_cast<const V*>(Ya) + base;
+  const V* B = reinterpret_cast<const V*>(Yb) + base;
+  V* C = reinterpret_cast<V*>(Yc) + base;
+  V* D = reinterpret_cast<V*>(Yd) + base;
+  const V* vg = reinterpret_cast<const V*>(Vt);
+  const V zero = V(T(0));
+  const int zl = nz - 1;
+  V b0[Q], b1v[Q], b2v[Q], av[Q], vc[Q], vd[Q], cm[Q], cc[Q], cl[Q], cf[Q];
+  // C(nz-1) and C(0): B planes nz-2, nz-1, 0, 1 and A, V on nz-1 and 0
+  {
+    V bm2[Q], bm1[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const int gi = threadIdx.x + j * blockDim.x;
+      bm2[j] = bm1[j] = b0[j] = b1v[j] = zero;
+      if (gi < G) {
+        bm2[j] = B[(int64_t)(zl - 1) * G + gi];
+        bm1[j] = B[(int64_t)zl * G + gi];
+        b0[j] = B[gi];
+        b1v[j] = B[(int64_t)G + gi];
+        lds[gi] = bm1[j];              // buffer 0, B slot: plane nz-1
+        lds[2 * G + gi] = b0[j];       // buffer 1, B slot: plane 0
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const int gi = threadIdx.x + j * blockDim.x;
+      cl[j] = cf[j] = zero;
+      if (gi < G) {
+        const V al = A[(int64_t)zl * G + gi], a0 = A[gi];
+        const V vl = vg[(int64_t)zl * G + gi], v0 = vg[gi];
+        cl[j] = step_group<T, W>(lds, gi, G, nx, ny, nxg, bm1[j], bm2[j], b0[j], vl, al, wx, wy,
+                                 wz, dshift, a1, b1);
+        cf[j] = step_group<T, W>(lds + 2 * G, gi, G, nx, ny, nxg, b0[j], bm1[j], b1v[j], v0, a0,
+                                 wx, wy, wz, dshift, a1, b1);
+        C[(int64_t)zl * G + gi] = cl[j];
+        C[gi] = cf[j];
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    const int gi = threadIdx.x + j * blockDim.x;
+    b2v[j] = av[j] = vc[j] = vd[j] = zero;
+    if (gi < G) {
+      b2v[j] = B[(int64_t)2 * G + gi];
+      av[j] = A[(int64_t)G + gi];
+      vd[j] = vg[gi];
+      vc[j] = vg[(int64_t)G + gi];
+    }
+    cm[j] = cl[j];
+    cc[j] = cf[j];
+  }
+  for (int z = 0; z < nz; ++z) {
+    V* lb = lds + (z & 1) * 2 * G;
+    V* lc = lb + G;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const int gi = threadIdx.x + j * blockDim.x;
+      if (gi < G) {
+        lb[gi] = b1v[j];
+        lc[gi] = cc[j];
+      }
+    }
+    __syncthreads();
+    // operands of the next plane, issued before this plane's arithmetic: B(z+3)
+    // and A(z+2) while C(z+2) is still to be formed, V(z+2) while z+2 < nz
+    const bool nextc = z + 2 <= nz - 2;
+    V nb[Q], na[Q], nv[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const int gi = threadIdx.x + j * blockDim.x;
+      nb[j] = na[j] = nv[j] = zero;
+      if (gi < G) {
+        if (nextc) {
+          nb[j] = B[(int64_t)(z + 3) * G + gi];
+          na[j] = A[(int64_t)(z + 2) * G + gi];
+        }
+        if (z + 2 < nz) nv[j] = vg[(int64_t)(z + 2) * G + gi];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const int gi = threadIdx.x + j * blockDim.x;
+      if (gi >= G) continue;
+      V cn;
+      if (z + 1 <= nz - 2) {
+        cn = step_group<T, W>(lb, gi, G, nx, ny, nxg, b1v[j], b0[j], b2v[j], vc[j], av[j], wx, wy,
+                              wz, dshift, a1, b1);
+        C[(int64_t)(z + 1) * G + gi] = cn;
+      } else {
+        cn = (z + 1 == zl) ? cl[j] : cf[j];
+      }
+      D[(int64_t)z * G + gi] = step_group<T, W>(lc, gi, G, nx, ny, nxg, cc[j], cm[j], cn, vd[j],
+                                                b0[j], wx, wy, wz, dshift, a2, b2);
+      cm[j] = cc[j];
+      cc[j] = cn;
+    }
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      b0[j] = b1v[j];
+      b1v[j] = b2v[j];
+      b2v[j] = nb[j];
+      av[j] = na[j];
+      vd[j] = vc[j];
+      vc[j] = nv[j];
+    }
+  }
+}
+
 __global__ void convert_kernel(const double* __restrict__ a, int64_t n, float* __restrict__ b) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) b[i] = (float)a[i];
@@ -325,6 +493,46 @@ hipError_t launch_cheb_step_vec(lrdm_ctx* ctx, const Grid3& g, const T* Vt, cons
                              c0, beta);
 }
 
+template <typename T>
+bool cheb_pair_ok(const Grid3& g, int N) {
+  constexpr int W = 16 / sizeof(T);
+  // one group per thread (a plane of at most 1024 groups): with two the sweep's
+  // registers would spill
+  if (!cheb_vec_ok<T>(g) || g.nz < 4 || g.nx * g.ny / W > 1024) return false;
+  // the pair needs a block per whole z column, which the single step also uses
+  // once N alone fills the chip or the column is short
+  return (int64_t)N >= 1024 || g.nz / 2 < 8;
+}
+
+template <typename T>
+hipError_t launch_cheb_pair_vec(lrdm_ctx* ctx, const Grid3& g, const T* Vt, const T* Ya,
+                                const T* Yb, T* Yc, T* Yd, int N, double c0, double a1, double b1,
+                                double a2, double b2) {
+  constexpr int W = 16 / sizeof(T);
+  if (!cheb_pair_ok<T>(g, N)) return hipErrorInvalidValue;
+  const int P = g.nx * g.ny, G = P / W;
+  const int threads = ((G + 63) / 64) * 64;
+  const size_t smem = 4 * (size_t)P * sizeof(T);
+  const T wx = T(-0.5 / (g.hx * g.hx)), wy = T(-0.5 / (g.hy * g.hy)), wz = T(-0.5 / (g.hz * g.hz));
+  const T dshift = T(1.0 / (g.hx * g.hx) + 1.0 / (g.hy * g.hy) + 1.0 / (g.hz * g.hz) - c0);
+  if (smem > 65536)
+    LRDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&cheb_pair_kernel<T, 1>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+  ProfScope prof(ctx, "cheb_pair");
+  cheb_pair_kernel<T, 1><<<N, threads, smem, ctx->stream>>>(Ya, Yb, Yc, Yd, Vt, g.nx, g.ny, g.nz,
+                                                            wx, wy, wz, dshift, T(a1), T(b1),
+                                                            T(a2), T(b2));
+  return hipGetLastError();
+}
+
+template bool cheb_pair_ok<double>(const Grid3&, int);
+template bool cheb_pair_ok<float>(const Grid3&, int);
+template hipError_t launch_cheb_pair_vec<double>(lrdm_ctx*, const Grid3&, const double*,
+                                                 const double*, const double*, double*, double*,
+                                                 int, double, double, double, double, double);
+template hipError_t launch_cheb_pair_vec<float>(lrdm_ctx*, const Grid3&, const float*,
+                                                const float*, const float*, float*, float*, int,
+                                                double, double, double, double, double);
 template bool cheb_vec_ok<double>(const Grid3&);
 template bool cheb_vec_ok<float>(const Grid3&);
 template hipError_t launch_cheb_step_vec<double>(lrdm_ctx*, const Grid3&, const double*,
