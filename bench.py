@@ -176,7 +176,7 @@ def main():
             log(f"form {form} unavailable: {ex}")
             continue
         ctx.profile(True)
-        for k in ["cheb_step", "cheb_pair", "hpsi", "proj", "gram", "backproj", "nn", "eigh", "chol", "jac_sweep", "jac_solve", "jac_update", "hartree"]:
+        for k in ["cheb_step", "cheb_pair", "cheb_triple", "hpsi", "proj", "gram", "backproj", "nn", "eigh", "chol", "jac_sweep", "jac_solve", "jac_update", "hartree"]:
             ctx.profile_read(k)
         torch.cuda.synchronize()
         t_start = time.perf_counter()
@@ -186,7 +186,7 @@ def main():
         elapsed = time.perf_counter() - t_start
         ctx.profile(False)
         kern = {k: ctx.profile_read(k) for k in
-                ["cheb_step", "cheb_pair", "hpsi", "proj", "gram", "backproj", "nn", "eigh", "chol", "jac_sweep", "jac_solve", "jac_update", "hartree"]}
+                ["cheb_step", "cheb_pair", "cheb_triple", "hpsi", "proj", "gram", "backproj", "nn", "eigh", "chol", "jac_sweep", "jac_solve", "jac_update", "hartree"]}
         ms_step = 1e3 * elapsed / args.steps
         # response only (r directions on this form's Ritz pairs): r / T_resp
         torch.cuda.synchronize()
@@ -313,11 +313,12 @@ def main():
     per_launch = {
         # algorithmic work per launch: back-projection 2 M N^2 + 2 M N per direction,
         # projection 2 M N^2 per direction (full N x N), filter step 3 M N s bytes,
-        # two filter steps in one sweep 4 M N s bytes
+        # two or three filter steps in one sweep 4 M N s bytes
         "backproj": ("mfma", r * (2.0 * M * N * N + 2.0 * M * N)),
         "proj": ("mfma", r * 2.0 * M * N * N),
         "cheb_step": ("hbm", 3.0 * M * N * s_bytes + 8.0 * M),
         "cheb_pair": ("hbm", 4.0 * M * N * s_bytes + 8.0 * M),
+        "cheb_triple": ("hbm", 4.0 * M * N * s_bytes + 8.0 * M),
     }
     dom = max(per_launch, key=lambda k: hr["kernels"][k][0])
     ms_tot, launches = hr["kernels"][dom]
@@ -337,7 +338,7 @@ def main():
     executed = {"backproj": products * r * (2.0 * M * 128 * sum(N - 128 * i for i in range(nt))
                                             + 2.0 * M * N),
                 "proj": products * r * 2.0 * M * 128 * 128 * nt * (nt + 1) / 2,
-                "cheb_step": work, "cheb_pair": work}[dom]
+                "cheb_step": work, "cheb_pair": work, "cheb_triple": work}[dom]
     ex_rate = executed / avg_s / (1e9 if bound == "hbm" else 1e12)
     roofline = dict(kernel=dom, bound=bound, achieved=round(achieved, 3), peak=peak, unit=unit,
                     frac=round(achieved / peak, 4),

@@ -128,8 +128,9 @@ size_t lrdm_workspace_bytes(const lrdm_ctx* ctx);
 
 /* Per-kernel timing for measurement: with enable = 1 the context records a
  * hipEvent pair on its stream around each launch of its main kernels
- * ("cheb_step": single filter steps, "cheb_pair": two filter steps in one
- * sweep, "hpsi": plain H X and the first step of the unvectorised filter,
+ * ("cheb_step": single filter steps, "cheb_pair" and "cheb_triple": two and
+ * three filter steps in one sweep, "hpsi": plain H X and the first step of the
+ * unvectorised filter,
  * "proj": projected perturbation, "gram": Gram and
  * projected-Hamiltonian products, "backproj", "nn", "eigh" (one launch per
  * eigensolve), "jac_sweep" (one per outer sweep), "jac_solve", "jac_update",

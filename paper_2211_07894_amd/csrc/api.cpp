@@ -430,15 +430,26 @@ hipError_t run_filter(lrdm_ctx* ctx, const Grid3& g, const double* V, const T* X
   T* bufA = (degree % 2 == 1) ? Y : W;
   T* bufB = (degree % 2 == 1) ? W : Y;
   LRDM_HIP(step(X, nullptr, bufA, sigma1 / e, 0.0));
-  // steps k and k+1 in one sweep where the vectorised form can own whole z columns
+  // steps k .. k+2 (or k, k+1) in one sweep where the vectorised form can own
+  // whole z columns
   const bool pair = vec && cheb_pair_ok<T>(g, N);
+  const bool triple = vec && cheb_triple_ok<T>(g, N);
   double sigma = sigma1;
   for (int k = 2; k <= degree;) {
     T* ykm1 = (k % 2 == 0) ? bufA : bufB;         // Y_{k-1}
     const T* ykm2 = (k == 2) ? X : ((k % 2 == 0) ? bufB : bufA);  // Y_{k-2}
     T* out = (k % 2 == 1) ? bufA : bufB;          // overwrites Y_{k-2} (k > 2)
     const double s1 = 1.0 / (2.0 / sigma1 - sigma);
-    if (pair && k + 1 <= degree) {
+    if (triple && k + 2 <= degree) {
+      const double s2 = 1.0 / (2.0 / sigma1 - s1);
+      const double s3 = 1.0 / (2.0 / sigma1 - s2);
+      const double a[3] = {2.0 * s1 / e, 2.0 * s2 / e, 2.0 * s3 / e};
+      const double b[3] = {-sigma * s1, -s1 * s2, -s2 * s3};
+      // Y_{k+1} overwrites Y_{k-1}, Y_{k+2} overwrites Y_{k-2}; Y_k stays on chip
+      LRDM_HIP(launch_cheb_triple_vec<T>(ctx, g, Vt, ykm2, ykm1, ykm1, out, N, c0, a, b));
+      sigma = s3;
+      k += 3;
+    } else if (pair && k + 1 <= degree) {
       const double s2 = 1.0 / (2.0 / sigma1 - s1);
       // Y_{k+1} overwrites Y_{k-1}
       LRDM_HIP(launch_cheb_pair_vec<T>(ctx, g, Vt, ykm2, ykm1, out, ykm1, N, c0,

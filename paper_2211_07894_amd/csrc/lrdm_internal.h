@@ -123,6 +123,16 @@ template <typename T>
 hipError_t launch_cheb_pair_vec(lrdm_ctx* ctx, const Grid3& g, const T* Vt, const T* Ya,
                                 const T* Yb, T* Yc, T* Yd, int N, double c0, double a1, double b1,
                                 double a2, double b2);
+// Three consecutive steps in one sweep: Y_{k+s} = a[s-1] (H - c0) Y_{k+s-1} +
+// b[s-1] Y_{k+s-2} for s = 1, 2, 3 with Ya = Y_{k-1}, Yb = Y_k; writes Y_{k+2} to
+// Yp and Y_{k+3} to Yq only.  Usable when cheb_triple_ok(g, N): cheb_pair_ok and
+// nz >= 8.  Yp and Yq may be the buffers of Ya and Yb, either way round.
+template <typename T>
+bool cheb_triple_ok(const Grid3& g, int N);
+template <typename T>
+hipError_t launch_cheb_triple_vec(lrdm_ctx* ctx, const Grid3& g, const T* Vt, const T* Ya,
+                                  const T* Yb, T* Yp, T* Yq, int N, double c0, const double* a,
+                                  const double* b);
 // b[i] = (float)a[i], i < n.
 hipError_t launch_to_float(lrdm_ctx* ctx, const double* a, int64_t n, float* b);
 

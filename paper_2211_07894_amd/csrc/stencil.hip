@@ -20,10 +20,11 @@
 // fewer registers than the scalar form.  Yout may be the same buffer as Yold
 // (each element is read, then written, by the same thread).
 //
-// Where a block owns a whole z column (N of 1024 and more, or short columns) two
-// consecutive steps run in one sweep: the intermediate block is formed plane by
-// plane and used for the second step while its planes are still in registers
-// and LDS, so two steps move 4 M N s bytes instead of 6.
+// Where a block owns a whole z column (N of 1024 and more, or short columns)
+// three (or two) consecutive steps run in one sweep: each intermediate block is
+// formed plane by plane and used by the next step while its planes are still in
+// registers and LDS, and only the last two blocks (the next sweep's inputs) are
+// written, so three steps move 4 M N s bytes instead of 9.
 #include "lrdm_internal.h"
 
 namespace lrdm {
@@ -455,6 +456,139 @@ __global__ __launch_bounds__(1024) void cheb_pair_kernel(const T* Ya, const T* Y
   }
 }
 
+template <typename T, int S>
+struct ChebCoef {
+  T a[S], b[S];
+};
+
+// S recurrence steps in one sweep, for a block that owns the whole z column of
+// one vector (periodic in z, nz >= 2 S + 2).  Stage 0 is Y_k (Yb), stage -1 is
+// Y_{k-1} (Ya); stage s = 1 .. S is Y_{k+s} = a_s (H - c0) Y_{k+s-1} + b_s Y_{k+s-2},
+// each element formed as the single step forms it.  Only the last two stages are
+// written (stage S-1 to Yp, stage S to Yq; they are the next group's inputs), so
+// S steps move 4 M N s bytes.  Yp and Yq may be the buffers of Ya and Yb (either
+// way round): a thread reads each element of Ya and Yb before it writes the same
+// element of Yp or Yq, and the planes written first are never read again.
+// At step h of the sweep stage s is formed on plane h + S - s from stage s-1 on
+// planes h + S - s - 1 .. h + S - s + 1 (registers for z, an LDS plane for x and
+// y) and stage s-2 on its own plane.  The planes that close the period (stage s on
+// nz - (S - s) .. nz - 1 and 0 .. S - s - 1) are formed before the sweep and kept
+// in registers.  LDS: [2 buffers][S planes][G groups].
+template <typename T, int S>
+__global__ __launch_bounds__(1024) void cheb_multi_kernel(const T* Ya, const T* Yb, T* Yp, T* Yq,
+                                                         const T* __restrict__ Vt, int nx, int ny,
+                                                         int nz, T wx, T wy, T wz, T dshift,
+                                                         ChebCoef<T, S> cf) {
+  constexpr int W = 16 / sizeof(T);
+  using V = vec_t<T, W>;
+  extern __shared__ unsigned char smem_raw[];
+  V* lds = reinterpret_cast<V*>(smem_raw);
+  const int P = nx * ny, G = P / W, nxg = nx / W;
+  const int gi = threadIdx.x;
+  const bool on = gi < G;
+  const int64_t base = (int64_t)blockIdx.x * G * nz;
+  const V* A = reinterpret_cast<const V*>(Ya) + base;
+  const V* B = reinterpret_cast<const V*>(Yb) + base;
+  V* Op = reinterpret_cast<V*>(Yp) + base;
+  V* Oq = reinterpret_cast<V*>(Yq) + base;
+  const V* vg = reinterpret_cast<const V*>(Vt);
+  const V zero = V(T(0));
+  auto ld = [&](const V* src, int z) { return on ? src[(int64_t)z * G + gi] : zero; };
+  // plane of index j in the closing region: nz - S + j (j < S), j - S (j >= S)
+  auto plane = [&](int j) { return j < S ? nz - S + j : j - S; };
+
+  // ---- the closing region: stage s on j in [s, 2S - s)
+  V pro[S][2 * S];
+#pragma unroll
+  for (int j = 0; j < 2 * S; ++j) pro[0][j] = ld(B, plane(j));
+#pragma unroll
+  for (int s = 1; s < S; ++s) {
+#pragma unroll
+    for (int j = s; j < 2 * S - s; ++j)
+      if (on) lds[(j - s) * G + gi] = pro[s - 1][j];
+    __syncthreads();
+#pragma unroll
+    for (int j = s; j < 2 * S - s; ++j) {
+      const int z = plane(j);
+      const V o = s == 1 ? ld(A, z) : pro[s - 2][j];
+      pro[s][j] = zero;
+      if (on) {
+        pro[s][j] = step_group<T, W>(lds + (j - s) * G, gi, G, nx, ny, nxg, pro[s - 1][j],
+                                     pro[s - 1][j - 1], pro[s - 1][j + 1], vg[(int64_t)z * G + gi],
+                                     o, wx, wy, wz, dshift, cf.a[s - 1], cf.b[s - 1]);
+        if (s == S - 1) Op[(int64_t)z * G + gi] = pro[s][j];
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- the sweep.  win[s]: stage s on planes p_s - 2, p_s - 1, p_s once stage s
+  // is formed on p_s = h + S - s (stage 0: loaded, p_0 = h + S).
+  V win[S][3];
+#pragma unroll
+  for (int s = 1; s < S; ++s) {
+    win[s][0] = zero;
+    win[s][1] = pro[s][2 * S - s - 2];
+    win[s][2] = pro[s][2 * S - s - 1];
+  }
+  win[0][0] = zero;
+  win[0][1] = pro[0][2 * S - 2];
+  win[0][2] = pro[0][2 * S - 1];
+  V bnext = ld(B, S);
+  V areg = ld(A, S - 1);
+  V vw[S + 1];                       // vw[s] = V on p_s, s = 1 .. S
+#pragma unroll
+  for (int s = 1; s <= S; ++s) vw[s] = ld(vg, S - s);
+  for (int h = 0; h < nz; ++h) {
+    win[0][0] = win[0][1];
+    win[0][1] = win[0][2];
+    win[0][2] = bnext;
+    V* buf = lds + (h & 1) * S * G;
+    if (on) {
+      buf[gi] = win[0][1];
+#pragma unroll
+      for (int s = 1; s < S; ++s) buf[s * G + gi] = win[s][2];
+    }
+    __syncthreads();
+    // operands of the next step, issued before this step's arithmetic: B and A
+    // while stage 1 is still formed, V while its plane is inside the column
+    const bool next1 = h + S <= nz - S;
+    bnext = next1 ? ld(B, h + S + 1) : zero;
+    const V anext = next1 ? ld(A, h + S) : zero;
+    const V vnext = h + S < nz ? ld(vg, h + S) : zero;
+#pragma unroll
+    for (int s = 1; s <= S; ++s) {
+      const int p = h + S - s;
+      V val;
+      if (p <= nz - 1 - (S - s)) {
+        const V o = s == 1 ? areg : win[s - 2][0];
+        val = on ? step_group<T, W>(buf + (s - 1) * G, gi, G, nx, ny, nxg, win[s - 1][1],
+                                    win[s - 1][0], win[s - 1][2], vw[s], o, wx, wy, wz, dshift,
+                                    cf.a[s - 1], cf.b[s - 1])
+                 : zero;
+        if (on && s == S - 1) Op[(int64_t)p * G + gi] = val;
+      } else {
+        const int jj = p - nz + S;     // in [s, 2S - s)
+        val = zero;
+#pragma unroll
+        for (int j = s; j < 2 * S - s; ++j)
+          if (j == jj) val = pro[s][j];
+      }
+      if (s == S) {
+        if (on) Oq[(int64_t)h * G + gi] = val;
+      } else {
+        win[s][0] = win[s][1];
+        win[s][1] = win[s][2];
+        win[s][2] = val;
+      }
+    }
+    areg = anext;
+#pragma unroll
+    for (int s = S; s > 1; --s) vw[s] = vw[s - 1];
+    vw[1] = vnext;
+  }
+}
+
 __global__ void convert_kernel(const double* __restrict__ a, int64_t n, float* __restrict__ b) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) b[i] = (float)a[i];
@@ -525,6 +659,44 @@ hipError_t launch_cheb_pair_vec(lrdm_ctx* ctx, const Grid3& g, const T* Vt, cons
   return hipGetLastError();
 }
 
+template <typename T>
+bool cheb_triple_ok(const Grid3& g, int N) {
+  return cheb_pair_ok<T>(g, N) && g.nz >= 8;
+}
+
+template <typename T>
+hipError_t launch_cheb_triple_vec(lrdm_ctx* ctx, const Grid3& g, const T* Vt, const T* Ya,
+                                  const T* Yb, T* Yp, T* Yq, int N, double c0, const double* a,
+                                  const double* b) {
+  constexpr int W = 16 / sizeof(T);
+  if (!cheb_triple_ok<T>(g, N)) return hipErrorInvalidValue;
+  const int P = g.nx * g.ny, G = P / W;
+  const int threads = ((G + 63) / 64) * 64;
+  const size_t smem = 2 * 3 * (size_t)P * sizeof(T);
+  const T wx = T(-0.5 / (g.hx * g.hx)), wy = T(-0.5 / (g.hy * g.hy)), wz = T(-0.5 / (g.hz * g.hz));
+  const T dshift = T(1.0 / (g.hx * g.hx) + 1.0 / (g.hy * g.hy) + 1.0 / (g.hz * g.hz) - c0);
+  ChebCoef<T, 3> cf;
+  for (int s = 0; s < 3; ++s) {
+    cf.a[s] = T(a[s]);
+    cf.b[s] = T(b[s]);
+  }
+  if (smem > 65536)
+    LRDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&cheb_multi_kernel<T, 3>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+  ProfScope prof(ctx, "cheb_triple");
+  cheb_multi_kernel<T, 3><<<N, threads, smem, ctx->stream>>>(Ya, Yb, Yp, Yq, Vt, g.nx, g.ny, g.nz,
+                                                             wx, wy, wz, dshift, cf);
+  return hipGetLastError();
+}
+
+template bool cheb_triple_ok<double>(const Grid3&, int);
+template bool cheb_triple_ok<float>(const Grid3&, int);
+template hipError_t launch_cheb_triple_vec<double>(lrdm_ctx*, const Grid3&, const double*,
+                                                   const double*, const double*, double*, double*,
+                                                   int, double, const double*, const double*);
+template hipError_t launch_cheb_triple_vec<float>(lrdm_ctx*, const Grid3&, const float*,
+                                                  const float*, const float*, float*, float*, int,
+                                                  double, const double*, const double*);
 template bool cheb_pair_ok<double>(const Grid3&, int);
 template bool cheb_pair_ok<float>(const Grid3&, int);
 template hipError_t launch_cheb_pair_vec<double>(lrdm_ctx*, const Grid3&, const double*,

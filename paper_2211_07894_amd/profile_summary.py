@@ -30,15 +30,18 @@ KERNELS = {
     "fp64": {"proj": (r"tn_sym_f64_kernel<double, double>", "gemm.hip"),
              "backproj": (r"backproj_f64_kernel", "gemm.hip"),
              "cheb_step": (r"cheb_vec_kernel<double|cheb_plane_kernel<double, double", "stencil.hip"),
-             "cheb_pair": (r"cheb_pair_kernel<double", "stencil.hip")},
+             "cheb_pair": (r"cheb_pair_kernel<double", "stencil.hip"),
+             "cheb_triple": (r"cheb_multi_kernel<double", "stencil.hip")},
     "fp32": {"proj": (r"tn_sym_pipe_kernel<.*true>", "gemm_lp.hip"),
              "backproj": (r"backproj_pipe_kernel", "gemm_lp.hip"),
              "cheb_step": (r"cheb_vec_kernel<float|cheb_plane_kernel<float, float", "stencil.hip"),
-             "cheb_pair": (r"cheb_pair_kernel<float", "stencil.hip")},
+             "cheb_pair": (r"cheb_pair_kernel<float", "stencil.hip"),
+             "cheb_triple": (r"cheb_multi_kernel<float", "stencil.hip")},
     "bf16x3": {"proj": (r"tn_sym_p3_kernel|tn_sym_pipe_kernel<.*true>", "gemm_lp.hip"),
                "backproj": (r"backproj_p3_kernel|backproj_pipe_kernel", "gemm_lp.hip"),
                "cheb_step": (r"cheb_vec_kernel<float|cheb_plane_kernel<float, float", "stencil.hip"),
-               "cheb_pair": (r"cheb_pair_kernel<float", "stencil.hip")},
+               "cheb_pair": (r"cheb_pair_kernel<float", "stencil.hip"),
+             "cheb_triple": (r"cheb_multi_kernel<float", "stencil.hip")},
 }
 CALIBRATION_BYTES = 1 << 30
 

@@ -1,9 +1,10 @@
-"""Chebyshev filter where two recurrence steps run in one sweep (a block owns a
-whole z column: short columns, or 1024 states and more), against the FP64
-oracle: small grids with odd and even degrees (pairs plus a single last step),
-the shortest column the sweep takes (nz = 4), and the 64^3 / 1024-state
-workload in the launch configuration the bench times, on sampled states (the
-filter acts on each state alone, so the oracle filters only those)."""
+"""Chebyshev filter where two or three recurrence steps run in one sweep (a
+block owns a whole z column: short columns, or 1024 states and more), against
+the FP64 oracle: small grids with degrees that leave every mix of three-step,
+two-step and single sweeps, the shortest columns the sweeps take (nz = 4 for
+two steps, 8 for three), and the 64^3 / 1024-state workload in the launch
+configuration the bench times, on sampled states (the filter acts on each
+state alone, so the oracle filters only those)."""
 import numpy as np
 import pytest
 
@@ -20,10 +21,11 @@ import paper_2211_07894_amd as L  # noqa: E402
 
 
 @pytest.mark.parametrize("n,box,N", [((24, 20, 10), (10.0, 8.3, 4.2), 7),
+                                     ((12, 8, 8), (5.2, 3.5, 3.5), 4),
                                      ((16, 8, 4), (7.0, 3.5, 1.8), 3)])
-@pytest.mark.parametrize("degree", [2, 3, 8, 9])
+@pytest.mark.parametrize("degree", [2, 3, 4, 8, 9, 10])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_filter_pairs_small(n, box, N, degree, prec):
+def test_filter_sweeps_small(n, box, N, degree, prec):
     g = O.Grid(n, box)
     rng = np.random.default_rng(degree + 10 * N)
     V = rng.uniform(-1.0, 0.0, g.shape)
@@ -39,7 +41,7 @@ def test_filter_pairs_small(n, box, N, degree, prec):
 
 
 @pytest.mark.parametrize("degree", [5, 40])
-def test_filter_pairs_full_size_sampled(degree):
+def test_filter_sweeps_full_size_sampled(degree):
     """FP32 block of 1024 states on the 64^3 grid; states 0, 1, 517 and 1023
     against the oracle's filter of the same FP32-rounded states."""
     n, box, N = (64, 64, 64), (28.0, 28.0, 28.0), 1024
