@@ -86,9 +86,7 @@ hipError_t frob(lrdm_ctx* ctx, const double* A, int N, int lda, double* part, do
 }
 
 // --------------------------------------------------------------- block Jacobi
-constexpr int kJacThreads = 1024;   // threads of the pair-solve workgroup
-
-__global__ __launch_bounds__(kJacThreads) void jac_solve_kernel(const double* __restrict__ A, int Np,
+__global__ __launch_bounds__(1024) void jac_solve_kernel(const double* __restrict__ A, int Np,
                                                         int nb, int t,
                                                         const double* __restrict__ normF_ptr,
                                                         double* __restrict__ Ublk, int max_inner) {
@@ -155,15 +153,19 @@ __global__ __launch_bounds__(kJacThreads) void jac_solve_kernel(const double* __
           S[q1 * JP + q2] = x10 * sb + x11 * cb;
         }
       }
-      // U <- U J: item e takes pair e % 32 in row e / 32
-      for (int e = threadIdx.x; e < JB * JS; e += blockDim.x) {
-        const int al = e & 31, row = e >> 5;
+      // U <- U J: thread t takes pair t % 32 in rows t / 32 and t / 32 + 32
+      {
+        const int al = threadIdx.x & 31;
         const double2 ra = rcs[al];
         if (ra.y != 0.0) {
           const int2 ia = rpq[al];
-          const double up = U[row * JP + ia.x], uq = U[row * JP + ia.y];
-          U[row * JP + ia.x] = ra.x * up - ra.y * uq;
-          U[row * JP + ia.y] = ra.y * up + ra.x * uq;
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int row = (threadIdx.x >> 5) + 32 * h;
+            const double up = U[row * JP + ia.x], uq = U[row * JP + ia.y];
+            U[row * JP + ia.x] = ra.x * up - ra.y * uq;
+            U[row * JP + ia.y] = ra.y * up + ra.x * uq;
+          }
         }
       }
       __syncthreads();
@@ -500,7 +502,7 @@ lrdm_status sym_eigh(lrdm_ctx* ctx, const double* S, int lda, int N, const doubl
     for (int t = 0; t < nb - 1; ++t) {
       {
         ProfScope prof_solve(ctx, "jac_solve");
-        jac_solve_kernel<<<nb / 2, kJacThreads, 0, ctx->stream>>>(A, Np, nb, t, normF, Ublk, 1);
+        jac_solve_kernel<<<nb / 2, 1024, 0, ctx->stream>>>(A, Np, nb, t, normF, Ublk, 1);
       }
       if ((e = hipGetLastError()) != hipSuccess) return fail(e);
       const int np = nb / 2;
