@@ -36,6 +36,7 @@ namespace {
 constexpr int JB = 32;        // block width
 constexpr int JS = 64;        // pair problem size
 constexpr int JP = JS + 1;    // LDS pitch
+static_assert(JB * JB == 1024, "the pair solve gives one 2 x 2 rotation block to each thread");
 constexpr double kPad = 1e30; // diagonal of padding rows (decoupled, sorts last)
 constexpr double kDependentTol = 1e-10;  // Schur pivot (unit diagonal) of a dependent row
 // One Cholesky pass when cond(Gs) is below this: the basis T Y is then orthonormal
@@ -127,7 +128,13 @@ __global__ __launch_bounds__(1024) void jac_solve_kernel(const double* __restric
           const float az = fabsf(z);
           const float tf = __builtin_amdgcn_rcpf(az + sqrtf(1.0f + az * az));
           const double td = (z >= 0.0f ? 1.0 : -1.0) * (double)tf;
-          c = 1.0 / sqrt(1.0 + td * td);
+          // c = (1 + t^2)^{-1/2}: an FP32 estimate and two steps of Newton's
+          // iteration y <- y (3 - x y^2) / 2 in FP64 (x in [1, 2])
+          const double x = 1.0 + td * td;
+          double y = (double)__builtin_amdgcn_rsqf((float)x);
+          y = y * (1.5 - 0.5 * x * y * y);
+          y = y * (1.5 - 0.5 * x * y * y);
+          c = y;
           s = td * c;
           if (fabs(apq) > thr_flag) any_rot = 1;
         }
@@ -135,9 +142,10 @@ __global__ __launch_bounds__(1024) void jac_solve_kernel(const double* __restric
         rcs[i] = make_double2(c, s);
       }
       __syncthreads();
-      // S <- J^T S J on the 32 x 32 pair blocks (rows, then columns)
-      for (int blk = threadIdx.x; blk < JB * JB; blk += blockDim.x) {
-        const int al = blk >> 5, be = blk & 31;
+      // S <- J^T S J on the 32 x 32 pair blocks (rows, then columns), one per
+      // thread (the workgroup has JB * JB threads)
+      {
+        const int al = threadIdx.x >> 5, be = threadIdx.x & 31;
         const double2 ra = rcs[al], rb = rcs[be];
         if (ra.y != 0.0 || rb.y != 0.0) {
           const int2 ia = rpq[al], ib = rpq[be];

@@ -230,6 +230,9 @@ inline unsigned __float_as_uint(float x) { return __builtin_bit_cast(unsigned, x
 // v_rcp_f32 stand-in (the hardware result is within 1 ulp of this)
 inline float lrdm_emu_rcpf(float x) { return 1.0f / x; }
 #define __builtin_amdgcn_rcpf lrdm_emu_rcpf
+// v_rsq_f32 stand-in (the hardware result is within 1 ulp of this)
+inline float lrdm_emu_rsqf(float x) { return 1.0f / std::sqrt(x); }
+#define __builtin_amdgcn_rsqf lrdm_emu_rsqf
 inline float __uint_as_float(unsigned x) { return __builtin_bit_cast(float, x); }
 
 // ------------------------------------------------------------------ device math
