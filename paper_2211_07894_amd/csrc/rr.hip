@@ -143,12 +143,13 @@ __global__ __launch_bounds__(1024) void jac_solve_kernel(const double* __restric
       }
       __syncthreads();
       // S <- J^T S J on the 32 x 32 pair blocks (rows, then columns), one per
-      // thread (the workgroup has JB * JB threads)
+      // thread (the workgroup has JB * JB threads); U <- U J for the thread's row
+      // pair in rows be and be + 32
       {
         const int al = threadIdx.x >> 5, be = threadIdx.x & 31;
         const double2 ra = rcs[al], rb = rcs[be];
+        const int2 ia = rpq[al], ib = rpq[be];
         if (ra.y != 0.0 || rb.y != 0.0) {
-          const int2 ia = rpq[al], ib = rpq[be];
           const int p1 = ia.x, q1 = ia.y, p2 = ib.x, q2 = ib.y;
           const double ca = ra.x, sa = ra.y, cb = rb.x, sb = rb.y;
           const double b00 = S[p1 * JP + p2], b01 = S[p1 * JP + q2];
@@ -160,16 +161,10 @@ __global__ __launch_bounds__(1024) void jac_solve_kernel(const double* __restric
           S[q1 * JP + p2] = x10 * cb - x11 * sb;
           S[q1 * JP + q2] = x10 * sb + x11 * cb;
         }
-      }
-      // U <- U J: thread t takes pair t % 32 in rows t / 32 and t / 32 + 32
-      {
-        const int al = threadIdx.x & 31;
-        const double2 ra = rcs[al];
         if (ra.y != 0.0) {
-          const int2 ia = rpq[al];
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
-            const int row = (threadIdx.x >> 5) + 32 * h;
+            const int row = be + 32 * h;
             const double up = U[row * JP + ia.x], uq = U[row * JP + ia.y];
             U[row * JP + ia.x] = ra.x * up - ra.y * uq;
             U[row * JP + ia.y] = ra.y * up + ra.x * uq;
