@@ -323,15 +323,19 @@ lrdm_status lrdm_residual_derivative_xc(lrdm_ctx* ctx, const lrdm_grid* grid, co
                                         const double* u, int32_t r, lrdm_prec prec,
                                         const double* fxc, double* t);
 
-/* Parameters of the low-rank step (Sec. II B).  Values the paper uses:
- * s_tol 0.3, alpha_far 0.1, alpha_near 0.5, r_switch 1.0, and for the
- * accumulated variant at most 5 new directions per SCF step. */
+/* Parameters of the low-rank step (Sec. II B).  Values the paper uses (Sec.
+ * III A): s_tol 0.2-0.3, alpha 0.1 until ||R|| goes below 2.0 and 0.5 from then
+ * on (alpha_far 0.1, alpha_near 0.5, alpha_switch 2.0), and for the accumulated
+ * variant at most 5 new directions per SCF step, accumulating only while ||R||
+ * < 1.0 (a gate the driver applies, not this step).  The step takes alpha from
+ * the current ||R||; a driver that keeps alpha_near once the switch is made
+ * passes alpha_switch = +inf on the later steps. */
 typedef struct {
   double s_tol;       /* stop at the first rank whose s_rel (Eq. (10)) is below s_tol (>= 0) */
   int32_t r_max;      /* capacity of U and T in directions, 1..64 (kept + new) */
-  double alpha_far;   /* damping while ||R|| >= r_switch, in (0, 1] */
-  double alpha_near;  /* damping once ||R|| < r_switch, in (0, 1] */
-  double r_switch;    /* threshold on ||R|| (>= 0) */
+  double alpha_far;   /* damping while ||R|| >= alpha_switch, in (0, 1] */
+  double alpha_near;  /* damping when ||R|| < alpha_switch, in (0, 1] */
+  double alpha_switch; /* threshold on ||R|| (>= 0, +inf allowed: always alpha_near) */
   int32_t r_add_max;  /* new directions this call: k > 0 at most k, 0 up to r_max,
                          -1 none (fit R with the kept directions only) */
 } lrdm_lowrank_params;

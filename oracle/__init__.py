@@ -44,6 +44,7 @@ from .lrdm_oracle import (  # noqa: F401
     linearity_indicator,
     predicted_residual,
     lrdma_scf,
+    lrdma_event,
     lda_energy_density,
     lda_xc,
     pz81_eps_c,

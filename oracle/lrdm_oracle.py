@@ -474,10 +474,33 @@ def linearity_indicator(norm_R_lin: float, norm_R: float) -> float:
     return abs(norm_R_lin / norm_R - 1.0)
 
 
-def damping(norm_R: float, far: float = 0.1, near: float = 0.5, switch: float = 1.0) -> float:
-    """alpha of the quasi-Newton step (Eq. (4)) as Sec. II B sets it: the small
-    value while ||R|| is at or above a threshold of order one, the larger below."""
-    return far if norm_R >= switch else near
+def damping(norm_R: float, switched: bool = False, far: float = 0.1, near: float = 0.5,
+            switch: float = 2.0) -> float:
+    """alpha of the quasi-Newton step (Eq. (4)) by the schedule of Sec. III A:
+    0.1 until ||R|| goes below 2.0, and 0.5 from then on.  `switched` tells
+    whether an earlier SCF step already went below the threshold (the switch is
+    made once and kept)."""
+    return near if (switched or norm_R < switch) else far
+
+
+def lrdma_event(has_history: bool, clear_pending: bool, beta, kept_s_rel, norm_R: float,
+                s_tol: float = 0.3, beta_tol: float = 0.1, accumulate_below: float = 1.0) -> str:
+    """The LRDMA decision of Sec. II B 1 with the gates of Sec. III A, in the
+    order the text takes them: no history -> "fresh"; a clearing triggered at the
+    last step (s_rel not reached) -> "CT"; beta > beta_tol -> "CL"; the kept
+    approximation already fits R (kept_s_rel < s_tol) -> "reuse"; ||R|| not below
+    accumulate_below -> "CR"; otherwise "accumulate"."""
+    if not has_history:
+        return "fresh"
+    if clear_pending:
+        return "CT"
+    if beta > beta_tol:
+        return "CL"
+    if kept_s_rel < s_tol:
+        return "reuse"
+    if norm_R >= accumulate_below:
+        return "CR"
+    return "accumulate"
 
 
 def effective_potential(V_ext: np.ndarray, rho: np.ndarray, grid: Grid, xc: bool = False):
@@ -520,12 +543,15 @@ def scf_residual(rho: np.ndarray, V_ext: np.ndarray, grid: Grid, N: int, n_elect
 
 def lrdm_scf(rho0: np.ndarray, V_ext: np.ndarray, grid: Grid, N: int, n_electrons: float,
              kT: float, nspin: int = 1, s_tol: float = 0.3, r_max: int = 20,
-             tol: float = 1e-9, max_iter: int = 50, xc: bool = False):
+             tol: float = 1e-9, max_iter: int = 50, xc: bool = False,
+             alpha_switch: float = 2.0):
     """SCF by the damped quasi-Newton step rho <- rho - alpha P^lr_r R (Eq. (4),
     Sec. II B) with the directional derivatives of Eq. (7) from the subspace
-    density response (K = K_c, plus the LDA kernel at rho with xc).  Returns (rho,
-    [(||R||, rank, s_rel, alpha) per step])."""
+    density response (K = K_c, plus the LDA kernel at rho with xc); alpha follows
+    the schedule of Sec. III A (damping).  Returns (rho, [(||R||, rank, s_rel,
+    alpha) per step])."""
     rho = rho0.reshape((nspin,) + grid.shape).copy()
+    switched = False
     log = []
     for _ in range(max_iter):
         R, Psi, eps = scf_residual(rho, V_ext, grid, N, n_electrons, kT, nspin, xc)
@@ -540,7 +566,8 @@ def lrdm_scf(rho0: np.ndarray, V_ext: np.ndarray, grid: Grid, N: int, n_electron
                                        fxc)[0][0]
 
         drho, U, _, hist = lowrank_preconditioner(R, apply_t, grid, s_tol, r_max)
-        alpha = damping(nR)
+        switched = switched or nR < alpha_switch
+        alpha = damping(nR, switched, switch=alpha_switch)
         rho = rho - alpha * drho
         log.append((nR, len(U), float(hist[-1]), alpha))
     return rho, log
@@ -548,23 +575,28 @@ def lrdm_scf(rho0: np.ndarray, V_ext: np.ndarray, grid: Grid, N: int, n_electron
 
 def lrdma_scf(rho0: np.ndarray, V_ext: np.ndarray, grid: Grid, N: int, n_electrons: float,
               kT: float, nspin: int = 1, s_tol: float = 0.3, beta_tol: float = 0.1,
-              r_iter_max: int = 5, r_switch: float = 1.0, r_max: int = 20, tol: float = 1e-9,
-              max_iter: int = 50, xc: bool = False):
+              r_iter_max: int = 5, accumulate_below: float = 1.0, r_max: int = 20,
+              tol: float = 1e-9, max_iter: int = 50, xc: bool = False,
+              alpha_switch: float = 2.0):
     """SCF with the accumulated low-rank step (LRDMA, Sec. II B 1).
 
     At each step, with R = R[rho]:
       * no history, or a clearing pending from the last step (CT): build afresh;
       * beta = |||R_lin|| / ||R|| - 1| > beta_tol: clear (CL) and build afresh;
       * else if the kept approximation fits R (s_rel < s_tol): use it as it is;
-      * else if ||R|| > r_switch: clear (CR) and build afresh;
+      * else if ||R|| >= accumulate_below: clear (CR) and build afresh (Sec. III A
+        allows accumulation only while ||R|| < 1.0);
       * else accumulate up to r_iter_max new directions on the kept ones; if s_rel
         is still above s_tol, clear before the next step (CT).
     Building afresh is the LRDM step of Eqs. (8)-(10) (up to r_max directions);
     r_max also caps the accumulated rank (a full history is cleared, as CT).
     R_lin = R - alpha I_r^t R with I_r^t R = sum_i y_i t_i (Eq. (12)) is the
     residual this step's approximation and alpha predict for the next step.
+    alpha follows the schedule of Sec. III A (damping), whose threshold (2.0) is
+    not the accumulation gate (1.0).
     Returns (rho, log of (||R||, rank, added, event, s_rel, alpha, beta))."""
     rho = rho0.reshape((nspin,) + grid.shape).copy()
+    switched = False
     U, T = [], []
     norm_R_lin = None
     clear_next = False
@@ -582,34 +614,28 @@ def lrdma_scf(rho0: np.ndarray, V_ext: np.ndarray, grid: Grid, N: int, n_electro
                                        fxc)[0][0]
 
         beta = None if norm_R_lin is None else linearity_indicator(norm_R_lin, nR)
-        event = "fresh"
         if len(U) >= r_max:                          # no room to accumulate: start again
             clear_next = True
-        if U and not clear_next:
-            if beta > beta_tol:
-                event = "CL"
-            else:
-                event = "keep"
-        elif U and clear_next:
-            event = "CT"
-        if event == "keep":
-            drho, U2, T2, s_rel, added, fit = lowrank_accumulate(R, apply_t, grid, s_tol, U, T, 0)
-            if s_rel < s_tol:
-                event, U, T = "reuse", list(U2), list(T2)
-            elif nR > r_switch:
-                event = "CR"
-            else:
-                drho, U2, T2, s_rel, added, fit = lowrank_accumulate(
-                    R, apply_t, grid, s_tol, U, T, min(r_iter_max, r_max - len(U)))
-                U, T = list(U2), list(T2)
-                event = "accumulate"
-                clear_next = s_rel >= s_tol
+        kept_s_rel = np.inf
+        if U and not clear_next and beta <= beta_tol:
+            drho, U2, T2, kept_s_rel, added, fit = lowrank_accumulate(R, apply_t, grid, s_tol,
+                                                                      U, T, 0)
+        event = lrdma_event(bool(U), clear_next, beta, kept_s_rel, nR, s_tol, beta_tol,
+                            accumulate_below)
+        if event == "reuse":
+            U, T, s_rel = list(U2), list(T2), kept_s_rel
+        elif event == "accumulate":
+            drho, U2, T2, s_rel, added, fit = lowrank_accumulate(
+                R, apply_t, grid, s_tol, U, T, min(r_iter_max, r_max - len(U)))
+            U, T = list(U2), list(T2)
+            clear_next = s_rel >= s_tol
         if event in ("fresh", "CL", "CR", "CT"):
             drho, U2, T2, s_rel, added, fit = lowrank_accumulate(R, apply_t, grid, s_tol, [], [],
                                                                  r_max)
             U, T = list(U2), list(T2)
             clear_next = False
-        alpha = damping(nR, switch=r_switch)
+        switched = switched or nR < alpha_switch
+        alpha = damping(nR, switched, switch=alpha_switch)
         rho = rho - alpha * drho
         R_lin = predicted_residual(R, fit, alpha)
         norm_R_lin = np.sqrt(inner(R_lin, R_lin, grid))

@@ -993,7 +993,7 @@ lrdm_status run_lowrank(lrdm_ctx* ctx, const Grid3& g, const T* Psi, const doubl
   LR_HIP("lowrank sync", hipStreamSynchronize(ctx->stream));
   if (!std::isfinite(h[LR_NR2])) return fail(ctx, LRDM_ENONFINITE, "||R|| is not finite");
   const double nR = std::sqrt(h[LR_NR2]);
-  const double alpha = nR >= prm->r_switch ? prm->alpha_far : prm->alpha_near;
+  const double alpha = nR < prm->alpha_switch ? prm->alpha_near : prm->alpha_far;
   info->norm_R = nR;
   info->alpha = alpha;
   info->added = 0;

@@ -61,8 +61,8 @@ const char* check_lowrank(const lrdm_lowrank_params* p) {
     return "params: alpha_far must be in (0, 1]";
   if (!std::isfinite(p->alpha_near) || !(p->alpha_near > 0.0 && p->alpha_near <= 1.0))
     return "params: alpha_near must be in (0, 1]";
-  if (!std::isfinite(p->r_switch) || p->r_switch < 0.0)
-    return "params: r_switch must be finite and >= 0";
+  if (std::isnan(p->alpha_switch) || p->alpha_switch < 0.0)
+    return "params: alpha_switch must be >= 0 (+inf allowed)";
   if (p->r_add_max < -1 || p->r_add_max > 64) return "params: r_add_max must be in -1..64";
   return nullptr;
 }

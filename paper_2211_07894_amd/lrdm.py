@@ -59,7 +59,7 @@ class c_system(ctypes.Structure):
 class c_lowrank_params(ctypes.Structure):
     _fields_ = [("s_tol", ctypes.c_double), ("r_max", ctypes.c_int32),
                 ("alpha_far", ctypes.c_double), ("alpha_near", ctypes.c_double),
-                ("r_switch", ctypes.c_double), ("r_add_max", ctypes.c_int32)]
+                ("alpha_switch", ctypes.c_double), ("r_add_max", ctypes.c_int32)]
 
 
 class c_lowrank_info(ctypes.Structure):
@@ -477,17 +477,17 @@ class DensityResponse(torch.autograd.Function):
 @dataclass(frozen=True)
 class LowRankParams:
     """Parameters of the low-rank step (lrdm_lowrank_params); defaults are the
-    paper's values (Sec. II B)."""
+    values of Sec. III A (alpha 0.1 until ||R|| goes below 2.0, then 0.5)."""
     s_tol: float = 0.3
     r_max: int = 20
     alpha_far: float = 0.1
     alpha_near: float = 0.5
-    r_switch: float = 1.0
+    alpha_switch: float = 2.0
     r_add_max: int = 0           # 0: up to r_max; k > 0: at most k new; -1: kept ones only
 
     def c(self) -> c_lowrank_params:
         return c_lowrank_params(float(self.s_tol), int(self.r_max), float(self.alpha_far),
-                                float(self.alpha_near), float(self.r_switch), int(self.r_add_max))
+                                float(self.alpha_near), float(self.alpha_switch), int(self.r_add_max))
 
 
 def density(grid: Grid, Psi, eps, occ: Occupation, prec="fp64", rho_in=None, out=None, mu=None):

@@ -55,6 +55,7 @@ class _ModelSCF:
         self.Y = torch.empty_like(X)
         self.bounds = [None] * ns
         self.it = 0
+        self.switched = False       # alpha has switched to alpha_near (Sec. III A)
 
     def residual(self):
         """V_eff, one ChFSI pass per channel (first_passes on the first step), and
@@ -82,12 +83,37 @@ class _ModelSCF:
         density(g, self.X, self.eps, self.occ, prec=self.prec, rho_in=self.rho, out=self.R)
 
     def step(self, params: LowRankParams, r_keep: int, r_add_max: int, update: bool):
+        """One low-rank step on self.R.  alpha follows the schedule of Sec. III A:
+        alpha_far until ||R|| goes below alpha_switch, alpha_near from that step
+        on (the switch is made once; later steps pass an infinite threshold)."""
         p = LowRankParams(s_tol=params.s_tol, r_max=params.r_max, alpha_far=params.alpha_far,
-                          alpha_near=params.alpha_near, r_switch=params.r_switch,
+                          alpha_near=params.alpha_near,
+                          alpha_switch=float("inf") if self.switched else params.alpha_switch,
                           r_add_max=r_add_max)
-        return lowrank_step(self.grid, self.X, self.eps, self.occ, self.R, p, prec=self.prec,
-                            rho=self.rho if update else None, U=self.U, T=self.T, drho=self.drho,
-                            r_keep=r_keep, fxc=self.fxc)[3]
+        info = lowrank_step(self.grid, self.X, self.eps, self.occ, self.R, p, prec=self.prec,
+                            rho=self.rho if update else None, U=self.U, T=self.T,
+                            drho=self.drho, r_keep=r_keep, fxc=self.fxc)[3]
+        if update and info["norm_R"] < params.alpha_switch:
+            self.switched = True
+        return info
+
+
+def lrdma_event(kept: int, clear_pending: bool, beta, kept_s_rel, norm_R: float, s_tol: float,
+                beta_tol: float, accumulate_below: float) -> str:
+    """What the accumulated step does at this SCF step (Sec. II B 1, gates of
+    Sec. III A): "fresh" without kept directions, "CT" for a clearing left by the
+    last step, "CL" when the linearity indicator beta exceeds beta_tol, "reuse"
+    when the kept directions fit R to s_rel < s_tol, "CR" when ||R|| is not below
+    accumulate_below, else "accumulate"."""
+    if kept == 0:
+        return "fresh"
+    if clear_pending:
+        return "CT"
+    if beta > beta_tol:
+        return "CL"
+    if kept_s_rel < s_tol:
+        return "reuse"
+    return "CR" if norm_R >= accumulate_below else "accumulate"
 
 
 def _block(X, occ):
@@ -129,13 +155,14 @@ def lrdm_scf(grid: Grid, V_ext, X, occ: Occupation, degree: int, prec: str = "fp
 def lrdma_scf(grid: Grid, V_ext, X, occ: Occupation, degree: int, prec: str = "fp64",
               params: LowRankParams = LowRankParams(), beta_tol: float = 0.1, r_iter_max: int = 5,
               rho0=None, tol: float = 1e-8, max_iter: int = 50, first_passes: int = 4,
-              xc: bool = False):
+              xc: bool = False, accumulate_below: float = 1.0):
     """The model SCF of lrdm_scf with the accumulated low-rank step (LRDMA,
     Sec. II B 1).  At each SCF step, with R = R[rho]:
       * no kept directions, or a clearing pending (CT): build afresh;
       * beta = | ||R_lin|| / ||R|| - 1 | > beta_tol (Eq. (13)): clear (CL), afresh;
       * else if the kept directions fit R to s_rel < s_tol: reuse them;
-      * else if ||R|| > r_switch: clear (CR), afresh;
+      * else if ||R|| >= accumulate_below: clear (CR), afresh (Sec. III A
+        accumulates only while ||R|| < 1.0);
       * else add at most r_iter_max directions to the kept ones; if s_rel stays
         at or above s_tol, clear before the next step (CT).
     Building afresh is the LRDM step (up to params.r_max directions); a full
@@ -155,26 +182,24 @@ def lrdma_scf(grid: Grid, V_ext, X, occ: Occupation, degree: int, prec: str = "f
         if kept >= params.r_max:
             clear_next = True
         beta = None
-        event = "fresh" if kept == 0 else ("CT" if clear_next else None)
         info = None
-        if event is None:
+        if kept and not clear_next:
             probe = m.step(params, kept, -1, False)     # the kept directions against this R
             if probe["norm_R"] < tol:
                 log.append(dict(probe, event="done", beta=None, added=0))
                 break
             beta = abs(norm_R_lin / probe["norm_R"] - 1.0)
-            if beta > beta_tol:
-                event = "CL"
-            elif probe["s_rel"] < params.s_tol:
-                event = "reuse"
-                info = m.step(params, kept, -1, True)
-            elif probe["norm_R"] > params.r_switch:
-                event = "CR"
-            else:
-                event = "accumulate"
-                info = m.step(params, kept, min(r_iter_max, params.r_max - kept), True)
-                kept = info["rank"]
-                clear_next = info["s_rel"] >= params.s_tol
+            event = lrdma_event(kept, False, beta, probe["s_rel"], probe["norm_R"],
+                                params.s_tol, beta_tol, accumulate_below)
+        else:
+            event = lrdma_event(kept, clear_next, None, None, 0.0, params.s_tol, beta_tol,
+                                accumulate_below)
+        if event == "reuse":
+            info = m.step(params, kept, -1, True)
+        elif event == "accumulate":
+            info = m.step(params, kept, min(r_iter_max, params.r_max - kept), True)
+            kept = info["rank"]
+            clear_next = info["s_rel"] >= params.s_tol
         if info is None:
             info = m.step(params, 0, 0, True)
             kept = info["rank"]

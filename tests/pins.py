@@ -811,3 +811,40 @@ def pin_scf_derivative_fd_xc(nspin=1):
     lam = 2e-3
     fd = (4 * central(lam / 2) - central(lam)) / 3
     return _rel(t, fd)
+
+
+# ------------------------------------------------------------------ parameters printed in Sec. III A
+def sec3a_parameters():
+    """The preconditioner parameters Sec. III A prints (tests/golden fixture)."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "sec3a_parameters.json")) as f:
+        return json.load(f)
+
+
+def pin_damping_schedule():
+    """alpha = 0.1 until ||R|| goes below 2.0, then 0.5 from that step on."""
+    p = sec3a_parameters()
+    far, near, sw = p["alpha_far"], p["alpha_near"], p["alpha_switch_below_norm_R"]
+    return (O.damping(5.0) == far and O.damping(sw) == far and O.damping(1.5) == near
+            and O.damping(0.5) == near and O.damping(np.nextafter(sw, 0.0)) == near
+            and O.damping(3.0, switched=True) == near)
+
+
+def pin_lrdma_gates():
+    """Accumulation only while ||R|| < 1.0 (CR at 1.5, where alpha is already
+    0.5); CL once beta exceeds 0.1; reuse when the kept fit meets s_tol."""
+    p = sec3a_parameters()
+    gate, btol = p["lrdma_accumulate_only_below_norm_R"], p["lrdma_beta_tol"]
+    s_tol = p["s_tol_range"][1]
+
+    def ev(**kw):
+        args = dict(has_history=True, clear_pending=False, beta=0.0, kept_s_rel=0.9,
+                    norm_R=0.5, s_tol=s_tol)
+        args.update(kw)
+        return O.lrdma_event(**args)
+    return (ev(norm_R=1.5) == "CR" and O.damping(1.5) == p["alpha_near"]
+            and ev(norm_R=gate) == "CR" and ev(norm_R=np.nextafter(gate, 0.0)) == "accumulate"
+            and ev(beta=btol * 1.01) == "CL" and ev(beta=btol) == "accumulate"
+            and ev(kept_s_rel=0.5 * s_tol, norm_R=1.5) == "reuse"
+            and ev(clear_pending=True) == "CT" and ev(has_history=False) == "fresh")

@@ -105,7 +105,7 @@ def test_rank_and_plane_limits(lib):
     ("r_max", 65, "r_max must be in 1..64"),
     ("alpha_far", 0.0, "alpha_far must be in (0, 1]"),
     ("alpha_near", 1.5, "alpha_near must be in (0, 1]"),
-    ("r_switch", float("nan"), "r_switch must be finite"),
+    ("alpha_switch", float("nan"), "alpha_switch must be >= 0"),
     ("r_add_max", -2, "r_add_max must be in -1..64"),
 ])
 def test_lowrank_params_validation(lib, field, value, msg):

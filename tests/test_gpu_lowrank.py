@@ -144,10 +144,21 @@ def test_lowrank_step_edge_cases(c24):
     drho, U, _, info = L.lowrank_step(_grid(g), Psi_d, eps_d, occ, to_dev(R),
                                       L.LowRankParams(r_max=1))
     assert info["rank"] == 1 and rel(to_host(drho), d_o) < 1e-10
-    # a large residual takes the small damping
-    drho, _, _, info = L.lowrank_step(_grid(g), Psi_d, eps_d, occ, to_dev(100.0 * R),
-                                      L.LowRankParams(r_max=3))
-    assert info["norm_R"] > 1.0 and info["alpha"] == 0.1
+    # Sec. III A: alpha 0.1 while ||R|| >= 2.0, 0.5 below it (and at 1.5, where
+    # LRDMA would already clear as CR); an infinite threshold keeps 0.5
+    nR0 = float(np.sqrt(O.inner(R, R, g)))
+    for target, switch in ((100.0, 2.0), (2.5, 2.0), (1.5, 2.0), (0.5, 2.0), (2.5, np.inf)):
+        rho0 = np.random.default_rng(4).uniform(0, 0.01, (1,) + g.shape)
+        rho = to_dev(rho0)
+        Rs = (target / nR0) * R
+        drho, _, _, info = L.lowrank_step(_grid(g), Psi_d, eps_d, occ, to_dev(Rs),
+                                          L.LowRankParams(r_max=3, alpha_switch=switch), rho=rho)
+        a_o = O.damping(info["norm_R"], switched=switch == np.inf)
+        assert abs(info["norm_R"] - target) < 1e-12 * target
+        assert info["alpha"] == a_o == (0.1 if (target >= 2.0 and switch == 2.0) else 0.5)
+        d_o, _, _, _ = _oracle_step(wl, g, Psi2, eps2, 1, Rs, 0.3, 3)
+        assert rel(to_host(drho), d_o) < 1e-10
+        assert rel(to_host(rho), rho0 - a_o * d_o) < 1e-12
     # the tolerance at 1 stops at the first rank
     _, _, _, info = L.lowrank_step(_grid(g), Psi_d, eps_d, occ, to_dev(R),
                                    L.LowRankParams(s_tol=1.0))

@@ -49,3 +49,30 @@ def test_traffic_summary_scales_by_calibration_copy(tmp_path):
     assert recs["proj"]["write_bytes_per_launch"] == round(10.0 * 1024)
     assert recs["backproj"]["bytes_per_launch"] == round(500.0 * 1024 / 1.25) + round(20.0 * 1024)
     assert recs["proj"]["source"] == "gemm_lp.hip" and len(recs["proj"]["source_sha"]) == 16
+
+
+def test_lrdma_driver_gates_are_the_papers():
+    """The GPU driver's LRDMA decision against the parameters Sec. III A prints
+    (golden fixture): accumulation only while ||R|| < 1.0, CL above beta 0.1."""
+    from paper_2211_07894_amd.scf import lrdma_event
+    from tests.pins import sec3a_parameters
+    p = sec3a_parameters()
+    gate, btol, s_tol = (p["lrdma_accumulate_only_below_norm_R"], p["lrdma_beta_tol"],
+                         p["s_tol_range"][1])
+
+    def ev(kept=3, pending=False, beta=0.0, s_rel=0.9, nR=0.5):
+        return lrdma_event(kept, pending, beta, s_rel, nR, s_tol, btol, gate)
+    assert ev(nR=1.5) == "CR" and ev(nR=gate) == "CR" and ev(nR=0.999) == "accumulate"
+    assert ev(beta=0.11) == "CL" and ev(s_rel=0.1, nR=1.5) == "reuse"
+    assert ev(pending=True) == "CT" and ev(kept=0) == "fresh"
+
+
+def test_lowrank_params_defaults_are_the_papers():
+    """LowRankParams defaults: alpha 0.1 until ||R|| goes below 2.0, then 0.5."""
+    from paper_2211_07894_amd import LowRankParams
+    from tests.pins import sec3a_parameters
+    p, d = sec3a_parameters(), LowRankParams()
+    assert (d.alpha_far, d.alpha_near, d.alpha_switch) == (
+        p["alpha_far"], p["alpha_near"], p["alpha_switch_below_norm_R"])
+    assert p["s_tol_range"][0] <= d.s_tol <= p["s_tol_range"][1]
+

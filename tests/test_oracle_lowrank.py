@@ -40,8 +40,16 @@ def test_lowrank_spin_pair_is_direct_sum():
     assert np.allclose(h1, h2, rtol=1e-13)
 
 
-def test_damping_schedule():
-    assert O.damping(5.0) == 0.1 and O.damping(1.0) == 0.1 and O.damping(0.99) == 0.5
+def test_damping_schedule_is_the_papers():
+    """Sec. III A: alpha = 0.1 until ||R|| goes below 2.0, then 0.5 from that step
+    on (values from the golden fixture, typed in from the paper)."""
+    assert P.pin_damping_schedule()
+
+
+def test_lrdma_gates_are_the_papers():
+    """Sec. II B 1 with the gates of Sec. III A: accumulation only while ||R|| <
+    1.0 (a CR clearing at 1.5, where alpha is already 0.5), beta_tol 0.1."""
+    assert P.pin_lrdma_gates()
 
 
 @pytest.mark.parametrize("nspin", [1, 2])

@@ -228,13 +228,28 @@ def m_residual_derivative_drops_xc(mp):
     return lambda: P.pin_scf_derivative_fd_xc(1) < 1e-9
 
 
+def m_damping_one_threshold(mp):
+    """The schedule's switch merged with the accumulation gate at 1.0."""
+    _patch(mp, "damping", lambda nR, switched=False, far=0.1, near=0.5, switch=2.0:
+           ORIG["damping"](nR, switched, far, near, 1.0))
+    return lambda: P.pin_damping_schedule()
+
+
+def m_lrdma_gate_at_alpha_switch(mp):
+    """Accumulation allowed below the damping switch (2.0) instead of below 1.0."""
+    orig = ORIG["lrdma_event"]
+    _patch(mp, "lrdma_event", lambda *a, **kw: orig(*a, **{**kw, "accumulate_below": 2.0}))
+    return lambda: P.pin_lrdma_gates()
+
+
 MUTANTS = [m_drop_dmu, m_flip_F, m_shift_F_index, m_spin_factor, m_laplacian_half,
            m_cheb_sigma_sign, m_hartree_no_4pi, m_projection_layout, m_density_no_dv,
            m_rr_no_rotation, m_bisection_direction, m_spin_channel_potential,
            m_fermi_omf_subtraction_sign, m_lowrank_gs_sign, m_lowrank_no_S_inverse,
            m_lowrank_first_direction, m_hartree_sign_in_scf,
            m_recursion_drop_denominator_term, m_accumulate_first_direction_not_orthogonalised,
-           m_predicted_residual_sign, m_pz81_constant, m_residual_derivative_drops_xc]
+           m_predicted_residual_sign, m_pz81_constant, m_residual_derivative_drops_xc,
+           m_damping_one_threshold, m_lrdma_gate_at_alpha_switch]
 
 
 @pytest.mark.parametrize("mutant", MUTANTS, ids=[m.__name__ for m in MUTANTS])
