@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--fermi-depths", default="6,8,10,12,16",
                     help="depths of the recursive Fermi expansion compared with the exact "
                          "divided differences on the FP64 form ('' to skip)")
-    ap.add_argument("--scf-steps", type=int, default=12,
+    ap.add_argument("--scf-steps", type=int, default=40,
                     help="SCF steps of the model SCF run with the LRDM and the LRDMA step on "
                          "the headline form (0 to skip)")
     ap.add_argument("--grown", action="store_true",
@@ -58,6 +58,9 @@ def parse():
                     help="keep the default K-split counts of the projection contractions")
     ap.add_argument("--no-lrdm-step", action="store_true",
                     help="skip timing the low-rank step around the path")
+    ap.add_argument("--cpu-protocol", action="store_true",
+                    help="also time the oracle's median-of-3 full step on the 48^3 / 256-state "
+                         "workload (about two minutes of host time)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run three 1 GiB device copies first: a kernel of known traffic for "
                          "scaling hardware byte counters")
@@ -311,15 +314,18 @@ def main():
     # ---- roofline of the dominant kernel (largest total time in the timed steps)
     s_bytes = 8 if head == "fp64" else 4
     per_launch = {
-        # algorithmic work per launch: back-projection 2 M N^2 + 2 M N per direction,
-        # projection 2 M N^2 per direction (full N x N), filter step 3 M N s bytes,
-        # two or three filter steps in one sweep 4 M N s bytes
-        "backproj": ("mfma", r * (2.0 * M * N * N + 2.0 * M * N)),
-        "proj": ("mfma", r * 2.0 * M * N * N),
+        # algorithmic work per launch, the method's own: the projection H' = Psi^T
+        # diag(dV) Psi and the back-projection sum_ij Psi_i Gamma_ij Psi_j are
+        # symmetric in (i, j), M N^2 flops per direction each (the dense
+        # equivalent, 2 M N^2, is reported beside it); a filter step moves 3 M N s
+        # bytes, two or three steps in one sweep 4 M N s bytes
+        "backproj": ("mfma", r * 1.0 * M * N * N),
+        "proj": ("mfma", r * 1.0 * M * N * N),
         "cheb_step": ("hbm", 3.0 * M * N * s_bytes + 8.0 * M),
         "cheb_pair": ("hbm", 4.0 * M * N * s_bytes + 8.0 * M),
         "cheb_triple": ("hbm", 4.0 * M * N * s_bytes + 8.0 * M),
     }
+    dense_equiv = {"backproj": r * (2.0 * M * N * N + 2.0 * M * N), "proj": r * 2.0 * M * N * N}
     dom = max(per_launch, key=lambda k: hr["kernels"][k][0])
     ms_tot, launches = hr["kernels"][dom]
     bound, work = per_launch[dom]
@@ -342,10 +348,16 @@ def main():
     ex_rate = executed / avg_s / (1e9 if bound == "hbm" else 1e12)
     roofline = dict(kernel=dom, bound=bound, achieved=round(achieved, 3), peak=peak, unit=unit,
                     frac=round(achieved / peak, 4),
+                    work_unit=("method's own flops: M N^2 per direction (symmetric in i, j)"
+                               if bound == "mfma" else "algorithmic HBM bytes"),
                     executed_achieved=round(ex_rate, 3), executed_frac=round(ex_rate / peak, 4),
                     traffic=traffic_record(dom, WORKLOAD, head),
                     avg_launch_ms=round(1e3 * avg_s, 4), launches=launches,
                     work_per_launch=work, source=src)
+    if dom in dense_equiv:
+        de = dense_equiv[dom] / avg_s / 1e12
+        roofline["dense_equivalent_achieved"] = round(de, 3)
+        roofline["dense_equivalent_frac"] = round(de / peak, 4)
 
     # ---- achievable peaks measured on this device (STREAM-style copy; large
     # library GEMMs on the matrix cores), so the fraction is stated both ways
@@ -363,7 +375,7 @@ def main():
     # ---- CPU baseline: the oracle on a bounded sample of the same workload
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(wl, filt)
+        cpu = cpu_baseline(wl, filt, full_c2=args.cpu_protocol)
 
     line = {
         "metric": METRIC,
@@ -519,17 +531,100 @@ def measure_peaks(torch, dev):
     return out
 
 
-def cpu_baseline(wl, filt):
-    """The FP64 oracle timed on the host on a bounded sample: the filter on 4 states
-    (scaled by N/4), Rayleigh-Ritz on 128 states of the same grid (scaled by
-    (N/128)^2, its leading M N^2 terms), and one full-size direction of the residual
-    derivative (scaled by r)."""
-    import oracle as O
+def host_info():
+    """CPU model, core counts and the BLAS the oracle's NumPy calls."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    blas = []
     try:
         from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        for i in threadpool_info():
+            blas.append(dict(api=i.get("internal_api"), version=i.get("version"),
+                             threads=i.get("num_threads"), user_api=i.get("user_api")))
     except Exception:
-        cores = os.cpu_count()
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except Exception:
+        affinity = None
+    return dict(cpu_model=model, nproc=os.cpu_count(), affinity_cores=affinity, blas=blas)
+
+
+def _oracle_step(O, wl, X, filt, U):
+    """One step of the oracle: the degree-c filter, Rayleigh-Ritz, and the
+    residual derivative of every direction.  Returns the seconds taken."""
+    g = O.Grid(wl.n, wl.L)
+    t0 = time.perf_counter()
+    Y = O.chebyshev_filter(X, wl.V[0], g, wl.degree, *filt)
+    eps, Psi = O.rayleigh_ritz(Y, wl.V[0], g)
+    O.residual_derivative(Psi[None], eps[None], g, wl.n_electrons, wl.kT, U, 1)
+    return time.perf_counter() - t0
+
+
+def _cold_bounds(wl):
+    g = (wl.L[0] / wl.n[0], wl.L[1] / wl.n[1], wl.L[2] / wl.n[2])
+    b = sum(2.0 / hd ** 2 for hd in g) + float(wl.V[0].max())
+    a0 = float(wl.V[0].min()) - 0.1
+    return a0 + 0.25 * (b - a0), b, a0
+
+
+def _per_direction_single_core(O, wl, reps=3):
+    """Median seconds of one direction of the residual derivative with one BLAS
+    thread, on an orthonormal block of the workload's size (the cost does not
+    depend on the values)."""
+    from threadpoolctl import threadpool_limits
+    g = O.Grid(wl.n, wl.L)
+    Q, _ = np.linalg.qr(wl.block().reshape(wl.N, -1).T)
+    Psi = Q.T.reshape((wl.N,) + g.shape).copy()
+    del Q
+    eps = np.sort(np.random.default_rng(0).uniform(-2.0, 1.0, wl.N))
+    u = wl.directions(rank=1)
+    ts = []
+    with threadpool_limits(limits=1):
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            O.residual_derivative(Psi[None], eps[None], g, wl.n_electrons, wl.kT, u, 1)
+            ts.append(time.perf_counter() - t0)
+    return float(np.median(ts))
+
+
+def cpu_baseline(wl, filt, full_c2=False):
+    """The FP64 oracle timed on the host, following the protocol of the baseline
+    plan: the host's CPU model, cores and BLAS; on the 24^3 / 32-state workload
+    the median of three full steps (filter, Rayleigh-Ritz, all directions) with
+    all cores; one-thread seconds per direction on the 24^3 and 48^3 workloads;
+    with full_c2 also the median of three full steps on 48^3 / 256 states.  The
+    headline value is the 64^3 / 1024-state step estimated from a bounded
+    sample: the filter on 4 of 1024 states (scaled by N/4), Rayleigh-Ritz on 128
+    states of the same grid (scaled by (N/128)^2, its leading M N^2 terms), and
+    one full-size direction of the residual derivative (scaled by r)."""
+    import oracle as O
+    from inputs import make_workload
+    info = host_info()
+    cores = max([b.get("threads") or 1 for b in info["blas"]] + [1])
+    out = {"host": info}
+    c1 = make_workload("c24_n32")
+    ts = [_oracle_step(O, c1, c1.block(), _cold_bounds(c1), c1.directions()) for _ in range(3)]
+    out["c24_n32"] = dict(median_step_s=round(float(np.median(ts)), 4),
+                          steps_s=[round(t, 4) for t in ts],
+                          directions_per_s=round(c1.rank / float(np.median(ts)), 3),
+                          single_core_s_per_direction=round(_per_direction_single_core(O, c1), 4))
+    c2 = make_workload("c48_n256")
+    out["c48_n256"] = dict(single_core_s_per_direction=round(_per_direction_single_core(O, c2), 3))
+    if full_c2:
+        ts = [_oracle_step(O, c2, c2.block(), _cold_bounds(c2), c2.directions())
+              for _ in range(3)]
+        out["c48_n256"].update(median_step_s=round(float(np.median(ts)), 2),
+                               steps_s=[round(t, 2) for t in ts],
+                               directions_per_s=round(c2.rank / float(np.median(ts)), 4))
+    log(f"cpu oracle protocol: {out}")
+
     g = O.Grid(wl.n, wl.L)
     V = wl.V[0]
     N, r = wl.N, wl.rank
@@ -552,10 +647,14 @@ def cpu_baseline(wl, filt):
     del Psi
     t_step = t_filter + t_rr + r * t_dir
     log(f"cpu oracle: filter {t_filter:.1f}s (scaled), RR {t_rr:.1f}s (scaled), direction {t_dir:.2f}s")
-    return {"value": round(r / t_step, 5), "unit": "directions/s", "cores": cores, "kind": "oracle",
-            "sample": "FP64 NumPy oracle: filter on 4 of 1024 states (x256), Rayleigh-Ritz on 128 "
-                      "states (x64), one full-size residual-derivative direction (x16); "
-                      f"estimated step {t_step:.1f}s"}
+    out.update({"value": round(r / t_step, 5), "unit": "directions/s", "cores": cores,
+                "kind": "oracle",
+                "sample": "FP64 NumPy oracle: filter on 4 of 1024 states (x256), Rayleigh-Ritz on "
+                          "128 states (x64), one full-size residual-derivative direction (x16); "
+                          f"estimated step {t_step:.1f}s",
+                "c64_n1024_estimate_s": dict(filter=round(t_filter, 2), rayleigh_ritz=round(t_rr, 2),
+                                             per_direction=round(t_dir, 3))})
+    return out
 
 
 if __name__ == "__main__":

@@ -53,9 +53,12 @@
  *   - Precision forms (lrdm_prec): LRDM_FP64 keeps blocks in double;
  *     LRDM_FP32 keeps blocks in float and runs the long contractions on
  *     FP32 matrix cores with FP64 partial sums; LRDM_BF16X3 keeps blocks in
- *     float and runs the projection / back-projection contractions on BF16
- *     matrix cores with each operand split as hi + lo (hi*hi + hi*lo + lo*hi,
- *     FP32 accumulation inside a K tile, FP64 across tiles).  Potentials,
+ *     float and runs the projection / back-projection contractions (and the
+ *     Rayleigh-Ritz rotations) on BF16 matrix cores: every FP32 operand is
+ *     split exactly into three BF16 pieces x = x1 + x2 + x3 (8 significant
+ *     bits each), and the six products of order <= 2 are kept (x1*y1; x1*y2 +
+ *     x2*y1; x1*y3 + x2*y2 + x3*y1), accumulated in FP32 over four 32-wide K
+ *     tiles and in FP64 across them.  Potentials,
  *     eigenvalues, occupations, densities, mu and mu' are always double, and
  *     the subspace eigensolver, the Fermi-level bisection and the divided
  *     differences always run in FP64 on the GPU.
@@ -122,6 +125,12 @@ lrdm_status lrdm_set_checks(lrdm_ctx* ctx, int level);
  * mu stays at the Fermi-Dirac electron count.  While depth > 0,
  * density_response_backward returns LRDM_EUNSUPPORTED. */
 lrdm_status lrdm_set_fermi_expansion(lrdm_ctx* ctx, int32_t depth);
+
+/* Largest number of block Jacobi sweeps the subspace eigensolver of
+ * subspace_rayleigh_ritz may take (1..1000, default 40).  A solve that has not
+ * brought every off-diagonal entry below 1e-13 ||A||_F by then returns
+ * LRDM_ENOTCONV, at any checking level, and leaves Psi and eps undefined. */
+lrdm_status lrdm_set_eigensolver_sweeps(lrdm_ctx* ctx, int32_t max_sweeps);
 
 /* Bytes of device workspace the context currently holds. */
 size_t lrdm_workspace_bytes(const lrdm_ctx* ctx);

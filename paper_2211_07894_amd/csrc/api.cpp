@@ -269,6 +269,14 @@ extern "C" lrdm_status lrdm_set_fermi_expansion(lrdm_ctx* ctx, int32_t depth) {
   return LRDM_OK;
 }
 
+extern "C" lrdm_status lrdm_set_eigensolver_sweeps(lrdm_ctx* ctx, int32_t max_sweeps) {
+  if (!ctx) return fail(nullptr, LRDM_EINVAL, "ctx is NULL");
+  if (max_sweeps < 1 || max_sweeps > 1000)
+    return fail(ctx, LRDM_EINVAL, "max_sweeps must be in 1..1000");
+  ctx->eigh_max_sweeps = max_sweeps;
+  return LRDM_OK;
+}
+
 extern "C" size_t lrdm_workspace_bytes(const lrdm_ctx* ctx) { return ctx ? ctx->ws_cap : 0; }
 
 extern "C" lrdm_status lrdm_profile(lrdm_ctx* ctx, int enable) {

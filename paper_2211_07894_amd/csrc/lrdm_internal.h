@@ -40,6 +40,7 @@ struct lrdm_ctx {
   size_t ws_top = 0;         // bump pointer inside one call
   int checks = 0;
   int fermi_depth = 0;       // 0: exact divided differences; T > 0: recursive expansion
+  int eigh_max_sweeps = 40;  // block Jacobi sweeps before the eigensolver gives up
   lrdm_psi_pieces pieces;
   // K-split counts of the projection contraction chosen by lrdm_autotune, keyed by
   // (N, M, batch, arithmetic, weighted)

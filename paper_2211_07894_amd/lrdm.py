@@ -32,6 +32,7 @@ EXPORTED = [
     "density_response_backward", "density_response_batched",
     "lrdm_density", "lrdm_effective_potential", "lrdm_lowrank_step", "lrdm_set_fermi_expansion",
     "lrdm_lda_xc", "lrdm_residual_derivative_xc", "lrdm_autotune",
+    "lrdm_set_eigensolver_sweeps",
 ]
 
 
@@ -120,6 +121,7 @@ def library() -> ctypes.CDLL:
                 "lrdm_set_stream": [vp, vp],
                 "lrdm_set_checks": [vp, ctypes.c_int],
                 "lrdm_set_fermi_expansion": [vp, i32],
+                "lrdm_set_eigensolver_sweeps": [vp, i32],
                 "lrdm_workspace_bytes": [vp],
                 "lrdm_profile": [vp, ctypes.c_int],
                 "lrdm_profile_read": [vp, ctypes.c_char_p, ctypes.POINTER(f64), ctypes.POINTER(ctypes.c_int64)],
@@ -176,6 +178,11 @@ class Context:
         """0: exact Fermi-Dirac divided differences; T > 0: the recursive
         expansion of depth T in the response multiplier."""
         self.check(self.lib.lrdm_set_fermi_expansion(self.ptr, int(depth)))
+
+    def set_eigensolver_sweeps(self, max_sweeps: int):
+        """Sweep limit of the subspace eigensolver (default 40); beyond it
+        subspace_rayleigh_ritz raises LRDM_ENOTCONV."""
+        self.check(self.lib.lrdm_set_eigensolver_sweeps(self.ptr, int(max_sweeps)))
 
     def set_checks(self, level: int):
         self.check(self.lib.lrdm_set_checks(self.ptr, int(level)))

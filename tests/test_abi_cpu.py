@@ -176,3 +176,7 @@ def test_autotune_validation(lib):
     assert st == -1 and "nspin must be 1 or 2" in _err(lib)
     st = lib.lrdm_autotune(None, ctypes.byref(_grid()), 32, 1, 0, 0, None, None)
     assert st == -1 and "r (number of directions)" in _err(lib)
+
+
+def test_eigensolver_sweeps_needs_a_context(lib):
+    assert lib.lrdm_set_eigensolver_sweeps(None, 5) == -1 and "ctx is NULL" in _err(lib)

@@ -129,7 +129,7 @@ def test_full_size_80cubed_2048_states_rank20():
     Psi64 = Psi32.double()             # the same block in both storages
     eps = torch.sort(torch.rand(N, dtype=torch.float64, device="cuda", generator=gen) * 3.0 - 2.0)[0]
     U = grf_directions(wl.system_id, wl.n, wl.L, r)
-    dV = L.hartree_kernel(grid, to_dev(U.reshape(r, *g.shape))).reshape(r, 1, *g.shape).contiguous()
+    dV = to_dev(np.stack([O.hartree_kernel(U[k, 0], g)[None] for k in range(r)]))
     G = to_dev(grf_directions(wl.system_id + 100, wl.n, wl.L, r))
     gdV, gP, gE = L.density_response_backward(grid, Psi32, eps, occ, dV, G, prec="fp32")
     ref, _, _ = L.density_response(grid, Psi32, eps, occ, G, prec="fp32")

@@ -27,7 +27,7 @@ BOUND = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 1e-6}
 def c64():
     """Seeded unit-norm block (the response formula does not need orthonormal
     rows), sorted energies across the Fermi level, and dV = K_H u for the
-    workload's 16 GRF directions (formed on the GPU; the same dV feeds both
+    workload's 16 GRF directions (formed by the oracle; the same dV feeds both
     sides)."""
     wl = make_workload("c64_n1024_slab")
     g = O.Grid(wl.n, wl.L)
@@ -38,8 +38,8 @@ def c64():
     Psi /= torch.linalg.vector_norm(Psi.reshape(N, -1), dim=1).reshape(N, 1, 1, 1)
     eps = torch.sort(torch.rand(N, dtype=torch.float64, device="cuda", generator=gen) * 3.0
                      - 2.0)[0]
-    u = torch.from_numpy(wl.directions()).to("cuda")          # [r][1][nz][ny][nx]
-    dV = L.hartree_kernel(grid, u[:, 0].contiguous()).reshape(u.shape).contiguous()
+    u = wl.directions()                                       # [r][1][nz][ny][nx]
+    dV = to_dev(np.stack([O.hartree_kernel(u[k, 0], g)[None] for k in range(len(u))]))
     return wl, g, grid, Psi, eps, dV
 
 

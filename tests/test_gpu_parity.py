@@ -184,6 +184,27 @@ def test_rayleigh_ritz_multitile():
     assert np.max(np.abs(P @ P.T - np.eye(N))) < 1e-11
 
 
+def test_rayleigh_ritz_unconverged_eigensolver_is_an_error():
+    """A sweep limit of one on the multitile block (which needs several sweeps):
+    the eigensolver reports LRDM_ENOTCONV at the default checking level instead
+    of passing unconverged Ritz pairs on; with the limit restored the same call
+    succeeds."""
+    g = O.Grid((20, 18, 13), (8.0, 7.2, 5.2))
+    rng = np.random.default_rng(6)
+    V = rng.uniform(-1, 0, g.shape)
+    Y = rng.standard_normal((150,) + g.shape)
+    ctx = L.context()
+    ctx.set_eigensolver_sweeps(1)
+    try:
+        with pytest.raises(L.LrdmError, match="ENOTCONV"):
+            L.subspace_rayleigh_ritz(_grid(g), to_dev(V), to_dev(Y))
+    finally:
+        ctx.set_eigensolver_sweeps(40)
+    e = to_host(L.subspace_rayleigh_ritz(_grid(g), to_dev(V), to_dev(Y)))
+    eps_o, _ = O.rayleigh_ritz(Y, V, g)
+    assert np.max(np.abs(e - eps_o)) < 1e-10 * np.max(np.abs(eps_o))
+
+
 def _ritz_checks(Yd, e, V, g, N, tol_orth=1e-12):
     """Orthonormal Ritz vectors that diagonalise H in their span: returns the
     vectors (host) after asserting both properties."""
