@@ -45,6 +45,14 @@ from .lrdm_oracle import (  # noqa: F401
     predicted_residual,
     lrdma_scf,
     lrdma_event,
+    bloch_hamiltonian_apply,
+    chebyshev_filter_bloch,
+    rayleigh_ritz_bloch,
+    lowest_bloch_states,
+    fermi_level_bz,
+    projected_perturbation_complex,
+    density_from_matrix_complex,
+    density_response_bz,
     lda_energy_density,
     lda_xc,
     pz81_eps_c,

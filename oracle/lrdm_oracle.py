@@ -74,16 +74,21 @@ def chebyshev_filter(X: np.ndarray, V: np.ndarray, grid: Grid, degree: int,
         sigma_k = 1 / (2/sigma_1 - sigma_{k-1}),
         Y_k = (2 sigma_k / e)(H - c0) Y_{k-1} - sigma_{k-1} sigma_k Y_{k-2},   Y_0 = X.
     """
+    return _chebyshev(X.astype(np.float64, copy=True), lambda Y: hamiltonian_apply(Y, V, grid),
+                      degree, a, b, a0)
+
+
+def _chebyshev(X: np.ndarray, apply_H, degree: int, a: float, b: float, a0: float):
+    """The scaled three-term recurrence of chebyshev_filter for any H (apply_H)."""
     e = (b - a) / 2.0
     c0 = (b + a) / 2.0
     sigma1 = e / (a0 - c0)
-    y_prev = X.astype(np.float64, copy=True)
-    y = (sigma1 / e) * (hamiltonian_apply(y_prev, V, grid) - c0 * y_prev)
+    y_prev = X
+    y = (sigma1 / e) * (apply_H(y_prev) - c0 * y_prev)
     sigma = sigma1
     for _ in range(2, degree + 1):
         sigma_new = 1.0 / (2.0 / sigma1 - sigma)
-        y_new = (2.0 * sigma_new / e) * (hamiltonian_apply(y, V, grid) - c0 * y) \
-            - (sigma * sigma_new) * y_prev
+        y_new = (2.0 * sigma_new / e) * (apply_H(y) - c0 * y) - (sigma * sigma_new) * y_prev
         y_prev, y = y, y_new
         sigma = sigma_new
     return y
@@ -792,3 +797,133 @@ def density_response_vjp(Psi: np.ndarray, eps: np.ndarray, grid: Grid, n_electro
     if abs(S) >= 1e-300:
         ge = ge + np.stack(fp) / S * dL_dmu
     return g_dV, g_Psi.reshape(Psi.shape), ge
+
+
+# ---------------------------------------------------------------------------
+# Brillouin-zone sampling (Sec. II C, last paragraph, and its traceless
+# condition integrated over the zone)
+# ---------------------------------------------------------------------------
+def bloch_hamiltonian_apply(Y: np.ndarray, V: np.ndarray, grid: Grid, kvec) -> np.ndarray:
+    """H_k u for the cell-periodic part u of Bloch states e^{i k.x} u(x) with the
+    7-point stencil of hamiltonian_apply: the link to the neighbour at +h_d
+    carries the phase e^{i k_d h_d}, the link to -h_d its conjugate,
+        (H_k u)_p = -1/2 sum_d (e^{i k_d h_d} u_{p+e_d} + e^{-i k_d h_d} u_{p-e_d}
+                                - 2 u_p) / h_d^2 + V_p u_p.
+    k = 0 is hamiltonian_apply.  Y: complex [..., nz, ny, nx]; kvec = (kx, ky, kz)."""
+    Y = np.asarray(Y, dtype=np.complex128)
+    lap = np.zeros_like(Y)
+    for axis, hd, kd in ((-1, grid.h[0], kvec[0]), (-2, grid.h[1], kvec[1]),
+                         (-3, grid.h[2], kvec[2])):
+        ph = np.exp(1j * kd * hd)
+        lap += (ph * np.roll(Y, -1, axis=axis) + np.conj(ph) * np.roll(Y, 1, axis=axis)
+                - 2.0 * Y) / (hd * hd)
+    return -0.5 * lap + V * Y
+
+
+def chebyshev_filter_bloch(X: np.ndarray, V: np.ndarray, grid: Grid, kvec, degree: int,
+                           a: float, b: float, a0: float) -> np.ndarray:
+    """The scaled Chebyshev filter of chebyshev_filter with H_k in place of H, on a
+    complex block (the ChFSI of each k-point's subspace, Sec. II C)."""
+    return _chebyshev(np.asarray(X, dtype=np.complex128).copy(),
+                      lambda Y: bloch_hamiltonian_apply(Y, V, grid, kvec), degree, a, b, a0)
+
+
+def rayleigh_ritz_bloch(Y: np.ndarray, V: np.ndarray, grid: Grid, kvec):
+    """rayleigh_ritz for H_k on a complex block: Householder QR, the Hermitian
+    projected matrix and its eigenpairs.  Returns (eps [N], Psi_R complex [N][...])."""
+    N = Y.shape[0]
+    Psi_o, _ = np.linalg.qr(np.asarray(Y, dtype=np.complex128).reshape(N, -1).T)
+    HPsi = bloch_hamiltonian_apply(Psi_o.T.reshape(Y.shape), V, grid, kvec).reshape(N, -1).T
+    Hhat = Psi_o.conj().T @ HPsi
+    Hhat = 0.5 * (Hhat + Hhat.conj().T)
+    eps, Q = np.linalg.eigh(Hhat)
+    return eps, (Psi_o @ Q).T.reshape(Y.shape).copy()
+
+
+def lowest_bloch_states(V: np.ndarray, grid: Grid, kvec, N: int):
+    """The N lowest eigenpairs of H_k by dense diagonalisation (tiny grids).
+    Returns (eps [N], Psi complex [N][nz][ny][nx])."""
+    M = grid.M
+    Hd = bloch_hamiltonian_apply(np.eye(M, dtype=np.complex128).reshape((M,) + grid.shape), V,
+                                 grid, kvec).reshape(M, M).T
+    w, Q = np.linalg.eigh(0.5 * (Hd + Hd.conj().T))
+    return w[:N], Q[:, :N].T.reshape((N,) + grid.shape).copy()
+
+
+def fermi_level_bz(eps: np.ndarray, weights, n_electrons: float, kT: float, nspin: int = 1,
+                   max_iter: int = 200):
+    """mu solving s sum_sigma sum_k w_k sum_i f(eps_sigma,k,i, mu) = N_e (Eq. (1)
+    with the zone average sum_k w_k, sum_k w_k = 1), by the bisection of
+    fermi_level.  eps [nspin][nk][N].  Returns (mu, converged)."""
+    w = np.asarray(weights, dtype=np.float64)
+    eps = np.asarray(eps, dtype=np.float64).reshape(nspin, len(w), -1)
+    s = spin_factor(nspin)
+    lo = float(eps.min()) - 50.0 * kT
+    hi = float(eps.max()) + 50.0 * kT
+    converged = False
+    for _ in range(max_iter):
+        mid = 0.5 * (lo + hi)
+        if hi - lo <= 2.0 * np.spacing(abs(mid)):
+            converged = True
+            break
+        count = s * float(np.sum(w[None, :, None] * fermi_dirac(eps, mid, kT)[0]))
+        if count > n_electrons:
+            hi = mid
+        else:
+            lo = mid
+    return 0.5 * (lo + hi), converged
+
+
+def projected_perturbation_complex(Psi: np.ndarray, dV: np.ndarray) -> np.ndarray:
+    """H'_k = Psi_k^H diag(dV) Psi_k (Eq. (21) for a complex subspace); Psi [N][...]."""
+    N = Psi.shape[0]
+    P = Psi.reshape(N, -1).T                          # M x N
+    return P.conj().T @ (dV.reshape(-1)[:, None] * P)
+
+
+def density_from_matrix_complex(Psi: np.ndarray, Gamma: np.ndarray, dv: float,
+                                s: float) -> np.ndarray:
+    """(s/dv) diag(Psi Gamma Psi^H) with Psi the M x N matrix of the states as
+    columns (real for Hermitian Gamma)."""
+    N = Psi.shape[0]
+    P = Psi.reshape(N, -1).T
+    return ((s / dv) * np.real(np.sum((P @ Gamma) * P.conj(), axis=1))).reshape(Psi.shape[1:])
+
+
+def density_response_bz(Psi: np.ndarray, eps: np.ndarray, weights, grid: Grid,
+                        n_electrons: float, kT: float, dV: np.ndarray, nspin: int = 1):
+    """delta rho for each perturbation dV_r with Brillouin-zone sampling (Sec. II C,
+    last paragraph): each k-point's complex subspace responds as in Eq. (22),
+        Gamma_k = F_k o H'_k - mu' diag(f'_k),
+    with the common mu of the zone-averaged electron count and the common mu'
+    of the zone-averaged traceless condition,
+        mu' = sum_sigma sum_k w_k sum_i f'_ki H'_k,ii / sum_sigma sum_k w_k sum_i f'_ki,
+    and delta rho = (s/dv) sum_k w_k diag(Psi_k Gamma_k Psi_k^H) per channel.
+    Psi complex [nspin][nk][N][...], eps [nspin][nk][N], dV [r][nspin][...]
+    (lattice-periodic, the same at every k).  Returns (drho [r][nspin][...], mu,
+    dmu [r])."""
+    w = np.asarray(weights, dtype=np.float64)
+    nk = len(w)
+    Psi = np.asarray(Psi).reshape((nspin, nk) + Psi.shape[-4:])
+    eps = np.asarray(eps, dtype=np.float64).reshape(nspin, nk, -1)
+    dV = dV.reshape((-1, nspin) + grid.shape)
+    s = spin_factor(nspin)
+    mu, _ = fermi_level_bz(eps, w, n_electrons, kT, nspin)
+    fp = [[fermi_dirac(eps[c, k], mu, kT)[2] for k in range(nk)] for c in range(nspin)]
+    Fm = [[divided_differences(eps[c, k], mu, kT) for k in range(nk)] for c in range(nspin)]
+    r = dV.shape[0]
+    drho = np.zeros_like(dV)
+    dmu = np.empty(r)
+    for q in range(r):
+        Hp = [[projected_perturbation_complex(Psi[c, k], dV[q, c]) for k in range(nk)]
+              for c in range(nspin)]
+        num = sum(w[k] * np.sum(fp[c][k] * np.real(np.diag(Hp[c][k])))
+                  for c in range(nspin) for k in range(nk))
+        den = sum(w[k] * np.sum(fp[c][k]) for c in range(nspin) for k in range(nk))
+        dmu[q] = 0.0 if abs(den) < 1e-300 else num / den
+        for c in range(nspin):
+            for k in range(nk):
+                G = Fm[c][k] * Hp[c][k] - dmu[q] * np.diag(fp[c][k])
+                drho[q, c] += w[k] * density_from_matrix_complex(Psi[c, k], G, grid.dv, s)
+    return drho, mu, dmu
+

@@ -86,3 +86,27 @@ def fd_scalar(e1, e2, mu, kT):
     m = 0.5 * (e1 + e2)
     f = occupations(m, mu, kT)
     return -f * (1 - f) / kT
+
+
+def dense_bloch_hamiltonian(V: np.ndarray, n, L, kvec) -> np.ndarray:
+    """Dense complex M x M matrix of the Bloch Hamiltonian for the cell-periodic
+    part, assembled point by point: the hop from point p to its neighbour at +h_d
+    carries exp(i k_d h_d), the hop to -h_d exp(-i k_d h_d)."""
+    nx, ny, nz = n
+    h = (L[0] / nx, L[1] / ny, L[2] / nz)
+    M = nx * ny * nz
+    H = np.zeros((M, M), dtype=np.complex128)
+
+    def idx(x, y, z):
+        return (z % nz) * ny * nx + (y % ny) * nx + (x % nx)
+
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                p = idx(x, y, z)
+                H[p, p] += sum(1.0 / hd ** 2 for hd in h) + V[z, y, x]
+                for d, (dx, dy, dz) in enumerate(((1, 0, 0), (0, 1, 0), (0, 0, 1))):
+                    ph = np.exp(1j * kvec[d] * h[d])
+                    H[p, idx(x + dx, y + dy, z + dz)] += -0.5 * ph / h[d] ** 2
+                    H[p, idx(x - dx, y - dy, z - dz)] += -0.5 * np.conj(ph) / h[d] ** 2
+    return H

@@ -848,3 +848,164 @@ def pin_lrdma_gates():
             and ev(beta=btol * 1.01) == "CL" and ev(beta=btol) == "accumulate"
             and ev(kept_s_rel=0.5 * s_tol, norm_R=1.5) == "reuse"
             and ev(clear_pending=True) == "CT" and ev(has_history=False) == "fresh")
+
+
+# ------------------------------------------------------------------ Brillouin-zone sampling
+def pin_bloch_plane_wave():
+    """exp(i q.x) is an eigenvector of H_k for a constant potential V0, with
+    eigenvalue sum_d (1 - cos((q_d + k_d) h_d)) / h_d^2 + V0 (q on the grid)."""
+    g = O.Grid((6, 5, 4), (3.0, 2.6, 2.2))
+    V0, k = 0.37, (0.41, -0.77, 1.3)
+    z, y, x = np.meshgrid(*(np.arange(m) * hd for m, hd in zip(g.shape, g.h[::-1])),
+                          indexing="ij")
+    err = 0.0
+    for m in ((1, 2, 3), (0, 0, 0), (5, 4, 1)):
+        q = [2 * np.pi * m[d] / g.L[d] for d in range(3)]
+        u = np.exp(1j * (q[0] * x + q[1] * y + q[2] * z))
+        lam = sum((1 - np.cos((q[d] + k[d]) * g.h[d])) / g.h[d] ** 2 for d in range(3)) + V0
+        err = max(err, _rel(O.bloch_hamiltonian_apply(u, V0 * np.ones(g.shape), g, k), lam * u))
+    return err
+
+
+def pin_bloch_dense():
+    """H_k applied to the identity against the Bloch matrix assembled hop by hop."""
+    n, L = (4, 3, 3), (2.4, 2.0, 2.1)
+    g = O.Grid(n, L)
+    V = np.random.default_rng(31).uniform(-1, 0, g.shape)
+    k = (0.9, -0.4, 0.3)
+    Hd = O.bloch_hamiltonian_apply(np.eye(g.M).reshape((g.M,) + g.shape), V, g, k)
+    return _rel(Hd.reshape(g.M, g.M).T, bf.dense_bloch_hamiltonian(V, n, L, k))
+
+
+def _supercell(seed=33):
+    """A primitive cell and its double along x; k = 0 and pi/Lx sample the
+    double's zone-folded spectrum (Bloch's theorem)."""
+    n, L = (4, 3, 3), (2.4, 2.0, 2.1)
+    g = O.Grid(n, L)
+    V = small_wells(n, L, seed, nwells=2)
+    n2, L2 = (8, 3, 3), (4.8, 2.0, 2.1)
+    g2 = O.Grid(n2, L2)
+    V2 = np.concatenate([V, V], axis=2)
+    ks = [(0.0, 0.0, 0.0), (np.pi / L[0], 0.0, 0.0)]
+    return g, V, g2, V2, ks
+
+
+def pin_bloch_supercell_spectrum():
+    """The eigenvalues of H_k at k = 0 and pi/Lx on the primitive cell, together,
+    are those of H on the cell doubled along x."""
+    g, V, g2, V2, ks = _supercell()
+    lam_k = np.sort(np.concatenate([O.lowest_bloch_states(V, g, k, g.M)[0] for k in ks]))
+    lam_2 = np.linalg.eigvalsh(bf.dense_hamiltonian(V2, g2.n, g2.L))
+    return float(np.max(np.abs(lam_k - lam_2)) / np.max(np.abs(lam_2)))
+
+
+def pin_bz_supercell_response():
+    """Full space (every state of every k): the zone-sampled response at k = 0
+    and pi/Lx (weights 1/2) equals the response of the doubled cell at one point,
+    which is the dense-diagonalisation derivative of its density, for a
+    perturbation with the primitive period."""
+    g, V, g2, V2, ks = _supercell()
+    ne, kT = 9.0, 0.05
+    states = [O.lowest_bloch_states(V, g, k, g.M) for k in ks]
+    eps = np.stack([e for e, _ in states])[None]
+    Psi = np.stack([p for _, p in states])[None]
+    dV = np.random.default_rng(34).standard_normal(g.shape)
+    drho, _, _ = O.density_response_bz(Psi, eps, [0.5, 0.5], g, ne, kT, dV[None, None], 1)
+    dV2 = np.concatenate([dV, dV], axis=2)
+    ref = bf.richardson_derivative(
+        lambda t: bf.full_space_density(V2 + t * dV2, g2.n, g2.L, 2 * ne, kT, 2.0), 1e-3)
+    ref = ref.reshape(g2.shape)
+    return max(_rel(drho[0, 0], ref[:, :, :4]), _rel(drho[0, 0], ref[:, :, 4:]))
+
+
+def _bz_subspace_case(nspin=1, seed=35):
+    n, L = (5, 4, 4), (3.0, 2.5, 2.5)
+    g = O.Grid(n, L)
+    V = small_wells(n, L, seed)
+    ks = [(0.3, -0.5, 0.2), (-0.8, 0.1, 0.6)]
+    w = [0.3, 0.7]
+    N = 14
+    rng = np.random.default_rng(seed + 1)
+    Psi, eps = [], []
+    for c in range(nspin):
+        Vc = V + (0.05 * c) * rng.standard_normal(g.shape)
+        st = [O.lowest_bloch_states(Vc, g, k, N) for k in ks]
+        eps.append(np.stack([e for e, _ in st]))
+        Psi.append(np.stack([p for _, p in st]))
+    ne = 0.6 * N * (2.0 if nspin == 1 else 2.0)
+    return g, np.stack(Psi), np.stack(eps), w, ne, 0.04
+
+
+def pin_bz_subspace_fd(nspin=1):
+    """The zone-sampled subspace response against a Richardson central difference
+    in lam of (s/dv) sum_k w_k diag(Psi_k f(eigh(D_k + lam H'_k), mu(lam)) Psi_k^H),
+    with mu(lam) re-solved from the zone-averaged count (no divided differences)."""
+    g, Psi, eps, w, ne, kT = _bz_subspace_case(nspin)
+    nk, N = len(w), eps.shape[-1]
+    s = O.spin_factor(nspin)
+    dV = np.random.default_rng(37).standard_normal((1, nspin) + g.shape)
+    drho, _, _ = O.density_response_bz(Psi, eps, w, g, ne, kT, dV, nspin)
+    P = [[Psi[c, k].reshape(N, -1) for k in range(nk)] for c in range(nspin)]
+    Hp = [[np.einsum("ip,p,jp->ij", P[c][k].conj(), dV[0, c].ravel(), P[c][k], optimize=False)
+           for k in range(nk)] for c in range(nspin)]
+
+    def rho_all(lam):
+        ws, Ws = {}, {}
+        for c in range(nspin):
+            for k in range(nk):
+                ws[c, k], Ws[c, k] = np.linalg.eigh(np.diag(eps[c, k]) + lam * Hp[c][k])
+
+        def count(mu):
+            return s * sum(w[k] * np.sum(bf.occupations(ws[c, k], mu, kT))
+                           for c in range(nspin) for k in range(nk)) - ne
+        allw = np.concatenate(list(ws.values()))
+        from scipy.optimize import brentq
+        mu_l = brentq(count, allw.min() - 60 * kT, allw.max() + 60 * kT, xtol=1e-15, rtol=1e-15)
+        out = []
+        for c in range(nspin):
+            rho = 0.0
+            for k in range(nk):
+                f = bf.occupations(ws[c, k], mu_l, kT)
+                B = P[c][k].T @ Ws[c, k]
+                rho = rho + w[k] * (s / g.dv) * np.sum(np.abs(B) ** 2 * f[None, :], axis=1)
+            out.append(rho)
+        return np.concatenate(out)
+
+    ref = bf.richardson_derivative(rho_all, 2e-4)
+    return _rel(drho[0].reshape(-1), ref)
+
+
+def pin_bz_gamma_is_the_real_path():
+    """One k-point at k = 0 with real states: the zone-sampled response is the
+    real one."""
+    n, L = (5, 5, 4), (3.2, 3.2, 2.6)
+    g, V, eps, Psi = _rr_system(n, L, 16, seed=13)
+    dV = np.random.default_rng(38).standard_normal((2, 1) + g.shape)
+    a, mu_a, dmu_a = O.density_response(Psi[None], eps[None], g, 12.0, 0.03, dV, 1)
+    b, mu_b, dmu_b = O.density_response_bz(Psi[None, None].astype(np.complex128),
+                                           eps[None, None], [1.0], g, 12.0, 0.03, dV, 1)
+    return max(_rel(b, a), abs(mu_a - mu_b), _rel(dmu_b, dmu_a))
+
+
+def bz_invariants(nspin=1):
+    """Zone-sampled response: the integral of delta rho vanishes (zone traceless
+    condition), <dV_a, chi dV_b> is symmetric and <dV, chi dV> <= 0."""
+    g, Psi, eps, w, ne, kT = _bz_subspace_case(nspin)
+    dV = np.random.default_rng(39).standard_normal((3, nspin) + g.shape)
+    drho, _, _ = O.density_response_bz(Psi, eps, w, g, ne, kT, dV, nspin)
+    integral = max(abs(g.dv * drho[q].sum()) / (g.dv * np.abs(drho[q]).sum()) for q in range(3))
+    X = np.array([[g.dv * np.sum(dV[a] * drho[b]) for b in range(3)] for a in range(3)])
+    sym = float(np.max(np.abs(X - X.T)) / np.max(np.abs(X)))
+    return dict(integral=integral, symmetry=sym, nsd=float(np.max(np.linalg.eigvalsh(0.5 * (X + X.T)))))
+
+
+def pin_bz_time_reversal():
+    """For a real potential u_{-k} = conj(u_k): sampling {k, -k} with weights 1/2
+    gives the response of {k} alone."""
+    g, Psi, eps, w, ne, kT = _bz_subspace_case(1)
+    dV = np.random.default_rng(40).standard_normal((1, 1) + g.shape)
+    one, _, _ = O.density_response_bz(Psi[:, :1], eps[:, :1], [1.0], g, ne, kT, dV, 1)
+    Psi2 = np.concatenate([Psi[:, :1], Psi[:, :1].conj()], axis=1)
+    eps2 = np.concatenate([eps[:, :1], eps[:, :1]], axis=1)
+    two, _, _ = O.density_response_bz(Psi2, eps2, [0.5, 0.5], g, ne, kT, dV, 1)
+    return _rel(two, one)

@@ -242,6 +242,33 @@ def m_lrdma_gate_at_alpha_switch(mp):
     return lambda: P.pin_lrdma_gates()
 
 
+def m_bloch_phase_sign(mp):
+    """The Bloch phase on the wrong link (H_{-k} in place of H_k)."""
+    orig = ORIG["bloch_hamiltonian_apply"]
+    _patch(mp, "bloch_hamiltonian_apply",
+           lambda Y, V, grid, k: orig(Y, V, grid, tuple(-x for x in k)))
+    return lambda: P.pin_bloch_plane_wave() < 1e-13
+
+
+def m_bz_projection_without_conjugate(mp):
+    """Psi^T dV Psi in place of Psi^H dV Psi for the complex subspaces."""
+    def bad(Psi, dV):
+        N = Psi.shape[0]
+        Pm = Psi.reshape(N, -1).T
+        return Pm.T @ (dV.reshape(-1)[:, None] * Pm)
+    _patch(mp, "projected_perturbation_complex", bad)
+    return lambda: P.pin_bz_subspace_fd(1) < 1e-9
+
+
+def m_bz_count_without_weights(mp):
+    """The zone-averaged electron count without the k-point weights."""
+    orig = ORIG["fermi_level_bz"]
+    _patch(mp, "fermi_level_bz",
+           lambda eps, w, ne, kT, nspin=1, max_iter=200: orig(eps, [1.0 / len(w)] * len(w), ne, kT,
+                                                                nspin, max_iter))
+    return lambda: P.pin_bz_subspace_fd(1) < 1e-9
+
+
 MUTANTS = [m_drop_dmu, m_flip_F, m_shift_F_index, m_spin_factor, m_laplacian_half,
            m_cheb_sigma_sign, m_hartree_no_4pi, m_projection_layout, m_density_no_dv,
            m_rr_no_rotation, m_bisection_direction, m_spin_channel_potential,
@@ -249,7 +276,8 @@ MUTANTS = [m_drop_dmu, m_flip_F, m_shift_F_index, m_spin_factor, m_laplacian_hal
            m_lowrank_first_direction, m_hartree_sign_in_scf,
            m_recursion_drop_denominator_term, m_accumulate_first_direction_not_orthogonalised,
            m_predicted_residual_sign, m_pz81_constant, m_residual_derivative_drops_xc,
-           m_damping_one_threshold, m_lrdma_gate_at_alpha_switch]
+           m_damping_one_threshold, m_lrdma_gate_at_alpha_switch, m_bloch_phase_sign,
+           m_bz_projection_without_conjugate, m_bz_count_without_weights]
 
 
 @pytest.mark.parametrize("mutant", MUTANTS, ids=[m.__name__ for m in MUTANTS])
