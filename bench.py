@@ -296,7 +296,19 @@ def main():
             log("recursive Fermi expansion, delta rho error vs exact: "
                 + ", ".join(f"T={k} {v:.2e}" for k, v in expansion.items()))
             del t_exact, t_rec
+        # the response's block mask on this form's Ritz values (the library drops the
+        # blocks whose Fermi multiplier is at most 1e-14 of its largest entry):
+        # counted here only to state the executed work
+        _, _, _, Fm = L.fermi_occupations(e_resp, occ)
+        nt = (N + 127) // 128
+        bm = torch.zeros(nt, nt, dtype=torch.float64, device=dev)
+        for I in range(nt):
+            for J in range(I, nt):
+                bm[I, J] = Fm[0, 128 * I:128 * I + 128, 128 * J:128 * J + 128].abs().max()
+        active_blocks = int((bm > 1e-14 * bm.max()).sum().item())
+        del Fm
         results[form] = dict(ms_per_step=ms_step, value=r * args.steps / elapsed, kernels=kern,
+                             active_blocks=active_blocks,
                              lrdm_step=lrdm, fermi_expansion=expansion, model_scf=scf,
                              autotune=tuned,
                              rel_err_vs_fp64=rel, rel_err_end_to_end=rel_e2e,
@@ -337,13 +349,15 @@ def main():
         achieved, unit = work / avg_s / 1e12, "TFLOP/s"
     src = ("gemm.hip" if head == "fp64" else "gemm_lp.hip") if dom in ("backproj", "proj") \
         else "stencil.hip"
-    # executed work: the contractions skip the lower block triangle (128-wide
-    # tiles); the BF16X3 form issues six BF16 products per FP32 product
+    # executed work: the contractions form only the upper triangle of 128 x 128
+    # blocks, and of those only the active ones (blocks whose Fermi multiplier is
+    # above 1e-14 of its largest entry); the BF16X3 form issues six BF16
+    # products per FP32 product
     nt = (N + 127) // 128
     products = 6.0 if head == "bf16x3" else 1.0
-    executed = {"backproj": products * r * (2.0 * M * 128 * sum(N - 128 * i for i in range(nt))
-                                            + 2.0 * M * N),
-                "proj": products * r * 2.0 * M * 128 * 128 * nt * (nt + 1) / 2,
+    nblk = hr["active_blocks"]
+    executed = {"backproj": products * r * (2.0 * M * 128 * 128 * nblk + 2.0 * M * N),
+                "proj": products * r * 2.0 * M * 128 * 128 * nblk,
                 "cheb_step": work, "cheb_pair": work, "cheb_triple": work}[dom]
     ex_rate = executed / avg_s / (1e9 if bound == "hbm" else 1e12)
     roofline = dict(kernel=dom, bound=bound, achieved=round(achieved, 3), peak=peak, unit=unit,
@@ -353,7 +367,8 @@ def main():
                     executed_achieved=round(ex_rate, 3), executed_frac=round(ex_rate / peak, 4),
                     traffic=traffic_record(dom, WORKLOAD, head),
                     avg_launch_ms=round(1e3 * avg_s, 4), launches=launches,
-                    work_per_launch=work, source=src)
+                    work_per_launch=work, source=src,
+                    active_blocks=f"{nblk} of {nt * (nt + 1) // 2}")
     if dom in dense_equiv:
         de = dense_equiv[dom] / avg_s / 1e12
         roofline["dense_equivalent_achieved"] = round(de, 3)
@@ -403,6 +418,7 @@ def main():
                       "rel_err_end_to_end": v["rel_err_end_to_end"],
                       "lrdm_step": v["lrdm_step"],
                       "autotune_splits": (v["autotune"] or {}).get("splits"),
+                      "active_blocks": v["active_blocks"],
                       "kernel_ms": {k: round(x[0] / max(x[1], 1), 4) for k, x in v["kernels"].items() if x[1]}}
                   for f, v in results.items()},
         "fermi_expansion_rel_err": results.get("fp64", {}).get("fermi_expansion"),

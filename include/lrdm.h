@@ -126,6 +126,21 @@ lrdm_status lrdm_set_checks(lrdm_ctx* ctx, int level);
  * density_response_backward returns LRDM_EUNSUPPORTED. */
 lrdm_status lrdm_set_fermi_expansion(lrdm_ctx* ctx, int32_t depth);
 
+/* Blocks of the response left out.  Gamma = F o H' - mu' diag(f') (Eq. (22))
+ * is negligible wherever the Fermi multiplier F is: between two states both
+ * deep below the Fermi level, or both far above it.  For the response calls that
+ * follow on this context (density_response, lrdm_residual_derivative,
+ * density_response_batched, lrdm_lowrank_step), each 128 x 128 block (I, J) of
+ * the N x N matrices whose largest |F_ij| does not exceed tau times the largest
+ * |F| (over all blocks and channels) is dropped: its projection block is not
+ * formed (H' is taken as zero there, also in mu') and the back-projection skips
+ * it.  In the l2 norm the dropped part of delta rho is at most
+ * (s/dv) tau max|F| (||H'||_F + sqrt(N) |mu'|) per direction and channel, since
+ * Psi is orthonormal and |f'_i| = |F_ii| on a dropped diagonal block.  tau in
+ * [0, 1); 0 forms every block; the default is 1e-14.  The adjoint
+ * (density_response_backward) always forms every block. */
+lrdm_status lrdm_set_response_block_skip(lrdm_ctx* ctx, double tau);
+
 /* Largest number of block Jacobi sweeps the subspace eigensolver of
  * subspace_rayleigh_ritz may take (1..1000, default 40).  A solve that has not
  * brought every off-diagonal entry below 1e-13 ||A||_F by then returns
@@ -216,8 +231,9 @@ lrdm_status chfsi_filter(lrdm_ctx* ctx, const lrdm_grid* grid, const double* V,
  * directions are not determined by the input.  Synchronises the stream (the
  * pass count and the eigensolver's stop are decided on the host).  Errors:
  * EINVAL (arguments), ENOMEM (workspace), EDEVICE, ENOTCONV (eigensolver
- * without convergence in 40 sweeps, checking mode, or a block that five passes
- * could not orthonormalise). */
+ * without convergence within its sweep limit, 40 unless
+ * lrdm_set_eigensolver_sweeps says otherwise, at any checking level; or a
+ * block that five passes could not orthonormalise). */
 lrdm_status subspace_rayleigh_ritz(lrdm_ctx* ctx, const lrdm_grid* grid, const double* V,
                                    void* Psi, int32_t N, lrdm_prec prec, double* eps);
 
@@ -232,6 +248,27 @@ lrdm_status density_response(lrdm_ctx* ctx, const lrdm_grid* grid, const void* P
                              const double* eps, int32_t N, const lrdm_occ* occ,
                              const double* dV, int32_t r, lrdm_prec prec,
                              double* drho, double* mu, double* dmu);
+
+/* Subspace density response with Brillouin-zone sampling (Sec. II C, last
+ * paragraph, and the zone-integrated traceless condition there).  Each of the nk
+ * k-points has its own complex subspace Psi_k (from ChFSI of the Bloch
+ * Hamiltonian H_k) and Ritz values eps_k; the perturbation dV is lattice-periodic,
+ * the same at every k.  With weights w_k (sum_k w_k = 1):
+ *   H'_k = Psi_k^H diag(dV_q) Psi_k,  mu from s sum_k w_k sum_i f(eps_ki) = N_e,
+ *   mu'_q = sum_k w_k sum_i f'_ki H'_k,ii / sum_k w_k sum_i f'_ki (over both
+ *           channels), Gamma_k = F_k o H'_k - mu'_q diag(f'_k),
+ *   drho_q(x_p) = (s/dv) sum_k w_k sum_ij psi_ki(p) Gamma_k,ij conj(psi_kj(p)).
+ * Psi [nspin][nk][2][N][M]: for each channel and k-point the N real parts of the
+ * states, then their N imaginary parts (double for LRDM_FP64, float otherwise);
+ * eps [nspin][nk][N] and weights [nk] device doubles (weights non-negative and
+ * summing to 1, not checked); dV, drho [r][nspin][M] double; mu [1] and dmu [r]
+ * device doubles, either may be NULL.  The complex contractions run as the real
+ * ones with the 2N real rows [Re Psi_k; Im Psi_k].  Errors as for
+ * density_response, plus EINVAL for nk outside 1..64 or N > 4096. */
+lrdm_status density_response_bz(lrdm_ctx* ctx, const lrdm_grid* grid, const void* Psi,
+                                const double* eps, const double* weights, int32_t N, int32_t nk,
+                                const lrdm_occ* occ, const double* dV, int32_t r, lrdm_prec prec,
+                                double* drho, double* mu, double* dmu);
 
 /* Gateaux derivative of the SCF residual along u_k (Eq. (7)) with
  * J = chi0 K - I (Eq. (3)) and K = K_c: every channel sees

@@ -18,6 +18,7 @@ from .lrdm import (  # noqa: F401
     chfsi_filter,
     subspace_rayleigh_ritz,
     density_response,
+    density_response_bz,
     residual_derivative,
     density_response_backward,
     density_response_batched,

@@ -277,6 +277,13 @@ extern "C" lrdm_status lrdm_set_eigensolver_sweeps(lrdm_ctx* ctx, int32_t max_sw
   return LRDM_OK;
 }
 
+extern "C" lrdm_status lrdm_set_response_block_skip(lrdm_ctx* ctx, double tau) {
+  if (!ctx) return fail(nullptr, LRDM_EINVAL, "ctx is NULL");
+  if (!(tau >= 0.0 && tau < 1.0)) return fail(ctx, LRDM_EINVAL, "tau must be in [0, 1)");
+  ctx->block_tau = tau;
+  return LRDM_OK;
+}
+
 extern "C" size_t lrdm_workspace_bytes(const lrdm_ctx* ctx) { return ctx ? ctx->ws_cap : 0; }
 
 extern "C" lrdm_status lrdm_profile(lrdm_ctx* ctx, int enable) {
@@ -481,7 +488,13 @@ struct FermiState {
   double* omf;
   double* fp;
   double* F;
+  unsigned char* active;   // the response's block mask (blocks.h), NULL: every block
 };
+
+size_t block_mask_bytes(int N, int ns) {
+  const size_t ntb = (size_t)(N + 127) / 128;
+  return ws_align(ns * ntb * ntb * sizeof(double)) + ws_align(ns * ntb * ntb);
+}
 
 // mu by bisection, the occupations and the multiplier (exact divided differences,
 // or with the recursive expansion its multiplier and diagonal in the places of F
@@ -501,6 +514,13 @@ hipError_t run_fermi(lrdm_ctx* ctx, const double* eps, int N, const lrdm_occ* oc
                         st->fp, depth > 0 ? nullptr : st->F));
   if (depth > 0)
     LRDM_HIP(launch_recursive_multiplier(ctx, eps, st->mu, N, ns, occ->kT, depth, st->F, st->fp));
+  st->active = nullptr;
+  if (ctx->block_tau > 0.0 && N > 128) {
+    const size_t ntb = (size_t)(N + 127) / 128;
+    double* tmax = static_cast<double*>(ws_take(ctx, ns * ntb * ntb * sizeof(double)));
+    st->active = static_cast<unsigned char*>(ws_take(ctx, ns * ntb * ntb));
+    LRDM_HIP(launch_block_mask(ctx, st->F, N, ns, ctx->block_tau, tmax, st->active));
+  }
   return hipSuccess;
 }
 
@@ -523,10 +543,12 @@ hipError_t run_response(lrdm_ctx* ctx, const Grid3& g, const T* Psi, const doubl
   double* fp = fermi->fp;
   double* F = fermi->F;
   double* Hp = static_cast<double*>(ws_take(ctx, (size_t)batch * N * N * sizeof(double)));
-  LRDM_HIP(launch_tn_sym<T>(ctx, Psi, nullptr, dV, g.M, N, g.M, ns, batch, prec, Hp));
+  LRDM_HIP(launch_tn_sym<T>(ctx, Psi, nullptr, dV, g.M, N, g.M, ns, batch, prec, Hp,
+                            fermi->active));
   LRDM_HIP(launch_gamma(ctx, Hp, F, fp, N, ns, r, dmu_d));
   const double s = (ns == 1) ? 2.0 : 1.0;
-  LRDM_HIP(launch_backproj<T>(ctx, Psi, Hp, N, g.M, ns, batch, prec, s / g.dv, sub, out));
+  LRDM_HIP(launch_backproj<T>(ctx, Psi, Hp, N, g.M, ns, batch, prec, s / g.dv, sub, out,
+                              fermi->active));
   if (ctx->checks) LRDM_HIP(launch_check_finite(ctx, out, (int64_t)batch * g.M));
   return hipSuccess;
 }
@@ -594,6 +616,7 @@ size_t backward_bytes(int N, int64_t M, int r, int ns, lrdm_prec prec) {
 size_t response_bytes(int N, int64_t M, int r, int ns, lrdm_prec prec) {
   const int batch = r * ns;
   return ws_align(8) + ws_align((size_t)r * 8) + 3 * ws_align((size_t)ns * N * 8) +
+         block_mask_bytes(N, ns) +
          ws_align((size_t)ns * N * N * 8) + ws_align((size_t)batch * N * N * 8) +
          ws_align(tn_bytes(N, M, batch, prec)) + backproj_workspace_bytes(N, M, ns, batch, prec);
 }
@@ -667,6 +690,76 @@ extern "C" lrdm_status density_response(lrdm_ctx* ctx, const lrdm_grid* grid, co
         : run_response<float>(ctx, g, static_cast<const float*>(Psi), eps, N, occ, dV, r, prec,
                               nullptr, drho, mu, dmu);
     return e == hipSuccess ? LRDM_OK : fail_hip(ctx, "density_response", e);
+  });
+}
+
+namespace {
+
+size_t response_bz_bytes(int N, int64_t M, int r, int ns, int nk, lrdm_prec prec) {
+  const int nsk = ns * nk, batch = r * nsk, N2 = 2 * N;
+  return ws_align(8) + ws_align((size_t)r * 8) + 3 * ws_align((size_t)nsk * N * 8) +
+         ws_align((size_t)nsk * N * N * 8) + 2 * ws_align((size_t)batch * M * 8) +
+         ws_align((size_t)batch * N2 * N2 * 8) + ws_align(tn_bytes(N2, M, batch, prec)) +
+         backproj_workspace_bytes(N2, M, nsk, batch, prec);
+}
+
+template <typename T>
+hipError_t run_response_bz(lrdm_ctx* ctx, const Grid3& g, const T* Psi, const double* eps,
+                           const double* weights, int N, int nk, const lrdm_occ* occ,
+                           const double* dV, int r, lrdm_prec prec, double* drho, double* mu,
+                           double* dmu) {
+  const int ns = occ->nspin, nsk = ns * nk, batch = r * nsk, N2 = 2 * N;
+  double* mu_d = mu ? mu : static_cast<double*>(ws_take(ctx, 8));
+  double* dmu_d = dmu ? dmu : static_cast<double*>(ws_take(ctx, (size_t)r * 8));
+  const size_t vec = (size_t)nsk * N * sizeof(double);
+  double* f = static_cast<double*>(ws_take(ctx, vec));
+  double* omf = static_cast<double*>(ws_take(ctx, vec));
+  double* fp = static_cast<double*>(ws_take(ctx, vec));
+  double* F = static_cast<double*>(ws_take(ctx, (size_t)nsk * N * N * sizeof(double)));
+  LRDM_HIP(launch_fermi_bz(ctx, eps, N, ns, nk, weights, occ->kT, occ->n_electrons, mu_d, f, omf,
+                           fp, F));
+  double* W = static_cast<double*>(ws_take(ctx, (size_t)batch * g.M * sizeof(double)));
+  LRDM_HIP(launch_expand_dv(ctx, dV, r, ns, nk, g.M, W));
+  double* H2 = static_cast<double*>(ws_take(ctx, (size_t)batch * N2 * N2 * sizeof(double)));
+  LRDM_HIP(launch_tn_sym<T>(ctx, Psi, nullptr, W, g.M, N2, g.M, nsk, batch, prec, H2));
+  LRDM_HIP(launch_gamma_bz(ctx, H2, F, fp, weights, N, ns, nk, r, dmu_d));
+  double* part = static_cast<double*>(ws_take(ctx, (size_t)batch * g.M * sizeof(double)));
+  const double s = (ns == 1) ? 2.0 : 1.0;
+  LRDM_HIP(launch_backproj<T>(ctx, Psi, H2, N2, g.M, nsk, batch, prec, s / g.dv, nullptr, part));
+  LRDM_HIP(launch_sum_k(ctx, part, r, ns, nk, g.M, drho));
+  if (ctx->checks) LRDM_HIP(launch_check_finite(ctx, drho, (int64_t)r * ns * g.M));
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" lrdm_status density_response_bz(lrdm_ctx* ctx, const lrdm_grid* grid, const void* Psi,
+                                           const double* eps, const double* weights, int32_t N,
+                                           int32_t nk, const lrdm_occ* occ, const double* dV,
+                                           int32_t r, lrdm_prec prec, double* drho, double* mu,
+                                           double* dmu) {
+  LRDM_CHECK(ctx, check_grid(grid));
+  LRDM_CHECK(ctx, check_block(grid, N));
+  LRDM_CHECK(ctx, check_occ(occ, N));
+  LRDM_CHECK(ctx, check_rank(r));
+  LRDM_CHECK(ctx, check_prec(prec));
+  if (nk < 1 || nk > 64) return fail(ctx, LRDM_EINVAL, "nk must be in 1..64");
+  if (N > 4096) return fail(ctx, LRDM_EINVAL, "N must be <= 4096 (a k-point block holds 2N rows)");
+  LRDM_NONNULL(ctx, Psi, "Psi");
+  LRDM_NONNULL(ctx, eps, "eps");
+  LRDM_NONNULL(ctx, weights, "weights");
+  LRDM_NONNULL(ctx, dV, "dV");
+  LRDM_NONNULL(ctx, drho, "drho");
+  const Grid3 g = make_grid3(grid);
+  lrdm_status st = begin(ctx, response_bz_bytes(N, g.M, r, occ->nspin, nk, prec));
+  if (st != LRDM_OK) return st;
+  return guarded(ctx, [&]() -> lrdm_status {
+    hipError_t e = (prec == LRDM_FP64)
+        ? run_response_bz<double>(ctx, g, static_cast<const double*>(Psi), eps, weights, N, nk,
+                                  occ, dV, r, prec, drho, mu, dmu)
+        : run_response_bz<float>(ctx, g, static_cast<const float*>(Psi), eps, weights, N, nk, occ,
+                                 dV, r, prec, drho, mu, dmu);
+    return e == hipSuccess ? LRDM_OK : fail_hip(ctx, "density_response_bz", e);
   });
 }
 

@@ -6,6 +6,7 @@
 //     Gamma = F o H' - mu' diag(f'),   F_ij = (f_i - f_j)/(eps_i - eps_j), F_ii = f'_i,
 // and mu' follows from the traceless condition stated after Eq. (24).
 // Everything here is FP64.
+#include "blocks.h"
 #include "lrdm_internal.h"
 
 namespace lrdm {
@@ -32,11 +33,25 @@ __device__ inline double block_sum(double v, double* red) {
   return t;
 }
 
+__device__ inline double block_max(double v, double* red) {
+  // same pattern as block_sum, for a maximum of non-negative values
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double t = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  __syncthreads();
+  return t;
+}
+
 // One block: bisection for mu on [min eps - 50 kT, max eps + 50 kT] until the
-// bracket is within 2 ulp of its midpoint (at most 200 halvings).
+// bracket is within 2 ulp of its midpoint (at most 200 halvings).  With weights
+// (Brillouin-zone sampling) entry i of eps [nspin][nk][N] counts with weight
+// weights[(i / N) % nk].
 __global__ __launch_bounds__(kFermiThreads) void fermi_mu_kernel(
     const double* __restrict__ eps, int count, double s, double kT, double ne,
-    double* __restrict__ mu_out, int* __restrict__ status) {
+    const double* __restrict__ weights, int N, int nk, double* __restrict__ mu_out,
+    int* __restrict__ status) {
   __shared__ double red[4];
   double lo = 1e300, hi = -1e300;
   for (int i = threadIdx.x; i < count; i += blockDim.x) {
@@ -64,7 +79,10 @@ __global__ __launch_bounds__(kFermiThreads) void fermi_mu_kernel(
       break;
     }
     double part = 0.0;
-    for (int i = threadIdx.x; i < count; i += blockDim.x) part += logistic((eps[i] - mid) / kT);
+    for (int i = threadIdx.x; i < count; i += blockDim.x) {
+      const double fi = logistic((eps[i] - mid) / kT);
+      part += weights ? weights[(i / N) % nk] * fi : fi;
+    }
     const double cnt = s * block_sum(part, red);
     if (cnt > ne) hi = mid; else lo = mid;
   }
@@ -176,6 +194,47 @@ __global__ void gamma_kernel(double* __restrict__ Hp, const double* __restrict__
   Hp[off] = g;
 }
 
+// tmax[c][I][J] = largest |F_c| entry of the 128 x 128 block (I, J) for I <= J
+// (infinity when the block holds a NaN, so that it stays active).
+__global__ __launch_bounds__(256) void block_max_kernel(const double* __restrict__ F, int N,
+                                                       int ntb, double* __restrict__ tmax) {
+  __shared__ double red[4];
+  const int c = blockIdx.y;
+  const int I = blockIdx.x / ntb, J = blockIdx.x % ntb;
+  if (J < I) return;
+  double m = 0.0;
+  for (int idx = threadIdx.x; idx < kBlockEdge * kBlockEdge; idx += blockDim.x) {
+    const int i = I * kBlockEdge + idx / kBlockEdge, j = J * kBlockEdge + idx % kBlockEdge;
+    if (i < N && j < N) {
+      const double a = fabs(F[((size_t)c * N + i) * N + j]);
+      m = (a != a) ? INFINITY : fmax(m, a);
+    }
+  }
+  m = block_max(m, red);
+  if (threadIdx.x == 0) tmax[((size_t)c * ntb + I) * ntb + J] = m;
+}
+
+// active[c][I][J] = active[c][J][I] = (tmax of the block > tau * largest tmax);
+// every block is active when the largest is not finite.  One block of threads.
+__global__ __launch_bounds__(256) void block_mask_kernel(const double* __restrict__ tmax, int ntb,
+                                                        int nspin, double tau,
+                                                        unsigned char* __restrict__ active) {
+  __shared__ double red[4];
+  const int n = nspin * ntb * ntb;
+  double g = 0.0;
+  for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+    const int I = (idx / ntb) % ntb, J = idx % ntb;
+    if (J >= I) g = fmax(g, tmax[idx]);
+  }
+  g = block_max(g, red);
+  const bool all = !isfinite(g);
+  for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+    const int c = idx / (ntb * ntb), I = (idx / ntb) % ntb, J = idx % ntb;
+    const double m = tmax[((size_t)c * ntb + min(I, J)) * ntb + max(I, J)];
+    active[idx] = (all || m > tau * g) ? 1 : 0;
+  }
+}
+
 __global__ void check_finite_kernel(const double* __restrict__ x, int64_t n, int* status) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -189,8 +248,8 @@ hipError_t launch_fermi(lrdm_ctx* ctx, const double* eps, int N, int nspin, doub
                         double* F) {
   const int count = N * nspin;
   const double s = (nspin == 1) ? 2.0 : 1.0;
-  fermi_mu_kernel<<<1, kFermiThreads, 0, ctx->stream>>>(eps, count, s, kT, n_electrons, mu,
-                                                        ctx->dstatus);
+  fermi_mu_kernel<<<1, kFermiThreads, 0, ctx->stream>>>(eps, count, s, kT, n_electrons, nullptr,
+                                                        N, 1, mu, ctx->dstatus);
   LRDM_HIP(hipGetLastError());
   occupations_kernel<<<(count + 255) / 256, 256, 0, ctx->stream>>>(eps, count, kT, mu, f, omf,
                                                                    fprime);
@@ -202,6 +261,23 @@ hipError_t launch_fermi(lrdm_ctx* ctx, const double* eps, int N, int nspin, doub
     LRDM_HIP(hipGetLastError());
   }
   return hipSuccess;
+}
+
+hipError_t launch_fermi_bz(lrdm_ctx* ctx, const double* eps, int N, int nspin, int nk,
+                           const double* weights, double kT, double n_electrons, double* mu,
+                           double* f, double* omf, double* fprime, double* F) {
+  const int count = N * nspin * nk;
+  const double s = (nspin == 1) ? 2.0 : 1.0;
+  fermi_mu_kernel<<<1, kFermiThreads, 0, ctx->stream>>>(eps, count, s, kT, n_electrons, weights,
+                                                        N, nk, mu, ctx->dstatus);
+  LRDM_HIP(hipGetLastError());
+  occupations_kernel<<<(count + 255) / 256, 256, 0, ctx->stream>>>(eps, count, kT, mu, f, omf,
+                                                                   fprime);
+  LRDM_HIP(hipGetLastError());
+  dim3 blk(32, 8);
+  dim3 grd((N + 31) / 32, (N + 7) / 8, nspin * nk);
+  divided_diff_kernel<<<grd, blk, 0, ctx->stream>>>(eps, f, omf, N, kT, F);
+  return hipGetLastError();
 }
 
 hipError_t launch_recursive_multiplier(lrdm_ctx* ctx, const double* eps, const double* mu, int N,
@@ -219,6 +295,16 @@ hipError_t launch_gamma(lrdm_ctx* ctx, double* Hp, const double* F, const double
   dim3 blk(32, 8);
   dim3 grd((N + 31) / 32, (N + 7) / 8, r * nspin);
   gamma_kernel<<<grd, blk, 0, ctx->stream>>>(Hp, F, fprime, dmu, N, nspin);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_mask(lrdm_ctx* ctx, const double* F, int N, int nspin, double tau,
+                             double* tmax, unsigned char* active) {
+  const int ntb = (N + kBlockEdge - 1) / kBlockEdge;
+  dim3 grd((unsigned)(ntb * ntb), (unsigned)nspin);
+  block_max_kernel<<<grd, 256, 0, ctx->stream>>>(F, N, ntb, tmax);
+  LRDM_HIP(hipGetLastError());
+  block_mask_kernel<<<1, 256, 0, ctx->stream>>>(tmax, ntb, nspin, tau, active);
   return hipGetLastError();
 }
 

@@ -15,6 +15,7 @@
 //   A operand: lane l supplies A[l%16][l/16]   (row, k)
 //   B operand: lane l supplies B[l/16][l%16]   (k, col)
 //   D: lane l, register v holds D[4v + l/16][l%16].
+#include "blocks.h"
 #include "lrdm_internal.h"
 #include "xcd.h"
 
@@ -94,7 +95,7 @@ template <typename SA, typename SB>
 __global__ __launch_bounds__(256, 2) void tn_sym_f64_kernel(
     const SA* __restrict__ A, const SB* __restrict__ B, const double* __restrict__ w,
     int64_t w_stride, int N, int64_t M, int nspin, int ntb, int64_t kchunk, int nsplit, int batch,
-    double* __restrict__ part) {
+    const unsigned char* __restrict__ active, double* __restrict__ part) {
   __shared__ double As[KT * LDP];
   __shared__ double Bs[KT * LDP];
   __shared__ double Ws[KT];   // w over the current K-tile (1 when w is absent)
@@ -111,7 +112,8 @@ __global__ __launch_bounds__(256, 2) void tn_sym_f64_kernel(
   const SB* Bc = B + (int64_t)c * N * M;
   const double* wb = w ? w + (int64_t)b * w_stride : nullptr;
   const int64_t kbeg = (int64_t)split * kchunk;
-  const int64_t kend = min(M, kbeg + kchunk);
+  // an inactive block (blocks.h) keeps a zero partial tile
+  const int64_t kend = block_active(active, c, ntb, ti, tj) ? min(M, kbeg + kchunk) : kbeg;
 
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int wr = wid >> 1, wc = wid & 1;
@@ -235,7 +237,8 @@ struct RowLoad {
 // the directions of one point block run together on one XCD (xcd_map).
 __global__ __launch_bounds__(256, 2) void backproj_f64_kernel(
     const double* __restrict__ A, const double* __restrict__ G, int N, int64_t M, int nspin,
-    int batch, double scale, const double* __restrict__ sub, double* __restrict__ out) {
+    int batch, double scale, const double* __restrict__ sub,
+    const unsigned char* __restrict__ active, double* __restrict__ out) {
   __shared__ double Gs[KT * LDP];
   __shared__ double Ps[KT * LDP];
   __shared__ double red[4][64];
@@ -251,24 +254,33 @@ __global__ __launch_bounds__(256, 2) void backproj_f64_kernel(
   const int nib = (N + BT - 1) / BT;
   for (int ib = 0; ib < nib; ++ib) {
     const int i0 = ib * BT;
+    // K runs over j in [i0, N): the diagonal block once, blocks right of it twice
+    // (G symmetric), so only the upper block triangle is touched; inactive blocks
+    // (blocks.h) are skipped, and a row block with none active contributes nothing
+    const uint64_t bits = active_row_bits(active, c, nib, ib);
+    const int nk = active_ktiles(bits, N, KT);
+    if (nk == 0) continue;
     d4 acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
     RowLoad<double> lg, lp;
-    // K runs over j in [i0, N): the diagonal block once, blocks right of it twice
-    // (G symmetric), so only the upper block triangle is touched.
-    lg.load(Gb, N, N, N, i0, i0, 1.0);
-    lp.load(Ac, M, N, M, i0, p0, 1.0);
-    for (int j0 = i0; j0 < N; j0 += KT) {
+    {
+      int J;
+      const int j0 = active_ktile(bits, 0, KT, J);
+      lg.load(Gb, N, N, N, j0, i0, J > ib ? 2.0 : 1.0);
+      lp.load(Ac, M, N, M, j0, p0, 1.0);
+    }
+    for (int t = 0; t < nk; ++t) {
       __syncthreads();
       lg.store(Gs);
       lp.store(Ps);
       __syncthreads();
-      const int jn = j0 + KT;
-      if (jn < N) {
-        lg.load(Gb, N, N, N, jn, i0, (jn >= i0 + BT) ? 2.0 : 1.0);
+      if (t + 1 < nk) {
+        int J;
+        const int jn = active_ktile(bits, t + 1, KT, J);
+        lg.load(Gb, N, N, N, jn, i0, J > ib ? 2.0 : 1.0);
         lp.load(Ac, M, N, M, jn, p0, 1.0);
       }
 #pragma unroll
@@ -501,7 +513,7 @@ size_t tn_workspace_bytes(int N, int64_t M, int batch, lrdm_prec prec) {
 template <typename SA, typename SB>
 hipError_t launch_tn_sym_f64(lrdm_ctx* ctx, const SA* A, const SB* B, const double* w,
                              int64_t w_stride, int N, int64_t M, int nspin, int batch,
-                             double* H) {
+                             double* H, const unsigned char* active) {
   const int ntb = (N + BT - 1) / BT;
   const int ntiles = ntb * (ntb + 1) / 2;
   const int ns = tn_split_count(ctx, N, M, batch, TN_ARITH_F64, w != nullptr);
@@ -513,10 +525,10 @@ hipError_t launch_tn_sym_f64(lrdm_ctx* ctx, const SA* A, const SB* B, const doub
     ProfScope prof(ctx, w ? "proj" : "gram");
     if (B)
       tn_sym_f64_kernel<SA, SB><<<grd, 256, 0, ctx->stream>>>(A, B, w, w_stride, N, M, nspin, ntb,
-                                                               kchunk, ns, batch, part);
+                                                               kchunk, ns, batch, active, part);
     else
       tn_sym_f64_kernel<SA, SA><<<grd, 256, 0, ctx->stream>>>(A, A, w, w_stride, N, M, nspin, ntb,
-                                                               kchunk, ns, batch, part);
+                                                               kchunk, ns, batch, active, part);
     LRDM_HIP(hipGetLastError());
   }
   dim3 blk(32, 8);
@@ -526,28 +538,29 @@ hipError_t launch_tn_sym_f64(lrdm_ctx* ctx, const SA* A, const SB* B, const doub
 }
 template hipError_t launch_tn_sym_f64<double, double>(lrdm_ctx*, const double*, const double*,
                                                       const double*, int64_t, int, int64_t, int,
-                                                      int, double*);
+                                                      int, double*, const unsigned char*);
 template hipError_t launch_tn_sym_f64<float, float>(lrdm_ctx*, const float*, const float*,
                                                     const double*, int64_t, int, int64_t, int, int,
-                                                    double*);
+                                                    double*, const unsigned char*);
 template hipError_t launch_tn_sym_f64<float, double>(lrdm_ctx*, const float*, const double*,
                                                      const double*, int64_t, int, int64_t, int,
-                                                     int, double*);
+                                                     int, double*, const unsigned char*);
 
 template <>
 hipError_t launch_tn_sym<double>(lrdm_ctx* ctx, const double* A, const double* B,
                                  const double* w, int64_t w_stride, int N, int64_t M, int nspin,
-                                 int batch, lrdm_prec, double* H) {
-  return launch_tn_sym_f64<double, double>(ctx, A, B, w, w_stride, N, M, nspin, batch, H);
+                                 int batch, lrdm_prec, double* H, const unsigned char* active) {
+  return launch_tn_sym_f64<double, double>(ctx, A, B, w, w_stride, N, M, nspin, batch, H, active);
 }
 
 template <>
 hipError_t launch_backproj<double>(lrdm_ctx* ctx, const double* A, const double* G, int N,
                                    int64_t M, int nspin, int batch, lrdm_prec, double scale,
-                                   const double* sub, double* out) {
+                                   const double* sub, double* out, const unsigned char* active) {
   const unsigned grd = (unsigned)((M + BT - 1) / BT * batch);
   ProfScope prof(ctx, "backproj");
-  backproj_f64_kernel<<<grd, 256, 0, ctx->stream>>>(A, G, N, M, nspin, batch, scale, sub, out);
+  backproj_f64_kernel<<<grd, 256, 0, ctx->stream>>>(A, G, N, M, nspin, batch, scale, sub, active,
+                                                    out);
   return hipGetLastError();
 }
 

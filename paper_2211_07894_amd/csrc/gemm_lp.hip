@@ -25,6 +25,7 @@
 //   v_mfma_f32_16x16x4f32:      A lane l -> A[l%16][l/16], B lane l -> B[l/16][l%16]
 //   v_mfma_f32_16x16x32_bf16:   A lane l -> A[l%16][8(l/16)+e], B -> B[8(l/16)+e][l%16]
 //   both:                       D lane l, register v -> D[4(l/16) + v][l%16]
+#include "blocks.h"
 #include "lrdm_internal.h"
 #include "xcd.h"
 
@@ -534,7 +535,8 @@ template <Core C, bool W>
 __global__ __launch_bounds__(PT, 1) void tn_sym_pipe_kernel(
     const float* __restrict__ A, const float* __restrict__ B, const double* __restrict__ w,
     int64_t w_stride, int N, int64_t M, int nspin, int ntb, int64_t kchunk, int nsplit, int batch,
-    const float* __restrict__ zeros, double* __restrict__ part) {
+    const unsigned char* __restrict__ active, const float* __restrict__ zeros,
+    double* __restrict__ part) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_pipe[];
   constexpr int SB = 2 * TB + (W ? 1024 : 0);   // bytes of one stage
   const int ntiles = ntb * (ntb + 1) / 2;
@@ -549,7 +551,8 @@ __global__ __launch_bounds__(PT, 1) void tn_sym_pipe_kernel(
   const float* Bc = B + (int64_t)c * N * M;
   const double* wb = W ? w + (int64_t)b * w_stride : nullptr;
   const int64_t kbeg = (int64_t)sp * kchunk;
-  const int64_t kend = min(M, kbeg + kchunk);
+  // an inactive block (blocks.h) keeps a zero partial tile
+  const int64_t kend = block_active(active, c, ntb, ti, tj) ? min(M, kbeg + kchunk) : kbeg;
   const int nk = kbeg < kend ? (int)((kend - kbeg + KT - 1) / KT) : 0;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int wr = wid >> 1, wc = wid & 1;
@@ -599,7 +602,8 @@ template <Core C>
 __global__ __launch_bounds__(PT, 1) void backproj_pipe_kernel(
     const float* __restrict__ A, const float* __restrict__ AT, const float* __restrict__ Gf,
     int N, int64_t M, int ldk, int nspin, int batch, double scale, const double* __restrict__ sub,
-    const float* __restrict__ zeros, double* __restrict__ out) {
+    const unsigned char* __restrict__ active, const float* __restrict__ zeros,
+    double* __restrict__ out) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_pipe[];
   constexpr int SB = 2 * TB;
   double* red = reinterpret_cast<double*>(smem_pipe + NST * SB);   // [PW][64]
@@ -617,11 +621,15 @@ __global__ __launch_bounds__(PT, 1) void backproj_pipe_kernel(
   const int nib = (N + BT - 1) / BT;
   for (int ib = 0; ib < nib; ++ib) {
     const int i0 = ib * BT;
-    // j runs over [i0, N): the diagonal block once, blocks right of it twice
-    const int nk = (N - i0 + KT - 1) / KT;
+    // j runs over the active blocks (blocks.h) of [i0, N): the diagonal block
+    // once, blocks right of it twice
+    const uint64_t bits = active_row_bits(active, c, nib, ib);
+    const int nk = active_ktiles(bits, N, KT);
+    if (nk == 0) continue;
     auto issue = [&](int t) {
       unsigned char* st = smem_pipe + (t % NST) * SB;
-      const int64_t j0 = i0 + (int64_t)t * KT;
+      int J;
+      const int64_t j0 = active_ktile(bits, t, KT, J);
       const int64_t je = t < nk ? ldk : j0;
       dma_tile(Gb, ldk, N, i0, j0, je, zeros, st, wid, lane);
       dma_tile(ATc, ldk, (int)M, p0, j0, je, zeros, st + TB, wid, lane);
@@ -637,7 +645,9 @@ __global__ __launch_bounds__(PT, 1) void backproj_pipe_kernel(
       f.load(st, st + TB, wr, wc, lane);
       compiler_fence();
       issue(t + 2);
-      kt_step_pipe<C>(f, (t * KT >= BT) ? 2.0 : 1.0, acc);
+      int J;
+      active_ktile(bits, t, KT, J);
+      kt_step_pipe<C>(f, J > ib ? 2.0 : 1.0, acc);
     }
     wait_stage<0>();   // the copies past the end land before the ring is reused
     // row-dot with A[i][p]: all 32 reads issued first (indices clamped into
@@ -855,7 +865,8 @@ __device__ inline f4 mfma6(const bf8 (&a)[3], const bf8 (&b)[3], f4 c) {
 __global__ __launch_bounds__(PT, 1) void tn_sym_p3_kernel(
     const float* __restrict__ A, const __bf16* __restrict__ P3, const double* __restrict__ w,
     int64_t w_stride, int N, int64_t M, int nspin, int ntb, int64_t kchunk, int nsplit, int batch,
-    const float* __restrict__ zeros, double* __restrict__ part) {
+    const unsigned char* __restrict__ active, const float* __restrict__ zeros,
+    double* __restrict__ part) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_pipe[];
   constexpr int SB = TB + 3 * PB + 1024;   // A (FP32), B pieces, weights
   const int ntiles = ntb * (ntb + 1) / 2;
@@ -872,7 +883,8 @@ __global__ __launch_bounds__(PT, 1) void tn_sym_p3_kernel(
   const __bf16* Pc = P3 + (int64_t)c * 3 * N * M;
   const double* wb = w + (int64_t)b * w_stride;
   const int64_t kbeg = (int64_t)sp * kchunk;
-  const int64_t kend = min(M, kbeg + kchunk);
+  // an inactive block (blocks.h) keeps a zero partial tile
+  const int64_t kend = block_active(active, c, ntb, ti, tj) ? min(M, kbeg + kchunk) : kbeg;
   const int nk = kbeg < kend ? (int)((kend - kbeg + KT - 1) / KT) : 0;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int wr = wid >> 1, wc = wid & 1;
@@ -956,7 +968,8 @@ __global__ __launch_bounds__(PT, 1) void tn_sym_p3_kernel(
 __global__ __launch_bounds__(PT, 1) void backproj_p3_kernel(
     const float* __restrict__ A, const __bf16* __restrict__ PT3, const __bf16* __restrict__ G3,
     int N, int64_t M, int ldk, int nspin, int batch, double scale, const double* __restrict__ sub,
-    const float* __restrict__ zeros, double* __restrict__ out) {
+    const unsigned char* __restrict__ active, const float* __restrict__ zeros,
+    double* __restrict__ out) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_pipe[];
   constexpr int SB = 6 * PB;
   double* red = reinterpret_cast<double*>(smem_pipe + NST * SB);   // [PW][64]
@@ -977,10 +990,14 @@ __global__ __launch_bounds__(PT, 1) void backproj_p3_kernel(
   const int nib = (N + BT - 1) / BT;
   for (int ib = 0; ib < nib; ++ib) {
     const int i0 = ib * BT;
-    const int nk = (N - i0 + KT - 1) / KT;
+    // j runs over the active blocks (blocks.h) of [i0, N), kFlush K-tiles each
+    const uint64_t bits = active_row_bits(active, c, nib, ib);
+    const int nk = active_ktiles(bits, N, KT);
+    if (nk == 0) continue;
     auto issue = [&](int t) {
       unsigned char* st = smem_pipe + (t % NST) * SB;
-      const int64_t j0 = i0 + (int64_t)t * KT;
+      int J;
+      const int64_t j0 = active_ktile(bits, t, KT, J);
       const int64_t je = t < nk ? ldk : j0;
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
@@ -1017,9 +1034,11 @@ __global__ __launch_bounds__(PT, 1) void backproj_p3_kernel(
 #pragma unroll
           for (int j = 0; j < 4; ++j) cc[i][j] = mfma6(pa[i], pb[j], cc[i][j]);
       }
-      // a flush group of kFlush K-tiles (kFlush KT = BT) lies wholly on or off
-      // the diagonal block
-      flush_pipe(cc, t0 * KT >= BT ? 2.0 : 1.0, acc);
+      // a flush group of kFlush K-tiles (kFlush KT = BT) is one block, on or off
+      // the diagonal
+      int J;
+      active_ktile(bits, t0, KT, J);
+      flush_pipe(cc, J > ib ? 2.0 : 1.0, acc);
     }
     wait_stage<0>();
     float av[2][4][4];
@@ -1186,9 +1205,9 @@ size_t tn_split_bytes(int N, int64_t M, lrdm_prec prec) {
 template <>
 hipError_t launch_tn_sym<float>(lrdm_ctx* ctx, const float* A, const float* B, const double* w,
                                 int64_t w_stride, int N, int64_t M, int nspin, int batch,
-                                lrdm_prec prec, double* H) {
+                                lrdm_prec prec, double* H, const unsigned char* active) {
   if (prec == LRDM_FP64)
-    return launch_tn_sym_f64<float, float>(ctx, A, B, w, w_stride, N, M, nspin, batch, H);
+    return launch_tn_sym_f64<float, float>(ctx, A, B, w, w_stride, N, M, nspin, batch, H, active);
   const int ntb = (N + BT - 1) / BT;
   const int ntiles = ntb * (ntb + 1) / 2;
   const int ns = tn_split_count(ctx, N, M, batch,
@@ -1224,7 +1243,8 @@ hipError_t launch_tn_sym<float>(lrdm_ctx* ctx, const float* A, const float* B, c
     {
       ProfScope prof(ctx, "proj");
       tn_sym_p3_kernel<<<grd, PT, smem, ctx->stream>>>(A, P3, w, w_stride, N, M, nspin, ntb,
-                                                       kchunk, ns, batch, ctx->zeros, part);
+                                                       kchunk, ns, batch, active, ctx->zeros,
+                                                       part);
       LRDM_HIP(hipGetLastError());
     }
     dim3 blk(32, 8);
@@ -1237,7 +1257,7 @@ hipError_t launch_tn_sym<float>(lrdm_ctx* ctx, const float* A, const float* B, c
     LRDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, smem));
     kernel<<<grd, PT, smem, ctx->stream>>>(A, B, w, w_stride, N, M, nspin, ntb, kchunk, ns, batch,
-                                           ctx->zeros, part);
+                                           active, ctx->zeros, part);
     return hipGetLastError();
   };
   auto run_staged = [&](auto kernel) -> hipError_t {
@@ -1266,7 +1286,7 @@ hipError_t launch_tn_sym<float>(lrdm_ctx* ctx, const float* A, const float* B, c
 template <>
 hipError_t launch_backproj<float>(lrdm_ctx* ctx, const float* A, const double* G, int N,
                                   int64_t M, int nspin, int batch, lrdm_prec prec, double scale,
-                                  const double* sub, double* out) {
+                                  const double* sub, double* out, const unsigned char* active) {
   const int ldk = pad_k(N);
   const unsigned grd = (unsigned)((M + BT - 1) / BT * batch);
   dim3 gt((unsigned)((M + 63) / 64), (unsigned)(ldk / 64 + (ldk % 64 ? 1 : 0)), nspin);
@@ -1292,7 +1312,7 @@ hipError_t launch_backproj<float>(lrdm_ctx* ctx, const float* A, const double* G
                                  hipFuncAttributeMaxDynamicSharedMemorySize, smem));
     ProfScope prof(ctx, "backproj");
     backproj_p3_kernel<<<grd, PT, smem, ctx->stream>>>(A, PT3, G3, N, M, ldk, nspin, batch, scale,
-                                                       sub, ctx->zeros, out);
+                                                       sub, active, ctx->zeros, out);
     return hipGetLastError();
   }
   float* Gf = static_cast<float*>(ws_take(ctx, (size_t)batch * N * ldk * sizeof(float)));
@@ -1307,7 +1327,7 @@ hipError_t launch_backproj<float>(lrdm_ctx* ctx, const float* A, const double* G
                                hipFuncAttributeMaxDynamicSharedMemorySize, smem));
   ProfScope prof(ctx, "backproj");
   backproj_pipe_kernel<Core::F32><<<grd, PT, smem, ctx->stream>>>(
-      A, AT, Gf, N, M, ldk, nspin, batch, scale, sub, ctx->zeros, out);
+      A, AT, Gf, N, M, ldk, nspin, batch, scale, sub, active, ctx->zeros, out);
   return hipGetLastError();
 }
 

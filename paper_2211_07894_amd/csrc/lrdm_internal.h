@@ -41,6 +41,7 @@ struct lrdm_ctx {
   int checks = 0;
   int fermi_depth = 0;       // 0: exact divided differences; T > 0: recursive expansion
   int eigh_max_sweeps = 40;  // block Jacobi sweeps before the eigensolver gives up
+  double block_tau = 1e-14;  // response blocks with max |F| below tau max |F| are skipped
   lrdm_psi_pieces pieces;
   // K-split counts of the projection contraction chosen by lrdm_autotune, keyed by
   // (N, M, batch, arithmetic, weighted)
@@ -163,6 +164,29 @@ size_t rotate_bf16x3_bytes(int N, int64_t M);
 hipError_t launch_rotate_bf16x3(lrdm_ctx* ctx, const double* Wt, const float* B, float* Out,
                                 int N, int64_t M, bool upper);
 
+// launch_fermi with Brillouin-zone sampling: eps [nspin][nk][N], weights [nk]
+// (device); mu from the zone-averaged count, then f, 1 - f, f' and the divided
+// differences F [nspin][nk][N][N] of every (channel, k).
+hipError_t launch_fermi_bz(lrdm_ctx* ctx, const double* eps, int N, int nspin, int nk,
+                           const double* weights, double kT, double n_electrons, double* mu,
+                           double* f, double* omf, double* fprime, double* F);
+
+// The zone-sampled response's pieces (kpoints.hip).  Psi of channel c at k is
+// stored as the 2N real rows [Re psi_1..N; Im psi_1..N] ("realified"), so that
+// H2 = Phi^T diag(dV) Phi and the back-projection of G2 are the real kernels'
+// products with 2N states.
+// W[(q nspin + c) nk + k] = dV[q nspin + c] (M points each).
+hipError_t launch_expand_dv(lrdm_ctx* ctx, const double* dV, int r, int nspin, int nk, int64_t M,
+                            double* W);
+// mu'[q] of the zone-averaged traceless condition from H2 [r][nspin][nk][2N][2N],
+// then G2 = w_k [[Gr, Gi], [-Gi, Gr]] in place over H2, with
+// Gr = F o (H2_00 + H2_11) - mu' diag(f'), Gi = F o (H2_01 - H2_10).
+hipError_t launch_gamma_bz(lrdm_ctx* ctx, double* H2, const double* F, const double* fprime,
+                           const double* weights, int N, int nspin, int nk, int r, double* dmu);
+// drho[q nspin + c][p] = sum_k part[(q nspin + c) nk + k][p].
+hipError_t launch_sum_k(lrdm_ctx* ctx, const double* part, int r, int nspin, int nk, int64_t M,
+                        double* drho);
+
 // The recursive expansion's multiplier M [nspin][N][N] and its diagonal [nspin][N]
 // (depth T, mu on the device).
 hipError_t launch_recursive_multiplier(lrdm_ctx* ctx, const double* eps, const double* mu, int N,
@@ -197,25 +221,33 @@ enum { TN_ARITH_F64 = 0, TN_ARITH_F32 = 1, TN_ARITH_BF16X3 = 2 };
 int tn_split_count(const lrdm_ctx* ctx, int N, int64_t M, int batch, int arith, bool weighted);
 // T is the storage type of A and B; prec selects the arithmetic (LRDM_FP64: FP64
 // matrix cores on either storage type; LRDM_FP32 / LRDM_BF16X3: FP32 storage only).
+// active (blocks.h, may be NULL): the tiles of inactive blocks are left at zero.
 template <typename T>
 hipError_t launch_tn_sym(lrdm_ctx* ctx, const T* A, const T* B, const double* w,
                          int64_t w_stride, int N, int64_t M, int nspin, int batch, lrdm_prec prec,
-                         double* H);
+                         double* H, const unsigned char* active = nullptr);
 template <typename SA, typename SB>
 hipError_t launch_tn_sym_f64(lrdm_ctx* ctx, const SA* A, const SB* B, const double* w,
-                             int64_t w_stride, int N, int64_t M, int nspin, int batch, double* H);
+                             int64_t w_stride, int N, int64_t M, int nspin, int batch, double* H,
+                             const unsigned char* active = nullptr);
+
+// The response's block mask (blocks.h): active [nspin][ntb][ntb] from the
+// multiplier F [nspin][N][N]; tmax: nspin * ntb * ntb doubles of scratch.
+hipError_t launch_block_mask(lrdm_ctx* ctx, const double* F, int N, int nspin, double tau,
+                             double* tmax, unsigned char* active);
 
 // dmu[k] and Gamma[k][c] = F[c] o Hp[k][c] - dmu[k] diag(fprime[c]), in place over Hp.
 hipError_t launch_gamma(lrdm_ctx* ctx, double* Hp, const double* F, const double* fprime, int N,
                         int nspin, int r, double* dmu);
 
 // out[b][p] = scale * sum_ij A_c[i][p] G[b][i][j] A_c[j][p] (- sub[b][p] when sub != nullptr),
-// c = b % nspin, G symmetric.
+// c = b % nspin, G symmetric; the blocks of G that `active` (blocks.h, may be
+// NULL) marks inactive are left out.
 size_t backproj_workspace_bytes(int N, int64_t M, int nspin, int batch, lrdm_prec prec);
 template <typename T>
 hipError_t launch_backproj(lrdm_ctx* ctx, const T* A, const double* G, int N, int64_t M, int nspin,
                            int batch, lrdm_prec prec, double scale, const double* sub,
-                           double* out);
+                           double* out, const unsigned char* active = nullptr);
 
 // Out[i][p] = sum_j Wt[j][i] B[j][p]  (Out = Wt^T B), Wt double N x N, FP64
 // arithmetic for either storage type of B and Out.  upper: Wt is upper triangular

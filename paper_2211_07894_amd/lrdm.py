@@ -32,7 +32,7 @@ EXPORTED = [
     "density_response_backward", "density_response_batched",
     "lrdm_density", "lrdm_effective_potential", "lrdm_lowrank_step", "lrdm_set_fermi_expansion",
     "lrdm_lda_xc", "lrdm_residual_derivative_xc", "lrdm_autotune",
-    "lrdm_set_eigensolver_sweeps",
+    "lrdm_set_eigensolver_sweeps", "lrdm_set_response_block_skip", "density_response_bz",
 ]
 
 
@@ -122,6 +122,7 @@ def library() -> ctypes.CDLL:
                 "lrdm_set_checks": [vp, ctypes.c_int],
                 "lrdm_set_fermi_expansion": [vp, i32],
                 "lrdm_set_eigensolver_sweeps": [vp, i32],
+                "lrdm_set_response_block_skip": [vp, f64],
                 "lrdm_workspace_bytes": [vp],
                 "lrdm_profile": [vp, ctypes.c_int],
                 "lrdm_profile_read": [vp, ctypes.c_char_p, ctypes.POINTER(f64), ctypes.POINTER(ctypes.c_int64)],
@@ -133,6 +134,8 @@ def library() -> ctypes.CDLL:
                 "chfsi_filter": [vp, G, vp, vp, vp, i32, ctypes.c_int, i32, f64, f64, f64],
                 "subspace_rayleigh_ritz": [vp, G, vp, vp, i32, ctypes.c_int, vp],
                 "density_response": [vp, G, vp, vp, i32, O, vp, i32, ctypes.c_int, vp, vp, vp],
+                "density_response_bz": [vp, G, vp, vp, vp, i32, i32, O, vp, i32, ctypes.c_int,
+                                        vp, vp, vp],
                 "lrdm_residual_derivative": [vp, G, vp, vp, i32, O, vp, i32, ctypes.c_int, vp],
                 "density_response_backward": [vp, G, vp, vp, i32, O, vp, i32, ctypes.c_int, vp,
                                               vp, vp, vp],
@@ -183,6 +186,11 @@ class Context:
         """Sweep limit of the subspace eigensolver (default 40); beyond it
         subspace_rayleigh_ritz raises LRDM_ENOTCONV."""
         self.check(self.lib.lrdm_set_eigensolver_sweeps(self.ptr, int(max_sweeps)))
+
+    def set_response_block_skip(self, tau: float):
+        """Drop the response blocks whose largest Fermi multiplier entry is at
+        most tau times the largest (0: form every block; default 1e-14)."""
+        self.check(self.lib.lrdm_set_response_block_skip(self.ptr, float(tau)))
 
     def set_checks(self, level: int):
         self.check(self.lib.lrdm_set_checks(self.ptr, int(level)))
@@ -359,6 +367,31 @@ def density_response(grid: Grid, Psi, eps, occ: Occupation, dV, prec="fp64", out
         ctx.ptr, ctypes.byref(g), _ptr(Psi, "Psi", _block_dtype(prec), ns * N * grid.M),
         _ptr(eps, "eps", torch.float64, ns * N), N, ctypes.byref(o),
         _ptr(dV, "dV", torch.float64, r * ns * grid.M), r, _prec(prec),
+        _ptr(drho, "drho", torch.float64, r * ns * grid.M), _ptr(mu, "mu", torch.float64, 1),
+        _ptr(dmu, "dmu", torch.float64, r)))
+    return drho, mu, dmu
+
+
+def density_response_bz(grid: Grid, Psi, eps, weights, occ: Occupation, dV, prec="fp64",
+                        out=None, mu=None, dmu=None):
+    """Zone-sampled response (density_response_bz): Psi [nspin][nk][2][N][M] (real
+    then imaginary parts of each k-point's states), eps [nspin][nk][N], weights
+    [nk], dV [r][nspin][M]; returns (drho [r][nspin][M], mu [1], dmu [r])."""
+    ns = occ.nspin
+    nk = weights.numel()
+    N = eps.numel() // (ns * nk)
+    r = dV.numel() // (ns * grid.M)
+    dev = Psi.device
+    drho = torch.empty((r, ns) + grid.shape, dtype=torch.float64, device=dev) if out is None else out
+    mu = torch.empty(1, dtype=torch.float64, device=dev) if mu is None else mu
+    dmu = torch.empty(r, dtype=torch.float64, device=dev) if dmu is None else dmu
+    ctx = context(dev.index)
+    g = grid.c()
+    o = occ.c()
+    ctx.check(ctx.lib.density_response_bz(
+        ctx.ptr, ctypes.byref(g), _ptr(Psi, "Psi", _block_dtype(prec), ns * nk * 2 * N * grid.M),
+        _ptr(eps, "eps", torch.float64, ns * nk * N), _ptr(weights, "weights", torch.float64, nk),
+        N, nk, ctypes.byref(o), _ptr(dV, "dV", torch.float64, r * ns * grid.M), r, _prec(prec),
         _ptr(drho, "drho", torch.float64, r * ns * grid.M), _ptr(mu, "mu", torch.float64, 1),
         _ptr(dmu, "dmu", torch.float64, r)))
     return drho, mu, dmu

@@ -142,6 +142,62 @@ void scenario_response(lrdm_ctx* ctx, lrdm_grid g, int N, int nspin, int r,
         ctx, "fermi_occupations");
 }
 
+// A spectrum with deep occupied and high empty states, so that the response's
+// block mask drops blocks: the result with the default threshold against every
+// block formed (threshold 0).
+void scenario_block_skip(lrdm_ctx* ctx, lrdm_grid g, int N, int nspin, int r, lrdm_prec prec) {
+  const int64_t M = (int64_t)g.n[0] * g.n[1] * g.n[2];
+  std::vector<double> Psi0;
+  for (int c = 0; c < nspin; ++c) {
+    auto P = orthonormal(N, M, 21 + c);
+    Psi0.insert(Psi0.end(), P.begin(), P.end());
+  }
+  Block Psi(Psi0, prec);
+  std::vector<double> eps((size_t)nspin * N);
+  for (int c = 0; c < nspin; ++c)
+    for (int i = 0; i < N; ++i) eps[(size_t)c * N + i] = -3.0 + 4.0 * i / N + 0.001 * c;
+  lrdm_occ occ{nspin, 0.005, (nspin == 1 ? 0.8 : 0.4 * nspin) * N};
+  auto dV = randv((size_t)r * nspin * M, 6);
+  std::vector<double> a(dV.size()), b(dV.size()), mu(1), dmu(r);
+  char name[128];
+  std::snprintf(name, sizeof name, "density_response %s block skip N=%d nspin=%d r=%d",
+                prec_name(prec), N, nspin, r);
+  check(density_response(ctx, &g, Psi.data(), eps.data(), N, &occ, dV.data(), r, prec, a.data(),
+                         mu.data(), dmu.data()), ctx, name);
+  check(lrdm_set_response_block_skip(ctx, 0.0), ctx, "block skip off");
+  check(density_response(ctx, &g, Psi.data(), eps.data(), N, &occ, dV.data(), r, prec, b.data(),
+                         mu.data(), dmu.data()), ctx, "density_response, every block");
+  check(lrdm_set_response_block_skip(ctx, 1e-14), ctx, "block skip on");
+  double num = 0, den = 0;
+  for (size_t i = 0; i < a.size(); ++i) {
+    num += (a[i] - b[i]) * (a[i] - b[i]);
+    den += b[i] * b[i];
+  }
+  const double err = std::sqrt(num / den);
+  std::printf("     %s block skip vs every block: rel diff %.2e\n", prec_name(prec), err);
+  if (!finite(a) || !(err < (prec == LRDM_FP64 ? 1e-12 : 1e-6))) ++failures;
+}
+
+// Zone-sampled response: random realified blocks, unequal weights (bounds and
+// finiteness; the numbers are checked against the oracle on the GPU).
+void scenario_response_bz(lrdm_ctx* ctx, lrdm_grid g, int N, int nk, int nspin, int r,
+                          lrdm_prec prec) {
+  const int64_t M = (int64_t)g.n[0] * g.n[1] * g.n[2];
+  Block Psi(randv((size_t)nspin * nk * 2 * N * M, 31, 0.05), prec);
+  std::vector<double> eps((size_t)nspin * nk * N), w(nk);
+  for (size_t i = 0; i < eps.size(); ++i) eps[i] = -1.0 + 1.5 * (double)(i % N) / N + 0.001 * (i / N);
+  for (int k = 0; k < nk; ++k) w[k] = (1.0 + k) / (nk * (nk + 1) / 2.0);
+  lrdm_occ occ{nspin, 0.02, 0.8 * N};
+  auto dV = randv((size_t)r * nspin * M, 32);
+  std::vector<double> drho((size_t)r * nspin * M), mu(1), dmu(r);
+  char name[128];
+  std::snprintf(name, sizeof name, "density_response_bz %s N=%d nk=%d nspin=%d r=%d",
+                prec_name(prec), N, nk, nspin, r);
+  check(density_response_bz(ctx, &g, Psi.data(), eps.data(), w.data(), N, nk, &occ, dV.data(), r,
+                            prec, drho.data(), mu.data(), dmu.data()), ctx, name);
+  if (!finite(drho)) { std::printf("FAIL non-finite drho\n"); ++failures; }
+}
+
 void scenario_chfsi(lrdm_ctx* ctx, lrdm_grid g, int N, int degree, lrdm_prec prec = LRDM_FP64) {
   const int64_t M = (int64_t)g.n[0] * g.n[1] * g.n[2];
   auto V = randv((size_t)M, 3, 0.5);
@@ -442,6 +498,16 @@ int main(int argc, char** argv) {
   if (which == "all" || which == "tune") {
     scenario_autotune(ctx, grid(20, 18, 13, 0.4), 150, 1, 3, LRDM_FP64);
     scenario_autotune(ctx, grid(16, 16, 12, 0.4), 130, 2, 2, LRDM_BF16X3);
+  }
+  if (which == "all" || which == "skip") {
+    scenario_block_skip(ctx, grid(9, 8, 7, 0.5), 400, 1, 2, LRDM_FP64);
+    scenario_block_skip(ctx, grid(8, 8, 8, 0.5), 400, 2, 2, LRDM_FP32);
+    scenario_block_skip(ctx, grid(8, 8, 8, 0.5), 400, 1, 3, LRDM_BF16X3);
+  }
+  if (which == "all" || which == "bz") {
+    scenario_response_bz(ctx, grid(9, 8, 7, 0.5), 70, 2, 1, 2, LRDM_FP64);
+    scenario_response_bz(ctx, grid(9, 8, 7, 0.5), 70, 3, 2, 1, LRDM_FP32);
+    scenario_response_bz(ctx, grid(8, 8, 8, 0.5), 70, 2, 1, 2, LRDM_BF16X3);
   }
   if (which == "all" || which == "full") scenario_full_n(ctx);
   check(lrdm_destroy(ctx), nullptr, "lrdm_destroy");

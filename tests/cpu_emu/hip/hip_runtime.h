@@ -212,6 +212,9 @@ inline void global_load_lds(const void* src, void* base, unsigned size) {
 #define __builtin_amdgcn_mfma_f64_16x16x4f64 lrdm_emu::mfma_f64_16x16x4
 #define __builtin_amdgcn_mfma_f32_16x16x4f32 lrdm_emu::mfma_f32_16x16x4
 #define __builtin_amdgcn_mfma_f32_16x16x32_bf16 lrdm_emu::mfma_f32_16x16x32_bf16
+// instruction-scheduling hints: nothing to do on the CPU
+#define __builtin_amdgcn_sched_group_barrier(mask, count, id) ((void)0)
+#define __builtin_amdgcn_sched_barrier(mask) ((void)0)
 
 inline void __syncthreads() { lrdm_emu::yield_wait(1); }
 template <typename T>

@@ -180,3 +180,7 @@ def test_autotune_validation(lib):
 
 def test_eigensolver_sweeps_needs_a_context(lib):
     assert lib.lrdm_set_eigensolver_sweeps(None, 5) == -1 and "ctx is NULL" in _err(lib)
+
+
+def test_block_skip_needs_a_context(lib):
+    assert lib.lrdm_set_response_block_skip(None, 1e-14) == -1 and "ctx is NULL" in _err(lib)

@@ -314,3 +314,53 @@ def test_unsupported_and_invalid_are_errors():
         L.chfsi_filter(g, V, X, 3, 1.0, 0.5, -1.0)      # a > b
     with pytest.raises(L.LrdmError):
         L.chfsi_filter(g, V, X, 3, 1.0, 2.0, -1.0, out=X)  # X aliases Y
+
+
+# ------------------------------------------------------------------ response blocks left out
+def _skip_case(nspin):
+    """N = 400 (four 128-blocks, ragged) on a ragged grid: a spectrum with deep
+    occupied and high empty states at kT 0.005, so that several blocks of the
+    Fermi multiplier are below 1e-14 of its largest entry."""
+    g = O.Grid((20, 18, 13), (8.0, 7.2, 5.2))
+    N = 400
+    rng = np.random.default_rng(41)
+    Q, _ = np.linalg.qr(rng.standard_normal((g.M, N)))
+    Psi = np.stack([Q.T.reshape((N,) + g.shape)] * nspin)
+    eps = np.stack([-3.0 + 4.0 * np.arange(N) / N + 0.001 * c for c in range(nspin)])
+    ne = 0.8 * N if nspin == 1 else 0.4 * nspin * N
+    dV = rng.standard_normal((3, nspin) + g.shape)
+    return g, Psi, eps, ne, 0.005, dV
+
+
+@pytest.mark.parametrize("nspin", [1, 2])
+@pytest.mark.parametrize("prec,bound", [("fp64", 1e-10), ("fp32", 1e-5), ("bf16x3", 1e-6)])
+def test_density_response_block_skip(nspin, prec, bound):
+    """With the default threshold the blocks whose multiplier is below 1e-14 of
+    its largest entry are left out: the oracle (every block) is still met within
+    each form's bound, and the FP64 form moves by less than 1e-12 against
+    forming every block."""
+    g, Psi, eps, ne, kT, dV = _skip_case(nspin)
+    mu_o, _ = O.fermi_level(eps, ne, kT, nspin)
+    Fs = [O.divided_differences(eps[c], mu_o, kT) for c in range(nspin)]
+    Fmax = max(np.abs(F).max() for F in Fs)
+    dropped = sum(np.abs(F[128 * I:128 * I + 128, 128 * J:128 * J + 128]).max() <= 1e-14 * Fmax
+                  for F in Fs for I in range(4) for J in range(I, 4))
+    assert dropped >= 3                       # the case exercises the skipping
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    Pd = to_dev(Psi, dt)
+    occ = L.Occupation(nspin, kT, ne)
+    drho, _, _ = L.density_response(_grid(g), Pd, to_dev(eps), occ, to_dev(dV), prec=prec)
+    ref, _, _ = O.density_response(to_host(Pd), eps, g, ne, kT, dV, nspin)
+    err = rel(to_host(drho), ref)
+    ctx = L.context()
+    ctx.set_response_block_skip(0.0)
+    try:
+        full, _, _ = L.density_response(_grid(g), Pd, to_dev(eps), occ, to_dev(dV), prec=prec)
+    finally:
+        ctx.set_response_block_skip(1e-14)
+    diff = rel(to_host(drho), to_host(full))
+    print(f"{prec} nspin {nspin}: {dropped} blocks dropped, err vs oracle {err:.2e}, "
+          f"vs every block {diff:.2e}")
+    assert err < bound
+    if prec == "fp64":
+        assert diff < 1e-12
