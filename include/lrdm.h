@@ -270,6 +270,7 @@ lrdm_status density_response_bz(lrdm_ctx* ctx, const lrdm_grid* grid, const void
                                 const lrdm_occ* occ, const double* dV, int32_t r, lrdm_prec prec,
                                 double* drho, double* mu, double* dmu);
 
+
 /* Gateaux derivative of the SCF residual along u_k (Eq. (7)) with
  * J = chi0 K - I (Eq. (3)) and K = K_c: every channel sees
  * dV_k = K_c (sum_sigma u_k,sigma); t_k = drho[dV_k] - u_k.

@@ -577,12 +577,20 @@ hipError_t run_backward(lrdm_ctx* ctx, const Grid3& g, const T* Psi, const doubl
   double* gs = static_cast<double*>(ws_take(ctx, (size_t)batch * g.M * sizeof(double)));
   const double c = ((ns == 1) ? 2.0 : 1.0) / g.dv;
   LRDM_HIP(launch_fermi(ctx, eps, N, ns, occ->kT, occ->n_electrons, mu, f, omf, fp, F));
+  // the forward's block mask (blocks.h): the adjoint is that of the same map
+  unsigned char* active = nullptr;
+  if (ctx->block_tau > 0.0 && N > 128) {
+    const size_t ntb = (size_t)(N + 127) / 128;
+    double* tmax = static_cast<double*>(ws_take(ctx, ns * ntb * ntb * sizeof(double)));
+    active = static_cast<unsigned char*>(ws_take(ctx, ns * ntb * ntb));
+    LRDM_HIP(launch_block_mask(ctx, F, N, ns, ctx->block_tau, tmax, active));
+  }
   const size_t mark = ctx->ws_top;
   // H' and A = (s/dv) Psi diag(g) Psi^T (recomputed; nothing of the forward call is kept)
-  LRDM_HIP(launch_tn_sym<T>(ctx, Psi, nullptr, dV, g.M, N, g.M, ns, batch, prec, Hp));
+  LRDM_HIP(launch_tn_sym<T>(ctx, Psi, nullptr, dV, g.M, N, g.M, ns, batch, prec, Hp, active));
   ctx->ws_top = mark;
   LRDM_HIP(launch_scale(ctx, gd, c, (int64_t)batch * g.M, gs));
-  LRDM_HIP(launch_tn_sym<T>(ctx, Psi, nullptr, gs, g.M, N, g.M, ns, batch, prec, A));
+  LRDM_HIP(launch_tn_sym<T>(ctx, Psi, nullptr, gs, g.M, N, g.M, ns, batch, prec, A, active));
   ctx->ws_top = mark;
   // Gamma and dH' = F o A - nu diag(f'): the same map applied to copies
   LRDM_HIP(hipMemcpyAsync(Gm, Hp, mat, hipMemcpyDeviceToDevice, ctx->stream));
@@ -590,10 +598,12 @@ hipError_t run_backward(lrdm_ctx* ctx, const Grid3& g, const T* Psi, const doubl
   LRDM_HIP(hipMemcpyAsync(dH, A, mat, hipMemcpyDeviceToDevice, ctx->stream));
   LRDM_HIP(launch_gamma(ctx, dH, F, fp, N, ns, r, nu));
   if (g_dV) {
-    LRDM_HIP(launch_backproj<T>(ctx, Psi, dH, N, g.M, ns, batch, prec, 1.0, nullptr, g_dV));
+    LRDM_HIP(launch_backproj<T>(ctx, Psi, dH, N, g.M, ns, batch, prec, 1.0, nullptr, g_dV,
+                                active));
     ctx->ws_top = mark;
   }
-  if (g_Psi) LRDM_HIP(launch_adj_psi<T>(ctx, Gm, gs, dH, dV, r, Psi, N, g.M, ns, 2.0, g_Psi));
+  if (g_Psi)
+    LRDM_HIP(launch_adj_psi<T>(ctx, Gm, gs, dH, dV, r, Psi, N, g.M, ns, 2.0, g_Psi, active));
   if (g_eps)
     LRDM_HIP(launch_adj_eps(ctx, A, Hp, eps, F, f, omf, fp, dmu, nu, N, ns, r, occ->kT, part,
                             g_eps));
@@ -606,9 +616,11 @@ hipError_t run_backward(lrdm_ctx* ctx, const Grid3& g, const T* Psi, const doubl
 
 size_t backward_bytes(int N, int64_t M, int r, int ns, lrdm_prec prec) {
   const int batch = r * ns;
-  const size_t scratch = std::max(tn_bytes(N, M, batch, prec),
-                                  backproj_workspace_bytes(N, M, ns, batch, prec));
+  const size_t scratch = std::max({tn_bytes(N, M, batch, prec),
+                                   backproj_workspace_bytes(N, M, ns, batch, prec),
+                                   adj_psi_workspace_bytes(N, M, ns, r, prec != LRDM_FP64)});
   return ws_align(8) + 2 * ws_align((size_t)r * 8) + 4 * ws_align((size_t)ns * N * 8) +
+         block_mask_bytes(N, ns) +
          ws_align((size_t)ns * N * N * 8) + 4 * ws_align((size_t)batch * N * N * 8) +
          ws_align((size_t)batch * M * 8) + ws_align(scratch) + 4096;
 }

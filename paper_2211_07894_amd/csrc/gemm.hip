@@ -15,6 +15,8 @@
 //   A operand: lane l supplies A[l%16][l/16]   (row, k)
 //   B operand: lane l supplies B[l/16][l%16]   (k, col)
 //   D: lane l, register v holds D[4v + l/16][l%16].
+#include <algorithm>
+
 #include "blocks.h"
 #include "lrdm_internal.h"
 #include "xcd.h"
@@ -577,21 +579,16 @@ template hipError_t launch_nn_f64<double>(lrdm_ctx*, const double*, const double
 template hipError_t launch_nn_f64<float>(lrdm_ctx*, const double*, const float*, float*, int,
                                          int64_t, bool);
 
-template <typename T>
-hipError_t launch_adj_psi(lrdm_ctx* ctx, const double* X1, const double* w1, const double* X2,
-                          const double* w2, int nx, const T* Psi, int N, int64_t M, int nspin,
-                          double scale, T* Out) {
+template <>
+hipError_t launch_adj_psi<double>(lrdm_ctx* ctx, const double* X1, const double* w1,
+                                  const double* X2, const double* w2, int nx, const double* Psi,
+                                  int N, int64_t M, int nspin, double scale, double* Out,
+                                  const unsigned char*) {
   dim3 grd((unsigned)((M + BT - 1) / BT), (N + BT - 1) / BT, nspin);
   ProfScope prof(ctx, "adj_psi");
-  adj_psi_f64_kernel<T><<<grd, 256, 0, ctx->stream>>>(X1, w1, X2, w2, nx, Psi, N, M, nspin, scale,
-                                                      Out);
+  adj_psi_f64_kernel<double><<<grd, 256, 0, ctx->stream>>>(X1, w1, X2, w2, nx, Psi, N, M, nspin,
+                                                           scale, Out);
   return hipGetLastError();
 }
-template hipError_t launch_adj_psi<double>(lrdm_ctx*, const double*, const double*, const double*,
-                                           const double*, int, const double*, int, int64_t, int,
-                                           double, double*);
-template hipError_t launch_adj_psi<float>(lrdm_ctx*, const double*, const double*, const double*,
-                                          const double*, int, const float*, int, int64_t, int,
-                                          double, float*);
 
 }  // namespace lrdm

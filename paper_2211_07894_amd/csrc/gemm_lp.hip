@@ -738,6 +738,105 @@ __global__ __launch_bounds__(256) void transpose_pad_kernel(const float* __restr
   }
 }
 
+// Adjoint rotation on FP32 matrix cores (FP32 storage):
+//   Out_c[i][p] = scale * sum_m w_m[p] sum_j X_m[i][j] Psi_c[j][p]
+// over the 2 nx matrices X_m of channel c, staged as FP32 copies Xf
+// [2 nx][nspin][N][ldk] (X1's then X2's), with Psi^T as AT [nspin][M][ldk].  The
+// K-tiles of every matrix run through the same LDS ring; each K-tile's FP32
+// products are added into the FP64 accumulators with the weight w_m of their
+// output column.  The blocks (ib, J) that `active` marks inactive (blocks.h) are
+// zero in every X_m and are skipped.  1-D grid over (point block, channel) groups
+// of row blocks, the row blocks of one point block together on one XCD (they
+// stage the same tiles of AT).
+__global__ __launch_bounds__(PT, 1) void adj_psi_pipe_kernel(
+    const float* __restrict__ Xf, const double* __restrict__ w1, const double* __restrict__ w2,
+    int nx, const float* __restrict__ AT, int N, int64_t M, int ldk, int nspin, double scale,
+    const unsigned char* __restrict__ active, const float* __restrict__ zeros,
+    float* __restrict__ Out) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_pipe[];
+  constexpr int SB = 2 * TB;
+  const int nrb = (N + BT - 1) / BT;
+  const int npb = (int)((M + BT - 1) / BT);
+  int group, ib;
+  xcd_map(blockIdx.x, npb * nspin, nrb, group, ib);
+  const int pblk = group / nspin, c = group % nspin;
+  const int i0 = ib * BT;
+  const int64_t p0 = (int64_t)pblk * BT;
+  const float* ATc = AT + (int64_t)c * M * ldk;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  // K runs over the active blocks J of row block ib (every J, X_m being a full product)
+  uint64_t bits = 0;
+  for (int J = 0; J < nrb; ++J)
+    if (block_active(active, c, nrb, ib, J)) bits |= 1ull << J;
+  const int nkm = active_ktiles(bits, N, KT);     // K-tiles per matrix
+  const int nmat = 2 * nx;
+  const int nk = nmat * nkm;
+  auto issue = [&](int t) {
+    unsigned char* st = smem_pipe + (t % NST) * SB;
+    const int m = nkm > 0 ? min(t / nkm, nmat - 1) : 0;
+    int J;
+    const int64_t j0 = active_ktile(bits, nkm > 0 ? t % nkm : 0, KT, J);
+    const int64_t je = t < nk ? ldk : j0;
+    const float* Xm = Xf + ((int64_t)m * nspin + c) * N * ldk;
+    dma_tile(Xm, ldk, N, i0, j0, je, zeros, st, wid, lane);
+    dma_tile(ATc, ldk, (int)M, p0, j0, je, zeros, st + TB, wid, lane);
+  };
+  double acc[2][4][4];
+  zero_pipe(acc);
+  double wcol[4] = {0.0, 0.0, 0.0, 0.0};
+  issue(0);
+  issue(1);
+  for (int t = 0; t < nk; ++t) {
+    if (t % nkm == 0) {
+      // the weights of matrix m for this wave's output columns
+      const int m = t / nkm;
+      const double* w = (m < nx ? w1 : w2) + ((int64_t)(m % nx) * nspin + c) * M;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t p = p0 + wc * 64 + j * 16 + (lane & 15);
+        wcol[j] = p < M ? w[p] : 0.0;
+      }
+    }
+    wait_stage<4>();
+    const unsigned char* st = smem_pipe + (t % NST) * SB;
+    PipeFrag f;
+    f.load(st, st + TB, wr, wc, lane);
+    compiler_fence();
+    issue(t + 2);
+    f4 cc[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) cc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) cc[i][j] = mfma_f32(f.a[i][s], f.b[j][s], cc[i][j]);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[i][j][v] += wcol[j] * (double)cc[i][j][v];
+  }
+  wait_stage<0>();
+  float* Oc = Out + (int64_t)c * N * M;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int gi = i0 + wr * 32 + i * 16 + 4 * (lane >> 4) + v;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t p = p0 + wc * 64 + j * 16 + (lane & 15);
+        if (gi < N && p < M) Oc[(int64_t)gi * M + p] = (float)(scale * acc[i][j][v]);
+      }
+    }
+}
+
 // ================================================================== pre-split BF16X3
 // The exact three-piece split costs about as much VALU work as the six products,
 // and inside the kernels every wave repeats it for the fragments it shares with
@@ -1381,4 +1480,42 @@ hipError_t launch_psi_pieces(lrdm_ctx* ctx, const float* Psi, int N, int64_t M, 
   return hipGetLastError();
 }
 
+// Adjoint rotation for FP32 storage: FP32 copies of the 2 nx matrices and Psi^T,
+// then adj_psi_pipe_kernel.
+template <>
+hipError_t launch_adj_psi<float>(lrdm_ctx* ctx, const double* X1, const double* w1,
+                                 const double* X2, const double* w2, int nx, const float* Psi,
+                                 int N, int64_t M, int nspin, double scale, float* Out,
+                                 const unsigned char* active) {
+  const int ldk = pad_k(N);
+  const int64_t nX = (int64_t)nx * nspin * N * ldk;
+  float* Xf = static_cast<float*>(ws_take(ctx, (size_t)2 * nX * sizeof(float)));
+  float* AT = static_cast<float*>(ws_take(ctx, (size_t)nspin * M * ldk * sizeof(float)));
+  const unsigned g1 = (unsigned)((nX + 255) / 256);
+  gamma_pad_kernel<<<g1, 256, 0, ctx->stream>>>(X1, Xf, N, ldk, nx * nspin);
+  LRDM_HIP(hipGetLastError());
+  gamma_pad_kernel<<<g1, 256, 0, ctx->stream>>>(X2, Xf + nX, N, ldk, nx * nspin);
+  LRDM_HIP(hipGetLastError());
+  dim3 gt((unsigned)((M + 63) / 64), (unsigned)(ldk / 64 + (ldk % 64 ? 1 : 0)), nspin);
+  transpose_pad_kernel<<<gt, 256, 0, ctx->stream>>>(Psi, AT, N, M, ldk);
+  LRDM_HIP(hipGetLastError());
+  const int smem = NST * 2 * TB;
+  LRDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&adj_psi_pipe_kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, smem));
+  const unsigned grd = (unsigned)((M + BT - 1) / BT) * (unsigned)((N + BT - 1) / BT) *
+                       (unsigned)nspin;
+  ProfScope prof(ctx, "adj_psi");
+  adj_psi_pipe_kernel<<<grd, PT, smem, ctx->stream>>>(Xf, w1, w2, nx, AT, N, M, ldk, nspin, scale,
+                                                      active, ctx->zeros, Out);
+  return hipGetLastError();
+}
+
+size_t adj_psi_workspace_bytes(int N, int64_t M, int nspin, int nx, bool fp32) {
+  if (!fp32) return 0;
+  const size_t ldk = pad_k(N);
+  return ws_align((size_t)2 * nx * nspin * N * ldk * sizeof(float)) +
+         ws_align((size_t)nspin * M * ldk * sizeof(float));
+}
+
 }  // namespace lrdm
+

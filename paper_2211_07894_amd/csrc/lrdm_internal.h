@@ -164,6 +164,14 @@ size_t rotate_bf16x3_bytes(int N, int64_t M);
 hipError_t launch_rotate_bf16x3(lrdm_ctx* ctx, const double* Wt, const float* B, float* Out,
                                 int N, int64_t M, bool upper);
 
+// One Chebyshev step with the Bloch Hamiltonian of kvec (bloch.hip) on blocks of N
+// complex states stored as [2][N][M] (real parts, then imaginary parts):
+// out = alpha (H_k in - c0 in) + beta old; old may be out, beta = 0 ignores it.
+template <typename T>
+hipError_t launch_bloch_step(lrdm_ctx* ctx, const Grid3& g, const double* V, const double kvec[3],
+                             const T* in, const T* old, T* out, int N, double alpha, double c0,
+                             double beta);
+
 // launch_fermi with Brillouin-zone sampling: eps [nspin][nk][N], weights [nk]
 // (device); mu from the zone-averaged count, then f, 1 - f, f' and the divided
 // differences F [nspin][nk][N][N] of every (channel, k).
@@ -256,13 +264,16 @@ template <typename S>
 hipError_t launch_nn_f64(lrdm_ctx* ctx, const double* Wt, const S* B, S* Out, int N, int64_t M,
                          bool upper = false);
 
-// Adjoint rotation (gemm.hip): Out_c = scale * sum_m (X_m Psi_c) o w_m over two lists
-// of nx symmetric matrices [nx][nspin][N][N] with weights [nx][nspin][M], FP64
-// arithmetic; Out has Psi's storage type and layout.
+// Adjoint rotation: Out_c = scale * sum_m (X_m Psi_c) o w_m over two lists of nx
+// symmetric matrices [nx][nspin][N][N] with weights [nx][nspin][M]; Out has
+// Psi's storage type and layout.  FP64 storage: FP64 arithmetic (gemm.hip).  FP32
+// storage: FP32 matrix cores with FP64 accumulation across K-tiles, skipping the
+// blocks `active` marks inactive (gemm_lp.hip; workspace adj_psi_workspace_bytes).
 template <typename T>
 hipError_t launch_adj_psi(lrdm_ctx* ctx, const double* X1, const double* w1, const double* X2,
                           const double* w2, int nx, const T* Psi, int N, int64_t M, int nspin,
-                          double scale, T* Out);
+                          double scale, T* Out, const unsigned char* active = nullptr);
+size_t adj_psi_workspace_bytes(int N, int64_t M, int nspin, int nx, bool fp32);
 
 // Adjoint pieces (adjoint.hip).
 // y[i] = a * x[i] for i < n.

@@ -84,10 +84,12 @@ def test_density_response_bz(case, prec, nspin):
     assert abs(float(mu.item()) - mu_o) < 1e-12
     assert np.max(np.abs(to_host(dmu) - dmu_o)) < 10 * BOUND[prec] * max(1.0, np.max(np.abs(dmu_o)))
     assert err < BOUND[prec]
-    # the zone-averaged traceless condition: delta rho integrates to zero
+    # the zone-averaged traceless condition: delta rho integrates to zero (to the
+    # orthonormality of the stored states: about 1e-7 for FP32 storage)
+    tol = 1e-9 if prec == "fp64" else 1e-6
     for q in range(3):
         total = g.dv * float(to_host(drho)[q].sum())
-        assert abs(total) < 1e-9 * g.dv * float(np.abs(to_host(drho)[q]).sum())
+        assert abs(total) < tol * g.dv * float(np.abs(to_host(drho)[q]).sum())
 
 
 def test_density_response_bz_gamma_is_the_real_path():
