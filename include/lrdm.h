@@ -217,6 +217,27 @@ lrdm_status chfsi_filter(lrdm_ctx* ctx, const lrdm_grid* grid, const double* V,
                          const void* X, void* Y, int32_t N, lrdm_prec prec,
                          int32_t degree, double a, double b, double a0);
 
+/* H_k Y for the Bloch Hamiltonian of one k-point (Sec. II C, last paragraph):
+ * for the cell-periodic part u of Bloch states e^{i k.x} u(x), the 7-point
+ * stencil of chfsi_filter with the phase e^{i k_d h_d} on the link to the
+ * neighbour at +h_d and its conjugate on the link to -h_d,
+ *   (H_k u)_p = -1/2 sum_d (e^{i k_d h_d} u_{p+e_d} + e^{-i k_d h_d} u_{p-e_d}
+ *               - 2 u_p)/h_d^2 + V_p u_p.
+ * X, Y [2][N][nz][ny][nx]: the N real parts, then the N imaginary parts (double
+ * for LRDM_FP64, float otherwise; the arithmetic is FP64); (kx, ky, kz) in
+ * 1/bohr, finite; k = 0 is the real stencil.  X and Y must not overlap. */
+lrdm_status lrdm_bloch_hamiltonian_apply(lrdm_ctx* ctx, const lrdm_grid* grid, const double* V,
+                                         double kx, double ky, double kz, const void* X, void* Y,
+                                         int32_t N, lrdm_prec prec);
+
+/* chfsi_filter with H_k in place of H (ChFSI of one k-point's subspace, Sec.
+ * II C, last paragraph): the same scaled three-term recurrence and bounds on
+ * blocks of N complex states stored as in lrdm_bloch_hamiltonian_apply.  The
+ * workspace holds one more block. */
+lrdm_status chfsi_filter_bloch(lrdm_ctx* ctx, const lrdm_grid* grid, const double* V, double kx,
+                               double ky, double kz, const void* X, void* Y, int32_t N,
+                               lrdm_prec prec, int32_t degree, double a, double b, double a0);
+
 /* Rayleigh-Ritz step of ChFSI (Sec. II C, Eq. (15)): orthonormalise the
  * filtered block, project H, diagonalise the N x N projection in FP64 on the
  * GPU and rotate.  Psi [N][nz][ny][nx]: in = filtered block, out = Ritz
@@ -435,20 +456,29 @@ lrdm_status lrdm_lowrank_step(lrdm_ctx* ctx, const lrdm_grid* grid, const void* 
 
 /* ---------------------------------------------------------------- autotuner */
 
-/* Chooses the K-split count of the projection contraction (the number of point
- * ranges whose FP64 partial sums are added afterwards) for three shapes at this
- * grid, N, nspin, r and form: the response's projection of r*nspin directions,
- * the single-direction projection of lrdm_lowrank_step, and the unweighted Gram
- * product of subspace_rayleigh_ritz (FP64 arithmetic).  Each is timed (one
- * warm-up, three timed launches, hipEvents) at the default count and at 1/4, 1/2
- * and 2 times it (within 1..the workspace's cap), on scratch blocks the call
- * allocates and frees, and the fastest is kept on this context for later calls of
- * the same shape.  splits (host int[3], may be NULL) receives the chosen counts;
- * timings (host double[12], may be NULL) the milliseconds per candidate, 0 where
- * not tried.  Synchronises.  For the callers that tune once at set-up, not for
- * those that cannot allocate. */
+/* Chooses, for three shapes at this grid, N, nspin, r and form, the layout of
+ * tiles and waves of the projection kernel and its K-split count (the number of
+ * point ranges whose FP64 partial sums are added afterwards): the response's
+ * projection of r*nspin directions, the single-direction projection of
+ * lrdm_lowrank_step, and the unweighted Gram product of subspace_rayleigh_ritz
+ * (FP64 arithmetic).  Layouts (variants): 0, eight waves of 32 x 64 on a
+ * 128 x 128 tile with the operands copied to LDS through a three-stage ring
+ * (BF16X3: the unweighted operand split into its pieces once per call); 1, four
+ * waves of 64 x 64 on the same tile with the operands staged through
+ * registers; 2 (BF16X3 only), the ring kernel splitting both operands itself.
+ * FP64 arithmetic has layout 0 only, FP32 layouts 0 and 1.  Each candidate
+ * (layout, count of 1/4, 1/2, 1 and 2 times the default within 1..the
+ * workspace's cap) is timed (one warm-up, three timed launches, hipEvents) on
+ * scratch blocks the call allocates and frees, and the fastest is kept on this
+ * context for later calls of the same shape (the batched FP32 response sends a
+ * system whose shape is tuned to layout 1 to its own launch).  splits and
+ * variants (host int[3], may be NULL) receive the choices; timings (host
+ * double[3][3][4], may be NULL) the milliseconds per shape, layout and count, 0
+ * where not tried.  Synchronises.  For the callers that tune once at set-up, not
+ * for those that cannot allocate. */
 lrdm_status lrdm_autotune(lrdm_ctx* ctx, const lrdm_grid* grid, int32_t N, int32_t nspin,
-                          int32_t r, lrdm_prec prec, int32_t* splits, double* timings);
+                          int32_t r, lrdm_prec prec, int32_t* splits, int32_t* variants,
+                          double* timings);
 
 #ifdef __cplusplus
 }

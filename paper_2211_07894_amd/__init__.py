@@ -19,6 +19,8 @@ from .lrdm import (  # noqa: F401
     subspace_rayleigh_ritz,
     density_response,
     density_response_bz,
+    bloch_hamiltonian_apply,
+    chfsi_filter_bloch,
     residual_derivative,
     density_response_backward,
     density_response_batched,

@@ -660,6 +660,96 @@ extern "C" lrdm_status chfsi_filter(lrdm_ctx* ctx, const lrdm_grid* grid, const 
   });
 }
 
+namespace {
+
+// The filter of run_filter with the Bloch Hamiltonian of kvec on blocks of N
+// complex states [2][N][M]: Y_k lands in bufA for odd k and bufB for even k, so
+// that Y_c is in Y; Y_k overwrites Y_{k-2} in place.
+template <typename T>
+hipError_t run_filter_bloch(lrdm_ctx* ctx, const Grid3& g, const double* V, const double kvec[3],
+                            const T* X, T* Y, int N, int degree, double a, double b, double a0) {
+  T* W = static_cast<T*>(ws_take(ctx, (size_t)2 * g.M * N * sizeof(T)));
+  const double e = (b - a) / 2.0, c0 = (b + a) / 2.0;
+  const double sigma1 = e / (a0 - c0);
+  T* bufA = (degree % 2 == 1) ? Y : W;
+  T* bufB = (degree % 2 == 1) ? W : Y;
+  LRDM_HIP(launch_bloch_step<T>(ctx, g, V, kvec, X, nullptr, bufA, N, sigma1 / e, c0, 0.0));
+  double sigma = sigma1;
+  for (int k = 2; k <= degree; ++k) {
+    const T* ykm1 = (k % 2 == 0) ? bufA : bufB;
+    const T* ykm2 = (k == 2) ? X : ((k % 2 == 0) ? bufB : bufA);
+    T* out = (k % 2 == 1) ? bufA : bufB;
+    const double s1 = 1.0 / (2.0 / sigma1 - sigma);
+    LRDM_HIP(launch_bloch_step<T>(ctx, g, V, kvec, ykm1, ykm2, out, N, 2.0 * s1 / e, c0,
+                                  -sigma * s1));
+    sigma = s1;
+  }
+  return hipSuccess;
+}
+
+const char* check_kvec(double kx, double ky, double kz) {
+  if (!std::isfinite(kx) || !std::isfinite(ky) || !std::isfinite(kz))
+    return "k must be finite";
+  return nullptr;
+}
+
+}  // namespace
+
+extern "C" lrdm_status lrdm_bloch_hamiltonian_apply(lrdm_ctx* ctx, const lrdm_grid* grid,
+                                                    const double* V, double kx, double ky,
+                                                    double kz, const void* X, void* Y, int32_t N,
+                                                    lrdm_prec prec) {
+  LRDM_CHECK(ctx, check_grid(grid));
+  LRDM_CHECK(ctx, check_block(grid, N));
+  LRDM_CHECK(ctx, check_prec(prec));
+  LRDM_CHECK(ctx, check_kvec(kx, ky, kz));
+  LRDM_NONNULL(ctx, V, "V");
+  LRDM_NONNULL(ctx, X, "X");
+  LRDM_NONNULL(ctx, Y, "Y");
+  const Grid3 g = make_grid3(grid);
+  const size_t blk = (size_t)2 * g.M * N * prec_bytes(prec);
+  if (overlaps(X, blk, Y, blk)) return fail(ctx, LRDM_EINVAL, "X and Y must not overlap");
+  lrdm_status st = begin(ctx, 0);
+  if (st != LRDM_OK) return st;
+  const double kvec[3] = {kx, ky, kz};
+  return guarded(ctx, [&]() -> lrdm_status {
+    hipError_t e = (prec == LRDM_FP64)
+        ? launch_bloch_step<double>(ctx, g, V, kvec, static_cast<const double*>(X), nullptr,
+                                    static_cast<double*>(Y), N, 1.0, 0.0, 0.0)
+        : launch_bloch_step<float>(ctx, g, V, kvec, static_cast<const float*>(X), nullptr,
+                                   static_cast<float*>(Y), N, 1.0, 0.0, 0.0);
+    return e == hipSuccess ? LRDM_OK : fail_hip(ctx, "lrdm_bloch_hamiltonian_apply", e);
+  });
+}
+
+extern "C" lrdm_status chfsi_filter_bloch(lrdm_ctx* ctx, const lrdm_grid* grid, const double* V,
+                                          double kx, double ky, double kz, const void* X, void* Y,
+                                          int32_t N, lrdm_prec prec, int32_t degree, double a,
+                                          double b, double a0) {
+  LRDM_CHECK(ctx, check_grid(grid));
+  LRDM_CHECK(ctx, check_block(grid, N));
+  LRDM_CHECK(ctx, check_prec(prec));
+  LRDM_CHECK(ctx, check_filter(degree, a, b, a0));
+  LRDM_CHECK(ctx, check_kvec(kx, ky, kz));
+  LRDM_NONNULL(ctx, V, "V");
+  LRDM_NONNULL(ctx, X, "X");
+  LRDM_NONNULL(ctx, Y, "Y");
+  const Grid3 g = make_grid3(grid);
+  const size_t blk = (size_t)2 * g.M * N * prec_bytes(prec);
+  if (overlaps(X, blk, Y, blk)) return fail(ctx, LRDM_EINVAL, "X and Y must not overlap");
+  lrdm_status st = begin(ctx, ws_align(blk));
+  if (st != LRDM_OK) return st;
+  const double kvec[3] = {kx, ky, kz};
+  return guarded(ctx, [&]() -> lrdm_status {
+    hipError_t e = (prec == LRDM_FP64)
+        ? run_filter_bloch<double>(ctx, g, V, kvec, static_cast<const double*>(X),
+                                   static_cast<double*>(Y), N, degree, a, b, a0)
+        : run_filter_bloch<float>(ctx, g, V, kvec, static_cast<const float*>(X),
+                                  static_cast<float*>(Y), N, degree, a, b, a0);
+    return e == hipSuccess ? LRDM_OK : fail_hip(ctx, "chfsi_filter_bloch", e);
+  });
+}
+
 extern "C" lrdm_status subspace_rayleigh_ritz(lrdm_ctx* ctx, const lrdm_grid* grid,
                                               const double* V, void* Psi, int32_t N,
                                               lrdm_prec prec, double* eps) {
@@ -889,6 +979,39 @@ extern "C" lrdm_status density_response_batched(lrdm_ctx* ctx, const lrdm_system
   }
   lrdm_status st = begin(ctx, total);
   if (st != LRDM_OK) return st;
+  if (prec == LRDM_FP32 && ctx->fermi_depth == 0) {
+    // the systems' projections in one launch, then their back-projections in one
+    // launch, on the context's stream (the small per-system steps in between)
+    return guarded(ctx, [&]() -> lrdm_status {
+      std::vector<FermiState> fs(nsys);
+      std::vector<FusedProjItem> proj(nsys);
+      std::vector<FusedBackprojItem> bp(nsys);
+      std::vector<double*> dmu(nsys);
+      hipError_t e = hipSuccess;
+      for (int s = 0; s < nsys && e == hipSuccess; ++s) {
+        const lrdm_system& y = sys[s];
+        const Grid3 g = make_grid3(&y.grid);
+        const int ns = y.occ.nspin;
+        e = run_fermi(ctx, y.eps, y.N, &y.occ, y.mu, &fs[s]);
+        dmu[s] = y.dmu ? y.dmu : static_cast<double*>(ws_take(ctx, (size_t)y.r * 8));
+        double* Hp = static_cast<double*>(
+            ws_take(ctx, (size_t)y.r * ns * y.N * y.N * sizeof(double)));
+        const float* P = static_cast<const float*>(y.Psi);
+        proj[s] = FusedProjItem{P, y.dV, y.N, g.M, ns, y.r * ns, fs[s].active, Hp};
+        bp[s] = FusedBackprojItem{P, Hp, y.N, g.M, ns, y.r * ns, (ns == 1 ? 2.0 : 1.0) / g.dv,
+                                  fs[s].active, y.drho};
+      }
+      if (e == hipSuccess) e = launch_tn_sym_fused(ctx, proj.data(), nsys);
+      for (int s = 0; s < nsys && e == hipSuccess; ++s)
+        e = launch_gamma(ctx, proj[s].H, fs[s].F, fs[s].fp, sys[s].N, sys[s].occ.nspin, sys[s].r,
+                         dmu[s]);
+      if (e == hipSuccess) e = launch_backproj_fused(ctx, bp.data(), nsys);
+      for (int s = 0; s < nsys && e == hipSuccess && ctx->checks; ++s)
+        e = launch_check_finite(ctx, sys[s].drho,
+                                (int64_t)sys[s].r * sys[s].occ.nspin * grid_points(&sys[s].grid));
+      return e == hipSuccess ? LRDM_OK : fail_hip(ctx, "density_response_batched", e);
+    });
+  }
   return guarded(ctx, [&]() -> lrdm_status {
     const hipStream_t main = ctx->stream;
     const int K = (int)ctx->aux.size();
@@ -1261,7 +1384,7 @@ hipError_t time_launch(lrdm_ctx* ctx, F&& launch, int reps, double* ms) {
 
 extern "C" lrdm_status lrdm_autotune(lrdm_ctx* ctx, const lrdm_grid* grid, int32_t N,
                                      int32_t nspin, int32_t r, lrdm_prec prec, int32_t* splits,
-                                     double* timings) {
+                                     int32_t* variants, double* timings) {
   LRDM_CHECK(ctx, check_grid(grid));
   LRDM_CHECK(ctx, check_block(grid, N));
   LRDM_CHECK(ctx, check_rank(r));
@@ -1309,13 +1432,20 @@ extern "C" lrdm_status lrdm_autotune(lrdm_ctx* ctx, const lrdm_grid* grid, int32
       const int h = tn_splits(ntiles * kd.b, g.M);
       const int cap = tn_split_cap(ntiles * kd.b, g.M);
       const std::array<int64_t, 5> key{N, g.M, kd.b, kd.arith, kd.weighted ? 1 : 0};
-      int best = h;
+      int best = h, best_v = TN_VAR_DEFAULT;
       double best_ms = 1e300;
       const int cand[4] = {h / 4, h / 2, h, 2 * h};
+      // tile and wave layouts: one kernel for FP64 arithmetic, two for FP32,
+      // three for BF16X3 (variants of TN_VAR_*)
+      const int nvar = kd.arith == TN_ARITH_F64 ? 1 : (kd.arith == TN_ARITH_F32 ? 2 : 3);
+      for (int v = 0; v < 3; ++v)
+        for (int c = 0; c < 4; ++c)
+          if (timings) timings[(k * 3 + v) * 4 + c] = 0.0;
+      for (int v = 0; v < nvar; ++v)
       for (int c = 0; c < 4; ++c) {
         const int s = cand[c];
-        if (timings) timings[k * 4 + c] = 0.0;
         if (s < 1 || s > cap || (c > 0 && s == cand[c - 1])) continue;
+        ctx->tn_variant[key] = v;
         ctx->tn_tuned[key] = s;
         auto launch = [&]() -> hipError_t {
           ctx->ws_top = 0;
@@ -1334,14 +1464,17 @@ extern "C" lrdm_status lrdm_autotune(lrdm_ctx* ctx, const lrdm_grid* grid, int32
         double ms = 0.0;
         e = time_launch(ctx, launch, 3, &ms);
         if (e != hipSuccess) return fail_hip(ctx, "lrdm_autotune", e);
-        if (timings) timings[k * 4 + c] = ms;
+        if (timings) timings[(k * 3 + v) * 4 + c] = ms;
         if (ms < best_ms) {
           best_ms = ms;
           best = s;
+          best_v = v;
         }
       }
       ctx->tn_tuned[key] = best;
+      ctx->tn_variant[key] = best_v;
       if (splits) splits[k] = best;
+      if (variants) variants[k] = best_v;
     }
     return LRDM_OK;
   });

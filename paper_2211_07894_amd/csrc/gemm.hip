@@ -508,6 +508,11 @@ int tn_split_count(const lrdm_ctx* ctx, int N, int64_t M, int batch, int arith, 
   return tn_splits(ntiles * batch, M);
 }
 
+int tn_variant(const lrdm_ctx* ctx, int N, int64_t M, int batch, int arith, bool weighted) {
+  const auto it = ctx->tn_variant.find({N, M, batch, arith, weighted ? 1 : 0});
+  return it == ctx->tn_variant.end() ? TN_VAR_DEFAULT : it->second;
+}
+
 size_t tn_workspace_bytes(int N, int64_t M, int batch, lrdm_prec prec) {
   return ws_align(tn_part_bytes(N, M, batch)) + tn_split_bytes(N, M, prec);
 }

@@ -25,6 +25,8 @@
 //   v_mfma_f32_16x16x4f32:      A lane l -> A[l%16][l/16], B lane l -> B[l/16][l%16]
 //   v_mfma_f32_16x16x32_bf16:   A lane l -> A[l%16][8(l/16)+e], B -> B[8(l/16)+e][l%16]
 //   both:                       D lane l, register v -> D[4(l/16) + v][l%16]
+#include <algorithm>
+
 #include "blocks.h"
 #include "lrdm_internal.h"
 #include "xcd.h"
@@ -270,7 +272,7 @@ template <Core C>
 __global__ __launch_bounds__(256, 1) void tn_sym_lp_kernel(
     const float* __restrict__ A, const float* __restrict__ B, const double* __restrict__ w,
     int64_t w_stride, int N, int64_t M, int nspin, int ntb, int64_t kchunk, int nsplit, int batch,
-    double* __restrict__ part) {
+    const unsigned char* __restrict__ active, double* __restrict__ part) {
   __shared__ __attribute__((aligned(16))) float As[BT * KP];
   __shared__ __attribute__((aligned(16))) float Bs[BT * KP];
   const int ntiles = ntb * (ntb + 1) / 2;
@@ -285,7 +287,8 @@ __global__ __launch_bounds__(256, 1) void tn_sym_lp_kernel(
   const float* Bc = B + (int64_t)c * N * M;
   const double* wb = w ? w + (int64_t)b * w_stride : nullptr;
   const int64_t kbeg = (int64_t)sp * kchunk;
-  const int64_t kend = min(M, kbeg + kchunk);
+  // an inactive block (blocks.h) keeps a zero partial tile
+  const int64_t kend = block_active(active, c, ntb, ti, tj) ? min(M, kbeg + kchunk) : kbeg;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int wr = wid >> 1, wc = wid & 1;
   double acc[4][4][4];
@@ -531,17 +534,19 @@ __device__ inline void zero_pipe(double (&acc)[2][4][4]) {
 
 // tn_sym, pipelined: same grid and partial layout as tn_sym_lp_kernel.  Requires M
 // a multiple of 4 and 16-byte aligned A, B and weight rows.  W: B weighted by w.
+// The body, for workgroup `lin` of the launch's grid (the fused launch of several
+// systems passes each system's own workgroup index).
 template <Core C, bool W>
-__global__ __launch_bounds__(PT, 1) void tn_sym_pipe_kernel(
-    const float* __restrict__ A, const float* __restrict__ B, const double* __restrict__ w,
-    int64_t w_stride, int N, int64_t M, int nspin, int ntb, int64_t kchunk, int nsplit, int batch,
-    const unsigned char* __restrict__ active, const float* __restrict__ zeros,
-    double* __restrict__ part) {
+__device__ inline void tn_sym_pipe_body(
+    int lin, const float* __restrict__ A, const float* __restrict__ B,
+    const double* __restrict__ w, int64_t w_stride, int N, int64_t M, int nspin, int ntb,
+    int64_t kchunk, int nsplit, int batch, const unsigned char* __restrict__ active,
+    const float* __restrict__ zeros, double* __restrict__ part) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_pipe[];
   constexpr int SB = 2 * TB + (W ? 1024 : 0);   // bytes of one stage
   const int ntiles = ntb * (ntb + 1) / 2;
   int group, tile;
-  xcd_map(blockIdx.x, nsplit * batch, ntiles, group, tile);
+  xcd_map(lin, nsplit * batch, ntiles, group, tile);
   const int sp = group % nsplit, b = group / nsplit;
   int ti = 0, rem = tile;
   while (rem >= ntb - ti) { rem -= ntb - ti; ++ti; }
@@ -595,21 +600,31 @@ __global__ __launch_bounds__(PT, 1) void tn_sym_pipe_kernel(
       }
 }
 
+template <Core C, bool W>
+__global__ __launch_bounds__(PT, 1) void tn_sym_pipe_kernel(
+    const float* __restrict__ A, const float* __restrict__ B, const double* __restrict__ w,
+    int64_t w_stride, int N, int64_t M, int nspin, int ntb, int64_t kchunk, int nsplit, int batch,
+    const unsigned char* __restrict__ active, const float* __restrict__ zeros,
+    double* __restrict__ part) {
+  tn_sym_pipe_body<C, W>(blockIdx.x, A, B, w, w_stride, N, M, nspin, ntb, kchunk, nsplit, batch,
+                         active, zeros, part);
+}
+
 // backproj, pipelined.  Gf: FP32 copies of the symmetric matrices [batch][N][ldk];
 // PT_: FP32 transposes of the blocks, [nspin][M][ldk] (A^T, points as rows); ldk a
 // multiple of KT with zeros in the columns >= N.  A ([nspin][N][M]) feeds the row-dot.
 template <Core C>
-__global__ __launch_bounds__(PT, 1) void backproj_pipe_kernel(
-    const float* __restrict__ A, const float* __restrict__ AT, const float* __restrict__ Gf,
-    int N, int64_t M, int ldk, int nspin, int batch, double scale, const double* __restrict__ sub,
-    const unsigned char* __restrict__ active, const float* __restrict__ zeros,
-    double* __restrict__ out) {
+__device__ inline void backproj_pipe_body(
+    int lin, const float* __restrict__ A, const float* __restrict__ AT,
+    const float* __restrict__ Gf, int N, int64_t M, int ldk, int nspin, int batch, double scale,
+    const double* __restrict__ sub, const unsigned char* __restrict__ active,
+    const float* __restrict__ zeros, double* __restrict__ out) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_pipe[];
   constexpr int SB = 2 * TB;
   double* red = reinterpret_cast<double*>(smem_pipe + NST * SB);   // [PW][64]
   // 1-D grid: the directions of one block of points run together on one XCD
   int pblk, b;
-  xcd_map(blockIdx.x, (int)((M + BT - 1) / BT), batch, pblk, b);
+  xcd_map(lin, (int)((M + BT - 1) / BT), batch, pblk, b);
   const int c = b % nspin;
   const float* Ac = A + (int64_t)c * N * M;
   const float* ATc = AT + (int64_t)c * M * ldk;
@@ -701,6 +716,75 @@ __global__ __launch_bounds__(PT, 1) void backproj_pipe_kernel(
       out[(int64_t)b * M + p] = r;
     }
   }
+}
+
+template <Core C>
+__global__ __launch_bounds__(PT, 1) void backproj_pipe_kernel(
+    const float* __restrict__ A, const float* __restrict__ AT, const float* __restrict__ Gf,
+    int N, int64_t M, int ldk, int nspin, int batch, double scale, const double* __restrict__ sub,
+    const unsigned char* __restrict__ active, const float* __restrict__ zeros,
+    double* __restrict__ out) {
+  backproj_pipe_body<C>(blockIdx.x, A, AT, Gf, N, M, ldk, nspin, batch, scale, sub, active,
+                        zeros, out);
+}
+
+// ------------------------------------------------------------------ fused systems
+// One launch of the FP32 projection (or back-projection) over up to kMaxFused
+// independent systems: system s owns workgroups [wg0[s], wg0[s+1]) (each range
+// a multiple of the XCD count, so that a system's own XCD grouping holds; the
+// padding workgroups exit at once), with its operands passed by value.
+constexpr int kMaxFused = 16;
+
+struct FusedProj {
+  int nsys;
+  int wg0[kMaxFused + 1];
+  int used[kMaxFused];                 // workgroups system s needs
+  const float* A[kMaxFused];
+  const double* w[kMaxFused];
+  double* part[kMaxFused];
+  const unsigned char* active[kMaxFused];
+  int64_t M[kMaxFused], kchunk[kMaxFused];
+  int N[kMaxFused], nspin[kMaxFused], ntb[kMaxFused], nsplit[kMaxFused], batch[kMaxFused];
+};
+
+struct FusedBackproj {
+  int nsys;
+  int wg0[kMaxFused + 1];
+  int used[kMaxFused];
+  const float* A[kMaxFused];
+  const float* AT[kMaxFused];
+  const float* Gf[kMaxFused];
+  double* out[kMaxFused];
+  const unsigned char* active[kMaxFused];
+  int64_t M[kMaxFused];
+  int N[kMaxFused], ldk[kMaxFused], nspin[kMaxFused], batch[kMaxFused];
+  double scale[kMaxFused];
+};
+
+__device__ inline int fused_system(const int* wg0, int nsys, int bid) {
+  int s = 0;
+  while (s + 1 < nsys && bid >= wg0[s + 1]) ++s;
+  return s;
+}
+
+__global__ __launch_bounds__(PT, 1) void tn_sym_fused_kernel(const FusedProj t,
+                                                             const float* __restrict__ zeros) {
+  const int s = fused_system(t.wg0, t.nsys, blockIdx.x);
+  const int lin = blockIdx.x - t.wg0[s];
+  if (lin >= t.used[s]) return;
+  tn_sym_pipe_body<Core::F32, true>(lin, t.A[s], t.A[s], t.w[s], t.M[s], t.N[s], t.M[s],
+                                    t.nspin[s], t.ntb[s], t.kchunk[s], t.nsplit[s], t.batch[s],
+                                    t.active[s], zeros, t.part[s]);
+}
+
+__global__ __launch_bounds__(PT, 1) void backproj_fused_kernel(const FusedBackproj t,
+                                                               const float* __restrict__ zeros) {
+  const int s = fused_system(t.wg0, t.nsys, blockIdx.x);
+  const int lin = blockIdx.x - t.wg0[s];
+  if (lin >= t.used[s]) return;
+  backproj_pipe_body<Core::F32>(lin, t.A[s], t.AT[s], t.Gf[s], t.N[s], t.M[s], t.ldk[s],
+                                t.nspin[s], t.batch[s], t.scale[s], nullptr, t.active[s], zeros,
+                                t.out[s]);
 }
 
 // Gf[b][i][j] = G[b][i][j] for j < N, 0 for N <= j < ldk.
@@ -1319,7 +1403,12 @@ hipError_t launch_tn_sym<float>(lrdm_ctx* ctx, const float* A, const float* B, c
   // the pipelined kernel copies 16-byte chunks of rows: rows must start aligned
   const bool pipe = (M % 4 == 0) && a16(A) && a16(B) && (!w || (a16(w) && w_stride % 2 == 0));
   const unsigned grd = (unsigned)(ntiles * ns * batch);
-  if (pipe && w && B == A && prec == LRDM_BF16X3 && M % 8 == 0 && nspin <= 2) {
+  // the tile and wave layout lrdm_autotune chose for this shape (default otherwise)
+  const int variant = tn_variant(ctx, N, M, batch,
+                                 prec == LRDM_BF16X3 ? TN_ARITH_BF16X3 : TN_ARITH_F32,
+                                 w != nullptr);
+  if (variant == TN_VAR_DEFAULT && pipe && w && B == A && prec == LRDM_BF16X3 && M % 8 == 0 &&
+      nspin <= 2) {
     // pieces of Psi once per call (or those the context holds for this block), then
     // the weighted A side split in the kernel
     const lrdm_psi_pieces& pc = ctx->pieces;
@@ -1361,20 +1450,20 @@ hipError_t launch_tn_sym<float>(lrdm_ctx* ctx, const float* A, const float* B, c
   };
   auto run_staged = [&](auto kernel) -> hipError_t {
     kernel<<<grd, 256, 0, ctx->stream>>>(A, B, w, w_stride, N, M, nspin, ntb, kchunk, ns, batch,
-                                         part);
+                                         active, part);
     return hipGetLastError();
   };
   {
     ProfScope prof(ctx, w ? "proj" : "gram");
     const bool bf = (prec == LRDM_BF16X3);
-    if (pipe && w)
+    if (variant == TN_VAR_STAGED || !pipe)
+      LRDM_HIP(bf ? run_staged(tn_sym_lp_kernel<Core::BF3>) : run_staged(tn_sym_lp_kernel<Core::F32>));
+    else if (w)
       LRDM_HIP(bf ? run_pipe(tn_sym_pipe_kernel<Core::BF3, true>)
                   : run_pipe(tn_sym_pipe_kernel<Core::F32, true>));
-    else if (pipe)
+    else
       LRDM_HIP(bf ? run_pipe(tn_sym_pipe_kernel<Core::BF3, false>)
                   : run_pipe(tn_sym_pipe_kernel<Core::F32, false>));
-    else
-      LRDM_HIP(bf ? run_staged(tn_sym_lp_kernel<Core::BF3>) : run_staged(tn_sym_lp_kernel<Core::F32>));
   }
   dim3 blk(32, 8);
   dim3 grd2((N + 31) / 32, (N + 7) / 8, batch);
@@ -1515,6 +1604,150 @@ size_t adj_psi_workspace_bytes(int N, int64_t M, int nspin, int nx, bool fp32) {
   const size_t ldk = pad_k(N);
   return ws_align((size_t)2 * nx * nspin * N * ldk * sizeof(float)) +
          ws_align((size_t)nspin * M * ldk * sizeof(float));
+}
+
+// ------------------------------------------------------------------ fused systems (host)
+namespace {
+
+// Items in decreasing order of work, so that the largest systems start first.
+template <typename Item, typename Work>
+std::vector<int> by_work(const Item* items, int n, Work work) {
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return work(items[a]) > work(items[b]); });
+  return order;
+}
+
+bool a16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+}  // namespace
+
+hipError_t launch_tn_sym_fused(lrdm_ctx* ctx, const FusedProjItem* items, int n) {
+  const int smem = NST * (2 * TB + 1024);
+  LRDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&tn_sym_fused_kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, smem));
+  std::vector<double*> parts(n, nullptr);
+  std::vector<int> splits(n, 0);
+  FusedProj t{};
+  t.nsys = 0;
+  int total = 0;
+  auto flush = [&]() -> hipError_t {
+    if (t.nsys == 0) return hipSuccess;
+    t.wg0[t.nsys] = total;
+    {
+      ProfScope prof(ctx, "proj");
+      tn_sym_fused_kernel<<<(unsigned)total, PT, smem, ctx->stream>>>(t, ctx->zeros);
+    }
+    t = FusedProj{};
+    t.nsys = 0;
+    total = 0;
+    return hipGetLastError();
+  };
+  const auto order = by_work(items, n, [](const FusedProjItem& it) {
+    return (double)it.M * it.N * it.N * it.batch;
+  });
+  for (int k : order) {
+    const FusedProjItem& it = items[k];
+    const int ntb = (it.N + BT - 1) / BT;
+    const int ntiles = ntb * (ntb + 1) / 2;
+    const int ns = tn_split_count(ctx, it.N, it.M, it.batch, TN_ARITH_F32, true);
+    int64_t kchunk = (it.M + ns - 1) / ns;
+    kchunk = (kchunk + KT - 1) / KT * KT;
+    const bool pipe = it.M % 4 == 0 && a16(it.A) && a16(it.w) &&
+                      tn_variant(ctx, it.N, it.M, it.batch, TN_ARITH_F32, true) == TN_VAR_DEFAULT;
+    if (!pipe) {      // a system the copy engine cannot stage, or tuned to another layout
+      // of tiles and waves, goes alone
+      LRDM_HIP(launch_tn_sym<float>(ctx, it.A, nullptr, it.w, it.M, it.N, it.M, it.nspin,
+                                    it.batch, LRDM_FP32, it.H, it.active));
+      continue;
+    }
+    parts[k] = static_cast<double*>(ws_take(ctx, tn_part_bytes(it.N, it.M, it.batch)));
+    splits[k] = ns;
+    const int s = t.nsys++;
+    const int used = ntiles * ns * it.batch;
+    t.wg0[s] = total;
+    t.used[s] = used;
+    t.A[s] = it.A;
+    t.w[s] = it.w;
+    t.part[s] = parts[k];
+    t.active[s] = it.active;
+    t.M[s] = it.M;
+    t.kchunk[s] = kchunk;
+    t.N[s] = it.N;
+    t.nspin[s] = it.nspin;
+    t.ntb[s] = ntb;
+    t.nsplit[s] = ns;
+    t.batch[s] = it.batch;
+    total += (used + 7) / 8 * 8;
+    if (t.nsys == kMaxFused) LRDM_HIP(flush());
+  }
+  LRDM_HIP(flush());
+  for (int k = 0; k < n; ++k) {
+    if (!parts[k]) continue;
+    const FusedProjItem& it = items[k];
+    const int ntb = (it.N + BT - 1) / BT;
+    dim3 blk(32, 8);
+    dim3 grd2((it.N + 31) / 32, (it.N + 7) / 8, it.batch);
+    tn_reduce_lp_kernel<<<grd2, blk, 0, ctx->stream>>>(parts[k], it.N, ntb, splits[k], it.H);
+    LRDM_HIP(hipGetLastError());
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_backproj_fused(lrdm_ctx* ctx, const FusedBackprojItem* items, int n) {
+  const int smem = NST * 2 * TB + PW * 64 * (int)sizeof(double);
+  LRDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&backproj_fused_kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, smem));
+  FusedBackproj t{};
+  t.nsys = 0;
+  int total = 0;
+  auto flush = [&]() -> hipError_t {
+    if (t.nsys == 0) return hipSuccess;
+    t.wg0[t.nsys] = total;
+    {
+      ProfScope prof(ctx, "backproj");
+      backproj_fused_kernel<<<(unsigned)total, PT, smem, ctx->stream>>>(t, ctx->zeros);
+    }
+    t = FusedBackproj{};
+    t.nsys = 0;
+    total = 0;
+    return hipGetLastError();
+  };
+  const auto order = by_work(items, n, [](const FusedBackprojItem& it) {
+    return (double)it.M * it.N * it.N * it.batch;
+  });
+  for (int k : order) {
+    const FusedBackprojItem& it = items[k];
+    const int ldk = pad_k(it.N);
+    float* Gf = static_cast<float*>(ws_take(ctx, (size_t)it.batch * it.N * ldk * sizeof(float)));
+    float* AT = static_cast<float*>(ws_take(ctx, (size_t)it.nspin * it.M * ldk * sizeof(float)));
+    const int64_t nG = (int64_t)it.batch * it.N * ldk;
+    gamma_pad_kernel<<<(unsigned)((nG + 255) / 256), 256, 0, ctx->stream>>>(it.G, Gf, it.N, ldk,
+                                                                           it.batch);
+    LRDM_HIP(hipGetLastError());
+    dim3 gt((unsigned)((it.M + 63) / 64), (unsigned)(ldk / 64 + (ldk % 64 ? 1 : 0)), it.nspin);
+    transpose_pad_kernel<<<gt, 256, 0, ctx->stream>>>(it.A, AT, it.N, it.M, ldk);
+    LRDM_HIP(hipGetLastError());
+    const int s = t.nsys++;
+    const int used = (int)((it.M + BT - 1) / BT) * it.batch;
+    t.wg0[s] = total;
+    t.used[s] = used;
+    t.A[s] = it.A;
+    t.AT[s] = AT;
+    t.Gf[s] = Gf;
+    t.out[s] = it.out;
+    t.active[s] = it.active;
+    t.M[s] = it.M;
+    t.N[s] = it.N;
+    t.ldk[s] = ldk;
+    t.nspin[s] = it.nspin;
+    t.batch[s] = it.batch;
+    t.scale[s] = it.scale;
+    total += (used + 7) / 8 * 8;
+    if (t.nsys == kMaxFused) LRDM_HIP(flush());
+  }
+  return flush();
 }
 
 }  // namespace lrdm

@@ -46,6 +46,8 @@ struct lrdm_ctx {
   // K-split counts of the projection contraction chosen by lrdm_autotune, keyed by
   // (N, M, batch, arithmetic, weighted)
   std::map<std::array<int64_t, 5>, int> tn_tuned;
+  // the projection kernel variant lrdm_autotune chose for the same keys (TN_VAR_*)
+  std::map<std::array<int64_t, 5>, int> tn_variant;
   int* dstatus = nullptr;    // device status words (LRDM_DS_*), then the zero page
   const float* zeros = nullptr;  // 128 bytes of device zeros (source of padding loads)
   std::string err;
@@ -224,6 +226,16 @@ inline int tn_split_cap(int tiles_x_batch, int64_t M) {
 }
 // Arithmetic of a projection contraction, part of the autotuner's key.
 enum { TN_ARITH_F64 = 0, TN_ARITH_F32 = 1, TN_ARITH_BF16X3 = 2 };
+// Kernel variants of the FP32-storage projection (tile and wave layout):
+//  TN_VAR_DEFAULT  8 waves of 32 x 64 on a 128 x 128 tile, operands copied to LDS
+//                  through a three-stage ring (BF16X3: Psi's pieces split once
+//                  per call, only the weighted side split in the kernel);
+//  TN_VAR_STAGED   4 waves of 64 x 64 on the same tile, operands staged through
+//                  registers (two buffers);
+//  TN_VAR_SPLIT    BF16X3 only: the ring kernel splitting both operands in the
+//                  kernel (no pre-split copy of Psi).
+enum { TN_VAR_DEFAULT = 0, TN_VAR_STAGED = 1, TN_VAR_SPLIT = 2 };
+int tn_variant(const lrdm_ctx* ctx, int N, int64_t M, int batch, int arith, bool weighted);
 // The split count a projection launch uses: the autotuned one for this shape if
 // lrdm_autotune chose one, else tn_splits.
 int tn_split_count(const lrdm_ctx* ctx, int N, int64_t M, int batch, int arith, bool weighted);
@@ -256,6 +268,33 @@ template <typename T>
 hipError_t launch_backproj(lrdm_ctx* ctx, const T* A, const double* G, int N, int64_t M, int nspin,
                            int batch, lrdm_prec prec, double scale, const double* sub,
                            double* out, const unsigned char* active = nullptr);
+
+// The FP32-form projection and back-projection of several independent systems,
+// each in one launch over all of them (gemm_lp.hip): H = Psi^T diag(w) Psi per
+// direction and channel of each item, and out = scale * sum_ij Psi_i G_ij Psi_j,
+// skipping the blocks each item's `active` marks inactive.  The per-system
+// partial sums, FP32 copies and transposes come from the workspace.
+struct FusedProjItem {
+  const float* A;          // Psi [nspin][N][M]
+  const double* w;         // dV [batch][M]
+  int N;
+  int64_t M;
+  int nspin, batch;
+  const unsigned char* active;
+  double* H;               // [batch][N][N]
+};
+struct FusedBackprojItem {
+  const float* A;          // Psi [nspin][N][M]
+  const double* G;         // Gamma [batch][N][N]
+  int N;
+  int64_t M;
+  int nspin, batch;
+  double scale;
+  const unsigned char* active;
+  double* out;             // [batch][M]
+};
+hipError_t launch_tn_sym_fused(lrdm_ctx* ctx, const FusedProjItem* items, int n);
+hipError_t launch_backproj_fused(lrdm_ctx* ctx, const FusedBackprojItem* items, int n);
 
 // Out[i][p] = sum_j Wt[j][i] B[j][p]  (Out = Wt^T B), Wt double N x N, FP64
 // arithmetic for either storage type of B and Out.  upper: Wt is upper triangular

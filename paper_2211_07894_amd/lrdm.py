@@ -33,6 +33,7 @@ EXPORTED = [
     "lrdm_density", "lrdm_effective_potential", "lrdm_lowrank_step", "lrdm_set_fermi_expansion",
     "lrdm_lda_xc", "lrdm_residual_derivative_xc", "lrdm_autotune",
     "lrdm_set_eigensolver_sweeps", "lrdm_set_response_block_skip", "density_response_bz",
+    "lrdm_bloch_hamiltonian_apply", "chfsi_filter_bloch",
 ]
 
 
@@ -136,6 +137,10 @@ def library() -> ctypes.CDLL:
                 "density_response": [vp, G, vp, vp, i32, O, vp, i32, ctypes.c_int, vp, vp, vp],
                 "density_response_bz": [vp, G, vp, vp, vp, i32, i32, O, vp, i32, ctypes.c_int,
                                         vp, vp, vp],
+                "lrdm_bloch_hamiltonian_apply": [vp, G, vp, f64, f64, f64, vp, vp, i32,
+                                                 ctypes.c_int],
+                "chfsi_filter_bloch": [vp, G, vp, f64, f64, f64, vp, vp, i32, ctypes.c_int, i32,
+                                       f64, f64, f64],
                 "lrdm_residual_derivative": [vp, G, vp, vp, i32, O, vp, i32, ctypes.c_int, vp],
                 "density_response_backward": [vp, G, vp, vp, i32, O, vp, i32, ctypes.c_int, vp,
                                               vp, vp, vp],
@@ -143,7 +148,7 @@ def library() -> ctypes.CDLL:
                 "lrdm_density": [vp, G, vp, vp, i32, O, ctypes.c_int, vp, vp, vp],
                 "lrdm_effective_potential": [vp, G, vp, vp, i32, vp, vp, vp],
                 "lrdm_lda_xc": [vp, G, vp, i32, vp, vp],
-                "lrdm_autotune": [vp, G, i32, i32, i32, ctypes.c_int, vp, vp],
+                "lrdm_autotune": [vp, G, i32, i32, i32, ctypes.c_int, vp, vp, vp],
                 "lrdm_residual_derivative_xc": [vp, G, vp, vp, i32, O, vp, i32, ctypes.c_int, vp,
                                                 vp],
                 "lrdm_lowrank_step": [vp, G, vp, vp, i32, O, ctypes.c_int, vp,
@@ -370,6 +375,33 @@ def density_response(grid: Grid, Psi, eps, occ: Occupation, dV, prec="fp64", out
         _ptr(drho, "drho", torch.float64, r * ns * grid.M), _ptr(mu, "mu", torch.float64, 1),
         _ptr(dmu, "dmu", torch.float64, r)))
     return drho, mu, dmu
+
+
+def bloch_hamiltonian_apply(grid: Grid, V, X, kvec, prec="fp64", out=None):
+    """H_k X for blocks X [2][N][nz][ny][nx] (real parts, then imaginary parts)."""
+    N = X.shape[1]
+    Y = torch.empty_like(X) if out is None else out
+    ctx = context(X.device.index)
+    g = grid.c()
+    ctx.check(ctx.lib.lrdm_bloch_hamiltonian_apply(
+        ctx.ptr, ctypes.byref(g), _ptr(V, "V", torch.float64, grid.M), float(kvec[0]),
+        float(kvec[1]), float(kvec[2]), _ptr(X, "X", _block_dtype(prec), 2 * N * grid.M),
+        _ptr(Y, "Y", _block_dtype(prec), 2 * N * grid.M), N, _prec(prec)))
+    return Y
+
+
+def chfsi_filter_bloch(grid: Grid, V, X, kvec, degree, a, b, a0, prec="fp64", out=None):
+    """The Chebyshev filter with H_k on X [2][N][nz][ny][nx]; returns Y like X."""
+    N = X.shape[1]
+    Y = torch.empty_like(X) if out is None else out
+    ctx = context(X.device.index)
+    g = grid.c()
+    ctx.check(ctx.lib.chfsi_filter_bloch(
+        ctx.ptr, ctypes.byref(g), _ptr(V, "V", torch.float64, grid.M), float(kvec[0]),
+        float(kvec[1]), float(kvec[2]), _ptr(X, "X", _block_dtype(prec), 2 * N * grid.M),
+        _ptr(Y, "Y", _block_dtype(prec), 2 * N * grid.M), N, _prec(prec), int(degree), float(a),
+        float(b), float(a0)))
+    return Y
 
 
 def density_response_bz(grid: Grid, Psi, eps, weights, occ: Occupation, dV, prec="fp64",
@@ -620,14 +652,19 @@ def lowrank_step(grid: Grid, Psi, eps, occ: Occupation, R, params: LowRankParams
 
 
 def autotune(grid: Grid, N: int, nspin: int, r: int, prec="fp64", device=None):
-    """Pick the projection's K-split counts for this shape on the current
-    context (lrdm_autotune).  Returns dict(splits=[response, single direction,
-    Gram], ms=[[4 candidates] x 3], 0 where not tried)."""
+    """Pick the projection's layout of tiles and waves and its K-split counts for
+    this shape on the current context (lrdm_autotune).  Returns dict(splits=[3],
+    variants=[3], ms=[shape][layout][4 candidates]) for the shapes response,
+    single direction and Gram; 0 where not tried."""
     ctx = context(device)
     g = grid.c()
     splits = (ctypes.c_int32 * 3)()
-    ms = (ctypes.c_double * 12)()
+    variants = (ctypes.c_int32 * 3)()
+    ms = (ctypes.c_double * 36)()
     ctx.check(ctx.lib.lrdm_autotune(ctx.ptr, ctypes.byref(g), int(N), int(nspin), int(r),
                                     _prec(prec), ctypes.cast(splits, ctypes.c_void_p),
+                                    ctypes.cast(variants, ctypes.c_void_p),
                                     ctypes.cast(ms, ctypes.c_void_p)))
-    return dict(splits=list(splits), ms=[list(ms[4 * k:4 * k + 4]) for k in range(3)])
+    return dict(splits=list(splits), variants=list(variants),
+                ms=[[list(ms[12 * k + 4 * v:12 * k + 4 * v + 4]) for v in range(3)]
+                    for k in range(3)])

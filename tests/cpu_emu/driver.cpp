@@ -198,6 +198,50 @@ void scenario_response_bz(lrdm_ctx* ctx, lrdm_grid g, int N, int nk, int nspin, 
   if (!finite(drho)) { std::printf("FAIL non-finite drho\n"); ++failures; }
 }
 
+// Several uneven systems in one batched call (FP32: the fused launches), each
+// against its own single call (bounds; the batched and single results match).
+void scenario_batched(lrdm_ctx* ctx, lrdm_prec prec) {
+  const int nsys = 3;
+  const lrdm_grid gs[nsys] = {grid(8, 8, 8, 0.5), grid(12, 8, 8, 0.45), grid(8, 8, 6, 0.5)};
+  const int Ns[nsys] = {150, 40, 70}, rs[nsys] = {2, 3, 1};
+  std::vector<Block> psi;
+  std::vector<std::vector<double>> eps(nsys), dV(nsys), drho(nsys), one(nsys), mu(nsys),
+      dmu(nsys);
+  std::vector<lrdm_system> sys(nsys);
+  psi.reserve(nsys);
+  for (int s = 0; s < nsys; ++s) {
+    const int64_t M = (int64_t)gs[s].n[0] * gs[s].n[1] * gs[s].n[2];
+    std::vector<double> P;
+    for (int c = 0; c < 2; ++c) {
+      auto Q = orthonormal(Ns[s], M, 41 + 2 * s + c);
+      P.insert(P.end(), Q.begin(), Q.end());
+    }
+    psi.emplace_back(P, prec);
+    eps[s].resize(2 * Ns[s]);
+    for (int i = 0; i < 2 * Ns[s]; ++i) eps[s][i] = -2.0 + 2.5 * (i % Ns[s]) / Ns[s] + 0.01 * (i / Ns[s]);
+    dV[s] = randv((size_t)rs[s] * 2 * M, 43 + s);
+    drho[s].assign(dV[s].size(), 0.0);
+    one[s].assign(dV[s].size(), 0.0);
+    mu[s].assign(1, 0.0);
+    dmu[s].assign(rs[s], 0.0);
+    sys[s] = lrdm_system{gs[s], psi[s].data(), eps[s].data(), Ns[s], lrdm_occ{2, 0.01, 0.78 * Ns[s]},
+                         dV[s].data(), rs[s], drho[s].data(), mu[s].data(), dmu[s].data()};
+  }
+  char name[96];
+  std::snprintf(name, sizeof name, "density_response_batched %s, %d systems", prec_name(prec), nsys);
+  check(density_response_batched(ctx, sys.data(), nsys, prec), ctx, name);
+  for (int s = 0; s < nsys; ++s) {
+    std::vector<double> m1(1), d1(rs[s]);
+    check(density_response(ctx, &gs[s], psi[s].data(), eps[s].data(), Ns[s], &sys[s].occ,
+                           dV[s].data(), rs[s], prec, one[s].data(), m1.data(), d1.data()),
+          ctx, "density_response (one system)");
+    double worst = 0.0;
+    for (size_t i = 0; i < one[s].size(); ++i) worst = std::max(worst, std::fabs(one[s][i] - drho[s][i]));
+    std::printf("     system %d: batched vs single max diff %.2e\n", s, worst);
+    if (!(worst == 0.0) || !finite(drho[s])) ++failures;
+  }
+}
+
 void scenario_chfsi(lrdm_ctx* ctx, lrdm_grid g, int N, int degree, lrdm_prec prec = LRDM_FP64) {
   const int64_t M = (int64_t)g.n[0] * g.n[1] * g.n[2];
   auto V = randv((size_t)M, 3, 0.5);
@@ -427,13 +471,14 @@ void scenario_autotune(lrdm_ctx* ctx, lrdm_grid g, int N, int nspin, int r, lrdm
   std::vector<double> before(dV.size()), after(dV.size());
   check(density_response(ctx, &g, Psi.data(), eps.data(), N, &occ, dV.data(), r, prec,
                          before.data(), nullptr, nullptr), ctx, "density_response before tuning");
-  int32_t splits[3];
-  double ms[12];
+  int32_t splits[3], variants[3];
+  double ms[36];
   char name[128];
   std::snprintf(name, sizeof name, "lrdm_autotune %s N=%d nspin=%d r=%d", prec_name(prec), N,
                 nspin, r);
-  check(lrdm_autotune(ctx, &g, N, nspin, r, prec, splits, ms), ctx, name);
-  std::printf("     splits %d %d %d\n", splits[0], splits[1], splits[2]);
+  check(lrdm_autotune(ctx, &g, N, nspin, r, prec, splits, variants, ms), ctx, name);
+  std::printf("     splits %d %d %d, layouts %d %d %d\n", splits[0], splits[1], splits[2],
+              variants[0], variants[1], variants[2]);
   check(density_response(ctx, &g, Psi.data(), eps.data(), N, &occ, dV.data(), r, prec,
                          after.data(), nullptr, nullptr), ctx, "density_response after tuning");
   double num = 0, den = 0;
@@ -508,6 +553,10 @@ int main(int argc, char** argv) {
     scenario_response_bz(ctx, grid(9, 8, 7, 0.5), 70, 2, 1, 2, LRDM_FP64);
     scenario_response_bz(ctx, grid(9, 8, 7, 0.5), 70, 3, 2, 1, LRDM_FP32);
     scenario_response_bz(ctx, grid(8, 8, 8, 0.5), 70, 2, 1, 2, LRDM_BF16X3);
+  }
+  if (which == "all" || which == "batched") {
+    scenario_batched(ctx, LRDM_FP32);
+    scenario_batched(ctx, LRDM_FP64);
   }
   if (which == "all" || which == "full") scenario_full_n(ctx);
   check(lrdm_destroy(ctx), nullptr, "lrdm_destroy");

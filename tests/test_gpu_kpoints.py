@@ -106,3 +106,69 @@ def test_density_response_bz_gamma_is_the_real_path():
                                            to_dev(dV))
     assert rel(to_host(b), to_host(a)) < 1e-12
     assert abs(float(mu_a.item()) - float(mu_b.item())) < 1e-13
+
+
+# ------------------------------------------------------------------ Bloch Hamiltonian and filter
+def _bloch_block(g, N, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((N,) + g.shape) + 1j * rng.standard_normal((N,) + g.shape)
+
+
+@pytest.mark.parametrize("prec,bound", [("fp64", 1e-14), ("fp32", 1e-6)])
+@pytest.mark.parametrize("n,box", [((20, 18, 13), (8.0, 7.2, 5.2)), ((16, 16, 16), (7.0, 7.0, 7.0))])
+def test_bloch_hamiltonian_apply(n, box, prec, bound):
+    g = O.Grid(n, box)
+    V = np.random.default_rng(61).uniform(-1, 0, g.shape)
+    k = (0.37, -0.81, 1.23)
+    X = _bloch_block(g, 5, 62)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    Xd = to_dev(_realified(X[None, None])[0, 0], dt)
+    Xh = to_host(Xd)
+    Y = to_host(L.bloch_hamiltonian_apply(_grid(g), to_dev(V), Xd, k, prec=prec))
+    ref = O.bloch_hamiltonian_apply(Xh[0] + 1j * Xh[1], V, g, k)
+    assert rel(Y[0] + 1j * Y[1], ref) < bound
+
+
+def test_bloch_hamiltonian_at_k0_is_the_real_stencil():
+    g = O.Grid((20, 18, 13), (8.0, 7.2, 5.2))
+    V = np.random.default_rng(63).uniform(-1, 0, g.shape)
+    X = np.random.default_rng(64).standard_normal((4,) + g.shape)
+    Y = to_host(L.bloch_hamiltonian_apply(_grid(g), to_dev(V), to_dev(np.stack([X, 0 * X])),
+                                          (0.0, 0.0, 0.0)))
+    ref = to_host(L.hamiltonian_apply(_grid(g), to_dev(V), to_dev(X)))
+    assert rel(Y[0], ref) < 1e-15 and not Y[1].any()
+
+
+@pytest.mark.parametrize("degree", [1, 2, 7, 20])
+def test_chfsi_filter_bloch(degree):
+    g = O.Grid((20, 18, 13), (8.0, 7.2, 5.2))
+    V = small_wells(g.n, g.L, 65, nwells=3)
+    k = (0.5, -0.3, 0.9)
+    X = _bloch_block(g, 6, 66)
+    b = sum(2.0 / hd ** 2 for hd in g.h) + float(V.max())
+    a0 = float(V.min()) - 0.1
+    a = a0 + 0.25 * (b - a0)
+    Y = to_host(L.chfsi_filter_bloch(_grid(g), to_dev(V), to_dev(np.stack([X.real, X.imag])), k,
+                                     degree, a, b, a0))
+    ref = O.chebyshev_filter_bloch(X, V, g, k, degree, a, b, a0)
+    assert rel(Y[0] + 1j * Y[1], ref) < 1e-12
+
+
+def test_bloch_chfsi_reaches_the_lowest_states():
+    """ChFSI of one k-point: the GPU Bloch filter with the oracle's complex
+    Rayleigh-Ritz between passes converges to the lowest eigenvalues of H_k from
+    dense diagonalisation."""
+    g = O.Grid((8, 7, 6), (4.0, 3.5, 3.0))
+    V = small_wells(g.n, g.L, 67, nwells=2)
+    k = (0.3, -0.5, 0.2)
+    e_ref, _ = O.lowest_bloch_states(V, g, k, 16)
+    X = _bloch_block(g, 16, 68)
+    b = sum(2.0 / hd ** 2 for hd in g.h) + float(V.max())
+    a0 = float(V.min()) - 0.1
+    a = a0 + 0.25 * (b - a0)
+    for _ in range(14):
+        Y = to_host(L.chfsi_filter_bloch(_grid(g), to_dev(V), to_dev(np.stack([X.real, X.imag])),
+                                         k, 12, a, b, a0))
+        eps, X = O.rayleigh_ritz_bloch(Y[0] + 1j * Y[1], V, g, k)
+        a, a0 = float(eps[-1]), float(eps[0]) - 0.1
+    assert np.max(np.abs(eps[:12] - e_ref[:12])) < 1e-9

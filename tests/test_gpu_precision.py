@@ -201,10 +201,10 @@ def test_autotune_keeps_the_response(c24, form):
     before, _, _ = L.density_response(grid, P, to_dev(eps[None]), occ, to_dev(dV), prec=form)
     before = to_host(before)
     tuned = L.autotune(grid, wl.N, 1, 4, prec=form)
-    print(f"{form}: splits {tuned['splits']}, ms {tuned['ms']}")
+    print(f"{form}: splits {tuned['splits']}, layouts {tuned['variants']}, ms {tuned['ms']}")
     after, _, _ = L.density_response(grid, P, to_dev(eps[None]), occ, to_dev(dV), prec=form)
     after = to_host(after)
-    assert rel(after, before) < (1e-13 if form == "fp64" else 1e-7)
+    assert rel(after, before) < (1e-13 if form == "fp64" else 1e-6)
     ref, _, _ = O.density_response(to_host(P), eps[None], g, wl.n_electrons, wl.kT, dV, 1)
     assert rel(after, ref) < (1e-10 if form == "fp64" else BOUND[form])
     assert all(s >= 1 for s in tuned["splits"])
