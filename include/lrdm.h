@@ -291,6 +291,25 @@ lrdm_status density_response_bz(lrdm_ctx* ctx, const lrdm_grid* grid, const void
                                 const lrdm_occ* occ, const double* dV, int32_t r, lrdm_prec prec,
                                 double* drho, double* mu, double* dmu);
 
+/* density_response for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, results and errors as density_response, but every intermediate
+ * lives in a fixed scratch array of 256 MiB per GPU, part of the library's
+ * device image (held from the first use of the library on that GPU until the
+ * process ends); the call allocates nothing and never grows the context's
+ * workspace.  When the intermediates would not fit, the projection's K-split
+ * count is lowered (this changes only the order of its FP64 partial sums); a
+ * problem that still needs more than 256 MiB returns LRDM_EINVAL with the
+ * bytes it needs, before any launch (FP64 on a 48^3 grid with 256 states and 8
+ * directions fits; the FP32-storage forms also need a transposed copy of Psi).
+ * All calls on one GPU share its scratch array: calls that overlap on one GPU
+ * (on different streams or contexts) race and must be ordered by the caller.
+ * Timing (lrdm_profile) is not recorded for these calls.  In checking mode
+ * (lrdm_set_checks) the call synchronises, which graph capture does not allow. */
+lrdm_status density_response_noalloc(lrdm_ctx* ctx, const lrdm_grid* grid, const void* Psi,
+                                     const double* eps, int32_t N, const lrdm_occ* occ,
+                                     const double* dV, int32_t r, lrdm_prec prec, double* drho,
+                                     double* mu, double* dmu);
 
 /* Gateaux derivative of the SCF residual along u_k (Eq. (7)) with
  * J = chi0 K - I (Eq. (3)) and K = K_c: every channel sees

@@ -171,8 +171,8 @@ ProfScope::~ProfScope() {
   ctx_->prof.push_back({name_, start_, stop});
 }
 
-size_t tn_bytes(int N, int64_t M, int batch, lrdm_prec prec) {
-  return tn_workspace_bytes(N, M, batch, prec);
+size_t tn_bytes(int N, int64_t M, int batch, lrdm_prec prec, int split_limit = 0) {
+  return tn_workspace_bytes(N, M, batch, prec, split_limit);
 }
 
 }  // namespace lrdm
@@ -205,6 +205,12 @@ extern "C" lrdm_status lrdm_create(lrdm_ctx** ctx, int device, void* hip_stream,
     return fail_hip(nullptr, "hipMemset status", e);
   }
   c->zeros = reinterpret_cast<const float*>(c->dstatus + 32);
+  {
+    // the allocation-free entry point's scratch address on this device, looked up
+    // once per device at set-up (a failure is reported by that entry point)
+    void* scratch = nullptr;
+    (void)noalloc_scratch(device, &scratch);
+  }
   for (int k = 0; k < kAuxStreams; ++k) {
     hipStream_t st = nullptr;
     e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
@@ -625,12 +631,13 @@ size_t backward_bytes(int N, int64_t M, int r, int ns, lrdm_prec prec) {
          ws_align((size_t)batch * M * 8) + ws_align(scratch) + 4096;
 }
 
-size_t response_bytes(int N, int64_t M, int r, int ns, lrdm_prec prec) {
+size_t response_bytes(int N, int64_t M, int r, int ns, lrdm_prec prec, int split_limit = 0) {
   const int batch = r * ns;
   return ws_align(8) + ws_align((size_t)r * 8) + 3 * ws_align((size_t)ns * N * 8) +
          block_mask_bytes(N, ns) +
          ws_align((size_t)ns * N * N * 8) + ws_align((size_t)batch * N * N * 8) +
-         ws_align(tn_bytes(N, M, batch, prec)) + backproj_workspace_bytes(N, M, ns, batch, prec);
+         ws_align(tn_bytes(N, M, batch, prec, split_limit)) +
+         backproj_workspace_bytes(N, M, ns, batch, prec);
 }
 
 }  // namespace
@@ -792,6 +799,84 @@ extern "C" lrdm_status density_response(lrdm_ctx* ctx, const lrdm_grid* grid, co
         : run_response<float>(ctx, g, static_cast<const float*>(Psi), eps, N, occ, dV, r, prec,
                               nullptr, drho, mu, dmu);
     return e == hipSuccess ? LRDM_OK : fail_hip(ctx, "density_response", e);
+  });
+}
+
+// The context's workspace, split limit and profiling switch, replaced for the
+// duration of one allocation-free call and put back afterwards.
+struct ScratchSwap {
+  lrdm_ctx* ctx;
+  void* ws;
+  size_t cap, top;
+  int split_limit;
+  bool profiling;
+  ScratchSwap(lrdm_ctx* c, void* scratch, size_t bytes, int limit)
+      : ctx(c), ws(c->ws), cap(c->ws_cap), top(c->ws_top), split_limit(c->split_limit),
+        profiling(c->profiling) {
+    c->ws = scratch;
+    c->ws_cap = bytes;
+    c->ws_top = 0;
+    c->split_limit = limit;
+    c->profiling = false;     // timing events are created on demand: not here
+  }
+  ~ScratchSwap() {
+    ctx->ws = ws;
+    ctx->ws_cap = cap;
+    ctx->ws_top = top;
+    ctx->split_limit = split_limit;
+    ctx->profiling = profiling;
+  }
+};
+
+extern "C" lrdm_status density_response_noalloc(lrdm_ctx* ctx, const lrdm_grid* grid,
+                                                const void* Psi, const double* eps, int32_t N,
+                                                const lrdm_occ* occ, const double* dV, int32_t r,
+                                                lrdm_prec prec, double* drho, double* mu,
+                                                double* dmu) {
+  LRDM_CHECK(ctx, check_grid(grid));
+  LRDM_CHECK(ctx, check_block(grid, N));
+  LRDM_CHECK(ctx, check_occ(occ, N));
+  LRDM_CHECK(ctx, check_rank(r));
+  LRDM_CHECK(ctx, check_prec(prec));
+  LRDM_NONNULL(ctx, Psi, "Psi");
+  LRDM_NONNULL(ctx, eps, "eps");
+  LRDM_NONNULL(ctx, dV, "dV");
+  LRDM_NONNULL(ctx, drho, "drho");
+  if (!ctx) return fail(nullptr, LRDM_EINVAL, "ctx is NULL");
+  const Grid3 g = make_grid3(grid);
+  const size_t cap = noalloc_scratch_bytes();
+  const int ns = occ->nspin;
+  // fewer K-splits shrink the projection's partial sums until the call fits
+  int limit = 0;
+  size_t need = response_bytes(N, g.M, r, ns, prec) + (1u << 20);
+  if (need > cap) {
+    const int ntb = (N + 127) / 128;
+    for (limit = tn_split_cap(ntb * (ntb + 1) / 2 * r * ns, g.M); limit > 1 && need > cap;
+         limit /= 2)
+      need = response_bytes(N, g.M, r, ns, prec, limit / 2) + (1u << 20);
+    limit = std::max(limit, 1);
+  }
+  if (need > cap) {
+    char msg[200];
+    std::snprintf(msg, sizeof msg,
+                  "this response needs %zu bytes of scratch, more than the %zu the "
+                  "allocation-free entry point holds per GPU: use density_response",
+                  need, cap);
+    return fail(ctx, LRDM_EINVAL, msg);
+  }
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return fail_hip(ctx, "hipSetDevice", e);
+  void* scratch = nullptr;
+  e = noalloc_scratch(ctx->device, &scratch);
+  if (e != hipSuccess || !scratch) return fail_hip(ctx, "scratch symbol address", e);
+  ScratchSwap swap(ctx, scratch, cap, limit);
+  return guarded(ctx, [&]() -> lrdm_status {
+    hipError_t e2 = (prec == LRDM_FP64)
+        ? run_response<double>(ctx, g, static_cast<const double*>(Psi), eps, N, occ, dV, r, prec,
+                               nullptr, drho, mu, dmu)
+        : run_response<float>(ctx, g, static_cast<const float*>(Psi), eps, N, occ, dV, r, prec,
+                              nullptr, drho, mu, dmu);
+    return e2 == hipSuccess ? LRDM_OK : fail_hip(ctx, "density_response_noalloc", e2);
   });
 }
 

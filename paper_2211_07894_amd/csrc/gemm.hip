@@ -492,10 +492,11 @@ __global__ __launch_bounds__(256, 2) void adj_psi_f64_kernel(
 
 }  // namespace
 
-size_t tn_part_bytes(int N, int64_t M, int batch) {
+size_t tn_part_bytes(int N, int64_t M, int batch, int split_limit) {
   const int ntb = (N + BT - 1) / BT;
   const int ntiles = ntb * (ntb + 1) / 2;
-  const int ns = tn_split_cap(ntiles * batch, M);
+  int ns = tn_split_cap(ntiles * batch, M);
+  if (split_limit > 0) ns = std::min(ns, split_limit);
   return (size_t)batch * ns * ntiles * BT * BT * sizeof(double);
 }
 
@@ -503,9 +504,11 @@ int tn_split_count(const lrdm_ctx* ctx, int N, int64_t M, int batch, int arith, 
   const int ntb = (N + BT - 1) / BT;
   const int ntiles = ntb * (ntb + 1) / 2;
   const auto it = ctx->tn_tuned.find({N, M, batch, arith, weighted ? 1 : 0});
+  int s = tn_splits(ntiles * batch, M);
   if (it != ctx->tn_tuned.end() && it->second >= 1 && it->second <= tn_split_cap(ntiles * batch, M))
-    return it->second;
-  return tn_splits(ntiles * batch, M);
+    s = it->second;
+  if (ctx->split_limit > 0) s = std::min(s, ctx->split_limit);
+  return s;
 }
 
 int tn_variant(const lrdm_ctx* ctx, int N, int64_t M, int batch, int arith, bool weighted) {
@@ -513,8 +516,8 @@ int tn_variant(const lrdm_ctx* ctx, int N, int64_t M, int batch, int arith, bool
   return it == ctx->tn_variant.end() ? TN_VAR_DEFAULT : it->second;
 }
 
-size_t tn_workspace_bytes(int N, int64_t M, int batch, lrdm_prec prec) {
-  return ws_align(tn_part_bytes(N, M, batch)) + tn_split_bytes(N, M, prec);
+size_t tn_workspace_bytes(int N, int64_t M, int batch, lrdm_prec prec, int split_limit) {
+  return ws_align(tn_part_bytes(N, M, batch, split_limit)) + tn_split_bytes(N, M, prec);
 }
 
 template <typename SA, typename SB>
@@ -526,7 +529,7 @@ hipError_t launch_tn_sym_f64(lrdm_ctx* ctx, const SA* A, const SB* B, const doub
   const int ns = tn_split_count(ctx, N, M, batch, TN_ARITH_F64, w != nullptr);
   int64_t kchunk = (M + ns - 1) / ns;
   kchunk = (kchunk + KT - 1) / KT * KT;
-  double* part = static_cast<double*>(ws_take(ctx, tn_part_bytes(N, M, batch)));
+  double* part = static_cast<double*>(ws_take(ctx, tn_part_bytes(N, M, batch, ctx->split_limit)));
   const unsigned grd = (unsigned)(ntiles * ns * batch);
   {
     ProfScope prof(ctx, w ? "proj" : "gram");

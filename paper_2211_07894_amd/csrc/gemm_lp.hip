@@ -1397,7 +1397,7 @@ hipError_t launch_tn_sym<float>(lrdm_ctx* ctx, const float* A, const float* B, c
                                 prec == LRDM_BF16X3 ? TN_ARITH_BF16X3 : TN_ARITH_F32, w != nullptr);
   int64_t kchunk = (M + ns - 1) / ns;
   kchunk = (kchunk + KT - 1) / KT * KT;
-  double* part = static_cast<double*>(ws_take(ctx, tn_part_bytes(N, M, batch)));
+  double* part = static_cast<double*>(ws_take(ctx, tn_part_bytes(N, M, batch, ctx->split_limit)));
   if (!B) B = A;
   auto a16 = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
   // the pipelined kernel copies 16-byte chunks of rows: rows must start aligned

@@ -42,6 +42,7 @@ struct lrdm_ctx {
   int fermi_depth = 0;       // 0: exact divided differences; T > 0: recursive expansion
   int eigh_max_sweeps = 40;  // block Jacobi sweeps before the eigensolver gives up
   double block_tau = 1e-14;  // response blocks with max |F| below tau max |F| are skipped
+  int split_limit = 0;       // > 0: cap on the projection's K-split count (allocation-free calls)
   lrdm_psi_pieces pieces;
   // K-split counts of the projection contraction chosen by lrdm_autotune, keyed by
   // (N, M, batch, arithmetic, weighted)
@@ -206,9 +207,10 @@ hipError_t launch_recursive_multiplier(lrdm_ctx* ctx, const double* eps, const d
 // only the upper triangle is formed and mirrored (the callers' products are
 // symmetric).  B == nullptr means B = A; w == nullptr means w = 1.
 // A, B: nspin blocks of [N][M].
-size_t tn_workspace_bytes(int N, int64_t M, int batch, lrdm_prec prec);
+// split_limit > 0 caps the K-split count (and with it the partial sums' size).
+size_t tn_workspace_bytes(int N, int64_t M, int batch, lrdm_prec prec, int split_limit = 0);
 size_t tn_split_bytes(int N, int64_t M, lrdm_prec prec);
-size_t tn_part_bytes(int N, int64_t M, int batch);
+size_t tn_part_bytes(int N, int64_t M, int batch, int split_limit = 0);
 // Split count of the K = M contraction: enough blocks to fill 256 CUs several
 // times over, with each split at least 4096 grid points long.
 inline int tn_splits(int tiles_x_batch, int64_t M) {
@@ -224,6 +226,12 @@ inline int tn_split_cap(int tiles_x_batch, int64_t M) {
   while (c > h && M / c < 2048) c /= 2;
   return c;
 }
+// The allocation-free entry point's device scratch (noalloc.hip): its size, and
+// the device address of `device`'s copy (looked up once per device, with that
+// device current).
+size_t noalloc_scratch_bytes();
+hipError_t noalloc_scratch(int device, void** out);
+
 // Arithmetic of a projection contraction, part of the autotuner's key.
 enum { TN_ARITH_F64 = 0, TN_ARITH_F32 = 1, TN_ARITH_BF16X3 = 2 };
 // Kernel variants of the FP32-storage projection (tile and wave layout):

@@ -34,6 +34,7 @@ EXPORTED = [
     "lrdm_lda_xc", "lrdm_residual_derivative_xc", "lrdm_autotune",
     "lrdm_set_eigensolver_sweeps", "lrdm_set_response_block_skip", "density_response_bz",
     "lrdm_bloch_hamiltonian_apply", "chfsi_filter_bloch",
+    "density_response_noalloc",
 ]
 
 
@@ -141,6 +142,8 @@ def library() -> ctypes.CDLL:
                                                  ctypes.c_int],
                 "chfsi_filter_bloch": [vp, G, vp, f64, f64, f64, vp, vp, i32, ctypes.c_int, i32,
                                        f64, f64, f64],
+                "density_response_noalloc": [vp, G, vp, vp, i32, O, vp, i32, ctypes.c_int, vp, vp,
+                                             vp],
                 "lrdm_residual_derivative": [vp, G, vp, vp, i32, O, vp, i32, ctypes.c_int, vp],
                 "density_response_backward": [vp, G, vp, vp, i32, O, vp, i32, ctypes.c_int, vp,
                                               vp, vp, vp],

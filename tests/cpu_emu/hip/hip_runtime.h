@@ -31,6 +31,9 @@
 #define __forceinline__ inline
 #define __launch_bounds__(...)
 #define __shared__ static thread_local
+#define __align__(n) __attribute__((aligned(n)))
+// a device variable's address on the host: the variable itself in this build
+#define HIP_SYMBOL(x) (&(x))
 #define __HIPCC__ 1
 
 // ------------------------------------------------------------------ runtime types
@@ -39,6 +42,7 @@ typedef enum {
   hipErrorInvalidValue = 1,
   hipErrorOutOfMemory = 2,
   hipErrorNotSupported = 801,
+  hipErrorInvalidDevice = 101,
   hipErrorIllegalAddress = 700,
 } hipError_t;
 typedef void* hipStream_t;
@@ -292,6 +296,10 @@ inline hipError_t hipStreamIsCapturing(hipStream_t, hipStreamCaptureStatus* c) {
 }
 inline hipError_t hipDeviceSynchronize() { return hipSuccess; }
 inline hipError_t hipFuncSetAttribute(const void*, hipFuncAttribute, int) { return hipSuccess; }
+inline hipError_t hipGetSymbolAddress(void** p, const void* symbol) {
+  *p = const_cast<void*>(symbol);
+  return hipSuccess;
+}
 inline hipError_t hipEventCreate(hipEvent_t* e) { *e = new lrdm_emu_event(); return hipSuccess; }
 inline hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned) { return hipEventCreate(e); }
 inline hipError_t hipEventDestroy(hipEvent_t e) { delete e; return hipSuccess; }
