@@ -147,6 +147,14 @@ lrdm_status lrdm_set_response_block_skip(lrdm_ctx* ctx, double tau);
  * LRDM_ENOTCONV, at any checking level, and leaves Psi and eps undefined. */
 lrdm_status lrdm_set_eigensolver_sweeps(lrdm_ctx* ctx, int32_t max_sweeps);
 
+/* Layout of the BF16X3 back-projection (Eqs. (16), (20)).  1 (the default):
+ * 256 grid points per workgroup, each staged tile of Gamma's pieces serving
+ * twice as many points, and each row block of Gamma's products summed in FP32
+ * before the FP64 fold with Psi; 0: 128 points per workgroup, FP32 partials
+ * added into FP64 once per 128 x 128 block.  The results agree to FP32
+ * rounding of 128- to N-term partial sums.  Other values: LRDM_EINVAL. */
+lrdm_status lrdm_set_backproj_layout(lrdm_ctx* ctx, int32_t layout);
+
 /* Bytes of device workspace the context currently holds. */
 size_t lrdm_workspace_bytes(const lrdm_ctx* ctx);
 

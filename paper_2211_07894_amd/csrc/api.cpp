@@ -290,6 +290,14 @@ extern "C" lrdm_status lrdm_set_response_block_skip(lrdm_ctx* ctx, double tau) {
   return LRDM_OK;
 }
 
+extern "C" lrdm_status lrdm_set_backproj_layout(lrdm_ctx* ctx, int32_t layout) {
+  if (!ctx) return fail(nullptr, LRDM_EINVAL, "ctx is NULL");
+  if (layout != BP_VAR_NARROW && layout != BP_VAR_WIDE)
+    return fail(ctx, LRDM_EINVAL, "layout must be 0 (128 points) or 1 (256 points)");
+  ctx->bp_variant = layout;
+  return LRDM_OK;
+}
+
 extern "C" size_t lrdm_workspace_bytes(const lrdm_ctx* ctx) { return ctx ? ctx->ws_cap : 0; }
 
 extern "C" lrdm_status lrdm_profile(lrdm_ctx* ctx, int enable) {

@@ -980,9 +980,11 @@ __global__ __launch_bounds__(256) void transpose_split3_kernel(const float* __re
   }
 }
 
-// G3[b][q][i][j] = piece q of (float)G[b][i][j] for j < N, 0 for N <= j < ldk.
+// G3[b][q][i][j] = piece q of (float)G[b][i][j] for j < N, 0 for N <= j < ldk;
+// with upper2, entries of the blocks right of the diagonal block (j / 128 > i /
+// 128) are doubled (exact: the pieces of 2x are twice the pieces of x).
 __global__ void gamma_split3_kernel(const double* __restrict__ G, __bf16* __restrict__ G3, int N,
-                                    int ldk, int batch) {
+                                    int ldk, int batch, int upper2) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t per = (int64_t)N * ldk;
   if (idx >= (int64_t)batch * per) return;
@@ -990,6 +992,7 @@ __global__ void gamma_split3_kernel(const double* __restrict__ G, __bf16* __rest
   const int j = (int)(rem % ldk);
   const int64_t i = rem / ldk;
   float x = j < N ? (float)G[(b * N + i) * N + j] : 0.f;
+  if (upper2 && j / BT > i / BT) x *= 2.f;
   __bf16* out = G3 + b * 3 * per + rem;
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
@@ -1071,10 +1074,38 @@ __global__ __launch_bounds__(PT, 1) void tn_sym_p3_kernel(
   const int nk = kbeg < kend ? (int)((kend - kbeg + KT - 1) / KT) : 0;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int wr = wid >> 1, wc = wid & 1;
+  // Per-lane source addresses of a full K-tile (k0 + KT <= kend) are base + k0:
+  // the copy slots of dma_tile / dma_piece with rows past N reading row N - 1
+  // instead of zeros (their products land in rows or columns of the partial
+  // tile the reduction never reads), so the loop spends one address add per
+  // copy.  The last, partial K-tile takes the checked copies.
+  const float* abase[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int r = (wid * 2 + u) * 8 + (lane >> 3);
+    const int q = (lane & 7) ^ tile_swizzle(r);
+    abase[u] = Ac + (int64_t)min(ti * BT + r, N - 1) * M + 4 * q;
+  }
+  const __bf16* pbase;
+  {
+    const int r = wid * 16 + (lane >> 2);
+    const int q = (lane & 3) ^ piece_swizzle(r);
+    pbase = Pc + (int64_t)min(tj * BT + r, N - 1) * M + 8 * q;
+  }
+  const double* wbase = wb + 2 * (lane & 15);
   // copies per stage and wave: 2 (A) + 3 (pieces of B), plus the weights in wave 0
   auto issue = [&](int t) {
     unsigned char* st = smem_pipe + (t % NST) * SB;
     const int64_t k0 = kbeg + (int64_t)t * KT;
+    if (t < nk && k0 + KT <= kend) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) dma16(abase[u] + k0, st + (wid * 2 + u) * 1024);
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        dma16(pbase + (int64_t)q * N * M + k0, st + TB + q * PB + wid * 1024);
+      if (wid == 0) dma16(wbase + k0, st + TB + 3 * PB);
+      return;
+    }
     const int64_t ke = t < nk ? kend : k0;
     dma_tile(Ac, M, N, (int64_t)ti * BT, k0, ke, zeros, st, wid, lane);
 #pragma unroll
@@ -1266,6 +1297,156 @@ __global__ __launch_bounds__(PT, 1) void backproj_p3_kernel(
     double v = 0.0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) v += red[(2 * q + wcc) * 64 + cl];
+    const int64_t p = p0 + col;
+    if (p < M) {
+      double r = scale * v;
+      if (sub) r -= sub[(int64_t)b * M + p];
+      out[(int64_t)b * M + p] = r;
+    }
+  }
+}
+
+// Back-projection, BF16X3, wide point tiles: as backproj_p3_kernel, but each
+// workgroup owns 256 grid points (twice the points per staged Gamma tile, so
+// each direction's Gamma pieces are read half as often) and each of its eight
+// waves a 64 x 64 part (rows of Gamma x points), so every LDS fragment feeds
+// four matrix products instead of two.  Gamma's pieces come with the blocks
+// right of the diagonal doubled (gamma_split3_kernel, upper2), so a row block's
+// products accumulate in FP32 over all its active blocks and meet Psi once, in
+// FP64, at the end of the row block.  Two ring stages (72 KB each); the first
+// K-tile of the next active row block is in flight while the current one's
+// products are folded with Psi.
+constexpr int BPW = 2 * BT;               // points per workgroup
+constexpr int SBW = 9 * PB;               // one stage: 3 Gamma pieces, 3 x 2 Psi^T pieces
+
+__global__ __launch_bounds__(PT, 1) void backproj_p3w_kernel(
+    const float* __restrict__ A, const __bf16* __restrict__ PT3, const __bf16* __restrict__ G3,
+    int N, int64_t M, int ldk, int nspin, int batch, double scale, const double* __restrict__ sub,
+    const unsigned char* __restrict__ active, const float* __restrict__ zeros,
+    double* __restrict__ out) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_pipe[];
+  double* red = reinterpret_cast<double*>(smem_pipe + 2 * SBW);   // [PW][64]
+  int pblk, b;
+  xcd_map(blockIdx.x, (int)((M + BPW - 1) / BPW), batch, pblk, b);
+  const int c = b % nspin;
+  const float* Ac = A + (int64_t)c * N * M;
+  const int64_t gplane = (int64_t)N * ldk, pplane = M * ldk;
+  const __bf16* Gb = G3 + (int64_t)b * 3 * gplane;
+  const __bf16* Pb = PT3 + (int64_t)c * 3 * pplane;
+  const int64_t p0 = (int64_t)pblk * BPW;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int wr = wid >> 2, wc = wid & 3;          // rows wr*64.., points wc*64..
+  const int nib = (N + BT - 1) / BT;
+  // next row block at or after ib with active K-tiles (nib when none)
+  auto next_row = [&](int ib, uint64_t& bits, int& nk) {
+    for (; ib < nib; ++ib) {
+      bits = active_row_bits(active, c, nib, ib);
+      nk = active_ktiles(bits, N, KT);
+      if (nk > 0) return ib;
+    }
+    return nib;
+  };
+  // This lane's copy slot of a piece tile (dma_piece): row wid * 16 + lane / 4,
+  // 16-byte chunk q; every K-tile lies inside [0, ldk), and rows past N (Gamma)
+  // or M (Psi^T) read the last row instead of zeros (their products land in rows
+  // or points that fold() masks), so a copy's address is base + j0.
+  const int slot_r = wid * 16 + (lane >> 2);
+  const int slot_k = 8 * ((lane & 3) ^ piece_swizzle(slot_r));
+  const __bf16* pbase[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+    pbase[h] = Pb + min(p0 + h * BT + slot_r, M - 1) * ldk + slot_k;
+  // K-tile t of row block ib into ring stage s
+  auto issue = [&](int ib, uint64_t bits, int t, int s) {
+    unsigned char* st = smem_pipe + s * SBW;
+    int J;
+    const int64_t j0 = active_ktile(bits, t, KT, J);
+    const __bf16* gbase = Gb + (int64_t)min(ib * BT + slot_r, N - 1) * ldk + slot_k + j0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      dma16(gbase + q * gplane, st + q * PB + wid * 1024);
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        dma16(pbase[h] + q * pplane + j0, st + (3 + 2 * q + h) * PB + wid * 1024);
+    }
+  };
+  double dsum[4] = {0.0, 0.0, 0.0, 0.0};
+  uint64_t bits = 0;
+  int nk = 0;
+  int ib = next_row(0, bits, nk);
+  int s = 0;                                      // ring stage of the next K-tile
+  if (ib < nib) issue(ib, bits, 0, s);
+  while (ib < nib) {
+    uint64_t nbits = 0;
+    int nnk = 0;
+    const int nib2 = next_row(ib + 1, nbits, nnk);
+    f4 cc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) cc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < nk; ++t) {
+      // this stage's copies have landed for every wave, and every wave has read
+      // the other stage (its previous K-tile) into registers
+      wait_stage<0>();
+      const unsigned char* st = smem_pipe + s * SBW;
+      bf8 pa[4][3], pb[4][3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        bf8 va[4], vb[4];
+        frag_piece<4>(st + q * PB, wr * 64, lane, va);
+        frag_piece<4>(st + (3 + 2 * q + (wc >> 1)) * PB, (wc & 1) * 64, lane, vb);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) pa[i][q] = va[i];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) pb[j][q] = vb[j];
+      }
+      compiler_fence();
+      s ^= 1;
+      if (t + 1 < nk)
+        issue(ib, bits, t + 1, s);
+      else if (nib2 < nib)
+        issue(nib2, nbits, 0, s);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) cc[i][j] = mfma6(pa[i], pb[j], cc[i][j]);
+    }
+    // fold the row block's products with Psi: sum_i Psi_ip (Gamma Psi)_ip
+    const int i0 = ib * BT;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gi = i0 + wr * 64 + i * 16 + 4 * (lane >> 4) + v;
+        const int gic = min(gi, N - 1);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int64_t p = p0 + wc * 64 + j * 16 + (lane & 15);
+          const float a = Ac[(int64_t)gic * M + min(p, M - 1)];
+          if (gi < N && p < M) dsum[j] += (double)cc[i][j][v] * (double)a;
+        }
+      }
+    ib = nib2;
+    bits = nbits;
+    nk = nnk;
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    double v = dsum[j];
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    dsum[j] = v;
+  }
+  if (lane < 16) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) red[wid * 64 + j * 16 + lane] = dsum[j];
+  }
+  __syncthreads();
+  if (threadIdx.x < BPW) {
+    const int col = threadIdx.x;
+    const int wcc = col >> 6, cl = col & 63;
+    const double v = red[wcc * 64 + cl] + red[(4 + wcc) * 64 + cl];
     const int64_t p = p0 + col;
     if (p < M) {
       double r = scale * v;
@@ -1481,8 +1662,9 @@ hipError_t launch_backproj<float>(lrdm_ctx* ctx, const float* A, const double* G
   if (prec == LRDM_BF16X3) {
     const int64_t nG = (int64_t)batch * N * ldk;
     __bf16* G3 = static_cast<__bf16*>(ws_take(ctx, (size_t)nG * 3 * sizeof(__bf16)));
+    const bool wide = ctx->bp_variant == BP_VAR_WIDE;   // Gamma's upper blocks doubled
     gamma_split3_kernel<<<(unsigned)((nG + 255) / 256), 256, 0, ctx->stream>>>(G, G3, N, ldk,
-                                                                              batch);
+                                                                              batch, wide);
     LRDM_HIP(hipGetLastError());
     const lrdm_psi_pieces& pc = ctx->pieces;
     const __bf16* PT3 = nullptr;
@@ -1494,6 +1676,16 @@ hipError_t launch_backproj<float>(lrdm_ctx* ctx, const float* A, const double* G
       transpose_split3_kernel<<<gt, 256, 0, ctx->stream>>>(A, P, N, M, ldk);
       LRDM_HIP(hipGetLastError());
       PT3 = P;
+    }
+    if (wide) {
+      const int smem = 2 * SBW + PW * 64 * (int)sizeof(double);
+      LRDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&backproj_p3w_kernel),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, smem));
+      const unsigned grdw = (unsigned)((M + BPW - 1) / BPW * batch);
+      ProfScope prof(ctx, "backproj");
+      backproj_p3w_kernel<<<grdw, PT, smem, ctx->stream>>>(A, PT3, G3, N, M, ldk, nspin, batch,
+                                                           scale, sub, active, ctx->zeros, out);
+      return hipGetLastError();
     }
     const int smem = NST * 6 * PB + PW * 64 * (int)sizeof(double);
     LRDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&backproj_p3_kernel),

@@ -42,6 +42,7 @@ struct lrdm_ctx {
   int fermi_depth = 0;       // 0: exact divided differences; T > 0: recursive expansion
   int eigh_max_sweeps = 40;  // block Jacobi sweeps before the eigensolver gives up
   double block_tau = 1e-14;  // response blocks with max |F| below tau max |F| are skipped
+  int bp_variant = 1;        // BF16X3 back-projection layout (BP_VAR_*)
   int split_limit = 0;       // > 0: cap on the projection's K-split count (allocation-free calls)
   lrdm_psi_pieces pieces;
   // K-split counts of the projection contraction chosen by lrdm_autotune, keyed by
@@ -243,6 +244,12 @@ enum { TN_ARITH_F64 = 0, TN_ARITH_F32 = 1, TN_ARITH_BF16X3 = 2 };
 //  TN_VAR_SPLIT    BF16X3 only: the ring kernel splitting both operands in the
 //                  kernel (no pre-split copy of Psi).
 enum { TN_VAR_DEFAULT = 0, TN_VAR_STAGED = 1, TN_VAR_SPLIT = 2 };
+// Layouts of the BF16X3 back-projection:
+//  BP_VAR_NARROW  128 points per workgroup, 8 waves of 32 x 64, three ring stages,
+//                 FP32 partials added into FP64 once per 128 x 128 block
+//  BP_VAR_WIDE    256 points per workgroup, 8 waves of 64 x 64, two ring stages,
+//                 FP32 sums over a whole row block of Gamma
+enum { BP_VAR_NARROW = 0, BP_VAR_WIDE = 1 };
 int tn_variant(const lrdm_ctx* ctx, int N, int64_t M, int batch, int arith, bool weighted);
 // The split count a projection launch uses: the autotuned one for this shape if
 // lrdm_autotune chose one, else tn_splits.

@@ -34,7 +34,7 @@ EXPORTED = [
     "lrdm_lda_xc", "lrdm_residual_derivative_xc", "lrdm_autotune",
     "lrdm_set_eigensolver_sweeps", "lrdm_set_response_block_skip", "density_response_bz",
     "lrdm_bloch_hamiltonian_apply", "chfsi_filter_bloch",
-    "density_response_noalloc",
+    "density_response_noalloc", "lrdm_set_backproj_layout",
 ]
 
 
@@ -125,6 +125,7 @@ def library() -> ctypes.CDLL:
                 "lrdm_set_fermi_expansion": [vp, i32],
                 "lrdm_set_eigensolver_sweeps": [vp, i32],
                 "lrdm_set_response_block_skip": [vp, f64],
+                "lrdm_set_backproj_layout": [vp, i32],
                 "lrdm_workspace_bytes": [vp],
                 "lrdm_profile": [vp, ctypes.c_int],
                 "lrdm_profile_read": [vp, ctypes.c_char_p, ctypes.POINTER(f64), ctypes.POINTER(ctypes.c_int64)],
@@ -199,6 +200,11 @@ class Context:
         """Drop the response blocks whose largest Fermi multiplier entry is at
         most tau times the largest (0: form every block; default 1e-14)."""
         self.check(self.lib.lrdm_set_response_block_skip(self.ptr, float(tau)))
+
+    def set_backproj_layout(self, layout: int):
+        """BF16X3 back-projection layout: 1 = 256 points per workgroup (default),
+        0 = 128 points."""
+        self.check(self.lib.lrdm_set_backproj_layout(self.ptr, int(layout)))
 
     def set_checks(self, level: int):
         self.check(self.lib.lrdm_set_checks(self.ptr, int(level)))

@@ -184,3 +184,7 @@ def test_eigensolver_sweeps_needs_a_context(lib):
 
 def test_block_skip_needs_a_context(lib):
     assert lib.lrdm_set_response_block_skip(None, 1e-14) == -1 and "ctx is NULL" in _err(lib)
+
+
+def test_backproj_layout_needs_a_context(lib):
+    assert lib.lrdm_set_backproj_layout(None, 1) == -1 and "ctx is NULL" in _err(lib)

@@ -76,6 +76,36 @@ def test_density_response_ragged_multitile(form, nspin):
     assert max(errs) < BOUND[form]
 
 
+@pytest.mark.parametrize("nspin", [1, 2])
+def test_bf16x3_backproj_layouts(nspin):
+    """Both BF16X3 back-projection layouts (256 and 128 points per workgroup)
+    against the oracle: N = 300 (three row blocks, the last ragged), 4680 grid
+    points (18 whole 256-point blocks and a ragged one), kT = 0.005 so that the
+    occupied-occupied block drops out, and the two layouts within 1e-6 of each
+    other."""
+    g, Psi, eps, rng = _random_subspace((20, 18, 13), (8.0, 7.2, 5.2), 300, nspin, 21)
+    ne = 0.6 * 300
+    dV = rng.standard_normal((4, nspin) + g.shape)
+    ref, _, _ = O.density_response(Psi, eps, g, ne, 0.005, dV, nspin)
+    ctx = L.context()
+    got = {}
+    try:
+        for layout in (1, 0):
+            ctx.set_backproj_layout(layout)
+            drho, _, _ = L.density_response(_grid(g), f32(Psi), to_dev(eps),
+                                            L.Occupation(nspin, 0.005, ne), to_dev(dV),
+                                            prec="bf16x3")
+            got[layout] = to_host(drho)
+            errs = [rel(got[layout][k, c], ref[k, c]) for k in range(4) for c in range(nspin)]
+            print(f"layout {layout} nspin {nspin}: drho rel err {max(errs):.3e}")
+            assert max(errs) < BOUND["bf16x3"]
+    finally:
+        ctx.set_backproj_layout(1)
+    d = max(rel(got[1][k, c], got[0][k, c]) for k in range(4) for c in range(nspin))
+    print(f"layouts differ by {d:.2e}")
+    assert d < 1e-6
+
+
 @pytest.mark.parametrize("form", FORMS)
 def test_density_response_three_tiles_odd(form):
     """N = 300 (three tiles, the last ragged) and an odd grid of 7 x 9 x 11."""
