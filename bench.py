@@ -61,6 +61,9 @@ def parse():
     ap.add_argument("--cpu-protocol", action="store_true",
                     help="also time the oracle's median-of-3 full step on the 48^3 / 256-state "
                          "workload (about two minutes of host time)")
+    ap.add_argument("--backproj-layout", type=int, choices=(0, 1), default=1,
+                    help="BF16X3 back-projection layout: 1 = 256 points per workgroup (the "
+                         "library default), 0 = 128 points")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run three 1 GiB device copies first: a kernel of known traffic for "
                          "scaling hardware byte counters")
@@ -159,6 +162,7 @@ def main():
         Yf = torch.empty_like(Xf)
         t_out = torch.empty((r, 1) + grid.shape, dtype=torch.float64, device=dev)
         ctx = L.context()
+        ctx.set_backproj_layout(args.backproj_layout)
 
         e_resp = torch.empty(N, dtype=torch.float64, device=dev)
         # K-split counts of the projection contractions for this form's shapes
@@ -419,6 +423,7 @@ def main():
                       "lrdm_step": v["lrdm_step"],
                       "autotune_splits": (v["autotune"] or {}).get("splits"),
                       "active_blocks": v["active_blocks"],
+                      "backproj_layout": args.backproj_layout if f == "bf16x3" else None,
                       "kernel_ms": {k: round(x[0] / max(x[1], 1), 4) for k, x in v["kernels"].items() if x[1]}}
                   for f, v in results.items()},
         "fermi_expansion_rel_err": results.get("fp64", {}).get("fermi_expansion"),
