@@ -58,7 +58,9 @@
  *     split exactly into three BF16 pieces x = x1 + x2 + x3 (8 significant
  *     bits each), and the six products of order <= 2 are kept (x1*y1; x1*y2 +
  *     x2*y1; x1*y3 + x2*y2 + x3*y1), accumulated in FP32 over four 32-wide K
- *     tiles and in FP64 across them.  Potentials,
+ *     tiles and in FP64 across them (the default back-projection layout sums
+ *     a 128-row block of Gamma's products in FP32 before its FP64 fold with
+ *     Psi; lrdm_set_backproj_layout).  Potentials,
  *     eigenvalues, occupations, densities, mu and mu' are always double, and
  *     the subspace eigensolver, the Fermi-level bisection and the divided
  *     differences always run in FP64 on the GPU.
