@@ -423,7 +423,9 @@ def main():
                       "lrdm_step": v["lrdm_step"],
                       "autotune_splits": (v["autotune"] or {}).get("splits"),
                       "active_blocks": v["active_blocks"],
-                      "backproj_layout": args.backproj_layout if f == "bf16x3" else None,
+                      "backproj_layout": ((v["autotune"] or {}).get("backproj_layout",
+                                                                     args.backproj_layout)
+                                          if f == "bf16x3" else None),
                       "kernel_ms": {k: round(x[0] / max(x[1], 1), 4) for k, x in v["kernels"].items() if x[1]}}
                   for f, v in results.items()},
         "fermi_expansion_rel_err": results.get("fp64", {}).get("fermi_expansion"),

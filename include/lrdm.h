@@ -503,11 +503,15 @@ lrdm_status lrdm_lowrank_step(lrdm_ctx* ctx, const lrdm_grid* grid, const void* 
  * system whose shape is tuned to layout 1 to its own launch).  splits and
  * variants (host int[3], may be NULL) receive the choices; timings (host
  * double[3][3][4], may be NULL) the milliseconds per shape, layout and count, 0
- * where not tried.  Synchronises.  For the callers that tune once at set-up, not
- * for those that cannot allocate. */
+ * where not tried.  In the BF16X3 form it also times both back-projection
+ * layouts (lrdm_set_backproj_layout) on the response's shape and keeps the
+ * faster on the context; backproj_layout (host int, may be NULL) receives the
+ * layout in use afterwards, backproj_ms (host double[2], may be NULL) the
+ * milliseconds of layouts 0 and 1 (0 when not timed).  Synchronises.  For the
+ * callers that tune once at set-up, not for those that cannot allocate. */
 lrdm_status lrdm_autotune(lrdm_ctx* ctx, const lrdm_grid* grid, int32_t N, int32_t nspin,
                           int32_t r, lrdm_prec prec, int32_t* splits, int32_t* variants,
-                          double* timings);
+                          double* timings, int32_t* backproj_layout, double* backproj_ms);
 
 #ifdef __cplusplus
 }

@@ -1477,7 +1477,8 @@ hipError_t time_launch(lrdm_ctx* ctx, F&& launch, int reps, double* ms) {
 
 extern "C" lrdm_status lrdm_autotune(lrdm_ctx* ctx, const lrdm_grid* grid, int32_t N,
                                      int32_t nspin, int32_t r, lrdm_prec prec, int32_t* splits,
-                                     int32_t* variants, double* timings) {
+                                     int32_t* variants, double* timings,
+                                     int32_t* backproj_layout, double* backproj_ms) {
   LRDM_CHECK(ctx, check_grid(grid));
   LRDM_CHECK(ctx, check_block(grid, N));
   LRDM_CHECK(ctx, check_rank(r));
@@ -1488,7 +1489,8 @@ extern "C" lrdm_status lrdm_autotune(lrdm_ctx* ctx, const lrdm_grid* grid, int32
   const size_t el = prec_bytes(prec);
   const size_t ws = std::max({tn_workspace_bytes(N, g.M, batch, prec),
                               tn_workspace_bytes(N, g.M, nspin, prec),
-                              tn_workspace_bytes(N, g.M, 1, LRDM_FP64)});
+                              tn_workspace_bytes(N, g.M, 1, LRDM_FP64),
+                              backproj_workspace_bytes(N, g.M, nspin, batch, prec)});
   lrdm_status st = begin(ctx, ws);
   if (st != LRDM_OK) return st;
   void* A = nullptr;
@@ -1569,6 +1571,34 @@ extern "C" lrdm_status lrdm_autotune(lrdm_ctx* ctx, const lrdm_grid* grid, int32
       if (splits) splits[k] = best;
       if (variants) variants[k] = best_v;
     }
+    // the BF16X3 back-projection layouts on the response's shape: Gamma = the
+    // projected matrices just formed (every block), the result into w
+    int bp_best = ctx->bp_variant;
+    if (backproj_ms) backproj_ms[0] = backproj_ms[1] = 0.0;
+    if (prec == LRDM_BF16X3) {
+      double best_ms = 1e300;
+      for (int v = BP_VAR_NARROW; v <= BP_VAR_WIDE; ++v) {
+        ctx->bp_variant = v;
+        auto launch = [&]() -> hipError_t {
+          ctx->ws_top = 0;
+          return launch_backproj<float>(ctx, static_cast<const float*>(A), H, N, g.M, nspin, batch,
+                                        prec, 1.0, nullptr, w, nullptr);
+        };
+        double ms = 0.0;
+        e = time_launch(ctx, launch, 3, &ms);
+        if (e != hipSuccess) {
+          ctx->bp_variant = bp_best;
+          return fail_hip(ctx, "lrdm_autotune", e);
+        }
+        if (backproj_ms) backproj_ms[v] = ms;
+        if (ms < best_ms) {
+          best_ms = ms;
+          bp_best = v;
+        }
+      }
+      ctx->bp_variant = bp_best;
+    }
+    if (backproj_layout) *backproj_layout = bp_best;
     return LRDM_OK;
   });
 }

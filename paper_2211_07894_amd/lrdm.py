@@ -152,7 +152,7 @@ def library() -> ctypes.CDLL:
                 "lrdm_density": [vp, G, vp, vp, i32, O, ctypes.c_int, vp, vp, vp],
                 "lrdm_effective_potential": [vp, G, vp, vp, i32, vp, vp, vp],
                 "lrdm_lda_xc": [vp, G, vp, i32, vp, vp],
-                "lrdm_autotune": [vp, G, i32, i32, i32, ctypes.c_int, vp, vp, vp],
+                "lrdm_autotune": [vp, G, i32, i32, i32, ctypes.c_int, vp, vp, vp, vp, vp],
                 "lrdm_residual_derivative_xc": [vp, G, vp, vp, i32, O, vp, i32, ctypes.c_int, vp,
                                                 vp],
                 "lrdm_lowrank_step": [vp, G, vp, vp, i32, O, ctypes.c_int, vp,
@@ -662,18 +662,24 @@ def lowrank_step(grid: Grid, Psi, eps, occ: Occupation, R, params: LowRankParams
 
 def autotune(grid: Grid, N: int, nspin: int, r: int, prec="fp64", device=None):
     """Pick the projection's layout of tiles and waves and its K-split counts for
-    this shape on the current context (lrdm_autotune).  Returns dict(splits=[3],
-    variants=[3], ms=[shape][layout][4 candidates]) for the shapes response,
-    single direction and Gram; 0 where not tried."""
+    this shape on the current context (lrdm_autotune), and in the BF16X3 form the
+    back-projection layout.  Returns dict(splits=[3], variants=[3],
+    ms=[shape][layout][4 candidates], backproj_layout, backproj_ms=[2]) for the
+    shapes response, single direction and Gram; 0 where not tried."""
     ctx = context(device)
     g = grid.c()
     splits = (ctypes.c_int32 * 3)()
     variants = (ctypes.c_int32 * 3)()
     ms = (ctypes.c_double * 36)()
+    bp = ctypes.c_int32()
+    bp_ms = (ctypes.c_double * 2)()
     ctx.check(ctx.lib.lrdm_autotune(ctx.ptr, ctypes.byref(g), int(N), int(nspin), int(r),
                                     _prec(prec), ctypes.cast(splits, ctypes.c_void_p),
                                     ctypes.cast(variants, ctypes.c_void_p),
-                                    ctypes.cast(ms, ctypes.c_void_p)))
+                                    ctypes.cast(ms, ctypes.c_void_p),
+                                    ctypes.cast(ctypes.byref(bp), ctypes.c_void_p),
+                                    ctypes.cast(bp_ms, ctypes.c_void_p)))
     return dict(splits=list(splits), variants=list(variants),
                 ms=[[list(ms[12 * k + 4 * v:12 * k + 4 * v + 4]) for v in range(3)]
-                    for k in range(3)])
+                    for k in range(3)],
+                backproj_layout=int(bp.value), backproj_ms=list(bp_ms))

@@ -476,9 +476,11 @@ void scenario_autotune(lrdm_ctx* ctx, lrdm_grid g, int N, int nspin, int r, lrdm
   char name[128];
   std::snprintf(name, sizeof name, "lrdm_autotune %s N=%d nspin=%d r=%d", prec_name(prec), N,
                 nspin, r);
-  check(lrdm_autotune(ctx, &g, N, nspin, r, prec, splits, variants, ms), ctx, name);
-  std::printf("     splits %d %d %d, layouts %d %d %d\n", splits[0], splits[1], splits[2],
-              variants[0], variants[1], variants[2]);
+  int32_t bp = -1;
+  double bp_ms[2];
+  check(lrdm_autotune(ctx, &g, N, nspin, r, prec, splits, variants, ms, &bp, bp_ms), ctx, name);
+  std::printf("     splits %d %d %d, layouts %d %d %d, back-projection layout %d\n", splits[0],
+              splits[1], splits[2], variants[0], variants[1], variants[2], bp);
   check(density_response(ctx, &g, Psi.data(), eps.data(), N, &occ, dV.data(), r, prec,
                          after.data(), nullptr, nullptr), ctx, "density_response after tuning");
   double num = 0, den = 0;

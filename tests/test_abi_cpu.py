@@ -172,9 +172,11 @@ def test_lda_validation(lib):
 
 
 def test_autotune_validation(lib):
-    st = lib.lrdm_autotune(None, ctypes.byref(_grid()), 32, 3, 2, 0, None, None, None)
+    st = lib.lrdm_autotune(None, ctypes.byref(_grid()), 32, 3, 2, 0, None, None, None, None,
+                           None)
     assert st == -1 and "nspin must be 1 or 2" in _err(lib)
-    st = lib.lrdm_autotune(None, ctypes.byref(_grid()), 32, 1, 0, 0, None, None, None)
+    st = lib.lrdm_autotune(None, ctypes.byref(_grid()), 32, 1, 0, 0, None, None, None, None,
+                           None)
     assert st == -1 and "r (number of directions)" in _err(lib)
 
 

@@ -231,13 +231,19 @@ def test_autotune_keeps_the_response(c24, form):
     before, _, _ = L.density_response(grid, P, to_dev(eps[None]), occ, to_dev(dV), prec=form)
     before = to_host(before)
     tuned = L.autotune(grid, wl.N, 1, 4, prec=form)
-    print(f"{form}: splits {tuned['splits']}, layouts {tuned['variants']}, ms {tuned['ms']}")
+    print(f"{form}: splits {tuned['splits']}, layouts {tuned['variants']}, ms {tuned['ms']}, "
+          f"back-projection layout {tuned['backproj_layout']} ({tuned['backproj_ms']} ms)")
     after, _, _ = L.density_response(grid, P, to_dev(eps[None]), occ, to_dev(dV), prec=form)
     after = to_host(after)
     assert rel(after, before) < (1e-13 if form == "fp64" else 1e-6)
     ref, _, _ = O.density_response(to_host(P), eps[None], g, wl.n_electrons, wl.kT, dV, 1)
     assert rel(after, ref) < (1e-10 if form == "fp64" else BOUND[form])
     assert all(s >= 1 for s in tuned["splits"])
+    if form == "bf16x3":
+        assert tuned["backproj_layout"] in (0, 1) and min(tuned["backproj_ms"]) > 0.0
+        L.context().set_backproj_layout(1)     # the library default, for the tests after this one
+    else:
+        assert tuned["backproj_ms"] == [0.0, 0.0]
 
 
 def test_rayleigh_ritz_bf16x3_fresh_context_two_passes():
