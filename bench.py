@@ -438,7 +438,7 @@ def main():
 
 
 def grown_forms(torch, L, dev, reps=5):
-    """Times of the grown forms (FP32 storage):
+    """Times of the grown forms (FP32 storage; FP32 and BF16X3 arithmetic):
     * 16 uneven spin-polarised systems (grids 32^3..56^3, 64-512 states, 4-20
       directions) in one density_response_batched call, eager and replayed from
       one captured HIP graph (median of `reps`);
@@ -482,20 +482,25 @@ def grown_forms(torch, L, dev, reps=5):
              torch.empty(1, dtype=torch.float64, device=dev),
              torch.empty(si["dV"].shape[0], dtype=torch.float64, device=dev)) for si in systems]
     side = torch.cuda.Stream()
-    with torch.cuda.stream(side):
-        L.density_response_batched(systems, prec="fp32", outs=outs)     # sizes the workspace
-        side.synchronize()
+    batched = {}
+    for form in ("fp32", "bf16x3"):
+        with torch.cuda.stream(side):
+            L.density_response_batched(systems, prec=form, outs=outs)     # sizes the workspace
+            side.synchronize()
 
-        def eager():
-            L.density_response_batched(systems, prec="fp32", outs=outs)
-        eager_ms = ms_of(eager)
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph, stream=side):
-            L.density_response_batched(systems, prec="fp32", outs=outs)
-        replay_ms = ms_of(graph.replay)
-    del graph
-    log(f"batched 16 systems ({directions} directions x 2 channels): eager {eager_ms:.1f} ms, "
-        f"graph replay {replay_ms:.1f} ms")
+            def eager():
+                L.density_response_batched(systems, prec=form, outs=outs)
+            eager_ms = ms_of(eager)
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph, stream=side):
+                L.density_response_batched(systems, prec=form, outs=outs)
+            replay_ms = ms_of(graph.replay)
+        del graph
+        log(f"batched 16 systems ({directions} directions x 2 channels, {form}): eager "
+            f"{eager_ms:.1f} ms, graph replay {replay_ms:.1f} ms")
+        batched[form] = dict(systems=16, directions=directions, eager_ms=round(eager_ms, 3),
+                             graph_replay_ms=round(replay_ms, 3),
+                             directions_per_s=round(1e3 * directions / replay_ms, 2))
     del systems, outs
 
     wl = make_workload("c80_n2048")
@@ -508,15 +513,16 @@ def grown_forms(torch, L, dev, reps=5):
     dV = L.hartree_kernel(grid, U.reshape((wl.rank,) + grid.shape).contiguous())
     dV = dV.reshape((wl.rank, 1) + grid.shape).contiguous()
     G = torch.from_numpy(grf_directions(wl.system_id + 100, wl.n, wl.L, wl.rank)).to(dev)
-    fwd_ms = ms_of(lambda: L.density_response(grid, Psi, eps, occ, dV, prec="fp32"))
-    bwd_ms = ms_of(lambda: L.density_response_backward(grid, Psi, eps, occ, dV, G, prec="fp32"))
-    log(f"80^3 / 2048 states / 20 directions (fp32): forward {fwd_ms:.1f} ms, "
-        f"adjoint {bwd_ms:.1f} ms")
-    return dict(batched=dict(systems=16, directions=directions, eager_ms=round(eager_ms, 3),
-                             graph_replay_ms=round(replay_ms, 3),
-                             directions_per_s=round(1e3 * directions / replay_ms, 2)),
-                adjoint_c80=dict(N=wl.N, M=wl.M, r=wl.rank, forward_ms=round(fwd_ms, 2),
-                                 backward_ms=round(bwd_ms, 2)))
+    adjoint = {}
+    for form in ("fp32", "bf16x3"):
+        fwd_ms = ms_of(lambda: L.density_response(grid, Psi, eps, occ, dV, prec=form))
+        bwd_ms = ms_of(lambda: L.density_response_backward(grid, Psi, eps, occ, dV, G, prec=form))
+        log(f"80^3 / 2048 states / 20 directions ({form}): forward {fwd_ms:.1f} ms, "
+            f"adjoint {bwd_ms:.1f} ms")
+        adjoint[form] = dict(N=wl.N, M=wl.M, r=wl.rank, forward_ms=round(fwd_ms, 2),
+                             backward_ms=round(bwd_ms, 2))
+    return dict(batched=batched["fp32"], batched_bf16x3=batched["bf16x3"],
+                adjoint_c80=adjoint["fp32"], adjoint_c80_bf16x3=adjoint["bf16x3"])
 
 
 def measure_peaks(torch, dev):

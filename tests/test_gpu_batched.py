@@ -3,7 +3,9 @@ with grids from {32,40,48,56}^3, 64-512 states and 4-20 directions each, FP32
 storage.  Each system's result is bit-identical to a single density_response
 call; the two smallest systems match the FP64 oracle everywhere and all 16 on
 sampled points; and the batch captured into a HIP graph replays to the same
-bits."""
+bits.  The BF16X3 form of the batch (the systems forked over streams) is
+bit-identical to its single calls and within its 1e-6 bound of the oracle on
+the two smallest systems."""
 import time
 
 import numpy as np
@@ -85,6 +87,24 @@ def test_batched_smallest_systems_match_oracle(systems):
         err = max(rel(to_host(d)[j, c], ref[j, c]) for j in range(wl.rank) for c in range(2))
         print(f"system {k} ({wl.n[0]}^3, N={wl.N}, r={wl.rank}): rel err {err:.2e}")
         assert err < 1e-5
+
+
+def test_batched_bf16x3_equals_single_calls_and_oracle(systems):
+    wls, sys_in = systems
+    out = L.density_response_batched(sys_in, prec="bf16x3")
+    single = [L.density_response(s["grid"], s["Psi"], s["eps"], s["occ"], s["dV"],
+                                 prec="bf16x3") for s in sys_in]
+    for (d, mu, dmu), (ds, mus, dmus) in zip(out, single):
+        assert torch.equal(d, ds) and torch.equal(mu, mus) and torch.equal(dmu, dmus)
+    order = sorted(range(len(wls)), key=lambda k: wls[k].M * wls[k].N ** 2)[:2]
+    for k in order:
+        wl, s, d = wls[k], sys_in[k], out[k][0]
+        g = O.Grid(wl.n, wl.L)
+        ref, _, _ = O.density_response(to_host(s["Psi"]), to_host(s["eps"]), g, wl.n_electrons,
+                                       wl.kT, to_host(s["dV"]), 2)
+        err = max(rel(to_host(d)[j, c], ref[j, c]) for j in range(wl.rank) for c in range(2))
+        print(f"bf16x3 system {k} ({wl.n[0]}^3, N={wl.N}, r={wl.rank}): rel err {err:.2e}")
+        assert err < 1e-6
 
 
 def test_batched_all_systems_match_oracle_sampled(systems):
