@@ -1322,8 +1322,7 @@ constexpr int SBW = 9 * PB;               // one stage: 3 Gamma pieces, 3 x 2 Ps
 __global__ __launch_bounds__(PT, 1) void backproj_p3w_kernel(
     const float* __restrict__ A, const __bf16* __restrict__ PT3, const __bf16* __restrict__ G3,
     int N, int64_t M, int ldk, int nspin, int batch, double scale, const double* __restrict__ sub,
-    const unsigned char* __restrict__ active, const float* __restrict__ zeros,
-    double* __restrict__ out) {
+    const unsigned char* __restrict__ active, double* __restrict__ out) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_pipe[];
   double* red = reinterpret_cast<double*>(smem_pipe + 2 * SBW);   // [PW][64]
   int pblk, b;
@@ -1684,7 +1683,7 @@ hipError_t launch_backproj<float>(lrdm_ctx* ctx, const float* A, const double* G
       const unsigned grdw = (unsigned)((M + BPW - 1) / BPW * batch);
       ProfScope prof(ctx, "backproj");
       backproj_p3w_kernel<<<grdw, PT, smem, ctx->stream>>>(A, PT3, G3, N, M, ldk, nspin, batch,
-                                                           scale, sub, active, ctx->zeros, out);
+                                                           scale, sub, active, out);
       return hipGetLastError();
     }
     const int smem = NST * 6 * PB + PW * 64 * (int)sizeof(double);
