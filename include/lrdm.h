@@ -268,6 +268,25 @@ lrdm_status chfsi_filter_bloch(lrdm_ctx* ctx, const lrdm_grid* grid, const doubl
 lrdm_status subspace_rayleigh_ritz(lrdm_ctx* ctx, const lrdm_grid* grid, const double* V,
                                    void* Psi, int32_t N, lrdm_prec prec, double* eps);
 
+/* subspace_rayleigh_ritz for the Bloch Hamiltonian H_k of one k-point (Sec. II
+ * C, last paragraph; H_k as in lrdm_bloch_hamiltonian_apply): Psi [2][N][M]
+ * (the N real parts, then the N imaginary parts, double), in = the filtered
+ * complex block, out = N Ritz vectors orthonormal in the complex l2 product;
+ * eps [N] double (device), ascending.  The complex block is handled as the 2N
+ * real vectors of y_i and i y_i: their Gram matrix (the real part of the complex
+ * one) is factored by the FP64 Cholesky QR of subspace_rayleigh_ritz, the
+ * projection of the real form of H_k is diagonalised by the same block Jacobi
+ * eigensolver (each Ritz value of H_k appears twice there, with the vectors v
+ * and i v), and one vector of each pair is kept.  Each Ritz vector's phase is
+ * arbitrary.  Synchronises the stream.  Errors: EINVAL (arguments; N at most
+ * 4096), ENOMEM, EDEVICE, ENOTCONV (eigensolver without convergence; a complex
+ * block numerically rank deficient as given, or one that three passes could
+ * not orthonormalise; Ritz values so close that the pairs could not be told
+ * apart). */
+lrdm_status subspace_rayleigh_ritz_bloch(lrdm_ctx* ctx, const lrdm_grid* grid, const double* V,
+                                         double kx, double ky, double kz, double* Psi,
+                                         int32_t N, double* eps);
+
 /* Subspace density response (Eqs. (19)-(22), traceless condition after
  * Eq. (24); per channel without the factor 2 in Sec. II D):
  *   Hp_k = Psi^T diag(dV_k) Psi,  mu'_k = sum f'_i Hp_k,ii / sum f'_i (over

@@ -21,6 +21,7 @@ from .lrdm import (  # noqa: F401
     density_response_bz,
     bloch_hamiltonian_apply,
     chfsi_filter_bloch,
+    subspace_rayleigh_ritz_bloch,
     residual_derivative,
     density_response_backward,
     density_response_batched,

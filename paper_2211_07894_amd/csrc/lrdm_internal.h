@@ -361,6 +361,11 @@ template <typename T>
 lrdm_status rayleigh_ritz(lrdm_ctx* ctx, const Grid3& g, const double* V, T* Psi, int N,
                           lrdm_prec prec, double* eps);
 size_t rr_workspace_bytes(int N, int64_t M, lrdm_prec prec);
+// Rayleigh-Ritz of the Bloch Hamiltonian H_k on N complex states [2][N][M]
+// (real parts, then imaginary parts), FP64 storage.
+lrdm_status rayleigh_ritz_bloch(lrdm_ctx* ctx, const Grid3& g, const double* V,
+                                const double kvec[3], double* Psi, int N, double* eps);
+size_t rr_bloch_workspace_bytes(int N, int64_t M);
 
 // Hartree kernel (poisson.hip): dV[k] = 4 pi (-Lap_h)^{-1} (sum_c u[k][c]) for k < r,
 // written to every channel slot of dV when nspin_out > 1.

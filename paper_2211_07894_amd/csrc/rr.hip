@@ -664,4 +664,479 @@ template lrdm_status rayleigh_ritz<double>(lrdm_ctx*, const Grid3&, const double
 template lrdm_status rayleigh_ritz<float>(lrdm_ctx*, const Grid3&, const double*, float*, int,
                                           lrdm_prec, double*);
 
+// ------------------------------------------------------ Rayleigh-Ritz of H_k
+// The complex subspace of one k-point (Sec. II C, last paragraph) is handled as
+// a real one: the N complex states y_i and their multiples i y_i are 2N real
+// vectors [Re | Im] of length 2M, whose real inner products are the real parts
+// of the complex ones and on which H_k acts as the real symmetric operator
+// [[Re H_k, -Im H_k], [Im H_k, Re H_k]].  Rayleigh-Ritz of that operator on the
+// 2N real vectors (the Cholesky factor, the block Jacobi eigensolver and the
+// rotations of the real path) gives every Ritz value of H_k twice: multiplication
+// by i maps each eigenspace of the real form onto itself, so a complex Ritz value
+// of multiplicity d is a cluster of 2d real Ritz values whose vectors span d
+// complex dimensions.  Clusters are runs of real Ritz values with consecutive
+// gaps below 1e-8 of the spectrum's scale (two copies of one value differ by
+// rounding only).  A cluster of two gives one complex Ritz vector, either real
+// vector of the pair.  A larger one (a degenerate or nearly degenerate multiplet)
+// takes its complex overlaps <psi_a, psi_b>, a pivoted complex Gram-Schmidt that
+// picks d orthonormal combinations, and the d x d Hermitian projection of H_k on
+// them, diagonalised by complex Jacobi rotations; the cluster must span exactly
+// d complex dimensions, or the call reports ENOTCONV.
+namespace {
+
+constexpr int kPairMax = 64;           // real Ritz values per cluster (2 d)
+constexpr int kPairRow = 4 * kPairMax; // scratch entries per real Ritz vector
+constexpr double kClusterTol = 1e-8;   // cluster gap, relative to the spectrum's scale
+
+struct cplx {
+  double re, im;
+};
+__device__ inline cplx c_mul(cplx a, cplx b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__device__ inline cplx c_conj_mul(cplx a, cplx b) {   // conj(a) b
+  return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+__device__ inline double c_abs2(cplx a) { return a.re * a.re + a.im * a.im; }
+
+// B [2][2N][M]: the complex block of the 2N states y_i, i y_i from Y [2][N][M].
+__global__ void realify_kernel(const double* __restrict__ Y, int N, int64_t M,
+                               double* __restrict__ B) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (p >= M) return;
+  const double yr = Y[(int64_t)i * M + p], yi = Y[((int64_t)N + i) * M + p];
+  const int64_t n2 = 2 * (int64_t)N;
+  B[(int64_t)i * M + p] = yr;
+  B[((int64_t)N + i) * M + p] = -yi;
+  B[(n2 + i) * M + p] = yi;
+  B[(n2 + N + i) * M + p] = yr;
+}
+
+__global__ void add_inplace_kernel(double* __restrict__ a, const double* __restrict__ b,
+                                   int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] += b[i];
+}
+
+__global__ void zero_int_kernel(int* __restrict__ x) { *x = 0; }
+
+// Cluster gap of the ascending real Ritz values e2 [n2].
+__device__ inline double cluster_tol(const double* e2, int n2) {
+  const double scale = fmax(fmax(fabs(e2[0]), fabs(e2[n2 - 1])), e2[n2 - 1] - e2[0]);
+  return kClusterTol * scale;
+}
+
+// cs, cn [n2]: first index and size of each real Ritz value's cluster.
+__global__ void cluster_kernel(const double* __restrict__ e2, int n2, int* __restrict__ cs,
+                               int* __restrict__ cn) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n2) return;
+  const double tol = cluster_tol(e2, n2);
+  int a = m, b = m + 1;
+  while (a > 0 && e2[a] - e2[a - 1] <= tol) --a;
+  while (b < n2 && e2[b] - e2[b - 1] <= tol) ++b;
+  cs[m] = a;
+  cn[m] = b - a;
+}
+
+// Complex overlaps <psi_a, psi_b> of real Ritz vector a (one block) with every
+// member b of its cluster, for clusters of four or more; R [2][n2][M].
+__global__ __launch_bounds__(256) void cluster_overlap_kernel(const double* __restrict__ R,
+                                                              const int* __restrict__ cs,
+                                                              const int* __restrict__ cn, int n2,
+                                                              int64_t M, cplx* __restrict__ scr) {
+  __shared__ double red[2][256];
+  const int a = blockIdx.x, t = threadIdx.x;
+  const int s = cs[a], n = cn[a];
+  if (n < 4 || n > kPairMax) return;
+  const double* ar = R + (int64_t)a * M;
+  const double* ai = R + ((int64_t)n2 + a) * M;
+  for (int j = 0; j < n; ++j) {
+    const double* br = R + (int64_t)(s + j) * M;
+    const double* bi = R + ((int64_t)n2 + s + j) * M;
+    double re = 0.0, im = 0.0;
+    for (int64_t p = t; p < M; p += 256) {
+      re += ar[p] * br[p] + ai[p] * bi[p];
+      im += ar[p] * bi[p] - ai[p] * br[p];
+    }
+    red[0][t] = re;
+    red[1][t] = im;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (t < w) {
+        red[0][t] += red[0][t + w];
+        red[1][t] += red[1][t + w];
+      }
+      __syncthreads();
+    }
+    if (t == 0) scr[(size_t)a * kPairRow + j] = cplx{red[0][0], red[1][0]};
+    __syncthreads();
+  }
+}
+
+// One thread per cluster (its first index m): the d = n/2 complex Ritz pairs of
+// the cluster, written to outputs m/2 .. m/2 + d - 1 as coefficients over the
+// cluster's real Ritz vectors (coef [N][kPairMax]), with ostart / osize naming
+// the cluster.  flag = 1 when a cluster has an odd size or more than kPairMax
+// members, or does not span exactly d complex dimensions.
+__global__ void cluster_pair_kernel(const double* __restrict__ e2, const int* __restrict__ cs,
+                                    const int* __restrict__ cn, int N, cplx* __restrict__ scr,
+                                    cplx* __restrict__ coef, int* __restrict__ ostart,
+                                    int* __restrict__ osize, double* __restrict__ eps,
+                                    int* __restrict__ flag) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n2 = 2 * N;
+  if (m >= n2 || cs[m] != m) return;
+  const int n = cn[m];
+  if ((n & 1) || n > kPairMax) {
+    atomicOr(flag, 1);
+    return;
+  }
+  const int d = n / 2, o0 = m / 2;
+  cplx* row0 = scr + (size_t)m * kPairRow;
+  cplx* C = coef + (size_t)o0 * kPairMax;
+  if (n == 2) {   // one complex Ritz vector: the first real one of the pair
+    C[0] = cplx{1.0, 0.0};
+    C[1] = cplx{0.0, 0.0};
+    ostart[o0] = m;
+    osize[o0] = 2;
+    eps[o0] = e2[m];
+    return;
+  }
+  // scratch rows m .. m+n-1: S | S C_k | projected H_k | Jacobi vectors
+  auto S = [&](int j, int l) -> cplx& { return row0[(size_t)j * kPairRow + l]; };
+  auto SC = [&](int k, int l) -> cplx& { return row0[(size_t)k * kPairRow + kPairMax + l]; };
+  auto Hc = [&](int k, int l) -> cplx& { return row0[(size_t)k * kPairRow + 2 * kPairMax + l]; };
+  auto W = [&](int k, int l) -> cplx& { return row0[(size_t)k * kPairRow + 3 * kPairMax + l]; };
+  auto Cc = [&](int k, int l) -> cplx& { return C[(size_t)k * kPairMax + l]; };
+  // S v into SC row k, for v = C_k
+  auto apply_s = [&](int k) {
+    for (int j = 0; j < n; ++j) {
+      cplx acc{0.0, 0.0};
+      for (int l = 0; l < n; ++l) {
+        const cplx x = c_mul(S(j, l), Cc(k, l));
+        acc.re += x.re;
+        acc.im += x.im;
+      }
+      SC(k, j) = acc;
+    }
+  };
+  // pivoted complex Gram-Schmidt: C_k (rows of coefficients), orthonormal in S
+  unsigned long long used = 0;
+  for (int k = 0; k < d; ++k) {
+    int best = -1;
+    double bestn = -1.0;
+    for (int l = 0; l < n; ++l) {
+      if ((used >> l) & 1ull) continue;
+      double nv = S(l, l).re;
+      for (int q = 0; q < k; ++q) nv -= c_abs2(SC(q, l));   // |<phi_q, psi_l>|^2
+      if (nv > bestn) {
+        bestn = nv;
+        best = l;
+      }
+    }
+    if (bestn < 1e-4) {
+      atomicOr(flag, 1);
+      return;
+    }
+    used |= 1ull << best;
+    for (int l = 0; l < n; ++l) Cc(k, l) = cplx{l == best ? 1.0 : 0.0, 0.0};
+    for (int pass = 0; pass < 2; ++pass) {
+      apply_s(k);
+      for (int q = 0; q < k; ++q) {
+        cplx o{0.0, 0.0};   // <phi_q, v> = C_q^H S v
+        for (int j = 0; j < n; ++j) {
+          const cplx x = c_conj_mul(Cc(q, j), SC(k, j));
+          o.re += x.re;
+          o.im += x.im;
+        }
+        for (int l = 0; l < n; ++l) {
+          const cplx x = c_mul(o, Cc(q, l));
+          Cc(k, l).re -= x.re;
+          Cc(k, l).im -= x.im;
+        }
+      }
+    }
+    apply_s(k);
+    double nrm = 0.0;
+    for (int j = 0; j < n; ++j) nrm += c_conj_mul(Cc(k, j), SC(k, j)).re;
+    const double inv = 1.0 / sqrt(nrm);
+    for (int j = 0; j < n; ++j) {
+      Cc(k, j).re *= inv;
+      Cc(k, j).im *= inv;
+      SC(k, j).re *= inv;
+      SC(k, j).im *= inv;
+    }
+  }
+  // the cluster spans exactly d complex dimensions: nothing of any member is left
+  for (int l = 0; l < n; ++l) {
+    double res = S(l, l).re;
+    for (int k = 0; k < d; ++k) res -= c_abs2(SC(k, l));
+    if (res > 1e-6) {
+      atomicOr(flag, 1);
+      return;
+    }
+  }
+  // projected H_k on the combinations: <psi_j, H psi_l> = (e_j + e_l)/2 <psi_j, psi_l>
+  // (exact for Ritz vectors, whose real Ritz values differ only inside one eigenspace)
+  for (int k2 = 0; k2 < d; ++k2)
+    for (int j = 0; j < n; ++j) {
+      cplx acc{0.0, 0.0};
+      for (int l = 0; l < n; ++l) {
+        const double h = 0.5 * (e2[m + j] + e2[m + l]);
+        const cplx x = c_mul(S(j, l), Cc(k2, l));
+        acc.re += h * x.re;
+        acc.im += h * x.im;
+      }
+      W(k2, j) = acc;   // (Hs C_k2)_j
+    }
+  for (int k = 0; k < d; ++k)
+    for (int k2 = 0; k2 < d; ++k2) {
+      cplx acc{0.0, 0.0};
+      for (int j = 0; j < n; ++j) {
+        const cplx x = c_conj_mul(Cc(k, j), W(k2, j));
+        acc.re += x.re;
+        acc.im += x.im;
+      }
+      Hc(k, k2) = acc;
+    }
+  for (int k = 0; k < d; ++k) {
+    Hc(k, k).im = 0.0;
+    for (int k2 = k + 1; k2 < d; ++k2) {
+      const cplx a = Hc(k, k2), b = Hc(k2, k);
+      Hc(k, k2) = cplx{0.5 * (a.re + b.re), 0.5 * (a.im - b.im)};
+      Hc(k2, k) = cplx{Hc(k, k2).re, -Hc(k, k2).im};
+    }
+    for (int k2 = 0; k2 < d; ++k2) W(k, k2) = cplx{k == k2 ? 1.0 : 0.0, 0.0};
+  }
+  // cyclic complex Jacobi: for a_pq = r e^{i phi}, G = diag(1, e^{-i phi}) R(theta)
+  // on rows / columns p, q makes the (p, q) entry zero
+  const double scale = fmax(fabs(e2[m]), fabs(e2[m + n - 1])) + 1e-300;
+  for (int sweep = 0; sweep < 50; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < d; ++p)
+      for (int q = p + 1; q < d; ++q) off += c_abs2(Hc(p, q));
+    if (sqrt(off) <= 1e-15 * scale) break;
+    for (int p = 0; p < d; ++p)
+      for (int q = p + 1; q < d; ++q) {
+        const double r = sqrt(c_abs2(Hc(p, q)));
+        if (r <= 1e-300) continue;
+        const cplx ph{Hc(p, q).re / r, Hc(p, q).im / r};
+        const cplx phc{ph.re, -ph.im};
+        const double tau = (Hc(q, q).re - Hc(p, p).re) / (2.0 * r);
+        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        const double c = 1.0 / sqrt(1.0 + t * t), sn = t * c;
+        for (int k = 0; k < d; ++k) {   // columns: X <- X G
+          const cplx xp = Hc(k, p), xq = c_mul(phc, Hc(k, q));
+          Hc(k, p) = cplx{c * xp.re - sn * xq.re, c * xp.im - sn * xq.im};
+          Hc(k, q) = cplx{sn * xp.re + c * xq.re, sn * xp.im + c * xq.im};
+          const cplx wp = W(k, p), wq = c_mul(phc, W(k, q));
+          W(k, p) = cplx{c * wp.re - sn * wq.re, c * wp.im - sn * wq.im};
+          W(k, q) = cplx{sn * wp.re + c * wq.re, sn * wp.im + c * wq.im};
+        }
+        for (int k = 0; k < d; ++k) {   // rows: X <- G^H X
+          const cplx xp = Hc(p, k), xq = c_mul(ph, Hc(q, k));
+          Hc(p, k) = cplx{c * xp.re - sn * xq.re, c * xp.im - sn * xq.im};
+          Hc(q, k) = cplx{sn * xp.re + c * xq.re, sn * xp.im + c * xq.im};
+        }
+      }
+  }
+  // ascending eigenvalues; output k = sum_i W(i, k) phi_i, staged in SC
+  int order[kPairMax / 2];
+  for (int k = 0; k < d; ++k) order[k] = k;
+  for (int k = 0; k < d; ++k)
+    for (int q = k + 1; q < d; ++q)
+      if (Hc(order[q], order[q]).re < Hc(order[k], order[k]).re) {
+        const int x = order[k];
+        order[k] = order[q];
+        order[q] = x;
+      }
+  for (int k = 0; k < d; ++k) {
+    const int w = order[k];
+    for (int l = 0; l < n; ++l) {
+      cplx acc{0.0, 0.0};
+      for (int i = 0; i < d; ++i) {
+        const cplx x = c_mul(W(i, w), Cc(i, l));
+        acc.re += x.re;
+        acc.im += x.im;
+      }
+      SC(k, l) = acc;
+    }
+  }
+  for (int k = 0; k < d; ++k) {
+    for (int l = 0; l < n; ++l) Cc(k, l) = SC(k, l);
+    ostart[o0 + k] = m;
+    osize[o0 + k] = n;
+    eps[o0 + k] = Hc(order[k], order[k]).re;
+  }
+}
+
+// Psi [2][N][M]: the complex Ritz vectors sum_l coef[o][l] psi_{ostart[o] + l} from
+// the real ones R [2][2N][M] (real part of (a + ib)(re + i im) = a re - b im).
+__global__ void cluster_combine_kernel(const double* __restrict__ R, const cplx* __restrict__ coef,
+                                       const int* __restrict__ ostart,
+                                       const int* __restrict__ osize, int N, int64_t M,
+                                       double* __restrict__ Psi) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int o = blockIdx.y;
+  if (p >= M) return;
+  const int s = ostart[o], n = osize[o], n2 = 2 * N;
+  if (s < 0 || n < 1 || n > kPairMax || s + n > n2) return;
+  double xr = 0.0, xi = 0.0;
+  for (int l = 0; l < n; ++l) {
+    const cplx c = coef[(size_t)o * kPairMax + l];
+    if (c.re == 0.0 && c.im == 0.0) continue;
+    const double re = R[(int64_t)(s + l) * M + p], im = R[((int64_t)n2 + s + l) * M + p];
+    xr += c.re * re - c.im * im;
+    xi += c.re * im + c.im * re;
+  }
+  Psi[(int64_t)o * M + p] = xr;
+  Psi[((int64_t)N + o) * M + p] = xi;
+}
+
+}  // namespace
+
+size_t rr_bloch_workspace_bytes(int N, int64_t M) {
+  const int n2 = 2 * N;
+  const int Np = ((n2 + JS - 1) / JS) * JS;
+  const int nb = Np / JB;
+  size_t b = 3 * ws_align((size_t)2 * n2 * M * sizeof(double));   // B, spare, H B
+  b += 7 * ws_align((size_t)n2 * n2 * sizeof(double));            // G, G2, T, C, X, Wt, Q
+  b += ws_align((size_t)n2 * sizeof(double));                     // real Ritz values
+  b += 2 * ws_align((size_t)n2 * sizeof(int));                    // clusters
+  b += ws_align((size_t)n2 * kPairRow * sizeof(cplx));            // cluster scratch
+  b += ws_align((size_t)N * kPairMax * sizeof(cplx));             // coefficients
+  b += 2 * ws_align((size_t)N * sizeof(int)) + ws_align(64);
+  size_t inner = chol_orth_bytes(n2);
+  inner = std::max(inner, 2 * ws_align((size_t)Np * Np * sizeof(double)) +
+                              ws_align((size_t)(nb / 2) * JS * JS * 8) + ws_align(256) +
+                              ws_align((size_t)Np * 4) + ws_align(kFrobBlocks * sizeof(double)));
+  inner = std::max(inner, ws_align(tn_workspace_bytes(n2, M, 1, LRDM_FP64)));
+  return b + inner;
+}
+
+// Psi [2][N][M] (real parts, then imaginary parts; the filtered block on entry)
+// -> Ritz vectors of H_k, eps ascending.  FP64 storage.
+lrdm_status rayleigh_ritz_bloch(lrdm_ctx* ctx, const Grid3& g, const double* V,
+                                const double kvec[3], double* Psi, int N, double* eps) {
+  const int64_t M = g.M;
+  const int n2 = 2 * N;
+  const size_t plane = (size_t)n2 * M;
+  const size_t nn = (size_t)n2 * n2 * sizeof(double);
+  double* B = static_cast<double*>(ws_take(ctx, 2 * plane * sizeof(double)));
+  double* spare = static_cast<double*>(ws_take(ctx, 2 * plane * sizeof(double)));
+  double* HB = static_cast<double*>(ws_take(ctx, 2 * plane * sizeof(double)));
+  double* G = static_cast<double*>(ws_take(ctx, nn));
+  double* G2 = static_cast<double*>(ws_take(ctx, nn));
+  double* Tm = static_cast<double*>(ws_take(ctx, nn));
+  double* C = static_cast<double*>(ws_take(ctx, nn));
+  double* X = static_cast<double*>(ws_take(ctx, nn));
+  double* Wt = static_cast<double*>(ws_take(ctx, nn));
+  double* Q = static_cast<double*>(ws_take(ctx, nn));
+  double* e2 = static_cast<double*>(ws_take(ctx, (size_t)n2 * sizeof(double)));
+  int* cs = static_cast<int*>(ws_take(ctx, (size_t)n2 * sizeof(int)));
+  int* cn = static_cast<int*>(ws_take(ctx, (size_t)n2 * sizeof(int)));
+  cplx* scr = static_cast<cplx*>(ws_take(ctx, (size_t)n2 * kPairRow * sizeof(cplx)));
+  cplx* coef = static_cast<cplx*>(ws_take(ctx, (size_t)N * kPairMax * sizeof(cplx)));
+  int* ostart = static_cast<int*>(ws_take(ctx, (size_t)N * sizeof(int)));
+  int* osize = static_cast<int*>(ws_take(ctx, (size_t)N * sizeof(int)));
+  int* flag = static_cast<int*>(ws_take(ctx, 64));
+  const size_t mark = ctx->ws_top;
+  hipError_t e;
+  auto fail = [&](const char* what, hipError_t err) {
+    ctx->err = std::string("rayleigh_ritz_bloch: ") + what + ": " + hipGetErrorString(err);
+    return LRDM_EDEVICE;
+  };
+  const dim3 blk(32, 8), grd((n2 + 31) / 32, (n2 + 7) / 8);
+  const int64_t nsq = (int64_t)n2 * n2;
+  const unsigned add_grid = (unsigned)((nsq + 255) / 256);
+  realify_kernel<<<dim3((unsigned)((M + 255) / 256), N), 256, 0, ctx->stream>>>(Psi, N, M, B);
+  if ((e = hipGetLastError()) != hipSuccess) return fail("realify", e);
+  // out = P_re Q_re^T + P_im Q_im^T (Q = P when Q2 is null).  Each product forms its
+  // upper tiles and mirrors them; the sum of the two is symmetric, so the mirrored
+  // sum is the sum.  A product's partial sums are free once its reduction is queued.
+  auto two_plane = [&](const double* P, const double* Q2, double* out) -> hipError_t {
+    hipError_t err = launch_tn_sym_f64<double, double>(ctx, P, Q2, nullptr, 0, n2, M, 1, 1, out);
+    ctx->ws_top = mark;
+    if (err != hipSuccess) return err;
+    err = launch_tn_sym_f64<double, double>(ctx, P + plane, Q2 ? Q2 + plane : nullptr, nullptr, 0,
+                                            n2, M, 1, 1, G2);
+    ctx->ws_top = mark;
+    if (err != hipSuccess) return err;
+    add_inplace_kernel<<<add_grid, 256, 0, ctx->stream>>>(out, G2, nsq);
+    return hipGetLastError();
+  };
+  double* Bc = B;
+  CholInfo ci;
+  for (int pass = 0;; ++pass) {
+    if (pass > 0) {
+      if (pass == 3) {
+        ctx->err = "rayleigh_ritz_bloch: the block could not be orthonormalised";
+        return LRDM_ENOTCONV;
+      }
+      transpose_kernel<<<grd, blk, 0, ctx->stream>>>(Tm, n2, Wt);
+      for (int h = 0; h < 2; ++h)
+        if ((e = launch_nn_f64<double>(ctx, Wt, Bc + h * plane, spare + h * plane, n2, M,
+                                       true)) != hipSuccess)
+          return fail("rotation", e);
+      std::swap(Bc, spare);
+    }
+    if ((e = two_plane(Bc, nullptr, G)) != hipSuccess) return fail("gram", e);
+    lrdm_status st = chol_orth(ctx, G, n2, kDependentTol, Tm, &ci);
+    ctx->ws_top = mark;
+    if (st != LRDM_OK) return st;
+    if (ci.live < n2) {
+      ctx->err = "rayleigh_ritz_bloch: the complex block is numerically rank deficient";
+      return LRDM_ENOTCONV;
+    }
+    if (ci.cond < kOnePassCond64) break;
+  }
+  // H_k on the 2N complex states, then the projected real operator
+  if ((e = launch_bloch_step<double>(ctx, g, V, kvec, Bc, nullptr, HB, n2, 1.0, 0.0, 0.0)) !=
+      hipSuccess)
+    return fail("H_k", e);
+  if ((e = two_plane(Bc, HB, G)) != hipSuccess) return fail("projection", e);
+  if ((e = small_gemm(ctx, false, false, n2, n2, n2, 1.0, Tm, n2, G, n2, 0.0, X, n2)) !=
+      hipSuccess)
+    return fail("gemm", e);
+  if ((e = small_gemm(ctx, false, true, n2, n2, n2, 1.0, X, n2, Tm, n2, 0.0, C, n2)) !=
+      hipSuccess)
+    return fail("gemm", e);
+  lrdm_status st = sym_eigh(ctx, C, n2, n2, nullptr, e2, Q);
+  if (st != LRDM_OK) return st;
+  ctx->ws_top = mark;
+  // the 2N real Ritz vectors Wt^T B, Wt = T^T Q
+  if ((e = small_gemm(ctx, true, false, n2, n2, n2, 1.0, Tm, n2, Q, n2, 0.0, Wt, n2)) !=
+      hipSuccess)
+    return fail("gemm", e);
+  double* R = (Bc == B) ? spare : B;
+  for (int h = 0; h < 2; ++h)
+    if ((e = launch_nn_f64<double>(ctx, Wt, Bc + h * plane, R + h * plane, n2, M)) !=
+        hipSuccess)
+      return fail("rotation", e);
+  // clusters of real Ritz values, the complex pairs of each, and their vectors
+  const unsigned cgrid = (unsigned)((n2 + 255) / 256);
+  zero_int_kernel<<<1, 1, 0, ctx->stream>>>(flag);
+  cluster_kernel<<<cgrid, 256, 0, ctx->stream>>>(e2, n2, cs, cn);
+  cluster_overlap_kernel<<<n2, 256, 0, ctx->stream>>>(R, cs, cn, n2, M, scr);
+  cluster_pair_kernel<<<cgrid, 256, 0, ctx->stream>>>(e2, cs, cn, N, scr, coef, ostart, osize,
+                                                      eps, flag);
+  if ((e = hipGetLastError()) != hipSuccess) return fail("pairs", e);
+  int host_flag = 0;
+  if ((e = hipMemcpyAsync(&host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream)) !=
+      hipSuccess)
+    return fail("flag", e);
+  if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return fail("flag", e);
+  if (host_flag) {
+    ctx->err = "rayleigh_ritz_bloch: the real Ritz values do not fall into clusters of complex "
+               "pairs (at most 32 equal Ritz values of H_k are resolved)";
+    return LRDM_ENOTCONV;
+  }
+  cluster_combine_kernel<<<dim3((unsigned)((M + 255) / 256), N), 256, 0, ctx->stream>>>(
+      R, coef, ostart, osize, N, M, Psi);
+  if ((e = hipGetLastError()) != hipSuccess) return fail("combine", e);
+  return LRDM_OK;
+}
+
 }  // namespace lrdm

@@ -33,7 +33,7 @@ EXPORTED = [
     "lrdm_density", "lrdm_effective_potential", "lrdm_lowrank_step", "lrdm_set_fermi_expansion",
     "lrdm_lda_xc", "lrdm_residual_derivative_xc", "lrdm_autotune",
     "lrdm_set_eigensolver_sweeps", "lrdm_set_response_block_skip", "density_response_bz",
-    "lrdm_bloch_hamiltonian_apply", "chfsi_filter_bloch",
+    "lrdm_bloch_hamiltonian_apply", "chfsi_filter_bloch", "subspace_rayleigh_ritz_bloch",
     "density_response_noalloc", "lrdm_set_backproj_layout",
 ]
 
@@ -143,6 +143,7 @@ def library() -> ctypes.CDLL:
                                                  ctypes.c_int],
                 "chfsi_filter_bloch": [vp, G, vp, f64, f64, f64, vp, vp, i32, ctypes.c_int, i32,
                                        f64, f64, f64],
+                "subspace_rayleigh_ritz_bloch": [vp, G, vp, f64, f64, f64, vp, i32, vp],
                 "density_response_noalloc": [vp, G, vp, vp, i32, O, vp, i32, ctypes.c_int, vp, vp,
                                              vp],
                 "lrdm_residual_derivative": [vp, G, vp, vp, i32, O, vp, i32, ctypes.c_int, vp],
@@ -411,6 +412,20 @@ def chfsi_filter_bloch(grid: Grid, V, X, kvec, degree, a, b, a0, prec="fp64", ou
         _ptr(Y, "Y", _block_dtype(prec), 2 * N * grid.M), N, _prec(prec), int(degree), float(a),
         float(b), float(a0)))
     return Y
+
+
+def subspace_rayleigh_ritz_bloch(grid: Grid, V, Psi, kvec, eps=None):
+    """In place: filtered complex block Psi [2][N][nz][ny][nx] (FP64; real parts,
+    then imaginary parts) -> Ritz vectors of H_k; returns eps (ascending)."""
+    N = Psi.shape[1]
+    e = torch.empty(N, dtype=torch.float64, device=Psi.device) if eps is None else eps
+    ctx = context(Psi.device.index)
+    g = grid.c()
+    ctx.check(ctx.lib.subspace_rayleigh_ritz_bloch(
+        ctx.ptr, ctypes.byref(g), _ptr(V, "V", torch.float64, grid.M), float(kvec[0]),
+        float(kvec[1]), float(kvec[2]), _ptr(Psi, "Psi", torch.float64, 2 * N * grid.M), N,
+        _ptr(e, "eps", torch.float64, N)))
+    return e
 
 
 def density_response_bz(grid: Grid, Psi, eps, weights, occ: Occupation, dV, prec="fp64",

@@ -276,6 +276,115 @@ void scenario_chfsi(lrdm_ctx* ctx, lrdm_grid g, int N, int degree, lrdm_prec pre
   check(lrdm_hartree_kernel(ctx, &g, u.data(), dV.data(), 2), ctx, "hartree_kernel");
 }
 
+// ChFSI of one k-point: the Bloch filter, then the complex Rayleigh-Ritz; the Ritz
+// vectors must be orthonormal and diagonalise H_k in the complex product.
+void scenario_rr_bloch(lrdm_ctx* ctx, lrdm_grid g, int N, int degree) {
+  const int64_t M = (int64_t)g.n[0] * g.n[1] * g.n[2];
+  auto V = randv((size_t)M, 3, 0.5);
+  const double k[3] = {0.5, -0.3, 0.9};
+  std::vector<double> X = randv((size_t)2 * N * M, 14), Y((size_t)2 * N * M),
+                      HY((size_t)2 * N * M), eps(N);
+  double hx = g.L[0] / g.n[0], hy = g.L[1] / g.n[1], hz = g.L[2] / g.n[2];
+  const double b = 2 / (hx * hx) + 2 / (hy * hy) + 2 / (hz * hz) + 0.5;
+  char name[128];
+  std::snprintf(name, sizeof name, "chfsi_filter_bloch N=%d degree=%d", N, degree);
+  check(chfsi_filter_bloch(ctx, &g, V.data(), k[0], k[1], k[2], X.data(), Y.data(), N, LRDM_FP64,
+                           degree, -0.2, b, -1.0),
+        ctx, name);
+  std::snprintf(name, sizeof name, "subspace_rayleigh_ritz_bloch N=%d grid %dx%dx%d", N, g.n[0],
+                g.n[1], g.n[2]);
+  check(subspace_rayleigh_ritz_bloch(ctx, &g, V.data(), k[0], k[1], k[2], Y.data(), N,
+                                     eps.data()),
+        ctx, name);
+  check(lrdm_bloch_hamiltonian_apply(ctx, &g, V.data(), k[0], k[1], k[2], Y.data(), HY.data(), N,
+                                     LRDM_FP64),
+        ctx, "bloch_hamiltonian_apply of the Ritz vectors");
+  if (!finite(eps) || !finite(Y)) { std::printf("FAIL non-finite Ritz output\n"); ++failures; }
+  // <psi_i, psi_j> = delta_ij and <psi_i, H_k psi_j> = eps_i delta_ij (complex products)
+  const size_t im = (size_t)N * M;
+  double worst_o = 0, worst_h = 0, worst_order = 0;
+  for (int i = 0; i < N; i += 7)
+    for (int j = 0; j < N; j += 5) {
+      double ore = 0, oim = 0, hre = 0, him = 0;
+      for (int64_t p = 0; p < M; ++p) {
+        const double ar = Y[(size_t)i * M + p], ai = Y[im + (size_t)i * M + p];
+        const double br = Y[(size_t)j * M + p], bi = Y[im + (size_t)j * M + p];
+        const double cr = HY[(size_t)j * M + p], ci = HY[im + (size_t)j * M + p];
+        ore += ar * br + ai * bi;
+        oim += ar * bi - ai * br;
+        hre += ar * cr + ai * ci;
+        him += ar * ci - ai * cr;
+      }
+      worst_o = std::fmax(worst_o, std::hypot(ore - (i == j), oim));
+      worst_h = std::fmax(worst_h, std::hypot(hre - (i == j ? eps[i] : 0.0), him));
+    }
+  for (int i = 1; i < N; ++i) worst_order = std::fmax(worst_order, eps[i - 1] - eps[i]);
+  std::printf("     complex orthonormality %.2e, projected H_k off the Ritz values %.2e, "
+              "order %.2e\n", worst_o, worst_h, worst_order);
+  if (!(worst_o < 1e-10) || !(worst_h < 1e-9) || !(worst_order <= 0.0)) ++failures;
+}
+
+// Degenerate Ritz values of H_k: free electrons (V = 0) on a cubic 6^3 grid at
+// k = 0, the subspace of the 19 lowest plane waves (1 + 6 + 12 equal energies)
+// mixed by a random complex matrix.  The complex Rayleigh-Ritz must return the
+// three exact energies with their multiplicities and orthonormal vectors.
+void scenario_rr_bloch_degenerate(lrdm_ctx* ctx) {
+  const lrdm_grid g = grid(6, 6, 6, 0.5);
+  const int n = 6, N = 19;
+  const int64_t M = (int64_t)n * n * n;
+  const double h = 0.5, pi = 3.14159265358979323846;
+  std::vector<double> V((size_t)M, 0.0);
+  std::vector<int> waves;   // (nx, ny, nz) in {-1, 0, 1}^3 with at most two nonzero
+  for (int a = -1; a <= 1; ++a)
+    for (int b = -1; b <= 1; ++b)
+      for (int c = -1; c <= 1; ++c)
+        if (std::abs(a) + std::abs(b) + std::abs(c) <= 2) {
+          waves.push_back(a);
+          waves.push_back(b);
+          waves.push_back(c);
+        }
+  std::vector<double> mix = randv((size_t)2 * N * N, 21);
+  std::vector<double> Y((size_t)2 * N * M, 0.0), eps(N);
+  for (int i = 0; i < N; ++i)
+    for (int w = 0; w < N; ++w) {
+      const double qr = mix[(size_t)i * N + w], qi = mix[(size_t)N * N + i * N + w];
+      for (int z = 0; z < n; ++z)
+        for (int y = 0; y < n; ++y)
+          for (int x = 0; x < n; ++x) {
+            const double ph = 2 * pi * (waves[3 * w] * x + waves[3 * w + 1] * y +
+                                        waves[3 * w + 2] * z) / n;
+            const double wr = std::cos(ph) / std::sqrt((double)M), wi = std::sin(ph) / std::sqrt((double)M);
+            const size_t p = ((size_t)z * n + y) * n + x;
+            Y[(size_t)i * M + p] += qr * wr - qi * wi;
+            Y[(size_t)N * M + (size_t)i * M + p] += qr * wi + qi * wr;
+          }
+    }
+  check(subspace_rayleigh_ritz_bloch(ctx, &g, V.data(), 0.0, 0.0, 0.0, Y.data(), N, eps.data()),
+        ctx, "subspace_rayleigh_ritz_bloch degenerate N=19 (1 + 6 + 12)");
+  const double e1 = (1 - std::cos(2 * pi / n)) / (h * h);   // one direction at +-1
+  double worst_e = 0;
+  for (int i = 0; i < N; ++i) {
+    const double ref = i == 0 ? 0.0 : (i < 7 ? e1 : 2 * e1);
+    worst_e = std::fmax(worst_e, std::fabs(eps[i] - ref));
+  }
+  double worst_o = 0;
+  const size_t im = (size_t)N * M;
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      double ore = 0, oim = 0;
+      for (int64_t p = 0; p < M; ++p) {
+        const double ar = Y[(size_t)i * M + p], ai = Y[im + (size_t)i * M + p];
+        const double br = Y[(size_t)j * M + p], bi = Y[im + (size_t)j * M + p];
+        ore += ar * br + ai * bi;
+        oim += ar * bi - ai * br;
+      }
+      worst_o = std::fmax(worst_o, std::hypot(ore - (i == j), oim));
+    }
+  std::printf("     Ritz values off the exact shells %.2e, complex orthonormality %.2e\n", worst_e,
+              worst_o);
+  if (!(worst_e < 1e-12) || !(worst_o < 1e-11) || !finite(Y)) ++failures;
+}
+
 // Rayleigh-Ritz of a block with exactly and nearly dependent rows (exact copies, a
 // combination, a zero row): the orthonormalisation takes its multi-pass route,
 // residual rows and pseudo-random completion included; the Ritz vectors must still
@@ -555,6 +664,12 @@ int main(int argc, char** argv) {
     scenario_response_bz(ctx, grid(9, 8, 7, 0.5), 70, 2, 1, 2, LRDM_FP64);
     scenario_response_bz(ctx, grid(9, 8, 7, 0.5), 70, 3, 2, 1, LRDM_FP32);
     scenario_response_bz(ctx, grid(8, 8, 8, 0.5), 70, 2, 1, 2, LRDM_BF16X3);
+  }
+  if (which == "all" || which == "kpt") {
+    scenario_rr_bloch(ctx, grid(10, 9, 8, 0.45), 150, 5);
+    // 4N > M: the overlap product of the pairing has more rows than points
+    scenario_rr_bloch(ctx, grid(7, 9, 11, 0.5), 200, 4);
+    scenario_rr_bloch_degenerate(ctx);
   }
   if (which == "all" || which == "batched") {
     scenario_batched(ctx, LRDM_FP32);

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from tests.gpu_common import rel, to_dev, to_host
+from tests.gpu_common import filter_bounds, rel, to_dev, to_host
 from tests.pins import small_wells
 
 torch = pytest.importorskip("torch")
@@ -172,3 +172,145 @@ def test_bloch_chfsi_reaches_the_lowest_states():
         eps, X = O.rayleigh_ritz_bloch(Y[0] + 1j * Y[1], V, g, k)
         a, a0 = float(eps[-1]), float(eps[0]) - 0.1
     assert np.max(np.abs(eps[:12] - e_ref[:12])) < 1e-9
+
+
+# ------------------------------------------------- Rayleigh-Ritz of H_k on the GPU
+def _bloch_ritz_checks(P, e, V, g, k, tol_orth=1e-10):
+    """P complex [N][M] orthonormal, diagonalising H_k in its span.  One Cholesky
+    pass is taken below a Gram condition number of 1e3, so orthonormality holds to
+    about 1e3 * N * eps_64 (1e-10 here)."""
+    N = P.shape[0]
+    assert np.all(np.diff(e) >= 0.0)
+    assert np.max(np.abs(P.conj() @ P.T - np.eye(N))) < tol_orth
+    HP = O.bloch_hamiltonian_apply(P.reshape((N,) + g.shape), V, g, k).reshape(N, -1)
+    assert np.max(np.abs(P.conj() @ HP.T - np.diag(e))) < 1e-10 * np.max(np.abs(e))
+
+
+def _bloch_rr_case(case):
+    if case == "small":
+        g = O.Grid((8, 7, 6), (4.0, 3.5, 3.0))
+        V = small_wells(g.n, g.L, 71, nwells=2)
+        return g, V, (0.3, -0.5, 0.2), _bloch_block(g, 16, 72)
+    if case == "multitile":   # 2N = 300 realified rows: three 128-row tiles, ragged grid
+        g = O.Grid((20, 18, 13), (8.0, 7.2, 5.2))
+        V = small_wells(g.n, g.L, 73, nwells=3)
+        k = (0.5, -0.3, 0.9)
+        a, b, a0 = filter_bounds(V, g)
+        return g, V, k, O.chebyshev_filter_bloch(_bloch_block(g, 150, 74), V, g, k, 4, a, b, a0)
+    # 4N = 800 rows in the pairing's overlap product, more than the 693 points
+    g = O.Grid((7, 9, 11), (3.5, 4.5, 5.5))
+    V = small_wells(g.n, g.L, 75, nwells=2)
+    return g, V, (-0.7, 0.4, 0.25), _bloch_block(g, 200, 76)
+
+
+@pytest.mark.parametrize("case", ["small", "multitile", "wide"])
+def test_rayleigh_ritz_bloch_matches_oracle(case):
+    """Complex Rayleigh-Ritz of one k-point: Ritz values match the oracle's
+    (Householder QR and the Hermitian eigensolver on the complex block), the GPU
+    Ritz vectors are orthonormal in the complex product and diagonalise H_k, and
+    each one equals the oracle's up to its phase, within a bound that scales with
+    the inverse gap to its neighbours."""
+    g, V, k, Y = _bloch_rr_case(case)
+    N = Y.shape[0]
+    print(f"case {case}: grid {g.n}, N={N}, k={k}", flush=True)
+    eps_o, Psi_o = O.rayleigh_ritz_bloch(Y, V, g, k)
+    Yd = to_dev(np.stack([Y.real, Y.imag]))
+    e = to_host(L.subspace_rayleigh_ritz_bloch(_grid(g), to_dev(V), Yd, k))
+    scale = np.max(np.abs(eps_o))
+    assert np.max(np.abs(e - eps_o)) < 1e-10 * scale
+    Yh = to_host(Yd)
+    P = (Yh[0] + 1j * Yh[1]).reshape(N, -1)
+    _bloch_ritz_checks(P, e, V, g, k)
+    Po = Psi_o.reshape(N, -1)
+    gaps = np.full(N, np.inf)
+    gaps[1:] = np.minimum(gaps[1:], np.diff(eps_o))
+    gaps[:-1] = np.minimum(gaps[:-1], np.diff(eps_o))
+    worst = 0.0
+    for i in range(N):
+        c = np.vdot(Po[i], P[i])
+        err = np.linalg.norm(P[i] - (c / abs(c)) * Po[i])
+        worst = max(worst, err * gaps[i] / scale)
+        assert err < 1e-11 * scale / gaps[i] + 1e-10, (i, err, gaps[i])
+    print(f"max vector error x gap / scale: {worst:.2e}")
+
+
+def test_rayleigh_ritz_bloch_at_k0_is_the_real_path():
+    """k = 0 and real states: the complex Rayleigh-Ritz returns each Ritz value of
+    the real path once, and real Ritz vectors up to a phase."""
+    g = O.Grid((20, 18, 13), (8.0, 7.2, 5.2))
+    V = small_wells(g.n, g.L, 77, nwells=3)
+    N = 130
+    Y = np.random.default_rng(78).standard_normal((N,) + g.shape)
+    e_real = to_host(L.subspace_rayleigh_ritz(_grid(g), to_dev(V), to_dev(Y)))
+    Yd = to_dev(np.stack([Y, np.zeros_like(Y)]))
+    e = to_host(L.subspace_rayleigh_ritz_bloch(_grid(g), to_dev(V), Yd, (0.0, 0.0, 0.0)))
+    assert np.max(np.abs(e - e_real)) < 1e-10 * np.max(np.abs(e_real))
+    Yh = to_host(Yd)
+    P = (Yh[0] + 1j * Yh[1]).reshape(N, -1)
+    _bloch_ritz_checks(P, e, V, g, (0.0, 0.0, 0.0))
+    # the phase of each vector is arbitrary; removed, it is real
+    for i in range(N):
+        j = np.argmax(np.abs(P[i]))
+        q = P[i] * (abs(P[i, j]) / P[i, j])
+        assert np.max(np.abs(q.imag)) < 1e-9
+
+
+def test_bloch_chfsi_on_the_gpu_reaches_the_lowest_states():
+    """ChFSI of one k-point entirely on the GPU (Bloch filter, complex
+    Rayleigh-Ritz) converges to the lowest eigenvalues of H_k from dense
+    diagonalisation."""
+    g = O.Grid((8, 7, 6), (4.0, 3.5, 3.0))
+    V = small_wells(g.n, g.L, 67, nwells=2)
+    k = (0.3, -0.5, 0.2)
+    e_ref, _ = O.lowest_bloch_states(V, g, k, 16)
+    X0 = _bloch_block(g, 16, 68)
+    X = to_dev(np.stack([X0.real, X0.imag]))
+    b = sum(2.0 / hd ** 2 for hd in g.h) + float(V.max())
+    a0 = float(V.min()) - 0.1
+    a = a0 + 0.25 * (b - a0)
+    Vd = to_dev(V)
+    for _ in range(14):
+        Y = L.chfsi_filter_bloch(_grid(g), Vd, X, k, 12, a, b, a0)
+        eps = to_host(L.subspace_rayleigh_ritz_bloch(_grid(g), Vd, Y, k))
+        X = Y
+        a, a0 = float(eps[-1]), float(eps[0]) - 0.1
+    assert np.max(np.abs(eps[:12] - e_ref[:12])) < 1e-9
+
+
+def test_rayleigh_ritz_bloch_dependent_block_is_an_error():
+    """A state that is a complex multiple of another: the complex block is rank
+    deficient, and the call reports ENOTCONV."""
+    g = O.Grid((8, 7, 6), (4.0, 3.5, 3.0))
+    V = small_wells(g.n, g.L, 79, nwells=2)
+    Y = _bloch_block(g, 16, 80)
+    Y[5] = (0.3 - 0.7j) * Y[2]
+    with pytest.raises(L.LrdmError, match="ENOTCONV"):
+        L.subspace_rayleigh_ritz_bloch(_grid(g), to_dev(V), to_dev(np.stack([Y.real, Y.imag])),
+                                       (0.2, 0.1, -0.4))
+
+
+@pytest.mark.parametrize("k", [(0.0, 0.0, 0.0), (0.4, 0.0, 0.0), (0.3, 0.3, 0.0)])
+def test_rayleigh_ritz_bloch_degenerate_multiplets(k):
+    """Free electrons (V = 0) on a cubic grid: H_k has exactly degenerate
+    multiplets (six and twelve equal energies at k = 0, fourfold and twofold
+    ones along the axis and the face diagonal).  The subspace of the lowest
+    eigenvectors up to a gap, mixed by a random complex matrix, is invariant, so
+    its Ritz values are those energies with their multiplicities; each multiplet
+    is a cluster of real Ritz values that the pairing must split into
+    orthonormal complex vectors."""
+    g = O.Grid((6, 6, 6), (3.0, 3.0, 3.0))
+    V = np.zeros(g.shape)
+    e_all, P_all = O.lowest_bloch_states(V, g, k, 40)
+    gaps = np.nonzero(np.diff(e_all) > 1e-6)[0] + 1
+    N = int(gaps[gaps <= 24].max())
+    mult = np.diff(np.concatenate([[0], gaps[gaps <= N]]))
+    print(f"k={k}: N={N}, multiplicities {mult.tolist()}", flush=True)
+    assert mult.max() >= 4
+    rng = np.random.default_rng(81)
+    Q = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    Y = np.tensordot(Q, P_all[:N], axes=1)
+    Yd = to_dev(np.stack([Y.real, Y.imag]))
+    e = to_host(L.subspace_rayleigh_ritz_bloch(_grid(g), to_dev(V), Yd, k))
+    assert np.max(np.abs(e - e_all[:N])) < 1e-10 * np.max(np.abs(e_all[:N]))
+    Yh = to_host(Yd)
+    _bloch_ritz_checks((Yh[0] + 1j * Yh[1]).reshape(N, -1), e, V, g, k)
