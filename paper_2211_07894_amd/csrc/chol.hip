@@ -80,116 +80,71 @@ __global__ void chol_init_kernel(const double* __restrict__ G, const double* __r
 }
 
 // Factor the diagonal block kb (dependent rows: zero column, unit diagonal) and
-// write L_kk to A and its inverse to Linv[kb].  256 threads; thread t keeps the
-// lower-triangle entries e = t + 256 s (row-major order of the triangle) in
-// registers.  Column j: its entries, as updated so far, go to an LDS column buffer
-// (two alternating buffers), and after one barrier every thread applies
-// S_il -= S_ij S_lj / S_jj to the entries it owns with l > j (nothing for a
-// dependent column).  The inverse is built by substitution on 16 x 16 diagonal
-// blocks and doubling.
-constexpr int kTri = CB * (CB + 1) / 2;          // 2080 lower-triangle entries
-constexpr int kOwn = (kTri + 255) / 256;         // 9 per thread
-
-__global__ __launch_bounds__(256) void chol_diag_kernel(double* __restrict__ A, int Np, int kb,
-                                                        double tau, int* __restrict__ dead,
-                                                        double* __restrict__ Linv) {
-  __shared__ double col[2][CB];
+// write L_kk to A and its inverse to Linv[kb].  One wave: lane i keeps row i of
+// the block in registers.  At column j every lane publishes its entry S_ij to an
+// LDS column, and lane i applies S_il -= S_ij S_lj / S_jj for l > j (nothing for a
+// dependent column); the entries as they stood when their column was eliminated
+// give L.  The inverse follows by forward substitution, lane c taking column c.
+// The chain of 64 eliminations runs inside one wave, so each step costs a few
+// LDS accesses rather than a workgroup barrier.
+__global__ __launch_bounds__(64) void chol_diag_kernel(double* __restrict__ A, int Np, int kb,
+                                                       double tau, int* __restrict__ dead,
+                                                       double* __restrict__ Linv) {
+  __shared__ double col[CB];
   __shared__ double piv[CB];
-  __shared__ double tmp[CB * CB / 4];
+  __shared__ double sq[CB];
   __shared__ double L[CB * CP];
-  __shared__ double X[CB * CP];
-  const int t = threadIdx.x;
+  const int lane = threadIdx.x;
   const int64_t o = (int64_t)kb * CB;
-  int ri[kOwn], ci[kOwn];
-  double v[kOwn];
-#pragma unroll
-  for (int s = 0; s < kOwn; ++s) {
-    const int e = t + 256 * s;
-    int i = -1, l = -1;
-    if (e < kTri) {
-      i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-      while ((i + 1) * (i + 2) / 2 <= e) ++i;
-      while (i * (i + 1) / 2 > e) --i;
-      l = e - i * (i + 1) / 2;
-    }
-    ri[s] = i;
-    ci[s] = l;
-    v[s] = (i >= 0) ? A[(o + i) * Np + o + l] : 0.0;
-    if (l == 0) col[0][i] = v[s];
-  }
+  // rows through LDS, so that the global reads are coalesced
+  for (int i = 0; i < CB; ++i) L[i * CP + lane] = A[(o + i) * Np + o + lane];
   __syncthreads();
+  double r[CB];
+#pragma unroll
+  for (int l = 0; l < CB; ++l) r[l] = (l <= lane) ? L[lane * CP + l] : 0.0;
+#pragma unroll
   for (int j = 0; j < CB; ++j) {
-    const double* cj = col[j & 1];
-    double* cn = col[(j + 1) & 1];
-    const double d = cj[j];
-    const bool live = d > tau;  // NaN is dependent
-    const double inv = live ? 1.0 / d : 0.0;
+    col[lane] = r[j];
+    __syncthreads();
+    const double d = col[j];
+    const double f = d > tau ? r[j] / d : 0.0;  // NaN is dependent
 #pragma unroll
-    for (int s = 0; s < kOwn; ++s) {
-      if (ci[s] > j) v[s] -= cj[ri[s]] * cj[ci[s]] * inv;
-      if (ci[s] == j + 1) cn[ri[s]] = v[s];
-    }
-    if (t == 0) piv[j] = d;
+    for (int l = j + 1; l < CB; ++l) r[l] -= f * col[l];
+    piv[j] = d;   // every lane stores the same value
     __syncthreads();
   }
-  // L from the entries as they stood when their column was eliminated
-#pragma unroll
-  for (int s = 0; s < kOwn; ++s) {
-    if (ri[s] < 0) continue;
-    const int i = ri[s], l = ci[s];
-    const double d = piv[l];
-    const bool live = d > tau;
-    double x;
-    if (i == l)
-      x = live ? sqrt(d) : 1.0;
-    else
-      x = live ? v[s] / sqrt(d) : 0.0;
-    L[i * CP + l] = x;
-  }
-  for (int e = t; e < CB * CB; e += 256) {
-    const int i = e / CB, c = e % CB;
-    if (c > i) L[i * CP + c] = 0.0;
-    X[i * CP + c] = 0.0;
+  {
+    const double d = piv[lane];
+    sq[lane] = d > tau ? sqrt(d) : 0.0;
   }
   __syncthreads();
-  // X = L^{-1}: the four 16 x 16 diagonal blocks by forward substitution (a
-  // thread per column), then doubling: X21 = -X22 (L21 X11) for neighbouring
-  // super-blocks of 16 and then 32.
-  if (t < CB) {
-    const int b0 = (t >> 4) * 16, c = b0 + (t & 15);
-    for (int i = c; i < b0 + 16; ++i) {
-      double sum = (i == c) ? 1.0 : 0.0;
-      for (int l = c; l < i; ++l) sum -= L[i * CP + l] * X[l * CP + c];
-      X[i * CP + c] = sum / L[i * CP + i];
-    }
+#pragma unroll
+  for (int l = 0; l < CB; ++l) {
+    const double s = sq[l];
+    double x = 0.0;
+    if (l < lane)
+      x = s > 0.0 ? r[l] / s : 0.0;
+    else if (l == lane)
+      x = s > 0.0 ? s : 1.0;
+    L[lane * CP + l] = x;
   }
   __syncthreads();
-  for (int h = 16; h < CB; h *= 2) {
-    const int n = (CB / (2 * h)) * h * h;  // elements of all pairs' h x h blocks
-    for (int e = t; e < n; e += 256) {
-      const int pr = e / (h * h), i = (e / h) % h, j = e % h;
-      const int c0 = 2 * h * pr, r0 = c0 + h;
-      double sum = 0.0;
-      for (int l = j; l < h; ++l) sum += L[(r0 + i) * CP + c0 + l] * X[(c0 + l) * CP + c0 + j];
-      tmp[e] = sum;
-    }
-    __syncthreads();
-    for (int e = t; e < n; e += 256) {
-      const int pr = e / (h * h), i = (e / h) % h, j = e % h;
-      const int c0 = 2 * h * pr, r0 = c0 + h;
-      double sum = 0.0;
-      for (int l = 0; l <= i; ++l) sum += X[(r0 + i) * CP + r0 + l] * tmp[pr * h * h + l * h + j];
-      X[(r0 + i) * CP + c0 + j] = -sum;
-    }
-    __syncthreads();
+  // X = L^{-1}, column `lane`: x_i = (delta_ic - sum_{l<i} L_il x_l) / L_ii
+  double x[CB];
+#pragma unroll
+  for (int i = 0; i < CB; ++i) {
+    double sum = (i == lane) ? 1.0 : 0.0;
+#pragma unroll
+    for (int l = 0; l < i; ++l) sum -= L[i * CP + l] * x[l];
+    x[i] = sum / L[i * CP + i];
   }
   double* Li = Linv + (int64_t)kb * CB * CB;
-  for (int e = t; e < CB * CB; e += 256) {
-    const int i = e / CB, j = e % CB;
-    A[(o + i) * Np + o + j] = L[i * CP + j];
-    Li[e] = X[i * CP + j];
+#pragma unroll
+  for (int i = 0; i < CB; ++i) {
+    Li[i * CB + lane] = x[i];
+    A[(o + i) * Np + o + lane] = L[i * CP + lane];
   }
-  if (t < CB) dead[o + t] = piv[t] > tau ? 0 : 1;
+  dead[o + lane] = piv[lane] > tau ? 0 : 1;
 }
 
 // Panel below the diagonal block: L_ib,kb = A_ib,kb Linv_kk^T, dependent columns zero.
@@ -485,7 +440,7 @@ lrdm_status chol_orth(lrdm_ctx* ctx, const double* G, int N, double tau, double*
   chol_max_kernel<<<1, 256, 0, ctx->stream>>>(pw, N, sc);
   if ((e = hipGetLastError()) != hipSuccess) return fail(e);
   for (int kb = 0; kb < nb; ++kb) {
-    chol_diag_kernel<<<1, 256, 0, ctx->stream>>>(A, Np, kb, tau, dead, Linv);
+    chol_diag_kernel<<<1, CB, 0, ctx->stream>>>(A, Np, kb, tau, dead, Linv);
     const int m = nb - kb - 1;
     if (m > 0) {
       chol_trsm_kernel<<<m, 256, 0, ctx->stream>>>(A, Np, kb, Linv, dead);
