@@ -521,8 +521,81 @@ def grown_forms(torch, L, dev, reps=5):
             f"adjoint {bwd_ms:.1f} ms")
         adjoint[form] = dict(N=wl.N, M=wl.M, r=wl.rank, forward_ms=round(fwd_ms, 2),
                              backward_ms=round(bwd_ms, 2))
+    del Psi, eps, U, dV, G
     return dict(batched=batched["fp32"], batched_bf16x3=batched["bf16x3"],
-                adjoint_c80=adjoint["fp32"], adjoint_c80_bf16x3=adjoint["bf16x3"])
+                adjoint_c80=adjoint["fp32"], adjoint_c80_bf16x3=adjoint["bf16x3"],
+                kpoints_c48=kpoint_forms(torch, L, dev, ms_of))
+
+
+def kpoint_forms(torch, L, dev, ms_of):
+    """Brillouin-zone sampling on the 48^3 / 256-state cell: four k-points (Gamma,
+    two zone-face midpoints along x and y, and the body diagonal's midpoint; weights
+    1/8, 3/8, 3/8, 1/8).  Set-up (untimed): three real ChFSI passes (degree 10, then
+    30) from the seeded block give a Gamma subspace; each k-point starts from it,
+    takes one Bloch filter pass and the complex Rayleigh-Ritz.  Timed (median of
+    the repetitions): one ChFSI pass of each k-point (Bloch filter, degree 30, and
+    the complex Rayleigh-Ritz, FP64), and the zone-sampled response of the eight
+    GRF directions (density_response_bz) in the three forms."""
+    import numpy as np
+    from inputs import grf_directions, make_workload
+    wl = make_workload("c48_n256")
+    grid = L.Grid(tuple(wl.n), tuple(wl.L))
+    occ = L.Occupation(1, wl.kT, wl.n_electrons)
+    N = wl.N
+    V = torch.from_numpy(np.ascontiguousarray(wl.V[0])).to(dev)
+    b_up = sum(2.0 / hd ** 2 for hd in wl.h) + float(wl.V[0].max())
+    X = torch.from_numpy(wl.block()).to(dev).reshape((N,) + grid.shape).contiguous()
+    Y = torch.empty_like(X)
+    a0 = float(wl.V[0].min()) - 0.1
+    a = a0 + 0.25 * (b_up - a0)
+    for p in range(3):
+        L.chfsi_filter(grid, V, X, 10 if p == 0 else wl.degree, a, b_up, a0, out=Y)
+        e = L.subspace_rayleigh_ritz(grid, V, Y)
+        X, Y = Y, X
+        a, a0 = float(e[-1].item()), float(e[0].item()) - 0.2
+    kx, ky, kz = (np.pi / L_ for L_ in wl.L)
+    ks = [(0.0, 0.0, 0.0), (0.5 * kx, 0.0, 0.0), (0.0, 0.5 * ky, 0.0),
+          (0.5 * kx, 0.5 * ky, 0.5 * kz)]
+    weights = torch.tensor([0.125, 0.375, 0.375, 0.125], dtype=torch.float64, device=dev)
+    nk = len(ks)
+    Psi = torch.zeros((1, nk, 2, N) + grid.shape, dtype=torch.float64, device=dev)
+    eps = torch.empty((1, nk, N), dtype=torch.float64, device=dev)
+    Yk = torch.empty((2, N) + grid.shape, dtype=torch.float64, device=dev)
+    bounds = []
+    for q, k in enumerate(ks):
+        Psi[0, q, 0] = X
+        L.chfsi_filter_bloch(grid, V, Psi[0, q], k, wl.degree, a, b_up, a0, out=Yk)
+        eps[0, q] = L.subspace_rayleigh_ritz_bloch(grid, V, Yk, k)
+        Psi[0, q].copy_(Yk)
+        bounds.append((float(eps[0, q, -1].item()), b_up, float(eps[0, q, 0].item()) - 0.2))
+
+    def chfsi_pass(q):
+        L.chfsi_filter_bloch(grid, V, Psi[0, q], ks[q], wl.degree, *bounds[q], out=Yk)
+        L.subspace_rayleigh_ritz_bloch(grid, V, Yk, ks[q])
+
+    pass_ms = [ms_of(lambda q=q: chfsi_pass(q)) for q in range(nk)]
+    u = torch.from_numpy(grf_directions(wl.system_id, wl.n, wl.L, wl.rank)).to(dev)
+    dV = L.hartree_kernel(grid, u.reshape((wl.rank,) + grid.shape).contiguous())
+    dV = dV.reshape((wl.rank, 1) + grid.shape).contiguous()
+    response = {}
+    drho64 = None
+    for form in ("fp64", "fp32", "bf16x3"):
+        P = Psi if form == "fp64" else Psi.float()
+        ms = ms_of(lambda: L.density_response_bz(grid, P, eps, weights, occ, dV, prec=form))
+        drho, _, _ = L.density_response_bz(grid, P, eps, weights, occ, dV, prec=form)
+        if drho64 is None:
+            drho64 = drho.clone()
+        err = float((torch.linalg.vector_norm(drho - drho64) /
+                     torch.linalg.vector_norm(drho64)).item())
+        response[form] = dict(ms=round(ms, 3), directions_per_s=round(1e3 * wl.rank / ms, 2),
+                              rel_err_vs_fp64=err)
+        log(f"zone sampling 48^3 / 256 states / 4 k-points / {wl.rank} directions ({form}): "
+            f"response {ms:.2f} ms, rel err vs fp64 {err:.1e}")
+    log("zone sampling: ChFSI pass per k-point (Bloch filter degree "
+        f"{wl.degree} + complex Rayleigh-Ritz) " + ", ".join(f"{t:.1f}" for t in pass_ms) + " ms")
+    return dict(grid=list(wl.n), N=N, nk=nk, weights=[0.125, 0.375, 0.375, 0.125],
+                directions=wl.rank, chfsi_pass_ms_per_k=[round(t, 2) for t in pass_ms],
+                response=response)
 
 
 def measure_peaks(torch, dev):

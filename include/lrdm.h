@@ -277,12 +277,18 @@ lrdm_status subspace_rayleigh_ritz(lrdm_ctx* ctx, const lrdm_grid* grid, const d
  * one) is factored by the FP64 Cholesky QR of subspace_rayleigh_ritz, the
  * projection of the real form of H_k is diagonalised by the same block Jacobi
  * eigensolver (each Ritz value of H_k appears twice there, with the vectors v
- * and i v), and one vector of each pair is kept.  Each Ritz vector's phase is
- * arbitrary.  Synchronises the stream.  Errors: EINVAL (arguments; N at most
- * 4096), ENOMEM, EDEVICE, ENOTCONV (eigensolver without convergence; a complex
- * block numerically rank deficient as given, or one that three passes could
- * not orthonormalise; Ritz values so close that the pairs could not be told
- * apart). */
+ * and i v), and one vector of each pair is kept; a multiplet of equal Ritz
+ * values comes out as orthonormal complex vectors spanning it.  Each Ritz
+ * vector's phase is arbitrary.  Rows that the first Cholesky pass finds
+ * dependent are resolved, as in subspace_rayleigh_ritz, by a pass over their
+ * explicit residuals; unlike there, a block that stays rank deficient is an
+ * error, not completed with pseudo-random rows.  Synchronises the stream.
+ * Errors: EINVAL (arguments; N at most 4096), ENOMEM, EDEVICE, ENOTCONV
+ * (eigensolver without convergence; a complex block numerically rank deficient
+ * as given, i.e. a state whose residual against the states before it is below
+ * 1e-8 of its length, or one that five passes could not orthonormalise; a
+ * multiplet of more than 32 equal Ritz values, or real Ritz values that do not
+ * fall into pairs). */
 lrdm_status subspace_rayleigh_ritz_bloch(lrdm_ctx* ctx, const lrdm_grid* grid, const double* V,
                                          double kx, double ky, double kz, double* Psi,
                                          int32_t N, double* eps);

@@ -721,6 +721,27 @@ __global__ void add_inplace_kernel(double* __restrict__ a, const double* __restr
 
 __global__ void zero_int_kernel(int* __restrict__ x) { *x = 0; }
 
+// *out = min_i G_ii over the n x n matrix G (a non-finite or negative entry counts
+// as 0).
+__global__ __launch_bounds__(256) void min_diag_kernel(const double* __restrict__ G, int n,
+                                                       double* __restrict__ out) {
+  __shared__ double red[256];
+  const int t = threadIdx.x;
+  double m = __builtin_huge_val();
+  for (int i = t; i < n; i += 256) {
+    double v = G[(int64_t)i * n + i];
+    if (!(v > 0.0 && v < __builtin_huge_val())) v = 0.0;
+    m = fmin(m, v);
+  }
+  red[t] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) red[t] = fmin(red[t], red[t + w]);
+    __syncthreads();
+  }
+  if (t == 0) *out = red[0];
+}
+
 // Cluster gap of the ascending real Ritz values e2 [n2].
 __device__ inline double cluster_tol(const double* e2, int n2) {
   const double scale = fmax(fmax(fabs(e2[0]), fabs(e2[n2 - 1])), e2[n2 - 1] - e2[0]);
@@ -1007,7 +1028,7 @@ size_t rr_bloch_workspace_bytes(int N, int64_t M) {
   b += 2 * ws_align((size_t)n2 * sizeof(int));                    // clusters
   b += ws_align((size_t)n2 * kPairRow * sizeof(cplx));            // cluster scratch
   b += ws_align((size_t)N * kPairMax * sizeof(cplx));             // coefficients
-  b += 2 * ws_align((size_t)N * sizeof(int)) + ws_align(64);
+  b += 2 * ws_align((size_t)N * sizeof(int)) + 2 * ws_align(64);
   size_t inner = chol_orth_bytes(n2);
   inner = std::max(inner, 2 * ws_align((size_t)Np * Np * sizeof(double)) +
                               ws_align((size_t)(nb / 2) * JS * JS * 8) + ws_align(256) +
@@ -1042,6 +1063,7 @@ lrdm_status rayleigh_ritz_bloch(lrdm_ctx* ctx, const Grid3& g, const double* V,
   int* ostart = static_cast<int*>(ws_take(ctx, (size_t)N * sizeof(int)));
   int* osize = static_cast<int*>(ws_take(ctx, (size_t)N * sizeof(int)));
   int* flag = static_cast<int*>(ws_take(ctx, 64));
+  double* dmin = static_cast<double*>(ws_take(ctx, 64));
   const size_t mark = ctx->ws_top;
   hipError_t e;
   auto fail = [&](const char* what, hipError_t err) {
@@ -1067,30 +1089,56 @@ lrdm_status rayleigh_ritz_bloch(lrdm_ctx* ctx, const Grid3& g, const double* V,
     add_inplace_kernel<<<add_grid, 256, 0, ctx->stream>>>(out, G2, nsq);
     return hipGetLastError();
   };
+  // Orthonormal basis as in the real path: one Cholesky pass for a well-conditioned
+  // block, more over the explicitly formed basis otherwise.  Rows the factor finds
+  // dependent become their explicit residuals relative to their own length; one
+  // below 1e-8 (or a row still dependent on the third pass) means the complex
+  // block is rank deficient as given, which is an error here: completing it
+  // with pseudo-random rows, as the real path does, would break the pairing of
+  // y and i y.
   double* Bc = B;
-  CholInfo ci;
+  CholInfo ci{n2, 0.0};
+  bool check_residuals = false;
   for (int pass = 0;; ++pass) {
     if (pass > 0) {
-      if (pass == 3) {
+      if (pass == kMaxOrthPasses) {
         ctx->err = "rayleigh_ritz_bloch: the block could not be orthonormalised";
         return LRDM_ENOTCONV;
       }
       transpose_kernel<<<grd, blk, 0, ctx->stream>>>(Tm, n2, Wt);
       for (int h = 0; h < 2; ++h)
         if ((e = launch_nn_f64<double>(ctx, Wt, Bc + h * plane, spare + h * plane, n2, M,
-                                       true)) != hipSuccess)
+                                       ci.live == n2)) != hipSuccess)
           return fail("rotation", e);
       std::swap(Bc, spare);
     }
     if ((e = two_plane(Bc, nullptr, G)) != hipSuccess) return fail("gram", e);
+    if (check_residuals) {
+      min_diag_kernel<<<1, 256, 0, ctx->stream>>>(G, n2, dmin);
+      double host_min = 0.0;
+      if ((e = hipGetLastError()) != hipSuccess ||
+          (e = hipMemcpyAsync(&host_min, dmin, sizeof(double), hipMemcpyDeviceToHost,
+                              ctx->stream)) != hipSuccess ||
+          (e = hipStreamSynchronize(ctx->stream)) != hipSuccess)
+        return fail("residual norms", e);
+      if (host_min < 1e-16) {
+        ctx->err = "rayleigh_ritz_bloch: the complex block is numerically rank deficient";
+        return LRDM_ENOTCONV;
+      }
+      check_residuals = false;
+    }
     lrdm_status st = chol_orth(ctx, G, n2, kDependentTol, Tm, &ci);
     ctx->ws_top = mark;
     if (st != LRDM_OK) return st;
     if (ci.live < n2) {
-      ctx->err = "rayleigh_ritz_bloch: the complex block is numerically rank deficient";
-      return LRDM_ENOTCONV;
+      if (pass >= 2) {
+        ctx->err = "rayleigh_ritz_bloch: the complex block is numerically rank deficient";
+        return LRDM_ENOTCONV;
+      }
+      check_residuals = true;
+    } else if (ci.cond < kOnePassCond64) {
+      break;
     }
-    if (ci.cond < kOnePassCond64) break;
   }
   // H_k on the 2N complex states, then the projected real operator
   if ((e = launch_bloch_step<double>(ctx, g, V, kvec, Bc, nullptr, HB, n2, 1.0, 0.0, 0.0)) !=

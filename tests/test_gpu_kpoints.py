@@ -314,3 +314,23 @@ def test_rayleigh_ritz_bloch_degenerate_multiplets(k):
     assert np.max(np.abs(e - e_all[:N])) < 1e-10 * np.max(np.abs(e_all[:N]))
     Yh = to_host(Yd)
     _bloch_ritz_checks((Yh[0] + 1j * Yh[1]).reshape(N, -1), e, V, g, k)
+
+
+def test_rayleigh_ritz_bloch_near_dependent_block():
+    """A state that is a complex multiple of another plus 1e-6 of noise: the first
+    Cholesky pass finds it dependent, the pass over the explicitly formed basis
+    resolves its residual, and the Ritz pairs match the oracle's (Householder QR
+    of the complex block)."""
+    g = O.Grid((8, 7, 6), (4.0, 3.5, 3.0))
+    V = small_wells(g.n, g.L, 83, nwells=2)
+    k = (0.2, 0.1, -0.4)
+    Y = _bloch_block(g, 16, 84)
+    Y[5] = (0.3 - 0.7j) * Y[2] + 1e-6 * _bloch_block(g, 1, 85)[0]
+    eps_o, _ = O.rayleigh_ritz_bloch(Y, V, g, k)
+    Yd = to_dev(np.stack([Y.real, Y.imag]))
+    e = to_host(L.subspace_rayleigh_ritz_bloch(_grid(g), to_dev(V), Yd, k))
+    assert np.max(np.abs(e - eps_o)) < 1e-8 * np.max(np.abs(eps_o))
+    # the residual of the nearly dependent state is formed to a relative accuracy
+    # of about u / 1e-6 = 1e-10, the bound on the pairing and on orthonormality
+    Yh = to_host(Yd)
+    _bloch_ritz_checks((Yh[0] + 1j * Yh[1]).reshape(16, -1), e, V, g, k, tol_orth=1e-9)
