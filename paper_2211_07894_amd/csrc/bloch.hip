@@ -11,8 +11,10 @@
 // s_d = sin(k_d h_d):
 //   Re H_k u = -1/2 sum_d (c_d (a+ + a-) - s_d (b+ - b-) - 2a)/h_d^2 + V a,
 //   Im H_k u = -1/2 sum_d (c_d (b+ + b-) + s_d (a+ - a-) - 2b)/h_d^2 + V b.
-// One thread forms both planes of one point of one state; the neighbours come
-// through the caches (x fastest, so a wavefront reads contiguous rows).
+// Planes of up to 3072 points: a workgroup marches through a run of z-planes of
+// one state with plane z of both parts in LDS (bloch_plane_kernel).  Larger
+// planes: one thread forms both parts of one point of one state, the neighbours
+// through the caches (bloch_step_kernel).
 #include "lrdm_internal.h"
 
 namespace lrdm {
@@ -70,6 +72,122 @@ __global__ __launch_bounds__(kBlochThreads) void bloch_step_kernel(
   out[ob] = (T)hi;
 }
 
+// The same step over a run of z-planes of one state (blockIdx.x), for planes of at
+// most 1024 Q points: plane z of both parts is staged in LDS for the x and y
+// neighbours, planes z - 1 and z + 1 stay in registers as the run advances.  Each
+// thread owns Q points of the plane.  The arithmetic is that of bloch_step_kernel,
+// term for term.
+template <typename T, int Q, int TB>
+__global__ __launch_bounds__(TB) void bloch_plane_kernel(
+    const T* __restrict__ in, const T* old, T* out, const double* __restrict__ V, int nx, int ny,
+    int nz, int N, int zrun, BlochCoef k, double alpha, double c0, double beta) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char bloch_smem[];
+  double* bloch_lds = reinterpret_cast<double*>(bloch_smem);   // [2][P]: plane z, both parts
+  const int P = nx * ny;
+  const int64_t M = (int64_t)P * nz;
+  const int i = blockIdx.x;
+  const int z0 = blockIdx.y * zrun, z1 = min(nz, z0 + zrun);
+  const T* a = in + (int64_t)i * M;
+  const T* b = in + ((int64_t)N + i) * M;
+  double* la = bloch_lds;
+  double* lb = bloch_lds + P;
+  double am[Q], ac[Q], ap[Q], bm[Q], bc[Q], bp[Q];
+  {
+    const int64_t zm = z0 == 0 ? nz - 1 : z0 - 1, zp = z0 + 1 == nz ? 0 : z0 + 1;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const int q = threadIdx.x + j * blockDim.x;
+      am[j] = ac[j] = ap[j] = bm[j] = bc[j] = bp[j] = 0.0;
+      if (q < P) {
+        am[j] = (double)a[zm * P + q];
+        ac[j] = (double)a[(int64_t)z0 * P + q];
+        ap[j] = (double)a[zp * P + q];
+        bm[j] = (double)b[zm * P + q];
+        bc[j] = (double)b[(int64_t)z0 * P + q];
+        bp[j] = (double)b[zp * P + q];
+      }
+    }
+  }
+  for (int z = z0; z < z1; ++z) {
+    __syncthreads();   // every read of the previous plane is done
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const int q = threadIdx.x + j * blockDim.x;
+      if (q < P) {
+        la[q] = ac[j];
+        lb[q] = bc[j];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const int q = threadIdx.x + j * blockDim.x;
+      if (q >= P) continue;
+      const int y = q / nx, x = q - y * nx;
+      const int xp = x + 1 == nx ? q - x : q + 1, xm = x == 0 ? q + nx - 1 : q - 1;
+      const int yp = y + 1 == ny ? x : q + nx, ym = y == 0 ? q + (ny - 1) * nx : q - nx;
+      const double apc = ac[j], bpc = bc[j];
+      const double a1[3] = {la[xp], la[yp], ap[j]}, a0m[3] = {la[xm], la[ym], am[j]};
+      const double b1[3] = {lb[xp], lb[yp], bp[j]}, b0m[3] = {lb[xm], lb[ym], bm[j]};
+      double lr = 0.0, li = 0.0;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        lr += (k.c[d] * (a1[d] + a0m[d]) - k.s[d] * (b1[d] - b0m[d]) - 2.0 * apc) * k.ih2[d];
+        li += (k.c[d] * (b1[d] + b0m[d]) + k.s[d] * (a1[d] - a0m[d]) - 2.0 * bpc) * k.ih2[d];
+      }
+      const int64_t pz = (int64_t)z * P + q;
+      const double v = V[pz];
+      double hr = -0.5 * lr + v * apc - c0 * apc;
+      double hi = -0.5 * li + v * bpc - c0 * bpc;
+      hr *= alpha;
+      hi *= alpha;
+      const int64_t oa = (int64_t)i * M + pz, ob = ((int64_t)N + i) * M + pz;
+      if (beta != 0.0) {
+        hr += beta * (double)old[oa];
+        hi += beta * (double)old[ob];
+      }
+      out[oa] = (T)hr;
+      out[ob] = (T)hi;
+      // one point's neighbour values live at a time
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // advance the run; plane z + 2 is loaded here and first used after the next
+    // plane's two barriers
+    const bool more = z + 1 < z1;
+    const int64_t zpp = z + 2 >= nz ? z + 2 - nz : z + 2;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const int q = threadIdx.x + j * blockDim.x;
+      am[j] = ac[j];
+      ac[j] = ap[j];
+      bm[j] = bc[j];
+      bc[j] = bp[j];
+      if (q < P && more) {
+        ap[j] = (double)a[zpp * P + q];
+        bp[j] = (double)b[zpp * P + q];
+      }
+    }
+  }
+}
+
+template <typename T, int Q, int TB>
+hipError_t launch_plane(const Grid3& g, const double* V, const T* in, const T* old, T* out, int N,
+                        int threads, const BlochCoef& k, double alpha, double c0, double beta,
+                        hipStream_t stream) {
+  // z runs: enough blocks for the chip (N * runs >= ~1024), runs of >= 8 planes
+  int runs = 1;
+  while ((int64_t)N * runs < 1024 && g.nz / (runs * 2) >= 8) runs *= 2;
+  const int zrun = (g.nz + runs - 1) / runs;
+  const size_t smem = 2 * (size_t)g.nx * g.ny * sizeof(double);
+  if (smem > 65536)
+    LRDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&bloch_plane_kernel<T, Q, TB>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+  dim3 grd((unsigned)N, (unsigned)((g.nz + zrun - 1) / zrun));
+  bloch_plane_kernel<T, Q, TB><<<grd, threads, smem, stream>>>(in, old, out, V, g.nx, g.ny, g.nz,
+                                                              N, zrun, k, alpha, c0, beta);
+  return hipGetLastError();
+}
+
 BlochCoef coef(const Grid3& g, const double kvec[3]) {
   BlochCoef k;
   const double h[3] = {g.hx, g.hy, g.hz};
@@ -87,10 +205,22 @@ template <typename T>
 hipError_t launch_bloch_step(lrdm_ctx* ctx, const Grid3& g, const double* V, const double kvec[3],
                              const T* in, const T* old, T* out, int N, double alpha, double c0,
                              double beta) {
-  dim3 grd((unsigned)((g.M + kBlochThreads - 1) / kBlochThreads), (unsigned)N);
   ProfScope prof(ctx, "bloch_step");
+  const BlochCoef k = coef(g, kvec);
+  // planes of up to 3072 points: the plane-staged kernel (1024 threads, up to
+  // three points each, at most 48 KB of LDS for both parts in FP64); larger
+  // planes take the per-point kernel
+  const int P = g.nx * g.ny;
+  if (P <= 1024)
+    return launch_plane<T, 1, 1024>(g, V, in, old, out, N, ((P + 63) / 64) * 64, k, alpha, c0,
+                                    beta, ctx->stream);
+  if (P <= 2048)
+    return launch_plane<T, 2, 1024>(g, V, in, old, out, N, 1024, k, alpha, c0, beta, ctx->stream);
+  if (P <= 3072)
+    return launch_plane<T, 3, 1024>(g, V, in, old, out, N, 1024, k, alpha, c0, beta, ctx->stream);
+  dim3 grd((unsigned)((g.M + kBlochThreads - 1) / kBlochThreads), (unsigned)N);
   bloch_step_kernel<T><<<grd, kBlochThreads, 0, ctx->stream>>>(in, old, out, V, g.nx, g.ny, g.nz,
-                                                               N, coef(g, kvec), alpha, c0, beta);
+                                                               N, k, alpha, c0, beta);
   return hipGetLastError();
 }
 template hipError_t launch_bloch_step<double>(lrdm_ctx*, const Grid3&, const double*,
