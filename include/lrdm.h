@@ -270,9 +270,10 @@ lrdm_status subspace_rayleigh_ritz(lrdm_ctx* ctx, const lrdm_grid* grid, const d
 
 /* subspace_rayleigh_ritz for the Bloch Hamiltonian H_k of one k-point (Sec. II
  * C, last paragraph; H_k as in lrdm_bloch_hamiltonian_apply): Psi [2][N][M]
- * (the N real parts, then the N imaginary parts, double), in = the filtered
- * complex block, out = N Ritz vectors orthonormal in the complex l2 product;
- * eps [N] double (device), ascending.  The complex block is handled as the 2N
+ * (the N real parts, then the N imaginary parts; double for LRDM_FP64, float
+ * for LRDM_FP32 and LRDM_BF16X3, whose arithmetic here is FP64 as well, H_k Psi
+ * included), in = the filtered complex block, out = N Ritz vectors orthonormal
+ * in the complex l2 product; eps [N] double (device), ascending.  The complex block is handled as the 2N
  * real vectors of y_i and i y_i: their Gram matrix (the real part of the complex
  * one) is factored by the FP64 Cholesky QR of subspace_rayleigh_ritz, the
  * projection of the real form of H_k is diagonalised by the same block Jacobi
@@ -290,8 +291,8 @@ lrdm_status subspace_rayleigh_ritz(lrdm_ctx* ctx, const lrdm_grid* grid, const d
  * multiplet of more than 32 equal Ritz values, or real Ritz values that do not
  * fall into pairs). */
 lrdm_status subspace_rayleigh_ritz_bloch(lrdm_ctx* ctx, const lrdm_grid* grid, const double* V,
-                                         double kx, double ky, double kz, double* Psi,
-                                         int32_t N, double* eps);
+                                         double kx, double ky, double kz, void* Psi, int32_t N,
+                                         lrdm_prec prec, double* eps);
 
 /* Subspace density response (Eqs. (19)-(22), traceless condition after
  * Eq. (24); per channel without the factor 2 in Sec. II D):

@@ -786,21 +786,24 @@ extern "C" lrdm_status subspace_rayleigh_ritz(lrdm_ctx* ctx, const lrdm_grid* gr
 
 extern "C" lrdm_status subspace_rayleigh_ritz_bloch(lrdm_ctx* ctx, const lrdm_grid* grid,
                                                     const double* V, double kx, double ky,
-                                                    double kz, double* Psi, int32_t N,
-                                                    double* eps) {
+                                                    double kz, void* Psi, int32_t N,
+                                                    lrdm_prec prec, double* eps) {
   LRDM_CHECK(ctx, check_grid(grid));
   LRDM_CHECK(ctx, check_block(grid, N));
   if (N > 4096) return fail(ctx, LRDM_EINVAL, "N must be <= 4096 for a complex block");
+  LRDM_CHECK(ctx, check_prec(prec));
   LRDM_CHECK(ctx, check_kvec(kx, ky, kz));
   LRDM_NONNULL(ctx, V, "V");
   LRDM_NONNULL(ctx, Psi, "Psi");
   LRDM_NONNULL(ctx, eps, "eps");
   const Grid3 g = make_grid3(grid);
-  lrdm_status st = begin(ctx, rr_bloch_workspace_bytes(N, g.M));
+  lrdm_status st = begin(ctx, rr_bloch_workspace_bytes(N, g.M, prec));
   if (st != LRDM_OK) return st;
   const double kvec[3] = {kx, ky, kz};
   return guarded(ctx, [&]() -> lrdm_status {
-    return rayleigh_ritz_bloch(ctx, g, V, kvec, Psi, N, eps);
+    if (prec == LRDM_FP64)
+      return rayleigh_ritz_bloch<double>(ctx, g, V, kvec, static_cast<double*>(Psi), N, eps);
+    return rayleigh_ritz_bloch<float>(ctx, g, V, kvec, static_cast<float*>(Psi), N, eps);
   });
 }
 

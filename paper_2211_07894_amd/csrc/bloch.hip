@@ -28,9 +28,9 @@ struct BlochCoef {
 
 // out = alpha (H_k in - c0 in) + beta old (old may be out itself: each thread
 // reads old at its point before writing it; beta = 0 ignores old).
-template <typename T>
+template <typename TI, typename TO>
 __global__ __launch_bounds__(kBlochThreads) void bloch_step_kernel(
-    const T* __restrict__ in, const T* old, T* out, const double* __restrict__ V, int nx, int ny,
+    const TI* __restrict__ in, const TO* old, TO* out, const double* __restrict__ V, int nx, int ny,
     int nz, int N, BlochCoef k, double alpha, double c0, double beta) {
   const int64_t M = (int64_t)nx * ny * nz;
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -39,8 +39,8 @@ __global__ __launch_bounds__(kBlochThreads) void bloch_step_kernel(
   const int x = (int)(p % nx);
   const int y = (int)((p / nx) % ny);
   const int z = (int)(p / ((int64_t)nx * ny));
-  const T* a = in + (int64_t)i * M;            // real plane of state i
-  const T* b = in + ((int64_t)N + i) * M;      // imaginary plane
+  const TI* a = in + (int64_t)i * M;           // real plane of state i
+  const TI* b = in + ((int64_t)N + i) * M;     // imaginary plane
   const int64_t xp = p - x + (x + 1 == nx ? 0 : x + 1), xm = p - x + (x == 0 ? nx - 1 : x - 1);
   const int64_t yo = (int64_t)nx;
   const int64_t yp = p + (y + 1 == ny ? -(int64_t)(ny - 1) * yo : yo);
@@ -68,8 +68,8 @@ __global__ __launch_bounds__(kBlochThreads) void bloch_step_kernel(
     hr += beta * (double)old[oa];
     hi += beta * (double)old[ob];
   }
-  out[oa] = (T)hr;
-  out[ob] = (T)hi;
+  out[oa] = (TO)hr;
+  out[ob] = (TO)hi;
 }
 
 // The same step over a run of z-planes of one state (blockIdx.x), for planes of at
@@ -77,9 +77,9 @@ __global__ __launch_bounds__(kBlochThreads) void bloch_step_kernel(
 // neighbours, planes z - 1 and z + 1 stay in registers as the run advances.  Each
 // thread owns Q points of the plane.  The arithmetic is that of bloch_step_kernel,
 // term for term.
-template <typename T, int Q, int TB>
+template <typename TI, typename TO, int Q, int TB>
 __global__ __launch_bounds__(TB) void bloch_plane_kernel(
-    const T* __restrict__ in, const T* old, T* out, const double* __restrict__ V, int nx, int ny,
+    const TI* __restrict__ in, const TO* old, TO* out, const double* __restrict__ V, int nx, int ny,
     int nz, int N, int zrun, BlochCoef k, double alpha, double c0, double beta) {
   extern __shared__ __attribute__((aligned(16))) unsigned char bloch_smem[];
   double* bloch_lds = reinterpret_cast<double*>(bloch_smem);   // [2][P]: plane z, both parts
@@ -87,8 +87,8 @@ __global__ __launch_bounds__(TB) void bloch_plane_kernel(
   const int64_t M = (int64_t)P * nz;
   const int i = blockIdx.x;
   const int z0 = blockIdx.y * zrun, z1 = min(nz, z0 + zrun);
-  const T* a = in + (int64_t)i * M;
-  const T* b = in + ((int64_t)N + i) * M;
+  const TI* a = in + (int64_t)i * M;
+  const TI* b = in + ((int64_t)N + i) * M;
   double* la = bloch_lds;
   double* lb = bloch_lds + P;
   double am[Q], ac[Q], ap[Q], bm[Q], bc[Q], bp[Q];
@@ -146,8 +146,8 @@ __global__ __launch_bounds__(TB) void bloch_plane_kernel(
         hr += beta * (double)old[oa];
         hi += beta * (double)old[ob];
       }
-      out[oa] = (T)hr;
-      out[ob] = (T)hi;
+      out[oa] = (TO)hr;
+      out[ob] = (TO)hi;
       // one point's neighbour values live at a time
       __builtin_amdgcn_sched_barrier(0);
     }
@@ -170,21 +170,22 @@ __global__ __launch_bounds__(TB) void bloch_plane_kernel(
   }
 }
 
-template <typename T, int Q, int TB>
-hipError_t launch_plane(const Grid3& g, const double* V, const T* in, const T* old, T* out, int N,
-                        int threads, const BlochCoef& k, double alpha, double c0, double beta,
-                        hipStream_t stream) {
+template <typename TI, typename TO, int Q, int TB>
+hipError_t launch_plane(const Grid3& g, const double* V, const TI* in, const TO* old, TO* out,
+                        int N, int threads, const BlochCoef& k, double alpha, double c0,
+                        double beta, hipStream_t stream) {
   // z runs: enough blocks for the chip (N * runs >= ~1024), runs of >= 8 planes
   int runs = 1;
   while ((int64_t)N * runs < 1024 && g.nz / (runs * 2) >= 8) runs *= 2;
   const int zrun = (g.nz + runs - 1) / runs;
   const size_t smem = 2 * (size_t)g.nx * g.ny * sizeof(double);
   if (smem > 65536)
-    LRDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&bloch_plane_kernel<T, Q, TB>),
+    LRDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&bloch_plane_kernel<TI, TO, Q, TB>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
   dim3 grd((unsigned)N, (unsigned)((g.nz + zrun - 1) / zrun));
-  bloch_plane_kernel<T, Q, TB><<<grd, threads, smem, stream>>>(in, old, out, V, g.nx, g.ny, g.nz,
-                                                              N, zrun, k, alpha, c0, beta);
+  bloch_plane_kernel<TI, TO, Q, TB><<<grd, threads, smem, stream>>>(in, old, out, V, g.nx, g.ny,
+                                                                   g.nz, N, zrun, k, alpha, c0,
+                                                                   beta);
   return hipGetLastError();
 }
 
@@ -199,12 +200,11 @@ BlochCoef coef(const Grid3& g, const double kvec[3]) {
   return k;
 }
 
-}  // namespace
-
-template <typename T>
-hipError_t launch_bloch_step(lrdm_ctx* ctx, const Grid3& g, const double* V, const double kvec[3],
-                             const T* in, const T* old, T* out, int N, double alpha, double c0,
-                             double beta) {
+// out = alpha (H_k in - c0 in) + beta old on blocks of N complex states.
+template <typename TI, typename TO>
+hipError_t bloch_dispatch(lrdm_ctx* ctx, const Grid3& g, const double* V, const double kvec[3],
+                          const TI* in, const TO* old, TO* out, int N, double alpha, double c0,
+                          double beta) {
   ProfScope prof(ctx, "bloch_step");
   const BlochCoef k = coef(g, kvec);
   // planes of up to 3072 points: the plane-staged kernel (1024 threads, up to
@@ -212,17 +212,38 @@ hipError_t launch_bloch_step(lrdm_ctx* ctx, const Grid3& g, const double* V, con
   // planes take the per-point kernel
   const int P = g.nx * g.ny;
   if (P <= 1024)
-    return launch_plane<T, 1, 1024>(g, V, in, old, out, N, ((P + 63) / 64) * 64, k, alpha, c0,
-                                    beta, ctx->stream);
+    return launch_plane<TI, TO, 1, 1024>(g, V, in, old, out, N, ((P + 63) / 64) * 64, k, alpha,
+                                         c0, beta, ctx->stream);
   if (P <= 2048)
-    return launch_plane<T, 2, 1024>(g, V, in, old, out, N, 1024, k, alpha, c0, beta, ctx->stream);
+    return launch_plane<TI, TO, 2, 1024>(g, V, in, old, out, N, 1024, k, alpha, c0, beta,
+                                         ctx->stream);
   if (P <= 3072)
-    return launch_plane<T, 3, 1024>(g, V, in, old, out, N, 1024, k, alpha, c0, beta, ctx->stream);
+    return launch_plane<TI, TO, 3, 1024>(g, V, in, old, out, N, 1024, k, alpha, c0, beta,
+                                         ctx->stream);
   dim3 grd((unsigned)((g.M + kBlochThreads - 1) / kBlochThreads), (unsigned)N);
-  bloch_step_kernel<T><<<grd, kBlochThreads, 0, ctx->stream>>>(in, old, out, V, g.nx, g.ny, g.nz,
-                                                               N, k, alpha, c0, beta);
+  bloch_step_kernel<TI, TO><<<grd, kBlochThreads, 0, ctx->stream>>>(
+      in, old, out, V, g.nx, g.ny, g.nz, N, k, alpha, c0, beta);
   return hipGetLastError();
 }
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_bloch_step(lrdm_ctx* ctx, const Grid3& g, const double* V, const double kvec[3],
+                             const T* in, const T* old, T* out, int N, double alpha, double c0,
+                             double beta) {
+  return bloch_dispatch<T, T>(ctx, g, V, kvec, in, old, out, N, alpha, c0, beta);
+}
+
+template <typename T>
+hipError_t launch_bloch_hpsi_f64(lrdm_ctx* ctx, const Grid3& g, const double* V,
+                                 const double kvec[3], const T* in, double* out, int N) {
+  return bloch_dispatch<T, double>(ctx, g, V, kvec, in, nullptr, out, N, 1.0, 0.0, 0.0);
+}
+template hipError_t launch_bloch_hpsi_f64<double>(lrdm_ctx*, const Grid3&, const double*,
+                                                  const double[3], const double*, double*, int);
+template hipError_t launch_bloch_hpsi_f64<float>(lrdm_ctx*, const Grid3&, const double*,
+                                                 const double[3], const float*, double*, int);
 template hipError_t launch_bloch_step<double>(lrdm_ctx*, const Grid3&, const double*,
                                               const double[3], const double*, const double*,
                                               double*, int, double, double, double);

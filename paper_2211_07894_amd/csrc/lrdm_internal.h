@@ -175,6 +175,10 @@ template <typename T>
 hipError_t launch_bloch_step(lrdm_ctx* ctx, const Grid3& g, const double* V, const double kvec[3],
                              const T* in, const T* old, T* out, int N, double alpha, double c0,
                              double beta);
+// out = H_k in in FP64 for a block of N complex states stored as T (bloch.hip).
+template <typename T>
+hipError_t launch_bloch_hpsi_f64(lrdm_ctx* ctx, const Grid3& g, const double* V,
+                                 const double kvec[3], const T* in, double* out, int N);
 
 // launch_fermi with Brillouin-zone sampling: eps [nspin][nk][N], weights [nk]
 // (device); mu from the zone-averaged count, then f, 1 - f, f' and the divided
@@ -362,10 +366,11 @@ lrdm_status rayleigh_ritz(lrdm_ctx* ctx, const Grid3& g, const double* V, T* Psi
                           lrdm_prec prec, double* eps);
 size_t rr_workspace_bytes(int N, int64_t M, lrdm_prec prec);
 // Rayleigh-Ritz of the Bloch Hamiltonian H_k on N complex states [2][N][M]
-// (real parts, then imaginary parts), FP64 storage.
+// (real parts, then imaginary parts) stored as T; FP64 arithmetic.
+template <typename T>
 lrdm_status rayleigh_ritz_bloch(lrdm_ctx* ctx, const Grid3& g, const double* V,
-                                const double kvec[3], double* Psi, int N, double* eps);
-size_t rr_bloch_workspace_bytes(int N, int64_t M);
+                                const double kvec[3], T* Psi, int N, double* eps);
+size_t rr_bloch_workspace_bytes(int N, int64_t M, lrdm_prec prec);
 
 // Hartree kernel (poisson.hip): dV[k] = 4 pi (-Lap_h)^{-1} (sum_c u[k][c]) for k < r,
 // written to every channel slot of dV when nspin_out > 1.

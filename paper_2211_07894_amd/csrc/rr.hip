@@ -700,12 +700,12 @@ __device__ inline cplx c_conj_mul(cplx a, cplx b) {   // conj(a) b
 __device__ inline double c_abs2(cplx a) { return a.re * a.re + a.im * a.im; }
 
 // B [2][2N][M]: the complex block of the 2N states y_i, i y_i from Y [2][N][M].
-__global__ void realify_kernel(const double* __restrict__ Y, int N, int64_t M,
-                               double* __restrict__ B) {
+template <typename T>
+__global__ void realify_kernel(const T* __restrict__ Y, int N, int64_t M, T* __restrict__ B) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y;
   if (p >= M) return;
-  const double yr = Y[(int64_t)i * M + p], yi = Y[((int64_t)N + i) * M + p];
+  const T yr = Y[(int64_t)i * M + p], yi = Y[((int64_t)N + i) * M + p];
   const int64_t n2 = 2 * (int64_t)N;
   B[(int64_t)i * M + p] = yr;
   B[((int64_t)N + i) * M + p] = -yi;
@@ -763,7 +763,8 @@ __global__ void cluster_kernel(const double* __restrict__ e2, int n2, int* __res
 
 // Complex overlaps <psi_a, psi_b> of real Ritz vector a (one block) with every
 // member b of its cluster, for clusters of four or more; R [2][n2][M].
-__global__ __launch_bounds__(256) void cluster_overlap_kernel(const double* __restrict__ R,
+template <typename T>
+__global__ __launch_bounds__(256) void cluster_overlap_kernel(const T* __restrict__ R,
                                                               const int* __restrict__ cs,
                                                               const int* __restrict__ cn, int n2,
                                                               int64_t M, cplx* __restrict__ scr) {
@@ -771,15 +772,16 @@ __global__ __launch_bounds__(256) void cluster_overlap_kernel(const double* __re
   const int a = blockIdx.x, t = threadIdx.x;
   const int s = cs[a], n = cn[a];
   if (n < 4 || n > kPairMax) return;
-  const double* ar = R + (int64_t)a * M;
-  const double* ai = R + ((int64_t)n2 + a) * M;
+  const T* ar = R + (int64_t)a * M;
+  const T* ai = R + ((int64_t)n2 + a) * M;
   for (int j = 0; j < n; ++j) {
-    const double* br = R + (int64_t)(s + j) * M;
-    const double* bi = R + ((int64_t)n2 + s + j) * M;
+    const T* br = R + (int64_t)(s + j) * M;
+    const T* bi = R + ((int64_t)n2 + s + j) * M;
     double re = 0.0, im = 0.0;
     for (int64_t p = t; p < M; p += 256) {
-      re += ar[p] * br[p] + ai[p] * bi[p];
-      im += ar[p] * bi[p] - ai[p] * br[p];
+      const double xr = ar[p], xi = ai[p], yr = br[p], yi = bi[p];
+      re += xr * yr + xi * yi;
+      im += xr * yi - xi * yr;
     }
     red[0][t] = re;
     red[1][t] = im;
@@ -995,10 +997,11 @@ __global__ void cluster_pair_kernel(const double* __restrict__ e2, const int* __
 
 // Psi [2][N][M]: the complex Ritz vectors sum_l coef[o][l] psi_{ostart[o] + l} from
 // the real ones R [2][2N][M] (real part of (a + ib)(re + i im) = a re - b im).
-__global__ void cluster_combine_kernel(const double* __restrict__ R, const cplx* __restrict__ coef,
+template <typename T>
+__global__ void cluster_combine_kernel(const T* __restrict__ R, const cplx* __restrict__ coef,
                                        const int* __restrict__ ostart,
                                        const int* __restrict__ osize, int N, int64_t M,
-                                       double* __restrict__ Psi) {
+                                       T* __restrict__ Psi) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int o = blockIdx.y;
   if (p >= M) return;
@@ -1012,17 +1015,19 @@ __global__ void cluster_combine_kernel(const double* __restrict__ R, const cplx*
     xr += c.re * re - c.im * im;
     xi += c.re * im + c.im * re;
   }
-  Psi[(int64_t)o * M + p] = xr;
-  Psi[((int64_t)N + o) * M + p] = xi;
+  Psi[(int64_t)o * M + p] = (T)xr;
+  Psi[((int64_t)N + o) * M + p] = (T)xi;
 }
 
 }  // namespace
 
-size_t rr_bloch_workspace_bytes(int N, int64_t M) {
+size_t rr_bloch_workspace_bytes(int N, int64_t M, lrdm_prec prec) {
   const int n2 = 2 * N;
   const int Np = ((n2 + JS - 1) / JS) * JS;
   const int nb = Np / JB;
-  size_t b = 3 * ws_align((size_t)2 * n2 * M * sizeof(double));   // B, spare, H B
+  const size_t s = prec == LRDM_FP64 ? sizeof(double) : sizeof(float);
+  size_t b = 2 * ws_align((size_t)2 * n2 * M * s);                 // B, spare
+  b += ws_align((size_t)2 * n2 * M * sizeof(double));              // H B
   b += 7 * ws_align((size_t)n2 * n2 * sizeof(double));            // G, G2, T, C, X, Wt, Q
   b += ws_align((size_t)n2 * sizeof(double));                     // real Ritz values
   b += 2 * ws_align((size_t)n2 * sizeof(int));                    // clusters
@@ -1033,20 +1038,22 @@ size_t rr_bloch_workspace_bytes(int N, int64_t M) {
   inner = std::max(inner, 2 * ws_align((size_t)Np * Np * sizeof(double)) +
                               ws_align((size_t)(nb / 2) * JS * JS * 8) + ws_align(256) +
                               ws_align((size_t)Np * 4) + ws_align(kFrobBlocks * sizeof(double)));
-  inner = std::max(inner, ws_align(tn_workspace_bytes(n2, M, 1, LRDM_FP64)));
+  inner = std::max(inner, ws_align(tn_workspace_bytes(n2, M, 1, prec)));
   return b + inner;
 }
 
 // Psi [2][N][M] (real parts, then imaginary parts; the filtered block on entry)
-// -> Ritz vectors of H_k, eps ascending.  FP64 storage.
+// -> Ritz vectors of H_k, eps ascending.  Storage T, FP64 arithmetic throughout
+// (H B is formed and kept in FP64, as in the real path).
+template <typename T>
 lrdm_status rayleigh_ritz_bloch(lrdm_ctx* ctx, const Grid3& g, const double* V,
-                                const double kvec[3], double* Psi, int N, double* eps) {
+                                const double kvec[3], T* Psi, int N, double* eps) {
   const int64_t M = g.M;
   const int n2 = 2 * N;
   const size_t plane = (size_t)n2 * M;
   const size_t nn = (size_t)n2 * n2 * sizeof(double);
-  double* B = static_cast<double*>(ws_take(ctx, 2 * plane * sizeof(double)));
-  double* spare = static_cast<double*>(ws_take(ctx, 2 * plane * sizeof(double)));
+  T* B = static_cast<T*>(ws_take(ctx, 2 * plane * sizeof(T)));
+  T* spare = static_cast<T*>(ws_take(ctx, 2 * plane * sizeof(T)));
   double* HB = static_cast<double*>(ws_take(ctx, 2 * plane * sizeof(double)));
   double* G = static_cast<double*>(ws_take(ctx, nn));
   double* G2 = static_cast<double*>(ws_take(ctx, nn));
@@ -1073,17 +1080,19 @@ lrdm_status rayleigh_ritz_bloch(lrdm_ctx* ctx, const Grid3& g, const double* V,
   const dim3 blk(32, 8), grd((n2 + 31) / 32, (n2 + 7) / 8);
   const int64_t nsq = (int64_t)n2 * n2;
   const unsigned add_grid = (unsigned)((nsq + 255) / 256);
-  realify_kernel<<<dim3((unsigned)((M + 255) / 256), N), 256, 0, ctx->stream>>>(Psi, N, M, B);
+  realify_kernel<T><<<dim3((unsigned)((M + 255) / 256), N), 256, 0, ctx->stream>>>(Psi, N, M, B);
   if ((e = hipGetLastError()) != hipSuccess) return fail("realify", e);
   // out = P_re Q_re^T + P_im Q_im^T (Q = P when Q2 is null).  Each product forms its
   // upper tiles and mirrors them; the sum of the two is symmetric, so the mirrored
   // sum is the sum.  A product's partial sums are free once its reduction is queued.
-  auto two_plane = [&](const double* P, const double* Q2, double* out) -> hipError_t {
-    hipError_t err = launch_tn_sym_f64<double, double>(ctx, P, Q2, nullptr, 0, n2, M, 1, 1, out);
+  auto two_plane = [&](const T* P, const double* Q2, double* out) -> hipError_t {
+    hipError_t err = Q2 ? launch_tn_sym_f64<T, double>(ctx, P, Q2, nullptr, 0, n2, M, 1, 1, out)
+                        : launch_tn_sym_f64<T, T>(ctx, P, nullptr, nullptr, 0, n2, M, 1, 1, out);
     ctx->ws_top = mark;
     if (err != hipSuccess) return err;
-    err = launch_tn_sym_f64<double, double>(ctx, P + plane, Q2 ? Q2 + plane : nullptr, nullptr, 0,
-                                            n2, M, 1, 1, G2);
+    err = Q2 ? launch_tn_sym_f64<T, double>(ctx, P + plane, Q2 + plane, nullptr, 0, n2, M, 1, 1,
+                                            G2)
+             : launch_tn_sym_f64<T, T>(ctx, P + plane, nullptr, nullptr, 0, n2, M, 1, 1, G2);
     ctx->ws_top = mark;
     if (err != hipSuccess) return err;
     add_inplace_kernel<<<add_grid, 256, 0, ctx->stream>>>(out, G2, nsq);
@@ -1096,7 +1105,7 @@ lrdm_status rayleigh_ritz_bloch(lrdm_ctx* ctx, const Grid3& g, const double* V,
   // block is rank deficient as given, which is an error here: completing it
   // with pseudo-random rows, as the real path does, would break the pairing of
   // y and i y.
-  double* Bc = B;
+  T* Bc = B;
   CholInfo ci{n2, 0.0};
   bool check_residuals = false;
   for (int pass = 0;; ++pass) {
@@ -1107,8 +1116,8 @@ lrdm_status rayleigh_ritz_bloch(lrdm_ctx* ctx, const Grid3& g, const double* V,
       }
       transpose_kernel<<<grd, blk, 0, ctx->stream>>>(Tm, n2, Wt);
       for (int h = 0; h < 2; ++h)
-        if ((e = launch_nn_f64<double>(ctx, Wt, Bc + h * plane, spare + h * plane, n2, M,
-                                       ci.live == n2)) != hipSuccess)
+        if ((e = launch_nn_f64<T>(ctx, Wt, Bc + h * plane, spare + h * plane, n2, M,
+                                  ci.live == n2)) != hipSuccess)
           return fail("rotation", e);
       std::swap(Bc, spare);
     }
@@ -1141,8 +1150,7 @@ lrdm_status rayleigh_ritz_bloch(lrdm_ctx* ctx, const Grid3& g, const double* V,
     }
   }
   // H_k on the 2N complex states, then the projected real operator
-  if ((e = launch_bloch_step<double>(ctx, g, V, kvec, Bc, nullptr, HB, n2, 1.0, 0.0, 0.0)) !=
-      hipSuccess)
+  if ((e = launch_bloch_hpsi_f64<T>(ctx, g, V, kvec, Bc, HB, n2)) != hipSuccess)
     return fail("H_k", e);
   if ((e = two_plane(Bc, HB, G)) != hipSuccess) return fail("projection", e);
   if ((e = small_gemm(ctx, false, false, n2, n2, n2, 1.0, Tm, n2, G, n2, 0.0, X, n2)) !=
@@ -1158,16 +1166,15 @@ lrdm_status rayleigh_ritz_bloch(lrdm_ctx* ctx, const Grid3& g, const double* V,
   if ((e = small_gemm(ctx, true, false, n2, n2, n2, 1.0, Tm, n2, Q, n2, 0.0, Wt, n2)) !=
       hipSuccess)
     return fail("gemm", e);
-  double* R = (Bc == B) ? spare : B;
+  T* R = (Bc == B) ? spare : B;
   for (int h = 0; h < 2; ++h)
-    if ((e = launch_nn_f64<double>(ctx, Wt, Bc + h * plane, R + h * plane, n2, M)) !=
-        hipSuccess)
+    if ((e = launch_nn_f64<T>(ctx, Wt, Bc + h * plane, R + h * plane, n2, M)) != hipSuccess)
       return fail("rotation", e);
   // clusters of real Ritz values, the complex pairs of each, and their vectors
   const unsigned cgrid = (unsigned)((n2 + 255) / 256);
   zero_int_kernel<<<1, 1, 0, ctx->stream>>>(flag);
   cluster_kernel<<<cgrid, 256, 0, ctx->stream>>>(e2, n2, cs, cn);
-  cluster_overlap_kernel<<<n2, 256, 0, ctx->stream>>>(R, cs, cn, n2, M, scr);
+  cluster_overlap_kernel<T><<<n2, 256, 0, ctx->stream>>>(R, cs, cn, n2, M, scr);
   cluster_pair_kernel<<<cgrid, 256, 0, ctx->stream>>>(e2, cs, cn, N, scr, coef, ostart, osize,
                                                       eps, flag);
   if ((e = hipGetLastError()) != hipSuccess) return fail("pairs", e);
@@ -1181,10 +1188,15 @@ lrdm_status rayleigh_ritz_bloch(lrdm_ctx* ctx, const Grid3& g, const double* V,
                "pairs (at most 32 equal Ritz values of H_k are resolved)";
     return LRDM_ENOTCONV;
   }
-  cluster_combine_kernel<<<dim3((unsigned)((M + 255) / 256), N), 256, 0, ctx->stream>>>(
+  cluster_combine_kernel<T><<<dim3((unsigned)((M + 255) / 256), N), 256, 0, ctx->stream>>>(
       R, coef, ostart, osize, N, M, Psi);
   if ((e = hipGetLastError()) != hipSuccess) return fail("combine", e);
   return LRDM_OK;
 }
+
+template lrdm_status rayleigh_ritz_bloch<double>(lrdm_ctx*, const Grid3&, const double*,
+                                                 const double[3], double*, int, double*);
+template lrdm_status rayleigh_ritz_bloch<float>(lrdm_ctx*, const Grid3&, const double*,
+                                                const double[3], float*, int, double*);
 
 }  // namespace lrdm

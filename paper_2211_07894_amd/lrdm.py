@@ -143,7 +143,8 @@ def library() -> ctypes.CDLL:
                                                  ctypes.c_int],
                 "chfsi_filter_bloch": [vp, G, vp, f64, f64, f64, vp, vp, i32, ctypes.c_int, i32,
                                        f64, f64, f64],
-                "subspace_rayleigh_ritz_bloch": [vp, G, vp, f64, f64, f64, vp, i32, vp],
+                "subspace_rayleigh_ritz_bloch": [vp, G, vp, f64, f64, f64, vp, i32, ctypes.c_int,
+                                                 vp],
                 "density_response_noalloc": [vp, G, vp, vp, i32, O, vp, i32, ctypes.c_int, vp, vp,
                                              vp],
                 "lrdm_residual_derivative": [vp, G, vp, vp, i32, O, vp, i32, ctypes.c_int, vp],
@@ -414,17 +415,18 @@ def chfsi_filter_bloch(grid: Grid, V, X, kvec, degree, a, b, a0, prec="fp64", ou
     return Y
 
 
-def subspace_rayleigh_ritz_bloch(grid: Grid, V, Psi, kvec, eps=None):
-    """In place: filtered complex block Psi [2][N][nz][ny][nx] (FP64; real parts,
-    then imaginary parts) -> Ritz vectors of H_k; returns eps (ascending)."""
+def subspace_rayleigh_ritz_bloch(grid: Grid, V, Psi, kvec, prec="fp64", eps=None):
+    """In place: filtered complex block Psi [2][N][nz][ny][nx] (real parts, then
+    imaginary parts; float64 for fp64, float32 otherwise) -> Ritz vectors of H_k;
+    returns eps (ascending, FP64)."""
     N = Psi.shape[1]
     e = torch.empty(N, dtype=torch.float64, device=Psi.device) if eps is None else eps
     ctx = context(Psi.device.index)
     g = grid.c()
     ctx.check(ctx.lib.subspace_rayleigh_ritz_bloch(
         ctx.ptr, ctypes.byref(g), _ptr(V, "V", torch.float64, grid.M), float(kvec[0]),
-        float(kvec[1]), float(kvec[2]), _ptr(Psi, "Psi", torch.float64, 2 * N * grid.M), N,
-        _ptr(e, "eps", torch.float64, N)))
+        float(kvec[1]), float(kvec[2]), _ptr(Psi, "Psi", _block_dtype(prec), 2 * N * grid.M), N,
+        _prec(prec), _ptr(e, "eps", torch.float64, N)))
     return e
 
 

@@ -294,7 +294,7 @@ void scenario_rr_bloch(lrdm_ctx* ctx, lrdm_grid g, int N, int degree) {
   std::snprintf(name, sizeof name, "subspace_rayleigh_ritz_bloch N=%d grid %dx%dx%d", N, g.n[0],
                 g.n[1], g.n[2]);
   check(subspace_rayleigh_ritz_bloch(ctx, &g, V.data(), k[0], k[1], k[2], Y.data(), N,
-                                     eps.data()),
+                                     LRDM_FP64, eps.data()),
         ctx, name);
   check(lrdm_bloch_hamiltonian_apply(ctx, &g, V.data(), k[0], k[1], k[2], Y.data(), HY.data(), N,
                                      LRDM_FP64),
@@ -359,7 +359,8 @@ void scenario_rr_bloch_degenerate(lrdm_ctx* ctx) {
             Y[(size_t)N * M + (size_t)i * M + p] += qr * wi + qi * wr;
           }
     }
-  check(subspace_rayleigh_ritz_bloch(ctx, &g, V.data(), 0.0, 0.0, 0.0, Y.data(), N, eps.data()),
+  check(subspace_rayleigh_ritz_bloch(ctx, &g, V.data(), 0.0, 0.0, 0.0, Y.data(), N, LRDM_FP64,
+                                     eps.data()),
         ctx, "subspace_rayleigh_ritz_bloch degenerate N=19 (1 + 6 + 12)");
   const double e1 = (1 - std::cos(2 * pi / n)) / (h * h);   // one direction at +-1
   double worst_e = 0;

@@ -196,13 +196,14 @@ def test_backproj_layout_needs_a_context(lib):
     (dict(N=5000), "N must be <= 4096 for a complex block"),
     (dict(N=9000), "N must not exceed"),
     (dict(k=(0.1, float("nan"), 0.0)), "k must be finite"),
+    (dict(prec=5), "prec must be"),
     (dict(Psi=None), "Psi is NULL"),
     (dict(eps=None), "eps is NULL"),
     (dict(), "ctx is NULL"),
 ])
 def test_bloch_rayleigh_ritz_validation(lib, args, msg):
-    a = dict(N=64, k=(0.1, 0.2, 0.3), Psi=P, eps=P)
+    a = dict(N=64, k=(0.1, 0.2, 0.3), Psi=P, eps=P, prec=0)
     a.update(args)
     st = lib.subspace_rayleigh_ritz_bloch(None, ctypes.byref(_grid((20, 20, 20), (8.0, 8.0, 8.0))),
-                                          P, *a["k"], a["Psi"], a["N"], a["eps"])
+                                          P, *a["k"], a["Psi"], a["N"], a["prec"], a["eps"])
     assert st == -1 and msg in _err(lib)

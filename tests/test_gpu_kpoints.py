@@ -340,3 +340,26 @@ def test_rayleigh_ritz_bloch_near_dependent_block():
     # of about u / 1e-6 = 1e-10, the bound on the pairing and on orthonormality
     Yh = to_host(Yd)
     _bloch_ritz_checks((Yh[0] + 1j * Yh[1]).reshape(16, -1), e, V, g, k, tol_orth=1e-9)
+
+
+@pytest.mark.parametrize("form", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("case", ["multitile", "wide"])
+def test_rayleigh_ritz_bloch_fp32_storage(case, form):
+    """FP32 storage (the arithmetic stays FP64, H_k Psi included): Ritz values of
+    the FP32-rounded block within 1e-6 of the oracle's scale, Ritz vectors
+    orthonormal and diagonalising H_k to 1e-5."""
+    g, V, k, Y = _bloch_rr_case(case)
+    N = Y.shape[0]
+    Y32 = np.stack([Y.real, Y.imag]).astype(np.float32)
+    eps_o, _ = O.rayleigh_ritz_bloch(Y32[0].astype(np.float64) + 1j * Y32[1], V, g, k)
+    Yd = to_dev(Y32, torch.float32)
+    e = to_host(L.subspace_rayleigh_ritz_bloch(_grid(g), to_dev(V), Yd, k, prec=form))
+    scale = np.max(np.abs(eps_o))
+    err = np.max(np.abs(e - eps_o)) / scale
+    print(f"{case} {form}: Ritz values rel err {err:.2e}")
+    assert err < 1e-6
+    Yh = to_host(Yd)
+    P = (Yh[0] + 1j * Yh[1]).reshape(N, -1)
+    assert np.max(np.abs(P.conj() @ P.T - np.eye(N))) < 1e-5
+    HP = O.bloch_hamiltonian_apply(P.reshape((N,) + g.shape), V, g, k).reshape(N, -1)
+    assert np.max(np.abs(P.conj() @ HP.T - np.diag(e))) < 1e-5 * scale
