@@ -324,6 +324,35 @@ void scenario_rr_bloch(lrdm_ctx* ctx, lrdm_grid g, int N, int degree) {
   if (!(worst_o < 1e-10) || !(worst_h < 1e-9) || !(worst_order <= 0.0)) ++failures;
 }
 
+// The complex Rayleigh-Ritz on an FP32 block (FP64 arithmetic): orthonormal
+// Ritz vectors in the complex product, ascending Ritz values.
+void scenario_rr_bloch_fp32(lrdm_ctx* ctx, lrdm_grid g, int N) {
+  const int64_t M = (int64_t)g.n[0] * g.n[1] * g.n[2];
+  auto V = randv((size_t)M, 3, 0.5);
+  const std::vector<double> y = randv((size_t)2 * N * M, 17);
+  std::vector<float> Y(y.begin(), y.end());
+  std::vector<double> eps(N);
+  check(subspace_rayleigh_ritz_bloch(ctx, &g, V.data(), 0.3, -0.2, 0.5, Y.data(), N, LRDM_FP32,
+                                     eps.data()),
+        ctx, "subspace_rayleigh_ritz_bloch fp32");
+  const size_t im = (size_t)N * M;
+  double worst = 0, order = 0;
+  for (int i = 0; i < N; i += 3)
+    for (int j = 0; j < N; j += 2) {
+      double ore = 0, oim = 0;
+      for (int64_t p = 0; p < M; ++p) {
+        const double ar = Y[(size_t)i * M + p], ai = Y[im + (size_t)i * M + p];
+        const double br = Y[(size_t)j * M + p], bi = Y[im + (size_t)j * M + p];
+        ore += ar * br + ai * bi;
+        oim += ar * bi - ai * br;
+      }
+      worst = std::fmax(worst, std::hypot(ore - (i == j), oim));
+    }
+  for (int i = 1; i < N; ++i) order = std::fmax(order, eps[i - 1] - eps[i]);
+  std::printf("     complex orthonormality %.2e (bound 1e-5), order %.2e\n", worst, order);
+  if (!(worst < 1e-5) || !(order <= 0.0) || !finite(eps)) ++failures;
+}
+
 // Degenerate Ritz values of H_k: free electrons (V = 0) on a cubic 6^3 grid at
 // k = 0, the subspace of the 19 lowest plane waves (1 + 6 + 12 equal energies)
 // mixed by a random complex matrix.  The complex Rayleigh-Ritz must return the
@@ -671,6 +700,7 @@ int main(int argc, char** argv) {
     // 4N > M: the overlap product of the pairing has more rows than points
     scenario_rr_bloch(ctx, grid(7, 9, 11, 0.5), 200, 4);
     scenario_rr_bloch_degenerate(ctx);
+    scenario_rr_bloch_fp32(ctx, grid(9, 8, 7, 0.5), 60);
   }
   if (which == "all" || which == "batched") {
     scenario_batched(ctx, LRDM_FP32);
