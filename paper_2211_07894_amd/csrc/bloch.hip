@@ -11,7 +11,7 @@
 // s_d = sin(k_d h_d):
 //   Re H_k u = -1/2 sum_d (c_d (a+ + a-) - s_d (b+ - b-) - 2a)/h_d^2 + V a,
 //   Im H_k u = -1/2 sum_d (c_d (b+ + b-) + s_d (a+ - a-) - 2b)/h_d^2 + V b.
-// Planes of up to 3072 points: a workgroup marches through a run of z-planes of
+// Planes of up to 4096 points: a workgroup marches through a run of z-planes of
 // one state with plane z of both parts in LDS (bloch_plane_kernel).  Larger
 // planes: one thread forms both parts of one point of one state, the neighbours
 // through the caches (bloch_step_kernel).
@@ -207,9 +207,10 @@ hipError_t bloch_dispatch(lrdm_ctx* ctx, const Grid3& g, const double* V, const 
                           double beta) {
   ProfScope prof(ctx, "bloch_step");
   const BlochCoef k = coef(g, kvec);
-  // planes of up to 3072 points: the plane-staged kernel (1024 threads, up to
-  // three points each, at most 48 KB of LDS for both parts in FP64); larger
-  // planes take the per-point kernel
+  // planes of up to 4096 points: the plane-staged kernel (1024 threads, up to
+  // four points each, at most 64 KB of LDS for both parts in FP64; at four
+  // points a few registers spill, and 64^2 planes still run 1.27x faster than
+  // with the per-point kernel); larger planes take the per-point kernel
   const int P = g.nx * g.ny;
   if (P <= 1024)
     return launch_plane<TI, TO, 1, 1024>(g, V, in, old, out, N, ((P + 63) / 64) * 64, k, alpha,
@@ -219,6 +220,9 @@ hipError_t bloch_dispatch(lrdm_ctx* ctx, const Grid3& g, const double* V, const 
                                          ctx->stream);
   if (P <= 3072)
     return launch_plane<TI, TO, 3, 1024>(g, V, in, old, out, N, 1024, k, alpha, c0, beta,
+                                         ctx->stream);
+  if (P <= 4096)
+    return launch_plane<TI, TO, 4, 1024>(g, V, in, old, out, N, 1024, k, alpha, c0, beta,
                                          ctx->stream);
   dim3 grd((unsigned)((g.M + kBlochThreads - 1) / kBlochThreads), (unsigned)N);
   bloch_step_kernel<TI, TO><<<grd, kBlochThreads, 0, ctx->stream>>>(

@@ -117,11 +117,12 @@ def _bloch_block(g, N, seed):
 @pytest.mark.parametrize("prec,bound", [("fp64", 1e-14), ("fp32", 1e-6)])
 @pytest.mark.parametrize("n,box", [((20, 18, 13), (8.0, 7.2, 5.2)), ((16, 16, 16), (7.0, 7.0, 7.0)),
                                    ((20, 18, 16), (8.0, 7.2, 6.4)), ((40, 36, 5), (16.0, 14.4, 2.0)),
-                                   ((48, 48, 4), (19.2, 19.2, 1.6)), ((70, 60, 3), (28.0, 24.0, 1.2))])
+                                   ((48, 48, 4), (19.2, 19.2, 1.6)), ((64, 64, 3), (25.6, 25.6, 1.2)),
+                                   ((70, 60, 3), (28.0, 24.0, 1.2))])
 def test_bloch_hamiltonian_apply(n, box, prec, bound):
-    """Planes of 256-3072 points take the plane-staged kernel (one, two and three
-    points per thread; runs of z-planes split over blocks for the 16-plane grids),
-    4200 points the per-point kernel."""
+    """Planes of 256-4096 points take the plane-staged kernel (one to four points
+    per thread; runs of z-planes split over blocks for the 16-plane grids), 4200
+    points the per-point kernel."""
     g = O.Grid(n, box)
     V = np.random.default_rng(61).uniform(-1, 0, g.shape)
     k = (0.37, -0.81, 1.23)
