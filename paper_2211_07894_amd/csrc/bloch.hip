@@ -11,6 +11,9 @@
 // s_d = sin(k_d h_d):
 //   Re H_k u = -1/2 sum_d (c_d (a+ + a-) - s_d (b+ - b-) - 2a)/h_d^2 + V a,
 //   Im H_k u = -1/2 sum_d (c_d (b+ + b-) + s_d (a+ - a-) - 2b)/h_d^2 + V b.
+// The kernels take the distance between states and the offset of a state's
+// imaginary part, so that the complex Rayleigh-Ritz can also apply H_k to rows
+// [Re | Im] of length 2M.
 // Planes of up to 4096 points: a workgroup marches through a run of z-planes of
 // one state with plane z of both parts in LDS (bloch_plane_kernel).  Larger
 // planes: one thread forms both parts of one point of one state, the neighbours
@@ -31,7 +34,7 @@ struct BlochCoef {
 template <typename TI, typename TO>
 __global__ __launch_bounds__(kBlochThreads) void bloch_step_kernel(
     const TI* __restrict__ in, const TO* old, TO* out, const double* __restrict__ V, int nx, int ny,
-    int nz, int N, BlochCoef k, double alpha, double c0, double beta) {
+    int nz, int64_t sr, int64_t si, BlochCoef k, double alpha, double c0, double beta) {
   const int64_t M = (int64_t)nx * ny * nz;
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y;
@@ -39,8 +42,8 @@ __global__ __launch_bounds__(kBlochThreads) void bloch_step_kernel(
   const int x = (int)(p % nx);
   const int y = (int)((p / nx) % ny);
   const int z = (int)(p / ((int64_t)nx * ny));
-  const TI* a = in + (int64_t)i * M;           // real plane of state i
-  const TI* b = in + ((int64_t)N + i) * M;     // imaginary plane
+  const TI* a = in + (int64_t)i * sr;          // real part of state i
+  const TI* b = a + si;                        // imaginary part
   const int64_t xp = p - x + (x + 1 == nx ? 0 : x + 1), xm = p - x + (x == 0 ? nx - 1 : x - 1);
   const int64_t yo = (int64_t)nx;
   const int64_t yp = p + (y + 1 == ny ? -(int64_t)(ny - 1) * yo : yo);
@@ -63,7 +66,7 @@ __global__ __launch_bounds__(kBlochThreads) void bloch_step_kernel(
   double hi = -0.5 * li + v * bp - c0 * bp;
   hr *= alpha;
   hi *= alpha;
-  const int64_t oa = (int64_t)i * M + p, ob = ((int64_t)N + i) * M + p;
+  const int64_t oa = (int64_t)i * sr + p, ob = oa + si;
   if (beta != 0.0) {
     hr += beta * (double)old[oa];
     hi += beta * (double)old[ob];
@@ -80,15 +83,14 @@ __global__ __launch_bounds__(kBlochThreads) void bloch_step_kernel(
 template <typename TI, typename TO, int Q, int TB>
 __global__ __launch_bounds__(TB) void bloch_plane_kernel(
     const TI* __restrict__ in, const TO* old, TO* out, const double* __restrict__ V, int nx, int ny,
-    int nz, int N, int zrun, BlochCoef k, double alpha, double c0, double beta) {
+    int nz, int64_t sr, int64_t si, int zrun, BlochCoef k, double alpha, double c0, double beta) {
   extern __shared__ __attribute__((aligned(16))) unsigned char bloch_smem[];
   double* bloch_lds = reinterpret_cast<double*>(bloch_smem);   // [2][P]: plane z, both parts
   const int P = nx * ny;
-  const int64_t M = (int64_t)P * nz;
   const int i = blockIdx.x;
   const int z0 = blockIdx.y * zrun, z1 = min(nz, z0 + zrun);
-  const TI* a = in + (int64_t)i * M;
-  const TI* b = in + ((int64_t)N + i) * M;
+  const TI* a = in + (int64_t)i * sr;
+  const TI* b = a + si;
   double* la = bloch_lds;
   double* lb = bloch_lds + P;
   double am[Q], ac[Q], ap[Q], bm[Q], bc[Q], bp[Q];
@@ -141,7 +143,7 @@ __global__ __launch_bounds__(TB) void bloch_plane_kernel(
       double hi = -0.5 * li + v * bpc - c0 * bpc;
       hr *= alpha;
       hi *= alpha;
-      const int64_t oa = (int64_t)i * M + pz, ob = ((int64_t)N + i) * M + pz;
+      const int64_t oa = (int64_t)i * sr + pz, ob = oa + si;
       if (beta != 0.0) {
         hr += beta * (double)old[oa];
         hi += beta * (double)old[ob];
@@ -172,8 +174,8 @@ __global__ __launch_bounds__(TB) void bloch_plane_kernel(
 
 template <typename TI, typename TO, int Q, int TB>
 hipError_t launch_plane(const Grid3& g, const double* V, const TI* in, const TO* old, TO* out,
-                        int N, int threads, const BlochCoef& k, double alpha, double c0,
-                        double beta, hipStream_t stream) {
+                        int N, int64_t sr, int64_t si, int threads, const BlochCoef& k,
+                        double alpha, double c0, double beta, hipStream_t stream) {
   // z runs: enough blocks for the chip (N * runs >= ~1024), runs of >= 8 planes
   int runs = 1;
   while ((int64_t)N * runs < 1024 && g.nz / (runs * 2) >= 8) runs *= 2;
@@ -184,8 +186,8 @@ hipError_t launch_plane(const Grid3& g, const double* V, const TI* in, const TO*
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
   dim3 grd((unsigned)N, (unsigned)((g.nz + zrun - 1) / zrun));
   bloch_plane_kernel<TI, TO, Q, TB><<<grd, threads, smem, stream>>>(in, old, out, V, g.nx, g.ny,
-                                                                   g.nz, N, zrun, k, alpha, c0,
-                                                                   beta);
+                                                                   g.nz, sr, si, zrun, k, alpha,
+                                                                   c0, beta);
   return hipGetLastError();
 }
 
@@ -203,8 +205,8 @@ BlochCoef coef(const Grid3& g, const double kvec[3]) {
 // out = alpha (H_k in - c0 in) + beta old on blocks of N complex states.
 template <typename TI, typename TO>
 hipError_t bloch_dispatch(lrdm_ctx* ctx, const Grid3& g, const double* V, const double kvec[3],
-                          const TI* in, const TO* old, TO* out, int N, double alpha, double c0,
-                          double beta) {
+                          const TI* in, const TO* old, TO* out, int N, int64_t sr, int64_t si,
+                          double alpha, double c0, double beta) {
   ProfScope prof(ctx, "bloch_step");
   const BlochCoef k = coef(g, kvec);
   // planes of up to 4096 points: the plane-staged kernel (1024 threads, up to
@@ -213,20 +215,20 @@ hipError_t bloch_dispatch(lrdm_ctx* ctx, const Grid3& g, const double* V, const 
   // with the per-point kernel); larger planes take the per-point kernel
   const int P = g.nx * g.ny;
   if (P <= 1024)
-    return launch_plane<TI, TO, 1, 1024>(g, V, in, old, out, N, ((P + 63) / 64) * 64, k, alpha,
-                                         c0, beta, ctx->stream);
+    return launch_plane<TI, TO, 1, 1024>(g, V, in, old, out, N, sr, si, ((P + 63) / 64) * 64, k,
+                                         alpha, c0, beta, ctx->stream);
   if (P <= 2048)
-    return launch_plane<TI, TO, 2, 1024>(g, V, in, old, out, N, 1024, k, alpha, c0, beta,
+    return launch_plane<TI, TO, 2, 1024>(g, V, in, old, out, N, sr, si, 1024, k, alpha, c0, beta,
                                          ctx->stream);
   if (P <= 3072)
-    return launch_plane<TI, TO, 3, 1024>(g, V, in, old, out, N, 1024, k, alpha, c0, beta,
+    return launch_plane<TI, TO, 3, 1024>(g, V, in, old, out, N, sr, si, 1024, k, alpha, c0, beta,
                                          ctx->stream);
   if (P <= 4096)
-    return launch_plane<TI, TO, 4, 1024>(g, V, in, old, out, N, 1024, k, alpha, c0, beta,
+    return launch_plane<TI, TO, 4, 1024>(g, V, in, old, out, N, sr, si, 1024, k, alpha, c0, beta,
                                          ctx->stream);
   dim3 grd((unsigned)((g.M + kBlochThreads - 1) / kBlochThreads), (unsigned)N);
   bloch_step_kernel<TI, TO><<<grd, kBlochThreads, 0, ctx->stream>>>(
-      in, old, out, V, g.nx, g.ny, g.nz, N, k, alpha, c0, beta);
+      in, old, out, V, g.nx, g.ny, g.nz, sr, si, k, alpha, c0, beta);
   return hipGetLastError();
 }
 
@@ -236,18 +238,22 @@ template <typename T>
 hipError_t launch_bloch_step(lrdm_ctx* ctx, const Grid3& g, const double* V, const double kvec[3],
                              const T* in, const T* old, T* out, int N, double alpha, double c0,
                              double beta) {
-  return bloch_dispatch<T, T>(ctx, g, V, kvec, in, old, out, N, alpha, c0, beta);
+  return bloch_dispatch<T, T>(ctx, g, V, kvec, in, old, out, N, g.M, (int64_t)N * g.M, alpha, c0,
+                              beta);
 }
 
 template <typename T>
 hipError_t launch_bloch_hpsi_f64(lrdm_ctx* ctx, const Grid3& g, const double* V,
-                                 const double kvec[3], const T* in, double* out, int N) {
-  return bloch_dispatch<T, double>(ctx, g, V, kvec, in, nullptr, out, N, 1.0, 0.0, 0.0);
+                                 const double kvec[3], const T* in, double* out, int N,
+                                 int64_t sr, int64_t si) {
+  return bloch_dispatch<T, double>(ctx, g, V, kvec, in, nullptr, out, N, sr, si, 1.0, 0.0, 0.0);
 }
 template hipError_t launch_bloch_hpsi_f64<double>(lrdm_ctx*, const Grid3&, const double*,
-                                                  const double[3], const double*, double*, int);
+                                                  const double[3], const double*, double*, int,
+                                                  int64_t, int64_t);
 template hipError_t launch_bloch_hpsi_f64<float>(lrdm_ctx*, const Grid3&, const double*,
-                                                 const double[3], const float*, double*, int);
+                                                 const double[3], const float*, double*, int,
+                                                 int64_t, int64_t);
 template hipError_t launch_bloch_step<double>(lrdm_ctx*, const Grid3&, const double*,
                                               const double[3], const double*, const double*,
                                               double*, int, double, double, double);

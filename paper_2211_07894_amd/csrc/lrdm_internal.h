@@ -175,10 +175,13 @@ template <typename T>
 hipError_t launch_bloch_step(lrdm_ctx* ctx, const Grid3& g, const double* V, const double kvec[3],
                              const T* in, const T* old, T* out, int N, double alpha, double c0,
                              double beta);
-// out = H_k in in FP64 for a block of N complex states stored as T (bloch.hip).
+// out = H_k in in FP64 for a block of N complex states stored as T (bloch.hip);
+// state i has its real part at i sr and its imaginary part at i sr + si (in and
+// out alike): sr = M, si = N M for [2][N][M], sr = 2M, si = M for [N][2][M].
 template <typename T>
 hipError_t launch_bloch_hpsi_f64(lrdm_ctx* ctx, const Grid3& g, const double* V,
-                                 const double kvec[3], const T* in, double* out, int N);
+                                 const double kvec[3], const T* in, double* out, int N,
+                                 int64_t sr, int64_t si);
 
 // launch_fermi with Brillouin-zone sampling: eps [nspin][nk][N], weights [nk]
 // (device); mu from the zone-averaged count, then f, 1 - f, f' and the divided

@@ -699,24 +699,21 @@ __device__ inline cplx c_conj_mul(cplx a, cplx b) {   // conj(a) b
 }
 __device__ inline double c_abs2(cplx a) { return a.re * a.re + a.im * a.im; }
 
-// B [2][2N][M]: the complex block of the 2N states y_i, i y_i from Y [2][N][M].
+// B [2N][2M]: the 2N real vectors [Re | Im] of the states y_i, i y_i, from Y
+// [2][N][M] (real parts, then imaginary parts).  Each real vector is one row of
+// length 2M, so the Gram matrix, the projection and the rotations of the 2N
+// vectors are the real path's products with K = 2M.
 template <typename T>
 __global__ void realify_kernel(const T* __restrict__ Y, int N, int64_t M, T* __restrict__ B) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y;
   if (p >= M) return;
   const T yr = Y[(int64_t)i * M + p], yi = Y[((int64_t)N + i) * M + p];
-  const int64_t n2 = 2 * (int64_t)N;
-  B[(int64_t)i * M + p] = yr;
-  B[((int64_t)N + i) * M + p] = -yi;
-  B[(n2 + i) * M + p] = yi;
-  B[(n2 + N + i) * M + p] = yr;
-}
-
-__global__ void add_inplace_kernel(double* __restrict__ a, const double* __restrict__ b,
-                                   int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) a[i] += b[i];
+  const int64_t m2 = 2 * M;
+  B[(int64_t)i * m2 + p] = yr;
+  B[(int64_t)i * m2 + M + p] = yi;
+  B[((int64_t)N + i) * m2 + p] = -yi;
+  B[((int64_t)N + i) * m2 + M + p] = yr;
 }
 
 __global__ void zero_int_kernel(int* __restrict__ x) { *x = 0; }
@@ -762,7 +759,7 @@ __global__ void cluster_kernel(const double* __restrict__ e2, int n2, int* __res
 }
 
 // Complex overlaps <psi_a, psi_b> of real Ritz vector a (one block) with every
-// member b of its cluster, for clusters of four or more; R [2][n2][M].
+// member b of its cluster, for clusters of four or more; R [n2][2M].
 template <typename T>
 __global__ __launch_bounds__(256) void cluster_overlap_kernel(const T* __restrict__ R,
                                                               const int* __restrict__ cs,
@@ -772,11 +769,11 @@ __global__ __launch_bounds__(256) void cluster_overlap_kernel(const T* __restric
   const int a = blockIdx.x, t = threadIdx.x;
   const int s = cs[a], n = cn[a];
   if (n < 4 || n > kPairMax) return;
-  const T* ar = R + (int64_t)a * M;
-  const T* ai = R + ((int64_t)n2 + a) * M;
+  const T* ar = R + (int64_t)a * 2 * M;
+  const T* ai = ar + M;
   for (int j = 0; j < n; ++j) {
-    const T* br = R + (int64_t)(s + j) * M;
-    const T* bi = R + ((int64_t)n2 + s + j) * M;
+    const T* br = R + (int64_t)(s + j) * 2 * M;
+    const T* bi = br + M;
     double re = 0.0, im = 0.0;
     for (int64_t p = t; p < M; p += 256) {
       const double xr = ar[p], xi = ai[p], yr = br[p], yi = bi[p];
@@ -996,7 +993,7 @@ __global__ void cluster_pair_kernel(const double* __restrict__ e2, const int* __
 }
 
 // Psi [2][N][M]: the complex Ritz vectors sum_l coef[o][l] psi_{ostart[o] + l} from
-// the real ones R [2][2N][M] (real part of (a + ib)(re + i im) = a re - b im).
+// the real ones R [2N][2M] (real part of (a + ib)(re + i im) = a re - b im).
 template <typename T>
 __global__ void cluster_combine_kernel(const T* __restrict__ R, const cplx* __restrict__ coef,
                                        const int* __restrict__ ostart,
@@ -1011,7 +1008,7 @@ __global__ void cluster_combine_kernel(const T* __restrict__ R, const cplx* __re
   for (int l = 0; l < n; ++l) {
     const cplx c = coef[(size_t)o * kPairMax + l];
     if (c.re == 0.0 && c.im == 0.0) continue;
-    const double re = R[(int64_t)(s + l) * M + p], im = R[((int64_t)n2 + s + l) * M + p];
+    const double re = R[(int64_t)(s + l) * 2 * M + p], im = R[(int64_t)(s + l) * 2 * M + M + p];
     xr += c.re * re - c.im * im;
     xi += c.re * im + c.im * re;
   }
@@ -1028,7 +1025,7 @@ size_t rr_bloch_workspace_bytes(int N, int64_t M, lrdm_prec prec) {
   const size_t s = prec == LRDM_FP64 ? sizeof(double) : sizeof(float);
   size_t b = 2 * ws_align((size_t)2 * n2 * M * s);                 // B, spare
   b += ws_align((size_t)2 * n2 * M * sizeof(double));              // H B
-  b += 7 * ws_align((size_t)n2 * n2 * sizeof(double));            // G, G2, T, C, X, Wt, Q
+  b += 6 * ws_align((size_t)n2 * n2 * sizeof(double));            // G, T, C, X, Wt, Q
   b += ws_align((size_t)n2 * sizeof(double));                     // real Ritz values
   b += 2 * ws_align((size_t)n2 * sizeof(int));                    // clusters
   b += ws_align((size_t)n2 * kPairRow * sizeof(cplx));            // cluster scratch
@@ -1038,7 +1035,7 @@ size_t rr_bloch_workspace_bytes(int N, int64_t M, lrdm_prec prec) {
   inner = std::max(inner, 2 * ws_align((size_t)Np * Np * sizeof(double)) +
                               ws_align((size_t)(nb / 2) * JS * JS * 8) + ws_align(256) +
                               ws_align((size_t)Np * 4) + ws_align(kFrobBlocks * sizeof(double)));
-  inner = std::max(inner, ws_align(tn_workspace_bytes(n2, M, 1, prec)));
+  inner = std::max(inner, ws_align(tn_workspace_bytes(n2, 2 * M, 1, prec)));
   return b + inner;
 }
 
@@ -1056,7 +1053,6 @@ lrdm_status rayleigh_ritz_bloch(lrdm_ctx* ctx, const Grid3& g, const double* V,
   T* spare = static_cast<T*>(ws_take(ctx, 2 * plane * sizeof(T)));
   double* HB = static_cast<double*>(ws_take(ctx, 2 * plane * sizeof(double)));
   double* G = static_cast<double*>(ws_take(ctx, nn));
-  double* G2 = static_cast<double*>(ws_take(ctx, nn));
   double* Tm = static_cast<double*>(ws_take(ctx, nn));
   double* C = static_cast<double*>(ws_take(ctx, nn));
   double* X = static_cast<double*>(ws_take(ctx, nn));
@@ -1078,25 +1074,17 @@ lrdm_status rayleigh_ritz_bloch(lrdm_ctx* ctx, const Grid3& g, const double* V,
     return LRDM_EDEVICE;
   };
   const dim3 blk(32, 8), grd((n2 + 31) / 32, (n2 + 7) / 8);
-  const int64_t nsq = (int64_t)n2 * n2;
-  const unsigned add_grid = (unsigned)((nsq + 255) / 256);
+  const int64_t M2 = 2 * M;
   realify_kernel<T><<<dim3((unsigned)((M + 255) / 256), N), 256, 0, ctx->stream>>>(Psi, N, M, B);
   if ((e = hipGetLastError()) != hipSuccess) return fail("realify", e);
-  // out = P_re Q_re^T + P_im Q_im^T (Q = P when Q2 is null).  Each product forms its
-  // upper tiles and mirrors them; the sum of the two is symmetric, so the mirrored
-  // sum is the sum.  A product's partial sums are free once its reduction is queued.
-  auto two_plane = [&](const T* P, const double* Q2, double* out) -> hipError_t {
-    hipError_t err = Q2 ? launch_tn_sym_f64<T, double>(ctx, P, Q2, nullptr, 0, n2, M, 1, 1, out)
-                        : launch_tn_sym_f64<T, T>(ctx, P, nullptr, nullptr, 0, n2, M, 1, 1, out);
+  // out = P Q^T over rows of length 2M (Q = P when Q2 is null); the partial sums
+  // are free once the reduction is queued
+  auto gram = [&](const T* P, const double* Q2, double* out) -> hipError_t {
+    const hipError_t err =
+        Q2 ? launch_tn_sym_f64<T, double>(ctx, P, Q2, nullptr, 0, n2, M2, 1, 1, out)
+           : launch_tn_sym_f64<T, T>(ctx, P, nullptr, nullptr, 0, n2, M2, 1, 1, out);
     ctx->ws_top = mark;
-    if (err != hipSuccess) return err;
-    err = Q2 ? launch_tn_sym_f64<T, double>(ctx, P + plane, Q2 + plane, nullptr, 0, n2, M, 1, 1,
-                                            G2)
-             : launch_tn_sym_f64<T, T>(ctx, P + plane, nullptr, nullptr, 0, n2, M, 1, 1, G2);
-    ctx->ws_top = mark;
-    if (err != hipSuccess) return err;
-    add_inplace_kernel<<<add_grid, 256, 0, ctx->stream>>>(out, G2, nsq);
-    return hipGetLastError();
+    return err;
   };
   // Orthonormal basis as in the real path: one Cholesky pass for a well-conditioned
   // block, more over the explicitly formed basis otherwise.  Rows the factor finds
@@ -1115,13 +1103,11 @@ lrdm_status rayleigh_ritz_bloch(lrdm_ctx* ctx, const Grid3& g, const double* V,
         return LRDM_ENOTCONV;
       }
       transpose_kernel<<<grd, blk, 0, ctx->stream>>>(Tm, n2, Wt);
-      for (int h = 0; h < 2; ++h)
-        if ((e = launch_nn_f64<T>(ctx, Wt, Bc + h * plane, spare + h * plane, n2, M,
-                                  ci.live == n2)) != hipSuccess)
-          return fail("rotation", e);
+      if ((e = launch_nn_f64<T>(ctx, Wt, Bc, spare, n2, M2, ci.live == n2)) != hipSuccess)
+        return fail("rotation", e);
       std::swap(Bc, spare);
     }
-    if ((e = two_plane(Bc, nullptr, G)) != hipSuccess) return fail("gram", e);
+    if ((e = gram(Bc, nullptr, G)) != hipSuccess) return fail("gram", e);
     if (check_residuals) {
       min_diag_kernel<<<1, 256, 0, ctx->stream>>>(G, n2, dmin);
       double host_min = 0.0;
@@ -1150,9 +1136,9 @@ lrdm_status rayleigh_ritz_bloch(lrdm_ctx* ctx, const Grid3& g, const double* V,
     }
   }
   // H_k on the 2N complex states, then the projected real operator
-  if ((e = launch_bloch_hpsi_f64<T>(ctx, g, V, kvec, Bc, HB, n2)) != hipSuccess)
+  if ((e = launch_bloch_hpsi_f64<T>(ctx, g, V, kvec, Bc, HB, n2, M2, M)) != hipSuccess)
     return fail("H_k", e);
-  if ((e = two_plane(Bc, HB, G)) != hipSuccess) return fail("projection", e);
+  if ((e = gram(Bc, HB, G)) != hipSuccess) return fail("projection", e);
   if ((e = small_gemm(ctx, false, false, n2, n2, n2, 1.0, Tm, n2, G, n2, 0.0, X, n2)) !=
       hipSuccess)
     return fail("gemm", e);
@@ -1167,9 +1153,7 @@ lrdm_status rayleigh_ritz_bloch(lrdm_ctx* ctx, const Grid3& g, const double* V,
       hipSuccess)
     return fail("gemm", e);
   T* R = (Bc == B) ? spare : B;
-  for (int h = 0; h < 2; ++h)
-    if ((e = launch_nn_f64<T>(ctx, Wt, Bc + h * plane, R + h * plane, n2, M)) != hipSuccess)
-      return fail("rotation", e);
+  if ((e = launch_nn_f64<T>(ctx, Wt, Bc, R, n2, M2)) != hipSuccess) return fail("rotation", e);
   // clusters of real Ritz values, the complex pairs of each, and their vectors
   const unsigned cgrid = (unsigned)((n2 + 255) / 256);
   zero_int_kernel<<<1, 1, 0, ctx->stream>>>(flag);

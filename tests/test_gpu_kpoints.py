@@ -182,7 +182,7 @@ def test_bloch_chfsi_reaches_the_lowest_states():
 
 
 # ------------------------------------------------- Rayleigh-Ritz of H_k on the GPU
-def _bloch_ritz_checks(P, e, V, g, k, tol_orth=1e-10):
+def _bloch_ritz_checks(P, e, V, g, k, tol_orth=1e-10, tol_diag=1e-10):
     """P complex [N][M] orthonormal, diagonalising H_k in its span.  One Cholesky
     pass is taken below a Gram condition number of 1e3, so orthonormality holds to
     about 1e3 * N * eps_64 (1e-10 here)."""
@@ -190,7 +190,7 @@ def _bloch_ritz_checks(P, e, V, g, k, tol_orth=1e-10):
     assert np.all(np.diff(e) >= 0.0)
     assert np.max(np.abs(P.conj() @ P.T - np.eye(N))) < tol_orth
     HP = O.bloch_hamiltonian_apply(P.reshape((N,) + g.shape), V, g, k).reshape(N, -1)
-    assert np.max(np.abs(P.conj() @ HP.T - np.diag(e))) < 1e-10 * np.max(np.abs(e))
+    assert np.max(np.abs(P.conj() @ HP.T - np.diag(e))) < tol_diag * np.max(np.abs(e))
 
 
 def _bloch_rr_case(case):
@@ -338,9 +338,11 @@ def test_rayleigh_ritz_bloch_near_dependent_block():
     e = to_host(L.subspace_rayleigh_ritz_bloch(_grid(g), to_dev(V), Yd, k))
     assert np.max(np.abs(e - eps_o)) < 1e-8 * np.max(np.abs(eps_o))
     # the residual of the nearly dependent state is formed to a relative accuracy
-    # of about u / 1e-6 = 1e-10, the bound on the pairing and on orthonormality
+    # of about u / 1e-6 = 1e-10, which bounds the pairing, the orthonormality and
+    # the diagonalisation of H_k (with a margin of 10)
     Yh = to_host(Yd)
-    _bloch_ritz_checks((Yh[0] + 1j * Yh[1]).reshape(16, -1), e, V, g, k, tol_orth=1e-9)
+    _bloch_ritz_checks((Yh[0] + 1j * Yh[1]).reshape(16, -1), e, V, g, k, tol_orth=1e-9,
+                       tol_diag=1e-9)
 
 
 @pytest.mark.parametrize("form", ["fp32", "bf16x3"])
