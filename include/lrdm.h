@@ -82,7 +82,7 @@ typedef enum {
   LRDM_EDEVICE = -3,      /* a HIP call failed */
   LRDM_ENOTCONV = -4,     /* bisection or eigensolver did not converge (checking mode only) */
   LRDM_ENONFINITE = -5,   /* NaN/Inf found in an output (checking mode only) */
-  LRDM_EUNSUPPORTED = -6  /* valid request this build does not implement */
+  LRDM_EUNSUPPORTED = -6  /* a valid request that the library does not implement */
 } lrdm_status;
 
 typedef enum { LRDM_FP64 = 0, LRDM_FP32 = 1, LRDM_BF16X3 = 2 } lrdm_prec;
