@@ -368,12 +368,14 @@ def test_rayleigh_ritz_bloch_fp32_storage(case, form):
     assert np.max(np.abs(P.conj() @ HP.T - np.diag(e))) < 1e-5 * scale
 
 
-def test_zone_sampling_pipeline_on_the_gpu_matches_the_oracle():
+@pytest.mark.parametrize("prec,bound", [("fp64", 1e-8), ("fp32", 1e-5), ("bf16x3", 1e-5)])
+def test_zone_sampling_pipeline_on_the_gpu_matches_the_oracle(prec, bound):
     """The whole zone-sampled path on the GPU: per k-point the Bloch filter and
     the complex Rayleigh-Ritz, then density_response_bz on the resulting Ritz
     pairs, against the oracle taking the same steps from the same blocks.  The
     response depends on the subspaces and Ritz values only, not on the Ritz
-    vectors' phases, so it is compared directly."""
+    vectors' phases, so it is compared directly.  In the FP32-storage forms the
+    blocks are stored in FP32 from the filter on (the bound of those forms)."""
     g = O.Grid((10, 9, 8), (5.0, 4.6, 4.1))
     V = small_wells(g.n, g.L, 87, nwells=3)
     ks = [(0.0, 0.0, 0.0), (0.5, -0.3, 0.2)]
@@ -390,18 +392,22 @@ def test_zone_sampling_pipeline_on_the_gpu_matches_the_oracle():
         e, P = O.rayleigh_ritz_bloch(Y, V, g, k)
         eps_o.append(e)
         Psi_o.append(P)
-        Yd = L.chfsi_filter_bloch(_grid(g), to_dev(V), to_dev(np.stack([X.real, X.imag])), k, 10,
-                                  a, b, a0)
-        eps_g.append(to_host(L.subspace_rayleigh_ritz_bloch(_grid(g), to_dev(V), Yd, k)))
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        Yd = L.chfsi_filter_bloch(_grid(g), to_dev(V), to_dev(np.stack([X.real, X.imag]), dt), k,
+                                  10, a, b, a0, prec=prec)
+        eps_g.append(to_host(L.subspace_rayleigh_ritz_bloch(_grid(g), to_dev(V), Yd, k,
+                                                            prec=prec)))
         Psi_g.append(to_host(Yd))
-        assert np.max(np.abs(eps_g[-1] - e)) < 1e-10 * np.max(np.abs(e))
+        assert np.max(np.abs(eps_g[-1] - e)) < (1e-10 if prec == "fp64" else 1e-5) * np.max(np.abs(e))
     dV = np.random.default_rng(89).standard_normal((2, 1) + g.shape)
     occ = L.Occupation(1, kT, ne)
-    drho, mu, _ = L.density_response_bz(_grid(g), to_dev(np.stack(Psi_g)[None]),
-                                        to_dev(np.stack(eps_g)[None]), to_dev(w), occ, to_dev(dV))
+    Pd = to_dev(np.stack(Psi_g)[None], torch.float64 if prec == "fp64" else torch.float32)
+    drho, mu, _ = L.density_response_bz(_grid(g), Pd, to_dev(np.stack(eps_g)[None]), to_dev(w),
+                                        occ, to_dev(dV), prec=prec)
     ref, mu_o, _ = O.density_response_bz(np.stack(Psi_o)[None], np.stack(eps_o)[None], w, g, ne,
                                          kT, dV, 1)
     err = max(rel(to_host(drho)[q, 0], ref[q, 0]) for q in range(2))
-    print(f"zone-sampled pipeline: mu {float(mu.item()):.12f} vs {mu_o:.12f}, drho rel err {err:.2e}")
-    assert abs(float(mu.item()) - mu_o) < 1e-10
-    assert err < 1e-8
+    print(f"zone-sampled pipeline ({prec}): mu {float(mu.item()):.12f} vs {mu_o:.12f}, "
+          f"drho rel err {err:.2e}")
+    assert abs(float(mu.item()) - mu_o) < (1e-10 if prec == "fp64" else 1e-6)
+    assert err < bound
