@@ -368,7 +368,7 @@ def test_rayleigh_ritz_bloch_fp32_storage(case, form):
     assert np.max(np.abs(P.conj() @ HP.T - np.diag(e))) < 1e-5 * scale
 
 
-@pytest.mark.parametrize("prec,bound", [("fp64", 1e-8), ("fp32", 1e-5), ("bf16x3", 1e-5)])
+@pytest.mark.parametrize("prec,bound", [("fp64", 1e-8), ("fp32", 1e-5), ("bf16x3", 1e-6)])
 def test_zone_sampling_pipeline_on_the_gpu_matches_the_oracle(prec, bound):
     """The whole zone-sampled path on the GPU: per k-point the Bloch filter and
     the complex Rayleigh-Ritz, then density_response_bz on the resulting Ritz
