@@ -616,8 +616,18 @@ hipError_t run_backward(lrdm_ctx* ctx, const Grid3& g, const T* Psi, const doubl
                                 active));
     ctx->ws_top = mark;
   }
-  if (g_Psi)
-    LRDM_HIP(launch_adj_psi<T>(ctx, Gm, gs, dH, dV, r, Psi, N, g.M, ns, 2.0, g_Psi, active));
+  if (g_Psi) {
+    bool done = false;
+    if constexpr (sizeof(T) == sizeof(float)) {
+      if (prec == LRDM_BF16X3) {
+        LRDM_HIP(launch_adj_psi_bf16x3(ctx, Gm, gs, dH, dV, r, Psi, N, g.M, ns, 2.0, g_Psi,
+                                       active));
+        done = true;
+      }
+    }
+    if (!done)
+      LRDM_HIP(launch_adj_psi<T>(ctx, Gm, gs, dH, dV, r, Psi, N, g.M, ns, 2.0, g_Psi, active));
+  }
   if (g_eps)
     LRDM_HIP(launch_adj_eps(ctx, A, Hp, eps, F, f, omf, fp, dmu, nu, N, ns, r, occ->kT, part,
                             g_eps));
@@ -632,7 +642,9 @@ size_t backward_bytes(int N, int64_t M, int r, int ns, lrdm_prec prec) {
   const int batch = r * ns;
   const size_t scratch = std::max({tn_bytes(N, M, batch, prec),
                                    backproj_workspace_bytes(N, M, ns, batch, prec),
-                                   adj_psi_workspace_bytes(N, M, ns, r, prec != LRDM_FP64)});
+                                   adj_psi_workspace_bytes(N, M, ns, r, prec != LRDM_FP64),
+                                   prec == LRDM_BF16X3 ? adj_psi_bf16x3_bytes(N, M, ns, r)
+                                                       : size_t(0)});
   return ws_align(8) + 2 * ws_align((size_t)r * 8) + 4 * ws_align((size_t)ns * N * 8) +
          block_mask_bytes(N, ns) +
          ws_align((size_t)ns * N * N * 8) + 4 * ws_align((size_t)batch * N * N * 8) +

@@ -1044,6 +1044,106 @@ __device__ inline f4 mfma6(const bf8 (&a)[3], const bf8 (&b)[3], f4 c) {
   return mfma_bf16(a[0], b[0], c);
 }
 
+// Adjoint rotation in the BF16X3 form: adj_psi_pipe_kernel's product with both
+// operands pre-split into three BF16 pieces, X3 [2 nx][nspin][3][N][ldk] (the
+// FP32 rounding of each X_m, split) and PT3 [nspin][3][M][ldk] (Psi^T, split).
+// Each K-tile's six products of order <= 2 accumulate in FP32 and are added
+// into the FP64 accumulators with the weight w_m of their output column.
+__global__ __launch_bounds__(PT, 1) void adj_psi_p3_kernel(
+    const __bf16* __restrict__ X3, const double* __restrict__ w1, const double* __restrict__ w2,
+    int nx, const __bf16* __restrict__ PT3, int N, int64_t M, int ldk, int nspin, double scale,
+    const unsigned char* __restrict__ active, const float* __restrict__ zeros,
+    float* __restrict__ Out) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_pipe[];
+  constexpr int SB = 6 * PB;
+  const int nrb = (N + BT - 1) / BT;
+  const int npb = (int)((M + BT - 1) / BT);
+  int group, ib;
+  xcd_map(blockIdx.x, npb * nspin, nrb, group, ib);
+  const int pblk = group / nspin, c = group % nspin;
+  const int i0 = ib * BT;
+  const int64_t p0 = (int64_t)pblk * BT;
+  const int64_t gplane = (int64_t)N * ldk, pplane = M * ldk;
+  const __bf16* Pc = PT3 + (int64_t)c * 3 * pplane;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  uint64_t bits = 0;
+  for (int J = 0; J < nrb; ++J)
+    if (block_active(active, c, nrb, ib, J)) bits |= 1ull << J;
+  const int nkm = active_ktiles(bits, N, KT);     // K-tiles per matrix
+  const int nmat = 2 * nx;
+  const int nk = nmat * nkm;
+  auto issue = [&](int t) {
+    unsigned char* st = smem_pipe + (t % NST) * SB;
+    const int m = nkm > 0 ? min(t / nkm, nmat - 1) : 0;
+    int J;
+    const int64_t j0 = active_ktile(bits, nkm > 0 ? t % nkm : 0, KT, J);
+    const int64_t je = t < nk ? ldk : j0;
+    const __bf16* Xm = X3 + ((int64_t)m * nspin + c) * 3 * gplane;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      dma_piece(Xm + q * gplane, ldk, N, i0, j0, je, zeros, st + q * PB, wid, lane);
+      dma_piece(Pc + q * pplane, ldk, M, p0, j0, je, zeros, st + (3 + q) * PB, wid, lane);
+    }
+  };
+  double acc[2][4][4];
+  zero_pipe(acc);
+  double wcol[4] = {0.0, 0.0, 0.0, 0.0};
+  issue(0);
+  issue(1);
+  for (int t = 0; t < nk; ++t) {
+    if (t % nkm == 0) {
+      // the weights of matrix m for this wave's output columns
+      const int m = t / nkm;
+      const double* w = (m < nx ? w1 : w2) + ((int64_t)(m % nx) * nspin + c) * M;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t p = p0 + wc * 64 + j * 16 + (lane & 15);
+        wcol[j] = p < M ? w[p] : 0.0;
+      }
+    }
+    wait_stage<6>();
+    const unsigned char* st = smem_pipe + (t % NST) * SB;
+    bf8 pa[2][3], pb[4][3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      bf8 va[2], vb[4];
+      frag_piece<2>(st + q * PB, wr * 32, lane, va);
+      frag_piece<4>(st + (3 + q) * PB, wc * 64, lane, vb);
+#pragma unroll
+      for (int i = 0; i < 2; ++i) pa[i][q] = va[i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) pb[j][q] = vb[j];
+    }
+    compiler_fence();
+    issue(t + 2);
+    f4 cc[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) cc[i][j] = mfma6(pa[i], pb[j], f4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[i][j][v] += wcol[j] * (double)cc[i][j][v];
+  }
+  wait_stage<0>();
+  float* Oc = Out + (int64_t)c * N * M;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int gi = i0 + wr * 32 + i * 16 + 4 * (lane >> 4) + v;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t p = p0 + wc * 64 + j * 16 + (lane & 15);
+        if (gi < N && p < M) Oc[(int64_t)gi * M + p] = (float)(scale * acc[i][j][v]);
+      }
+    }
+}
+
 // Projection, BF16X3, pre-split B: H[b] = (w o A_c) B_c^T with A = B = Psi; A
 // FP32 tiles weighted and split in the kernel, B from the pieces P3
 // [nspin][3][N][M].  Same grid and partial layout as tn_sym_pipe_kernel; M a
@@ -1795,6 +1895,41 @@ size_t adj_psi_workspace_bytes(int N, int64_t M, int nspin, int nx, bool fp32) {
   const size_t ldk = pad_k(N);
   return ws_align((size_t)2 * nx * nspin * N * ldk * sizeof(float)) +
          ws_align((size_t)nspin * M * ldk * sizeof(float));
+}
+
+// Adjoint rotation in the BF16X3 form: the 2 nx matrices and Psi^T split into
+// three BF16 pieces each, then adj_psi_p3_kernel.
+hipError_t launch_adj_psi_bf16x3(lrdm_ctx* ctx, const double* X1, const double* w1,
+                                 const double* X2, const double* w2, int nx, const float* Psi,
+                                 int N, int64_t M, int nspin, double scale, float* Out,
+                                 const unsigned char* active) {
+  const int ldk = pad_k(N);
+  const int64_t nX = (int64_t)nx * nspin * N * ldk;
+  __bf16* X3 = static_cast<__bf16*>(ws_take(ctx, (size_t)2 * 3 * nX * sizeof(__bf16)));
+  __bf16* PT3 = static_cast<__bf16*>(ws_take(ctx, (size_t)nspin * 3 * M * ldk * sizeof(__bf16)));
+  const unsigned g1 = (unsigned)((nX + 255) / 256);
+  gamma_split3_kernel<<<g1, 256, 0, ctx->stream>>>(X1, X3, N, ldk, nx * nspin, 0);
+  LRDM_HIP(hipGetLastError());
+  gamma_split3_kernel<<<g1, 256, 0, ctx->stream>>>(X2, X3 + 3 * nX, N, ldk, nx * nspin, 0);
+  LRDM_HIP(hipGetLastError());
+  dim3 gt((unsigned)((M + 63) / 64), (unsigned)(ldk / 64 + (ldk % 64 ? 1 : 0)), nspin);
+  transpose_split3_kernel<<<gt, 256, 0, ctx->stream>>>(Psi, PT3, N, M, ldk);
+  LRDM_HIP(hipGetLastError());
+  const int smem = NST * 6 * PB;
+  LRDM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&adj_psi_p3_kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, smem));
+  const unsigned grd = (unsigned)((M + BT - 1) / BT) * (unsigned)((N + BT - 1) / BT) *
+                       (unsigned)nspin;
+  ProfScope prof(ctx, "adj_psi");
+  adj_psi_p3_kernel<<<grd, PT, smem, ctx->stream>>>(X3, w1, w2, nx, PT3, N, M, ldk, nspin, scale,
+                                                    active, ctx->zeros, Out);
+  return hipGetLastError();
+}
+
+size_t adj_psi_bf16x3_bytes(int N, int64_t M, int nspin, int nx) {
+  const size_t ldk = pad_k(N);
+  return ws_align((size_t)2 * 3 * nx * nspin * N * ldk * sizeof(__bf16)) +
+         ws_align((size_t)nspin * 3 * M * ldk * sizeof(__bf16));
 }
 
 // ------------------------------------------------------------------ fused systems (host)

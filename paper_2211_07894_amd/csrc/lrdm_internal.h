@@ -335,6 +335,14 @@ hipError_t launch_adj_psi(lrdm_ctx* ctx, const double* X1, const double* w1, con
                           const double* w2, int nx, const T* Psi, int N, int64_t M, int nspin,
                           double scale, T* Out, const unsigned char* active = nullptr);
 size_t adj_psi_workspace_bytes(int N, int64_t M, int nspin, int nx, bool fp32);
+// The same rotation in the BF16X3 form (FP32 storage): both operands split into
+// three BF16 pieces, six products, FP32 partial sums per K-tile weighted into
+// FP64 (gemm_lp.hip); workspace adj_psi_bf16x3_bytes.
+hipError_t launch_adj_psi_bf16x3(lrdm_ctx* ctx, const double* X1, const double* w1,
+                                 const double* X2, const double* w2, int nx, const float* Psi,
+                                 int N, int64_t M, int nspin, double scale, float* Out,
+                                 const unsigned char* active);
+size_t adj_psi_bf16x3_bytes(int N, int64_t M, int nspin, int nx);
 
 // Adjoint pieces (adjoint.hip).
 // y[i] = a * x[i] for i < n.

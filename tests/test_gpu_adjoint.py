@@ -140,6 +140,12 @@ def test_full_size_80cubed_2048_states_rank20():
                                                 want=("Psi", "eps"))
     assert rel(to_host(gE), to_host(gE64)) < 1e-5
     assert rel(to_host(gP), to_host(gP64)) < 1e-5
+    # the BF16X3 form's Psi gradient (split-operand rotation) at full size
+    _, gPb, _ = L.density_response_backward(grid, Psi32, eps, occ, dV, G, prec="bf16x3",
+                                            want=("Psi",))
+    eb = rel(to_host(gPb), to_host(gP64))
+    print(f"bf16x3 Psi gradient against fp64: {eb:.2e}")
+    assert eb < 1e-5
 
     def Lf(Pv, Ev):
         return float((G * L.density_response(grid, Pv, Ev, occ, dV)[0]).sum().item())
