@@ -395,7 +395,9 @@ lrdm_status density_response_batched(lrdm_ctx* ctx, const lrdm_system* sys, int3
  * H' are recomputed, nothing of the forward call is kept.  Any of the three
  * outputs may be NULL (not computed); g_Psi may not alias Psi.  FP64 outputs
  * are written whatever prec is; prec selects the arithmetic of the two
- * projections and the back-projection, the rotation for g_Psi is FP64. */
+ * projections, the back-projection and the rotation for g_Psi (FP64; FP32 on
+ * FP32 matrix cores; BF16X3 on three-piece BF16 operands), whose K-tile sums
+ * are accumulated in FP64 in every form. */
 lrdm_status density_response_backward(lrdm_ctx* ctx, const lrdm_grid* grid, const void* Psi,
                                       const double* eps, int32_t N, const lrdm_occ* occ,
                                       const double* dV, int32_t r, lrdm_prec prec,
